@@ -1,0 +1,496 @@
+/*
+ * mmgap_oracle.c -- plain, slow CPU oracle for the Ising hot path of the
+ * MIMO detector / vector-perturbation precoder of "MMGaP: Multi-User MIMO
+ * Detection and Precoding using GPU-assisted Physics-inspired Computation".
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header or constant table with the GPU library; both follow the same written
+ * arithmetic contract so that their chains can be compared spin for spin.
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -fopenmp -shared -fPIC
+ * (no fused multiply-add except the explicit fmaf() calls below; float
+ * arithmetic in float, RNE).
+ *
+ * What is computed (paper §3.2 "Processing Flow" and §2.3):
+ *   * every MIMO problem becomes an Ising problem; N independent anneals are
+ *     run on it from random initial states, each anneal's *final* state is a
+ *     candidate, candidates are ranked by the ML objective (Eq. ml), and the
+ *     MMSE solution replaces a candidate whose energy is larger;
+ *   * the anneal here is a single-spin-flip Metropolis chain on the structured
+ *     (level-domain) Ising form E(x) = x^T G x - 2 f^T x with
+ *     x_k = sum_b w_b s_{k,b}, s in {-1,+1}.
+ *
+ * The chain arithmetic, in the order the oracle performs it:
+ *   fresh field   g_k = (sum_{l<K} G_kl * x_l) - f_k      (left to right, no FMA)
+ *   flip of s_i   i = k*q + b,  d = -2 w_b s_i            (a power of two)
+ *                 dE = d * ((g_k + g_k) + d * G_kk)
+ *                 z  = beta2_t * dE                       (beta2 = beta*log2 e)
+ *                 accept iff z <= 0, or z < 16 and m < 2^16 * 2^-z,
+ *                 m = 16-bit Philox draw, 2^-z evaluated as below
+ *   on accept     s_i = -s_i;  g_j = g_j + G_kj * d for all j
+ *   energy        E = sum_k x_k * (g_k - f_k)             (left to right, no FMA)
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10: J. K. Salmon, M. A. Moraes, R. O. Dror, D. E. Shaw,
+ * "Parallel random numbers: as easy as 1, 2, 3", SC'11.  Each round takes the
+ * 32x32->64-bit products of the two multipliers with counter words 0 and 2,
+ * and forms the new counter (hi1^c1^k0, lo1, hi0^c3^k1, lo0); the key is
+ * advanced by the two Weyl constants between rounds.                        */
+static const uint32_t PHILOX_MUL_A = 0xD2511F53u;
+static const uint32_t PHILOX_MUL_B = 0xCD9E8D57u;
+static const uint32_t PHILOX_WEYL_A = 0x9E3779B9u;
+static const uint32_t PHILOX_WEYL_B = 0xBB67AE85u;
+
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += PHILOX_WEYL_A;
+            k1 += PHILOX_WEYL_B;
+        }
+        uint64_t pa = (uint64_t)PHILOX_MUL_A * (uint64_t)c0;
+        uint64_t pb = (uint64_t)PHILOX_MUL_B * (uint64_t)c2;
+        uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)pb;
+        uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)pa;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* The 16-bit draw used for spin i at sweep t of chain ch of instance inst:
+ * counter (i/8, t, ch, inst), key (seed_lo, seed_hi); word (i%8)/2, low half
+ * for even i, high half for odd i.  Initial spins use t = 0xFFFFFFFF.       */
+static uint32_t draw16(uint32_t i, uint32_t t, uint32_t ch, uint32_t inst, const uint32_t key[2])
+{
+    uint32_t ctr[4] = {i / 8u, t, ch, inst};
+    uint32_t out[4];
+    oracle_philox4x32_10(ctr, key, out);
+    uint32_t word = out[(i % 8u) / 2u];
+    return (i % 2u == 0u) ? (word & 0xFFFFu) : (word >> 16);
+}
+
+uint32_t oracle_draw16(uint32_t i, uint32_t t, uint32_t ch, uint32_t inst, uint64_t seed)
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    return draw16(i, t, ch, inst, key);
+}
+
+/* ------------------------------------------------------------------------ */
+/* 2^-r on [0,1): Taylor series of e^(-r ln 2) truncated after degree 6,
+ * coefficients a_k = (-ln 2)^k / k! formed in double by the recurrence
+ * a_k = (a_{k-1} * (-ln 2)) / k and rounded once to float, evaluated by Horner's
+ * rule with one fused multiply-add (fmaf, a single rounding) per step.      */
+#define EXP2_DEGREE 6
+static float exp2_coef[EXP2_DEGREE + 1];
+static int exp2_ready = 0;
+
+static void exp2_init(void)
+{
+    if (exp2_ready) return;
+    const double ln2 = 0.693147180559945309417232121458176568;
+    double a = 1.0;
+    exp2_coef[0] = 1.0f;
+    for (int k = 1; k <= EXP2_DEGREE; ++k) {
+        a = (a * (-ln2)) / (double)k;
+        exp2_coef[k] = (float)a;
+    }
+    exp2_ready = 1;
+}
+
+static float exp2_neg_frac(float r)
+{
+    float p = exp2_coef[EXP2_DEGREE];
+    for (int k = EXP2_DEGREE - 1; k >= 0; --k) p = fmaf(p, r, exp2_coef[k]);
+    return p;
+}
+
+/* Metropolis test on the scaled energy change z = beta2 * dE.              */
+static int metropolis_accept(float z, uint32_t m)
+{
+    if (z <= 0.0f) return 1;
+    if (!(z < 16.0f)) return 0;                  /* also rejects NaN */
+    float fl = floorf(z);
+    int n = (int)fl;
+    float r = z - fl;                            /* exact */
+    float thr = ldexpf(exp2_neg_frac(r), 16 - n); /* 2^16 * 2^-z, exact scaling */
+    return (float)m < thr;
+}
+
+float oracle_exp2_neg(float z)
+{
+    exp2_init();
+    float fl = floorf(z);
+    return ldexpf(exp2_neg_frac(z - fl), -(int)fl);
+}
+
+int oracle_accept(float z, uint32_t m)
+{
+    exp2_init();
+    return metropolis_accept(z, m);
+}
+
+void oracle_exp2_coefficients(float *out)
+{
+    exp2_init();
+    for (int k = 0; k <= EXP2_DEGREE; ++k) out[k] = exp2_coef[k];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Level-domain helpers.                                                     */
+
+/* fresh field g = G x - f, accumulated left to right, no fused operations */
+static void fresh_field(int K, const float *G, const float *f, const float *x, float *g)
+{
+    for (int k = 0; k < K; ++k) {
+        float acc = 0.0f;
+        for (int l = 0; l < K; ++l) {
+            float prod = G[k * K + l] * x[l];
+            acc = acc + prod;
+        }
+        g[k] = acc - f[k];
+    }
+}
+
+/* E = x^T G x - 2 f^T x written as sum_k x_k (g_k - f_k) with g = G x - f */
+static float level_energy(int K, const float *f, const float *x, const float *g)
+{
+    float acc = 0.0f;
+    for (int k = 0; k < K; ++k) {
+        float diff = g[k] - f[k];
+        float term = x[k] * diff;
+        acc = acc + term;
+    }
+    return acc;
+}
+
+static void levels_from_spins(int K, int q, const signed char *w, const signed char *s, float *x)
+{
+    for (int k = 0; k < K; ++k) {
+        int lv = 0;
+        for (int b = 0; b < q; ++b) lv += (int)w[b] * (int)s[k * q + b];
+        x[k] = (float)lv;
+    }
+}
+
+/* Spins representing level lv: MSB first, s_b = +1 if the remainder is
+ * positive, else -1.  Exact for binary weights and for unit weights.       */
+static void spins_from_level(int q, const signed char *w, int lv, signed char *s)
+{
+    int rem = lv;
+    for (int b = 0; b < q; ++b) {
+        s[b] = (rem > 0) ? 1 : -1;
+        rem -= (int)w[b] * (int)s[b];
+    }
+}
+
+/* Total order on candidate energies: numeric, all NaNs after everything.  */
+static int energy_less(float a, float b)
+{
+    int an = isnan(a), bn = isnan(b);
+    if (an) return 0;
+    if (bn) return 1;
+    return a < b;
+}
+
+/* One anneal: returns final energy, writes final spins (N = K*q).          */
+static float run_chain(int K, int q, const signed char *w, const float *G, const float *f,
+                       const signed char *xfb, int sweeps, const float *beta2,
+                       const uint32_t key[2], uint32_t inst, uint32_t ch, int init_mode,
+                       signed char *s, float *x, float *g)
+{
+    const int N = K * q;
+    if (init_mode == 1 && xfb != NULL) {
+        for (int k = 0; k < K; ++k) spins_from_level(q, w, (int)xfb[k], s + k * q);
+    } else {
+        for (int i = 0; i < N; ++i) {
+            uint32_t d = draw16((uint32_t)i, 0xFFFFFFFFu, ch, inst, key);
+            s[i] = (d & 0x8000u) ? -1 : 1;
+        }
+    }
+    levels_from_spins(K, q, w, s, x);
+    fresh_field(K, G, f, x, g);
+
+    for (int t = 0; t < sweeps; ++t) {
+        const float b2 = beta2[t];
+        for (int i = 0; i < N; ++i) {
+            const int k = i / q, b = i % q;
+            const float delta = (float)(-2 * (int)w[b] * (int)s[i]);
+            const float twice = g[k] + g[k];
+            const float curv = delta * G[k * K + k];
+            const float inner = twice + curv;
+            const float dE = delta * inner;
+            const float z = b2 * dE;
+            const uint32_t m = draw16((uint32_t)i, (uint32_t)t, ch, inst, key);
+            if (metropolis_accept(z, m)) {
+                s[i] = (signed char)(-s[i]);
+                for (int j = 0; j < K; ++j) {
+                    float step = G[k * K + j] * delta;
+                    g[j] = g[j] + step;
+                }
+            }
+        }
+    }
+    levels_from_spins(K, q, w, s, x);
+    fresh_field(K, G, f, x, g);
+    return level_energy(K, f, x, g);
+}
+
+/*
+ * oracle_solve: best-of-C annealed candidates per instance, with fallback.
+ *   G            [n_G][K][K] float, symmetric; instance n uses G[inst_of(n)/inst_per_G]
+ *   f            [n][K] float
+ *   x_fb         [n][K] int8 levels or NULL (no fallback)
+ *   inst_ids     [n] uint32 Philox instance index of each instance, or NULL (0..n-1).
+ *                G is indexed by inst_ids[n] / inst_per_G minus g_base.
+ *   beta2        [sweeps] float
+ *   spins_out    [n][K*q] int8 (+1/-1); e_out [n]; win_out [n] (chain index, C = fallback)
+ *   chain_e_out  [n][C] float or NULL (energy of every chain's final state)
+ */
+int oracle_solve(int n, int K, int q, const signed char *w, const float *G, int inst_per_G,
+                 long g_base, const float *f, const signed char *x_fb, const uint32_t *inst_ids,
+                 int chains, int sweeps, const float *beta2, uint64_t seed, int init_mode,
+                 signed char *spins_out, float *e_out, int *win_out, float *chain_e_out,
+                 int nthreads)
+{
+    if (n < 0 || K <= 0 || q <= 0 || chains <= 0 || sweeps < 0 || inst_per_G <= 0) return -1;
+    exp2_init();
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    const int N = K * q;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    int bad = 0;
+#pragma omp parallel
+    {
+        signed char *s = (signed char *)malloc((size_t)N);
+        signed char *sbest = (signed char *)malloc((size_t)N);
+        float *x = (float *)malloc(sizeof(float) * (size_t)K);
+        float *g = (float *)malloc(sizeof(float) * (size_t)K);
+        if (!s || !sbest || !x || !g) {
+#pragma omp atomic write
+            bad = 1;
+        } else {
+#pragma omp for schedule(dynamic, 4)
+            for (int idx = 0; idx < n; ++idx) {
+                const uint32_t inst = inst_ids ? inst_ids[idx] : (uint32_t)idx;
+                const long gi = (long)(inst / (uint32_t)inst_per_G) - g_base;
+                const float *Gi = G + (size_t)gi * (size_t)K * (size_t)K;
+                const float *fi = f + (size_t)idx * (size_t)K;
+                const signed char *xi = x_fb ? x_fb + (size_t)idx * (size_t)K : NULL;
+                float ebest = 0.0f;
+                int win = -1;
+                for (int ch = 0; ch < chains; ++ch) {
+                    float e = run_chain(K, q, w, Gi, fi, xi, sweeps, beta2, key, inst,
+                                        (uint32_t)ch, init_mode, s, x, g);
+                    if (chain_e_out) chain_e_out[(size_t)idx * (size_t)chains + (size_t)ch] = e;
+                    if (win < 0 || energy_less(e, ebest)) {
+                        ebest = e;
+                        win = ch;
+                        memcpy(sbest, s, (size_t)N);
+                    }
+                }
+                if (xi) {
+                    for (int k = 0; k < K; ++k) x[k] = (float)xi[k];
+                    fresh_field(K, Gi, fi, x, g);
+                    float efb = level_energy(K, fi, x, g);
+                    if (energy_less(efb, ebest)) {
+                        ebest = efb;
+                        win = chains;
+                        for (int k = 0; k < K; ++k) spins_from_level(q, w, (int)xi[k], sbest + k * q);
+                    }
+                }
+                memcpy(spins_out + (size_t)idx * (size_t)N, sbest, (size_t)N);
+                e_out[idx] = ebest;
+                if (win_out) win_out[idx] = win;
+            }
+        }
+        free(s); free(sbest); free(x); free(g);
+    }
+    return bad ? -2 : 0;
+}
+
+/* Energy of given levels on the structured form (the F6/F7 arithmetic).    */
+float oracle_level_energy(int K, const float *G, const float *f, const signed char *lv)
+{
+    float x[256], g[256];
+    if (K <= 0 || K > 256) return NAN;
+    for (int k = 0; k < K; ++k) x[k] = (float)lv[k];
+    fresh_field(K, G, f, x, g);
+    return level_energy(K, f, x, g);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Vector-perturbation couplings (paper §3.3, Eqs. VPP and its rewriting with
+ * y~ = W u, H_p = -tau W / 2).  With W = H^H (H H^H)^-1 the Gram of H_p is
+ * (tau/2)^2 (H H^H)^-1 and its matched filter is -(tau/2) (H H^H)^-1 u, so
+ * the couplings need A^-1 for A = H H^H only.  A^-1 is formed in double by a
+ * fixed sequence of IEEE operations (so that two implementations following
+ * the same sequence agree bit for bit):
+ *   A_il  = sum_j H_ij conj(H_lj)              j ascending, i >= l, mirrored
+ *   LDL^H d_j = Re A_jj - sum_{k<j} ((Re L_jk)^2 + (Im L_jk)^2) d_k
+ *         L_ij = (A_ij - sum_{k<j} (L_ik conj(L_jk)) d_k) / d_j
+ *   M = L^-1   M_im = -sum_{k=m}^{i-1} L_ik M_km  (M_mm = 1)
+ *   A^-1_il = sum_{k=i}^{n-1} (conj(M_ki) M_kl) / d_k   i >= l, mirrored (conj)
+ *   z = A^-1 u  z_i = sum_l A^-1_il u_l         l ascending
+ * Complex products: (a+bi)(c+di) = (ac - bd) + (ad + bc)i and
+ * conj(a+bi)(c+di) = (ac + bd) + (ad - bc)i, each product and sum rounded.  */
+typedef struct { double re, im; } cplx;
+
+static cplx cmul(cplx a, cplx b) { cplx r; r.re = a.re * b.re - a.im * b.im; r.im = a.re * b.im + a.im * b.re; return r; }
+static cplx cmulc(cplx a, cplx b) { cplx r; r.re = a.re * b.re + a.im * b.im; r.im = a.re * b.im - a.im * b.re; return r; }
+
+/* A^-1 of A = H H^H for one subcarrier.  H: [n_u][n_t] complex64 interleaved;
+ * out: [n_u][n_u] complex double interleaved.  n_u <= 32.                  */
+static void vpp_gram_inverse(int n_u, int n_t, const float *H, cplx *Ainv)
+{
+    cplx A[32 * 32], L[32 * 32], M[32 * 32];
+    double d[32];
+    const int n = n_u;
+    for (int i = 0; i < n; ++i) {
+        for (int l = 0; l <= i; ++l) {
+            double re = 0.0, im = 0.0;
+            for (int j = 0; j < n_t; ++j) {
+                double a = H[2 * (i * n_t + j)], b = H[2 * (i * n_t + j) + 1];
+                double c = H[2 * (l * n_t + j)], e = H[2 * (l * n_t + j) + 1];
+                double pre = a * c + b * e;   /* H_ij conj(H_lj) */
+                double pim = b * c - a * e;
+                re = re + pre;
+                im = im + pim;
+            }
+            A[i * n + l].re = re; A[i * n + l].im = im;
+            A[l * n + i].re = re; A[l * n + i].im = -im;
+        }
+    }
+    for (int j = 0; j < n; ++j) {
+        double dj = A[j * n + j].re;
+        for (int k = 0; k < j; ++k) {
+            cplx v = L[j * n + k];
+            double t = v.re * v.re + v.im * v.im;
+            t = t * d[k];
+            dj = dj - t;
+        }
+        d[j] = dj;
+        for (int i = j + 1; i < n; ++i) {
+            cplx s = A[i * n + j];
+            for (int k = 0; k < j; ++k) {
+                cplx v = cmulc(L[j * n + k], L[i * n + k]);   /* L_ik conj(L_jk) */
+                v.re = v.re * d[k];
+                v.im = v.im * d[k];
+                s.re = s.re - v.re;
+                s.im = s.im - v.im;
+            }
+            L[i * n + j].re = s.re / d[j];
+            L[i * n + j].im = s.im / d[j];
+        }
+    }
+    for (int m = 0; m < n; ++m) {
+        M[m * n + m].re = 1.0; M[m * n + m].im = 0.0;
+        for (int i = m + 1; i < n; ++i) {
+            cplx s = {0.0, 0.0};
+            for (int k = m; k < i; ++k) {
+                cplx v = cmul(L[i * n + k], M[k * n + m]);
+                s.re = s.re + v.re;
+                s.im = s.im + v.im;
+            }
+            M[i * n + m].re = -s.re; M[i * n + m].im = -s.im;
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        for (int l = 0; l <= i; ++l) {
+            cplx acc = {0.0, 0.0};
+            for (int k = i; k < n; ++k) {
+                cplx v = cmulc(M[k * n + i], M[k * n + l]);   /* conj(M_ki) M_kl */
+                v.re = v.re / d[k];
+                v.im = v.im / d[k];
+                acc.re = acc.re + v.re;
+                acc.im = acc.im + v.im;
+            }
+            Ainv[i * n + l] = acc;
+            Ainv[l * n + i].re = acc.re; Ainv[l * n + i].im = -acc.im;
+        }
+    }
+}
+
+/*
+ * oracle_vpp_build: VPP Ising couplings for a slot.
+ *   H [n_sc][n_u][n_t] complex64; u [n_sc][n_sym][n_u] complex64; tau > 0.
+ *   G_out [n_sc][2n_u][2n_u] float = (tau/2)^2 * real form of A^-1
+ *   f_out [n_sc*n_sym][2n_u] float = -(tau/2) * [Re z; Im z],  z = A^-1 u
+ *   Ainv_out [n_sc][n_u][n_u] complex double (may be NULL)
+ * Real form of X + iY: [[X, -Y], [Y, X]].
+ */
+int oracle_vpp_build(int n_sc, int n_sym, int n_u, int n_t, const float *H, const float *u,
+                     double tau, float *G_out, float *f_out, double *Ainv_out, int nthreads)
+{
+    if (n_u <= 0 || n_u > 32 || n_t <= 0 || n_sc < 0 || n_sym <= 0 || !(tau > 0.0)) return -1;
+    const double ht = 0.5 * tau;
+    const double sg = ht * ht;
+    const double sf = -ht;
+    const int K = 2 * n_u;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int sc = 0; sc < n_sc; ++sc) {
+        cplx Ainv[32 * 32];
+        vpp_gram_inverse(n_u, n_t, H + (size_t)sc * (size_t)n_u * (size_t)n_t * 2u, Ainv);
+        if (Ainv_out) {
+            for (int e = 0; e < n_u * n_u; ++e) {
+                Ainv_out[((size_t)sc * n_u * n_u + e) * 2] = Ainv[e].re;
+                Ainv_out[((size_t)sc * n_u * n_u + e) * 2 + 1] = Ainv[e].im;
+            }
+        }
+        float *Gs = G_out + (size_t)sc * (size_t)K * (size_t)K;
+        for (int i = 0; i < n_u; ++i) {
+            for (int l = 0; l < n_u; ++l) {
+                cplx a = Ainv[i * n_u + l];
+                Gs[i * K + l] = (float)(sg * a.re);
+                Gs[(i + n_u) * K + (l + n_u)] = (float)(sg * a.re);
+                Gs[i * K + (l + n_u)] = (float)(sg * (-a.im));
+                Gs[(i + n_u) * K + l] = (float)(sg * a.im);
+            }
+        }
+        for (int sym = 0; sym < n_sym; ++sym) {
+            const float *us = u + ((size_t)sc * n_sym + sym) * (size_t)n_u * 2u;
+            float *fs = f_out + ((size_t)sc * n_sym + sym) * (size_t)K;
+            for (int i = 0; i < n_u; ++i) {
+                cplx z = {0.0, 0.0};
+                for (int l = 0; l < n_u; ++l) {
+                    cplx ul = {(double)us[2 * l], (double)us[2 * l + 1]};
+                    cplx v = cmul(Ainv[i * n_u + l], ul);
+                    z.re = z.re + v.re;
+                    z.im = z.im + v.im;
+                }
+                fs[i] = (float)(sf * z.re);
+                fs[i + n_u] = (float)(sf * z.im);
+            }
+        }
+    }
+    return 0;
+}
+
+int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,441 @@
+"""CPU oracle of the MMGaP Ising hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
+import this module.  It shares no code with the GPU library: the plain
+definitions are written out here in float64 numpy, and the stochastic chains
+(which must reproduce the GPU's spins under identical Philox streams) are the
+plain C loops of ``mmgap_oracle.c``.
+
+Paper passages followed (arXiv 2510.01579):
+
+* §2.1 Eq. 1 and Eq. ``ml``: y = Hx + noise, x_ML = argmin ||y - Hx||^2.
+* §2.1 MMSE: x_MMSE = (H^H H + rho I)^-1 H^H y, rho = E|noise|^2 / E|x|^2.
+* §2.2 ZF precoder W = H^H (H H^H)^-1 and the VPP problem
+  v* = argmin ||W (u + tau v)||; §3.3 rewrites it with y~ = W u and
+  H_p = -tau W / 2 as argmin_{v in 2Z} ||y~ - H_p v||, solved like detection
+  with an all-zeros vector in place of the MMSE solution.
+* §2.3 Ising problem; §3.2 "Processing Flow": N_a anneals per problem, each
+  anneal's final state is a candidate, candidates are ranked by the Eq. ``ml``
+  energy, the MMSE solution replaces a candidate whose energy is larger, and
+  the best candidate is returned.
+
+Readings (where the paper is silent), all shared with the GPU library's
+contract: binary-weighted spin encoding x_k = sum_b 2^(q-1-b) s_{k,b} of the
+odd PAM levels (VPP: two unit-weight spins per real dimension, levels
+{-2, 0, 2} = 2v); a single-spin-flip Metropolis anneal in place of CIM-CAC;
+couplings and fields built in float64 and rounded once to float32.
+
+Parity pins live in tests/test_oracle_*.py (closed forms, library routines,
+brute force, known-answer vectors, invariants).  The chain dynamics themselves
+have no numeric reference in the paper (its solver is CIM-CAC and its figures
+are not available): *parity unpinned* for solution quality versus the paper.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+def lib():
+    """Load (building if needed) the oracle's C library."""
+    global _lib
+    if _lib is None:
+        path = _build.build_oracle(force=False)
+        L = ctypes.CDLL(path)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        L.oracle_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.oracle_philox4x32_10.restype = None
+        L.oracle_draw16.argtypes = [ctypes.c_uint32] * 4 + [ctypes.c_uint64]
+        L.oracle_draw16.restype = ctypes.c_uint32
+        L.oracle_exp2_neg.argtypes = [ctypes.c_float]
+        L.oracle_exp2_neg.restype = ctypes.c_float
+        L.oracle_accept.argtypes = [ctypes.c_float, ctypes.c_uint32]
+        L.oracle_accept.restype = ctypes.c_int
+        L.oracle_exp2_coefficients.argtypes = [ctypes.c_void_p]
+        L.oracle_exp2_coefficients.restype = None
+        L.oracle_solve.argtypes = [
+            ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,  # n K q w
+            ctypes.c_void_p, ctypes.c_int, ctypes.c_long,                # G inst_per_G g_base
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,           # f x_fb inst_ids
+            ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+        L.oracle_solve.restype = ctypes.c_int
+        L.oracle_level_energy.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p]
+        L.oracle_level_energy.restype = ctypes.c_float
+        L.oracle_vpp_build.argtypes = [ctypes.c_int] * 4 + [ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_int]
+        L.oracle_vpp_build.restype = ctypes.c_int
+        L.oracle_max_threads.argtypes = []
+        L.oracle_max_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+# --------------------------------------------------------------------------
+# Constellation and encoding (reading of the paper's unspecified encoding)
+
+def qam_bits(qam: int) -> int:
+    """q = log2(M)/2 spins per real dimension."""
+    q = {4: 1, 16: 2, 64: 3, 256: 4}.get(int(qam))
+    if q is None:
+        raise ValueError(f"unsupported QAM order {qam}")
+    return q
+
+
+def qam_scale(qam: int) -> float:
+    """c with unit average energy: E|x|^2 = 2 c^2 (M-1)/3 = 1."""
+    return 1.0 / math.sqrt(2.0 * (qam - 1) / 3.0)
+
+
+def det_weights(qam: int) -> np.ndarray:
+    """Binary weights w_b = 2^(q-1-b), MSB first (int8)."""
+    q = qam_bits(qam)
+    return np.array([1 << (q - 1 - b) for b in range(q)], dtype=np.int8)
+
+
+VPP_WEIGHTS = np.array([1, 1], dtype=np.int8)
+
+
+def levels_from_spins(spins: np.ndarray, K: int, q: int, w: np.ndarray) -> np.ndarray:
+    s = np.asarray(spins, dtype=np.int64).reshape(-1, K, q)
+    return (s * np.asarray(w, dtype=np.int64)[None, None, :]).sum(axis=2)
+
+
+def vpp_tau(qam: int) -> float:
+    """tau = 2 (c_max + d/2) = 2 sqrt(M) c for the square M-QAM alphabet."""
+    return 2.0 * math.sqrt(qam) * qam_scale(qam)
+
+
+# --------------------------------------------------------------------------
+# Real decomposition and the Ising form (float64 definitions)
+
+def real_matrix(H: np.ndarray) -> np.ndarray:
+    """H_r = [[Re H, -Im H], [Im H, Re H]] so that (H x)_r = H_r x_r."""
+    A = H.real.astype(np.float64)
+    B = H.imag.astype(np.float64)
+    top = np.concatenate([A, -B], axis=-1)
+    bot = np.concatenate([B, A], axis=-1)
+    return np.concatenate([top, bot], axis=-2)
+
+
+def real_vector(y: np.ndarray) -> np.ndarray:
+    """y_r = [Re y; Im y] along the last axis."""
+    return np.concatenate([y.real, y.imag], axis=-1).astype(np.float64)
+
+
+def det_ising64(H: np.ndarray, y: np.ndarray, qam: int):
+    """float64 couplings and fields of the detection problem.
+
+    ||y - H c x||^2 = ||y||^2 + x^T (c^2 H_r^T H_r) x - 2 (c H_r^T y_r)^T x, so
+    G = c^2 H_r^T H_r (per subcarrier) and f = c H_r^T y_r (per instance).
+    G is made exactly symmetric by mirroring its upper triangle.
+    H: [n_sc][n_r][n_t]; y: [n_sc][n_sym][n_r].
+    """
+    c = qam_scale(qam)
+    c2 = 1.0 / (2.0 * (qam - 1) / 3.0)
+    Hr = real_matrix(H.astype(np.complex128))                 # [n_sc][2n_r][K]
+    Gr = np.einsum("sik,sil->skl", Hr, Hr)
+    iu = np.triu_indices(Gr.shape[-1], 1)
+    Gr[:, iu[1], iu[0]] = Gr[:, iu[0], iu[1]]
+    yr = real_vector(y.astype(np.complex128))                 # [n_sc][n_sym][2n_r]
+    fr = np.einsum("sik,sbi->sbk", Hr, yr)                     # [n_sc][n_sym][K]
+    return Gr * c2, fr * c
+
+
+def det_ising(H: np.ndarray, y: np.ndarray, qam: int):
+    """float32 couplings [n_sc][K][K] and fields [n_sc*n_sym][K], each rounded once."""
+    G64, f64 = det_ising64(H, y, qam)
+    K = G64.shape[-1]
+    return G64.astype(np.float32), f64.reshape(-1, K).astype(np.float32)
+
+
+def mmse(H: np.ndarray, y: np.ndarray, noise_var: float) -> np.ndarray:
+    """x_MMSE = (H^H H + rho I)^-1 H^H y with rho = sigma^2 (unit-energy symbols)."""
+    H = H.astype(np.complex128)
+    y = y.astype(np.complex128)
+    n_t = H.shape[-1]
+    Hh = np.conj(np.swapaxes(H, -1, -2))
+    A = Hh @ H + noise_var * np.eye(n_t)[None]
+    rhs = Hh @ np.swapaxes(y, -1, -2)                           # [n_sc][n_t][n_sym]
+    x = np.linalg.solve(A, rhs)
+    return np.swapaxes(x, -1, -2)                                # [n_sc][n_sym][n_t]
+
+
+def slice_levels(x: np.ndarray, qam: int) -> np.ndarray:
+    """Nearest odd PAM level per real dimension: 2 floor(t/2) + 1 with t = x/c,
+    clamped to +-(2^q - 1).  Returns int8 [..., 2 n_t] in real-form order."""
+    q = qam_bits(qam)
+    top = (1 << q) - 1
+    t = real_vector(x) / qam_scale(qam)
+    lv = 2.0 * np.floor(t / 2.0) + 1.0
+    lv = np.clip(lv, -top, top)
+    return lv.astype(np.int8)
+
+
+def levels_to_symbols(levels: np.ndarray, qam: int) -> np.ndarray:
+    """Real-form levels [..., 2 n_t] -> Gray-labelled symbol indices [..., n_t]."""
+    q = qam_bits(qam)
+    lv = np.asarray(levels, dtype=np.int64)
+    n_t = lv.shape[-1] // 2
+    top = (1 << q) - 1
+    pI = (lv[..., :n_t] + top) // 2
+    pQ = (lv[..., n_t:] + top) // 2
+    gI = pI ^ (pI >> 1)
+    gQ = pQ ^ (pQ >> 1)
+    return ((gI << q) | gQ).astype(np.uint8)
+
+
+def det_metric(H: np.ndarray, y: np.ndarray, levels: np.ndarray, qam: int) -> np.ndarray:
+    """||y - H c x||^2 (Eq. ml objective) in float64, per instance.
+
+    H [n_sc][n_r][n_t]; y [n_sc][n_sym][n_r]; levels [n_sc*n_sym][2 n_t]."""
+    n_sc, n_sym, n_r = y.shape
+    n_t = H.shape[-1]
+    lv = np.asarray(levels, dtype=np.float64).reshape(n_sc, n_sym, 2 * n_t)
+    x = qam_scale(qam) * (lv[..., :n_t] + 1j * lv[..., n_t:])
+    r = y.astype(np.complex128) - np.einsum("srt,sbt->sbr", H.astype(np.complex128), x)
+    return (np.abs(r) ** 2).sum(axis=-1).reshape(-1)
+
+
+# --------------------------------------------------------------------------
+# The anneal (C loops) and selection
+
+def solve(G, f, K, q, w, chains, sweeps, beta2, seed, x_fb=None, inst_per_G=1,
+          inst_ids=None, init_mode=0, nthreads=0, want_chain_energies=False):
+    """Best-of-`chains` Metropolis anneals per instance, with optional fallback.
+
+    G [n_G][K][K] float32 (instance n uses G[inst_ids[n] // inst_per_G - g_base]
+    where g_base is inst_ids.min() // inst_per_G); f [n][K]; x_fb [n][K] int8 or
+    None.  Returns dict(spins int8 [n][K*q], E float32 [n], win int32 [n],
+    chain_E [n][chains] if requested).
+    """
+    G = np.ascontiguousarray(G, dtype=np.float32).reshape(-1, K, K)
+    f = np.ascontiguousarray(f, dtype=np.float32).reshape(-1, K)
+    n = f.shape[0]
+    w = np.ascontiguousarray(w, dtype=np.int8)
+    if w.shape != (q,):
+        raise ValueError("w must have q entries")
+    beta2 = np.ascontiguousarray(beta2, dtype=np.float32)
+    if beta2.shape != (sweeps,):
+        raise ValueError("beta2 must have `sweeps` entries")
+    if inst_ids is None:
+        ids = None
+        g_base = 0
+    else:
+        ids = np.ascontiguousarray(inst_ids, dtype=np.uint32)
+        if ids.shape != (n,):
+            raise ValueError("inst_ids must have one entry per instance")
+        g_base = 0
+    if x_fb is not None:
+        x_fb = np.ascontiguousarray(x_fb, dtype=np.int8).reshape(n, K)
+    spins = np.zeros((n, K * q), dtype=np.int8)
+    E = np.zeros(n, dtype=np.float32)
+    win = np.zeros(n, dtype=np.int32)
+    chainE = np.zeros((n, chains), dtype=np.float32) if want_chain_energies else None
+    rc = lib().oracle_solve(n, K, q, _ptr(w), _ptr(G), int(inst_per_G), int(g_base), _ptr(f),
+                            _ptr(x_fb), _ptr(ids), int(chains), int(sweeps), _ptr(beta2),
+                            int(seed) & 0xFFFFFFFFFFFFFFFF, int(init_mode), _ptr(spins),
+                            _ptr(E), _ptr(win), _ptr(chainE), int(nthreads))
+    if rc != 0:
+        raise RuntimeError(f"oracle_solve failed ({rc})")
+    out = dict(spins=spins, E=E, win=win)
+    if chainE is not None:
+        out["chain_E"] = chainE
+    return out
+
+
+def level_energy32(G: np.ndarray, f: np.ndarray, levels: np.ndarray) -> float:
+    """The float32 selection energy of given levels (same arithmetic as the chains)."""
+    G = np.ascontiguousarray(G, dtype=np.float32)
+    f = np.ascontiguousarray(f, dtype=np.float32)
+    lv = np.ascontiguousarray(levels, dtype=np.int8)
+    return float(lib().oracle_level_energy(int(f.shape[-1]), _ptr(G), _ptr(f), _ptr(lv)))
+
+
+def detect(H, y, noise_var, qam, chains, sweeps, beta2, seed, inst_ids=None,
+           init_mode=0, nthreads=0):
+    """Uplink ML-MIMO detection through the Ising reduction (paper §3.2).
+
+    Returns dict(sym uint8 [n][n_t], metric float64 [n], levels int8 [n][K],
+    E float32 [n], win int32 [n], spins int8 [n][K q]) for the instances
+    inst = sc * n_sym + sym listed in inst_ids (all by default).
+    """
+    n_sc, n_sym, n_r = y.shape
+    n_t = H.shape[-1]
+    K, q = 2 * n_t, qam_bits(qam)
+    w = det_weights(qam)
+    G, f_all = det_ising(H, y, qam)
+    x_fb_all = slice_levels(mmse(H, y, noise_var), qam).reshape(-1, K)
+    ids = np.arange(n_sc * n_sym, dtype=np.uint32) if inst_ids is None \
+        else np.asarray(inst_ids, dtype=np.uint32)
+    res = solve(G, f_all[ids], K, q, w, chains, sweeps, beta2, seed,
+                x_fb=x_fb_all[ids], inst_per_G=n_sym, inst_ids=ids,
+                init_mode=init_mode, nthreads=nthreads)
+    lv = levels_from_spins(res["spins"], K, q, w).astype(np.int8)
+    sc = ids // n_sym
+    sy = ids % n_sym
+    H_sel = H[sc]
+    y_sel = y[sc, sy][:, None, :]
+    metric = det_metric(H_sel, y_sel, lv, qam)
+    res.update(sym=levels_to_symbols(lv, qam), metric=metric, levels=lv, inst_ids=ids,
+               x_fb=x_fb_all[ids])
+    return res
+
+
+# --------------------------------------------------------------------------
+# Downlink vector perturbation (paper §2.2, §3.3)
+
+def zf_precoder(H: np.ndarray) -> np.ndarray:
+    """W = H^H (H H^H)^-1 in float64.  H [.., n_u, n_t] -> W [.., n_t, n_u]."""
+    H = H.astype(np.complex128)
+    Hh = np.conj(np.swapaxes(H, -1, -2))
+    return Hh @ np.linalg.inv(H @ Hh)
+
+
+def vpp_build(H: np.ndarray, u: np.ndarray, tau: float, nthreads: int = 0):
+    """VPP couplings [n_sc][K][K], fields [n_sc*n_sym][K] (float32), and
+    A^-1 = (H H^H)^-1 [n_sc][n_u][n_u] complex128, by the fixed-order
+    LDL^H arithmetic of mmgap_oracle.c."""
+    H = np.ascontiguousarray(H, dtype=np.complex64)
+    u = np.ascontiguousarray(u, dtype=np.complex64)
+    n_sc, n_u, n_t = H.shape
+    n_sym = u.shape[1]
+    K = 2 * n_u
+    G = np.zeros((n_sc, K, K), dtype=np.float32)
+    f = np.zeros((n_sc * n_sym, K), dtype=np.float32)
+    Ainv = np.zeros((n_sc, n_u, n_u), dtype=np.complex128)
+    rc = lib().oracle_vpp_build(n_sc, n_sym, n_u, n_t, _ptr(H), _ptr(u), float(tau),
+                                _ptr(G), _ptr(f), _ptr(Ainv), int(nthreads))
+    if rc != 0:
+        raise RuntimeError(f"oracle_vpp_build failed ({rc})")
+    return G, f, Ainv
+
+
+def vpp_precode(H, u, qam, chains, sweeps, beta2, seed, tau=None, inst_ids=None,
+                init_mode=0, nthreads=0):
+    """Vector-perturbation precoding through the Ising reduction (paper §3.3).
+
+    Perturbation alphabet {-1, 0, 1} per real dimension, two unit-weight spins
+    each (levels 2v); fallback v = 0 (plain ZF).  Returns dict(v int8 [n][K],
+    x complex128 [n][n_t] = W (u + tau v), gamma float64 [n] = ||x||^2, E, win,
+    spins) for the listed instances.
+    """
+    n_sc, n_sym, n_u = u.shape
+    n_t = H.shape[-1]
+    K = 2 * n_u
+    tau = vpp_tau(qam) if tau is None or tau <= 0 else float(tau)
+    G, f_all, _ = vpp_build(H, u, tau, nthreads=nthreads)
+    ids = np.arange(n_sc * n_sym, dtype=np.uint32) if inst_ids is None \
+        else np.asarray(inst_ids, dtype=np.uint32)
+    x_fb = np.zeros((ids.size, K), dtype=np.int8)
+    res = solve(G, f_all[ids], K, 2, VPP_WEIGHTS, chains, sweeps, beta2, seed, x_fb=x_fb,
+                inst_per_G=n_sym, inst_ids=ids, init_mode=init_mode, nthreads=nthreads)
+    lv = levels_from_spins(res["spins"], K, 2, VPP_WEIGHTS)
+    v = (lv // 2).astype(np.int8)
+    sc = ids // n_sym
+    sy = ids % n_sym
+    W = zf_precoder(H[sc])                                       # [n][n_t][n_u]
+    pert = u[sc, sy].astype(np.complex128) + tau * (v[:, :n_u] + 1j * v[:, n_u:])
+    x = np.einsum("ntu,nu->nt", W, pert)
+    res.update(v=v, x=x, gamma=(np.abs(x) ** 2).sum(axis=-1), inst_ids=ids, tau=tau)
+    return res
+
+
+# --------------------------------------------------------------------------
+# Brute force (tiny sizes only) and the spin-domain expansion
+
+def brute_force_ml(H: np.ndarray, y: np.ndarray, qam: int) -> np.ndarray:
+    """Exhaustive Eq. ``ml`` over Omega^{n_t} for one instance: H [n_r][n_t],
+    y [n_r]; returns the minimising real-form levels (int8 [2 n_t])."""
+    q = qam_bits(qam)
+    n_t = H.shape[-1]
+    pam = np.arange(-(1 << q) + 1, 1 << q, 2)
+    grids = np.meshgrid(*([pam] * (2 * n_t)), indexing="ij")
+    cand = np.stack([g.reshape(-1) for g in grids], axis=1)      # [M^n_t][2 n_t]
+    x = qam_scale(qam) * (cand[:, :n_t] + 1j * cand[:, n_t:])
+    r = y.astype(np.complex128)[None, :] - x @ H.astype(np.complex128).T
+    cost = (np.abs(r) ** 2).sum(axis=1)
+    return cand[int(np.argmin(cost))].astype(np.int8)
+
+
+def brute_force_vpp(H: np.ndarray, u: np.ndarray, tau: float) -> tuple[np.ndarray, float]:
+    """Exhaustive VPP over v in {-1,0,1}^(2 n_u): H [n_u][n_t], u [n_u].
+    Returns (v int8 [2 n_u], gamma = ||W (u + tau v)||^2)."""
+    n_u = H.shape[0]
+    W = zf_precoder(H)
+    grids = np.meshgrid(*([np.array([-1, 0, 1])] * (2 * n_u)), indexing="ij")
+    cand = np.stack([g.reshape(-1) for g in grids], axis=1)
+    pert = u.astype(np.complex128)[None, :] + tau * (cand[:, :n_u] + 1j * cand[:, n_u:])
+    x = pert @ W.T
+    cost = (np.abs(x) ** 2).sum(axis=1)
+    i = int(np.argmin(cost))
+    return cand[i].astype(np.int8), float(cost[i])
+
+
+def spin_ising(G: np.ndarray, f: np.ndarray, q: int, w: np.ndarray):
+    """Expand the level-domain form into a dense spin Ising problem (paper §2.3).
+
+    With x_k = sum_b w_b s_{k,b} and spin index i = k q + b:
+      x^T G x - 2 f^T x = -sum_{i<j} J_ij s_i s_j - sum_i h_i s_i + const,
+      J_ij = -2 w_i w_j G_{k(i)k(j)} (i != j), h_i = 2 w_i f_{k(i)},
+      const = sum_i w_i^2 G_{k(i)k(i)}.
+    Returns float64 (J [N][N] zero diagonal, h [N], const).
+    """
+    G = np.asarray(G, dtype=np.float64)
+    f = np.asarray(f, dtype=np.float64)
+    K = G.shape[-1]
+    wv = np.tile(np.asarray(w, dtype=np.float64), K)
+    kk = np.repeat(np.arange(K), q)
+    J = -2.0 * wv[:, None] * wv[None, :] * G[kk][:, kk]
+    np.fill_diagonal(J, 0.0)
+    h = 2.0 * wv * f[kk]
+    const = float((wv ** 2 * G[kk, kk]).sum())
+    return J, h, const
+
+
+def max_threads() -> int:
+    return int(lib().oracle_max_threads())
+
+
+def philox(ctr, key):
+    c = (ctypes.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib().oracle_philox4x32_10(c, k, o)
+    return [int(v) for v in o]
+
+
+def draw16(i, t, ch, inst, seed) -> int:
+    return int(lib().oracle_draw16(i, t, ch, inst, int(seed) & 0xFFFFFFFFFFFFFFFF))
+
+
+def exp2_neg(z: float) -> float:
+    return float(lib().oracle_exp2_neg(z))
+
+
+def accept(z: float, m: int) -> bool:
+    return bool(lib().oracle_accept(z, m))
+
+
+def exp2_coefficients() -> np.ndarray:
+    out = np.zeros(7, dtype=np.float32)
+    lib().oracle_exp2_coefficients(_ptr(out))
+    return out
+
+
+def nthreads_env() -> int:
+    v = os.environ.get("OMP_NUM_THREADS")
+    return int(v) if v and v.isdigit() else 0

@@ -1,0 +1,405 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks one oracle function against something other than itself:
+published known-answer vectors, closed forms, library routines written
+differently, brute-force enumeration, or invariants of the Metropolis chain.
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from workload import synth as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- Philox
+def test_philox_known_answers():
+    """Philox4x32-10 against the published known-answer vectors (SC'11 / Random123)."""
+    rows = []
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                rows.append([int(v, 16) for v in line.split()])
+    assert len(rows) == 3
+    for r in rows:
+        assert O.philox(r[0:4], r[4:6]) == r[6:10]
+
+
+def test_draw16_uniform_chi2():
+    """16-bit draws are uniform: chi^2 over 256 bins of the top byte."""
+    seed = W.job_seed(11)
+    vals = np.array([O.draw16(i, t, ch, 3, seed) for i in range(16) for t in range(40)
+                     for ch in range(32)])
+    assert vals.max() < 65536
+    counts = np.bincount(vals >> 8, minlength=256)
+    exp = vals.size / 256
+    chi2 = ((counts - exp) ** 2 / exp).sum()
+    # 255 dof: mean 255, sd ~22.6; 6 sd bound
+    assert chi2 < 255 + 6 * 22.6
+
+
+def test_draw16_distinct_streams():
+    """Different (spin, sweep, chain, instance, key) give different draws."""
+    seed = W.job_seed(5)
+    base = [O.draw16(i, 0, 0, 0, seed) for i in range(8)]
+    assert len(set(base)) == 8
+    assert O.draw16(0, 1, 0, 0, seed) != base[0] or O.draw16(1, 1, 0, 0, seed) != base[1]
+    assert [O.draw16(i, 0, 1, 0, seed) for i in range(4)] != base[:4]
+    assert [O.draw16(i, 0, 0, 1, seed) for i in range(4)] != base[:4]
+    assert [O.draw16(i, 0, 0, 0, seed + 1) for i in range(4)] != base[:4]
+
+
+# ---------------------------------------------------------------- exp2 / acceptance
+def test_exp2_coefficients_are_taylor():
+    a = O.exp2_coefficients()
+    for k in range(7):
+        exact = (-math.log(2.0)) ** k / math.factorial(k)
+        assert abs(float(a[k]) - exact) <= 1e-7 * max(1.0, abs(exact))
+
+
+def test_exp2_against_numpy():
+    """2^-z on [0,16) within the truncation bound (ln2)^7/7!/0.5 plus float rounding,
+    and never below the true value (alternating series cut after a positive term)."""
+    z = np.linspace(0.0, 15.999, 4001, dtype=np.float32)
+    got = np.array([O.exp2_neg(float(v)) for v in z])
+    ref = np.exp2(-z.astype(np.float64))
+    rel = (got - ref) / ref
+    bound = (math.log(2.0) ** 7 / math.factorial(7)) / 0.5
+    assert np.max(np.abs(rel)) <= bound + 4e-7
+    assert np.min(rel) >= -4e-7
+
+
+def test_accept_rule_counts():
+    """For fixed z the number of accepted 16-bit draws matches 2^16 * 2^-z."""
+    for z in [-3.0, 0.0, 1e-7, 0.37, 1.0, 2.5, 7.25, 12.0, 15.5, 15.99, 16.0, 40.0,
+              float("inf"), float("nan")]:
+        acc = [O.accept(z, m) for m in range(0, 65536, 1)] if z in (0.37, 7.25) else None
+        if z <= 0:
+            assert O.accept(z, 65535) and O.accept(z, 0)
+            continue
+        if not (z < 16):
+            assert not O.accept(z, 0)
+            continue
+        if acc is not None:
+            n = sum(acc)
+            # accepted draws form a prefix m < T
+            assert all(acc[:n]) and not any(acc[n:])
+            assert abs(n / 65536 - 2.0 ** (-z)) <= 2.0 ** -16 + 3.1e-5 * 2.0 ** (-z)
+        # monotone: m = 0 accepted whenever 2^16 * 2^-z > 0
+        assert O.accept(z, 0)
+
+
+# ---------------------------------------------------------------- encoding
+@pytest.mark.parametrize("qam", [4, 16, 64, 256])
+def test_binary_encoding_bijection(qam):
+    """All 2^q spin patterns map one-to-one onto the odd PAM levels."""
+    q = O.qam_bits(qam)
+    w = O.det_weights(qam)
+    pats = np.array(list(itertools.product([-1, 1], repeat=q)), dtype=np.int8)
+    lv = O.levels_from_spins(pats.reshape(-1), 1 * len(pats), q, w).reshape(-1)
+    assert sorted(lv.tolist()) == list(range(-(1 << q) + 1, 1 << q, 2))
+
+
+def test_vpp_encoding():
+    pats = np.array(list(itertools.product([-1, 1], repeat=2)), dtype=np.int8)
+    lv = O.levels_from_spins(pats.reshape(-1), 4, 2, O.VPP_WEIGHTS).reshape(-1)
+    assert sorted(lv.tolist()) == [-2, 0, 0, 2]
+
+
+@pytest.mark.parametrize("qam", [4, 16, 64])
+def test_symbol_labels_roundtrip_and_gray(qam):
+    """Oracle decode inverts the generator's labelling; neighbours differ in one bit."""
+    q = O.qam_bits(qam)
+    idx = np.arange(qam)
+    li, lq = W.symbol_levels(idx, qam)
+    back = O.levels_to_symbols(np.stack([li, lq], axis=1), qam)[:, 0]
+    assert np.array_equal(back, idx.astype(np.uint8))
+    lv = np.arange(-(1 << q) + 1, 1 << q, 2)
+    lab = O.levels_to_symbols(np.stack([lv, np.full_like(lv, lv[0])], axis=1), qam)[:, 0] >> q
+    for a, b in zip(lab[:-1], lab[1:]):
+        assert bin(int(a) ^ int(b)).count("1") == 1
+
+
+# ---------------------------------------------------------------- real form / Ising
+def test_real_decomposition_identity():
+    rng = np.random.default_rng(1)
+    H = rng.standard_normal((5, 7, 3)) + 1j * rng.standard_normal((5, 7, 3))
+    x = rng.standard_normal((5, 3)) + 1j * rng.standard_normal((5, 3))
+    y = rng.standard_normal((5, 7)) + 1j * rng.standard_normal((5, 7))
+    lhs = (np.abs(y - np.einsum("srt,st->sr", H, x)) ** 2).sum(-1)
+    Hr = O.real_matrix(H)
+    rhs = ((O.real_vector(y) - np.einsum("sik,sk->si", Hr, O.real_vector(x))) ** 2).sum(-1)
+    assert np.allclose(lhs, rhs, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("qam,n_r,n_t", [(4, 4, 4), (16, 8, 8), (64, 16, 16), (16, 6, 3)])
+def test_energy_identity(qam, n_r, n_t):
+    """x^T G x - 2 f^T x = ||y - H c x||^2 - ||y||^2 for every level vector (FP64)."""
+    d = W.det_slot(21, n_r, n_t, qam, 3, 2, 12.0)
+    G, f = O.det_ising64(d.H, d.y, qam)
+    q = O.qam_bits(qam)
+    rng = np.random.default_rng(2)
+    for _ in range(5):
+        lv = (2 * rng.integers(0, 1 << q, size=(3 * 2, 2 * n_t)) - ((1 << q) - 1))
+        lv_ = lv.reshape(3, 2, 2 * n_t).astype(np.float64)
+        E = np.einsum("sbk,skl,sbl->sb", lv_, G, lv_) - 2 * np.einsum("sbk,sbk->sb", f, lv_)
+        res = O.det_metric(d.H, d.y, lv, qam).reshape(3, 2)
+        ynorm = (np.abs(d.y.astype(np.complex128)) ** 2).sum(-1)
+        assert np.allclose(E + ynorm, res, rtol=1e-10, atol=1e-10)
+    # float32 energy of the chain arithmetic stays within float rounding of FP64
+    G32, f32 = O.det_ising(d.H, d.y, qam)
+    lv0 = lv[0].astype(np.int8)
+    e32 = O.level_energy32(G32[0], f32[0], lv0)
+    e64 = lv0 @ G[0] @ lv0 - 2 * f[0, 0] @ lv0
+    scale = np.abs(lv0) @ np.abs(G[0]) @ np.abs(lv0) + 2 * np.abs(f[0, 0]) @ np.abs(lv0)
+    assert abs(e32 - e64) <= 8 * (2 * n_t + 2) * 2.0 ** -24 * scale
+
+
+@pytest.mark.parametrize("q,w", [(1, [1]), (2, [2, 1]), (3, [4, 2, 1]), (2, [1, 1])])
+def test_spin_expansion(q, w):
+    """Dense spin Ising (J, h, const) reproduces the level-domain energy exactly."""
+    G, f = W.random_structured_ising(3, 1, 1, 5)
+    G64 = G[0].astype(np.float64)
+    f64 = f[0].astype(np.float64)
+    J, h, c = O.spin_ising(G64, f64, q, np.array(w))
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        s = rng.choice([-1.0, 1.0], size=5 * q)
+        x = (s.reshape(5, q) * np.array(w)).sum(1)
+        E_lvl = x @ G64 @ x - 2 * f64 @ x
+        E_spin = -0.5 * s @ J @ s - h @ s + c
+        assert abs(E_lvl - E_spin) <= 1e-9 * (1 + abs(E_lvl))
+    assert np.allclose(J, J.T) and np.all(np.diag(J) == 0)
+
+
+# ---------------------------------------------------------------- MMSE / ZF / slicing
+def test_mmse_against_regularised_least_squares():
+    """MMSE = argmin ||y - Hx||^2 + sigma^2 ||x||^2, solved by lstsq on [H; sigma I]."""
+    d = W.det_slot(8, 8, 8, 16, 4, 3, 10.0)
+    x = O.mmse(d.H, d.y, d.noise_var)
+    s = math.sqrt(d.noise_var)
+    for sc in range(4):
+        Haug = np.vstack([d.H[sc].astype(np.complex128), s * np.eye(8)])
+        for b in range(3):
+            yaug = np.concatenate([d.y[sc, b].astype(np.complex128), np.zeros(8)])
+            ref = np.linalg.lstsq(Haug, yaug, rcond=None)[0]
+            assert np.allclose(x[sc, b], ref, rtol=1e-9, atol=1e-10)
+
+
+@pytest.mark.parametrize("qam", [4, 16, 64])
+def test_slicing_is_nearest_level(qam):
+    q = O.qam_bits(qam)
+    c = O.qam_scale(qam)
+    rng = np.random.default_rng(5)
+    x = (rng.standard_normal((200, 3)) + 1j * rng.standard_normal((200, 3))) * 1.3
+    lv = O.slice_levels(x, qam)
+    pam = np.arange(-(1 << q) + 1, 1 << q, 2)
+    t = O.real_vector(x) / c
+    ref = pam[np.argmin(np.abs(t[..., None] - pam), axis=-1)]
+    assert np.array_equal(lv, ref)
+
+
+def test_zf_precoder():
+    s = W.vpp_slot(9, 4, 6, 16, 3, 1)
+    Wz = O.zf_precoder(s.H)
+    for sc in range(3):
+        assert np.allclose(Wz[sc], np.linalg.pinv(s.H[sc].astype(np.complex128)), atol=1e-10)
+        assert np.allclose(s.H[sc] @ Wz[sc], np.eye(4), atol=1e-9)
+
+
+# ---------------------------------------------------------------- VPP couplings
+@pytest.mark.parametrize("n_u,n_t", [(2, 2), (4, 4), (8, 8), (16, 16), (4, 7)])
+def test_vpp_build_matches_plain_definition(n_u, n_t):
+    """LDL^H-based couplings equal the Gram / matched filter of H_p = -tau W / 2
+    with y~ = W u (paper §3.3), W = pinv(H) from numpy."""
+    s = W.vpp_slot(31 + n_u, n_u, n_t, 16, 6, 3)
+    tau = O.vpp_tau(16)
+    G, f, Ainv = O.vpp_build(s.H, s.u, tau)
+    for sc in range(6):
+        H = s.H[sc].astype(np.complex128)
+        assert np.allclose(Ainv[sc], np.linalg.inv(H @ H.conj().T), rtol=1e-9,
+                           atol=1e-9 * np.abs(Ainv[sc]).max())
+        Wz = np.linalg.pinv(H)
+        Hp = -tau * Wz / 2
+        Hpr = O.real_matrix(Hp)
+        Gref = Hpr.T @ Hpr
+        assert np.allclose(G[sc], Gref, rtol=0, atol=2e-6 * np.abs(Gref).max())
+        assert np.array_equal(G[sc], G[sc].T)
+        for b in range(3):
+            yt = Wz @ s.u[sc, b].astype(np.complex128)
+            fref = Hpr.T @ O.real_vector(yt)
+            assert np.allclose(f[sc * 3 + b], fref, rtol=0, atol=2e-6 * np.abs(fref).max() + 1e-12)
+
+
+def test_vpp_energy_identity():
+    """E(l) + ||W u||^2 = ||W (u + tau l / 2)||^2 for l = 2v."""
+    s = W.vpp_slot(41, 4, 4, 16, 2, 2)
+    tau = O.vpp_tau(16)
+    G, f, _ = O.vpp_build(s.H, s.u, tau)
+    rng = np.random.default_rng(6)
+    for sc in range(2):
+        Wz = O.zf_precoder(s.H[sc])
+        for b in range(2):
+            u = s.u[sc, b].astype(np.complex128)
+            for _ in range(5):
+                v = rng.integers(-1, 2, size=8)
+                lv = 2 * v
+                E = lv @ G[sc].astype(np.float64) @ lv - 2 * f[sc * 2 + b].astype(np.float64) @ lv
+                lhs = E + np.sum(np.abs(Wz @ u) ** 2)
+                rhs = np.sum(np.abs(Wz @ (u + tau * (v[:4] + 1j * v[4:]))) ** 2)
+                assert abs(lhs - rhs) <= 1e-5 * max(1.0, rhs)
+
+
+# ---------------------------------------------------------------- brute force
+def test_brute_force_ml_noiseless_recovers_symbols():
+    d = W.det_slot(12, 3, 2, 16, 4, 1, 300.0)
+    for sc in range(4):
+        lv = O.brute_force_ml(d.H[sc], d.y[sc, 0], 16)
+        assert np.array_equal(O.levels_to_symbols(lv, 16), d.sym[sc, 0])
+
+
+def test_brute_force_vpp_not_worse_than_zf():
+    s = W.vpp_slot(13, 2, 2, 16, 5, 1)
+    tau = O.vpp_tau(16)
+    for sc in range(5):
+        v, g = O.brute_force_vpp(s.H[sc], s.u[sc, 0], tau)
+        Wz = O.zf_precoder(s.H[sc])
+        g_zf = np.sum(np.abs(Wz @ s.u[sc, 0].astype(np.complex128)) ** 2)
+        assert g <= g_zf + 1e-12
+        x = Wz @ (s.u[sc, 0] + tau * (v[:2] + 1j * v[2:]))
+        assert abs(np.sum(np.abs(x) ** 2) - g) <= 1e-9 * g
+
+
+# ---------------------------------------------------------------- chains vs brute force
+def test_detect_c1_reaches_ml():
+    """4x4 QPSK, 64 subcarriers, 10 dB, 32 chains x 100 sweeps: the anneal finds the
+    brute-force ML solution (256 candidates) on (almost) every instance."""
+    d = W.det_slot(0, 4, 4, 4, 64, 1, 10.0)
+    b0, b1 = W.det_beta_range(4, 4, d.noise_var)
+    r = O.detect(d.H, d.y, d.noise_var, 4, 32, 100, W.linear_beta2(100, b0, b1), W.job_seed(0))
+    ml = np.array([O.brute_force_ml(d.H[s], d.y[s, 0], 4) for s in range(64)])
+    assert np.mean(np.all(ml == r["levels"], axis=1)) >= 0.97
+
+
+@pytest.mark.parametrize("qam", [16, 64])
+def test_detect_2x2_reaches_ml(qam):
+    d = W.det_slot(14, 2, 2, qam, 12, 2, 18.0)
+    b0, b1 = W.det_beta_range(qam, 2, d.noise_var)
+    r = O.detect(d.H, d.y, d.noise_var, qam, 32, 100, W.linear_beta2(100, b0, b1), W.job_seed(7))
+    ml = np.array([O.brute_force_ml(d.H[i // 2], d.y[i // 2, i % 2], qam) for i in range(24)])
+    assert np.mean(np.all(ml == r["levels"], axis=1)) >= 0.9
+
+
+def test_vpp_small_reaches_brute_force():
+    s = W.vpp_slot(15, 2, 2, 16, 10, 2)
+    tau = O.vpp_tau(16)
+    b0, b1 = W.vpp_beta_range(16, 2)
+    r = O.vpp_precode(s.H, s.u, 16, 32, 100, W.linear_beta2(100, b0, b1), W.job_seed(8))
+    bf = np.array([O.brute_force_vpp(s.H[i // 2], s.u[i // 2, i % 2], tau)[1] for i in range(20)])
+    assert np.mean(r["gamma"] <= bf * (1 + 1e-9)) >= 0.9
+    Wz = O.zf_precoder(s.H)
+    g_zf = (np.abs(np.einsum("stu,sbu->sbt", Wz, s.u.astype(np.complex128))) ** 2).sum(-1)
+    assert np.all(r["gamma"] <= g_zf.reshape(-1) * (1 + 1e-5) + 1e-9)
+
+
+# ---------------------------------------------------------------- Metropolis invariants
+def test_fixed_beta_boltzmann_histogram():
+    """At constant beta the chain's final state follows exp(-beta E) (chi^2, 8 states)."""
+    G = np.array([[[1.0, 0.3, -0.2], [0.3, 0.8, 0.5], [-0.2, 0.5, 1.2]]], dtype=np.float32)
+    f = np.array([[0.2, -0.35, 0.1]], dtype=np.float32)
+    beta = 0.9
+    S = 12
+    beta2 = np.full(S, beta / math.log(2.0), dtype=np.float32)
+    n_inst = 600
+    chains = 64
+    r = O.solve(G, np.repeat(f, n_inst, 0), 3, 1, np.array([1], np.int8), chains, S, beta2,
+                W.job_seed(21), inst_per_G=n_inst, want_chain_energies=True)
+    states = np.array(list(itertools.product([-1, 1], repeat=3)), dtype=np.float64)
+    Es = np.array([s @ G[0] @ s - 2 * f[0] @ s for s in states])
+    assert len(set(np.round(Es, 5))) == 8
+    chainE = r["chain_E"].reshape(-1).astype(np.float64)
+    idx = np.argmin(np.abs(chainE[:, None] - Es[None, :]), axis=1)
+    assert np.max(np.abs(chainE - Es[idx])) < 1e-5
+    counts = np.bincount(idx, minlength=8)
+    p = np.exp(-beta * (Es - Es.min()))
+    p /= p.sum()
+    expct = p * chainE.size
+    chi2 = ((counts - expct) ** 2 / expct).sum()
+    assert chi2 < 30.0          # 7 dof: p(chi2 > 30) ~ 1e-4
+
+
+def test_zero_temperature_ends_in_local_minimum():
+    """With beta -> infinity every final state is a single-flip local minimum."""
+    G, f = W.random_structured_ising(4, 1, 40, 8)
+    q, w = 2, np.array([2, 1], np.int8)
+    S = 30
+    beta2 = np.full(S, 1e30, dtype=np.float32)
+    r = O.solve(G, f, 8, q, w, 1, S, beta2, W.job_seed(22), inst_per_G=40)
+    G64 = G[0].astype(np.float64)
+    for n in range(40):
+        s = r["spins"][n].astype(np.float64)
+        x = (s.reshape(8, q) * w).sum(1)
+        E0 = x @ G64 @ x - 2 * f[n].astype(np.float64) @ x
+        for i in range(8 * q):
+            k, b = divmod(i, q)
+            x2 = x.copy()
+            x2[k] -= 2 * w[b] * s[i]
+            E1 = x2 @ G64 @ x2 - 2 * f[n].astype(np.float64) @ x2
+            assert E1 >= E0 - 1e-4 * (1 + abs(E0))
+
+
+def test_selection_and_fallback_rule():
+    """E_out = min over chains (lowest index on ties); the fallback wins only when
+    strictly lower (paper §3.2: an anneal worse than the MMSE solution is replaced)."""
+    d = W.det_slot(23, 8, 8, 16, 6, 4, 20.0)
+    G, f = O.det_ising(d.H, d.y, 16)
+    x_fb = O.slice_levels(O.mmse(d.H, d.y, d.noise_var), 16).reshape(-1, 16)
+    beta2 = np.zeros(1, dtype=np.float32)        # one sweep at infinite temperature
+    r = O.solve(G, f, 16, 2, O.det_weights(16), 8, 1, beta2, W.job_seed(9), x_fb=x_fb,
+                inst_per_G=4, want_chain_energies=True)
+    n_fb = 0
+    for n in range(24):
+        ce = r["chain_E"][n]
+        best = int(np.argmin(ce))
+        efb = O.level_energy32(G[n // 4], f[n], x_fb[n])
+        if efb < ce[best]:
+            assert r["win"][n] == 8 and r["E"][n] == np.float32(efb)
+            lv = O.levels_from_spins(r["spins"][n], 16, 2, O.det_weights(16))[0]
+            assert np.array_equal(lv, x_fb[n])
+            n_fb += 1
+        else:
+            assert r["win"][n] == best and r["E"][n] == ce[best]
+    assert n_fb > 0
+
+
+def test_subset_of_instances_is_stream_invariant():
+    """Solving a subset reproduces the full run (streams keyed by instance id)."""
+    d = W.det_slot(24, 4, 4, 16, 8, 3, 15.0)
+    b0, b1 = W.det_beta_range(16, 4, d.noise_var)
+    beta2 = W.linear_beta2(30, b0, b1)
+    full = O.detect(d.H, d.y, d.noise_var, 16, 16, 30, beta2, W.job_seed(3))
+    ids = np.array([23, 0, 7, 11], dtype=np.uint32)
+    sub = O.detect(d.H, d.y, d.noise_var, 16, 16, 30, beta2, W.job_seed(3), inst_ids=ids)
+    assert np.array_equal(sub["spins"], full["spins"][ids])
+    assert np.array_equal(sub["E"], full["E"][ids])
+
+
+def test_final_energy_matches_fp64_of_final_levels():
+    d = W.det_slot(25, 8, 8, 16, 5, 4, 15.0)
+    b0, b1 = W.det_beta_range(16, 8, d.noise_var)
+    r = O.detect(d.H, d.y, d.noise_var, 16, 16, 40, W.linear_beta2(40, b0, b1), W.job_seed(4))
+    G, f = O.det_ising64(d.H, d.y, 16)
+    f = f.reshape(-1, 16)
+    for n in range(20):
+        x = r["levels"][n].astype(np.float64)
+        e64 = x @ G[n // 4] @ x - 2 * f[n] @ x
+        scale = np.abs(x) @ np.abs(G[n // 4]) @ np.abs(x) + 2 * np.abs(f[n]) @ np.abs(x)
+        assert abs(float(r["E"][n]) - e64) <= 40 * 2.0 ** -24 * scale
+        # reported metric is the FP64 residual: E + ||y||^2
+        yn = np.sum(np.abs(d.y[n // 4, n % 4].astype(np.complex128)) ** 2)
+        assert abs(r["metric"][n] - (e64 + yn)) <= 1e-9 * max(1.0, r["metric"][n])
