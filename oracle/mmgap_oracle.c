@@ -26,7 +26,7 @@
  *   flip of s_i   i = k*q + b,  d = -2 w_b s_i            (a power of two)
  *                 dE = d * ((g_k + g_k) + d * G_kk)
  *                 z  = beta2_t * dE                       (beta2 = beta*log2 e)
- *                 accept iff z <= 0, or z < 16 and m < 2^16 * 2^-z,
+ *                 accept iff (m + 1) <= 2^16 * 2^-z, z clamped to [0, 32],
  *                 m = 16-bit Philox draw, 2^-z evaluated as below
  *   on accept     s_i = -s_i;  g_j = g_j + G_kj * d for all j
  *   energy        E = sum_k x_k * (g_k - f_k)             (left to right, no FMA)
@@ -117,16 +117,18 @@ static float exp2_neg_frac(float r)
     return p;
 }
 
-/* Metropolis test on the scaled energy change z = beta2 * dE.              */
+/* Metropolis test on the scaled energy change z = beta2 * dE with the 16-bit
+ * draw m read as the uniform u = (m + 1) / 2^16 in (0, 1]: accept iff
+ * u <= 2^-z.  z is clamped to [0, 32] first (NaN clamps to 0), n = floor(z),
+ * r = z - n, and 2^16 * 2^-z = ldexp(2^-r, 16 - n) is exact scaling of the
+ * polynomial value.  z <= 0 always accepts (threshold 2^16); z > 16 never does. */
 static int metropolis_accept(float z, uint32_t m)
 {
-    if (z <= 0.0f) return 1;
-    if (!(z < 16.0f)) return 0;                  /* also rejects NaN */
-    float fl = floorf(z);
-    int n = (int)fl;
-    float r = z - fl;                            /* exact */
-    float thr = ldexpf(exp2_neg_frac(r), 16 - n); /* 2^16 * 2^-z, exact scaling */
-    return (float)m < thr;
+    const float zc = fminf(fmaxf(z, 0.0f), 32.0f);
+    const int n = (int)zc;
+    const float r = zc - (float)n;               /* exact */
+    const float thr = ldexpf(exp2_neg_frac(r), 16 - n);
+    return (float)(m + 1u) <= thr;
 }
 
 float oracle_exp2_neg(float z)

@@ -75,23 +75,21 @@ def test_exp2_against_numpy():
 
 
 def test_accept_rule_counts():
-    """For fixed z the number of accepted 16-bit draws matches 2^16 * 2^-z."""
-    for z in [-3.0, 0.0, 1e-7, 0.37, 1.0, 2.5, 7.25, 12.0, 15.5, 15.99, 16.0, 40.0,
-              float("inf"), float("nan")]:
-        acc = [O.accept(z, m) for m in range(0, 65536, 1)] if z in (0.37, 7.25) else None
+    """Metropolis with u = (m+1)/2^16: for fixed z the accepted draws are the prefix
+    m + 1 <= 2^16 2^-z, their count matches 2^16 2^-z, z <= 0 always accepts and
+    z > 16 never does."""
+    for z in [-3.0, 0.0, 1e-7, 0.37, 1.0, 2.5, 7.25, 12.0, 15.5, 15.99, 16.0, 16.01,
+              17.0, 40.0, float("inf"), float("-inf")]:
+        acc = np.array([O.accept(z, m) for m in range(65536)])
+        n = int(acc.sum())
+        assert acc[:n].all() and not acc[n:].any()
         if z <= 0:
-            assert O.accept(z, 65535) and O.accept(z, 0)
-            continue
-        if not (z < 16):
-            assert not O.accept(z, 0)
-            continue
-        if acc is not None:
-            n = sum(acc)
-            # accepted draws form a prefix m < T
-            assert all(acc[:n]) and not any(acc[n:])
+            assert n == 65536
+        elif z > 16:
+            assert n == 0
+        else:
             assert abs(n / 65536 - 2.0 ** (-z)) <= 2.0 ** -16 + 3.1e-5 * 2.0 ** (-z)
-        # monotone: m = 0 accepted whenever 2^16 * 2^-z > 0
-        assert O.accept(z, 0)
+    assert sum(O.accept(16.0, m) for m in range(4)) == 1
 
 
 # ---------------------------------------------------------------- encoding
