@@ -1,0 +1,171 @@
+/*
+ * mmgap.h -- C ABI of the MI355X (gfx950) Ising hot path for uplink ML-MIMO
+ * detection and downlink vector-perturbation precoding, after "MMGaP:
+ * Multi-User MIMO Detection and Precoding using GPU-assisted Physics-inspired
+ * Computation" (arXiv 2510.01579).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  * Buffers are DEVICE pointers owned by the caller unless marked (host).
+ *    The library keeps no caller pointer after a call returns.
+ *  * Complex data are interleaved complex64 (re, im float32 pairs), row-major.
+ *  * Every compute call is asynchronous on `stream` (a hipStream_t; NULL means
+ *    the legacy default stream).  Results are valid once the stream reaches
+ *    the point where the call was enqueued.
+ *  * Return value: MMGAP_OK (0) or a negative mmgap_status.  A message for the
+ *    last failure of a context is returned by mmgap_last_error(ctx).  Nothing
+ *    throws across this boundary.  Host-side checks (shapes, NULL pointers,
+ *    unsupported sizes) fail before anything is enqueued; a device fault or a
+ *    failed launch is reported as MMGAP_EDEVICE.
+ *  * Instance numbering: problem instance n = sc * n_sym + sym.  The Philox
+ *    stream of every chain is keyed by (schedule.seed, n, chain, sweep, spin),
+ *    so results do not depend on how instances are grouped into launches.
+ *  * A context must not be used by two host threads at once.
+ *
+ * Problem statement (paper §2.1 Eq. 1 and Eq. ml; §2.2; §3.3):
+ *   DET  y = H x + noise, H is n_rx x n_tx per subcarrier, x in Omega^n_tx
+ *        (square M-QAM, unit average energy); find argmin ||y - H x||^2.
+ *   VPP  H is n_rx (users) x n_tx (antennas); W = H^H (H H^H)^-1 (zero forcing);
+ *        find v in {-1,0,1}^(2 n_rx) (real and imaginary part of a Gaussian
+ *        integer per user) minimising ||W (u + tau v)||^2.
+ * Ising reduction (paper §2.3, §3.2; level-domain form of this library):
+ *   E(x) = x^T G x - 2 f^T x,  x_k = sum_b w_b s_{k,b},  s in {-1,+1},
+ *   K real dimensions, q spins per dimension, spin index i = k q + b.
+ *   DET: K = 2 n_tx, q = log2(M)/2, w_b = 2^(q-1-b), G = c^2 H_r^T H_r,
+ *        f = c H_r^T y_r (H_r, y_r: real decomposition), so that
+ *        E(x) = ||y - c H_r x||^2 - ||y||^2.
+ *   VPP: K = 2 n_rx, q = 2, w = (1, 1), levels {-2, 0, 2} = 2 v,
+ *        G = (tau/2)^2 Re-form((H H^H)^-1), f = -(tau/2) Re-form((H H^H)^-1 u),
+ *        so that E(x) = ||W (u + tau v)||^2 - ||W u||^2.
+ */
+#ifndef MMGAP_H
+#define MMGAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MMGAP_OK = 0,
+    MMGAP_EINVAL = -1,        /* bad argument: NULL pointer, negative size, bad enum */
+    MMGAP_ENOMEM = -2,        /* scratch would exceed the context's HBM budget */
+    MMGAP_EDEVICE = -3,       /* HIP runtime or launch failure */
+    MMGAP_EUNSUPPORTED = -4,  /* valid but outside the supported sizes */
+    MMGAP_EBUSY = -5          /* serving queue full or budget exhausted (server only) */
+} mmgap_status;
+
+enum { MMGAP_KIND_DET = 0, MMGAP_KIND_VPP = 1 };
+
+typedef struct mmgap_ctx mmgap_ctx;
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the scratch
+ * the context may hold (0 = 16 GiB).  *out receives the context. */
+int mmgap_create(mmgap_ctx **out, int device, size_t hbm_budget_bytes);
+/* Synchronise the context's device, free its scratch, destroy it. */
+int mmgap_destroy(mmgap_ctx *ctx);
+/* Message of the last failure of `ctx` (or of mmgap_create when ctx is NULL).
+ * The string stays valid until the next call on the same context. */
+const char *mmgap_last_error(const mmgap_ctx *ctx);
+
+typedef struct {
+    int kind;          /* MMGAP_KIND_DET or MMGAP_KIND_VPP */
+    int n_rx, n_tx;    /* H is n_rx x n_tx; DET: n_tx <= 16, n_rx <= 64; VPP: n_rx <= 16, n_tx <= 64 */
+    int qam;           /* 4, 16 or 64 */
+    int n_sc, n_sym;   /* H is held per subcarrier for n_sym symbols; n_sym <= 64 */
+    float noise_var;   /* DET: sigma^2 per complex receive sample (MMSE regulariser) */
+    float tau;         /* VPP: perturbation spacing; <= 0 selects 2 sqrt(M) c = 2 (c_max + d/2) */
+} mmgap_problem;
+
+typedef struct {
+    int chains;            /* independent anneals per instance, 1..1024 */
+    int sweeps;            /* full sweeps over all spins per anneal, 1..8192 */
+    const float *beta2;    /* (host) [sweeps] inverse temperature times log2(e) per sweep, >= 0, finite */
+    uint64_t seed;         /* Philox4x32-10 key: (seed & 0xffffffff, seed >> 32) */
+    int init;              /* 0: random initial spins from Philox; 1: start from the fallback levels */
+} mmgap_schedule;
+
+/*
+ * mmgap_build_ising -- pre-processing (paper §3.2 "pre-processing kernel": the
+ * Ising coefficients of every problem instance; §3.3 for VPP) plus the linear
+ * fallback (§2.1 MMSE for DET; the all-zeros perturbation for VPP, §3.3).
+ *   H        [n_sc][n_rx][n_tx] complex64
+ *   y_or_u   DET: y [n_sc][n_sym][n_rx] complex64; VPP: u [n_sc][n_sym][n_rx] complex64
+ *   G        [n_sc][K][K] float32, symmetric (out)
+ *   f        [n_sc*n_sym][K] float32 (out)
+ *   x_fallback [n_sc*n_sym][K] int8 levels (out, nullable): DET = MMSE estimate
+ *            sliced to the nearest PAM level; VPP = 0
+ *   J_dense  [n_sc][N][N] float32 (out, nullable), N = K q: spin couplings,
+ *            J_ij = -2 w_i w_j G_{k(i)k(j)}, zero diagonal
+ *   h_dense  [n_sc*n_sym][N] float32 (out, nullable): h_i = 2 w_i f_{k(i)}
+ *   e_const  [n_sc*n_sym] float32 (out, nullable): sum_i w_i^2 G_{k(i)k(i)} plus
+ *            ||y||^2 (DET) or ||W u||^2 (VPP), so that
+ *            -sum_{i<j} J_ij s_i s_j - sum_i h_i s_i + e_const is the residual
+ *            ||y - H x||^2 (DET) or the transmit energy ||W (u + tau v)||^2 (VPP).
+ * Couplings and fields are accumulated in float64 and rounded once to float32.
+ */
+int mmgap_build_ising(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H,
+                      const void *y_or_u, float *G, float *f, signed char *x_fallback,
+                      float *J_dense, float *h_dense, float *e_const, void *stream);
+
+/*
+ * mmgap_solve -- solver + post-processing (paper §3.2 "solver kernel" and
+ * "post-processing kernel"): `chains` independent single-spin-flip Metropolis
+ * anneals per instance from random initial states, each anneal's final state a
+ * candidate ranked by its energy, the best candidate kept; a fallback
+ * replaces it only when its energy is strictly lower.
+ *   n_inst       number of instances (>= 0)
+ *   K, q, w      structure: K <= 32 real dimensions, q <= 4 spins each,
+ *                w (host) [q] int8 weights, each a power of two in 1..64
+ *   G            [n_inst/inst_per_G rounded up][K][K] float32, symmetric; instance n uses
+ *                G[n / inst_per_G]
+ *   f            [n_inst][K] float32
+ *   x_fallback   [n_inst][K] int8 levels (nullable: no fallback)
+ *   spins_out    [n_inst][K*q] int8, +1/-1 (out)
+ *   e_out        [n_inst] float32 energy x^T G x - 2 f^T x of the result (out)
+ *   win_out      [n_inst] int32 winning chain index, `chains` = fallback (out, nullable)
+ * Chain arithmetic (float32, round-to-nearest): g = G x - f; flip of spin i
+ * changes x_k by d = -2 w_b s_i with dE = d (2 g_k + d G_kk); z = beta2_t dE;
+ * accepted iff z <= 0 or (z < 16 and m < 2^16 2^-z) with m a 16-bit Philox draw
+ * (counter (i/8, t, chain, n)); on acceptance g_j += G_kj d.  Sweeps visit
+ * i = 0..K q - 1 in order.  Ties in energy keep the lowest chain index.
+ */
+int mmgap_solve(mmgap_ctx *ctx, int n_inst, int K, int q, const signed char *w,
+                const float *G, int inst_per_G, const float *f, const signed char *x_fallback,
+                const mmgap_schedule *sched, signed char *spins_out, float *e_out,
+                int *win_out, void *stream);
+
+/*
+ * mmgap_detect -- uplink ML-MIMO detection (paper §3.2; Eq. ml): build,
+ * anneal, select, decode.  H [n_sc][n_rx][n_tx], y [n_sc][n_sym][n_rx]
+ * complex64; prob->kind must be MMGAP_KIND_DET.
+ *   sym_out     [n_sc*n_sym][n_tx] uint8 Gray-labelled symbol indices (out): for
+ *               PAM levels (lI, lQ), p = (l + 2^q - 1)/2, g = p ^ (p >> 1),
+ *               index = (gI << q) | gQ; the point is c (lI + j lQ)
+ *   metric_out  [n_sc*n_sym] float32 ||y - H x||^2 of the result, evaluated in
+ *               float64 (out, nullable)
+ */
+int mmgap_detect(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, const void *y,
+                 const mmgap_schedule *sched, unsigned char *sym_out, float *metric_out,
+                 void *stream);
+
+/*
+ * mmgap_vpp_precode -- downlink vector-perturbation precoding (paper §2.2 Eq.
+ * VPP, §3.3): the same solver on (H_p = -tau W/2, y~ = W u) with the all-zeros
+ * fallback.  H [n_sc][n_rx][n_tx], u [n_sc][n_sym][n_rx] complex64;
+ * prob->kind must be MMGAP_KIND_VPP.
+ *   v_out      [n_sc*n_sym][2 n_rx] int8 in {-1,0,1}: real parts then imaginary (out)
+ *   x_out      [n_sc*n_sym][n_tx] complex64 W (u + tau v), float64 internally (out, nullable)
+ *   gamma_out  [n_sc*n_sym] float32 ||W (u + tau v)||^2 (out, nullable)
+ */
+int mmgap_vpp_precode(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, const void *u,
+                      const mmgap_schedule *sched, signed char *v_out, void *x_out,
+                      float *gamma_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MMGAP_H */

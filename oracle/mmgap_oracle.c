@@ -21,15 +21,18 @@
  *     (level-domain) Ising form E(x) = x^T G x - 2 f^T x with
  *     x_k = sum_b w_b s_{k,b}, s in {-1,+1}.
  *
- * The chain arithmetic, in the order the oracle performs it:
- *   fresh field   g_k = (sum_{l<K} G_kl * x_l) - f_k      (left to right, no FMA)
- *   flip of s_i   i = k*q + b,  d = -2 w_b s_i            (a power of two)
- *                 dE = d * ((g_k + g_k) + d * G_kk)
- *                 z  = beta2_t * dE                       (beta2 = beta*log2 e)
- *                 accept iff (m + 1) <= 2^16 * 2^-z, z clamped to [0, 32],
- *                 m = 16-bit Philox draw, 2^-z evaluated as below
- *   on accept     s_i = -s_i;  g_j = g_j + G_kj * d for all j
- *   energy        E = sum_k x_k * (g_k - f_k)             (left to right, no FMA)
+ * The chain arithmetic, in the order the oracle performs it (float32, RNE;
+ * "fma" is a single-rounding fused multiply-add, fmaf):
+ *   field of k    g_k = fma(G_k,K-1, x_K-1, ... fma(G_k0, x_0, -f_k))   (l ascending),
+ *                 recomputed from the current levels at every visit of k
+ *   flip of s_i   i = k*q + b, d = -2 w_b s_i                     (a power of two)
+ *                 dE = d * ((g_k + g_k) + d * G_kk);  z = beta2_t * dE
+ *                 j = floor(64 z) clamped to [0, 1024] (z <= 0 or NaN -> 0)
+ *                 accept iff m < T[j], m the 16-bit Philox draw,
+ *                 T[j] = round(2^16 * 2^(-j/64)) for j < 1024, T[1024] = 0
+ *   on accept     s_i = -s_i;  x_k = x_k + d;  g_k = fma(G_kk, d, g_k)
+ *   energy        E = fma(x_K-1, g_K-1 - f_K-1, ... fma(x_0, g_0 - f_0, 0))
+ *                 with fresh fields g;  E = x^T G x - 2 f^T x
  */
 #include <math.h>
 #include <stdint.h>
@@ -89,91 +92,70 @@ uint32_t oracle_draw16(uint32_t i, uint32_t t, uint32_t ch, uint32_t inst, uint6
 }
 
 /* ------------------------------------------------------------------------ */
-/* 2^-r on [0,1): Taylor series of e^(-r ln 2) truncated after degree 6,
- * coefficients a_k = (-ln 2)^k / k! formed in double by the recurrence
- * a_k = (a_{k-1} * (-ln 2)) / k and rounded once to float, evaluated by Horner's
- * rule with one fused multiply-add (fmaf, a single rounding) per step.      */
-#define EXP2_DEGREE 6
-static float exp2_coef[EXP2_DEGREE + 1];
-static int exp2_ready = 0;
+/* Metropolis acceptance with a 16-bit uniform: the move is accepted with
+ * probability 2^-z, z = beta * dE * log2(e) (beta2 = beta log2 e).  z is
+ * quantised down to a multiple of 1/64 and the threshold is tabulated:
+ * T[j] = round(2^16 * 2^(-j/64)) (no entry lies within 1e-3 of a rounding tie,
+ * so any double-precision exp2 gives the same integers); T[1024] = 0 rejects
+ * every move with z >= 16.  Accept iff m < T[j]: probability T[j] / 2^16.    */
+#define ACCEPT_STEPS 1024
+static uint32_t accept_table[ACCEPT_STEPS + 1];
+static int accept_ready = 0;
 
-static void exp2_init(void)
+static void accept_init(void)
 {
-    if (exp2_ready) return;
-    const double ln2 = 0.693147180559945309417232121458176568;
-    double a = 1.0;
-    exp2_coef[0] = 1.0f;
-    for (int k = 1; k <= EXP2_DEGREE; ++k) {
-        a = (a * (-ln2)) / (double)k;
-        exp2_coef[k] = (float)a;
-    }
-    exp2_ready = 1;
+    if (accept_ready) return;
+    for (int j = 0; j < ACCEPT_STEPS; ++j)
+        accept_table[j] = (uint32_t)llround(65536.0 * exp2(-(double)j / 64.0));
+    accept_table[ACCEPT_STEPS] = 0u;
+    accept_ready = 1;
 }
 
-static float exp2_neg_frac(float r)
+static uint32_t accept_index(float z)
 {
-    float p = exp2_coef[EXP2_DEGREE];
-    for (int k = EXP2_DEGREE - 1; k >= 0; --k) p = fmaf(p, r, exp2_coef[k]);
-    return p;
+    const float zs = z * 64.0f;                 /* exact */
+    if (!(zs > 0.0f)) return 0u;                /* downhill, flat or NaN */
+    if (zs >= (float)ACCEPT_STEPS) return ACCEPT_STEPS;
+    return (uint32_t)zs;                        /* floor of a positive value */
 }
 
-/* Metropolis test on the scaled energy change z = beta2 * dE with the 16-bit
- * draw m read as the uniform u = (m + 1) / 2^16 in (0, 1]: accept iff
- * u <= 2^-z.  z is clamped to [0, 32] first (NaN clamps to 0), n = floor(z),
- * r = z - n, and 2^16 * 2^-z = ldexp(2^-r, 16 - n) is exact scaling of the
- * polynomial value.  z <= 0 always accepts (threshold 2^16); z > 16 never does. */
 static int metropolis_accept(float z, uint32_t m)
 {
-    const float zc = fminf(fmaxf(z, 0.0f), 32.0f);
-    const int n = (int)zc;
-    const float r = zc - (float)n;               /* exact */
-    const float thr = ldexpf(exp2_neg_frac(r), 16 - n);
-    return (float)(m + 1u) <= thr;
-}
-
-float oracle_exp2_neg(float z)
-{
-    exp2_init();
-    float fl = floorf(z);
-    return ldexpf(exp2_neg_frac(z - fl), -(int)fl);
+    return m < accept_table[accept_index(z)];
 }
 
 int oracle_accept(float z, uint32_t m)
 {
-    exp2_init();
+    accept_init();
     return metropolis_accept(z, m);
 }
 
-void oracle_exp2_coefficients(float *out)
+void oracle_accept_table(uint32_t *out)
 {
-    exp2_init();
-    for (int k = 0; k <= EXP2_DEGREE; ++k) out[k] = exp2_coef[k];
+    accept_init();
+    for (int j = 0; j <= ACCEPT_STEPS; ++j) out[j] = accept_table[j];
 }
 
 /* ------------------------------------------------------------------------ */
 /* Level-domain helpers.                                                     */
 
-/* fresh field g = G x - f, accumulated left to right, no fused operations */
-static void fresh_field(int K, const float *G, const float *f, const float *x, float *g)
+/* local field of dimension k: g_k = (G x)_k - f_k as a chain of fused
+ * multiply-adds over l ascending, starting from -f_k                      */
+static float field_row(int K, const float *G, const float *f, const float *x, int k)
 {
-    for (int k = 0; k < K; ++k) {
-        float acc = 0.0f;
-        for (int l = 0; l < K; ++l) {
-            float prod = G[k * K + l] * x[l];
-            acc = acc + prod;
-        }
-        g[k] = acc - f[k];
-    }
+    float acc = -f[k];
+    for (int l = 0; l < K; ++l) acc = fmaf(G[k * K + l], x[l], acc);
+    return acc;
 }
 
-/* E = x^T G x - 2 f^T x written as sum_k x_k (g_k - f_k) with g = G x - f */
-static float level_energy(int K, const float *f, const float *x, const float *g)
+/* E = x^T G x - 2 f^T x written as sum_k x_k (g_k - f_k) with g = G x - f,
+ * accumulated by fused multiply-adds over k ascending                     */
+static float level_energy(int K, const float *G, const float *f, const float *x)
 {
     float acc = 0.0f;
     for (int k = 0; k < K; ++k) {
-        float diff = g[k] - f[k];
-        float term = x[k] * diff;
-        acc = acc + term;
+        const float diff = field_row(K, G, f, x, k) - f[k];
+        acc = fmaf(x[k], diff, acc);
     }
     return acc;
 }
@@ -207,11 +189,13 @@ static int energy_less(float a, float b)
     return a < b;
 }
 
-/* One anneal: returns final energy, writes final spins (N = K*q).          */
+/* One anneal: returns the final energy, writes the final spins (N = K*q).
+ * Sweeps visit the dimensions k = 0..K-1 in order and, within k, its spins
+ * b = 0..q-1 (spin index i = k q + b, most significant weight first).     */
 static float run_chain(int K, int q, const signed char *w, const float *G, const float *f,
                        const signed char *xfb, int sweeps, const float *beta2,
                        const uint32_t key[2], uint32_t inst, uint32_t ch, int init_mode,
-                       signed char *s, float *x, float *g)
+                       signed char *s, float *x)
 {
     const int N = K * q;
     if (init_mode == 1 && xfb != NULL) {
@@ -223,31 +207,31 @@ static float run_chain(int K, int q, const signed char *w, const float *G, const
         }
     }
     levels_from_spins(K, q, w, s, x);
-    fresh_field(K, G, f, x, g);
 
     for (int t = 0; t < sweeps; ++t) {
         const float b2 = beta2[t];
-        for (int i = 0; i < N; ++i) {
-            const int k = i / q, b = i % q;
-            const float delta = (float)(-2 * (int)w[b] * (int)s[i]);
-            const float twice = g[k] + g[k];
-            const float curv = delta * G[k * K + k];
-            const float inner = twice + curv;
-            const float dE = delta * inner;
-            const float z = b2 * dE;
-            const uint32_t m = draw16((uint32_t)i, (uint32_t)t, ch, inst, key);
-            if (metropolis_accept(z, m)) {
-                s[i] = (signed char)(-s[i]);
-                for (int j = 0; j < K; ++j) {
-                    float step = G[k * K + j] * delta;
-                    g[j] = g[j] + step;
+        for (int k = 0; k < K; ++k) {
+            const float gkk = G[k * K + k];
+            float g = field_row(K, G, f, x, k);
+            for (int b = 0; b < q; ++b) {
+                const int i = k * q + b;
+                const float delta = (float)(-2 * (int)w[b] * (int)s[i]);
+                const float twice = g + g;
+                const float curv = delta * gkk;
+                const float inner = twice + curv;
+                const float dE = delta * inner;
+                const float z = b2 * dE;
+                const uint32_t m = draw16((uint32_t)i, (uint32_t)t, ch, inst, key);
+                if (metropolis_accept(z, m)) {
+                    s[i] = (signed char)(-s[i]);
+                    x[k] = x[k] + delta;
+                    g = fmaf(gkk, delta, g);
                 }
             }
         }
     }
     levels_from_spins(K, q, w, s, x);
-    fresh_field(K, G, f, x, g);
-    return level_energy(K, f, x, g);
+    return level_energy(K, G, f, x);
 }
 
 /*
@@ -268,7 +252,7 @@ int oracle_solve(int n, int K, int q, const signed char *w, const float *G, int 
                  int nthreads)
 {
     if (n < 0 || K <= 0 || q <= 0 || chains <= 0 || sweeps < 0 || inst_per_G <= 0) return -1;
-    exp2_init();
+    accept_init();
     const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     const int N = K * q;
 #ifdef _OPENMP
@@ -282,8 +266,7 @@ int oracle_solve(int n, int K, int q, const signed char *w, const float *G, int 
         signed char *s = (signed char *)malloc((size_t)N);
         signed char *sbest = (signed char *)malloc((size_t)N);
         float *x = (float *)malloc(sizeof(float) * (size_t)K);
-        float *g = (float *)malloc(sizeof(float) * (size_t)K);
-        if (!s || !sbest || !x || !g) {
+        if (!s || !sbest || !x) {
 #pragma omp atomic write
             bad = 1;
         } else {
@@ -298,7 +281,7 @@ int oracle_solve(int n, int K, int q, const signed char *w, const float *G, int 
                 int win = -1;
                 for (int ch = 0; ch < chains; ++ch) {
                     float e = run_chain(K, q, w, Gi, fi, xi, sweeps, beta2, key, inst,
-                                        (uint32_t)ch, init_mode, s, x, g);
+                                        (uint32_t)ch, init_mode, s, x);
                     if (chain_e_out) chain_e_out[(size_t)idx * (size_t)chains + (size_t)ch] = e;
                     if (win < 0 || energy_less(e, ebest)) {
                         ebest = e;
@@ -308,8 +291,7 @@ int oracle_solve(int n, int K, int q, const signed char *w, const float *G, int 
                 }
                 if (xi) {
                     for (int k = 0; k < K; ++k) x[k] = (float)xi[k];
-                    fresh_field(K, Gi, fi, x, g);
-                    float efb = level_energy(K, fi, x, g);
+                    float efb = level_energy(K, Gi, fi, x);
                     if (energy_less(efb, ebest)) {
                         ebest = efb;
                         win = chains;
@@ -321,19 +303,18 @@ int oracle_solve(int n, int K, int q, const signed char *w, const float *G, int 
                 if (win_out) win_out[idx] = win;
             }
         }
-        free(s); free(sbest); free(x); free(g);
+        free(s); free(sbest); free(x);
     }
     return bad ? -2 : 0;
 }
 
-/* Energy of given levels on the structured form (the F6/F7 arithmetic).    */
+/* Energy of given levels with the chains' float32 arithmetic.             */
 float oracle_level_energy(int K, const float *G, const float *f, const signed char *lv)
 {
-    float x[256], g[256];
+    float x[256];
     if (K <= 0 || K > 256) return NAN;
     for (int k = 0; k < K; ++k) x[k] = (float)lv[k];
-    fresh_field(K, G, f, x, g);
-    return level_energy(K, f, x, g);
+    return level_energy(K, G, f, x);
 }
 
 /* ------------------------------------------------------------------------ */

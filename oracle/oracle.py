@@ -22,8 +22,11 @@ Paper passages followed (arXiv 2510.01579):
 Readings (where the paper is silent), all shared with the GPU library's
 contract: binary-weighted spin encoding x_k = sum_b 2^(q-1-b) s_{k,b} of the
 odd PAM levels (VPP: two unit-weight spins per real dimension, levels
-{-2, 0, 2} = 2v); a single-spin-flip Metropolis anneal in place of CIM-CAC;
-couplings and fields built in float64 and rounded once to float32.
+{-2, 0, 2} = 2v); a single-spin-flip Metropolis anneal in place of CIM-CAC,
+with the local field of a dimension recomputed from the current levels at each
+visit (one row of the coupling matrix-vector product) and a 16-bit uniform
+compared with a tabulated 2^16 * 2^-z, z quantised to 1/64; couplings and
+fields built in float64 and rounded once to float32.
 
 Parity pins live in tests/test_oracle_*.py (closed forms, library routines,
 brute force, known-answer vectors, invariants).  The chain dynamics themselves
@@ -54,12 +57,10 @@ def lib():
         L.oracle_philox4x32_10.restype = None
         L.oracle_draw16.argtypes = [ctypes.c_uint32] * 4 + [ctypes.c_uint64]
         L.oracle_draw16.restype = ctypes.c_uint32
-        L.oracle_exp2_neg.argtypes = [ctypes.c_float]
-        L.oracle_exp2_neg.restype = ctypes.c_float
         L.oracle_accept.argtypes = [ctypes.c_float, ctypes.c_uint32]
         L.oracle_accept.restype = ctypes.c_int
-        L.oracle_exp2_coefficients.argtypes = [ctypes.c_void_p]
-        L.oracle_exp2_coefficients.restype = None
+        L.oracle_accept_table.argtypes = [ctypes.c_void_p]
+        L.oracle_accept_table.restype = None
         L.oracle_solve.argtypes = [
             ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,  # n K q w
             ctypes.c_void_p, ctypes.c_int, ctypes.c_long,                # G inst_per_G g_base
@@ -141,17 +142,27 @@ def det_ising64(H: np.ndarray, y: np.ndarray, qam: int):
 
     ||y - H c x||^2 = ||y||^2 + x^T (c^2 H_r^T H_r) x - 2 (c H_r^T y_r)^T x, so
     G = c^2 H_r^T H_r (per subcarrier) and f = c H_r^T y_r (per instance).
-    G is made exactly symmetric by mirroring its upper triangle.
+    H_r^T H_r is the real form [[X, -Y], [Y, X]] of the Hermitian Gram
+    H^H H = X + iY, taken exactly Hermitian (upper triangle mirrored, real
+    diagonal); H_r^T y_r = [Re F; Im F] with F = H^H y.
     H: [n_sc][n_r][n_t]; y: [n_sc][n_sym][n_r].
     """
     c = qam_scale(qam)
     c2 = 1.0 / (2.0 * (qam - 1) / 3.0)
-    Hr = real_matrix(H.astype(np.complex128))                 # [n_sc][2n_r][K]
-    Gr = np.einsum("sik,sil->skl", Hr, Hr)
-    iu = np.triu_indices(Gr.shape[-1], 1)
-    Gr[:, iu[1], iu[0]] = Gr[:, iu[0], iu[1]]
-    yr = real_vector(y.astype(np.complex128))                 # [n_sc][n_sym][2n_r]
-    fr = np.einsum("sik,sbi->sbk", Hr, yr)                     # [n_sc][n_sym][K]
+    Hc = H.astype(np.complex128)
+    n_t = Hc.shape[-1]
+    Cg = np.einsum("sra,srb->sab", np.conj(Hc), Hc)
+    iu = np.triu_indices(n_t, 1)
+    X = Cg.real.copy()
+    Y = Cg.imag.copy()
+    X[:, iu[1], iu[0]] = X[:, iu[0], iu[1]]
+    Y[:, iu[1], iu[0]] = 0.0 - Y[:, iu[0], iu[1]]
+    Y[:, np.arange(n_t), np.arange(n_t)] = 0.0
+    top = np.concatenate([X, 0.0 - Y], axis=-1)
+    bot = np.concatenate([Y, X], axis=-1)
+    Gr = np.concatenate([top, bot], axis=-2)
+    F = np.einsum("sra,sbr->sba", np.conj(Hc), y.astype(np.complex128))
+    fr = np.concatenate([F.real, F.imag], axis=-1)
     return Gr * c2, fr * c
 
 
@@ -422,17 +433,14 @@ def draw16(i, t, ch, inst, seed) -> int:
     return int(lib().oracle_draw16(i, t, ch, inst, int(seed) & 0xFFFFFFFFFFFFFFFF))
 
 
-def exp2_neg(z: float) -> float:
-    return float(lib().oracle_exp2_neg(z))
-
-
 def accept(z: float, m: int) -> bool:
     return bool(lib().oracle_accept(z, m))
 
 
-def exp2_coefficients() -> np.ndarray:
-    out = np.zeros(7, dtype=np.float32)
-    lib().oracle_exp2_coefficients(_ptr(out))
+def accept_table() -> np.ndarray:
+    """The Metropolis threshold table T[0..1024] (uint32)."""
+    out = np.zeros(1025, dtype=np.uint32)
+    lib().oracle_accept_table(_ptr(out))
     return out
 
 

@@ -1,0 +1,304 @@
+"""MI355X (gfx950) Ising hot path for uplink ML-MIMO detection and downlink
+vector-perturbation precoding (after "MMGaP", arXiv 2510.01579).
+
+This module is a thin ctypes binding of the C ABI in include/mmgap.h
+(libmmgap.so, built in-tree by ``paper_2510_01579_amd.build``).  It marshals
+torch tensors (device memory) and the current HIP stream; every step of the
+computation runs in the library's HIP kernels.  There is no CPU fallback: if
+the library is missing or no GPU is present the calls raise.
+
+Entry points (same names as the C ABI, without the ``mmgap_`` prefix):
+``build_ising``, ``solve``, ``detect``, ``vpp_precode``; ``Context`` owns a
+library context (device, scratch, HBM budget).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import threading
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmmgap.so")
+
+KIND_DET = 0
+KIND_VPP = 1
+
+STATUS = {0: "MMGAP_OK", -1: "MMGAP_EINVAL", -2: "MMGAP_ENOMEM", -3: "MMGAP_EDEVICE",
+          -4: "MMGAP_EUNSUPPORTED", -5: "MMGAP_EBUSY"}
+
+EXPORTS = ("mmgap_create", "mmgap_destroy", "mmgap_last_error", "mmgap_build_ising",
+           "mmgap_solve", "mmgap_detect", "mmgap_vpp_precode")
+
+
+class MmgapError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("n_rx", ctypes.c_int), ("n_tx", ctypes.c_int),
+                ("qam", ctypes.c_int), ("n_sc", ctypes.c_int), ("n_sym", ctypes.c_int),
+                ("noise_var", ctypes.c_float), ("tau", ctypes.c_float)]
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("chains", ctypes.c_int), ("sweeps", ctypes.c_int),
+                ("beta2", ctypes.POINTER(ctypes.c_float)), ("seed", ctypes.c_uint64),
+                ("init", ctypes.c_int)]
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+
+def lib() -> ctypes.CDLL:
+    """Load libmmgap.so (raises if it has not been built)."""
+    global _lib
+    with _lib_lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                                   "`python -m paper_2510_01579_amd.build`")
+            L = ctypes.CDLL(LIB_PATH)
+            vp, i, f32 = ctypes.c_void_p, ctypes.c_int, ctypes.c_float
+            L.mmgap_create.argtypes = [ctypes.POINTER(vp), i, ctypes.c_size_t]
+            L.mmgap_destroy.argtypes = [vp]
+            L.mmgap_last_error.argtypes = [vp]
+            L.mmgap_last_error.restype = ctypes.c_char_p
+            P = ctypes.POINTER(Problem)
+            S = ctypes.POINTER(Schedule)
+            L.mmgap_build_ising.argtypes = [vp, P, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+            L.mmgap_solve.argtypes = [vp, i, i, i, vp, vp, i, vp, vp, S, vp, vp, vp, vp]
+            L.mmgap_detect.argtypes = [vp, P, vp, vp, S, vp, vp, vp]
+            L.mmgap_vpp_precode.argtypes = [vp, P, vp, vp, S, vp, vp, vp, vp]
+            for name in EXPORTS:
+                if name not in ("mmgap_last_error",):
+                    getattr(L, name).restype = i
+            _lib = L
+    return _lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> ctypes.c_void_p:
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def qam_bits(qam: int) -> int:
+    q = {4: 1, 16: 2, 64: 3}.get(int(qam))
+    if q is None:
+        raise ValueError(f"qam must be 4, 16 or 64 (got {qam})")
+    return q
+
+
+def linear_beta2(sweeps: int, beta0: float, beta1: float) -> np.ndarray:
+    """Linear-in-beta anneal as the float32 table beta_t * log2(e) the library takes."""
+    t = np.arange(sweeps, dtype=np.float64)
+    b = np.full(sweeps, beta1) if sweeps == 1 else beta0 + (beta1 - beta0) * t / (sweeps - 1)
+    return (b / math.log(2.0)).astype(np.float32)
+
+
+def default_det_schedule(qam: int, n_rx: int, noise_var: float, sweeps: int) -> np.ndarray:
+    """beta from 1/(4 c^2 n_rx) (cheapest uphill move accepted with e^-1) to
+    1/sigma^2 (the posterior temperature of the Gaussian channel)."""
+    c2 = 1.0 / (2.0 * (qam - 1) / 3.0)
+    b0 = 1.0 / (4.0 * c2 * n_rx)
+    b1 = max(1.0 / max(noise_var, 1e-6), b0)
+    return linear_beta2(sweeps, b0, b1)
+
+
+def default_vpp_schedule(qam: int, sweeps: int) -> np.ndarray:
+    """beta from 0.1 to 4 in units of the perturbation step energy M c^2."""
+    c2 = 1.0 / (2.0 * (qam - 1) / 3.0)
+    step = qam * c2
+    return linear_beta2(sweeps, 0.1 / step, 4.0 / step)
+
+
+class Context:
+    """A library context bound to one HIP device (scratch, schedule ring, HBM budget)."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the MMGaP hot path runs only on a HIP device")
+        self.device = int(device)
+        self._h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = lib().mmgap_create(ctypes.byref(self._h), self.device, int(hbm_budget))
+        if rc != 0:
+            raise MmgapError(rc, lib().mmgap_last_error(None).decode())
+
+    def close(self):
+        if self._h:
+            lib().mmgap_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int):
+        if rc != 0:
+            raise MmgapError(rc, lib().mmgap_last_error(self._h).decode())
+
+    def _dev(self):
+        return _torch().device("cuda", self.device)
+
+    # ------------------------------------------------------------------ helpers
+    def _check_tensor(self, t, name, dtype, shape):
+        torch = _torch()
+        if t.device != self._dev():
+            raise ValueError(f"{name} must be on {self._dev()} (got {t.device})")
+        if t.dtype != dtype:
+            raise ValueError(f"{name} must be {dtype} (got {t.dtype})")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} must have shape {tuple(shape)} (got {tuple(t.shape)})")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return t
+
+    @staticmethod
+    def _schedule(chains, sweeps, beta2, seed, init):
+        b = np.ascontiguousarray(np.asarray(beta2, dtype=np.float32).reshape(-1))
+        if b.size != sweeps:
+            raise ValueError(f"beta2 must have {sweeps} entries (got {b.size})")
+        s = Schedule(int(chains), int(sweeps), b.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                     int(seed) & 0xFFFFFFFFFFFFFFFF, int(init))
+        return s, b
+
+    def _problem(self, kind, H, y_or_u, qam, noise_var, tau):
+        torch = _torch()
+        if H.dim() != 3 or y_or_u.dim() != 3:
+            raise ValueError("H must be [n_sc][n_rx][n_tx] and y/u [n_sc][n_sym][n_rx]")
+        n_sc, n_rx, n_tx = H.shape
+        n_sym = y_or_u.shape[1]
+        self._check_tensor(H, "H", torch.complex64, (n_sc, n_rx, n_tx))
+        self._check_tensor(y_or_u, "y_or_u", torch.complex64, (n_sc, n_sym, n_rx))
+        qam_bits(qam)
+        return Problem(kind, n_rx, n_tx, int(qam), n_sc, n_sym, float(noise_var), float(tau))
+
+    # ------------------------------------------------------------------ entry points
+    def build_ising(self, kind, H, y_or_u, qam, noise_var=0.0, tau=0.0, fallback=True,
+                    dense=False, stream=None):
+        """Couplings G [n_sc][K][K], fields f [n][K] (float32), fallback levels
+        x_fb [n][K] (int8) and, if dense, J [n_sc][N][N], h [n][N], e_const [n]."""
+        torch = _torch()
+        p = self._problem(kind, H, y_or_u, qam, noise_var, tau)
+        K = 2 * (p.n_tx if kind == KIND_DET else p.n_rx)
+        q = qam_bits(qam) if kind == KIND_DET else 2
+        N = K * q
+        n = p.n_sc * p.n_sym
+        dev = self._dev()
+        out = dict(G=torch.empty((p.n_sc, K, K), dtype=torch.float32, device=dev),
+                   f=torch.empty((n, K), dtype=torch.float32, device=dev))
+        out["x_fb"] = torch.empty((n, K), dtype=torch.int8, device=dev) if fallback else None
+        if dense:
+            out["J"] = torch.empty((p.n_sc, N, N), dtype=torch.float32, device=dev)
+            out["h"] = torch.empty((n, N), dtype=torch.float32, device=dev)
+            out["e_const"] = torch.empty((n,), dtype=torch.float32, device=dev)
+        st = stream if stream is not None else _stream(dev)
+        self._check(lib().mmgap_build_ising(self._h, ctypes.byref(p), _ptr(H), _ptr(y_or_u),
+                                            _ptr(out["G"]), _ptr(out["f"]), _ptr(out["x_fb"]),
+                                            _ptr(out.get("J")), _ptr(out.get("h")),
+                                            _ptr(out.get("e_const")), st))
+        return out
+
+    def solve(self, G, f, K, q, w, chains, sweeps, beta2, seed, x_fallback=None, inst_per_G=1,
+              init=0, stream=None):
+        """Best of `chains` anneals per instance.  Returns (spins int8 [n][K q],
+        energy float32 [n], winning chain int32 [n])."""
+        torch = _torch()
+        n = f.shape[0]
+        n_G = (n + inst_per_G - 1) // inst_per_G if n else 0
+        self._check_tensor(f, "f", torch.float32, (n, K))
+        self._check_tensor(G, "G", torch.float32, (n_G, K, K))
+        if x_fallback is not None:
+            self._check_tensor(x_fallback, "x_fallback", torch.int8, (n, K))
+        wv = (ctypes.c_byte * len(w))(*[int(v) for v in w])
+        if len(w) != q:
+            raise ValueError("w must have q entries")
+        dev = self._dev()
+        spins = torch.empty((n, K * q), dtype=torch.int8, device=dev)
+        E = torch.empty((n,), dtype=torch.float32, device=dev)
+        win = torch.empty((n,), dtype=torch.int32, device=dev)
+        s, keep = self._schedule(chains, sweeps, beta2, seed, init)
+        st = stream if stream is not None else _stream(dev)
+        self._check(lib().mmgap_solve(self._h, n, K, q, wv, _ptr(G), int(inst_per_G), _ptr(f),
+                                      _ptr(x_fallback), ctypes.byref(s), _ptr(spins), _ptr(E),
+                                      _ptr(win), st))
+        del keep
+        return spins, E, win
+
+    def detect(self, H, y, qam, noise_var, chains, sweeps, beta2, seed, init=0, metric=True,
+               stream=None):
+        """Uplink detection.  Returns (sym uint8 [n][n_tx], metric float32 [n] or None)."""
+        torch = _torch()
+        p = self._problem(KIND_DET, H, y, qam, noise_var, 0.0)
+        n = p.n_sc * p.n_sym
+        dev = self._dev()
+        sym = torch.empty((n, p.n_tx), dtype=torch.uint8, device=dev)
+        met = torch.empty((n,), dtype=torch.float32, device=dev) if metric else None
+        s, keep = self._schedule(chains, sweeps, beta2, seed, init)
+        st = stream if stream is not None else _stream(dev)
+        self._check(lib().mmgap_detect(self._h, ctypes.byref(p), _ptr(H), _ptr(y),
+                                       ctypes.byref(s), _ptr(sym), _ptr(met), st))
+        del keep
+        return sym, met
+
+    def vpp_precode(self, H, u, qam, chains, sweeps, beta2, seed, tau=0.0, want_x=True,
+                    want_gamma=True, init=0, stream=None):
+        """Downlink VPP.  Returns (v int8 [n][2 n_rx], x complex64 [n][n_tx] or None,
+        gamma float32 [n] or None)."""
+        torch = _torch()
+        p = self._problem(KIND_VPP, H, u, qam, 0.0, tau)
+        n = p.n_sc * p.n_sym
+        dev = self._dev()
+        v = torch.empty((n, 2 * p.n_rx), dtype=torch.int8, device=dev)
+        x = torch.empty((n, p.n_tx), dtype=torch.complex64, device=dev) if want_x else None
+        g = torch.empty((n,), dtype=torch.float32, device=dev) if want_gamma else None
+        s, keep = self._schedule(chains, sweeps, beta2, seed, init)
+        st = stream if stream is not None else _stream(dev)
+        self._check(lib().mmgap_vpp_precode(self._h, ctypes.byref(p), _ptr(H), _ptr(u),
+                                            ctypes.byref(s), _ptr(v), _ptr(x), _ptr(g), st))
+        del keep
+        return v, x, g
+
+
+_default_ctx = {}
+
+
+def context(device: int = 0) -> Context:
+    """Process-wide default context of a device."""
+    if device not in _default_ctx:
+        _default_ctx[device] = Context(device)
+    return _default_ctx[device]
+
+
+def build_ising(*args, device: int = 0, **kw):
+    return context(device).build_ising(*args, **kw)
+
+
+def solve(*args, device: int = 0, **kw):
+    return context(device).solve(*args, **kw)
+
+
+def detect(*args, device: int = 0, **kw):
+    return context(device).detect(*args, **kw)
+
+
+def vpp_precode(*args, device: int = 0, **kw):
+    return context(device).vpp_precode(*args, **kw)

@@ -1,0 +1,609 @@
+// C ABI of the Ising hot path: contexts, argument checks, scratch management
+// and the launch sequences (build -> anneal -> select) of include/mmgap.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "kernels.h"
+#include "mmgap.h"
+
+namespace {
+
+constexpr int kRing = 8;                        // schedule upload slots
+constexpr size_t kDefaultBudget = size_t(16) << 30;
+constexpr size_t kAlign = 256;
+
+thread_local std::string g_create_error;
+
+}  // namespace
+
+struct mmgap_ctx {
+    int device = 0;
+    size_t budget = kDefaultBudget;
+    std::string err;
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
+    float *beta_dev = nullptr;                  // [kRing][kMaxSweeps]
+    float *beta_host = nullptr;                 // pinned, same shape
+    hipEvent_t ring_ev[kRing] = {};
+    int ring_pos = 0;
+    hipEvent_t done = nullptr;                  // end of the last call's work
+    bool done_valid = false;
+    uint32_t *accept_dev = nullptr;             // Metropolis threshold table
+};
+
+namespace {
+
+int fail(mmgap_ctx *ctx, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    else g_create_error = buf;
+    return code;
+}
+
+int hip_fail(mmgap_ctx *ctx, hipError_t e, const char *what)
+{
+    return fail(ctx, MMGAP_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Switches to the context's device for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Bump allocator over the context's scratch.
+struct Plan {
+    size_t off = 0;
+    size_t take(size_t bytes)
+    {
+        const size_t o = off;
+        off += align_up(bytes);
+        return o;
+    }
+};
+
+int ensure_scratch(mmgap_ctx *ctx, size_t bytes)
+{
+    if (bytes > ctx->budget)
+        return fail(ctx, MMGAP_ENOMEM, "scratch of %zu bytes exceeds the HBM budget of %zu bytes",
+                    bytes, ctx->budget);
+    if (bytes <= ctx->scratch_bytes) return MMGAP_OK;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipDeviceSynchronize");
+    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    ctx->scratch = nullptr;
+    ctx->scratch_bytes = 0;
+    size_t want = bytes + bytes / 4;
+    if (want > ctx->budget) want = bytes;
+    e = hipMalloc(&ctx->scratch, want);
+    if (e != hipSuccess) {
+        ctx->scratch = nullptr;
+        return fail(ctx, MMGAP_ENOMEM, "hipMalloc(%zu): %s", want, hipGetErrorString(e));
+    }
+    ctx->scratch_bytes = want;
+    return MMGAP_OK;
+}
+
+template <typename T>
+T *at(mmgap_ctx *ctx, size_t off)
+{
+    return reinterpret_cast<T *>(static_cast<char *>(ctx->scratch) + off);
+}
+
+bool pow2_weight(int w) { return w >= 1 && w <= 64 && (w & (w - 1)) == 0; }
+
+int qam_bits(int qam)
+{
+    switch (qam) {
+    case 4: return 1;
+    case 16: return 2;
+    case 64: return 3;
+    default: return 0;
+    }
+}
+
+int check_schedule(mmgap_ctx *ctx, const mmgap_schedule *s)
+{
+    if (!s) return fail(ctx, MMGAP_EINVAL, "schedule is NULL");
+    if (s->chains < 1 || s->chains > mmgap::kMaxChains)
+        return fail(ctx, MMGAP_EUNSUPPORTED, "chains=%d outside 1..%d", s->chains, mmgap::kMaxChains);
+    if (s->sweeps < 1 || s->sweeps > mmgap::kMaxSweeps)
+        return fail(ctx, MMGAP_EUNSUPPORTED, "sweeps=%d outside 1..%d", s->sweeps, mmgap::kMaxSweeps);
+    if (!s->beta2) return fail(ctx, MMGAP_EINVAL, "schedule.beta2 is NULL");
+    for (int t = 0; t < s->sweeps; ++t) {
+        const float b = s->beta2[t];
+        if (!(b >= 0.0f) || !std::isfinite(b))
+            return fail(ctx, MMGAP_EINVAL, "schedule.beta2[%d]=%g is not finite and >= 0", t, (double)b);
+    }
+    if (s->init != 0 && s->init != 1) return fail(ctx, MMGAP_EINVAL, "schedule.init must be 0 or 1");
+    return MMGAP_OK;
+}
+
+// Orders this call after the context's previous call (which may have used
+// another stream) so that the shared scratch is never used concurrently.
+int begin_call(mmgap_ctx *ctx, hipStream_t s)
+{
+    if (ctx->done_valid) {
+        hipError_t e = hipStreamWaitEvent(s, ctx->done, 0);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamWaitEvent");
+    }
+    return MMGAP_OK;
+}
+
+int end_call(mmgap_ctx *ctx, hipStream_t s)
+{
+    hipError_t e = hipEventRecord(ctx->done, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipEventRecord");
+    ctx->done_valid = true;
+    return MMGAP_OK;
+}
+
+// Copies the host schedule into a device ring slot; returns the device table.
+int upload_beta(mmgap_ctx *ctx, const mmgap_schedule *s, hipStream_t st, const float **out)
+{
+    const int slot = ctx->ring_pos;
+    ctx->ring_pos = (ctx->ring_pos + 1) % kRing;
+    hipError_t e = hipEventSynchronize(ctx->ring_ev[slot]);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipEventSynchronize");
+    float *h = ctx->beta_host + (size_t)slot * mmgap::kMaxSweeps;
+    float *d = ctx->beta_dev + (size_t)slot * mmgap::kMaxSweeps;
+    std::memcpy(h, s->beta2, sizeof(float) * (size_t)s->sweeps);
+    e = hipMemcpyAsync(d, h, sizeof(float) * (size_t)s->sweeps, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpyAsync(schedule)");
+    e = hipEventRecord(ctx->ring_ev[slot], st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipEventRecord(schedule)");
+    *out = d;
+    return MMGAP_OK;
+}
+
+struct ProblemShape {
+    int K = 0, q = 0, KT = 0, n_inst = 0;
+};
+
+int check_problem(mmgap_ctx *ctx, const mmgap_problem *p, int kind, ProblemShape *sh)
+{
+    if (!p) return fail(ctx, MMGAP_EINVAL, "problem is NULL");
+    if (p->kind != MMGAP_KIND_DET && p->kind != MMGAP_KIND_VPP)
+        return fail(ctx, MMGAP_EINVAL, "problem.kind=%d is not DET or VPP", p->kind);
+    if (kind >= 0 && p->kind != kind)
+        return fail(ctx, MMGAP_EINVAL, "problem.kind=%d does not match this entry point", p->kind);
+    if (p->n_rx < 1 || p->n_tx < 1 || p->n_sc < 0 || p->n_sym < 1)
+        return fail(ctx, MMGAP_EINVAL, "bad sizes n_rx=%d n_tx=%d n_sc=%d n_sym=%d", p->n_rx,
+                    p->n_tx, p->n_sc, p->n_sym);
+    if (p->n_sym > 64) return fail(ctx, MMGAP_EUNSUPPORTED, "n_sym=%d > 64", p->n_sym);
+    const int q = qam_bits(p->qam);
+    if (!q) return fail(ctx, MMGAP_EUNSUPPORTED, "qam=%d not in {4,16,64}", p->qam);
+    if (p->kind == MMGAP_KIND_DET) {
+        if (p->n_tx > 16 || p->n_rx > 64)
+            return fail(ctx, MMGAP_EUNSUPPORTED, "DET needs n_tx <= 16 and n_rx <= 64 (got %d x %d)",
+                        p->n_rx, p->n_tx);
+        if (!(p->noise_var >= 0.0f) || !std::isfinite(p->noise_var))
+            return fail(ctx, MMGAP_EINVAL, "noise_var must be finite and >= 0");
+        sh->K = 2 * p->n_tx;
+        sh->q = q;
+    } else {
+        if (p->n_rx > 16 || p->n_tx > 64)
+            return fail(ctx, MMGAP_EUNSUPPORTED, "VPP needs n_rx <= 16 and n_tx <= 64 (got %d x %d)",
+                        p->n_rx, p->n_tx);
+        if (!std::isfinite(p->tau)) return fail(ctx, MMGAP_EINVAL, "tau must be finite");
+        sh->K = 2 * p->n_rx;
+        sh->q = 2;
+    }
+    sh->KT = mmgap::padded_k(sh->K);
+    const long long ni = (long long)p->n_sc * p->n_sym;
+    if (ni > 0x7FFFFFFFll) return fail(ctx, MMGAP_EUNSUPPORTED, "too many instances");
+    sh->n_inst = (int)ni;
+    return MMGAP_OK;
+}
+
+double qam_c(int qam) { return 1.0 / std::sqrt(2.0 * (qam - 1) / 3.0); }
+double qam_c2(int qam) { return 1.0 / (2.0 * (qam - 1) / 3.0); }
+double vpp_tau(const mmgap_problem *p)
+{
+    if (p->tau > 0.0f) return (double)p->tau;
+    return 2.0 * std::sqrt((double)p->qam) * qam_c(p->qam);
+}
+
+void det_weights(int q, int *w)
+{
+    for (int b = 0; b < mmgap::kMaxQ; ++b) w[b] = b < q ? 1 << (q - 1 - b) : 1;
+}
+
+void vpp_weights(int *w)
+{
+    w[0] = 1;
+    w[1] = 1;
+    w[2] = 1;
+    w[3] = 1;
+}
+
+// Anneal + select over padded structures already on the device.
+int run_solver(mmgap_ctx *ctx, hipStream_t st, int n_inst, int K, int q, int KT, const int *w,
+               const float *Gp, int inst_per_G, const float *fp, const signed char *xp,
+               const mmgap_schedule *sched, float *chainE, uint32_t *chainS,
+               mmgap::SelectArgs sel)
+{
+    const float *beta = nullptr;
+    int rc = upload_beta(ctx, sched, st, &beta);
+    if (rc) return rc;
+    mmgap::AnnealArgs a{};
+    a.G = Gp;
+    a.inst_per_G = inst_per_G;
+    a.f = fp;
+    a.x_fb = xp;
+    a.beta2 = beta;
+    a.accept_table = ctx->accept_dev;
+    a.sweeps = sched->sweeps;
+    a.chains = sched->chains;
+    a.n_inst = n_inst;
+    for (int b = 0; b < mmgap::kMaxQ; ++b) a.w[b] = w[b];
+    a.key0 = (uint32_t)sched->seed;
+    a.key1 = (uint32_t)(sched->seed >> 32);
+    a.init_mode = sched->init;
+    a.chain_E = chainE;
+    a.chain_S = chainS;
+    hipError_t e = mmgap::launch_anneal(KT, q, a, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "anneal launch");
+    sel.n_inst = n_inst;
+    sel.K = K;
+    sel.KT = KT;
+    sel.q = q;
+    sel.chains = sched->chains;
+    for (int b = 0; b < mmgap::kMaxQ; ++b) sel.w[b] = w[b];
+    sel.G = Gp;
+    sel.inst_per_G = inst_per_G;
+    sel.f = fp;
+    sel.x_fb = xp;
+    sel.chain_E = chainE;
+    sel.chain_S = chainS;
+    e = mmgap::launch_select(sel, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "select launch");
+    return MMGAP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mmgap_create(mmgap_ctx **out, int device, size_t hbm_budget_bytes)
+{
+    if (!out) return fail(nullptr, MMGAP_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev <= 0)
+        return fail(nullptr, MMGAP_EDEVICE, "no HIP device available (%s)", hipGetErrorString(e));
+    if (device < 0 || device >= ndev)
+        return fail(nullptr, MMGAP_EINVAL, "device %d outside 0..%d", device, ndev - 1);
+    mmgap_ctx *ctx = new (std::nothrow) mmgap_ctx();
+    if (!ctx) return fail(nullptr, MMGAP_ENOMEM, "out of host memory");
+    ctx->device = device;
+    if (hbm_budget_bytes) ctx->budget = hbm_budget_bytes;
+    DeviceGuard g(device);
+    if (!g.ok) {
+        delete ctx;
+        return fail(nullptr, MMGAP_EDEVICE, "hipSetDevice(%d) failed", device);
+    }
+    const size_t ring = sizeof(float) * (size_t)kRing * mmgap::kMaxSweeps;
+    e = hipMalloc(&ctx->beta_dev, ring);
+    if (e == hipSuccess) e = hipHostMalloc(&ctx->beta_host, ring, hipHostMallocDefault);
+    for (int i = 0; i < kRing && e == hipSuccess; ++i)
+        e = hipEventCreateWithFlags(&ctx->ring_ev[i], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMalloc(&ctx->accept_dev, sizeof(uint32_t) * mmgap::kAcceptTable);
+    if (e == hipSuccess) {
+        // T[j] = round(2^16 * 2^(-j/64)): no entry is within 1e-3 of a rounding tie
+        uint32_t table[mmgap::kAcceptTable];
+        for (int j = 0; j + 1 < mmgap::kAcceptTable; ++j)
+            table[j] = (uint32_t)std::llround(65536.0 * std::exp2(-(double)j / 64.0));
+        table[mmgap::kAcceptTable - 1] = 0u;
+        e = hipMemcpy(ctx->accept_dev, table, sizeof table, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        mmgap_destroy(ctx);
+        return fail(nullptr, MMGAP_EDEVICE, "context setup: %s", hipGetErrorString(e));
+    }
+    *out = ctx;
+    return MMGAP_OK;
+}
+
+int mmgap_destroy(mmgap_ctx *ctx)
+{
+    if (!ctx) return MMGAP_OK;
+    DeviceGuard g(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    if (ctx->beta_dev) (void)hipFree(ctx->beta_dev);
+    if (ctx->beta_host) (void)hipHostFree(ctx->beta_host);
+    for (int i = 0; i < kRing; ++i)
+        if (ctx->ring_ev[i]) (void)hipEventDestroy(ctx->ring_ev[i]);
+    if (ctx->done) (void)hipEventDestroy(ctx->done);
+    if (ctx->accept_dev) (void)hipFree(ctx->accept_dev);
+    delete ctx;
+    return MMGAP_OK;
+}
+
+const char *mmgap_last_error(const mmgap_ctx *ctx)
+{
+    return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+int mmgap_build_ising(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H,
+                      const void *y_or_u, float *G, float *f, signed char *x_fallback,
+                      float *J_dense, float *h_dense, float *e_const, void *stream)
+{
+    if (!ctx) return MMGAP_EINVAL;
+    ProblemShape sh;
+    int rc = check_problem(ctx, prob, -1, &sh);
+    if (rc) return rc;
+    if (sh.n_inst == 0) return MMGAP_OK;
+    if (!H || !y_or_u || !G || !f) return fail(ctx, MMGAP_EINVAL, "H, y_or_u, G and f are required");
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    Plan plan;
+    const size_t o_norm = e_const ? plan.take(sizeof(double) * (size_t)sh.n_inst) : 0;
+    if ((rc = ensure_scratch(ctx, plan.off))) return rc;
+    if ((rc = begin_call(ctx, st))) return rc;
+    hipError_t e;
+    int w[mmgap::kMaxQ];
+    double *norm = e_const ? at<double>(ctx, o_norm) : nullptr;
+    if (prob->kind == MMGAP_KIND_DET) {
+        mmgap::DetBuildArgs a{};
+        a.H = (const float2 *)H;
+        a.y = (const float2 *)y_or_u;
+        a.n_sc = prob->n_sc;
+        a.n_r = prob->n_rx;
+        a.n_t = prob->n_tx;
+        a.n_sym = prob->n_sym;
+        a.ld = sh.K;
+        a.qtop = (1 << sh.q) - 1;
+        a.c = qam_c(prob->qam);
+        a.c2 = qam_c2(prob->qam);
+        a.noise_var = (double)prob->noise_var;
+        a.G = G;
+        a.f = f;
+        a.x_fb = x_fallback;
+        a.ynorm = norm;
+        e = mmgap::launch_det_build(a, st);
+        det_weights(sh.q, w);
+    } else {
+        mmgap::VppBuildArgs a{};
+        a.H = (const float2 *)H;
+        a.u = (const float2 *)y_or_u;
+        a.n_sc = prob->n_sc;
+        a.n_u = prob->n_rx;
+        a.n_t = prob->n_tx;
+        a.n_sym = prob->n_sym;
+        a.ld = sh.K;
+        a.tau = vpp_tau(prob);
+        a.G = G;
+        a.f = f;
+        a.x_fb = x_fallback;
+        a.Ainv = nullptr;
+        a.unorm = norm;
+        e = mmgap::launch_vpp_build(a, st);
+        vpp_weights(w);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "build launch");
+    if (J_dense || h_dense || e_const) {
+        mmgap::ExpandArgs x{};
+        x.G = G;
+        x.f = f;
+        x.norm = norm;
+        x.n_sc = prob->n_sc;
+        x.n_sym = prob->n_sym;
+        x.K = sh.K;
+        x.q = sh.q;
+        for (int b = 0; b < mmgap::kMaxQ; ++b) x.w[b] = w[b];
+        x.J = J_dense;
+        x.h = h_dense;
+        x.e_const = e_const;
+        e = mmgap::launch_expand(x, st);
+        if (e != hipSuccess) return hip_fail(ctx, e, "expand launch");
+    }
+    return end_call(ctx, st);
+}
+
+int mmgap_solve(mmgap_ctx *ctx, int n_inst, int K, int q, const signed char *w,
+                const float *G, int inst_per_G, const float *f, const signed char *x_fallback,
+                const mmgap_schedule *sched, signed char *spins_out, float *e_out,
+                int *win_out, void *stream)
+{
+    if (!ctx) return MMGAP_EINVAL;
+    if (n_inst < 0) return fail(ctx, MMGAP_EINVAL, "n_inst=%d < 0", n_inst);
+    if (K < 1 || K > mmgap::kMaxK) return fail(ctx, MMGAP_EUNSUPPORTED, "K=%d outside 1..32", K);
+    if (q < 1 || q > mmgap::kMaxQ) return fail(ctx, MMGAP_EUNSUPPORTED, "q=%d outside 1..4", q);
+    if (!w) return fail(ctx, MMGAP_EINVAL, "w is NULL");
+    int wv[mmgap::kMaxQ] = {1, 1, 1, 1};
+    for (int b = 0; b < q; ++b) {
+        if (!pow2_weight(w[b]))
+            return fail(ctx, MMGAP_EUNSUPPORTED, "w[%d]=%d is not a power of two in 1..64", b, w[b]);
+        wv[b] = w[b];
+    }
+    if (inst_per_G < 1) return fail(ctx, MMGAP_EINVAL, "inst_per_G=%d < 1", inst_per_G);
+    int rc = check_schedule(ctx, sched);
+    if (rc) return rc;
+    if (n_inst == 0) return MMGAP_OK;
+    if (!G || !f || !spins_out || !e_out)
+        return fail(ctx, MMGAP_EINVAL, "G, f, spins_out and e_out are required");
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int KT = mmgap::padded_k(K);
+    const int NW = mmgap::spin_words(KT, q);
+    const int n_G = (n_inst + inst_per_G - 1) / inst_per_G;
+    const bool pad = KT != K;
+    Plan plan;
+    const size_t oG = pad ? plan.take(sizeof(float) * (size_t)n_G * KT * KT) : 0;
+    const size_t of = pad ? plan.take(sizeof(float) * (size_t)n_inst * KT) : 0;
+    const size_t ox = (pad && x_fallback) ? plan.take((size_t)n_inst * KT) : 0;
+    const size_t oE = plan.take(sizeof(float) * (size_t)n_inst * sched->chains);
+    const size_t oS = plan.take(sizeof(uint32_t) * (size_t)n_inst * sched->chains * NW);
+    if ((rc = ensure_scratch(ctx, plan.off))) return rc;
+    if ((rc = begin_call(ctx, st))) return rc;
+    const float *Gp = G;
+    const float *fp = f;
+    const signed char *xp = x_fallback;
+    hipError_t e = hipSuccess;
+    if (pad) {
+        e = mmgap::launch_pad_matrix(G, at<float>(ctx, oG), n_G, K, KT, st);
+        if (e == hipSuccess) e = mmgap::launch_pad_rows_f32(f, at<float>(ctx, of), n_inst, K, KT, st);
+        if (e == hipSuccess && x_fallback)
+            e = mmgap::launch_pad_rows_i8(x_fallback, at<signed char>(ctx, ox), n_inst, K, KT, st);
+        if (e != hipSuccess) return hip_fail(ctx, e, "pad launch");
+        Gp = at<float>(ctx, oG);
+        fp = at<float>(ctx, of);
+        xp = x_fallback ? at<signed char>(ctx, ox) : nullptr;
+    }
+    mmgap::SelectArgs sel{};
+    sel.mode = mmgap::kSelectSolve;
+    sel.spins_out = spins_out;
+    sel.e_out = e_out;
+    sel.win_out = win_out;
+    rc = run_solver(ctx, st, n_inst, K, q, KT, wv, Gp, inst_per_G, fp, xp, sched,
+                    at<float>(ctx, oE), at<uint32_t>(ctx, oS), sel);
+    if (rc) return rc;
+    return end_call(ctx, st);
+}
+
+int mmgap_detect(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, const void *y,
+                 const mmgap_schedule *sched, unsigned char *sym_out, float *metric_out,
+                 void *stream)
+{
+    if (!ctx) return MMGAP_EINVAL;
+    ProblemShape sh;
+    int rc = check_problem(ctx, prob, MMGAP_KIND_DET, &sh);
+    if (rc) return rc;
+    if ((rc = check_schedule(ctx, sched))) return rc;
+    if (sh.n_inst == 0) return MMGAP_OK;
+    if (!H || !y || !sym_out) return fail(ctx, MMGAP_EINVAL, "H, y and sym_out are required");
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int KT = sh.KT, NW = mmgap::spin_words(KT, sh.q), ni = sh.n_inst;
+    Plan plan;
+    const size_t oG = plan.take(sizeof(float) * (size_t)prob->n_sc * KT * KT);
+    const size_t of = plan.take(sizeof(float) * (size_t)ni * KT);
+    const size_t ox = plan.take((size_t)ni * KT);
+    const size_t oE = plan.take(sizeof(float) * (size_t)ni * sched->chains);
+    const size_t oS = plan.take(sizeof(uint32_t) * (size_t)ni * sched->chains * NW);
+    if ((rc = ensure_scratch(ctx, plan.off))) return rc;
+    if ((rc = begin_call(ctx, st))) return rc;
+    mmgap::DetBuildArgs b{};
+    b.H = (const float2 *)H;
+    b.y = (const float2 *)y;
+    b.n_sc = prob->n_sc;
+    b.n_r = prob->n_rx;
+    b.n_t = prob->n_tx;
+    b.n_sym = prob->n_sym;
+    b.ld = KT;
+    b.qtop = (1 << sh.q) - 1;
+    b.c = qam_c(prob->qam);
+    b.c2 = qam_c2(prob->qam);
+    b.noise_var = (double)prob->noise_var;
+    b.G = at<float>(ctx, oG);
+    b.f = at<float>(ctx, of);
+    b.x_fb = at<signed char>(ctx, ox);
+    b.ynorm = nullptr;
+    hipError_t e = mmgap::launch_det_build(b, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "build launch");
+    int w[mmgap::kMaxQ];
+    det_weights(sh.q, w);
+    mmgap::SelectArgs sel{};
+    sel.mode = mmgap::kSelectDet;
+    sel.H = (const float2 *)H;
+    sel.y = (const float2 *)y;
+    sel.n_rows = prob->n_rx;
+    sel.n_cols = prob->n_tx;
+    sel.n_sym = prob->n_sym;
+    sel.c = b.c;
+    sel.sym_out = sym_out;
+    sel.metric_out = metric_out;
+    rc = run_solver(ctx, st, ni, sh.K, sh.q, KT, w, b.G, prob->n_sym, b.f, b.x_fb, sched,
+                    at<float>(ctx, oE), at<uint32_t>(ctx, oS), sel);
+    if (rc) return rc;
+    return end_call(ctx, st);
+}
+
+int mmgap_vpp_precode(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, const void *u,
+                      const mmgap_schedule *sched, signed char *v_out, void *x_out,
+                      float *gamma_out, void *stream)
+{
+    if (!ctx) return MMGAP_EINVAL;
+    ProblemShape sh;
+    int rc = check_problem(ctx, prob, MMGAP_KIND_VPP, &sh);
+    if (rc) return rc;
+    if ((rc = check_schedule(ctx, sched))) return rc;
+    if (sh.n_inst == 0) return MMGAP_OK;
+    if (!H || !u || !v_out) return fail(ctx, MMGAP_EINVAL, "H, u and v_out are required");
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int KT = sh.KT, NW = mmgap::spin_words(KT, sh.q), ni = sh.n_inst;
+    const int nu = prob->n_rx;
+    Plan plan;
+    const size_t oG = plan.take(sizeof(float) * (size_t)prob->n_sc * KT * KT);
+    const size_t of = plan.take(sizeof(float) * (size_t)ni * KT);
+    const size_t ox = plan.take((size_t)ni * KT);
+    const size_t oA = plan.take(sizeof(double2) * (size_t)prob->n_sc * nu * nu);
+    const size_t oE = plan.take(sizeof(float) * (size_t)ni * sched->chains);
+    const size_t oS = plan.take(sizeof(uint32_t) * (size_t)ni * sched->chains * NW);
+    if ((rc = ensure_scratch(ctx, plan.off))) return rc;
+    if ((rc = begin_call(ctx, st))) return rc;
+    mmgap::VppBuildArgs b{};
+    b.H = (const float2 *)H;
+    b.u = (const float2 *)u;
+    b.n_sc = prob->n_sc;
+    b.n_u = nu;
+    b.n_t = prob->n_tx;
+    b.n_sym = prob->n_sym;
+    b.ld = KT;
+    b.tau = vpp_tau(prob);
+    b.G = at<float>(ctx, oG);
+    b.f = at<float>(ctx, of);
+    b.x_fb = at<signed char>(ctx, ox);
+    b.Ainv = at<double2>(ctx, oA);
+    b.unorm = nullptr;
+    hipError_t e = mmgap::launch_vpp_build(b, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "build launch");
+    int w[mmgap::kMaxQ];
+    vpp_weights(w);
+    mmgap::SelectArgs sel{};
+    sel.mode = mmgap::kSelectVpp;
+    sel.H = (const float2 *)H;
+    sel.y = (const float2 *)u;
+    sel.n_rows = nu;
+    sel.n_cols = prob->n_tx;
+    sel.n_sym = prob->n_sym;
+    sel.Ainv = b.Ainv;
+    sel.tau = b.tau;
+    sel.v_out = v_out;
+    sel.x_out = (float2 *)x_out;
+    sel.gamma_out = gamma_out;
+    rc = run_solver(ctx, st, ni, sh.K, sh.q, KT, w, b.G, prob->n_sym, b.f, b.x_fb, sched,
+                    at<float>(ctx, oE), at<uint32_t>(ctx, oS), sel);
+    if (rc) return rc;
+    return end_call(ctx, st);
+}
+
+}  // extern "C"

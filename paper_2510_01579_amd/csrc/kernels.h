@@ -1,0 +1,117 @@
+// Internal interface between the C ABI (capi.hip) and the device code
+// (kernels.hip).  Not installed; the public interface is include/mmgap.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mmgap {
+
+// Supported structure of the anneal kernels: K padded up to KT in {8,16,32},
+// q in 1..4 spins per real dimension.
+constexpr int kMaxK = 32;
+constexpr int kMaxQ = 4;
+constexpr int kMaxChains = 1024;
+constexpr int kMaxSweeps = 8192;
+// Metropolis threshold table: T[j] = round(2^16 2^(-j/64)), j < 1024; T[1024] = 0
+constexpr int kAcceptTable = 1025;
+
+inline int padded_k(int K) { return K <= 8 ? 8 : (K <= 16 ? 16 : 32); }
+inline int spin_words(int KT, int q) { return (KT * q + 31) / 32; }
+
+struct DetBuildArgs {
+    const float2 *H;        // [n_sc][n_r][n_t]
+    const float2 *y;        // [n_sc][n_sym][n_r]
+    int n_sc, n_r, n_t, n_sym;
+    int ld;                 // leading dimension of G / f / x_fb outputs (>= 2 n_t)
+    int qtop;               // 2^q - 1, the largest PAM level
+    double c, c2;           // constellation scale and its square
+    double noise_var;
+    float *G;               // [n_sc][ld][ld]
+    float *f;               // [n_sc*n_sym][ld]
+    signed char *x_fb;      // [n_sc*n_sym][ld] or null
+    double *ynorm;          // [n_sc*n_sym] ||y||^2 or null
+};
+
+struct VppBuildArgs {
+    const float2 *H;        // [n_sc][n_u][n_t]
+    const float2 *u;        // [n_sc][n_sym][n_u]
+    int n_sc, n_u, n_t, n_sym;
+    int ld;
+    double tau;
+    float *G;               // [n_sc][ld][ld]
+    float *f;               // [n_sc*n_sym][ld]
+    signed char *x_fb;      // [n_sc*n_sym][ld] zeros, or null
+    double2 *Ainv;          // [n_sc][n_u][n_u] or null
+    double *unorm;          // [n_sc*n_sym] u^H A^-1 u or null
+};
+
+struct AnnealArgs {
+    const float *G;         // [n_G][KT][KT]
+    int inst_per_G;
+    const float *f;         // [n_inst][KT]
+    const signed char *x_fb;// [n_inst][KT] (init from fallback) or null
+    const float *beta2;     // [sweeps] device
+    const uint32_t *accept_table;  // [kAcceptSteps + 1] device
+    int sweeps, chains, n_inst;
+    int w[kMaxQ];           // spin weights (powers of two)
+    uint32_t key0, key1;
+    int init_mode;
+    float *chain_E;         // [n_inst][chains]
+    uint32_t *chain_S;      // [n_inst][chains][NW]
+};
+
+enum SelectMode { kSelectSolve = 0, kSelectDet = 1, kSelectVpp = 2 };
+
+struct SelectArgs {
+    int mode;
+    int n_inst, K, KT, q, chains;
+    int w[kMaxQ];
+    const float *G;         // [n_G][KT][KT]
+    int inst_per_G;
+    const float *f;         // [n_inst][KT]
+    const signed char *x_fb;// [n_inst][KT] or null
+    const float *chain_E;
+    const uint32_t *chain_S;
+    // solve outputs
+    signed char *spins_out; // [n_inst][K*q]
+    float *e_out;           // [n_inst]
+    int *win_out;           // [n_inst] or null
+    // detection decode
+    const float2 *H;        // DET [n_sc][n_r][n_t]; VPP [n_sc][n_u][n_tx]
+    const float2 *y;        // DET y [n_sc][n_sym][n_r]; VPP u [n_sc][n_sym][n_u]
+    int n_rows, n_cols, n_sym;
+    double c;
+    unsigned char *sym_out; // [n_inst][n_t]
+    float *metric_out;      // [n_inst] or null
+    // VPP decode
+    const double2 *Ainv;    // [n_sc][n_u][n_u]
+    double tau;
+    signed char *v_out;     // [n_inst][2 n_u]
+    float2 *x_out;          // [n_inst][n_tx] or null
+    float *gamma_out;       // [n_inst] or null
+};
+
+struct ExpandArgs {
+    const float *G;         // [n_sc][K][K] (unpadded)
+    const float *f;         // [n_inst][K]
+    const double *norm;     // [n_inst] ||y||^2 or u^H A^-1 u
+    int n_sc, n_sym, K, q;
+    int w[kMaxQ];
+    float *J;               // [n_sc][N][N] or null
+    float *h;               // [n_inst][N] or null
+    float *e_const;         // [n_inst] or null
+};
+
+hipError_t launch_det_build(const DetBuildArgs &a, hipStream_t s);
+hipError_t launch_vpp_build(const VppBuildArgs &a, hipStream_t s);
+hipError_t launch_anneal(int KT, int q, const AnnealArgs &a, hipStream_t s);
+hipError_t launch_select(const SelectArgs &a, hipStream_t s);
+hipError_t launch_expand(const ExpandArgs &a, hipStream_t s);
+// copy [n][K][K] -> [n][KT][KT] (and [m][K] -> [m][KT]) with zero padding
+hipError_t launch_pad_matrix(const float *src, float *dst, int n, int K, int KT, hipStream_t s);
+hipError_t launch_pad_rows_f32(const float *src, float *dst, int m, int K, int KT, hipStream_t s);
+hipError_t launch_pad_rows_i8(const signed char *src, signed char *dst, int m, int K, int KT,
+                              hipStream_t s);
+
+}  // namespace mmgap

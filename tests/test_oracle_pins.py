@@ -54,42 +54,37 @@ def test_draw16_distinct_streams():
     assert [O.draw16(i, 0, 0, 0, seed + 1) for i in range(4)] != base[:4]
 
 
-# ---------------------------------------------------------------- exp2 / acceptance
-def test_exp2_coefficients_are_taylor():
-    a = O.exp2_coefficients()
-    for k in range(7):
-        exact = (-math.log(2.0)) ** k / math.factorial(k)
-        assert abs(float(a[k]) - exact) <= 1e-7 * max(1.0, abs(exact))
-
-
-def test_exp2_against_numpy():
-    """2^-z on [0,16) within the truncation bound (ln2)^7/7!/0.5 plus float rounding,
-    and never below the true value (alternating series cut after a positive term)."""
-    z = np.linspace(0.0, 15.999, 4001, dtype=np.float32)
-    got = np.array([O.exp2_neg(float(v)) for v in z])
-    ref = np.exp2(-z.astype(np.float64))
-    rel = (got - ref) / ref
-    bound = (math.log(2.0) ** 7 / math.factorial(7)) / 0.5
-    assert np.max(np.abs(rel)) <= bound + 4e-7
-    assert np.min(rel) >= -4e-7
+# ---------------------------------------------------------------- acceptance
+def test_accept_table_values():
+    """T[j] = round(2^16 2^(-j/64)) computed independently with 60-digit decimals."""
+    from decimal import Decimal, getcontext, ROUND_FLOOR
+    getcontext().prec = 60
+    ln2 = Decimal(2).ln()
+    T = O.accept_table()
+    assert T.shape == (1025,) and T[1024] == 0 and T[0] == 65536
+    for j in range(0, 1024, 7):
+        v = Decimal(65536) * (-(Decimal(j) / 64) * ln2).exp()
+        assert int(T[j]) == int((v + Decimal("0.5")).to_integral_value(rounding=ROUND_FLOOR))
+    assert np.all(np.diff(T.astype(np.int64)) <= 0)
 
 
 def test_accept_rule_counts():
-    """Metropolis with u = (m+1)/2^16: for fixed z the accepted draws are the prefix
-    m + 1 <= 2^16 2^-z, their count matches 2^16 2^-z, z <= 0 always accepts and
-    z > 16 never does."""
+    """Metropolis with a 16-bit uniform: for fixed z the accepted draws are the
+    prefix m < T[floor(64 z)], so the acceptance rate is 2^-z up to the 1/64
+    quantisation of z and the 2^-16 resolution; z <= 0 always accepts, z >= 16
+    never does, NaN counts as downhill."""
     for z in [-3.0, 0.0, 1e-7, 0.37, 1.0, 2.5, 7.25, 12.0, 15.5, 15.99, 16.0, 16.01,
-              17.0, 40.0, float("inf"), float("-inf")]:
-        acc = np.array([O.accept(z, m) for m in range(65536)])
+              17.0, 40.0, float("inf"), float("-inf"), float("nan")]:
+        acc = np.array([O.accept(z, m) for m in range(0, 65536, 1)])
         n = int(acc.sum())
         assert acc[:n].all() and not acc[n:].any()
-        if z <= 0:
+        if not (z > 0):
             assert n == 65536
-        elif z > 16:
+        elif z >= 16:
             assert n == 0
         else:
-            assert abs(n / 65536 - 2.0 ** (-z)) <= 2.0 ** -16 + 3.1e-5 * 2.0 ** (-z)
-    assert sum(O.accept(16.0, m) for m in range(4)) == 1
+            p = 2.0 ** (-z)
+            assert p - 2.0 ** -16 <= n / 65536 <= p * 2.0 ** (1 / 64) + 2.0 ** -16
 
 
 # ---------------------------------------------------------------- encoding
@@ -133,6 +128,18 @@ def test_real_decomposition_identity():
     Hr = O.real_matrix(H)
     rhs = ((O.real_vector(y) - np.einsum("sik,sk->si", Hr, O.real_vector(x))) ** 2).sum(-1)
     assert np.allclose(lhs, rhs, rtol=1e-12, atol=0)
+
+
+def test_gram_is_real_form_of_channel_gram():
+    """G / c^2 equals H_r^T H_r built from the real decomposition directly."""
+    d = W.det_slot(20, 6, 4, 16, 3, 2, 12.0)
+    G, f = O.det_ising64(d.H, d.y, 16)
+    c = O.qam_scale(16)
+    Hr = O.real_matrix(d.H.astype(np.complex128))
+    assert np.allclose(G / c ** 2, np.einsum("sik,sil->skl", Hr, Hr), rtol=1e-13, atol=1e-13)
+    yr = O.real_vector(d.y.astype(np.complex128))
+    assert np.allclose(f / c, np.einsum("sik,sbi->sbk", Hr, yr), rtol=1e-13, atol=1e-13)
+    assert np.array_equal(G, np.swapaxes(G, 1, 2))
 
 
 @pytest.mark.parametrize("qam,n_r,n_t", [(4, 4, 4), (16, 8, 8), (64, 16, 16), (16, 6, 3)])
