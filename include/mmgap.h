@@ -126,11 +126,20 @@ int mmgap_build_ising(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H,
  *   spins_out    [n_inst][K*q] int8, +1/-1 (out)
  *   e_out        [n_inst] float32 energy x^T G x - 2 f^T x of the result (out)
  *   win_out      [n_inst] int32 winning chain index, `chains` = fallback (out, nullable)
- * Chain arithmetic (float32, round-to-nearest): g = G x - f; flip of spin i
- * changes x_k by d = -2 w_b s_i with dE = d (2 g_k + d G_kk); z = beta2_t dE;
- * accepted iff z <= 0 or (z < 16 and m < 2^16 2^-z) with m a 16-bit Philox draw
- * (counter (i/8, t, chain, n)); on acceptance g_j += G_kj d.  Sweeps visit
- * i = 0..K q - 1 in order.  Ties in energy keep the lowest chain index.
+ * Chain arithmetic (float32, round-to-nearest, fma = single-rounding fused
+ * multiply-add).  Sweeps visit the dimensions k = 0..K-1 and, within k, the
+ * spins b = 0..q-1 (i = k q + b).  At each visit of k the field
+ * g_k = (G x)_k - f_k is recomputed as fma(G_k,K-1, x_K-1, ... fma(G_k0, x_0, -f_k));
+ * a flip of spin i changes x_k by d = -2 w_b s_i with dE = d ((g_k + g_k) + d G_kk),
+ * z = beta2_t dE, and is accepted iff m < T[j], where m is the 16-bit Philox
+ * draw of (spin i, sweep t, chain, instance n) -- Philox4x32-10 with counter
+ * (i/8, t, chain, n) and key (seed_lo, seed_hi), low half of word (i%8)/2 for
+ * even i, high half for odd i --, j = floor(64 z) clamped to
+ * [0, 1024] (z <= 0 or NaN gives 0) and T[j] = round(2^16 2^(-j/64)),
+ * T[1024] = 0; on acceptance x_k += d and g_k = fma(G_kk, d, g_k).  Initial
+ * spins: s_i = -1 iff bit 15 of the draw of (i, 0xffffffff, chain, n) is set.
+ * Energies E = fma(x_K-1, g_K-1 - f_K-1, ... fma(x_0, g_0 - f_0, 0)) with
+ * fresh fields.  Ties in energy keep the lowest chain index.
  */
 int mmgap_solve(mmgap_ctx *ctx, int n_inst, int K, int q, const signed char *w,
                 const float *G, int inst_per_G, const float *f, const signed char *x_fallback,
@@ -163,6 +172,19 @@ int mmgap_detect(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, const
 int mmgap_vpp_precode(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, const void *u,
                       const mmgap_schedule *sched, signed char *v_out, void *x_out,
                       float *gamma_out, void *stream);
+
+/*
+ * Tracing.  mmgap_set_profiling(ctx, 1) (re)starts recording: every later
+ * compute call records HIP events on its stream around its stages, keeping the
+ * last 256 calls.  mmgap_last_profile waits for those events and writes, oldest
+ * call first, three host floats per call -- elapsed milliseconds of the build
+ * (0 for mmgap_solve), the anneal kernel and the select/decode kernel -- for
+ * at most capacity/3 of the most recent calls.  Returns the number of floats
+ * written, or a negative mmgap_status (MMGAP_EINVAL if profiling is off or no
+ * call was recorded).  Recording adds no synchronisation to the calls.
+ */
+int mmgap_set_profiling(mmgap_ctx *ctx, int enable);
+int mmgap_last_profile(mmgap_ctx *ctx, float *ms, int capacity);
 
 #ifdef __cplusplus
 }

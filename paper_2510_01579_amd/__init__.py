@@ -30,7 +30,8 @@ STATUS = {0: "MMGAP_OK", -1: "MMGAP_EINVAL", -2: "MMGAP_ENOMEM", -3: "MMGAP_EDEV
           -4: "MMGAP_EUNSUPPORTED", -5: "MMGAP_EBUSY"}
 
 EXPORTS = ("mmgap_create", "mmgap_destroy", "mmgap_last_error", "mmgap_build_ising",
-           "mmgap_solve", "mmgap_detect", "mmgap_vpp_precode")
+           "mmgap_solve", "mmgap_detect", "mmgap_vpp_precode", "mmgap_set_profiling",
+           "mmgap_last_profile")
 
 
 class MmgapError(RuntimeError):
@@ -75,6 +76,8 @@ def lib() -> ctypes.CDLL:
             L.mmgap_solve.argtypes = [vp, i, i, i, vp, vp, i, vp, vp, S, vp, vp, vp, vp]
             L.mmgap_detect.argtypes = [vp, P, vp, vp, S, vp, vp, vp]
             L.mmgap_vpp_precode.argtypes = [vp, P, vp, vp, S, vp, vp, vp, vp]
+            L.mmgap_set_profiling.argtypes = [vp, i]
+            L.mmgap_last_profile.argtypes = [vp, ctypes.POINTER(f32), i]
             for name in EXPORTS:
                 if name not in ("mmgap_last_error",):
                     getattr(L, name).restype = i
@@ -157,6 +160,19 @@ class Context:
 
     def _dev(self):
         return _torch().device("cuda", self.device)
+
+    def set_profiling(self, enable: bool = True):
+        """(Re)start recording HIP events around the stages of every later call."""
+        self._check(lib().mmgap_set_profiling(self._h, int(bool(enable))))
+
+    def profile(self, max_calls: int = 256):
+        """[(build_ms, anneal_ms, select_ms), ...] of the recorded calls, oldest first
+        (waits for them)."""
+        buf = (ctypes.c_float * (3 * max_calls))()
+        rc = lib().mmgap_last_profile(self._h, buf, 3 * max_calls)
+        if rc < 0:
+            self._check(rc)
+        return [tuple(float(v) for v in buf[i:i + 3]) for i in range(0, rc, 3)]
 
     # ------------------------------------------------------------------ helpers
     def _check_tensor(self, t, name, dtype, shape):

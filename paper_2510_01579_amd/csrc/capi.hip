@@ -17,6 +17,7 @@ namespace {
 constexpr int kRing = 8;                        // schedule upload slots
 constexpr size_t kDefaultBudget = size_t(16) << 30;
 constexpr size_t kAlign = 256;
+constexpr int kProfRing = 256;                  // profiled calls kept
 
 thread_local std::string g_create_error;
 
@@ -35,6 +36,9 @@ struct mmgap_ctx {
     hipEvent_t done = nullptr;                  // end of the last call's work
     bool done_valid = false;
     uint32_t *accept_dev = nullptr;             // Metropolis threshold table
+    bool profiling = false;
+    long prof_count = 0;                        // profiled calls since enabling
+    hipEvent_t prof_ev[kProfRing][4] = {};      // start, before anneal, after anneal, end
 };
 
 namespace {
@@ -161,6 +165,11 @@ int end_call(mmgap_ctx *ctx, hipStream_t s)
     return MMGAP_OK;
 }
 
+void prof_mark(mmgap_ctx *ctx, int i, hipStream_t s)
+{
+    if (ctx->profiling) (void)hipEventRecord(ctx->prof_ev[ctx->prof_count % kProfRing][i], s);
+}
+
 // Copies the host schedule into a device ring slot; returns the device table.
 int upload_beta(mmgap_ctx *ctx, const mmgap_schedule *s, hipStream_t st, const float **out)
 {
@@ -265,8 +274,10 @@ int run_solver(mmgap_ctx *ctx, hipStream_t st, int n_inst, int K, int q, int KT,
     a.init_mode = sched->init;
     a.chain_E = chainE;
     a.chain_S = chainS;
+    prof_mark(ctx, 1, st);
     hipError_t e = mmgap::launch_anneal(KT, q, a, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "anneal launch");
+    prof_mark(ctx, 2, st);
     sel.n_inst = n_inst;
     sel.K = K;
     sel.KT = KT;
@@ -281,6 +292,8 @@ int run_solver(mmgap_ctx *ctx, hipStream_t st, int n_inst, int K, int q, int KT,
     sel.chain_S = chainS;
     e = mmgap::launch_select(sel, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "select launch");
+    prof_mark(ctx, 3, st);
+    if (ctx->profiling) ++ctx->prof_count;
     return MMGAP_OK;
 }
 
@@ -340,6 +353,9 @@ int mmgap_destroy(mmgap_ctx *ctx)
     if (ctx->beta_host) (void)hipHostFree(ctx->beta_host);
     for (int i = 0; i < kRing; ++i)
         if (ctx->ring_ev[i]) (void)hipEventDestroy(ctx->ring_ev[i]);
+    for (int r = 0; r < kProfRing; ++r)
+        for (int i = 0; i < 4; ++i)
+            if (ctx->prof_ev[r][i]) (void)hipEventDestroy(ctx->prof_ev[r][i]);
     if (ctx->done) (void)hipEventDestroy(ctx->done);
     if (ctx->accept_dev) (void)hipFree(ctx->accept_dev);
     delete ctx;
@@ -463,6 +479,7 @@ int mmgap_solve(mmgap_ctx *ctx, int n_inst, int K, int q, const signed char *w,
     const size_t oS = plan.take(sizeof(uint32_t) * (size_t)n_inst * sched->chains * NW);
     if ((rc = ensure_scratch(ctx, plan.off))) return rc;
     if ((rc = begin_call(ctx, st))) return rc;
+    prof_mark(ctx, 0, st);
     const float *Gp = G;
     const float *fp = f;
     const signed char *xp = x_fallback;
@@ -510,6 +527,7 @@ int mmgap_detect(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, const
     const size_t oS = plan.take(sizeof(uint32_t) * (size_t)ni * sched->chains * NW);
     if ((rc = ensure_scratch(ctx, plan.off))) return rc;
     if ((rc = begin_call(ctx, st))) return rc;
+    prof_mark(ctx, 0, st);
     mmgap::DetBuildArgs b{};
     b.H = (const float2 *)H;
     b.y = (const float2 *)y;
@@ -570,6 +588,7 @@ int mmgap_vpp_precode(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, 
     const size_t oS = plan.take(sizeof(uint32_t) * (size_t)ni * sched->chains * NW);
     if ((rc = ensure_scratch(ctx, plan.off))) return rc;
     if ((rc = begin_call(ctx, st))) return rc;
+    prof_mark(ctx, 0, st);
     mmgap::VppBuildArgs b{};
     b.H = (const float2 *)H;
     b.u = (const float2 *)u;
@@ -604,6 +623,46 @@ int mmgap_vpp_precode(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, 
                     at<float>(ctx, oE), at<uint32_t>(ctx, oS), sel);
     if (rc) return rc;
     return end_call(ctx, st);
+}
+
+int mmgap_set_profiling(mmgap_ctx *ctx, int enable)
+{
+    if (!ctx) return MMGAP_EINVAL;
+    DeviceGuard g(ctx->device);
+    if (enable && !ctx->prof_ev[0][0]) {
+        for (int r = 0; r < kProfRing; ++r)
+            for (int i = 0; i < 4; ++i) {
+                hipError_t e = hipEventCreate(&ctx->prof_ev[r][i]);
+                if (e != hipSuccess) return hip_fail(ctx, e, "hipEventCreate(profile)");
+            }
+    }
+    ctx->profiling = enable != 0;
+    ctx->prof_count = 0;
+    return MMGAP_OK;
+}
+
+int mmgap_last_profile(mmgap_ctx *ctx, float *ms, int capacity)
+{
+    if (!ctx) return MMGAP_EINVAL;
+    if (!ms || capacity < 3) return fail(ctx, MMGAP_EINVAL, "ms needs room for 3 entries");
+    if (!ctx->profiling || ctx->prof_count == 0)
+        return fail(ctx, MMGAP_EINVAL, "no profiled call (enable with mmgap_set_profiling)");
+    DeviceGuard g(ctx->device);
+    long avail = ctx->prof_count < kProfRing ? ctx->prof_count : kProfRing;
+    long n = capacity / 3 < avail ? capacity / 3 : avail;
+    const long first = ctx->prof_count - n;
+    for (long c = 0; c < n; ++c) {
+        hipEvent_t *ev = ctx->prof_ev[(first + c) % kProfRing];
+        hipError_t e = hipEventSynchronize(ev[3]);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipEventSynchronize(profile)");
+        for (int i = 0; i < 3; ++i) {
+            float v = 0.0f;
+            e = hipEventElapsedTime(&v, ev[i], ev[i + 1]);
+            if (e != hipSuccess) return hip_fail(ctx, e, "hipEventElapsedTime");
+            ms[3 * c + i] = v;
+        }
+    }
+    return (int)(3 * n);
 }
 
 }  // extern "C"

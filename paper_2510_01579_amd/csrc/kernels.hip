@@ -442,6 +442,12 @@ k_anneal(const float *__restrict__ G, int inst_per_G, const float *__restrict__ 
     constexpr int N = KT * Q;
     constexpr int NW = (N + 31) / 32;
     constexpr int NG = (N + 7) / 8;
+    // Spin state: one float flip step per spin when few spins, else one bit per
+    // spin (set = spin -1) so that large problems keep enough wavefronts
+    // resident; both hold the same values.
+    constexpr bool kBits = N > 48 || KT == 32;
+    constexpr int ND = kBits ? 1 : N;
+    constexpr int NB = kBits ? NW : 1;
     __shared__ uint32_t T[kAcceptSteps + 1];
     for (int e = threadIdx.x; e <= kAcceptSteps; e += kBlock) T[e] = accept_table[e];
     __syncthreads();
@@ -456,12 +462,25 @@ k_anneal(const float *__restrict__ G, int inst_per_G, const float *__restrict__ 
     const float *__restrict__ Gi = G + (size_t)(inst / inst_per_G) * (KT * KT);
     const float *__restrict__ fi = f + (size_t)inst * KT;
     const int wts[4] = {w0, w1, w2, w3};
+    float two_w[Q];
+#pragma unroll
+    for (int b = 0; b < Q; ++b) two_w[b] = (float)(2 * wts[b]);
 
     const uint32_t uch = (uint32_t)ch;
     const uint32_t uinst = (uint32_t)inst;
 
-    // flip steps d_i = -2 w_b s_i of the initial spins
-    float dv[N];
+    // flip steps d_i = -2 w_b s_i of the initial spins (or their sign bits)
+    float dv[ND];
+    uint32_t sb[NB];
+#pragma unroll
+    for (int w = 0; w < NB; ++w) sb[w] = 0u;
+    auto set_spin = [&](int i, bool negative) {
+        if constexpr (kBits) {
+            if (negative) sb[i >> 5] |= 1u << (i & 31);
+        } else {
+            dv[i] = negative ? two_w[i % Q] : -two_w[i % Q];
+        }
+    };
     if (init_mode == 1 && x_fb != nullptr) {
         const signed char *xi = x_fb + (size_t)inst * KT;
 #pragma unroll
@@ -471,7 +490,7 @@ k_anneal(const float *__restrict__ G, int inst_per_G, const float *__restrict__ 
             for (int b = 0; b < Q; ++b) {
                 const int sg = rem > 0 ? 1 : -1;
                 rem -= wts[b] * sg;
-                dv[k * Q + b] = (float)(-2 * wts[b] * sg);
+                set_spin(k * Q + b, sg < 0);
             }
         }
     } else {
@@ -484,18 +503,24 @@ k_anneal(const float *__restrict__ G, int inst_per_G, const float *__restrict__ 
                 const int i = 8 * j + e;
                 if (i < N) {
                     const uint32_t d = (e & 1) ? (r[e >> 1] >> 16) : (r[e >> 1] & 0xFFFFu);
-                    const float two_w = (float)(2 * wts[i % Q]);
-                    dv[i] = (d & 0x8000u) ? two_w : -two_w;   // spin -1 -> d = +2w
+                    set_spin(i, (d & 0x8000u) != 0u);   // spin -1 -> d = +2w
                 }
             }
         }
     }
+    auto step_of = [&](int i) -> float {
+        if constexpr (kBits) {
+            return ((sb[i >> 5] >> (i & 31)) & 1u) ? two_w[i % Q] : -two_w[i % Q];
+        } else {
+            return dv[i];
+        }
+    };
     float x[KT];
 #pragma unroll
     for (int k = 0; k < KT; ++k) {
         float lv = 0.0f;
 #pragma unroll
-        for (int b = 0; b < Q; ++b) lv = lv - 0.5f * dv[k * Q + b];   // w_b s = -d/2, exact
+        for (int b = 0; b < Q; ++b) lv = lv - 0.5f * step_of(k * Q + b);   // w_b s = -d/2, exact
         x[k] = lv;
     }
 
@@ -545,7 +570,7 @@ k_anneal(const float *__restrict__ G, int inst_per_G, const float *__restrict__ 
                 }
                 const int e = i & 7;
                 const uint32_t m = (e & 1) ? (r[e >> 1] >> 16) : (r[e >> 1] & 0xFFFFu);
-                const float d = dv[i];
+                const float d = step_of(i);
                 const float h = fmaf(d, gkh, g);                      // g + (d/2) G_kk
                 const float zs = (d * bd) * h;                        // 64 beta2 dE
                 const float zc = fminf(fmaxf(zs, 0.0f), (float)kAcceptSteps);
@@ -554,7 +579,11 @@ k_anneal(const float *__restrict__ G, int inst_per_G, const float *__restrict__ 
                 const float da = acc ? d : 0.0f;
                 x[k] = x[k] + da;
                 g = fmaf(gkk, da, g);
-                dv[i] = acc ? -d : d;
+                if constexpr (kBits) {
+                    sb[i >> 5] ^= acc ? (1u << (i & 31)) : 0u;
+                } else {
+                    dv[i] = acc ? -d : d;
+                }
             }
         }
     }
@@ -575,10 +604,14 @@ k_anneal(const float *__restrict__ G, int inst_per_G, const float *__restrict__ 
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
             uint32_t word = 0u;
+            if constexpr (kBits) {
+                word = sb[w];
+            } else {
 #pragma unroll
-            for (int bit = 0; bit < 32; ++bit) {
-                const int i = 32 * w + bit;
-                if (i < N && dv[i] > 0.0f) word |= 1u << bit;   // d > 0 <=> spin -1
+                for (int bit = 0; bit < 32; ++bit) {
+                    const int i = 32 * w + bit;
+                    if (i < N && dv[i] > 0.0f) word |= 1u << bit;   // d > 0 <=> spin -1
+                }
             }
             chain_S[o * NW + w] = word;
         }
