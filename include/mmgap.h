@@ -174,6 +174,59 @@ int mmgap_vpp_precode(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, 
                       float *gamma_out, void *stream);
 
 /*
+ * Batches: many jobs of mixed kinds and sizes in ONE persistent launch (paper
+ * §3.2 executes each stage as its own kernel over all instances; here the three
+ * stages of every instance run back to back inside one kernel that takes work
+ * items from a device queue, so that one launch serves a mixed workload).
+ *
+ * A job is one call's worth of work: a problem, its schedule, its inputs and
+ * its outputs, exactly as for mmgap_detect / mmgap_vpp_precode:
+ *   DET  y_or_u = y; out0 = sym_out [n_sc*n_sym][n_tx] uint8 (required),
+ *        out1 = metric_out [n_sc*n_sym] float32 (nullable), out2 unused.
+ *   VPP  y_or_u = u; out0 = v_out [n_sc*n_sym][2 n_rx] int8 (required),
+ *        out1 = x_out [n_sc*n_sym][n_tx] complex64 (nullable),
+ *        out2 = gamma_out [n_sc*n_sym] float32 (nullable).
+ * Every output of a job is bit-identical to that of the single-job entry point
+ * on the same arguments, whatever else is in the batch: a chain's random stream
+ * depends only on the job's seed and its instance and chain index.
+ * Limits: those of the single-job calls, and chains <= 256.
+ */
+typedef struct {
+    mmgap_problem prob;
+    mmgap_schedule sched;     /* beta2 is copied at plan creation */
+    const void *H;            /* device, [n_sc][n_rx][n_tx] complex64 */
+    const void *y_or_u;       /* device, [n_sc][n_sym][n_rx] complex64 */
+    void *out0, *out1, *out2; /* device, see above */
+} mmgap_job;
+
+typedef struct mmgap_plan mmgap_plan;
+
+enum { MMGAP_PLAN_GRAPH = 1 };   /* record the launch as a HIP graph, replayed by each launch */
+
+/*
+ * mmgap_plan_create -- validate `n_jobs` jobs (host array), copy their
+ * descriptors and schedules to the device, cut them into work items (one
+ * subcarrier and up to 4, 2 or 1 symbols for <= 64, <= 128, <= 256 chains)
+ * ordered by decreasing cost, and allocate the plan's own device scratch
+ * (couplings, fields, fallbacks, VPP inverses), counted against the context's
+ * HBM budget.  `blocks` = workgroups of the persistent launch, 0 = as many as
+ * the device holds at once.  flags: MMGAP_PLAN_GRAPH or 0.
+ * The plan stores the jobs' device pointers, not their contents: inputs may be
+ * rewritten between launches; they must stay allocated until the plan is
+ * destroyed.  Plans are independent of the context's other calls and must be
+ * destroyed before their context.  On failure *out is NULL and nothing is held.
+ */
+int mmgap_plan_create(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, int flags, int blocks,
+                      mmgap_plan **out);
+/* Enqueue one execution of every job of the plan on `stream`.  Launches of the
+ * same plan run one after another, also when issued on different streams. */
+int mmgap_plan_launch(mmgap_plan *plan, void *stream);
+/* (host) Work items and persistent workgroups of the plan. */
+int mmgap_plan_info(const mmgap_plan *plan, int *n_items, int *blocks);
+/* Wait for the plan's launches and free it (NULL is a no-op). */
+int mmgap_plan_destroy(mmgap_plan *plan);
+
+/*
  * Tracing.  mmgap_set_profiling(ctx, 1) (re)starts recording: every later
  * compute call records HIP events on its stream around its stages, keeping the
  * last 256 calls.  mmgap_last_profile waits for those events and writes, oldest

@@ -9,7 +9,9 @@ the library is missing or no GPU is present the calls raise.
 
 Entry points (same names as the C ABI, without the ``mmgap_`` prefix):
 ``build_ising``, ``solve``, ``detect``, ``vpp_precode``; ``Context`` owns a
-library context (device, scratch, HBM budget).
+library context (device, scratch, HBM budget); ``Context.plan_create`` returns a
+``Plan`` (``plan_launch``, ``plan_info``, ``plan_destroy``) that runs a batch of
+mixed jobs in one persistent launch.
 """
 from __future__ import annotations
 
@@ -31,7 +33,10 @@ STATUS = {0: "MMGAP_OK", -1: "MMGAP_EINVAL", -2: "MMGAP_ENOMEM", -3: "MMGAP_EDEV
 
 EXPORTS = ("mmgap_create", "mmgap_destroy", "mmgap_last_error", "mmgap_build_ising",
            "mmgap_solve", "mmgap_detect", "mmgap_vpp_precode", "mmgap_set_profiling",
-           "mmgap_last_profile")
+           "mmgap_last_profile", "mmgap_plan_create", "mmgap_plan_launch", "mmgap_plan_info",
+           "mmgap_plan_destroy")
+
+PLAN_GRAPH = 1
 
 
 class MmgapError(RuntimeError):
@@ -50,6 +55,12 @@ class Schedule(ctypes.Structure):
     _fields_ = [("chains", ctypes.c_int), ("sweeps", ctypes.c_int),
                 ("beta2", ctypes.POINTER(ctypes.c_float)), ("seed", ctypes.c_uint64),
                 ("init", ctypes.c_int)]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("prob", Problem), ("sched", Schedule), ("H", ctypes.c_void_p),
+                ("y_or_u", ctypes.c_void_p), ("out0", ctypes.c_void_p),
+                ("out1", ctypes.c_void_p), ("out2", ctypes.c_void_p)]
 
 
 _lib = None
@@ -78,6 +89,10 @@ def lib() -> ctypes.CDLL:
             L.mmgap_vpp_precode.argtypes = [vp, P, vp, vp, S, vp, vp, vp, vp]
             L.mmgap_set_profiling.argtypes = [vp, i]
             L.mmgap_last_profile.argtypes = [vp, ctypes.POINTER(f32), i]
+            L.mmgap_plan_create.argtypes = [vp, i, ctypes.POINTER(Job), i, i, ctypes.POINTER(vp)]
+            L.mmgap_plan_launch.argtypes = [vp, vp]
+            L.mmgap_plan_info.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i)]
+            L.mmgap_plan_destroy.argtypes = [vp]
             for name in EXPORTS:
                 if name not in ("mmgap_last_error",):
                     getattr(L, name).restype = i
@@ -292,6 +307,84 @@ class Context:
                                             ctypes.byref(s), _ptr(v), _ptr(x), _ptr(g), st))
         del keep
         return v, x, g
+
+    # ------------------------------------------------------------------ batches
+    def det_job(self, H, y, qam, noise_var, chains, sweeps, beta2, seed, init=0, metric=True):
+        """A detection job for ``plan_create`` with its output tensors allocated:
+        outputs["sym"] uint8 [n][n_tx], outputs["metric"] float32 [n] or None."""
+        torch = _torch()
+        p = self._problem(KIND_DET, H, y, qam, noise_var, 0.0)
+        n = p.n_sc * p.n_sym
+        dev = self._dev()
+        out = dict(sym=torch.empty((n, p.n_tx), dtype=torch.uint8, device=dev),
+                   metric=torch.empty((n,), dtype=torch.float32, device=dev) if metric else None)
+        s, keep = self._schedule(chains, sweeps, beta2, seed, init)
+        job = Job(p, s, _ptr(H).value, _ptr(y).value, _ptr(out["sym"]).value,
+                  None if out["metric"] is None else _ptr(out["metric"]).value, None)
+        return dict(job=job, keep=(H, y, keep), outputs=out)
+
+    def vpp_job(self, H, u, qam, chains, sweeps, beta2, seed, tau=0.0, want_x=True,
+                want_gamma=True, init=0):
+        """A VPP job for ``plan_create``: outputs["v"] int8 [n][2 n_rx],
+        outputs["x"] complex64 [n][n_tx] or None, outputs["gamma"] float32 [n] or None."""
+        torch = _torch()
+        p = self._problem(KIND_VPP, H, u, qam, 0.0, tau)
+        n = p.n_sc * p.n_sym
+        dev = self._dev()
+        out = dict(v=torch.empty((n, 2 * p.n_rx), dtype=torch.int8, device=dev),
+                   x=torch.empty((n, p.n_tx), dtype=torch.complex64, device=dev) if want_x else None,
+                   gamma=torch.empty((n,), dtype=torch.float32, device=dev) if want_gamma else None)
+        s, keep = self._schedule(chains, sweeps, beta2, seed, init)
+        job = Job(p, s, _ptr(H).value, _ptr(u).value, _ptr(out["v"]).value,
+                  None if out["x"] is None else _ptr(out["x"]).value,
+                  None if out["gamma"] is None else _ptr(out["gamma"]).value)
+        return dict(job=job, keep=(H, u, keep), outputs=out)
+
+    def plan_create(self, jobs, graph=True, blocks=0):
+        """A Plan running `jobs` (from det_job / vpp_job) in one persistent launch."""
+        arr = (Job * max(len(jobs), 1))(*[j["job"] for j in jobs])
+        h = ctypes.c_void_p()
+        self._check(lib().mmgap_plan_create(self._h, len(jobs), arr,
+                                            PLAN_GRAPH if graph else 0, int(blocks),
+                                            ctypes.byref(h)))
+        return Plan(self, h, jobs)
+
+
+class Plan:
+    """A batch of jobs compiled to one persistent launch (see mmgap_plan_create).
+    Holds references to the jobs' tensors, which the launches read and write."""
+
+    def __init__(self, ctx: Context, handle, jobs):
+        self.ctx = ctx
+        self._h = handle
+        self.jobs = jobs
+
+    def plan_launch(self, stream=None):
+        st = stream if stream is not None else _stream(self.ctx._dev())
+        self.ctx._check(lib().mmgap_plan_launch(self._h, st))
+
+    launch = plan_launch
+
+    def plan_info(self):
+        """(work items, persistent workgroups)."""
+        a, b = ctypes.c_int(), ctypes.c_int()
+        self.ctx._check(lib().mmgap_plan_info(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    info = plan_info
+
+    def plan_destroy(self):
+        if self._h:
+            lib().mmgap_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    destroy = plan_destroy
+
+    def __del__(self):
+        try:
+            self.plan_destroy()
+        except Exception:
+            pass
 
 
 _default_ctx = {}

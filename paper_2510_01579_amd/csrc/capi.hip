@@ -6,8 +6,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "kernels.h"
 #include "mmgap.h"
@@ -29,6 +31,7 @@ struct mmgap_ctx {
     std::string err;
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
+    size_t plan_bytes = 0;                      // device memory held by live plans
     float *beta_dev = nullptr;                  // [kRing][kMaxSweeps]
     float *beta_host = nullptr;                 // pinned, same shape
     hipEvent_t ring_ev[kRing] = {};
@@ -91,9 +94,10 @@ struct Plan {
 
 int ensure_scratch(mmgap_ctx *ctx, size_t bytes)
 {
-    if (bytes > ctx->budget)
-        return fail(ctx, MMGAP_ENOMEM, "scratch of %zu bytes exceeds the HBM budget of %zu bytes",
-                    bytes, ctx->budget);
+    if (bytes + ctx->plan_bytes > ctx->budget)
+        return fail(ctx, MMGAP_ENOMEM,
+                    "scratch of %zu bytes (+%zu held by plans) exceeds the HBM budget of %zu bytes",
+                    bytes, ctx->plan_bytes, ctx->budget);
     if (bytes <= ctx->scratch_bytes) return MMGAP_OK;
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(ctx, e, "hipDeviceSynchronize");
@@ -101,7 +105,7 @@ int ensure_scratch(mmgap_ctx *ctx, size_t bytes)
     ctx->scratch = nullptr;
     ctx->scratch_bytes = 0;
     size_t want = bytes + bytes / 4;
-    if (want > ctx->budget) want = bytes;
+    if (want + ctx->plan_bytes > ctx->budget) want = bytes;
     e = hipMalloc(&ctx->scratch, want);
     if (e != hipSuccess) {
         ctx->scratch = nullptr;
@@ -295,6 +299,50 @@ int run_solver(mmgap_ctx *ctx, hipStream_t st, int n_inst, int K, int q, int KT,
     prof_mark(ctx, 3, st);
     if (ctx->profiling) ++ctx->prof_count;
     return MMGAP_OK;
+}
+
+constexpr int kMaxFusedChains = 256;   // four wavefronts of a workgroup
+
+// Relative cost of one work item: the workgroup is held for `sweeps` sweeps of
+// KT Q flip attempts, each about 20 operations plus the K-term field row shared
+// by the Q attempts of a dimension.
+double item_cost(const mmgap::FusedJob &j)
+{
+    return (double)j.sweeps * j.KT * (20.0 * j.Q + j.KT);
+}
+
+}  // namespace
+
+struct mmgap_plan {
+    mmgap_ctx *ctx = nullptr;
+    int n_items = 0, blocks = 0;
+    void *mem = nullptr;
+    size_t bytes = 0;
+    mmgap::FusedJob *jobs_dev = nullptr;
+    mmgap::FusedItem *items_dev = nullptr;
+    unsigned int *counter = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;
+    bool done_valid = false;
+};
+
+namespace {
+
+void plan_free(mmgap_plan *p)
+{
+    if (!p) return;
+    if (p->done) {
+        if (p->done_valid) (void)hipEventSynchronize(p->done);
+        (void)hipEventDestroy(p->done);
+    }
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->mem) {
+        (void)hipFree(p->mem);
+        p->ctx->plan_bytes -= p->bytes;
+    }
+    delete p;
 }
 
 }  // namespace
@@ -663,6 +711,195 @@ int mmgap_last_profile(mmgap_ctx *ctx, float *ms, int capacity)
         }
     }
     return (int)(3 * n);
+}
+
+int mmgap_plan_create(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, int flags, int blocks,
+                      mmgap_plan **out)
+{
+    if (!ctx) return MMGAP_EINVAL;
+    if (!out) return fail(ctx, MMGAP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_jobs < 0 || (n_jobs > 0 && !jobs))
+        return fail(ctx, MMGAP_EINVAL, "n_jobs=%d with jobs=%p", n_jobs, (const void *)jobs);
+    if (flags & ~MMGAP_PLAN_GRAPH) return fail(ctx, MMGAP_EINVAL, "unknown flags 0x%x", flags);
+    if (blocks < 0) return fail(ctx, MMGAP_EINVAL, "blocks=%d < 0", blocks);
+
+    // host-side descriptors; device pointers are filled in after allocation
+    std::vector<mmgap::FusedJob> fj((size_t)n_jobs);
+    std::vector<size_t> oG(n_jobs), of(n_jobs), ox(n_jobs), oA(n_jobs), ob(n_jobs);
+    std::vector<mmgap::FusedItem> items;
+    Plan lay;
+    const size_t o_jobs = lay.take(sizeof(mmgap::FusedJob) * (size_t)std::max(n_jobs, 1));
+    for (int j = 0; j < n_jobs; ++j) {
+        const mmgap_job &jb = jobs[j];
+        ProblemShape sh;
+        int rc = check_problem(ctx, &jb.prob, -1, &sh);
+        if (!rc) rc = check_schedule(ctx, &jb.sched);
+        if (rc) return fail(ctx, rc, "job %d: %s", j, ctx->err.c_str());
+        if (jb.sched.chains > kMaxFusedChains)
+            return fail(ctx, MMGAP_EUNSUPPORTED, "job %d: chains=%d > %d in a batch", j,
+                        jb.sched.chains, kMaxFusedChains);
+        if (sh.n_inst > 0 && (!jb.H || !jb.y_or_u || !jb.out0))
+            return fail(ctx, MMGAP_EINVAL, "job %d: H, y_or_u and out0 are required", j);
+        const int cls = mmgap::fused_class(sh.KT, sh.q);
+        if (cls < 0) return fail(ctx, MMGAP_EUNSUPPORTED, "job %d: no fused variant", j);
+        const mmgap_problem &p = jb.prob;
+        mmgap::FusedJob &f = fj[j];
+        f.kind = p.kind;
+        f.cls = cls;
+        f.KT = sh.KT;
+        f.Q = sh.q;
+        f.K = sh.K;
+        f.n_rows = p.n_rx;
+        f.n_cols = p.n_tx;
+        f.n_sym = p.n_sym;
+        f.n_sc = p.n_sc;
+        f.chains = jb.sched.chains;
+        f.sweeps = jb.sched.sweeps;
+        f.init = jb.sched.init;
+        f.wpi = jb.sched.chains <= 64 ? 1 : (jb.sched.chains <= 128 ? 2 : 4);
+        f.ldf = (sh.KT + 31) / 32 * 32;   // 128-byte field rows: no scalar-cache line is shared
+
+        if (p.kind == MMGAP_KIND_DET) det_weights(sh.q, f.w);
+        else vpp_weights(f.w);
+        f.key0 = (uint32_t)jb.sched.seed;
+        f.key1 = (uint32_t)(jb.sched.seed >> 32);
+        f.c = qam_c(p.qam);
+        f.c2 = qam_c2(p.qam);
+        f.noise_var = (double)p.noise_var;
+        f.tau = p.kind == MMGAP_KIND_VPP ? vpp_tau(&p) : 0.0;
+        f.H = (const float2 *)jb.H;
+        f.y = (const float2 *)jb.y_or_u;
+        f.out0 = jb.out0;
+        f.out1 = jb.out1;
+        f.out2 = jb.out2;
+        const size_t ni = (size_t)sh.n_inst;
+        ob[j] = lay.take(sizeof(float) * (size_t)f.sweeps);
+        oG[j] = lay.take(sizeof(float) * (size_t)p.n_sc * sh.KT * sh.KT);
+        of[j] = lay.take(sizeof(float) * ni * f.ldf);
+        ox[j] = lay.take(ni * (size_t)sh.KT);
+        oA[j] = p.kind == MMGAP_KIND_VPP ? lay.take(sizeof(double2) * (size_t)p.n_sc * p.n_rx * p.n_rx)
+                                         : 0;
+        const int per = 4 / f.wpi;
+        for (int sc = 0; sc < p.n_sc; ++sc)
+            for (int s0 = 0; s0 < p.n_sym; s0 += per)
+                items.push_back({j, sc, s0, std::min(per, p.n_sym - s0)});
+    }
+    std::stable_sort(items.begin(), items.end(),
+                     [&](const mmgap::FusedItem &a, const mmgap::FusedItem &b) {
+                         return item_cost(fj[a.job]) > item_cost(fj[b.job]);
+                     });
+    const size_t o_items = lay.take(sizeof(mmgap::FusedItem) * std::max<size_t>(items.size(), 1));
+    const size_t o_counter = lay.take(sizeof(unsigned int));
+    if (items.size() > 0x7FFFFFFFu) return fail(ctx, MMGAP_EUNSUPPORTED, "too many work items");
+    if (lay.off + ctx->plan_bytes + ctx->scratch_bytes > ctx->budget)
+        return fail(ctx, MMGAP_ENOMEM,
+                    "plan of %zu bytes exceeds the HBM budget of %zu bytes (%zu in use)", lay.off,
+                    ctx->budget, ctx->plan_bytes + ctx->scratch_bytes);
+
+    DeviceGuard g(ctx->device);
+    int per_cu = 0, cus = 0;
+    hipError_t e = mmgap::fused_blocks_per_cu(&per_cu);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
+    if (e != hipSuccess) return hip_fail(ctx, e, "occupancy query");
+    if (per_cu < 1) return fail(ctx, MMGAP_EDEVICE, "the fused kernel does not fit a compute unit");
+    int grid = blocks > 0 ? blocks : per_cu * cus;
+    if ((size_t)grid > items.size()) grid = (int)std::max<size_t>(items.size(), 1);
+
+    mmgap_plan *plan = new (std::nothrow) mmgap_plan();
+    if (!plan) return fail(ctx, MMGAP_ENOMEM, "out of host memory");
+    plan->ctx = ctx;
+    plan->n_items = (int)items.size();
+    plan->blocks = grid;
+    e = hipMalloc(&plan->mem, lay.off);
+    if (e != hipSuccess) {
+        plan->mem = nullptr;
+        plan_free(plan);
+        return fail(ctx, MMGAP_ENOMEM, "hipMalloc(%zu): %s", lay.off, hipGetErrorString(e));
+    }
+    plan->bytes = lay.off;
+    ctx->plan_bytes += lay.off;
+    char *base = static_cast<char *>(plan->mem);
+    plan->jobs_dev = reinterpret_cast<mmgap::FusedJob *>(base + o_jobs);
+    plan->items_dev = reinterpret_cast<mmgap::FusedItem *>(base + o_items);
+    plan->counter = reinterpret_cast<unsigned int *>(base + o_counter);
+    for (int j = 0; j < n_jobs; ++j) {
+        mmgap::FusedJob &f = fj[j];
+        f.beta2 = reinterpret_cast<const float *>(base + ob[j]);
+        f.G = reinterpret_cast<float *>(base + oG[j]);
+        f.f = reinterpret_cast<float *>(base + of[j]);
+        f.x_fb = reinterpret_cast<signed char *>(base + ox[j]);
+        f.Ainv = f.kind == MMGAP_KIND_VPP ? reinterpret_cast<double2 *>(base + oA[j]) : nullptr;
+        e = hipMemcpy(base + ob[j], jobs[j].sched.beta2, sizeof(float) * (size_t)f.sweeps,
+                      hipMemcpyHostToDevice);
+        if (e != hipSuccess) break;
+    }
+    if (e == hipSuccess && n_jobs > 0)
+        e = hipMemcpy(plan->jobs_dev, fj.data(), sizeof(mmgap::FusedJob) * (size_t)n_jobs,
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess && !items.empty())
+        e = hipMemcpy(plan->items_dev, items.data(), sizeof(mmgap::FusedItem) * items.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&plan->done, hipEventDisableTiming);
+    if (e == hipSuccess && (flags & MMGAP_PLAN_GRAPH)) {
+        hipStream_t cs = nullptr;
+        e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e == hipSuccess) {
+            e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                const hipError_t el = mmgap::launch_fused(plan->jobs_dev, plan->items_dev,
+                                                          plan->n_items, plan->counter,
+                                                          ctx->accept_dev, plan->blocks, cs);
+                e = hipStreamEndCapture(cs, &plan->graph);
+                if (e == hipSuccess) e = el;
+            }
+            (void)hipStreamDestroy(cs);
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
+    }
+    if (e != hipSuccess) {
+        plan_free(plan);
+        return hip_fail(ctx, e, "plan setup");
+    }
+    *out = plan;
+    return MMGAP_OK;
+}
+
+int mmgap_plan_launch(mmgap_plan *plan, void *stream)
+{
+    if (!plan) return MMGAP_EINVAL;
+    mmgap_ctx *ctx = plan->ctx;
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (plan->done_valid) e = hipStreamWaitEvent(st, plan->done, 0);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamWaitEvent");
+    if (plan->exec) e = hipGraphLaunch(plan->exec, st);
+    else
+        e = mmgap::launch_fused(plan->jobs_dev, plan->items_dev, plan->n_items, plan->counter,
+                                ctx->accept_dev, plan->blocks, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "fused launch");
+    e = hipEventRecord(plan->done, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipEventRecord");
+    plan->done_valid = true;
+    return MMGAP_OK;
+}
+
+int mmgap_plan_info(const mmgap_plan *plan, int *n_items, int *blocks)
+{
+    if (!plan) return MMGAP_EINVAL;
+    if (n_items) *n_items = plan->n_items;
+    if (blocks) *blocks = plan->blocks;
+    return MMGAP_OK;
+}
+
+int mmgap_plan_destroy(mmgap_plan *plan)
+{
+    if (!plan) return MMGAP_OK;
+    DeviceGuard g(plan->ctx->device);
+    plan_free(plan);
+    return MMGAP_OK;
 }
 
 }  // extern "C"

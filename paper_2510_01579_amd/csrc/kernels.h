@@ -103,6 +103,38 @@ struct ExpandArgs {
     float *e_const;         // [n_inst] or null
 };
 
+// One job of the fused persistent kernel (device copy, read wave-uniformly).
+struct FusedJob {
+    int kind;               // 0 detection, 1 VPP
+    int cls;                // anneal variant: fused_class(KT, Q)
+    int KT, Q, K;
+    int n_rows, n_cols;     // H is n_rows x n_cols (DET: n_r x n_t; VPP: n_u x n_tx)
+    int n_sym, n_sc;
+    int chains, sweeps, init, wpi;
+    int ldf;                // row stride of f in floats: a multiple of 32 (128 bytes), >= KT
+    int w[kMaxQ];
+    uint32_t key0, key1;
+    double c, c2, noise_var, tau;
+    const float2 *H;
+    const float2 *y;        // y (DET) or u (VPP)
+    const float *beta2;     // [sweeps] device
+    float *G;               // [n_sc][KT][KT] scratch
+    float *f;               // [n_sc*n_sym][ldf] scratch
+    signed char *x_fb;      // [n_sc*n_sym][KT] scratch
+    double2 *Ainv;          // [n_sc][n_u][n_u] scratch (VPP)
+    void *out0, *out1, *out2;   // DET: sym, metric; VPP: v, x, gamma
+};
+// A work item: symbols sym0..sym0+ns-1 of subcarrier sc of job `job`.
+struct FusedItem {
+    int job, sc, sym0, ns;
+};
+
+int fused_class(int KT, int q);   // -1 if the fused kernel has no variant for it
+hipError_t launch_fused(const FusedJob *jobs, const FusedItem *items, int n_items,
+                        unsigned int *counter, const uint32_t *accept_table, int blocks,
+                        hipStream_t s);
+hipError_t fused_blocks_per_cu(int *blocks);
+
 hipError_t launch_det_build(const DetBuildArgs &a, hipStream_t s);
 hipError_t launch_vpp_build(const VppBuildArgs &a, hipStream_t s);
 hipError_t launch_anneal(int KT, int q, const AnnealArgs &a, hipStream_t s);

@@ -1,13 +1,17 @@
 // Device code of the Ising hot path (gfx950 / CDNA4, wave64).
 //
-//  * k_det_build / k_vpp_build -- pre-processing: the Ising couplings G and
-//    fields f of every instance (paper §3.2 pre-processing kernel; §3.3 for the
+// Shared device functions (used by both launch paths, so that both compute
+// the same values):
+//  * build_det_sc / build_vpp_sc -- pre-processing of one subcarrier: the Ising
+//    couplings G and fields f (paper §3.2 pre-processing kernel; §3.3 for the
 //    vector-perturbation rewriting) and the linear fallback (§2.1 MMSE).
-//  * k_anneal<KT,Q>            -- the solver: one single-spin-flip Metropolis
-//    anneal per lane, 64 anneals of one instance per wavefront (paper §3.2:
-//    one anneal per thread, no synchronisation between anneals).
-//  * k_select                  -- post-processing: best anneal per instance,
-//    fallback rule, decode and float64 metrics (paper §3.2 post-processing).
+//  * anneal_lane<KT,Q> -- one single-spin-flip Metropolis anneal per lane
+//    (paper §3.2: one anneal per thread, no synchronisation between anneals).
+//  * fallback_energy, winning_levels, decode_det / decode_vpp -- post-processing:
+//    best anneal, fallback rule, decode and float64 metrics (§3.2).
+// Plain path: k_det_build / k_vpp_build -> k_anneal -> k_select, one launch per
+// stage and problem size.  Fused path: k_fused, one persistent launch over a
+// device work queue of (job, subcarrier, symbols) items of mixed sizes.
 //
 // Floating point: float32 chain state with round-to-nearest and no implicit
 // contraction (this file is compiled with -ffp-contract=off and the pragma
@@ -84,334 +88,6 @@ __device__ __forceinline__ void upper_pair(int p, int n, int &i, int &j)
     j = row + rem;
 }
 
-// ---------------------------------------------------------------------------
-// Detection build: one workgroup per subcarrier.
-//   Cg = H^H H (float64, upper triangle, mirrored)      -> G (real form, x c^2)
-//   F  = H^H y per symbol                               -> f (real form, x c)
-//   MMSE (Cg + sigma^2 I)^-1 F by LDL^H, sliced to the nearest PAM level.
-__global__ void __launch_bounds__(kBlock) k_det_build(DetBuildArgs a)
-{
-    __shared__ float2 Hs[64 * 16];
-    __shared__ double2 Cg[16 * 16];
-    __shared__ double2 Fs[64 * 16];
-    __shared__ double2 Ls[16 * 16];
-    __shared__ double ds[16];
-
-    const int sc = blockIdx.x;
-    const int tid = threadIdx.x;
-    const int nr = a.n_r, nt = a.n_t, K = 2 * nt, ld = a.ld, nsym = a.n_sym;
-
-    const float2 *Hg = a.H + (size_t)sc * nr * nt;
-    for (int e = tid; e < nr * nt; e += kBlock) Hs[e] = Hg[e];
-    __syncthreads();
-
-    float *Gs = a.G + (size_t)sc * ld * ld;
-    // padding rows / columns of G
-    for (int e = tid; e < ld * ld; e += kBlock) {
-        const int r = e / ld, c = e % ld;
-        if (r >= K || c >= K) Gs[e] = 0.0f;
-    }
-    const int npair = nt * (nt + 1) / 2;
-    for (int p = tid; p < npair; p += kBlock) {
-        int ia, ib;
-        upper_pair(p, nt, ia, ib);
-        double re = 0.0, im = 0.0;
-        for (int r = 0; r < nr; ++r) {
-            const float2 h1 = Hs[r * nt + ia], h2 = Hs[r * nt + ib];
-            const double ar = h1.x, ai = h1.y, br = h2.x, bi = h2.y;
-            const double pre = ar * br + ai * bi;   // conj(h1) h2
-            const double pim = ar * bi - ai * br;
-            re = re + pre;
-            im = im + pim;
-        }
-        if (ia == ib) im = 0.0;
-        Cg[ia * 16 + ib] = make_double2(re, im);
-        Cg[ib * 16 + ia] = make_double2(re, 0.0 - im);
-        const float gre = (float)(a.c2 * re);
-        const float gim = (float)(a.c2 * im);
-        const float ngim = (float)(a.c2 * (0.0 - im));
-        Gs[ia * ld + ib] = gre;
-        Gs[ib * ld + ia] = gre;
-        Gs[(nt + ia) * ld + (nt + ib)] = gre;
-        Gs[(nt + ib) * ld + (nt + ia)] = gre;
-        // upper-right block -Im Cg, lower-left block Im Cg
-        Gs[ia * ld + (nt + ib)] = ngim;
-        Gs[(nt + ib) * ld + ia] = ngim;
-        Gs[(nt + ia) * ld + ib] = gim;
-        Gs[ib * ld + (nt + ia)] = gim;
-    }
-
-    // fields
-    for (int p = tid; p < nsym * nt; p += kBlock) {
-        const int sym = p / nt, ia = p % nt;
-        const float2 *ys = a.y + ((size_t)sc * nsym + sym) * nr;
-        double re = 0.0, im = 0.0;
-        for (int r = 0; r < nr; ++r) {
-            const float2 h = Hs[r * nt + ia];
-            const float2 yv = ys[r];
-            const double pre = (double)h.x * (double)yv.x + (double)h.y * (double)yv.y;
-            const double pim = (double)h.x * (double)yv.y - (double)h.y * (double)yv.x;
-            re = re + pre;
-            im = im + pim;
-        }
-        Fs[sym * 16 + ia] = make_double2(re, im);
-        float *fs = a.f + ((size_t)sc * nsym + sym) * ld;
-        fs[ia] = (float)(a.c * re);
-        fs[nt + ia] = (float)(a.c * im);
-    }
-    for (int p = tid; p < nsym * (ld - K); p += kBlock) {
-        const int sym = p / (ld - K), k = K + p % (ld - K);
-        a.f[((size_t)sc * nsym + sym) * ld + k] = 0.0f;
-    }
-    if (a.ynorm) {
-        for (int sym = tid; sym < nsym; sym += kBlock) {
-            const float2 *ys = a.y + ((size_t)sc * nsym + sym) * nr;
-            double acc = 0.0;
-            for (int r = 0; r < nr; ++r) {
-                const double yr = ys[r].x, yi = ys[r].y;
-                acc = acc + (yr * yr + yi * yi);
-            }
-            a.ynorm[(size_t)sc * nsym + sym] = acc;
-        }
-    }
-    if (!a.x_fb) return;   // uniform over the block
-    __syncthreads();
-
-    // LDL^H of Cg + sigma^2 I
-    for (int j = 0; j < nt; ++j) {
-        if (tid == 0) {
-            double dj = Cg[j * 16 + j].x + a.noise_var;
-            for (int k = 0; k < j; ++k) {
-                const double2 v = Ls[j * 16 + k];
-                double t = v.x * v.x + v.y * v.y;
-                t = t * ds[k];
-                dj = dj - t;
-            }
-            ds[j] = dj;
-        }
-        __syncthreads();
-        for (int i = j + 1 + tid; i < nt; i += kBlock) {
-            cd s = ld2(Cg[i * 16 + j]);
-            for (int k = 0; k < j; ++k) {
-                cd v = cmulc(ld2(Ls[j * 16 + k]), ld2(Ls[i * 16 + k]));
-                v.re = v.re * ds[k];
-                v.im = v.im * ds[k];
-                s.re = s.re - v.re;
-                s.im = s.im - v.im;
-            }
-            Ls[i * 16 + j] = make_double2(s.re / ds[j], s.im / ds[j]);
-        }
-        __syncthreads();
-    }
-    // per-symbol solves in place on Fs, then slicing
-    for (int sym = tid; sym < nsym; sym += kBlock) {
-        double2 *w = Fs + sym * 16;
-        for (int i = 0; i < nt; ++i) {
-            cd s = ld2(w[i]);
-            for (int k = 0; k < i; ++k) {
-                const cd v = cmul(ld2(Ls[i * 16 + k]), ld2(w[k]));
-                s.re = s.re - v.re;
-                s.im = s.im - v.im;
-            }
-            w[i] = st2(s);
-        }
-        for (int i = 0; i < nt; ++i) w[i] = make_double2(w[i].x / ds[i], w[i].y / ds[i]);
-        for (int i = nt - 1; i >= 0; --i) {
-            cd s = ld2(w[i]);
-            for (int k = i + 1; k < nt; ++k) {
-                const cd v = cmulc(ld2(Ls[k * 16 + i]), ld2(w[k]));
-                s.re = s.re - v.re;
-                s.im = s.im - v.im;
-            }
-            w[i] = st2(s);
-        }
-        signed char *xo = a.x_fb + ((size_t)sc * nsym + sym) * ld;
-        for (int i = 0; i < nt; ++i) {
-            const double tr = w[i].x / a.c, ti = w[i].y / a.c;
-            double lr = 2.0 * floor(tr / 2.0) + 1.0;
-            double li = 2.0 * floor(ti / 2.0) + 1.0;
-            lr = fmin(fmax(lr, (double)-a.qtop), (double)a.qtop);
-            li = fmin(fmax(li, (double)-a.qtop), (double)a.qtop);
-            if (lr != lr) lr = 1.0;   // NaN input: any valid level
-            if (li != li) li = 1.0;
-            xo[i] = (signed char)(int)lr;
-            xo[nt + i] = (signed char)(int)li;
-        }
-        for (int k = K; k < ld; ++k) xo[k] = 0;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// VPP build: one workgroup per subcarrier.  A = H H^H, its LDL^H, M = L^-1 and
-// A^-1 = M^H D^-1 M in a fixed operation order (so that any implementation of
-// the same sequence agrees bit for bit), then
-//   G = (tau/2)^2 Re-form(A^-1),  f = -(tau/2) Re-form(A^-1 u).
-__global__ void __launch_bounds__(kBlock) k_vpp_build(VppBuildArgs a)
-{
-    __shared__ float2 Hs[16 * 64];
-    __shared__ double2 As[16 * 16];
-    __shared__ double2 Ls[16 * 16];
-    __shared__ double2 Ms[16 * 16];
-    __shared__ double2 Zs[16 * 16];   // A^-1
-    __shared__ double ds[16];
-
-    const int sc = blockIdx.x;
-    const int tid = threadIdx.x;
-    const int n = a.n_u, ntx = a.n_t, K = 2 * n, ld = a.ld, nsym = a.n_sym;
-    const double ht = 0.5 * a.tau;
-    const double sg = ht * ht;
-    const double sf = -ht;
-
-    const float2 *Hg = a.H + (size_t)sc * n * ntx;
-    for (int e = tid; e < n * ntx; e += kBlock) Hs[e] = Hg[e];
-    __syncthreads();
-
-    // A_il = sum_j H_ij conj(H_lj), i >= l
-    const int npair = n * (n + 1) / 2;
-    for (int p = tid; p < npair; p += kBlock) {
-        int l, i;
-        upper_pair(p, n, l, i);   // l <= i
-        double re = 0.0, im = 0.0;
-        for (int j = 0; j < ntx; ++j) {
-            const double ar = Hs[i * ntx + j].x, ai = Hs[i * ntx + j].y;
-            const double cr = Hs[l * ntx + j].x, ci = Hs[l * ntx + j].y;
-            const double pre = ar * cr + ai * ci;
-            const double pim = ai * cr - ar * ci;
-            re = re + pre;
-            im = im + pim;
-        }
-        As[i * 16 + l] = make_double2(re, im);
-        As[l * 16 + i] = make_double2(re, -im);
-    }
-    __syncthreads();
-
-    for (int j = 0; j < n; ++j) {
-        if (tid == 0) {
-            double dj = As[j * 16 + j].x;
-            for (int k = 0; k < j; ++k) {
-                const double2 v = Ls[j * 16 + k];
-                double t = v.x * v.x + v.y * v.y;
-                t = t * ds[k];
-                dj = dj - t;
-            }
-            ds[j] = dj;
-        }
-        __syncthreads();
-        for (int i = j + 1 + tid; i < n; i += kBlock) {
-            cd s = ld2(As[i * 16 + j]);
-            for (int k = 0; k < j; ++k) {
-                cd v = cmulc(ld2(Ls[j * 16 + k]), ld2(Ls[i * 16 + k]));
-                v.re = v.re * ds[k];
-                v.im = v.im * ds[k];
-                s.re = s.re - v.re;
-                s.im = s.im - v.im;
-            }
-            Ls[i * 16 + j] = make_double2(s.re / ds[j], s.im / ds[j]);
-        }
-        __syncthreads();
-    }
-    // M = L^-1, one column per thread
-    for (int m = tid; m < n; m += kBlock) {
-        Ms[m * 16 + m] = make_double2(1.0, 0.0);
-        for (int i = m + 1; i < n; ++i) {
-            cd s{0.0, 0.0};
-            for (int k = m; k < i; ++k) {
-                const cd v = cmul(ld2(Ls[i * 16 + k]), ld2(Ms[k * 16 + m]));
-                s.re = s.re + v.re;
-                s.im = s.im + v.im;
-            }
-            Ms[i * 16 + m] = make_double2(-s.re, -s.im);
-        }
-    }
-    __syncthreads();
-    // A^-1_il = sum_{k>=i} conj(M_ki) M_kl / d_k, i >= l
-    for (int p = tid; p < npair; p += kBlock) {
-        int l, i;
-        upper_pair(p, n, l, i);
-        cd acc{0.0, 0.0};
-        for (int k = i; k < n; ++k) {
-            cd v = cmulc(ld2(Ms[k * 16 + i]), ld2(Ms[k * 16 + l]));
-            v.re = v.re / ds[k];
-            v.im = v.im / ds[k];
-            acc.re = acc.re + v.re;
-            acc.im = acc.im + v.im;
-        }
-        Zs[i * 16 + l] = st2(acc);
-        if (i != l) Zs[l * 16 + i] = make_double2(acc.re, -acc.im);
-        else Zs[i * 16 + i] = make_double2(acc.re, -acc.im);
-    }
-    __syncthreads();
-
-    if (a.Ainv) {
-        double2 *Ag = a.Ainv + (size_t)sc * n * n;
-        for (int e = tid; e < n * n; e += kBlock) Ag[e] = Zs[(e / n) * 16 + (e % n)];
-    }
-    float *Gs = a.G + (size_t)sc * ld * ld;
-    for (int e = tid; e < ld * ld; e += kBlock) {
-        const int r = e / ld, c = e % ld;
-        float v = 0.0f;
-        if (r < K && c < K) {
-            const int i = r % n, l = c % n;
-            const double2 z = Zs[i * 16 + l];
-            if ((r < n) == (c < n)) v = (float)(sg * z.x);
-            else if (r < n) v = (float)(sg * (-z.y));   // upper-right: -Im
-            else v = (float)(sg * z.y);                 // lower-left: Im
-        }
-        Gs[e] = v;
-    }
-    for (int p = tid; p < nsym * n; p += kBlock) {
-        const int sym = p / n, i = p % n;
-        const float2 *us = a.u + ((size_t)sc * nsym + sym) * n;
-        cd z{0.0, 0.0};
-        for (int l = 0; l < n; ++l) {
-            const cd ul{(double)us[l].x, (double)us[l].y};
-            const cd v = cmul(ld2(Zs[i * 16 + l]), ul);
-            z.re = z.re + v.re;
-            z.im = z.im + v.im;
-        }
-        float *fs = a.f + ((size_t)sc * nsym + sym) * ld;
-        fs[i] = (float)(sf * z.re);
-        fs[n + i] = (float)(sf * z.im);
-    }
-    for (int p = tid; p < nsym * (ld - K); p += kBlock) {
-        const int sym = p / (ld - K), k = K + p % (ld - K);
-        a.f[((size_t)sc * nsym + sym) * ld + k] = 0.0f;
-    }
-    if (a.x_fb) {
-        for (int p = tid; p < nsym * ld; p += kBlock) a.x_fb[(size_t)sc * nsym * ld + p] = 0;
-    }
-    if (a.unorm) {
-        for (int sym = tid; sym < nsym; sym += kBlock) {
-            const float2 *us = a.u + ((size_t)sc * nsym + sym) * n;
-            double acc = 0.0;
-            for (int i = 0; i < n; ++i) {
-                cd z{0.0, 0.0};
-                for (int l = 0; l < n; ++l) {
-                    const cd v = cmul(ld2(Zs[i * 16 + l]), cd{(double)us[l].x, (double)us[l].y});
-                    z.re = z.re + v.re;
-                    z.im = z.im + v.im;
-                }
-                acc = acc + ((double)us[i].x * z.re + (double)us[i].y * z.im);
-            }
-            a.unorm[(size_t)sc * nsym + sym] = acc;
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// The anneal.  One wavefront = 64 anneals (chains) of one instance; chains
-// >= 64 use several wavefronts.  G and f of the instance are wave-uniform and
-// read through the scalar cache one row ahead of use.  Per lane the state is
-// the flip step of every spin, d_i = -2 w_b s_i (+-2w_b as float), and the
-// levels x[KT]; the local field of a dimension is recomputed from the levels
-// when the sweep reaches it (one row of G x - f) and moved by G_kk d after an
-// accepted flip inside the dimension.
-//
-// Per attempt on spin i = k Q + b with h = g_k + (d/2) G_kk:
-//   2h = (g_k + g_k) + d G_kk exactly, and 64 beta2 dE = (128 beta2 d) h,
-//   the Metropolis threshold index is floor(64 beta2 dE) clamped to [0, 1024],
-//   and the flip is accepted iff the 16-bit draw m < T[index] (T in LDS).
-
 // Hides a pointer's value from the optimiser so that loads through it are
 // issued where written (here: one dimension ahead) instead of being hoisted
 // out of the sweep loop into registers.  The result lives in the constant
@@ -431,45 +107,370 @@ __device__ __forceinline__ uint32_t opaque_u32(uint32_t v)
     return v;
 }
 
+// Orders LDS writes of some lanes before LDS reads of other lanes of the same
+// wavefront.
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---------------------------------------------------------------------------
+// Detection build of one subcarrier (all threads of the block):
+//   Cg = H^H H (float64, upper triangle, mirrored)      -> G (real form, x c^2)
+//   F  = H^H y per symbol                               -> f (real form, x c)
+//   MMSE (Cg + sigma^2 I)^-1 F by LDL^H, sliced to the nearest PAM level.
+// Writes G (ld x ld, zero padded) to Gout and, for symbols sym0..sym0+ns-1,
+// the field rows to fout, the fallback levels to xout (if non-null) and ||y||^2
+// to ynorm (if non-null).  ns <= 64.
+struct DetShared {
+    float2 Hs[64 * 16];
+    double2 Cg[16 * 16];
+    double2 Fs[64 * 16];
+    double2 Ls[16 * 16];
+    double ds[16];
+};
+
+__device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, int nsym, int sc,
+                             int sym0, int ns, int ld, int ldf, int qtop, double c, double c2,
+                             double noise_var, float *Gout, float *fout, signed char *xout,
+                             double *ynorm, DetShared &sh)
+{
+    const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
+    const int K = 2 * nt;
+
+    const float2 *Hg = H + (size_t)sc * nr * nt;
+    for (int e = tid; e < nr * nt; e += nthr) sh.Hs[e] = Hg[e];
+    __syncthreads();
+
+    for (int e = tid; e < ld * ld; e += nthr) {
+        const int r = e / ld, cc = e % ld;
+        if (r >= K || cc >= K) Gout[e] = 0.0f;
+    }
+    const int npair = nt * (nt + 1) / 2;
+    for (int p = tid; p < npair; p += nthr) {
+        int ia, ib;
+        upper_pair(p, nt, ia, ib);
+        double re = 0.0, im = 0.0;
+        for (int r = 0; r < nr; ++r) {
+            const float2 h1 = sh.Hs[r * nt + ia], h2 = sh.Hs[r * nt + ib];
+            const double ar = h1.x, ai = h1.y, br = h2.x, bi = h2.y;
+            const double pre = ar * br + ai * bi;   // conj(h1) h2
+            const double pim = ar * bi - ai * br;
+            re = re + pre;
+            im = im + pim;
+        }
+        if (ia == ib) im = 0.0;
+        sh.Cg[ia * 16 + ib] = make_double2(re, im);
+        sh.Cg[ib * 16 + ia] = make_double2(re, 0.0 - im);
+        const float gre = (float)(c2 * re);
+        const float gim = (float)(c2 * im);
+        const float ngim = (float)(c2 * (0.0 - im));
+        Gout[ia * ld + ib] = gre;
+        Gout[ib * ld + ia] = gre;
+        Gout[(nt + ia) * ld + (nt + ib)] = gre;
+        Gout[(nt + ib) * ld + (nt + ia)] = gre;
+        // upper-right block -Im Cg, lower-left block Im Cg
+        Gout[ia * ld + (nt + ib)] = ngim;
+        Gout[(nt + ib) * ld + ia] = ngim;
+        Gout[(nt + ia) * ld + ib] = gim;
+        Gout[ib * ld + (nt + ia)] = gim;
+    }
+
+    for (int p = tid; p < ns * nt; p += nthr) {
+        const int r0 = p / nt, ia = p % nt;
+        const float2 *ys = y + ((size_t)sc * nsym + sym0 + r0) * nr;
+        double re = 0.0, im = 0.0;
+        for (int r = 0; r < nr; ++r) {
+            const float2 h = sh.Hs[r * nt + ia];
+            const float2 yv = ys[r];
+            const double pre = (double)h.x * (double)yv.x + (double)h.y * (double)yv.y;
+            const double pim = (double)h.x * (double)yv.y - (double)h.y * (double)yv.x;
+            re = re + pre;
+            im = im + pim;
+        }
+        sh.Fs[r0 * 16 + ia] = make_double2(re, im);
+        float *fs = fout + (size_t)r0 * ldf;
+        fs[ia] = (float)(c * re);
+        fs[nt + ia] = (float)(c * im);
+    }
+    for (int p = tid; p < ns * (ld - K); p += nthr) {
+        const int r0 = p / (ld - K), k = K + p % (ld - K);
+        fout[(size_t)r0 * ldf + k] = 0.0f;
+    }
+    if (ynorm) {
+        for (int r0 = tid; r0 < ns; r0 += nthr) {
+            const float2 *ys = y + ((size_t)sc * nsym + sym0 + r0) * nr;
+            double acc = 0.0;
+            for (int r = 0; r < nr; ++r) {
+                const double yr = ys[r].x, yi = ys[r].y;
+                acc = acc + (yr * yr + yi * yi);
+            }
+            ynorm[r0] = acc;
+        }
+    }
+    if (!xout) return;   // uniform over the block
+    __syncthreads();
+
+    // LDL^H of Cg + sigma^2 I
+    for (int j = 0; j < nt; ++j) {
+        if (tid == 0) {
+            double dj = sh.Cg[j * 16 + j].x + noise_var;
+            for (int k = 0; k < j; ++k) {
+                const double2 v = sh.Ls[j * 16 + k];
+                double t = v.x * v.x + v.y * v.y;
+                t = t * sh.ds[k];
+                dj = dj - t;
+            }
+            sh.ds[j] = dj;
+        }
+        __syncthreads();
+        for (int i = j + 1 + tid; i < nt; i += nthr) {
+            cd s = ld2(sh.Cg[i * 16 + j]);
+            for (int k = 0; k < j; ++k) {
+                cd v = cmulc(ld2(sh.Ls[j * 16 + k]), ld2(sh.Ls[i * 16 + k]));
+                v.re = v.re * sh.ds[k];
+                v.im = v.im * sh.ds[k];
+                s.re = s.re - v.re;
+                s.im = s.im - v.im;
+            }
+            sh.Ls[i * 16 + j] = make_double2(s.re / sh.ds[j], s.im / sh.ds[j]);
+        }
+        __syncthreads();
+    }
+    // per-symbol solves in place on Fs, then slicing
+    for (int r0 = tid; r0 < ns; r0 += nthr) {
+        double2 *w = sh.Fs + r0 * 16;
+        for (int i = 0; i < nt; ++i) {
+            cd s = ld2(w[i]);
+            for (int k = 0; k < i; ++k) {
+                const cd v = cmul(ld2(sh.Ls[i * 16 + k]), ld2(w[k]));
+                s.re = s.re - v.re;
+                s.im = s.im - v.im;
+            }
+            w[i] = st2(s);
+        }
+        for (int i = 0; i < nt; ++i) w[i] = make_double2(w[i].x / sh.ds[i], w[i].y / sh.ds[i]);
+        for (int i = nt - 1; i >= 0; --i) {
+            cd s = ld2(w[i]);
+            for (int k = i + 1; k < nt; ++k) {
+                const cd v = cmulc(ld2(sh.Ls[k * 16 + i]), ld2(w[k]));
+                s.re = s.re - v.re;
+                s.im = s.im - v.im;
+            }
+            w[i] = st2(s);
+        }
+        signed char *xo = xout + (size_t)r0 * ld;
+        for (int i = 0; i < nt; ++i) {
+            const double tr = w[i].x / c, ti = w[i].y / c;
+            double lr = 2.0 * floor(tr / 2.0) + 1.0;
+            double li = 2.0 * floor(ti / 2.0) + 1.0;
+            lr = fmin(fmax(lr, (double)-qtop), (double)qtop);
+            li = fmin(fmax(li, (double)-qtop), (double)qtop);
+            if (lr != lr) lr = 1.0;   // NaN input: any valid level
+            if (li != li) li = 1.0;
+            xo[i] = (signed char)(int)lr;
+            xo[nt + i] = (signed char)(int)li;
+        }
+        for (int k = K; k < ld; ++k) xo[k] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// VPP build of one subcarrier.  A = H H^H, its LDL^H, M = L^-1 and
+// A^-1 = M^H D^-1 M in a fixed operation order (so that any implementation of
+// the same sequence agrees bit for bit), then
+//   G = (tau/2)^2 Re-form(A^-1),  f = -(tau/2) Re-form(A^-1 u).
+struct VppShared {
+    float2 Hs[16 * 64];
+    double2 As[16 * 16];
+    double2 Ls[16 * 16];
+    double2 Ms[16 * 16];
+    double2 Zs[16 * 16];   // A^-1
+    double ds[16];
+};
+
+__device__ void build_vpp_sc(const float2 *H, const float2 *u, int n, int ntx, int nsym, int sc,
+                             int sym0, int ns, int ld, int ldf, double tau, float *Gout, float *fout,
+                             signed char *xout, double2 *Ainv_out, double *unorm, VppShared &sh)
+{
+    const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
+    const int K = 2 * n;
+    const double ht = 0.5 * tau;
+    const double sg = ht * ht;
+    const double sf = -ht;
+
+    const float2 *Hg = H + (size_t)sc * n * ntx;
+    for (int e = tid; e < n * ntx; e += nthr) sh.Hs[e] = Hg[e];
+    __syncthreads();
+
+    // A_il = sum_j H_ij conj(H_lj), i >= l
+    const int npair = n * (n + 1) / 2;
+    for (int p = tid; p < npair; p += nthr) {
+        int l, i;
+        upper_pair(p, n, l, i);   // l <= i
+        double re = 0.0, im = 0.0;
+        for (int j = 0; j < ntx; ++j) {
+            const double ar = sh.Hs[i * ntx + j].x, ai = sh.Hs[i * ntx + j].y;
+            const double cr = sh.Hs[l * ntx + j].x, ci = sh.Hs[l * ntx + j].y;
+            const double pre = ar * cr + ai * ci;
+            const double pim = ai * cr - ar * ci;
+            re = re + pre;
+            im = im + pim;
+        }
+        sh.As[i * 16 + l] = make_double2(re, im);
+        sh.As[l * 16 + i] = make_double2(re, -im);
+    }
+    __syncthreads();
+
+    for (int j = 0; j < n; ++j) {
+        if (tid == 0) {
+            double dj = sh.As[j * 16 + j].x;
+            for (int k = 0; k < j; ++k) {
+                const double2 v = sh.Ls[j * 16 + k];
+                double t = v.x * v.x + v.y * v.y;
+                t = t * sh.ds[k];
+                dj = dj - t;
+            }
+            sh.ds[j] = dj;
+        }
+        __syncthreads();
+        for (int i = j + 1 + tid; i < n; i += nthr) {
+            cd s = ld2(sh.As[i * 16 + j]);
+            for (int k = 0; k < j; ++k) {
+                cd v = cmulc(ld2(sh.Ls[j * 16 + k]), ld2(sh.Ls[i * 16 + k]));
+                v.re = v.re * sh.ds[k];
+                v.im = v.im * sh.ds[k];
+                s.re = s.re - v.re;
+                s.im = s.im - v.im;
+            }
+            sh.Ls[i * 16 + j] = make_double2(s.re / sh.ds[j], s.im / sh.ds[j]);
+        }
+        __syncthreads();
+    }
+    // M = L^-1, one column per thread
+    for (int m = tid; m < n; m += nthr) {
+        sh.Ms[m * 16 + m] = make_double2(1.0, 0.0);
+        for (int i = m + 1; i < n; ++i) {
+            cd s{0.0, 0.0};
+            for (int k = m; k < i; ++k) {
+                const cd v = cmul(ld2(sh.Ls[i * 16 + k]), ld2(sh.Ms[k * 16 + m]));
+                s.re = s.re + v.re;
+                s.im = s.im + v.im;
+            }
+            sh.Ms[i * 16 + m] = make_double2(-s.re, -s.im);
+        }
+    }
+    __syncthreads();
+    // A^-1_il = sum_{k>=i} conj(M_ki) M_kl / d_k, i >= l
+    for (int p = tid; p < npair; p += nthr) {
+        int l, i;
+        upper_pair(p, n, l, i);
+        cd acc{0.0, 0.0};
+        for (int k = i; k < n; ++k) {
+            cd v = cmulc(ld2(sh.Ms[k * 16 + i]), ld2(sh.Ms[k * 16 + l]));
+            v.re = v.re / sh.ds[k];
+            v.im = v.im / sh.ds[k];
+            acc.re = acc.re + v.re;
+            acc.im = acc.im + v.im;
+        }
+        sh.Zs[i * 16 + l] = st2(acc);
+        if (i != l) sh.Zs[l * 16 + i] = make_double2(acc.re, -acc.im);
+        else sh.Zs[i * 16 + i] = make_double2(acc.re, -acc.im);
+    }
+    __syncthreads();
+
+    if (Ainv_out) {
+        for (int e = tid; e < n * n; e += nthr) Ainv_out[e] = sh.Zs[(e / n) * 16 + (e % n)];
+    }
+    for (int e = tid; e < ld * ld; e += nthr) {
+        const int r = e / ld, cc = e % ld;
+        float v = 0.0f;
+        if (r < K && cc < K) {
+            const int i = r % n, l = cc % n;
+            const double2 z = sh.Zs[i * 16 + l];
+            if ((r < n) == (cc < n)) v = (float)(sg * z.x);
+            else if (r < n) v = (float)(sg * (-z.y));   // upper-right: -Im
+            else v = (float)(sg * z.y);                 // lower-left: Im
+        }
+        Gout[e] = v;
+    }
+    for (int p = tid; p < ns * n; p += nthr) {
+        const int r0 = p / n, i = p % n;
+        const float2 *us = u + ((size_t)sc * nsym + sym0 + r0) * n;
+        cd z{0.0, 0.0};
+        for (int l = 0; l < n; ++l) {
+            const cd ul{(double)us[l].x, (double)us[l].y};
+            const cd v = cmul(ld2(sh.Zs[i * 16 + l]), ul);
+            z.re = z.re + v.re;
+            z.im = z.im + v.im;
+        }
+        float *fs = fout + (size_t)r0 * ldf;
+        fs[i] = (float)(sf * z.re);
+        fs[n + i] = (float)(sf * z.im);
+    }
+    for (int p = tid; p < ns * (ld - K); p += nthr) {
+        const int r0 = p / (ld - K), k = K + p % (ld - K);
+        fout[(size_t)r0 * ldf + k] = 0.0f;
+    }
+    if (xout) {
+        for (int p = tid; p < ns * ld; p += nthr) xout[p] = 0;
+    }
+    if (unorm) {
+        for (int r0 = tid; r0 < ns; r0 += nthr) {
+            const float2 *us = u + ((size_t)sc * nsym + sym0 + r0) * n;
+            double acc = 0.0;
+            for (int i = 0; i < n; ++i) {
+                cd z{0.0, 0.0};
+                for (int l = 0; l < n; ++l) {
+                    const cd v = cmul(ld2(sh.Zs[i * 16 + l]), cd{(double)us[l].x, (double)us[l].y});
+                    z.re = z.re + v.re;
+                    z.im = z.im + v.im;
+                }
+                acc = acc + ((double)us[i].x * z.re + (double)us[i].y * z.im);
+            }
+            unorm[r0] = acc;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The anneal of one lane.  G and f of the instance are wave-uniform and read
+// through the scalar cache one row ahead of use.  Per lane the state is the
+// flip step of every spin, d_i = -2 w_b s_i (+-2w_b as float) -- or one bit per
+// spin (set = spin -1) for large problems, to keep enough wavefronts resident --
+// and the levels x[KT]; the local field of a dimension is recomputed from the
+// levels when the sweep reaches it (one row of G x - f) and moved by G_kk d
+// after an accepted flip inside the dimension.
+//
+// Per attempt on spin i = k Q + b with h = g_k + (d/2) G_kk:
+//   2h = (g_k + g_k) + d G_kk exactly, and 64 beta2 dE = (128 beta2 d) h,
+//   the Metropolis threshold index is floor(64 beta2 dE) clamped to [0, 1024],
+//   and the flip is accepted iff the 16-bit draw m < T[index] (T in LDS).
+// Returns the final energy sum_k x_k (g_k - f_k); `bits` receives the final
+// spins (bit set = spin -1).
 template <int KT, int Q>
-__global__ void __launch_bounds__(kBlock)
-k_anneal(const float *__restrict__ G, int inst_per_G, const float *__restrict__ f,
-         const signed char *__restrict__ x_fb, const float *__restrict__ beta2,
-         const uint32_t *__restrict__ accept_table, int sweeps, int chains, int n_inst, int w0,
-         int w1, int w2, int w3, uint32_t key0, uint32_t key1, int init_mode,
-         float *__restrict__ chain_E, uint32_t *__restrict__ chain_S)
+__device__ __forceinline__ float anneal_lane(const float *Gi, const float *fi,
+                                             const signed char *xfb_i, const float *beta2,
+                                             const uint32_t *T, int sweeps, const int (&wts)[4],
+                                             uint32_t key0, uint32_t key1, int init_mode,
+                                             uint32_t uch, uint32_t uinst,
+                                             uint32_t (&bits)[(KT * Q + 31) / 32])
 {
     constexpr int N = KT * Q;
     constexpr int NW = (N + 31) / 32;
     constexpr int NG = (N + 7) / 8;
-    // Spin state: one float flip step per spin when few spins, else one bit per
-    // spin (set = spin -1) so that large problems keep enough wavefronts
-    // resident; both hold the same values.
     constexpr bool kBits = N > 48 || KT == 32;
     constexpr int ND = kBits ? 1 : N;
     constexpr int NB = kBits ? NW : 1;
-    __shared__ uint32_t T[kAcceptSteps + 1];
-    for (int e = threadIdx.x; e <= kAcceptSteps; e += kBlock) T[e] = accept_table[e];
-    __syncthreads();
 
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    const int wpi = (chains + 63) >> 6;
-    const int gw = blockIdx.x * kWavesPerBlock + wave;
-    const int inst = gw / wpi;
-    if (inst >= n_inst) return;
-    const int ch = (gw - inst * wpi) * 64 + lane;
-    const float *__restrict__ Gi = G + (size_t)(inst / inst_per_G) * (KT * KT);
-    const float *__restrict__ fi = f + (size_t)inst * KT;
-    const int wts[4] = {w0, w1, w2, w3};
     float two_w[Q];
 #pragma unroll
     for (int b = 0; b < Q; ++b) two_w[b] = (float)(2 * wts[b]);
 
-    const uint32_t uch = (uint32_t)ch;
-    const uint32_t uinst = (uint32_t)inst;
-
-    // flip steps d_i = -2 w_b s_i of the initial spins (or their sign bits)
     float dv[ND];
     uint32_t sb[NB];
 #pragma unroll
@@ -481,11 +482,10 @@ k_anneal(const float *__restrict__ G, int inst_per_G, const float *__restrict__ 
             dv[i] = negative ? two_w[i % Q] : -two_w[i % Q];
         }
     };
-    if (init_mode == 1 && x_fb != nullptr) {
-        const signed char *xi = x_fb + (size_t)inst * KT;
+    if (init_mode == 1 && xfb_i != nullptr) {
 #pragma unroll
         for (int k = 0; k < KT; ++k) {
-            int rem = xi[k];
+            int rem = xfb_i[k];
 #pragma unroll
             for (int b = 0; b < Q; ++b) {
                 const int sg = rem > 0 ? 1 : -1;
@@ -598,28 +598,25 @@ k_anneal(const float *__restrict__ G, int inst_per_G, const float *__restrict__ 
         const float diff = acc - fi[k];
         E = fmaf(x[k], diff, E);
     }
-    if (ch < chains) {
-        const size_t o = (size_t)inst * chains + ch;
-        chain_E[o] = E;
 #pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            uint32_t word = 0u;
-            if constexpr (kBits) {
-                word = sb[w];
-            } else {
+    for (int w = 0; w < NW; ++w) {
+        uint32_t word = 0u;
+        if constexpr (kBits) {
+            word = sb[w];
+        } else {
 #pragma unroll
-                for (int bit = 0; bit < 32; ++bit) {
-                    const int i = 32 * w + bit;
-                    if (i < N && dv[i] > 0.0f) word |= 1u << bit;   // d > 0 <=> spin -1
-                }
+            for (int bit = 0; bit < 32; ++bit) {
+                const int i = 32 * w + bit;
+                if (i < N && dv[i] > 0.0f) word |= 1u << bit;   // d > 0 <=> spin -1
             }
-            chain_S[o * NW + w] = word;
         }
+        bits[w] = word;
     }
+    return E;
 }
 
 // ---------------------------------------------------------------------------
-// Selection, fallback and decode.  One wavefront per instance.
+// Selection helpers.
 __device__ __forceinline__ uint32_t energy_key(float e)
 {
     if (e != e) return 0xFFFFFFFFu;            // NaN after everything
@@ -652,6 +649,178 @@ __device__ __forceinline__ double wave_sum_f64(double v)
     return v;
 }
 
+// Energy of the fallback levels with the chains' arithmetic (one wavefront;
+// `terms` is this wavefront's LDS scratch of 32 floats).
+__device__ float fallback_energy(const float *Gi, int KT, int K, const float *fi,
+                                 const signed char *xi, float *terms, int lane)
+{
+    if (lane < K) {
+        float acc = -fi[lane];
+        for (int l = 0; l < K; ++l) acc = fmaf(Gi[lane * KT + l], (float)xi[l], acc);
+        terms[lane] = acc - fi[lane];
+    }
+    wave_sync_lds();
+    float e = 0.0f;
+    for (int k = 0; k < K; ++k) e = fmaf((float)xi[k], terms[k], e);
+    wave_sync_lds();
+    return e;
+}
+
+// Levels of the winning candidate into lv[0..K): the fallback's, or those of
+// the spin words S (bit set = spin -1).
+__device__ void winning_levels(bool use_fb, const signed char *xi, const uint32_t *S, int K, int q,
+                               const int *w, int *lv, int lane)
+{
+    if (lane < K) {
+        int v;
+        if (use_fb) {
+            v = xi[lane];
+        } else {
+            v = 0;
+            for (int b = 0; b < q; ++b) {
+                const int i = lane * q + b;
+                v += ((S[i >> 5] >> (i & 31)) & 1u) ? -w[b] : w[b];
+            }
+        }
+        lv[lane] = v;
+    }
+    wave_sync_lds();
+}
+
+// Decode of the winning levels (lv: this wavefront's LDS copy of K levels).
+__device__ void decode_det(const int *lv, int n, int sc, int sy, int nsym, int nr, int nt, int q,
+                           double c, const float2 *H, const float2 *y, unsigned char *sym_out,
+                           float *metric_out, int lane)
+{
+    const int qtop = (1 << q) - 1;
+    if (lane < nt) {
+        const int pI = (lv[lane] + qtop) >> 1;
+        const int pQ = (lv[nt + lane] + qtop) >> 1;
+        const int gI = pI ^ (pI >> 1), gQ = pQ ^ (pQ >> 1);
+        sym_out[(size_t)n * nt + lane] = (unsigned char)((gI << q) | gQ);
+    }
+    if (metric_out) {
+        double part = 0.0;
+        for (int r = lane; r < nr; r += 64) {
+            const float2 *Hr = H + ((size_t)sc * nr + r) * nt;
+            const float2 yv = y[((size_t)sc * nsym + sy) * nr + r];
+            double re = yv.x, im = yv.y;
+            for (int t = 0; t < nt; ++t) {
+                const double xr = c * (double)lv[t];
+                const double xi = c * (double)lv[nt + t];
+                const double hr = Hr[t].x, hi = Hr[t].y;
+                re = re - (hr * xr - hi * xi);
+                im = im - (hr * xi + hi * xr);
+            }
+            part = part + (re * re + im * im);
+        }
+        const double tot = wave_sum_f64(part);
+        if (lane == 0) metric_out[n] = (float)tot;
+    }
+}
+
+// VPP: v = level / 2; x = H^H A^-1 (u + tau v); gamma = ||x||^2.
+// zsh: this wavefront's LDS scratch of 16 double2.
+__device__ void decode_vpp(const int *lv, int n, int sc, int sy, int nsym, int nu, int ntx,
+                           double tau, const double2 *Z, const float2 *H, const float2 *u,
+                           signed char *v_out, float2 *x_out, float *gamma_out, double2 *zsh,
+                           int lane)
+{
+    const int K = 2 * nu;
+    if (lane < K) v_out[(size_t)n * K + lane] = (signed char)(lv[lane] / 2);
+    if (!x_out && !gamma_out) return;
+    const float2 *us = u + ((size_t)sc * nsym + sy) * nu;
+    if (lane < nu) {
+        double zr = 0.0, zi = 0.0;
+        for (int l = 0; l < nu; ++l) {
+            const double pr = (double)us[l].x + tau * (double)(lv[l] / 2);
+            const double pi = (double)us[l].y + tau * (double)(lv[nu + l] / 2);
+            const double2 zz = Z[lane * nu + l];
+            zr = zr + (zz.x * pr - zz.y * pi);
+            zi = zi + (zz.x * pi + zz.y * pr);
+        }
+        zsh[lane] = make_double2(zr, zi);
+    }
+    wave_sync_lds();
+    double part = 0.0;
+    for (int j = lane; j < ntx; j += 64) {
+        double xr = 0.0, xi = 0.0;
+        for (int i = 0; i < nu; ++i) {
+            const float2 h = H[((size_t)sc * nu + i) * ntx + j];
+            const double2 z = zsh[i];
+            // conj(H_ij) z_i
+            xr = xr + ((double)h.x * z.x + (double)h.y * z.y);
+            xi = xi + ((double)h.x * z.y - (double)h.y * z.x);
+        }
+        if (x_out) x_out[(size_t)n * ntx + j] = make_float2((float)xr, (float)xi);
+        part = part + (xr * xr + xi * xi);
+    }
+    const double tot = wave_sum_f64(part);
+    if (lane == 0 && gamma_out) gamma_out[n] = (float)tot;
+    wave_sync_lds();
+}
+
+// ---------------------------------------------------------------------------
+// Plain path kernels.
+__global__ void __launch_bounds__(kBlock) k_det_build(DetBuildArgs a)
+{
+    __shared__ DetShared sh;
+    const int sc = blockIdx.x;
+    const size_t o = (size_t)sc * a.n_sym;
+    build_det_sc(a.H, a.y, a.n_r, a.n_t, a.n_sym, sc, 0, a.n_sym, a.ld, a.ld, a.qtop, a.c, a.c2,
+                 a.noise_var, a.G + (size_t)sc * a.ld * a.ld, a.f + o * a.ld,
+                 a.x_fb ? a.x_fb + o * a.ld : nullptr, a.ynorm ? a.ynorm + o : nullptr, sh);
+}
+
+__global__ void __launch_bounds__(kBlock) k_vpp_build(VppBuildArgs a)
+{
+    __shared__ VppShared sh;
+    const int sc = blockIdx.x;
+    const size_t o = (size_t)sc * a.n_sym;
+    build_vpp_sc(a.H, a.u, a.n_u, a.n_t, a.n_sym, sc, 0, a.n_sym, a.ld, a.ld, a.tau,
+                 a.G + (size_t)sc * a.ld * a.ld, a.f + o * a.ld,
+                 a.x_fb ? a.x_fb + o * a.ld : nullptr,
+                 a.Ainv ? a.Ainv + (size_t)sc * a.n_u * a.n_u : nullptr,
+                 a.unorm ? a.unorm + o : nullptr, sh);
+}
+
+// One wavefront = 64 chains of one instance; chains >= 64 use several
+// wavefronts.  Writes every chain's final energy and spin words.
+template <int KT, int Q>
+__global__ void __launch_bounds__(kBlock)
+k_anneal(const float *__restrict__ G, int inst_per_G, const float *__restrict__ f,
+         const signed char *__restrict__ x_fb, const float *__restrict__ beta2,
+         const uint32_t *__restrict__ accept_table, int sweeps, int chains, int n_inst, int w0,
+         int w1, int w2, int w3, uint32_t key0, uint32_t key1, int init_mode,
+         float *__restrict__ chain_E, uint32_t *__restrict__ chain_S)
+{
+    constexpr int NW = (KT * Q + 31) / 32;
+    __shared__ uint32_t T[kAcceptSteps + 1];
+    for (int e = threadIdx.x; e <= kAcceptSteps; e += kBlock) T[e] = accept_table[e];
+    __syncthreads();
+
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int wpi = (chains + 63) >> 6;
+    const int gw = blockIdx.x * kWavesPerBlock + wave;
+    const int inst = gw / wpi;
+    if (inst >= n_inst) return;
+    const int ch = (gw - inst * wpi) * 64 + lane;
+    const float *Gi = G + (size_t)(inst / inst_per_G) * (KT * KT);
+    const float *fi = f + (size_t)inst * KT;
+    const signed char *xi = x_fb ? x_fb + (size_t)inst * KT : nullptr;
+    const int wts[4] = {w0, w1, w2, w3};
+    uint32_t bits[NW];
+    const float E = anneal_lane<KT, Q>(Gi, fi, xi, beta2, T, sweeps, wts, key0, key1, init_mode,
+                                       (uint32_t)ch, (uint32_t)inst, bits);
+    if (ch < chains) {
+        const size_t o = (size_t)inst * chains + ch;
+        chain_E[o] = E;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) chain_S[o * NW + w] = bits[w];
+    }
+}
+
 __global__ void __launch_bounds__(kBlock) k_select(SelectArgs a)
 {
     __shared__ float terms[kWavesPerBlock][32];
@@ -677,41 +846,15 @@ __global__ void __launch_bounds__(kBlock) k_select(SelectArgs a)
 
     const float *Gi = a.G + (size_t)(n / a.inst_per_G) * KT * KT;
     const float *fi = a.f + (size_t)n * KT;
+    const signed char *xi = a.x_fb ? a.x_fb + (size_t)n * KT : nullptr;
     bool use_fb = false;
     float Efb = 0.0f;
-    if (a.x_fb) {
-        const signed char *xi = a.x_fb + (size_t)n * KT;
-        if (lane < K) {
-            float acc = -fi[lane];
-            for (int l = 0; l < K; ++l) acc = fmaf(Gi[lane * KT + l], (float)xi[l], acc);
-            terms[wave][lane] = acc - fi[lane];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        float e = 0.0f;
-        for (int k = 0; k < K; ++k) e = fmaf((float)xi[k], terms[wave][k], e);
-        Efb = e;
+    if (xi) {
+        Efb = fallback_energy(Gi, KT, K, fi, xi, terms[wave], lane);
         use_fb = energy_less(Efb, Eb);
     }
-    // winning levels into LDS
-    if (lane < K) {
-        int lv;
-        if (use_fb) {
-            lv = a.x_fb[(size_t)n * KT + lane];
-        } else {
-            const uint32_t *S = a.chain_S + ((size_t)n * C + bch) * NW;
-            lv = 0;
-            for (int b = 0; b < q; ++b) {
-                const int i = lane * q + b;
-                lv += ((S[i >> 5] >> (i & 31)) & 1u) ? -a.w[b] : a.w[b];
-            }
-        }
-        lvs[wave][lane] = lv;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint32_t *S = a.chain_S + ((size_t)n * C + bch) * NW;
+    winning_levels(use_fb, xi, S, K, q, a.w, lvs[wave], lane);
 
     if (a.mode == kSelectSolve) {
         const int N = K * q;
@@ -726,7 +869,6 @@ __global__ void __launch_bounds__(kBlock) k_select(SelectArgs a)
                     rem -= a.w[bb] * s;
                 }
             } else {
-                const uint32_t *S = a.chain_S + ((size_t)n * C + bch) * NW;
                 s = ((S[i >> 5] >> (i & 31)) & 1u) ? -1 : 1;
             }
             a.spins_out[(size_t)n * N + i] = (signed char)s;
@@ -737,75 +879,203 @@ __global__ void __launch_bounds__(kBlock) k_select(SelectArgs a)
         }
         return;
     }
-
-    const int nsym = a.n_sym;
-    const int sc = n / nsym, sy = n % nsym;
+    const int sc = n / a.n_sym, sy = n % a.n_sym;
     if (a.mode == kSelectDet) {
-        const int nt = a.n_cols, nr = a.n_rows;
-        const int qtop = (1 << q) - 1;
-        if (lane < nt) {
-            const int pI = (lvs[wave][lane] + qtop) >> 1;
-            const int pQ = (lvs[wave][nt + lane] + qtop) >> 1;
-            const int gI = pI ^ (pI >> 1), gQ = pQ ^ (pQ >> 1);
-            a.sym_out[(size_t)n * nt + lane] = (unsigned char)((gI << q) | gQ);
-        }
-        if (a.metric_out) {
-            double part = 0.0;
-            for (int r = lane; r < nr; r += 64) {
-                const float2 *Hr = a.H + ((size_t)sc * nr + r) * nt;
-                const float2 yv = a.y[((size_t)sc * nsym + sy) * nr + r];
-                double re = yv.x, im = yv.y;
-                for (int t = 0; t < nt; ++t) {
-                    const double xr = a.c * (double)lvs[wave][t];
-                    const double xi = a.c * (double)lvs[wave][nt + t];
-                    const double hr = Hr[t].x, hi = Hr[t].y;
-                    re = re - (hr * xr - hi * xi);
-                    im = im - (hr * xi + hi * xr);
-                }
-                part = part + (re * re + im * im);
-            }
-            const double tot = wave_sum_f64(part);
-            if (lane == 0) a.metric_out[n] = (float)tot;
-        }
-        return;
+        decode_det(lvs[wave], n, sc, sy, a.n_sym, a.n_rows, a.n_cols, q, a.c, a.H, a.y,
+                   a.sym_out, a.metric_out, lane);
+    } else {
+        decode_vpp(lvs[wave], n, sc, sy, a.n_sym, a.n_rows, a.n_cols, a.tau,
+                   a.Ainv + (size_t)sc * a.n_rows * a.n_rows, a.H, a.y, a.v_out, a.x_out,
+                   a.gamma_out, zsh[wave], lane);
     }
+}
 
-    // VPP: v = level / 2; x = H^H A^-1 (u + tau v); gamma = ||x||^2
-    const int nu = a.n_rows, ntx = a.n_cols;
-    if (lane < K) a.v_out[(size_t)n * K + lane] = (signed char)(lvs[wave][lane] / 2);
-    if (a.x_out || a.gamma_out) {
-        const double2 *Z = a.Ainv + (size_t)sc * nu * nu;
-        const float2 *us = a.y + ((size_t)sc * nsym + sy) * nu;
-        if (lane < nu) {
-            double zr = 0.0, zi = 0.0;
-            for (int l = 0; l < nu; ++l) {
-                const double pr = (double)us[l].x + a.tau * (double)(lvs[wave][l] / 2);
-                const double pi = (double)us[l].y + a.tau * (double)(lvs[wave][nu + l] / 2);
-                const double2 zz = Z[lane * nu + l];
-                zr = zr + (zz.x * pr - zz.y * pi);
-                zi = zi + (zz.x * pi + zz.y * pr);
-            }
-            zsh[wave][lane] = make_double2(zr, zi);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        double part = 0.0;
-        for (int j = lane; j < ntx; j += 64) {
-            double xr = 0.0, xi = 0.0;
-            for (int i = 0; i < nu; ++i) {
-                const float2 h = a.H[((size_t)sc * nu + i) * ntx + j];
-                const double2 z = zsh[wave][i];
-                // conj(H_ij) z_i
-                xr = xr + ((double)h.x * z.x + (double)h.y * z.y);
-                xi = xi + ((double)h.x * z.y - (double)h.y * z.x);
-            }
-            if (a.x_out) a.x_out[(size_t)n * ntx + j] = make_float2((float)xr, (float)xi);
-            part = part + (xr * xr + xi * xi);
-        }
-        const double tot = wave_sum_f64(part);
-        if (lane == 0 && a.gamma_out) a.gamma_out[n] = (float)tot;
+// ---------------------------------------------------------------------------
+// Fused path: one persistent launch.  Each workgroup takes work items from a
+// device counter; an item is (job, subcarrier, up to 4 symbols).  For its item
+// the workgroup builds the subcarrier's couplings (into the job's
+// per-subcarrier slot; several items of one subcarrier write identical values)
+// and the symbols' fields and fallbacks; then each wavefront anneals 64 chains
+// of one instance, the chains of an instance are reduced in registers and LDS,
+// and the winner's wavefront decodes.  Items come ordered by decreasing cost.
+struct FusedShared {
+    union {
+        DetShared det;
+        VppShared vpp;
+    } b;
+    uint32_t T[kAcceptSteps + 1];
+    uint64_t keys[kWavesPerBlock];
+    float terms[kWavesPerBlock][32];
+    int lvs[kWavesPerBlock][32];
+    double2 zsh[kWavesPerBlock][16];
+    int item;
+};
+// The fused kernel's workgroup-shared state, at namespace scope so that the
+// out-of-line variants address it as LDS.
+__shared__ FusedShared g_fsh;
+
+// Wave-uniform copies of call arguments (arguments of a non-inlined function
+// arrive in vector registers).
+template <typename T>
+__device__ __forceinline__ T *uniform_ptr(T *p)
+{
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (T *)(((uint64_t)hi << 32) | lo);
+}
+
+// One variant per (KT, Q), kept out of line so that each is register-allocated
+// on its own: inlined together in the persistent kernel, the variants' union
+// would set the register budget of every wavefront.
+__device__ __forceinline__ int rfl(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint32_t rflu(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double rfld(double v)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint64_t lo = rflu((uint32_t)b), hi = rflu((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)((hi << 32) | lo));
+}
+
+template <int KT, int Q>
+__device__ __attribute__((noinline)) void fused_anneal(const FusedJob *jobs_in, int job_in,
+                                                       int sc_in, int sym0_in, int ns_in)
+{
+    constexpr int NW = (KT * Q + 31) / 32;
+    // every descriptor field as a wave-uniform (scalar) value
+    const FusedJob *jp = uniform_ptr(jobs_in) + rfl(job_in);
+    const int sc = rfl(sc_in), sym0 = rfl(sym0_in), ns = rfl(ns_in);
+    FusedShared &sh = g_fsh;
+    const int kind = rfl(jp->kind), K = rfl(jp->K);
+    const int n_rows = rfl(jp->n_rows), n_cols = rfl(jp->n_cols), n_sym = rfl(jp->n_sym);
+    const int chains = rfl(jp->chains), sweeps = rfl(jp->sweeps), init = rfl(jp->init);
+    const int wpi = rfl(jp->wpi);                       // wavefronts per instance: 1, 2 or 4
+    const int ldf = rfl(jp->ldf);
+    const int w[4] = {rfl(jp->w[0]), rfl(jp->w[1]), rfl(jp->w[2]), rfl(jp->w[3])};
+    const uint32_t key0 = rflu(jp->key0), key1 = rflu(jp->key1);
+    const double c = rfld(jp->c), tau = rfld(jp->tau);
+    const float2 *H = uniform_ptr(jp->H);
+    const float2 *y = uniform_ptr(jp->y);
+    const float *beta2 = uniform_ptr(jp->beta2);
+    const float *Gbase = uniform_ptr(jp->G);
+    const float *fbase = uniform_ptr(jp->f);
+    const signed char *xbase = uniform_ptr(jp->x_fb);
+    const double2 *Abase = uniform_ptr(jp->Ainv);
+    void *out0 = uniform_ptr(jp->out0), *out1 = uniform_ptr(jp->out1);
+    void *out2 = uniform_ptr(jp->out2);
+
+    const int wave = rfl(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int r0 = wave / wpi;                 // instance of this wavefront within the item
+    const int chunk = wave - r0 * wpi;
+    const bool active = r0 < ns;               // uniform over the wavefront
+    const int n = sc * n_sym + sym0 + (active ? r0 : 0);
+    const int ch = chunk * 64 + lane;
+    const float *Gi = Gbase + (size_t)sc * (KT * KT);
+    const float *fi = fbase + (size_t)n * ldf;
+    const signed char *xi = xbase + (size_t)n * KT;
+    uint32_t bits[NW];
+    float E = 0.0f;
+    if (active) {
+        E = anneal_lane<KT, Q>(Gi, fi, xi, beta2, sh.T, sweeps, w, key0, key1, init,
+                               (uint32_t)ch, (uint32_t)n, bits);
+        uint64_t key = ~0ull;
+        if (ch < chains) key = ((uint64_t)energy_key(E) << 32) | (uint32_t)ch;
+        key = wave_min_u64(key);
+        if (lane == 0) sh.keys[wave] = key;
     }
+    __syncthreads();
+    int bch = 0;
+    if (active) {
+        uint64_t best = ~0ull;
+        for (int c2 = 0; c2 < wpi; ++c2) {
+            const uint64_t o = sh.keys[r0 * wpi + c2];
+            best = o < best ? o : best;
+        }
+        bch = (int)(uint32_t)best;
+        if (ch == bch) {                        // the winning lane publishes its spins
+            for (int ww = 0; ww < NW; ++ww) sh.lvs[wave][ww] = (int)bits[ww];
+        }
+    }
+    __syncthreads();
+    if (!active || chunk != bch / 64) return;   // the winner's wavefront decodes
+    uint32_t S[NW];
+    for (int ww = 0; ww < NW; ++ww) S[ww] = (uint32_t)sh.lvs[wave][ww];
+    wave_sync_lds();
+    const float Ebest = __shfl(E, bch & 63, 64);
+    const float Efb = fallback_energy(Gi, KT, K, fi, xi, sh.terms[wave], lane);
+    const bool use_fb = energy_less(Efb, Ebest);
+    winning_levels(use_fb, xi, S, K, Q, w, sh.lvs[wave], lane);
+    const int sy = sym0 + r0;
+    if (kind == 0) {
+        decode_det(sh.lvs[wave], n, sc, sy, n_sym, n_rows, n_cols, Q, c, H, y,
+                   (unsigned char *)out0, (float *)out1, lane);
+    } else {
+        decode_vpp(sh.lvs[wave], n, sc, sy, n_sym, n_rows, n_cols, tau,
+                   Abase + (size_t)sc * n_rows * n_rows, H, y, (signed char *)out0,
+                   (float2 *)out1, (float *)out2, sh.zsh[wave], lane);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_fused(const FusedJob *__restrict__ jobs, const FusedItem *__restrict__ items, int n_items,
+        unsigned int *__restrict__ counter, const uint32_t *__restrict__ accept_table)
+{
+    FusedShared &sh = g_fsh;
+    for (int e = threadIdx.x; e <= kAcceptSteps; e += kBlock) sh.T[e] = accept_table[e];
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) sh.item = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int item = __builtin_amdgcn_readfirstlane(sh.item);
+        if (item >= n_items) break;           // every wavefront of the block leaves here
+        const FusedItem it = items[item];
+        const FusedJob &jb = jobs[it.job];
+        float *Gs = jb.G + (size_t)it.sc * jb.KT * jb.KT;
+        float *fs = jb.f + ((size_t)it.sc * jb.n_sym + it.sym0) * jb.ldf;
+        signed char *xs = jb.x_fb + ((size_t)it.sc * jb.n_sym + it.sym0) * jb.KT;
+        if (jb.kind == 0) {
+            build_det_sc(jb.H, jb.y, jb.n_rows, jb.n_cols, jb.n_sym, it.sc, it.sym0, it.ns, jb.KT,
+                         jb.ldf, (1 << jb.Q) - 1, jb.c, jb.c2, jb.noise_var, Gs, fs, xs, nullptr,
+                         sh.b.det);
+        } else {
+            build_vpp_sc(jb.H, jb.y, jb.n_rows, jb.n_cols, jb.n_sym, it.sc, it.sym0, it.ns, jb.KT,
+                         jb.ldf, jb.tau, Gs, fs, xs, jb.Ainv + (size_t)it.sc * jb.n_rows * jb.n_rows,
+                         nullptr, sh.b.vpp);
+        }
+        // The couplings and fields were written with vector stores by this
+        // workgroup and are read back through the scalar cache, which vector
+        // stores do not update.  (1) Every thread waits until its stores are
+        // acknowledged by the L2 of this XCD before the barrier (a
+        // workgroup-scope release alone emits no such wait; an agent-scope one
+        // would also write back and invalidate the L2).  (2) No scalar-cache
+        // line can hold a stale copy: a line is read only after this workgroup
+        // wrote it -- coupling slots (>= 256 B) start on 256-byte boundaries and
+        // field rows are padded to 128 bytes (ldf), so that no line holds data of
+        // two work items; other items of the same subcarrier write identical
+        // couplings.
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        switch (jb.cls) {
+        case 0: fused_anneal<8, 1>(jobs, it.job, it.sc, it.sym0, it.ns); break;
+        case 1: fused_anneal<8, 2>(jobs, it.job, it.sc, it.sym0, it.ns); break;
+        case 2: fused_anneal<8, 3>(jobs, it.job, it.sc, it.sym0, it.ns); break;
+        case 3: fused_anneal<16, 1>(jobs, it.job, it.sc, it.sym0, it.ns); break;
+        case 4: fused_anneal<16, 2>(jobs, it.job, it.sc, it.sym0, it.ns); break;
+        case 5: fused_anneal<16, 3>(jobs, it.job, it.sc, it.sym0, it.ns); break;
+        case 6: fused_anneal<32, 1>(jobs, it.job, it.sc, it.sym0, it.ns); break;
+        case 7: fused_anneal<32, 2>(jobs, it.job, it.sc, it.sym0, it.ns); break;
+        case 8: fused_anneal<32, 3>(jobs, it.job, it.sc, it.sym0, it.ns); break;
+        default: break;
+        }
+    }
+}
+
+__global__ void k_reset_counter(unsigned int *counter)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -894,6 +1164,13 @@ hipError_t launch_anneal_t(const AnnealArgs &a, hipStream_t s)
 
 }  // namespace
 
+int fused_class(int KT, int q)
+{
+    const int kt = KT == 8 ? 0 : (KT == 16 ? 1 : (KT == 32 ? 2 : -1));
+    if (kt < 0 || q < 1 || q > 3) return -1;
+    return kt * 3 + (q - 1);
+}
+
 hipError_t launch_det_build(const DetBuildArgs &a, hipStream_t s)
 {
     if (a.n_sc <= 0) return hipSuccess;
@@ -934,6 +1211,23 @@ hipError_t launch_select(const SelectArgs &a, hipStream_t s)
     const int blocks = (a.n_inst + kWavesPerBlock - 1) / kWavesPerBlock;
     hipLaunchKernelGGL(k_select, dim3(blocks), dim3(kBlock), 0, s, a);
     return hipGetLastError();
+}
+
+hipError_t launch_fused(const FusedJob *jobs, const FusedItem *items, int n_items,
+                        unsigned int *counter, const uint32_t *accept_table, int blocks,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || n_items <= 0 || blocks <= 0) return e;
+    hipLaunchKernelGGL(k_fused, dim3(blocks), dim3(kBlock), 0, s, jobs, items, n_items, counter,
+                       accept_table);
+    return hipGetLastError();
+}
+
+hipError_t fused_blocks_per_cu(int *blocks)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_fused, kBlock, 0);
 }
 
 hipError_t launch_expand(const ExpandArgs &a, hipStream_t s)
