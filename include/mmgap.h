@@ -207,10 +207,13 @@ enum { MMGAP_PLAN_GRAPH = 1 };   /* record the launch as a HIP graph, replayed b
  * mmgap_plan_create -- validate `n_jobs` jobs (host array), copy their
  * descriptors and schedules to the device, cut them into work items (one
  * subcarrier and up to 4, 2 or 1 symbols for <= 64, <= 128, <= 256 chains)
- * ordered by decreasing cost, and allocate the plan's own device scratch
- * (couplings, fields, fallbacks, VPP inverses), counted against the context's
- * HBM budget.  `blocks` = workgroups of the persistent launch, 0 = as many as
- * the device holds at once.  flags: MMGAP_PLAN_GRAPH or 0.
+ * grouped by register class of the problem size (K <= 8 or K <= 16 with QPSK;
+ * K <= 16 with 16-QAM; larger) and ordered by decreasing cost within a class,
+ * and allocate the plan's own device scratch (couplings, fields, fallbacks,
+ * VPP inverses), counted against the context's HBM budget.  A launch is one
+ * persistent kernel per class present, largest class first.  `blocks` =
+ * workgroups of each persistent kernel, 0 = as many as the device holds at
+ * once.  flags: MMGAP_PLAN_GRAPH or 0.
  * The plan stores the jobs' device pointers, not their contents: inputs may be
  * rewritten between launches; they must stay allocated until the plan is
  * destroyed.  Plans are independent of the context's other calls and must be
@@ -221,7 +224,7 @@ int mmgap_plan_create(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, int fla
 /* Enqueue one execution of every job of the plan on `stream`.  Launches of the
  * same plan run one after another, also when issued on different streams. */
 int mmgap_plan_launch(mmgap_plan *plan, void *stream);
-/* (host) Work items and persistent workgroups of the plan. */
+/* (host) Work items of the plan and the largest workgroup count of its kernels. */
 int mmgap_plan_info(const mmgap_plan *plan, int *n_items, int *blocks);
 /* Wait for the plan's launches and free it (NULL is a no-op). */
 int mmgap_plan_destroy(mmgap_plan *plan);

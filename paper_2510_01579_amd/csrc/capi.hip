@@ -315,12 +315,15 @@ double item_cost(const mmgap::FusedJob &j)
 
 struct mmgap_plan {
     mmgap_ctx *ctx = nullptr;
-    int n_items = 0, blocks = 0;
+    int n_items = 0;
+    int cls_items[mmgap::kFusedClasses] = {};   // items per register class
+    int cls_first[mmgap::kFusedClasses] = {};   // first item of the class
+    int cls_blocks[mmgap::kFusedClasses] = {};  // workgroups of the class's launch
     void *mem = nullptr;
     size_t bytes = 0;
     mmgap::FusedJob *jobs_dev = nullptr;
     mmgap::FusedItem *items_dev = nullptr;
-    unsigned int *counter = nullptr;
+    unsigned int *counters = nullptr;           // one work counter per class
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;
@@ -328,6 +331,16 @@ struct mmgap_plan {
 };
 
 namespace {
+
+// Counter reset, then the class kernels, largest problems first.
+hipError_t plan_enqueue(const mmgap_plan *p, hipStream_t st)
+{
+    hipError_t e = mmgap::launch_fused_reset(p->counters, st);
+    for (int c = mmgap::kFusedClasses - 1; c >= 0 && e == hipSuccess; --c)
+        e = mmgap::launch_fused(c, p->jobs_dev, p->items_dev + p->cls_first[c], p->cls_items[c],
+                                p->counters + c, p->ctx->accept_dev, p->cls_blocks[c], st);
+    return e;
+}
 
 void plan_free(mmgap_plan *p)
 {
@@ -741,12 +754,12 @@ int mmgap_plan_create(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, int fla
                         jb.sched.chains, kMaxFusedChains);
         if (sh.n_inst > 0 && (!jb.H || !jb.y_or_u || !jb.out0))
             return fail(ctx, MMGAP_EINVAL, "job %d: H, y_or_u and out0 are required", j);
-        const int cls = mmgap::fused_class(sh.KT, sh.q);
-        if (cls < 0) return fail(ctx, MMGAP_EUNSUPPORTED, "job %d: no fused variant", j);
+        const int variant = mmgap::fused_variant(sh.KT, sh.q);
+        if (variant < 0) return fail(ctx, MMGAP_EUNSUPPORTED, "job %d: no fused variant", j);
         const mmgap_problem &p = jb.prob;
         mmgap::FusedJob &f = fj[j];
         f.kind = p.kind;
-        f.cls = cls;
+        f.variant = variant;
         f.KT = sh.KT;
         f.Q = sh.q;
         f.K = sh.K;
@@ -785,12 +798,18 @@ int mmgap_plan_create(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, int fla
             for (int s0 = 0; s0 < p.n_sym; s0 += per)
                 items.push_back({j, sc, s0, std::min(per, p.n_sym - s0)});
     }
+    // grouped by register class, each group ordered by decreasing cost
+    auto cls_of = [&](const mmgap::FusedItem &a) {
+        return mmgap::fused_kernel_class(fj[a.job].variant);
+    };
     std::stable_sort(items.begin(), items.end(),
                      [&](const mmgap::FusedItem &a, const mmgap::FusedItem &b) {
+                         const int ca = cls_of(a), cb = cls_of(b);
+                         if (ca != cb) return ca < cb;
                          return item_cost(fj[a.job]) > item_cost(fj[b.job]);
                      });
     const size_t o_items = lay.take(sizeof(mmgap::FusedItem) * std::max<size_t>(items.size(), 1));
-    const size_t o_counter = lay.take(sizeof(unsigned int));
+    const size_t o_counter = lay.take(sizeof(unsigned int) * mmgap::kFusedClasses);
     if (items.size() > 0x7FFFFFFFu) return fail(ctx, MMGAP_EUNSUPPORTED, "too many work items");
     if (lay.off + ctx->plan_bytes + ctx->scratch_bytes > ctx->budget)
         return fail(ctx, MMGAP_ENOMEM,
@@ -798,20 +817,30 @@ int mmgap_plan_create(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, int fla
                     ctx->budget, ctx->plan_bytes + ctx->scratch_bytes);
 
     DeviceGuard g(ctx->device);
-    int per_cu = 0, cus = 0;
-    hipError_t e = mmgap::fused_blocks_per_cu(&per_cu);
-    if (e == hipSuccess)
-        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
-    if (e != hipSuccess) return hip_fail(ctx, e, "occupancy query");
-    if (per_cu < 1) return fail(ctx, MMGAP_EDEVICE, "the fused kernel does not fit a compute unit");
-    int grid = blocks > 0 ? blocks : per_cu * cus;
-    if ((size_t)grid > items.size()) grid = (int)std::max<size_t>(items.size(), 1);
+    int cus = 0;
+    hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipDeviceGetAttribute");
 
     mmgap_plan *plan = new (std::nothrow) mmgap_plan();
     if (!plan) return fail(ctx, MMGAP_ENOMEM, "out of host memory");
     plan->ctx = ctx;
     plan->n_items = (int)items.size();
-    plan->blocks = grid;
+    for (size_t i = 0; i < items.size(); ++i) {
+        const int c = cls_of(items[i]);
+        if (plan->cls_items[c] == 0) plan->cls_first[c] = (int)i;
+        ++plan->cls_items[c];
+    }
+    for (int c = 0; c < mmgap::kFusedClasses && e == hipSuccess; ++c) {
+        if (!plan->cls_items[c]) continue;
+        int per_cu = 0;
+        e = mmgap::fused_blocks_per_cu(c, &per_cu);
+        if (e == hipSuccess && per_cu < 1) e = hipErrorInvalidConfiguration;
+        plan->cls_blocks[c] = std::min(blocks > 0 ? blocks : per_cu * cus, plan->cls_items[c]);
+    }
+    if (e != hipSuccess) {
+        delete plan;
+        return hip_fail(ctx, e, "occupancy query");
+    }
     e = hipMalloc(&plan->mem, lay.off);
     if (e != hipSuccess) {
         plan->mem = nullptr;
@@ -823,7 +852,7 @@ int mmgap_plan_create(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, int fla
     char *base = static_cast<char *>(plan->mem);
     plan->jobs_dev = reinterpret_cast<mmgap::FusedJob *>(base + o_jobs);
     plan->items_dev = reinterpret_cast<mmgap::FusedItem *>(base + o_items);
-    plan->counter = reinterpret_cast<unsigned int *>(base + o_counter);
+    plan->counters = reinterpret_cast<unsigned int *>(base + o_counter);
     for (int j = 0; j < n_jobs; ++j) {
         mmgap::FusedJob &f = fj[j];
         f.beta2 = reinterpret_cast<const float *>(base + ob[j]);
@@ -848,9 +877,7 @@ int mmgap_plan_create(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, int fla
         if (e == hipSuccess) {
             e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
-                const hipError_t el = mmgap::launch_fused(plan->jobs_dev, plan->items_dev,
-                                                          plan->n_items, plan->counter,
-                                                          ctx->accept_dev, plan->blocks, cs);
+                const hipError_t el = plan_enqueue(plan, cs);
                 e = hipStreamEndCapture(cs, &plan->graph);
                 if (e == hipSuccess) e = el;
             }
@@ -876,9 +903,7 @@ int mmgap_plan_launch(mmgap_plan *plan, void *stream)
     if (plan->done_valid) e = hipStreamWaitEvent(st, plan->done, 0);
     if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamWaitEvent");
     if (plan->exec) e = hipGraphLaunch(plan->exec, st);
-    else
-        e = mmgap::launch_fused(plan->jobs_dev, plan->items_dev, plan->n_items, plan->counter,
-                                ctx->accept_dev, plan->blocks, st);
+    else e = plan_enqueue(plan, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "fused launch");
     e = hipEventRecord(plan->done, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "hipEventRecord");
@@ -890,7 +915,7 @@ int mmgap_plan_info(const mmgap_plan *plan, int *n_items, int *blocks)
 {
     if (!plan) return MMGAP_EINVAL;
     if (n_items) *n_items = plan->n_items;
-    if (blocks) *blocks = plan->blocks;
+    if (blocks) *blocks = std::max(plan->cls_blocks[0], std::max(plan->cls_blocks[1], plan->cls_blocks[2]));
     return MMGAP_OK;
 }
 

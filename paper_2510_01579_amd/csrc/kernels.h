@@ -106,7 +106,7 @@ struct ExpandArgs {
 // One job of the fused persistent kernel (device copy, read wave-uniformly).
 struct FusedJob {
     int kind;               // 0 detection, 1 VPP
-    int cls;                // anneal variant: fused_class(KT, Q)
+    int variant;            // anneal variant: fused_variant(KT, Q)
     int KT, Q, K;
     int n_rows, n_cols;     // H is n_rows x n_cols (DET: n_r x n_t; VPP: n_u x n_tx)
     int n_sym, n_sc;
@@ -129,11 +129,20 @@ struct FusedItem {
     int job, sc, sym0, ns;
 };
 
-int fused_class(int KT, int q);   // -1 if the fused kernel has no variant for it
-hipError_t launch_fused(const FusedJob *jobs, const FusedItem *items, int n_items,
+// Anneal variant of (KT, q) in the fused path (0..8), -1 if there is none;
+// the register class (0..2) of a variant, -1 if invalid.  One persistent
+// kernel per class, each with its own work counter.
+constexpr int kFusedClasses = 3;
+int fused_variant(int KT, int q);
+int fused_kernel_class(int variant);
+// Zero the kFusedClasses work counters (a kernel, so that it can be recorded
+// in a graph).
+hipError_t launch_fused_reset(unsigned int *counters, hipStream_t s);
+// The persistent kernel of class `cls` over `n_items` items of that class.
+hipError_t launch_fused(int cls, const FusedJob *jobs, const FusedItem *items, int n_items,
                         unsigned int *counter, const uint32_t *accept_table, int blocks,
                         hipStream_t s);
-hipError_t fused_blocks_per_cu(int *blocks);
+hipError_t fused_blocks_per_cu(int cls, int *blocks);
 
 hipError_t launch_det_build(const DetBuildArgs &a, hipStream_t s);
 hipError_t launch_vpp_build(const VppBuildArgs &a, hipStream_t s);

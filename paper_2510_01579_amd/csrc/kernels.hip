@@ -124,18 +124,20 @@ __device__ __forceinline__ void wave_sync_lds()
 // Writes G (ld x ld, zero padded) to Gout and, for symbols sym0..sym0+ns-1,
 // the field rows to fout, the fallback levels to xout (if non-null) and ||y||^2
 // to ynorm (if non-null).  ns <= 64.
-struct DetShared {
-    float2 Hs[64 * 16];
-    double2 Cg[16 * 16];
-    double2 Fs[64 * 16];
-    double2 Ls[16 * 16];
-    double ds[16];
+template <int NT, int NS>
+struct DetSharedT {
+    float2 Hs[64 * NT];
+    double2 Cg[NT * NT];
+    double2 Fs[NS * NT];
+    double2 Ls[NT * NT];
+    double ds[NT];
 };
 
+template <int NT, int NS>
 __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, int nsym, int sc,
                              int sym0, int ns, int ld, int ldf, int qtop, double c, double c2,
                              double noise_var, float *Gout, float *fout, signed char *xout,
-                             double *ynorm, DetShared &sh)
+                             double *ynorm, DetSharedT<NT, NS> &sh)
 {
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
@@ -163,8 +165,8 @@ __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, i
             im = im + pim;
         }
         if (ia == ib) im = 0.0;
-        sh.Cg[ia * 16 + ib] = make_double2(re, im);
-        sh.Cg[ib * 16 + ia] = make_double2(re, 0.0 - im);
+        sh.Cg[ia * NT + ib] = make_double2(re, im);
+        sh.Cg[ib * NT + ia] = make_double2(re, 0.0 - im);
         const float gre = (float)(c2 * re);
         const float gim = (float)(c2 * im);
         const float ngim = (float)(c2 * (0.0 - im));
@@ -191,7 +193,7 @@ __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, i
             re = re + pre;
             im = im + pim;
         }
-        sh.Fs[r0 * 16 + ia] = make_double2(re, im);
+        sh.Fs[r0 * NT + ia] = make_double2(re, im);
         float *fs = fout + (size_t)r0 * ldf;
         fs[ia] = (float)(c * re);
         fs[nt + ia] = (float)(c * im);
@@ -217,9 +219,9 @@ __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, i
     // LDL^H of Cg + sigma^2 I
     for (int j = 0; j < nt; ++j) {
         if (tid == 0) {
-            double dj = sh.Cg[j * 16 + j].x + noise_var;
+            double dj = sh.Cg[j * NT + j].x + noise_var;
             for (int k = 0; k < j; ++k) {
-                const double2 v = sh.Ls[j * 16 + k];
+                const double2 v = sh.Ls[j * NT + k];
                 double t = v.x * v.x + v.y * v.y;
                 t = t * sh.ds[k];
                 dj = dj - t;
@@ -228,25 +230,25 @@ __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, i
         }
         __syncthreads();
         for (int i = j + 1 + tid; i < nt; i += nthr) {
-            cd s = ld2(sh.Cg[i * 16 + j]);
+            cd s = ld2(sh.Cg[i * NT + j]);
             for (int k = 0; k < j; ++k) {
-                cd v = cmulc(ld2(sh.Ls[j * 16 + k]), ld2(sh.Ls[i * 16 + k]));
+                cd v = cmulc(ld2(sh.Ls[j * NT + k]), ld2(sh.Ls[i * NT + k]));
                 v.re = v.re * sh.ds[k];
                 v.im = v.im * sh.ds[k];
                 s.re = s.re - v.re;
                 s.im = s.im - v.im;
             }
-            sh.Ls[i * 16 + j] = make_double2(s.re / sh.ds[j], s.im / sh.ds[j]);
+            sh.Ls[i * NT + j] = make_double2(s.re / sh.ds[j], s.im / sh.ds[j]);
         }
         __syncthreads();
     }
     // per-symbol solves in place on Fs, then slicing
     for (int r0 = tid; r0 < ns; r0 += nthr) {
-        double2 *w = sh.Fs + r0 * 16;
+        double2 *w = sh.Fs + r0 * NT;
         for (int i = 0; i < nt; ++i) {
             cd s = ld2(w[i]);
             for (int k = 0; k < i; ++k) {
-                const cd v = cmul(ld2(sh.Ls[i * 16 + k]), ld2(w[k]));
+                const cd v = cmul(ld2(sh.Ls[i * NT + k]), ld2(w[k]));
                 s.re = s.re - v.re;
                 s.im = s.im - v.im;
             }
@@ -256,7 +258,7 @@ __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, i
         for (int i = nt - 1; i >= 0; --i) {
             cd s = ld2(w[i]);
             for (int k = i + 1; k < nt; ++k) {
-                const cd v = cmulc(ld2(sh.Ls[k * 16 + i]), ld2(w[k]));
+                const cd v = cmulc(ld2(sh.Ls[k * NT + i]), ld2(w[k]));
                 s.re = s.re - v.re;
                 s.im = s.im - v.im;
             }
@@ -283,18 +285,20 @@ __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, i
 // A^-1 = M^H D^-1 M in a fixed operation order (so that any implementation of
 // the same sequence agrees bit for bit), then
 //   G = (tau/2)^2 Re-form(A^-1),  f = -(tau/2) Re-form(A^-1 u).
-struct VppShared {
-    float2 Hs[16 * 64];
-    double2 As[16 * 16];
-    double2 Ls[16 * 16];
-    double2 Ms[16 * 16];
-    double2 Zs[16 * 16];   // A^-1
-    double ds[16];
+template <int NU>
+struct VppSharedT {
+    float2 Hs[NU * 64];
+    double2 As[NU * NU];
+    double2 Ls[NU * NU];
+    double2 Ms[NU * NU];
+    double2 Zs[NU * NU];   // A^-1
+    double ds[NU];
 };
 
+template <int NU>
 __device__ void build_vpp_sc(const float2 *H, const float2 *u, int n, int ntx, int nsym, int sc,
                              int sym0, int ns, int ld, int ldf, double tau, float *Gout, float *fout,
-                             signed char *xout, double2 *Ainv_out, double *unorm, VppShared &sh)
+                             signed char *xout, double2 *Ainv_out, double *unorm, VppSharedT<NU> &sh)
 {
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
@@ -321,16 +325,16 @@ __device__ void build_vpp_sc(const float2 *H, const float2 *u, int n, int ntx, i
             re = re + pre;
             im = im + pim;
         }
-        sh.As[i * 16 + l] = make_double2(re, im);
-        sh.As[l * 16 + i] = make_double2(re, -im);
+        sh.As[i * NU + l] = make_double2(re, im);
+        sh.As[l * NU + i] = make_double2(re, -im);
     }
     __syncthreads();
 
     for (int j = 0; j < n; ++j) {
         if (tid == 0) {
-            double dj = sh.As[j * 16 + j].x;
+            double dj = sh.As[j * NU + j].x;
             for (int k = 0; k < j; ++k) {
-                const double2 v = sh.Ls[j * 16 + k];
+                const double2 v = sh.Ls[j * NU + k];
                 double t = v.x * v.x + v.y * v.y;
                 t = t * sh.ds[k];
                 dj = dj - t;
@@ -339,29 +343,29 @@ __device__ void build_vpp_sc(const float2 *H, const float2 *u, int n, int ntx, i
         }
         __syncthreads();
         for (int i = j + 1 + tid; i < n; i += nthr) {
-            cd s = ld2(sh.As[i * 16 + j]);
+            cd s = ld2(sh.As[i * NU + j]);
             for (int k = 0; k < j; ++k) {
-                cd v = cmulc(ld2(sh.Ls[j * 16 + k]), ld2(sh.Ls[i * 16 + k]));
+                cd v = cmulc(ld2(sh.Ls[j * NU + k]), ld2(sh.Ls[i * NU + k]));
                 v.re = v.re * sh.ds[k];
                 v.im = v.im * sh.ds[k];
                 s.re = s.re - v.re;
                 s.im = s.im - v.im;
             }
-            sh.Ls[i * 16 + j] = make_double2(s.re / sh.ds[j], s.im / sh.ds[j]);
+            sh.Ls[i * NU + j] = make_double2(s.re / sh.ds[j], s.im / sh.ds[j]);
         }
         __syncthreads();
     }
     // M = L^-1, one column per thread
     for (int m = tid; m < n; m += nthr) {
-        sh.Ms[m * 16 + m] = make_double2(1.0, 0.0);
+        sh.Ms[m * NU + m] = make_double2(1.0, 0.0);
         for (int i = m + 1; i < n; ++i) {
             cd s{0.0, 0.0};
             for (int k = m; k < i; ++k) {
-                const cd v = cmul(ld2(sh.Ls[i * 16 + k]), ld2(sh.Ms[k * 16 + m]));
+                const cd v = cmul(ld2(sh.Ls[i * NU + k]), ld2(sh.Ms[k * NU + m]));
                 s.re = s.re + v.re;
                 s.im = s.im + v.im;
             }
-            sh.Ms[i * 16 + m] = make_double2(-s.re, -s.im);
+            sh.Ms[i * NU + m] = make_double2(-s.re, -s.im);
         }
     }
     __syncthreads();
@@ -371,27 +375,27 @@ __device__ void build_vpp_sc(const float2 *H, const float2 *u, int n, int ntx, i
         upper_pair(p, n, l, i);
         cd acc{0.0, 0.0};
         for (int k = i; k < n; ++k) {
-            cd v = cmulc(ld2(sh.Ms[k * 16 + i]), ld2(sh.Ms[k * 16 + l]));
+            cd v = cmulc(ld2(sh.Ms[k * NU + i]), ld2(sh.Ms[k * NU + l]));
             v.re = v.re / sh.ds[k];
             v.im = v.im / sh.ds[k];
             acc.re = acc.re + v.re;
             acc.im = acc.im + v.im;
         }
-        sh.Zs[i * 16 + l] = st2(acc);
-        if (i != l) sh.Zs[l * 16 + i] = make_double2(acc.re, -acc.im);
-        else sh.Zs[i * 16 + i] = make_double2(acc.re, -acc.im);
+        sh.Zs[i * NU + l] = st2(acc);
+        if (i != l) sh.Zs[l * NU + i] = make_double2(acc.re, -acc.im);
+        else sh.Zs[i * NU + i] = make_double2(acc.re, -acc.im);
     }
     __syncthreads();
 
     if (Ainv_out) {
-        for (int e = tid; e < n * n; e += nthr) Ainv_out[e] = sh.Zs[(e / n) * 16 + (e % n)];
+        for (int e = tid; e < n * n; e += nthr) Ainv_out[e] = sh.Zs[(e / n) * NU + (e % n)];
     }
     for (int e = tid; e < ld * ld; e += nthr) {
         const int r = e / ld, cc = e % ld;
         float v = 0.0f;
         if (r < K && cc < K) {
             const int i = r % n, l = cc % n;
-            const double2 z = sh.Zs[i * 16 + l];
+            const double2 z = sh.Zs[i * NU + l];
             if ((r < n) == (cc < n)) v = (float)(sg * z.x);
             else if (r < n) v = (float)(sg * (-z.y));   // upper-right: -Im
             else v = (float)(sg * z.y);                 // lower-left: Im
@@ -404,7 +408,7 @@ __device__ void build_vpp_sc(const float2 *H, const float2 *u, int n, int ntx, i
         cd z{0.0, 0.0};
         for (int l = 0; l < n; ++l) {
             const cd ul{(double)us[l].x, (double)us[l].y};
-            const cd v = cmul(ld2(sh.Zs[i * 16 + l]), ul);
+            const cd v = cmul(ld2(sh.Zs[i * NU + l]), ul);
             z.re = z.re + v.re;
             z.im = z.im + v.im;
         }
@@ -426,7 +430,7 @@ __device__ void build_vpp_sc(const float2 *H, const float2 *u, int n, int ntx, i
             for (int i = 0; i < n; ++i) {
                 cd z{0.0, 0.0};
                 for (int l = 0; l < n; ++l) {
-                    const cd v = cmul(ld2(sh.Zs[i * 16 + l]), cd{(double)us[l].x, (double)us[l].y});
+                    const cd v = cmul(ld2(sh.Zs[i * NU + l]), cd{(double)us[l].x, (double)us[l].y});
                     z.re = z.re + v.re;
                     z.im = z.im + v.im;
                 }
@@ -764,7 +768,7 @@ __device__ void decode_vpp(const int *lv, int n, int sc, int sy, int nsym, int n
 // Plain path kernels.
 __global__ void __launch_bounds__(kBlock) k_det_build(DetBuildArgs a)
 {
-    __shared__ DetShared sh;
+    __shared__ DetSharedT<16, 64> sh;
     const int sc = blockIdx.x;
     const size_t o = (size_t)sc * a.n_sym;
     build_det_sc(a.H, a.y, a.n_r, a.n_t, a.n_sym, sc, 0, a.n_sym, a.ld, a.ld, a.qtop, a.c, a.c2,
@@ -774,7 +778,7 @@ __global__ void __launch_bounds__(kBlock) k_det_build(DetBuildArgs a)
 
 __global__ void __launch_bounds__(kBlock) k_vpp_build(VppBuildArgs a)
 {
-    __shared__ VppShared sh;
+    __shared__ VppSharedT<16> sh;
     const int sc = blockIdx.x;
     const size_t o = (size_t)sc * a.n_sym;
     build_vpp_sc(a.H, a.u, a.n_u, a.n_t, a.n_sym, sc, 0, a.n_sym, a.ld, a.ld, a.tau,
@@ -891,18 +895,29 @@ __global__ void __launch_bounds__(kBlock) k_select(SelectArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// Fused path: one persistent launch.  Each workgroup takes work items from a
+// Fused path: persistent launches.  Each workgroup takes work items from a
 // device counter; an item is (job, subcarrier, up to 4 symbols).  For its item
 // the workgroup builds the subcarrier's couplings (into the job's
 // per-subcarrier slot; several items of one subcarrier write identical values)
 // and the symbols' fields and fallbacks; then each wavefront anneals 64 chains
 // of one instance, the chains of an instance are reduced in registers and LDS,
 // and the winner's wavefront decodes.  Items come ordered by decreasing cost.
-struct FusedShared {
-    union {
-        DetShared det;
-        VppShared vpp;
-    } b;
+//
+// The anneal variants differ in register demand (about 64 VGPRs for KT = 8,
+// 73 for KT = 16 with two spins per dimension, up to 128 for the largest), and
+// a kernel's register allocation is the maximum over all of its code.  So the
+// variants are grouped into three register classes, one persistent kernel each
+// with the class's variants inlined, its own queue, its own occupancy target
+// and build scratch sized for the problems it takes:
+//   class 0: KT = 8 (any q) and KT = 16 with q = 1   <= 64 VGPRs, 8 waves/SIMD
+//   class 1: KT = 16, q = 2                          <= 80 VGPRs, 6 waves/SIMD
+//   class 2: KT = 16, q = 3 and KT = 32              <= 128 VGPRs, 4 waves/SIMD
+constexpr int kFusedItemSyms = 4;   // symbols per work item at most
+
+// State shared by every class: threshold table, per-wavefront selection and
+// decode scratch, the current item.  At namespace scope so that the
+// out-of-line variants address it as LDS.
+struct FusedCommon {
     uint32_t T[kAcceptSteps + 1];
     uint64_t keys[kWavesPerBlock];
     float terms[kWavesPerBlock][32];
@@ -910,12 +925,42 @@ struct FusedShared {
     double2 zsh[kWavesPerBlock][16];
     int item;
 };
-// The fused kernel's workgroup-shared state, at namespace scope so that the
-// out-of-line variants address it as LDS.
-__shared__ FusedShared g_fsh;
+__shared__ FusedCommon g_fc;
 
-// Wave-uniform copies of call arguments (arguments of a non-inlined function
-// arrive in vector registers).
+// Build scratch per class: detection with n_t <= NTD, VPP with n_u <= NUV.
+template <int NTD, int NUV>
+union FusedBuildShared {
+    DetSharedT<NTD, kFusedItemSyms> det;
+    VppSharedT<NUV> vpp;
+};
+template <int CLS> struct FusedClassTraits;
+template <> struct FusedClassTraits<0> {
+    static constexpr int kNTD = 8, kNUV = 4, kMinWaves = 8;
+};
+template <> struct FusedClassTraits<1> {
+    static constexpr int kNTD = 8, kNUV = 8, kMinWaves = 6;
+};
+template <> struct FusedClassTraits<2> {
+    static constexpr int kNTD = 16, kNUV = 16, kMinWaves = 4;
+};
+// The class of a variant fixes these bounds: KT = 8 means n_t <= 4 (DET) or
+// n_u <= 4 (VPP); KT = 16 means n_t, n_u <= 8; KT = 32 means n_t, n_u <= 16.
+template <int CLS>
+using FusedBuildSharedOf =
+    FusedBuildShared<FusedClassTraits<CLS>::kNTD, FusedClassTraits<CLS>::kNUV>;
+__shared__ FusedBuildSharedOf<0> g_fb0;
+__shared__ FusedBuildSharedOf<1> g_fb1;
+__shared__ FusedBuildSharedOf<2> g_fb2;
+template <int CLS>
+__device__ __forceinline__ auto &fused_build_shared()
+{
+    if constexpr (CLS == 0) return g_fb0;
+    else if constexpr (CLS == 1) return g_fb1;
+    else return g_fb2;
+}
+
+// Wave-uniform copies of descriptor fields and item coordinates, so that the
+// compiler keeps them (and the addresses derived from them) in scalar registers.
 template <typename T>
 __device__ __forceinline__ T *uniform_ptr(T *p)
 {
@@ -924,10 +969,6 @@ __device__ __forceinline__ T *uniform_ptr(T *p)
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
     return (T *)(((uint64_t)hi << 32) | lo);
 }
-
-// One variant per (KT, Q), kept out of line so that each is register-allocated
-// on its own: inlined together in the persistent kernel, the variants' union
-// would set the register budget of every wavefront.
 __device__ __forceinline__ int rfl(int v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ uint32_t rflu(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ double rfld(double v)
@@ -937,15 +978,16 @@ __device__ __forceinline__ double rfld(double v)
     return __longlong_as_double((long long)((hi << 32) | lo));
 }
 
+// Anneal, select and decode of one work item by variant (KT, Q).
 template <int KT, int Q>
-__device__ __attribute__((noinline)) void fused_anneal(const FusedJob *jobs_in, int job_in,
-                                                       int sc_in, int sym0_in, int ns_in)
+__device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in, int sc_in,
+                                                  int sym0_in, int ns_in)
 {
     constexpr int NW = (KT * Q + 31) / 32;
     // every descriptor field as a wave-uniform (scalar) value
     const FusedJob *jp = uniform_ptr(jobs_in) + rfl(job_in);
     const int sc = rfl(sc_in), sym0 = rfl(sym0_in), ns = rfl(ns_in);
-    FusedShared &sh = g_fsh;
+    FusedCommon &sh = g_fc;
     const int kind = rfl(jp->kind), K = rfl(jp->K);
     const int n_rows = rfl(jp->n_rows), n_cols = rfl(jp->n_cols), n_sym = rfl(jp->n_sym);
     const int chains = rfl(jp->chains), sweeps = rfl(jp->sweeps), init = rfl(jp->init);
@@ -1017,11 +1059,38 @@ __device__ __attribute__((noinline)) void fused_anneal(const FusedJob *jobs_in, 
     }
 }
 
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
+template <int CLS>
+__device__ __forceinline__ void fused_dispatch(int variant, const FusedJob *jobs, const FusedItem &it)
+{
+    if constexpr (CLS == 0) {
+        switch (variant) {
+        case 0: fused_anneal<8, 1>(jobs, it.job, it.sc, it.sym0, it.ns); break;
+        case 1: fused_anneal<8, 2>(jobs, it.job, it.sc, it.sym0, it.ns); break;
+        case 2: fused_anneal<8, 3>(jobs, it.job, it.sc, it.sym0, it.ns); break;
+        case 3: fused_anneal<16, 1>(jobs, it.job, it.sc, it.sym0, it.ns); break;
+        default: break;
+        }
+    } else if constexpr (CLS == 1) {
+        if (variant == 4) fused_anneal<16, 2>(jobs, it.job, it.sc, it.sym0, it.ns);
+    } else {
+        switch (variant) {
+        case 5: fused_anneal<16, 3>(jobs, it.job, it.sc, it.sym0, it.ns); break;
+        case 6: fused_anneal<32, 1>(jobs, it.job, it.sc, it.sym0, it.ns); break;
+        case 7: fused_anneal<32, 2>(jobs, it.job, it.sc, it.sym0, it.ns); break;
+        case 8: fused_anneal<32, 3>(jobs, it.job, it.sc, it.sym0, it.ns); break;
+        default: break;
+        }
+    }
+}
+
+template <int CLS>
+__global__ void __launch_bounds__(kBlock)
+    __attribute__((amdgpu_waves_per_eu(FusedClassTraits<CLS>::kMinWaves, 8)))
 k_fused(const FusedJob *__restrict__ jobs, const FusedItem *__restrict__ items, int n_items,
         unsigned int *__restrict__ counter, const uint32_t *__restrict__ accept_table)
 {
-    FusedShared &sh = g_fsh;
+    FusedCommon &sh = g_fc;
+    auto &bs = fused_build_shared<CLS>();
     for (int e = threadIdx.x; e <= kAcceptSteps; e += kBlock) sh.T[e] = accept_table[e];
     for (;;) {
         __syncthreads();
@@ -1037,11 +1106,11 @@ k_fused(const FusedJob *__restrict__ jobs, const FusedItem *__restrict__ items, 
         if (jb.kind == 0) {
             build_det_sc(jb.H, jb.y, jb.n_rows, jb.n_cols, jb.n_sym, it.sc, it.sym0, it.ns, jb.KT,
                          jb.ldf, (1 << jb.Q) - 1, jb.c, jb.c2, jb.noise_var, Gs, fs, xs, nullptr,
-                         sh.b.det);
+                         bs.det);
         } else {
             build_vpp_sc(jb.H, jb.y, jb.n_rows, jb.n_cols, jb.n_sym, it.sc, it.sym0, it.ns, jb.KT,
-                         jb.ldf, jb.tau, Gs, fs, xs, jb.Ainv + (size_t)it.sc * jb.n_rows * jb.n_rows,
-                         nullptr, sh.b.vpp);
+                         jb.ldf, jb.tau, Gs, fs, xs,
+                         jb.Ainv + (size_t)it.sc * jb.n_rows * jb.n_rows, nullptr, bs.vpp);
         }
         // The couplings and fields were written with vector stores by this
         // workgroup and are read back through the scalar cache, which vector
@@ -1058,24 +1127,13 @@ k_fused(const FusedJob *__restrict__ jobs, const FusedItem *__restrict__ items, 
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        switch (jb.cls) {
-        case 0: fused_anneal<8, 1>(jobs, it.job, it.sc, it.sym0, it.ns); break;
-        case 1: fused_anneal<8, 2>(jobs, it.job, it.sc, it.sym0, it.ns); break;
-        case 2: fused_anneal<8, 3>(jobs, it.job, it.sc, it.sym0, it.ns); break;
-        case 3: fused_anneal<16, 1>(jobs, it.job, it.sc, it.sym0, it.ns); break;
-        case 4: fused_anneal<16, 2>(jobs, it.job, it.sc, it.sym0, it.ns); break;
-        case 5: fused_anneal<16, 3>(jobs, it.job, it.sc, it.sym0, it.ns); break;
-        case 6: fused_anneal<32, 1>(jobs, it.job, it.sc, it.sym0, it.ns); break;
-        case 7: fused_anneal<32, 2>(jobs, it.job, it.sc, it.sym0, it.ns); break;
-        case 8: fused_anneal<32, 3>(jobs, it.job, it.sc, it.sym0, it.ns); break;
-        default: break;
-        }
+        fused_dispatch<CLS>(jb.variant, jobs, it);
     }
 }
 
-__global__ void k_reset_counter(unsigned int *counter)
+__global__ void k_reset_counters(unsigned int *counters, int n)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
+    if (blockIdx.x == 0 && (int)threadIdx.x < n) counters[threadIdx.x] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -1164,11 +1222,17 @@ hipError_t launch_anneal_t(const AnnealArgs &a, hipStream_t s)
 
 }  // namespace
 
-int fused_class(int KT, int q)
+int fused_variant(int KT, int q)
 {
     const int kt = KT == 8 ? 0 : (KT == 16 ? 1 : (KT == 32 ? 2 : -1));
     if (kt < 0 || q < 1 || q > 3) return -1;
     return kt * 3 + (q - 1);
+}
+
+int fused_kernel_class(int variant)
+{
+    if (variant < 0 || variant > 8) return -1;
+    return variant <= 3 ? 0 : (variant == 4 ? 1 : 2);
 }
 
 hipError_t launch_det_build(const DetBuildArgs &a, hipStream_t s)
@@ -1213,21 +1277,43 @@ hipError_t launch_select(const SelectArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_fused(const FusedJob *jobs, const FusedItem *items, int n_items,
-                        unsigned int *counter, const uint32_t *accept_table, int blocks,
-                        hipStream_t s)
+hipError_t launch_fused_reset(unsigned int *counters, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || n_items <= 0 || blocks <= 0) return e;
-    hipLaunchKernelGGL(k_fused, dim3(blocks), dim3(kBlock), 0, s, jobs, items, n_items, counter,
-                       accept_table);
+    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, counters, kFusedClasses);
     return hipGetLastError();
 }
 
-hipError_t fused_blocks_per_cu(int *blocks)
+hipError_t launch_fused(int cls, const FusedJob *jobs, const FusedItem *items, int n_items,
+                        unsigned int *counter, const uint32_t *accept_table, int blocks,
+                        hipStream_t s)
 {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_fused, kBlock, 0);
+    if (n_items <= 0 || blocks <= 0) return hipSuccess;
+    switch (cls) {
+    case 0:
+        hipLaunchKernelGGL(k_fused<0>, dim3(blocks), dim3(kBlock), 0, s, jobs, items, n_items,
+                           counter, accept_table);
+        break;
+    case 1:
+        hipLaunchKernelGGL(k_fused<1>, dim3(blocks), dim3(kBlock), 0, s, jobs, items, n_items,
+                           counter, accept_table);
+        break;
+    case 2:
+        hipLaunchKernelGGL(k_fused<2>, dim3(blocks), dim3(kBlock), 0, s, jobs, items, n_items,
+                           counter, accept_table);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t fused_blocks_per_cu(int cls, int *blocks)
+{
+    switch (cls) {
+    case 0: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_fused<0>, kBlock, 0);
+    case 1: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_fused<1>, kBlock, 0);
+    case 2: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_fused<2>, kBlock, 0);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_expand(const ExpandArgs &a, hipStream_t s)

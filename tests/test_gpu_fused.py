@@ -220,7 +220,7 @@ def test_fused_full_slot_8x8_16qam_equals_plain(ctx):
 def test_fused_empty_and_errors(ctx):
     note("fused empty plans and argument errors")
     plan = ctx.plan_create([])
-    assert plan.plan_info() == (0, 1)
+    assert plan.plan_info() == (0, 0)
     plan.plan_launch()
     plan.plan_destroy()
     H = torch.zeros((0, 4, 4), dtype=torch.complex64, device="cuda:0")
