@@ -123,6 +123,26 @@ T *at(mmgap_ctx *ctx, size_t off)
 
 bool pow2_weight(int w) { return w >= 1 && w <= 64 && (w & (w - 1)) == 0; }
 
+int pow2_ceil(int v)
+{
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+// Lanes per instance when several instances share a wavefront: chains rounded
+// up to a power of two, at least 64 / max_per_wave; 0 (one instance per
+// wavefront) when chains > 32 or when the instances of a wavefront would not
+// share one G (64 / lanes must divide inst_per_G; 0 = no such constraint).
+int packed_lanes(int chains, int inst_per_G, int max_per_wave)
+{
+    if (chains > 32) return 0;
+    int per_wave = 64 / pow2_ceil(chains);
+    if (per_wave > max_per_wave) per_wave = max_per_wave;
+    while (inst_per_G > 0 && per_wave > 1 && inst_per_G % per_wave) per_wave >>= 1;
+    return per_wave > 1 ? 64 / per_wave : 0;
+}
+
 int qam_bits(int qam)
 {
     switch (qam) {
@@ -276,6 +296,7 @@ int run_solver(mmgap_ctx *ctx, hipStream_t st, int n_inst, int K, int q, int KT,
     a.key0 = (uint32_t)sched->seed;
     a.key1 = (uint32_t)(sched->seed >> 32);
     a.init_mode = sched->init;
+    a.glanes = packed_lanes(sched->chains, inst_per_G, 64);
     a.chain_E = chainE;
     a.chain_S = chainS;
     prof_mark(ctx, 1, st);
@@ -771,6 +792,7 @@ int mmgap_plan_create(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, int fla
         f.sweeps = jb.sched.sweeps;
         f.init = jb.sched.init;
         f.wpi = jb.sched.chains <= 64 ? 1 : (jb.sched.chains <= 128 ? 2 : 4);
+        f.glanes = packed_lanes(jb.sched.chains, 0, 16);   // an item lies in one subcarrier
         f.ldf = (sh.KT + 31) / 32 * 32;   // 128-byte field rows: no scalar-cache line is shared
 
         if (p.kind == MMGAP_KIND_DET) det_weights(sh.q, f.w);
@@ -793,7 +815,7 @@ int mmgap_plan_create(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, int fla
         ox[j] = lay.take(ni * (size_t)sh.KT);
         oA[j] = p.kind == MMGAP_KIND_VPP ? lay.take(sizeof(double2) * (size_t)p.n_sc * p.n_rx * p.n_rx)
                                          : 0;
-        const int per = 4 / f.wpi;
+        const int per = f.glanes ? 4 * (64 / f.glanes) : 4 / f.wpi;
         for (int sc = 0; sc < p.n_sc; ++sc)
             for (int s0 = 0; s0 < p.n_sym; s0 += per)
                 items.push_back({j, sc, s0, std::min(per, p.n_sym - s0)});

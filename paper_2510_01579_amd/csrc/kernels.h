@@ -57,6 +57,10 @@ struct AnnealArgs {
     int w[kMaxQ];           // spin weights (powers of two)
     uint32_t key0, key1;
     int init_mode;
+    int glanes;             // 0: one instance per wavefront (or several wavefronts per
+                            // instance); else lanes per instance, a power of two in
+                            // [chains, 32]: 64/glanes instances per wavefront share a G
+                            // (64/glanes must divide inst_per_G)
     float *chain_E;         // [n_inst][chains]
     uint32_t *chain_S;      // [n_inst][chains][NW]
 };
@@ -111,6 +115,8 @@ struct FusedJob {
     int n_rows, n_cols;     // H is n_rows x n_cols (DET: n_r x n_t; VPP: n_u x n_tx)
     int n_sym, n_sc;
     int chains, sweeps, init, wpi;
+    int glanes;             // 0, or lanes per instance (power of two in [max(chains, 4), 32])
+                            // with 64/glanes instances of the item per wavefront
     int ldf;                // row stride of f in floats: a multiple of 32 (128 bytes), >= KT
     int w[kMaxQ];
     uint32_t key0, key1;

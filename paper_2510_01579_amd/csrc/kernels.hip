@@ -123,7 +123,7 @@ __device__ __forceinline__ void wave_sync_lds()
 //   MMSE (Cg + sigma^2 I)^-1 F by LDL^H, sliced to the nearest PAM level.
 // Writes G (ld x ld, zero padded) to Gout and, for symbols sym0..sym0+ns-1,
 // the field rows to fout, the fallback levels to xout (if non-null) and ||y||^2
-// to ynorm (if non-null).  ns <= 64.
+// to ynorm (if non-null).  nt <= NT, nr <= 64, ns <= NS.
 template <int NT, int NS>
 struct DetSharedT {
     float2 Hs[64 * NT];
@@ -441,9 +441,25 @@ __device__ void build_vpp_sc(const float2 *H, const float2 *u, int n, int ntx, i
     }
 }
 
+// Field entry f_k of this lane's instance: through the scalar cache when the
+// instance is wave-uniform, else a vector load whose address is re-derived at
+// each use (so that the compiler keeps no row of f in registers).
+template <bool PACKED>
+__device__ __forceinline__ float load_field(const float *fi, int k)
+{
+    if constexpr (PACKED) {
+        const float *p = fi;
+        asm volatile("" : "+v"(p));
+        return p[k];
+    } else {
+        return opaque(fi)[k];
+    }
+}
+
 // ---------------------------------------------------------------------------
-// The anneal of one lane.  G and f of the instance are wave-uniform and read
-// through the scalar cache one row ahead of use.  Per lane the state is the
+// The anneal of one lane.  G of the instance is wave-uniform and read through
+// the scalar cache one row ahead of use, as is f unless several instances share
+// the wavefront (PACKED: f per lane, by vector loads).  Per lane the state is the
 // flip step of every spin, d_i = -2 w_b s_i (+-2w_b as float) -- or one bit per
 // spin (set = spin -1) for large problems, to keep enough wavefronts resident --
 // and the levels x[KT]; the local field of a dimension is recomputed from the
@@ -456,7 +472,7 @@ __device__ void build_vpp_sc(const float2 *H, const float2 *u, int n, int ntx, i
 //   and the flip is accepted iff the 16-bit draw m < T[index] (T in LDS).
 // Returns the final energy sum_k x_k (g_k - f_k); `bits` receives the final
 // spins (bit set = spin -1).
-template <int KT, int Q>
+template <int KT, int Q, bool PACKED = false>
 __device__ __forceinline__ float anneal_lane(const float *Gi, const float *fi,
                                              const signed char *xfb_i, const float *beta2,
                                              const uint32_t *T, int sweeps, const int (&wts)[4],
@@ -533,14 +549,15 @@ __device__ __forceinline__ float anneal_lane(const float *Gi, const float *fi,
         uint32_t r[4] = {0u, 0u, 0u, 0u};
         // rows of G in scalar registers; with KT <= 16 the next row is loaded
         // one dimension ahead, with KT = 32 two rows do not fit the SGPR file
-        constexpr bool kPrefetch = KT <= 16;
+        // (nor, packed, with KT = 16: the per-lane field loads need the room)
+        constexpr bool kPrefetch = PACKED ? KT <= 8 : KT <= 16;
         float grow[KT];
         float fk = 0.0f;
         if (kPrefetch) {
             cfloat *base = opaque(Gi);
 #pragma unroll
             for (int l = 0; l < KT; ++l) grow[l] = base[l];
-            fk = opaque(fi)[0];
+            fk = load_field<PACKED>(fi, 0);
         }
 #pragma unroll
         for (int k = 0; k < KT; ++k) {
@@ -548,7 +565,7 @@ __device__ __forceinline__ float anneal_lane(const float *Gi, const float *fi,
                 cfloat *base = opaque(Gi);
 #pragma unroll
                 for (int l = 0; l < KT; ++l) grow[l] = base[k * KT + l];
-                fk = opaque(fi)[k];
+                fk = load_field<PACKED>(fi, k);
             }
             // local field of dimension k from the current levels
             float g = -fk;
@@ -560,7 +577,7 @@ __device__ __forceinline__ float anneal_lane(const float *Gi, const float *fi,
                 cfloat *base = opaque(Gi);
 #pragma unroll
                 for (int l = 0; l < KT; ++l) grow[l] = base[(k + 1) * KT + l];
-                fk = opaque(fi)[k + 1];
+                fk = load_field<PACKED>(fi, k + 1);
             }
 #pragma unroll
             for (int b = 0; b < Q; ++b) {
@@ -788,14 +805,17 @@ __global__ void __launch_bounds__(kBlock) k_vpp_build(VppBuildArgs a)
                  a.unorm ? a.unorm + o : nullptr, sh);
 }
 
-// One wavefront = 64 chains of one instance; chains >= 64 use several
-// wavefronts.  Writes every chain's final energy and spin words.
-template <int KT, int Q>
+// One wavefront = 64 chains of one instance; chains > 64 use several
+// wavefronts.  PACKED: one wavefront = 64 / glanes instances of glanes lanes
+// each (glanes a power of two >= chains, <= 32), all sharing one G -- the host
+// guarantees that 64 / glanes divides inst_per_G.  Writes every chain's final
+// energy and spin words.
+template <int KT, int Q, bool PACKED>
 __global__ void __launch_bounds__(kBlock)
 k_anneal(const float *__restrict__ G, int inst_per_G, const float *__restrict__ f,
          const signed char *__restrict__ x_fb, const float *__restrict__ beta2,
          const uint32_t *__restrict__ accept_table, int sweeps, int chains, int n_inst, int w0,
-         int w1, int w2, int w3, uint32_t key0, uint32_t key1, int init_mode,
+         int w1, int w2, int w3, uint32_t key0, uint32_t key1, int init_mode, int glanes,
          float *__restrict__ chain_E, uint32_t *__restrict__ chain_S)
 {
     constexpr int NW = (KT * Q + 31) / 32;
@@ -805,19 +825,34 @@ k_anneal(const float *__restrict__ G, int inst_per_G, const float *__restrict__ 
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int wpi = (chains + 63) >> 6;
     const int gw = blockIdx.x * kWavesPerBlock + wave;
-    const int inst = gw / wpi;
-    if (inst >= n_inst) return;
-    const int ch = (gw - inst * wpi) * 64 + lane;
-    const float *Gi = G + (size_t)(inst / inst_per_G) * (KT * KT);
+    int inst, ch, inst0;
+    bool valid = true;
+    if constexpr (PACKED) {
+        const int per_wave = 64 / glanes;
+        inst0 = gw * per_wave;
+        if (inst0 >= n_inst) return;
+        inst = inst0 + lane / glanes;
+        ch = lane % glanes;
+        if (inst >= n_inst) {               // tail of the last wavefront: any valid data
+            valid = false;
+            inst = inst0;
+        }
+    } else {
+        const int wpi = (chains + 63) >> 6;
+        inst = gw / wpi;
+        if (inst >= n_inst) return;
+        inst0 = inst;
+        ch = (gw - inst * wpi) * 64 + lane;
+    }
+    const float *Gi = G + (size_t)(inst0 / inst_per_G) * (KT * KT);
     const float *fi = f + (size_t)inst * KT;
     const signed char *xi = x_fb ? x_fb + (size_t)inst * KT : nullptr;
     const int wts[4] = {w0, w1, w2, w3};
     uint32_t bits[NW];
-    const float E = anneal_lane<KT, Q>(Gi, fi, xi, beta2, T, sweeps, wts, key0, key1, init_mode,
-                                       (uint32_t)ch, (uint32_t)inst, bits);
-    if (ch < chains) {
+    const float E = anneal_lane<KT, Q, PACKED>(Gi, fi, xi, beta2, T, sweeps, wts, key0, key1,
+                                               init_mode, (uint32_t)ch, (uint32_t)inst, bits);
+    if (valid && ch < chains) {
         const size_t o = (size_t)inst * chains + ch;
         chain_E[o] = E;
 #pragma unroll
@@ -896,7 +931,8 @@ __global__ void __launch_bounds__(kBlock) k_select(SelectArgs a)
 
 // ---------------------------------------------------------------------------
 // Fused path: persistent launches.  Each workgroup takes work items from a
-// device counter; an item is (job, subcarrier, up to 4 symbols).  For its item
+// device counter; an item is (job, subcarrier, a range of symbols: one per
+// 64-chain wavefront, or 64 / glanes per wavefront when packed).  For its item
 // the workgroup builds the subcarrier's couplings (into the job's
 // per-subcarrier slot; several items of one subcarrier write identical values)
 // and the symbols' fields and fallbacks; then each wavefront anneals 64 chains
@@ -912,7 +948,7 @@ __global__ void __launch_bounds__(kBlock) k_select(SelectArgs a)
 //   class 0: KT = 8 (any q) and KT = 16 with q = 1   <= 64 VGPRs, 8 waves/SIMD
 //   class 1: KT = 16, q = 2                          <= 80 VGPRs, 6 waves/SIMD
 //   class 2: KT = 16, q = 3 and KT = 32              <= 128 VGPRs, 4 waves/SIMD
-constexpr int kFusedItemSyms = 4;   // symbols per work item at most
+constexpr int kFusedBuildSyms = 16;   // symbols per build pass (an item may take several)
 
 // State shared by every class: threshold table, per-wavefront selection and
 // decode scratch, the current item.  At namespace scope so that the
@@ -930,7 +966,7 @@ __shared__ FusedCommon g_fc;
 // Build scratch per class: detection with n_t <= NTD, VPP with n_u <= NUV.
 template <int NTD, int NUV>
 union FusedBuildShared {
-    DetSharedT<NTD, kFusedItemSyms> det;
+    DetSharedT<NTD, kFusedBuildSyms> det;
     VppSharedT<NUV> vpp;
 };
 template <int CLS> struct FusedClassTraits;
@@ -978,10 +1014,14 @@ __device__ __forceinline__ double rfld(double v)
     return __longlong_as_double((long long)((hi << 32) | lo));
 }
 
-// Anneal, select and decode of one work item by variant (KT, Q).
-template <int KT, int Q>
+// Anneal, select and decode of one work item by variant (KT, Q).  Unpacked:
+// wavefront w anneals 64 chains of instance w / wpi.  PACKED: wavefront w
+// anneals instances w P .. w P + P - 1 of the item, glanes = 64 / P lanes each,
+// reduces each group of lanes to its best chain and decodes its instances one
+// after another.
+template <int KT, int Q, bool PACKED>
 __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in, int sc_in,
-                                                  int sym0_in, int ns_in)
+                                             int sym0_in, int ns_in)
 {
     constexpr int NW = (KT * Q + 31) / 32;
     // every descriptor field as a wave-uniform (scalar) value
@@ -1008,19 +1048,73 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
 
     const int wave = rfl(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
+    const float *Gi = Gbase + (size_t)sc * (KT * KT);
+    if constexpr (PACKED) {
+        const int gl = rfl(jp->glanes);
+        const int lg = __builtin_ctz((unsigned)gl);
+        const int per_wave = 64 >> lg;
+        const int first = wave * per_wave;    // first instance of this wavefront in the item
+        if (first >= ns) return;              // whole wavefront idle (no barrier follows)
+        const int cnt = min(per_wave, ns - first);
+        const int grp = lane >> lg;
+        const int chn = lane & (gl - 1);
+        const bool valid = grp < cnt;
+        const int r = first + (valid ? grp : 0);
+        const int n = sc * n_sym + sym0 + r;
+        const float *fi = fbase + (size_t)n * ldf;
+        const signed char *xi = xbase + (size_t)n * KT;
+        uint32_t bits[NW];
+        const float E = anneal_lane<KT, Q, true>(Gi, fi, xi, beta2, sh.T, sweeps, w, key0, key1,
+                                                 init, (uint32_t)chn, (uint32_t)n, bits);
+        uint64_t key = ~0ull;
+        if (valid && chn < chains) key = ((uint64_t)energy_key(E) << 32) | (uint32_t)chn;
+        for (int off = gl >> 1; off >= 1; off >>= 1) {   // minimum within each group
+            const uint32_t lo = __shfl_xor((uint32_t)key, off, 64);
+            const uint32_t hi = __shfl_xor((uint32_t)(key >> 32), off, 64);
+            const uint64_t o = ((uint64_t)hi << 32) | lo;
+            key = o < key ? o : key;
+        }
+        for (int g = 0; g < cnt; ++g) {
+            const int bch = rfl((int)__shfl((uint32_t)key, g << lg, 64));
+            const int wl = (g << lg) + bch;            // the group's winning lane
+            if (lane == wl) {
+                for (int ww = 0; ww < NW; ++ww) sh.lvs[wave][ww] = (int)bits[ww];
+            }
+            wave_sync_lds();
+            uint32_t S[NW];
+            for (int ww = 0; ww < NW; ++ww) S[ww] = (uint32_t)sh.lvs[wave][ww];
+            wave_sync_lds();
+            const float Ebest = __shfl(E, wl, 64);
+            const int ng = sc * n_sym + sym0 + first + g;
+            const float *fg = fbase + (size_t)ng * ldf;
+            const signed char *xg = xbase + (size_t)ng * KT;
+            const float Efb = fallback_energy(Gi, KT, K, fg, xg, sh.terms[wave], lane);
+            const bool use_fb = energy_less(Efb, Ebest);
+            winning_levels(use_fb, xg, S, K, Q, w, sh.lvs[wave], lane);
+            if (kind == 0) {
+                decode_det(sh.lvs[wave], ng, sc, sym0 + first + g, n_sym, n_rows, n_cols, Q, c,
+                           H, y, (unsigned char *)out0, (float *)out1, lane);
+            } else {
+                decode_vpp(sh.lvs[wave], ng, sc, sym0 + first + g, n_sym, n_rows, n_cols, tau,
+                           Abase + (size_t)sc * n_rows * n_rows, H, y, (signed char *)out0,
+                           (float2 *)out1, (float *)out2, sh.zsh[wave], lane);
+            }
+            wave_sync_lds();
+        }
+        return;
+    }
     const int r0 = wave / wpi;                 // instance of this wavefront within the item
     const int chunk = wave - r0 * wpi;
     const bool active = r0 < ns;               // uniform over the wavefront
     const int n = sc * n_sym + sym0 + (active ? r0 : 0);
     const int ch = chunk * 64 + lane;
-    const float *Gi = Gbase + (size_t)sc * (KT * KT);
     const float *fi = fbase + (size_t)n * ldf;
     const signed char *xi = xbase + (size_t)n * KT;
     uint32_t bits[NW];
     float E = 0.0f;
     if (active) {
-        E = anneal_lane<KT, Q>(Gi, fi, xi, beta2, sh.T, sweeps, w, key0, key1, init,
-                               (uint32_t)ch, (uint32_t)n, bits);
+        E = anneal_lane<KT, Q, false>(Gi, fi, xi, beta2, sh.T, sweeps, w, key0, key1, init,
+                                      (uint32_t)ch, (uint32_t)n, bits);
         uint64_t key = ~0ull;
         if (ch < chains) key = ((uint64_t)energy_key(E) << 32) | (uint32_t)ch;
         key = wave_min_u64(key);
@@ -1059,29 +1153,36 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
     }
 }
 
+#define MMGAP_FUSED_CALL(kt, qq)                                             \
+    do {                                                                     \
+        if (packed) fused_anneal<kt, qq, true>(jobs, it.job, it.sc, it.sym0, it.ns);  \
+        else fused_anneal<kt, qq, false>(jobs, it.job, it.sc, it.sym0, it.ns);        \
+    } while (0)
 template <int CLS>
-__device__ __forceinline__ void fused_dispatch(int variant, const FusedJob *jobs, const FusedItem &it)
+__device__ __forceinline__ void fused_dispatch(int variant, bool packed, const FusedJob *jobs,
+                                               const FusedItem &it)
 {
     if constexpr (CLS == 0) {
         switch (variant) {
-        case 0: fused_anneal<8, 1>(jobs, it.job, it.sc, it.sym0, it.ns); break;
-        case 1: fused_anneal<8, 2>(jobs, it.job, it.sc, it.sym0, it.ns); break;
-        case 2: fused_anneal<8, 3>(jobs, it.job, it.sc, it.sym0, it.ns); break;
-        case 3: fused_anneal<16, 1>(jobs, it.job, it.sc, it.sym0, it.ns); break;
+        case 0: MMGAP_FUSED_CALL(8, 1); break;
+        case 1: MMGAP_FUSED_CALL(8, 2); break;
+        case 2: MMGAP_FUSED_CALL(8, 3); break;
+        case 3: MMGAP_FUSED_CALL(16, 1); break;
         default: break;
         }
     } else if constexpr (CLS == 1) {
-        if (variant == 4) fused_anneal<16, 2>(jobs, it.job, it.sc, it.sym0, it.ns);
+        if (variant == 4) MMGAP_FUSED_CALL(16, 2);
     } else {
         switch (variant) {
-        case 5: fused_anneal<16, 3>(jobs, it.job, it.sc, it.sym0, it.ns); break;
-        case 6: fused_anneal<32, 1>(jobs, it.job, it.sc, it.sym0, it.ns); break;
-        case 7: fused_anneal<32, 2>(jobs, it.job, it.sc, it.sym0, it.ns); break;
-        case 8: fused_anneal<32, 3>(jobs, it.job, it.sc, it.sym0, it.ns); break;
+        case 5: MMGAP_FUSED_CALL(16, 3); break;
+        case 6: MMGAP_FUSED_CALL(32, 1); break;
+        case 7: MMGAP_FUSED_CALL(32, 2); break;
+        case 8: MMGAP_FUSED_CALL(32, 3); break;
         default: break;
         }
     }
 }
+#undef MMGAP_FUSED_CALL
 
 template <int CLS>
 __global__ void __launch_bounds__(kBlock)
@@ -1101,16 +1202,20 @@ k_fused(const FusedJob *__restrict__ jobs, const FusedItem *__restrict__ items, 
         const FusedItem it = items[item];
         const FusedJob &jb = jobs[it.job];
         float *Gs = jb.G + (size_t)it.sc * jb.KT * jb.KT;
-        float *fs = jb.f + ((size_t)it.sc * jb.n_sym + it.sym0) * jb.ldf;
-        signed char *xs = jb.x_fb + ((size_t)it.sc * jb.n_sym + it.sym0) * jb.KT;
-        if (jb.kind == 0) {
-            build_det_sc(jb.H, jb.y, jb.n_rows, jb.n_cols, jb.n_sym, it.sc, it.sym0, it.ns, jb.KT,
-                         jb.ldf, (1 << jb.Q) - 1, jb.c, jb.c2, jb.noise_var, Gs, fs, xs, nullptr,
-                         bs.det);
-        } else {
-            build_vpp_sc(jb.H, jb.y, jb.n_rows, jb.n_cols, jb.n_sym, it.sc, it.sym0, it.ns, jb.KT,
-                         jb.ldf, jb.tau, Gs, fs, xs,
-                         jb.Ainv + (size_t)it.sc * jb.n_rows * jb.n_rows, nullptr, bs.vpp);
+        for (int s0 = 0; s0 < it.ns; s0 += kFusedBuildSyms) {
+            const int sym = it.sym0 + s0, cnt = min(kFusedBuildSyms, it.ns - s0);
+            float *fs = jb.f + ((size_t)it.sc * jb.n_sym + sym) * jb.ldf;
+            signed char *xs = jb.x_fb + ((size_t)it.sc * jb.n_sym + sym) * jb.KT;
+            if (s0 > 0) __syncthreads();      // the previous pass is done with the scratch
+            if (jb.kind == 0) {
+                build_det_sc(jb.H, jb.y, jb.n_rows, jb.n_cols, jb.n_sym, it.sc, sym, cnt, jb.KT,
+                             jb.ldf, (1 << jb.Q) - 1, jb.c, jb.c2, jb.noise_var, Gs, fs, xs,
+                             nullptr, bs.det);
+            } else {
+                build_vpp_sc(jb.H, jb.y, jb.n_rows, jb.n_cols, jb.n_sym, it.sc, sym, cnt, jb.KT,
+                             jb.ldf, jb.tau, Gs, fs, xs,
+                             jb.Ainv + (size_t)it.sc * jb.n_rows * jb.n_rows, nullptr, bs.vpp);
+            }
         }
         // The couplings and fields were written with vector stores by this
         // workgroup and are read back through the scalar cache, which vector
@@ -1127,7 +1232,7 @@ k_fused(const FusedJob *__restrict__ jobs, const FusedItem *__restrict__ items, 
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        fused_dispatch<CLS>(jb.variant, jobs, it);
+        fused_dispatch<CLS>(jb.variant, jb.glanes > 0, jobs, it);
     }
 }
 
@@ -1208,15 +1313,25 @@ int grid_for(size_t total)
 template <int KT, int Q>
 hipError_t launch_anneal_t(const AnnealArgs &a, hipStream_t s)
 {
-    const int wpi = (a.chains + 63) / 64;
-    const size_t waves = (size_t)a.n_inst * wpi;
+    const int per_wave = a.glanes > 0 ? 64 / a.glanes : 1;
+    if (a.glanes > 0 && (a.glanes > 32 || (a.glanes & (a.glanes - 1)) || a.chains > a.glanes ||
+                         a.inst_per_G % per_wave != 0))
+        return hipErrorInvalidValue;
+    const size_t waves = a.glanes > 0 ? ((size_t)a.n_inst + per_wave - 1) / per_wave
+                                      : (size_t)a.n_inst * ((a.chains + 63) / 64);
     const size_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
     if (blocks == 0) return hipSuccess;
     if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_anneal<KT, Q>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a.G,
-                       a.inst_per_G, a.f, a.x_fb, a.beta2, a.accept_table, a.sweeps, a.chains,
-                       a.n_inst, a.w[0], a.w[1], a.w[2], a.w[3], a.key0, a.key1, a.init_mode,
-                       a.chain_E, a.chain_S);
+    if (a.glanes > 0)
+        hipLaunchKernelGGL((k_anneal<KT, Q, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                           a.G, a.inst_per_G, a.f, a.x_fb, a.beta2, a.accept_table, a.sweeps,
+                           a.chains, a.n_inst, a.w[0], a.w[1], a.w[2], a.w[3], a.key0, a.key1,
+                           a.init_mode, a.glanes, a.chain_E, a.chain_S);
+    else
+        hipLaunchKernelGGL((k_anneal<KT, Q, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                           a.G, a.inst_per_G, a.f, a.x_fb, a.beta2, a.accept_table, a.sweeps,
+                           a.chains, a.n_inst, a.w[0], a.w[1], a.w[2], a.w[3], a.key0, a.key1,
+                           a.init_mode, 0, a.chain_E, a.chain_S);
     return hipGetLastError();
 }
 

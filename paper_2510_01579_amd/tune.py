@@ -1,0 +1,157 @@
+"""Offline schedule tuner: per job class, the cheapest anneal schedule (chains,
+sweeps, start) whose quality stays within a tolerance of the class's reference
+schedule at every SNR of the class's grid.
+
+Quality is the symbol error rate against the transmitted symbols (detection)
+or the mean transmit energy ||W (u + tau v)||^2 (VPP), measured on synthetic
+i.i.d. Rayleigh slots through the library itself (common random numbers: every
+candidate sees the same channels, symbols and noise).  Cost is the lane-time of
+the anneal: lanes per instance (the chain count, rounded up to a power of two
+when instances share a wavefront, or to whole wavefronts above 32) x sweeps x
+attempts per sweep x operations per attempt.
+
+    python -m paper_2510_01579_amd.tune --out paper_2510_01579_amd/tuned_schedules.json
+
+Needs a GPU.  The table it writes is read by ``tuned_schedule`` in the package.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# (kind, rows, cols, qam): reference schedule and SNR grid of each class
+CLASSES = {
+    "det-4x4-4": dict(ref=(32, 100, 0), snr=[0.0, 5.0, 10.0, 15.0]),
+    "det-8x8-4": dict(ref=(64, 200, 0), snr=[0.0, 5.0, 10.0, 15.0]),
+    "det-8x8-16": dict(ref=(64, 200, 0), snr=[5.0, 10.0, 15.0, 20.0, 25.0]),
+    "det-8x8-64": dict(ref=(64, 200, 1), snr=[15.0, 20.0, 25.0, 30.0]),
+    "det-16x16-4": dict(ref=(128, 400, 0), snr=[0.0, 5.0, 10.0, 15.0]),
+    "det-16x16-16": dict(ref=(128, 400, 0), snr=[5.0, 10.0, 15.0, 20.0, 25.0]),
+    "det-16x16-64": dict(ref=(128, 400, 1), snr=[15.0, 20.0, 25.0, 30.0]),
+    "vpp-8x8-4": dict(ref=(64, 200, 0), snr=[None]),
+    "vpp-8x8-16": dict(ref=(64, 200, 0), snr=[None]),
+    "vpp-8x8-64": dict(ref=(64, 200, 0), snr=[None]),
+    "vpp-16x16-4": dict(ref=(64, 200, 0), snr=[None]),
+    "vpp-16x16-16": dict(ref=(64, 200, 0), snr=[None]),
+    "vpp-16x16-64": dict(ref=(64, 200, 0), snr=[None]),
+}
+CHAINS = (4, 8, 16, 32, 64, 128)
+SWEEPS = (12, 25, 50, 100, 200, 400)
+TOLERANCE = 0.05
+
+
+def parse_class(name):
+    kind, size, qam = name.split("-")
+    rows, cols = (int(v) for v in size.split("x"))
+    return kind, rows, cols, int(qam)
+
+
+def lanes_per_instance(chains: int) -> int:
+    """Lanes an instance occupies in the fused path: up to 32 chains share a
+    wavefront with other instances of the subcarrier (a power of two >= 4
+    lanes each), more take whole wavefronts."""
+    if chains <= 32:
+        return max(4, 1 << math.ceil(math.log2(chains)))
+    return 64 * math.ceil(chains / 64)
+
+
+def cost(name, chains, sweeps) -> float:
+    kind, rows, cols, qam = parse_class(name)
+    K = 2 * (cols if kind == "det" else rows)
+    q = {4: 1, 16: 2, 64: 3}[qam] if kind == "det" else 2
+    KT = 8 if K <= 8 else (16 if K <= 16 else 32)
+    return lanes_per_instance(chains) * sweeps * KT * q * (18.5 + KT / q)
+
+
+def measure(ctx, name, snr, schedules, n_sc, n_sym, seed):
+    """Quality of each (chains, sweeps, init) on one synthetic slot."""
+    import torch
+    from workload import synth as W
+    kind, rows, cols, qam = parse_class(name)
+    dev = torch.device("cuda", ctx.device)
+    out = {}
+    if kind == "det":
+        d = W.det_slot(seed, rows, cols, qam, n_sc, n_sym, snr)
+        H, y = torch.from_numpy(d.H).to(dev), torch.from_numpy(d.y).to(dev)
+        truth = torch.from_numpy(d.sym.reshape(n_sc * n_sym, cols)).to(dev)
+        for (C, S, init) in schedules:
+            beta2 = W.linear_beta2(S, *W.det_beta_range(qam, rows, d.noise_var))
+            sym, _ = ctx.detect(H, y, qam, d.noise_var, C, S, beta2, W.job_seed(seed),
+                                init=init, metric=False)
+            out[(C, S, init)] = float((sym != truth).float().mean().item())
+    else:
+        s = W.vpp_slot(seed, rows, cols, qam, n_sc, n_sym)
+        H, u = torch.from_numpy(s.H).to(dev), torch.from_numpy(s.u).to(dev)
+        for (C, S, init) in schedules:
+            beta2 = W.linear_beta2(S, *W.vpp_beta_range(qam, cols))
+            _, _, g = ctx.vpp_precode(H, u, qam, C, S, beta2, W.job_seed(seed), init=init,
+                                      want_x=False)
+            out[(C, S, init)] = float(g.double().mean().item())
+    return out
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--out", default=os.path.join(os.path.dirname(__file__),
+                                                  "tuned_schedules.json"))
+    ap.add_argument("--classes", nargs="*", default=sorted(CLASSES))
+    ap.add_argument("--n-sc", type=int, default=3276)
+    ap.add_argument("--n-sym", type=int, default=12)
+    ap.add_argument("--seed", type=int, default=7000)
+    args = ap.parse_args(argv)
+
+    import paper_2510_01579_amd as M
+    ctx = M.Context(0)
+    table = {"tolerance": TOLERANCE, "slot": [args.n_sc, args.n_sym], "classes": {}}
+    if os.path.exists(args.out):
+        with open(args.out) as fh:
+            old = json.load(fh)
+        if old.get("slot") == table["slot"]:
+            table["classes"].update(old.get("classes", {}))
+    for name in args.classes:
+        spec = CLASSES[name]
+        ref = tuple(spec["ref"])
+        cands = sorted({(C, S, i) for C in CHAINS for S in SWEEPS for i in (0, 1)
+                        if cost(name, C, S) <= cost(name, ref[0], ref[1])} | {ref},
+                       key=lambda s: cost(name, s[0], s[1]))
+        t0 = time.time()
+        per_snr = []
+        for k, snr in enumerate(spec["snr"]):
+            q = measure(ctx, name, snr, cands, args.n_sc, args.n_sym, args.seed + 17 * k)
+            per_snr.append({"snr_db": snr, "ref": q[ref],
+                            "cands": {f"{C}x{S}/{i}": v for (C, S, i), v in q.items()}})
+        passing = []
+        for c in cands:
+            key = f"{c[0]}x{c[1]}/{c[2]}"
+            ok = all(r["cands"][key] <= (1 + TOLERANCE) * r["ref"] + 2e-5 for r in per_snr)
+            if ok:
+                passing.append(c)
+        best = min(passing, key=lambda s: (cost(name, s[0], s[1]), s[0], s[1]))
+        table["classes"][name] = {
+            "reference": {"chains": ref[0], "sweeps": ref[1], "init": ref[2]},
+            "tuned": {"chains": best[0], "sweeps": best[1], "init": best[2]},
+            "cost_ratio": cost(name, ref[0], ref[1]) / cost(name, best[0], best[1]),
+            "quality": "ser" if name.startswith("det") else "mean_gamma",
+            "per_snr": per_snr,
+        }
+        print(f"{name}: ref {ref} -> tuned {best}, cost ratio "
+              f"{table['classes'][name]['cost_ratio']:.2f} ({time.time() - t0:.1f} s)",
+              flush=True)
+        with open(args.out, "w") as fh:
+            json.dump(table, fh, indent=1)
+    ctx.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -59,6 +59,11 @@ MIX = [
     ("det", 4, 4, 64, 6, 3, 32, 20, 0),      # KT 8,  q 3
     ("det", 8, 8, 4, 5, 4, 64, 12, 0),       # KT 16, q 1
     ("vpp", 16, 16, 16, 3, 2, 64, 10, 0),    # KT 32, q 2
+    # several instances per wavefront: 16, 8 and 1 chains (4, 8 and 16 per wavefront)
+    ("det", 8, 8, 16, 7, 12, 16, 20, 0),     # KT 16, q 2
+    ("vpp", 8, 8, 64, 5, 9, 8, 15, 0),       # KT 16, q 2
+    ("det", 16, 16, 16, 3, 14, 16, 8, 1),    # KT 32, q 2
+    ("det", 4, 4, 16, 6, 33, 1, 10, 0),      # KT 8, q 2, ragged 33 = 2 x 16 + 1
 ]
 
 
@@ -128,8 +133,12 @@ def test_fused_mixed_batch_equals_single_calls_on_every_replay(ctx, mix):
     jobs = [job_of(ctx, inp) for inp in inputs]
     plan = ctx.plan_create(jobs, graph=True)
     n_items, blocks = plan.plan_info()
-    assert n_items == sum(s[4] * -(-s[5] // (4 // (1 if s[6] <= 64 else 2 if s[6] <= 128 else 4)))
-                          for s in MIX)
+    def per_item(chains):
+        if chains <= 32:
+            lanes = max(4, 1 << (chains - 1).bit_length())
+            return 4 * (64 // lanes)
+        return 4 // (1 if chains <= 64 else 2 if chains <= 128 else 4)
+    assert n_items == sum(s[4] * -(-s[5] // per_item(s[6])) for s in MIX)
     assert 1 <= blocks <= n_items
     for rep in range(3):
         clear(jobs)

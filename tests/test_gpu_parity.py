@@ -69,6 +69,12 @@ SOLVE_CASES = [
     (1, 4, [8, 4, 2, 1], 1, 5, 3, 1, False, 0),
     (32, 1, [1], 64, 10, 7, 7, True, 1),
     (8, 4, [8, 4, 2, 1], 192, 6, 5, 5, False, 0),
+    # several instances per wavefront (chains <= 32, 64/lanes divides inst_per_G)
+    (16, 2, [2, 1], 16, 20, 37, 4, True, 0),
+    (8, 3, [4, 2, 1], 8, 15, 50, 8, True, 1),
+    (32, 2, [1, 1], 32, 6, 12, 2, True, 0),
+    (4, 2, [2, 1], 1, 10, 130, 64, False, 0),
+    (12, 1, [1], 5, 12, 27, 24, True, 0),
 ]
 
 
@@ -149,6 +155,8 @@ DET_CASES = [
     (16, 16, 64, 5, 2, 25.0, 128, 12),
     (8, 8, 64, 11, 2, 25.0, 64, 20),
     (16, 16, 4, 6, 3, 8.0, 64, 15),
+    (8, 8, 16, 9, 12, 15.0, 16, 30),     # four instances per wavefront
+    (4, 4, 64, 10, 8, 25.0, 8, 25),      # eight per wavefront
 ]
 
 
@@ -171,6 +179,7 @@ VPP_CASES = [
     (8, 8, 16, 13, 3, 64, 30),
     (16, 16, 16, 5, 2, 128, 10),
     (4, 6, 64, 7, 2, 32, 25),
+    (8, 8, 16, 7, 4, 8, 25),             # four instances per wavefront
 ]
 
 
