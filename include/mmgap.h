@@ -230,6 +230,47 @@ int mmgap_plan_info(const mmgap_plan *plan, int *n_items, int *blocks);
 int mmgap_plan_destroy(mmgap_plan *plan);
 
 /*
+ * Serving (continuous batching).  A context may run one server: a native
+ * thread that admits submitted jobs (mmgap_job, as for plans) in arrival
+ * order while room in its HBM arena and a free in-flight slot allow, launches
+ * each admitted group of jobs as one batch of the persistent fused kernels on
+ * its own stream, so that batches overlap on the device, and observes their
+ * completion.  Jobs submitted while others run are admitted as soon as slots
+ * and memory free up.  Every job's outputs equal those of the single-job entry
+ * points (the Philox streams do not depend on batching).  Inputs and outputs
+ * stay on the device; the server keeps the job's pointers until the job is
+ * reported done, and copies its schedule.
+ *
+ * mmgap_server_start -- start the server: max_inflight concurrent batches
+ *   (1..8; each has its own stream), arena_bytes of HBM for the jobs' scratch
+ *   (0 = 1 GiB), taken from the context's budget (MMGAP_ENOMEM if it does not
+ *   fit), max_batch_jobs jobs per batch at most (0 = 64).  MMGAP_EBUSY if a
+ *   server is running.
+ * mmgap_server_submit -- queue one job; *job_id receives its id (> 0).  Work
+ *   already enqueued on `stream` (e.g. the copies that produced H and y) is
+ *   waited for before the job starts.  MMGAP_ENOMEM if the job could never fit
+ *   the arena, MMGAP_EBUSY if 4096 jobs are waiting, and the argument errors
+ *   of mmgap_plan_create.
+ * mmgap_server_poll -- *done = 1 once the job's outputs are complete, with
+ *   *latency_us (nullable) = microseconds from its submission to the moment
+ *   the server saw it complete; a job reported done is forgotten (a later poll
+ *   of its id is MMGAP_EINVAL).  Returns the job's status (MMGAP_EDEVICE if its
+ *   batch failed).
+ * mmgap_server_drain -- wait until every submitted job is complete.
+ * mmgap_server_stop -- drain, stop the thread, free the arena and streams
+ *   (also done by mmgap_destroy).
+ * Like every call on a context, submit/poll/drain/stop must not be made from
+ * two host threads at once; the server's own thread uses none of the
+ * context's other state.
+ */
+int mmgap_server_start(mmgap_ctx *ctx, int max_inflight, size_t arena_bytes, int max_batch_jobs);
+int mmgap_server_submit(mmgap_ctx *ctx, const mmgap_job *job, void *stream,
+                        unsigned long long *job_id);
+int mmgap_server_poll(mmgap_ctx *ctx, unsigned long long job_id, int *done, double *latency_us);
+int mmgap_server_drain(mmgap_ctx *ctx);
+int mmgap_server_stop(mmgap_ctx *ctx);
+
+/*
  * Tracing.  mmgap_set_profiling(ctx, 1) (re)starts recording: every later
  * compute call records HIP events on its stream around its stages, keeping the
  * last 256 calls.  mmgap_last_profile waits for those events and writes, oldest

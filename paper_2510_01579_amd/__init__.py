@@ -11,7 +11,9 @@ Entry points (same names as the C ABI, without the ``mmgap_`` prefix):
 ``build_ising``, ``solve``, ``detect``, ``vpp_precode``; ``Context`` owns a
 library context (device, scratch, HBM budget); ``Context.plan_create`` returns a
 ``Plan`` (``plan_launch``, ``plan_info``, ``plan_destroy``) that runs a batch of
-mixed jobs in one persistent launch.
+mixed jobs in one persistent launch; ``Context.server_start`` runs the native
+serving loop (``server_submit``, ``server_poll``, ``server_drain``,
+``server_stop``) that admits jobs as they arrive.
 """
 from __future__ import annotations
 
@@ -34,7 +36,8 @@ STATUS = {0: "MMGAP_OK", -1: "MMGAP_EINVAL", -2: "MMGAP_ENOMEM", -3: "MMGAP_EDEV
 EXPORTS = ("mmgap_create", "mmgap_destroy", "mmgap_last_error", "mmgap_build_ising",
            "mmgap_solve", "mmgap_detect", "mmgap_vpp_precode", "mmgap_set_profiling",
            "mmgap_last_profile", "mmgap_plan_create", "mmgap_plan_launch", "mmgap_plan_info",
-           "mmgap_plan_destroy")
+           "mmgap_plan_destroy", "mmgap_server_start", "mmgap_server_submit",
+           "mmgap_server_poll", "mmgap_server_drain", "mmgap_server_stop")
 
 PLAN_GRAPH = 1
 
@@ -93,6 +96,13 @@ def lib() -> ctypes.CDLL:
             L.mmgap_plan_launch.argtypes = [vp, vp]
             L.mmgap_plan_info.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i)]
             L.mmgap_plan_destroy.argtypes = [vp]
+            L.mmgap_server_start.argtypes = [vp, i, ctypes.c_size_t, i]
+            L.mmgap_server_submit.argtypes = [vp, ctypes.POINTER(Job), vp,
+                                              ctypes.POINTER(ctypes.c_ulonglong)]
+            L.mmgap_server_poll.argtypes = [vp, ctypes.c_ulonglong, ctypes.POINTER(i),
+                                            ctypes.POINTER(ctypes.c_double)]
+            L.mmgap_server_drain.argtypes = [vp]
+            L.mmgap_server_stop.argtypes = [vp]
             for name in EXPORTS:
                 if name not in ("mmgap_last_error",):
                     getattr(L, name).restype = i
@@ -142,6 +152,56 @@ def default_vpp_schedule(qam: int, sweeps: int) -> np.ndarray:
     c2 = 1.0 / (2.0 * (qam - 1) / 3.0)
     step = qam * c2
     return linear_beta2(sweeps, 0.1 / step, 4.0 / step)
+
+
+def _det_range(qam: int, n_rx: int, noise_var: float):
+    c2 = 1.0 / (2.0 * (qam - 1) / 3.0)
+    b0 = 1.0 / (4.0 * c2 * n_rx)
+    return b0, max(1.0 / max(noise_var, 1e-6), b0)
+
+
+def _vpp_range(qam: int):
+    step = qam / (2.0 * (qam - 1) / 3.0)
+    return 0.1 / step, 4.0 / step
+
+
+TUNED_TABLE = os.path.join(_PKG, "tuned_schedules.json")
+_tuned_cache = {}
+
+
+def tuned_schedule(kind: int, n_rx: int, n_tx: int, qam: int, noise_var: float = 0.0,
+                   table: str = TUNED_TABLE) -> dict:
+    """Schedule picked by the offline tuner (``python -m paper_2510_01579_amd.tune``)
+    for a job class: dict(chains, sweeps, init, beta2, tuned).  A class the
+    table does not hold gets the reference schedule of its size (tuned=False).
+
+    The temperature shape (r, m) ends the linear-in-beta anneal at m beta1 and
+    starts it at r m beta1 (r = 0: at the default beta0)."""
+    import json
+    if table not in _tuned_cache:
+        _tuned_cache[table] = {}
+        if os.path.exists(table):
+            with open(table) as fh:
+                _tuned_cache[table] = json.load(fh).get("classes", {})
+    name = f"{'det' if kind == KIND_DET else 'vpp'}-{n_rx}x{n_tx}-{int(qam)}"
+    rec = _tuned_cache[table].get(name)
+    if rec is None:
+        big = max(n_rx, n_tx) > 8
+        sched = dict(chains=128 if big and kind == KIND_DET else 64,
+                     sweeps=400 if big and kind == KIND_DET else 200,
+                     init=1 if (kind == KIND_DET and qam == 64) else 0, shape=[0.0, 1.0])
+        tuned = False
+    else:
+        sched = dict(rec["tuned"])
+        tuned = True
+    b0, b1 = _det_range(qam, n_rx, noise_var) if kind == KIND_DET else _vpp_range(qam)
+    r, m = sched.get("shape", [0.0, 1.0])
+    end = m * b1
+    start = b0 if r == 0.0 else max(b0, r * end)
+    return dict(chains=int(sched["chains"]), sweeps=int(sched["sweeps"]),
+                init=int(sched["init"]), beta2=linear_beta2(int(sched["sweeps"]),
+                                                            min(start, end), end),
+                tuned=tuned)
 
 
 class Context:
@@ -348,6 +408,39 @@ class Context:
                                             PLAN_GRAPH if graph else 0, int(blocks),
                                             ctypes.byref(h)))
         return Plan(self, h, jobs)
+
+    # ------------------------------------------------------------------ serving
+    def server_start(self, max_inflight: int = 2, arena_bytes: int = 0, max_batch_jobs: int = 0):
+        """Start the native serving loop (see mmgap_server_start)."""
+        self._check(lib().mmgap_server_start(self._h, int(max_inflight), int(arena_bytes),
+                                             int(max_batch_jobs)))
+        self._server_jobs = {}
+
+    def server_submit(self, job, stream=None) -> int:
+        """Queue a job made by det_job / vpp_job; returns its id.  The job's
+        tensors are kept alive until it is reported done."""
+        st = stream if stream is not None else _stream(self._dev())
+        jid = ctypes.c_ulonglong()
+        self._check(lib().mmgap_server_submit(self._h, ctypes.byref(job["job"]), st,
+                                              ctypes.byref(jid)))
+        self.__dict__.setdefault("_server_jobs", {})[jid.value] = job
+        return jid.value
+
+    def server_poll(self, job_id: int):
+        """(done, latency_us or None)."""
+        done, lat = ctypes.c_int(), ctypes.c_double()
+        rc = lib().mmgap_server_poll(self._h, int(job_id), ctypes.byref(done), ctypes.byref(lat))
+        if done.value:
+            self.__dict__.get("_server_jobs", {}).pop(int(job_id), None)
+        self._check(rc)
+        return bool(done.value), (lat.value if done.value else None)
+
+    def server_drain(self):
+        self._check(lib().mmgap_server_drain(self._h))
+
+    def server_stop(self):
+        self._check(lib().mmgap_server_stop(self._h))
+        self._server_jobs = {}
 
 
 class Plan:

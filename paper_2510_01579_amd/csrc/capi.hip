@@ -11,40 +11,16 @@
 #include <string>
 #include <vector>
 
-#include "kernels.h"
-#include "mmgap.h"
+#include "context.h"
+
+using namespace mmgap::host;
 
 namespace {
-
-constexpr int kRing = 8;                        // schedule upload slots
-constexpr size_t kDefaultBudget = size_t(16) << 30;
-constexpr size_t kAlign = 256;
-constexpr int kProfRing = 256;                  // profiled calls kept
-
 thread_local std::string g_create_error;
-
 }  // namespace
 
-struct mmgap_ctx {
-    int device = 0;
-    size_t budget = kDefaultBudget;
-    std::string err;
-    void *scratch = nullptr;
-    size_t scratch_bytes = 0;
-    size_t plan_bytes = 0;                      // device memory held by live plans
-    float *beta_dev = nullptr;                  // [kRing][kMaxSweeps]
-    float *beta_host = nullptr;                 // pinned, same shape
-    hipEvent_t ring_ev[kRing] = {};
-    int ring_pos = 0;
-    hipEvent_t done = nullptr;                  // end of the last call's work
-    bool done_valid = false;
-    uint32_t *accept_dev = nullptr;             // Metropolis threshold table
-    bool profiling = false;
-    long prof_count = 0;                        // profiled calls since enabling
-    hipEvent_t prof_ev[kProfRing][4] = {};      // start, before anneal, after anneal, end
-};
-
-namespace {
+namespace mmgap {
+namespace host {
 
 int fail(mmgap_ctx *ctx, int code, const char *fmt, ...)
 {
@@ -63,34 +39,10 @@ int hip_fail(mmgap_ctx *ctx, hipError_t e, const char *what)
     return fail(ctx, MMGAP_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-// Switches to the context's device for the duration of a call.
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = true;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
-    }
-    ~DeviceGuard()
-    {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
+}  // namespace host
+}  // namespace mmgap
 
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-// Bump allocator over the context's scratch.
-struct Plan {
-    size_t off = 0;
-    size_t take(size_t bytes)
-    {
-        const size_t o = off;
-        off += align_up(bytes);
-        return o;
-    }
-};
+namespace {
 
 int ensure_scratch(mmgap_ctx *ctx, size_t bytes)
 {
@@ -153,6 +105,12 @@ int qam_bits(int qam)
     }
 }
 
+
+}  // namespace
+
+namespace mmgap {
+namespace host {
+
 int check_schedule(mmgap_ctx *ctx, const mmgap_schedule *s)
 {
     if (!s) return fail(ctx, MMGAP_EINVAL, "schedule is NULL");
@@ -169,6 +127,47 @@ int check_schedule(mmgap_ctx *ctx, const mmgap_schedule *s)
     if (s->init != 0 && s->init != 1) return fail(ctx, MMGAP_EINVAL, "schedule.init must be 0 or 1");
     return MMGAP_OK;
 }
+
+int check_problem(mmgap_ctx *ctx, const mmgap_problem *p, int kind, ProblemShape *sh)
+{
+    if (!p) return fail(ctx, MMGAP_EINVAL, "problem is NULL");
+    if (p->kind != MMGAP_KIND_DET && p->kind != MMGAP_KIND_VPP)
+        return fail(ctx, MMGAP_EINVAL, "problem.kind=%d is not DET or VPP", p->kind);
+    if (kind >= 0 && p->kind != kind)
+        return fail(ctx, MMGAP_EINVAL, "problem.kind=%d does not match this entry point", p->kind);
+    if (p->n_rx < 1 || p->n_tx < 1 || p->n_sc < 0 || p->n_sym < 1)
+        return fail(ctx, MMGAP_EINVAL, "bad sizes n_rx=%d n_tx=%d n_sc=%d n_sym=%d", p->n_rx,
+                    p->n_tx, p->n_sc, p->n_sym);
+    if (p->n_sym > 64) return fail(ctx, MMGAP_EUNSUPPORTED, "n_sym=%d > 64", p->n_sym);
+    const int q = qam_bits(p->qam);
+    if (!q) return fail(ctx, MMGAP_EUNSUPPORTED, "qam=%d not in {4,16,64}", p->qam);
+    if (p->kind == MMGAP_KIND_DET) {
+        if (p->n_tx > 16 || p->n_rx > 64)
+            return fail(ctx, MMGAP_EUNSUPPORTED, "DET needs n_tx <= 16 and n_rx <= 64 (got %d x %d)",
+                        p->n_rx, p->n_tx);
+        if (!(p->noise_var >= 0.0f) || !std::isfinite(p->noise_var))
+            return fail(ctx, MMGAP_EINVAL, "noise_var must be finite and >= 0");
+        sh->K = 2 * p->n_tx;
+        sh->q = q;
+    } else {
+        if (p->n_rx > 16 || p->n_tx > 64)
+            return fail(ctx, MMGAP_EUNSUPPORTED, "VPP needs n_rx <= 16 and n_tx <= 64 (got %d x %d)",
+                        p->n_rx, p->n_tx);
+        if (!std::isfinite(p->tau)) return fail(ctx, MMGAP_EINVAL, "tau must be finite");
+        sh->K = 2 * p->n_rx;
+        sh->q = 2;
+    }
+    sh->KT = mmgap::padded_k(sh->K);
+    const long long ni = (long long)p->n_sc * p->n_sym;
+    if (ni > 0x7FFFFFFFll) return fail(ctx, MMGAP_EUNSUPPORTED, "too many instances");
+    sh->n_inst = (int)ni;
+    return MMGAP_OK;
+}
+
+}  // namespace host
+}  // namespace mmgap
+
+namespace {
 
 // Orders this call after the context's previous call (which may have used
 // another stream) so that the shared scratch is never used concurrently.
@@ -209,46 +208,6 @@ int upload_beta(mmgap_ctx *ctx, const mmgap_schedule *s, hipStream_t st, const f
     e = hipEventRecord(ctx->ring_ev[slot], st);
     if (e != hipSuccess) return hip_fail(ctx, e, "hipEventRecord(schedule)");
     *out = d;
-    return MMGAP_OK;
-}
-
-struct ProblemShape {
-    int K = 0, q = 0, KT = 0, n_inst = 0;
-};
-
-int check_problem(mmgap_ctx *ctx, const mmgap_problem *p, int kind, ProblemShape *sh)
-{
-    if (!p) return fail(ctx, MMGAP_EINVAL, "problem is NULL");
-    if (p->kind != MMGAP_KIND_DET && p->kind != MMGAP_KIND_VPP)
-        return fail(ctx, MMGAP_EINVAL, "problem.kind=%d is not DET or VPP", p->kind);
-    if (kind >= 0 && p->kind != kind)
-        return fail(ctx, MMGAP_EINVAL, "problem.kind=%d does not match this entry point", p->kind);
-    if (p->n_rx < 1 || p->n_tx < 1 || p->n_sc < 0 || p->n_sym < 1)
-        return fail(ctx, MMGAP_EINVAL, "bad sizes n_rx=%d n_tx=%d n_sc=%d n_sym=%d", p->n_rx,
-                    p->n_tx, p->n_sc, p->n_sym);
-    if (p->n_sym > 64) return fail(ctx, MMGAP_EUNSUPPORTED, "n_sym=%d > 64", p->n_sym);
-    const int q = qam_bits(p->qam);
-    if (!q) return fail(ctx, MMGAP_EUNSUPPORTED, "qam=%d not in {4,16,64}", p->qam);
-    if (p->kind == MMGAP_KIND_DET) {
-        if (p->n_tx > 16 || p->n_rx > 64)
-            return fail(ctx, MMGAP_EUNSUPPORTED, "DET needs n_tx <= 16 and n_rx <= 64 (got %d x %d)",
-                        p->n_rx, p->n_tx);
-        if (!(p->noise_var >= 0.0f) || !std::isfinite(p->noise_var))
-            return fail(ctx, MMGAP_EINVAL, "noise_var must be finite and >= 0");
-        sh->K = 2 * p->n_tx;
-        sh->q = q;
-    } else {
-        if (p->n_rx > 16 || p->n_tx > 64)
-            return fail(ctx, MMGAP_EUNSUPPORTED, "VPP needs n_rx <= 16 and n_tx <= 64 (got %d x %d)",
-                        p->n_rx, p->n_tx);
-        if (!std::isfinite(p->tau)) return fail(ctx, MMGAP_EINVAL, "tau must be finite");
-        sh->K = 2 * p->n_rx;
-        sh->q = 2;
-    }
-    sh->KT = mmgap::padded_k(sh->K);
-    const long long ni = (long long)p->n_sc * p->n_sym;
-    if (ni > 0x7FFFFFFFll) return fail(ctx, MMGAP_EUNSUPPORTED, "too many instances");
-    sh->n_inst = (int)ni;
     return MMGAP_OK;
 }
 
@@ -322,8 +281,6 @@ int run_solver(mmgap_ctx *ctx, hipStream_t st, int n_inst, int K, int q, int KT,
     return MMGAP_OK;
 }
 
-constexpr int kMaxFusedChains = 256;   // four wavefronts of a workgroup
-
 // Relative cost of one work item: the workgroup is held for `sweeps` sweeps of
 // KT Q flip attempts, each about 20 operations plus the K-term field row shared
 // by the Q attempts of a dimension.
@@ -334,17 +291,167 @@ double item_cost(const mmgap::FusedJob &j)
 
 }  // namespace
 
+namespace mmgap {
+namespace host {
+
+int batch_layout(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, BatchLayout *out)
+{
+    BatchLayout &L = *out;
+    L = BatchLayout();
+    L.jobs.resize((size_t)n_jobs);
+    L.betas.resize((size_t)n_jobs);
+    for (int j = 0; j < n_jobs; ++j) {
+        const mmgap_job &jb = jobs[j];
+        ProblemShape sh;
+        int rc = check_problem(ctx, &jb.prob, -1, &sh);
+        if (!rc) rc = check_schedule(ctx, &jb.sched);
+        if (rc) return fail(ctx, rc, "job %d: %s", j, ctx->err.c_str());
+        if (jb.sched.chains > kMaxFusedChains)
+            return fail(ctx, MMGAP_EUNSUPPORTED, "job %d: chains=%d > %d in a batch", j,
+                        jb.sched.chains, kMaxFusedChains);
+        if (sh.n_inst > 0 && (!jb.H || !jb.y_or_u || !jb.out0))
+            return fail(ctx, MMGAP_EINVAL, "job %d: H, y_or_u and out0 are required", j);
+        const int variant = mmgap::fused_variant(sh.KT, sh.q);
+        if (variant < 0) return fail(ctx, MMGAP_EUNSUPPORTED, "job %d: no fused variant", j);
+        const mmgap_problem &p = jb.prob;
+        mmgap::FusedJob &f = L.jobs[j];
+        f = mmgap::FusedJob{};
+        f.kind = p.kind;
+        f.variant = variant;
+        f.KT = sh.KT;
+        f.Q = sh.q;
+        f.K = sh.K;
+        f.n_rows = p.n_rx;
+        f.n_cols = p.n_tx;
+        f.n_sym = p.n_sym;
+        f.n_sc = p.n_sc;
+        f.chains = jb.sched.chains;
+        f.sweeps = jb.sched.sweeps;
+        f.init = jb.sched.init;
+        f.wpi = jb.sched.chains <= 64 ? 1 : (jb.sched.chains <= 128 ? 2 : 4);
+        f.glanes = packed_lanes(jb.sched.chains, 0, 16);   // an item lies in one subcarrier
+        f.ldf = (sh.KT + 31) / 32 * 32;   // 128-byte field rows: no scalar-cache line is shared
+        if (p.kind == MMGAP_KIND_DET) det_weights(sh.q, f.w);
+        else vpp_weights(f.w);
+        f.key0 = (uint32_t)jb.sched.seed;
+        f.key1 = (uint32_t)(jb.sched.seed >> 32);
+        f.c = qam_c(p.qam);
+        f.c2 = qam_c2(p.qam);
+        f.noise_var = (double)p.noise_var;
+        f.tau = p.kind == MMGAP_KIND_VPP ? vpp_tau(&p) : 0.0;
+        f.H = (const float2 *)jb.H;
+        f.y = (const float2 *)jb.y_or_u;
+        f.out0 = jb.out0;
+        f.out1 = jb.out1;
+        f.out2 = jb.out2;
+        L.betas[j].assign(jb.sched.beta2, jb.sched.beta2 + jb.sched.sweeps);
+        const int per = f.glanes ? 4 * (64 / f.glanes) : 4 / f.wpi;
+        for (int sc = 0; sc < p.n_sc; ++sc)
+            for (int s0 = 0; s0 < p.n_sym; s0 += per)
+                L.items.push_back({j, sc, s0, std::min(per, p.n_sym - s0)});
+    }
+    if (L.items.size() > 0x7FFFFFFFu) return fail(ctx, MMGAP_EUNSUPPORTED, "too many work items");
+    // grouped by register class, each group ordered by decreasing cost
+    auto cls_of = [&](const mmgap::FusedItem &a) {
+        return mmgap::fused_kernel_class(L.jobs[a.job].variant);
+    };
+    std::stable_sort(L.items.begin(), L.items.end(),
+                     [&](const mmgap::FusedItem &a, const mmgap::FusedItem &b) {
+                         const int ca = cls_of(a), cb = cls_of(b);
+                         if (ca != cb) return ca < cb;
+                         return item_cost(L.jobs[a.job]) > item_cost(L.jobs[b.job]);
+                     });
+    for (size_t i = 0; i < L.items.size(); ++i) {
+        const int c = cls_of(L.items[i]);
+        if (L.cls_items[c] == 0) L.cls_first[c] = (int)i;
+        ++L.cls_items[c];
+    }
+    Bump lay;
+    L.o_jobs = lay.take(sizeof(mmgap::FusedJob) * std::max<size_t>(L.jobs.size(), 1));
+    L.o_items = lay.take(sizeof(mmgap::FusedItem) * std::max<size_t>(L.items.size(), 1));
+    L.o_counters = lay.take(sizeof(unsigned int) * mmgap::kFusedClasses);
+    L.ob.resize(n_jobs);
+    L.oG.resize(n_jobs);
+    L.of.resize(n_jobs);
+    L.ox.resize(n_jobs);
+    L.oA.resize(n_jobs);
+    for (int j = 0; j < n_jobs; ++j) L.ob[j] = lay.take(sizeof(float) * L.betas[j].size());
+    L.header_bytes = lay.off;
+    for (int j = 0; j < n_jobs; ++j) {
+        const mmgap::FusedJob &f = L.jobs[j];
+        const size_t ni = (size_t)f.n_sc * f.n_sym;
+        L.oG[j] = lay.take(sizeof(float) * (size_t)f.n_sc * f.KT * f.KT);
+        L.of[j] = lay.take(sizeof(float) * ni * f.ldf);
+        L.ox[j] = lay.take(ni * (size_t)f.KT);
+        L.oA[j] = f.kind == MMGAP_KIND_VPP
+                      ? lay.take(sizeof(double2) * (size_t)f.n_sc * f.n_rows * f.n_rows)
+                      : 0;
+    }
+    L.bytes = lay.off;
+    return MMGAP_OK;
+}
+
+void batch_bind(BatchLayout &L, char *base, std::vector<unsigned char> &image)
+{
+    for (size_t j = 0; j < L.jobs.size(); ++j) {
+        mmgap::FusedJob &f = L.jobs[j];
+        f.beta2 = reinterpret_cast<const float *>(base + L.ob[j]);
+        f.G = reinterpret_cast<float *>(base + L.oG[j]);
+        f.f = reinterpret_cast<float *>(base + L.of[j]);
+        f.x_fb = reinterpret_cast<signed char *>(base + L.ox[j]);
+        f.Ainv = f.kind == MMGAP_KIND_VPP ? reinterpret_cast<double2 *>(base + L.oA[j]) : nullptr;
+    }
+    image.assign(L.header_bytes, 0);
+    if (!L.jobs.empty())
+        std::memcpy(image.data() + L.o_jobs, L.jobs.data(), sizeof(mmgap::FusedJob) * L.jobs.size());
+    if (!L.items.empty())
+        std::memcpy(image.data() + L.o_items, L.items.data(),
+                    sizeof(mmgap::FusedItem) * L.items.size());
+    for (size_t j = 0; j < L.jobs.size(); ++j)
+        std::memcpy(image.data() + L.ob[j], L.betas[j].data(), sizeof(float) * L.betas[j].size());
+}
+
+int batch_launch_config(mmgap_ctx *ctx, const BatchLayout &L, char *base, int blocks,
+                        BatchLaunch *out)
+{
+    BatchLaunch &b = *out;
+    b = BatchLaunch();
+    b.jobs = reinterpret_cast<mmgap::FusedJob *>(base + L.o_jobs);
+    b.items = reinterpret_cast<mmgap::FusedItem *>(base + L.o_items);
+    b.counters = reinterpret_cast<unsigned int *>(base + L.o_counters);
+    hipError_t e = hipSuccess;
+    if (ctx->cus == 0)
+        e = hipDeviceGetAttribute(&ctx->cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
+    for (int c = 0; c < mmgap::kFusedClasses && e == hipSuccess; ++c) {
+        b.first[c] = L.cls_first[c];
+        b.count[c] = L.cls_items[c];
+        if (!b.count[c]) continue;
+        if (ctx->fused_per_cu[c] == 0) e = mmgap::fused_blocks_per_cu(c, &ctx->fused_per_cu[c]);
+        if (e == hipSuccess && ctx->fused_per_cu[c] < 1) e = hipErrorInvalidConfiguration;
+        b.blocks[c] = std::min(blocks > 0 ? blocks : ctx->fused_per_cu[c] * ctx->cus, b.count[c]);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "occupancy query");
+    return MMGAP_OK;
+}
+
+hipError_t batch_enqueue(const BatchLaunch &b, const uint32_t *accept_table, hipStream_t st)
+{
+    hipError_t e = mmgap::launch_fused_reset(b.counters, st);
+    for (int c = mmgap::kFusedClasses - 1; c >= 0 && e == hipSuccess; --c)
+        e = mmgap::launch_fused(c, b.jobs, b.items + b.first[c], b.count[c], b.counters + c,
+                                accept_table, b.blocks[c], st);
+    return e;
+}
+
+}  // namespace host
+}  // namespace mmgap
+
 struct mmgap_plan {
     mmgap_ctx *ctx = nullptr;
     int n_items = 0;
-    int cls_items[mmgap::kFusedClasses] = {};   // items per register class
-    int cls_first[mmgap::kFusedClasses] = {};   // first item of the class
-    int cls_blocks[mmgap::kFusedClasses] = {};  // workgroups of the class's launch
+    BatchLaunch launch;
     void *mem = nullptr;
     size_t bytes = 0;
-    mmgap::FusedJob *jobs_dev = nullptr;
-    mmgap::FusedItem *items_dev = nullptr;
-    unsigned int *counters = nullptr;           // one work counter per class
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;
@@ -352,16 +459,6 @@ struct mmgap_plan {
 };
 
 namespace {
-
-// Counter reset, then the class kernels, largest problems first.
-hipError_t plan_enqueue(const mmgap_plan *p, hipStream_t st)
-{
-    hipError_t e = mmgap::launch_fused_reset(p->counters, st);
-    for (int c = mmgap::kFusedClasses - 1; c >= 0 && e == hipSuccess; --c)
-        e = mmgap::launch_fused(c, p->jobs_dev, p->items_dev + p->cls_first[c], p->cls_items[c],
-                                p->counters + c, p->ctx->accept_dev, p->cls_blocks[c], st);
-    return e;
-}
 
 void plan_free(mmgap_plan *p)
 {
@@ -429,6 +526,7 @@ int mmgap_destroy(mmgap_ctx *ctx)
 {
     if (!ctx) return MMGAP_OK;
     DeviceGuard g(ctx->device);
+    server_shutdown(ctx);
     (void)hipDeviceSynchronize();
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     if (ctx->beta_dev) (void)hipFree(ctx->beta_dev);
@@ -461,7 +559,7 @@ int mmgap_build_ising(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H,
     if (!H || !y_or_u || !G || !f) return fail(ctx, MMGAP_EINVAL, "H, y_or_u, G and f are required");
     DeviceGuard g(ctx->device);
     hipStream_t st = (hipStream_t)stream;
-    Plan plan;
+    Bump plan;
     const size_t o_norm = e_const ? plan.take(sizeof(double) * (size_t)sh.n_inst) : 0;
     if ((rc = ensure_scratch(ctx, plan.off))) return rc;
     if ((rc = begin_call(ctx, st))) return rc;
@@ -553,7 +651,7 @@ int mmgap_solve(mmgap_ctx *ctx, int n_inst, int K, int q, const signed char *w,
     const int NW = mmgap::spin_words(KT, q);
     const int n_G = (n_inst + inst_per_G - 1) / inst_per_G;
     const bool pad = KT != K;
-    Plan plan;
+    Bump plan;
     const size_t oG = pad ? plan.take(sizeof(float) * (size_t)n_G * KT * KT) : 0;
     const size_t of = pad ? plan.take(sizeof(float) * (size_t)n_inst * KT) : 0;
     const size_t ox = (pad && x_fallback) ? plan.take((size_t)n_inst * KT) : 0;
@@ -601,7 +699,7 @@ int mmgap_detect(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, const
     DeviceGuard g(ctx->device);
     hipStream_t st = (hipStream_t)stream;
     const int KT = sh.KT, NW = mmgap::spin_words(KT, sh.q), ni = sh.n_inst;
-    Plan plan;
+    Bump plan;
     const size_t oG = plan.take(sizeof(float) * (size_t)prob->n_sc * KT * KT);
     const size_t of = plan.take(sizeof(float) * (size_t)ni * KT);
     const size_t ox = plan.take((size_t)ni * KT);
@@ -661,7 +759,7 @@ int mmgap_vpp_precode(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, 
     hipStream_t st = (hipStream_t)stream;
     const int KT = sh.KT, NW = mmgap::spin_words(KT, sh.q), ni = sh.n_inst;
     const int nu = prob->n_rx;
-    Plan plan;
+    Bump plan;
     const size_t oG = plan.take(sizeof(float) * (size_t)prob->n_sc * KT * KT);
     const size_t of = plan.take(sizeof(float) * (size_t)ni * KT);
     const size_t ox = plan.take((size_t)ni * KT);
@@ -758,140 +856,35 @@ int mmgap_plan_create(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, int fla
     if (flags & ~MMGAP_PLAN_GRAPH) return fail(ctx, MMGAP_EINVAL, "unknown flags 0x%x", flags);
     if (blocks < 0) return fail(ctx, MMGAP_EINVAL, "blocks=%d < 0", blocks);
 
-    // host-side descriptors; device pointers are filled in after allocation
-    std::vector<mmgap::FusedJob> fj((size_t)n_jobs);
-    std::vector<size_t> oG(n_jobs), of(n_jobs), ox(n_jobs), oA(n_jobs), ob(n_jobs);
-    std::vector<mmgap::FusedItem> items;
-    Plan lay;
-    const size_t o_jobs = lay.take(sizeof(mmgap::FusedJob) * (size_t)std::max(n_jobs, 1));
-    for (int j = 0; j < n_jobs; ++j) {
-        const mmgap_job &jb = jobs[j];
-        ProblemShape sh;
-        int rc = check_problem(ctx, &jb.prob, -1, &sh);
-        if (!rc) rc = check_schedule(ctx, &jb.sched);
-        if (rc) return fail(ctx, rc, "job %d: %s", j, ctx->err.c_str());
-        if (jb.sched.chains > kMaxFusedChains)
-            return fail(ctx, MMGAP_EUNSUPPORTED, "job %d: chains=%d > %d in a batch", j,
-                        jb.sched.chains, kMaxFusedChains);
-        if (sh.n_inst > 0 && (!jb.H || !jb.y_or_u || !jb.out0))
-            return fail(ctx, MMGAP_EINVAL, "job %d: H, y_or_u and out0 are required", j);
-        const int variant = mmgap::fused_variant(sh.KT, sh.q);
-        if (variant < 0) return fail(ctx, MMGAP_EUNSUPPORTED, "job %d: no fused variant", j);
-        const mmgap_problem &p = jb.prob;
-        mmgap::FusedJob &f = fj[j];
-        f.kind = p.kind;
-        f.variant = variant;
-        f.KT = sh.KT;
-        f.Q = sh.q;
-        f.K = sh.K;
-        f.n_rows = p.n_rx;
-        f.n_cols = p.n_tx;
-        f.n_sym = p.n_sym;
-        f.n_sc = p.n_sc;
-        f.chains = jb.sched.chains;
-        f.sweeps = jb.sched.sweeps;
-        f.init = jb.sched.init;
-        f.wpi = jb.sched.chains <= 64 ? 1 : (jb.sched.chains <= 128 ? 2 : 4);
-        f.glanes = packed_lanes(jb.sched.chains, 0, 16);   // an item lies in one subcarrier
-        f.ldf = (sh.KT + 31) / 32 * 32;   // 128-byte field rows: no scalar-cache line is shared
-
-        if (p.kind == MMGAP_KIND_DET) det_weights(sh.q, f.w);
-        else vpp_weights(f.w);
-        f.key0 = (uint32_t)jb.sched.seed;
-        f.key1 = (uint32_t)(jb.sched.seed >> 32);
-        f.c = qam_c(p.qam);
-        f.c2 = qam_c2(p.qam);
-        f.noise_var = (double)p.noise_var;
-        f.tau = p.kind == MMGAP_KIND_VPP ? vpp_tau(&p) : 0.0;
-        f.H = (const float2 *)jb.H;
-        f.y = (const float2 *)jb.y_or_u;
-        f.out0 = jb.out0;
-        f.out1 = jb.out1;
-        f.out2 = jb.out2;
-        const size_t ni = (size_t)sh.n_inst;
-        ob[j] = lay.take(sizeof(float) * (size_t)f.sweeps);
-        oG[j] = lay.take(sizeof(float) * (size_t)p.n_sc * sh.KT * sh.KT);
-        of[j] = lay.take(sizeof(float) * ni * f.ldf);
-        ox[j] = lay.take(ni * (size_t)sh.KT);
-        oA[j] = p.kind == MMGAP_KIND_VPP ? lay.take(sizeof(double2) * (size_t)p.n_sc * p.n_rx * p.n_rx)
-                                         : 0;
-        const int per = f.glanes ? 4 * (64 / f.glanes) : 4 / f.wpi;
-        for (int sc = 0; sc < p.n_sc; ++sc)
-            for (int s0 = 0; s0 < p.n_sym; s0 += per)
-                items.push_back({j, sc, s0, std::min(per, p.n_sym - s0)});
-    }
-    // grouped by register class, each group ordered by decreasing cost
-    auto cls_of = [&](const mmgap::FusedItem &a) {
-        return mmgap::fused_kernel_class(fj[a.job].variant);
-    };
-    std::stable_sort(items.begin(), items.end(),
-                     [&](const mmgap::FusedItem &a, const mmgap::FusedItem &b) {
-                         const int ca = cls_of(a), cb = cls_of(b);
-                         if (ca != cb) return ca < cb;
-                         return item_cost(fj[a.job]) > item_cost(fj[b.job]);
-                     });
-    const size_t o_items = lay.take(sizeof(mmgap::FusedItem) * std::max<size_t>(items.size(), 1));
-    const size_t o_counter = lay.take(sizeof(unsigned int) * mmgap::kFusedClasses);
-    if (items.size() > 0x7FFFFFFFu) return fail(ctx, MMGAP_EUNSUPPORTED, "too many work items");
-    if (lay.off + ctx->plan_bytes + ctx->scratch_bytes > ctx->budget)
+    BatchLayout lay;
+    int rc = batch_layout(ctx, n_jobs, jobs, &lay);
+    if (rc) return rc;
+    if (lay.bytes + ctx->plan_bytes + ctx->scratch_bytes > ctx->budget)
         return fail(ctx, MMGAP_ENOMEM,
-                    "plan of %zu bytes exceeds the HBM budget of %zu bytes (%zu in use)", lay.off,
+                    "plan of %zu bytes exceeds the HBM budget of %zu bytes (%zu in use)", lay.bytes,
                     ctx->budget, ctx->plan_bytes + ctx->scratch_bytes);
 
     DeviceGuard g(ctx->device);
-    int cus = 0;
-    hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
-    if (e != hipSuccess) return hip_fail(ctx, e, "hipDeviceGetAttribute");
-
     mmgap_plan *plan = new (std::nothrow) mmgap_plan();
     if (!plan) return fail(ctx, MMGAP_ENOMEM, "out of host memory");
     plan->ctx = ctx;
-    plan->n_items = (int)items.size();
-    for (size_t i = 0; i < items.size(); ++i) {
-        const int c = cls_of(items[i]);
-        if (plan->cls_items[c] == 0) plan->cls_first[c] = (int)i;
-        ++plan->cls_items[c];
-    }
-    for (int c = 0; c < mmgap::kFusedClasses && e == hipSuccess; ++c) {
-        if (!plan->cls_items[c]) continue;
-        int per_cu = 0;
-        e = mmgap::fused_blocks_per_cu(c, &per_cu);
-        if (e == hipSuccess && per_cu < 1) e = hipErrorInvalidConfiguration;
-        plan->cls_blocks[c] = std::min(blocks > 0 ? blocks : per_cu * cus, plan->cls_items[c]);
-    }
-    if (e != hipSuccess) {
-        delete plan;
-        return hip_fail(ctx, e, "occupancy query");
-    }
-    e = hipMalloc(&plan->mem, lay.off);
+    plan->n_items = (int)lay.items.size();
+    hipError_t e = hipMalloc(&plan->mem, lay.bytes);
     if (e != hipSuccess) {
         plan->mem = nullptr;
         plan_free(plan);
-        return fail(ctx, MMGAP_ENOMEM, "hipMalloc(%zu): %s", lay.off, hipGetErrorString(e));
+        return fail(ctx, MMGAP_ENOMEM, "hipMalloc(%zu): %s", lay.bytes, hipGetErrorString(e));
     }
-    plan->bytes = lay.off;
-    ctx->plan_bytes += lay.off;
+    plan->bytes = lay.bytes;
+    ctx->plan_bytes += lay.bytes;
     char *base = static_cast<char *>(plan->mem);
-    plan->jobs_dev = reinterpret_cast<mmgap::FusedJob *>(base + o_jobs);
-    plan->items_dev = reinterpret_cast<mmgap::FusedItem *>(base + o_items);
-    plan->counters = reinterpret_cast<unsigned int *>(base + o_counter);
-    for (int j = 0; j < n_jobs; ++j) {
-        mmgap::FusedJob &f = fj[j];
-        f.beta2 = reinterpret_cast<const float *>(base + ob[j]);
-        f.G = reinterpret_cast<float *>(base + oG[j]);
-        f.f = reinterpret_cast<float *>(base + of[j]);
-        f.x_fb = reinterpret_cast<signed char *>(base + ox[j]);
-        f.Ainv = f.kind == MMGAP_KIND_VPP ? reinterpret_cast<double2 *>(base + oA[j]) : nullptr;
-        e = hipMemcpy(base + ob[j], jobs[j].sched.beta2, sizeof(float) * (size_t)f.sweeps,
-                      hipMemcpyHostToDevice);
-        if (e != hipSuccess) break;
+    if ((rc = batch_launch_config(ctx, lay, base, blocks, &plan->launch))) {
+        plan_free(plan);
+        return rc;
     }
-    if (e == hipSuccess && n_jobs > 0)
-        e = hipMemcpy(plan->jobs_dev, fj.data(), sizeof(mmgap::FusedJob) * (size_t)n_jobs,
-                      hipMemcpyHostToDevice);
-    if (e == hipSuccess && !items.empty())
-        e = hipMemcpy(plan->items_dev, items.data(), sizeof(mmgap::FusedItem) * items.size(),
-                      hipMemcpyHostToDevice);
+    std::vector<unsigned char> image;
+    batch_bind(lay, base, image);
+    e = hipMemcpy(base, image.data(), image.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&plan->done, hipEventDisableTiming);
     if (e == hipSuccess && (flags & MMGAP_PLAN_GRAPH)) {
         hipStream_t cs = nullptr;
@@ -899,7 +892,7 @@ int mmgap_plan_create(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, int fla
         if (e == hipSuccess) {
             e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
-                const hipError_t el = plan_enqueue(plan, cs);
+                const hipError_t el = batch_enqueue(plan->launch, ctx->accept_dev, cs);
                 e = hipStreamEndCapture(cs, &plan->graph);
                 if (e == hipSuccess) e = el;
             }
@@ -925,7 +918,7 @@ int mmgap_plan_launch(mmgap_plan *plan, void *stream)
     if (plan->done_valid) e = hipStreamWaitEvent(st, plan->done, 0);
     if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamWaitEvent");
     if (plan->exec) e = hipGraphLaunch(plan->exec, st);
-    else e = plan_enqueue(plan, st);
+    else e = batch_enqueue(plan->launch, ctx->accept_dev, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "fused launch");
     e = hipEventRecord(plan->done, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "hipEventRecord");
@@ -937,7 +930,9 @@ int mmgap_plan_info(const mmgap_plan *plan, int *n_items, int *blocks)
 {
     if (!plan) return MMGAP_EINVAL;
     if (n_items) *n_items = plan->n_items;
-    if (blocks) *blocks = std::max(plan->cls_blocks[0], std::max(plan->cls_blocks[1], plan->cls_blocks[2]));
+    if (blocks)
+        *blocks = std::max(plan->launch.blocks[0],
+                           std::max(plan->launch.blocks[1], plan->launch.blocks[2]));
     return MMGAP_OK;
 }
 

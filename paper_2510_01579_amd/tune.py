@@ -1,6 +1,12 @@
 """Offline schedule tuner: per job class, the cheapest anneal schedule (chains,
-sweeps, start) whose quality stays within a tolerance of the class's reference
-schedule at every SNR of the class's grid.
+sweeps, start state, temperature shape) whose quality stays within a tolerance
+of the class's reference schedule at every SNR of the class's grid.
+
+A schedule is linear in beta from beta_start to beta_end.  The reference shape
+is the class's default range (beta0, beta1) of ``workload.synth``; a shape
+(r, m) ends at m beta1 and starts at r m beta1 (r = 0: at beta0), so that
+r > 0 starts cold -- a descent from the start state rather than a fresh
+anneal, which pays off when the start is the linear estimate.
 
 Quality is the symbol error rate against the transmitted symbols (detection)
 or the mean transmit energy ||W (u + tau v)||^2 (VPP), measured on synthetic
@@ -47,7 +53,20 @@ CLASSES = {
 }
 CHAINS = (4, 8, 16, 32, 64, 128)
 SWEEPS = (12, 25, 50, 100, 200, 400)
+SHAPES = ((0.0, 1.0), (1.0 / 16, 1.0), (1.0 / 4, 1.0), (1.0 / 16, 4.0))
 TOLERANCE = 0.05
+
+
+def shaped_range(b0: float, b1: float, shape) -> tuple[float, float]:
+    r, m = shape
+    end = m * b1
+    start = b0 if r == 0.0 else max(b0, r * end)
+    return min(start, end), end
+
+
+def schedule_key(c) -> str:
+    C, S, init, shape = c
+    return f"{C}x{S}/{init}/{shape[0]:g},{shape[1]:g}"
 
 
 def parse_class(name):
@@ -84,19 +103,20 @@ def measure(ctx, name, snr, schedules, n_sc, n_sym, seed):
         d = W.det_slot(seed, rows, cols, qam, n_sc, n_sym, snr)
         H, y = torch.from_numpy(d.H).to(dev), torch.from_numpy(d.y).to(dev)
         truth = torch.from_numpy(d.sym.reshape(n_sc * n_sym, cols)).to(dev)
-        for (C, S, init) in schedules:
-            beta2 = W.linear_beta2(S, *W.det_beta_range(qam, rows, d.noise_var))
+        for (C, S, init, shape) in schedules:
+            rng = shaped_range(*W.det_beta_range(qam, rows, d.noise_var), shape)
+            beta2 = W.linear_beta2(S, *rng)
             sym, _ = ctx.detect(H, y, qam, d.noise_var, C, S, beta2, W.job_seed(seed),
                                 init=init, metric=False)
-            out[(C, S, init)] = float((sym != truth).float().mean().item())
+            out[(C, S, init, shape)] = float((sym != truth).float().mean().item())
     else:
         s = W.vpp_slot(seed, rows, cols, qam, n_sc, n_sym)
         H, u = torch.from_numpy(s.H).to(dev), torch.from_numpy(s.u).to(dev)
-        for (C, S, init) in schedules:
-            beta2 = W.linear_beta2(S, *W.vpp_beta_range(qam, cols))
+        for (C, S, init, shape) in schedules:
+            beta2 = W.linear_beta2(S, *shaped_range(*W.vpp_beta_range(qam, cols), shape))
             _, _, g = ctx.vpp_precode(H, u, qam, C, S, beta2, W.job_seed(seed), init=init,
                                       want_x=False)
-            out[(C, S, init)] = float(g.double().mean().item())
+            out[(C, S, init, shape)] = float(g.double().mean().item())
     return out
 
 
@@ -120,26 +140,30 @@ def main(argv=None) -> int:
             table["classes"].update(old.get("classes", {}))
     for name in args.classes:
         spec = CLASSES[name]
-        ref = tuple(spec["ref"])
-        cands = sorted({(C, S, i) for C in CHAINS for S in SWEEPS for i in (0, 1)
+        ref = tuple(spec["ref"]) + (SHAPES[0],)
+        cands = sorted({(C, S, i, sh) for C in CHAINS for S in SWEEPS for i in (0, 1)
+                        for sh in SHAPES
                         if cost(name, C, S) <= cost(name, ref[0], ref[1])} | {ref},
-                       key=lambda s: cost(name, s[0], s[1]))
+                       key=lambda s: (cost(name, s[0], s[1]), s))
         t0 = time.time()
         per_snr = []
         for k, snr in enumerate(spec["snr"]):
             q = measure(ctx, name, snr, cands, args.n_sc, args.n_sym, args.seed + 17 * k)
             per_snr.append({"snr_db": snr, "ref": q[ref],
-                            "cands": {f"{C}x{S}/{i}": v for (C, S, i), v in q.items()}})
+                            "cands": {schedule_key(c): v for c, v in q.items()}})
+            print(f"  {name} snr {snr}: {len(q)} schedules", flush=True)
         passing = []
         for c in cands:
-            key = f"{c[0]}x{c[1]}/{c[2]}"
+            key = schedule_key(c)
             ok = all(r["cands"][key] <= (1 + TOLERANCE) * r["ref"] + 2e-5 for r in per_snr)
             if ok:
                 passing.append(c)
-        best = min(passing, key=lambda s: (cost(name, s[0], s[1]), s[0], s[1]))
+        best = min(passing, key=lambda s: (cost(name, s[0], s[1]), s[0], s[1], s[3]))
         table["classes"][name] = {
-            "reference": {"chains": ref[0], "sweeps": ref[1], "init": ref[2]},
-            "tuned": {"chains": best[0], "sweeps": best[1], "init": best[2]},
+            "reference": {"chains": ref[0], "sweeps": ref[1], "init": ref[2],
+                          "shape": list(ref[3])},
+            "tuned": {"chains": best[0], "sweeps": best[1], "init": best[2],
+                      "shape": list(best[3])},
             "cost_ratio": cost(name, ref[0], ref[1]) / cost(name, best[0], best[1]),
             "quality": "ser" if name.startswith("det") else "mean_gamma",
             "per_snr": per_snr,
