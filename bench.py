@@ -3,14 +3,19 @@
 
 A step is one 5G slot of every job of the workload through the whole path --
 Gram/field build, annealing, selection and decode -- on synthetic i.i.d.
-Rayleigh channels (inputs resident in HBM before the timed region).  Two legs
-run on the same inputs and schedules:
-  * fused: one persistent launch per slot (a batch plan replayed as a HIP graph);
-  * plain: the per-size entry points, one build, anneal and select launch each.
-Their outputs must be identical.  The JSON line reports the fused leg's
-whole-job throughput (Ising solves/s) and slot latency percentiles, the plain
-leg beside it, the roofline position of the dominant kernel (VALU-bound), and
-the CPU oracle timed on a bounded sample of the same workload.
+Rayleigh channels (inputs resident in HBM before the timed region).  Three legs
+run on the same inputs:
+  * plain: the per-size entry points (one build, anneal and select launch each)
+    at the workload's reference schedule -- the baseline;
+  * fused: one persistent launch per slot (a batch plan replayed as a HIP
+    graph) at the same schedule -- outputs must be identical to plain;
+  * tuned: the fused launch at the schedules the offline tuner picked for each
+    job class (tuned_schedules.json), if it has them.
+The reported value is the tuned leg's throughput when its quality on this
+slot -- symbol error rate (detection) or mean transmit energy (VPP) -- is
+within 5% of the plain leg's, else the fused leg's ("at matched SER").  The
+JSON line also carries slot latency percentiles, the roofline position of the
+dominant kernel (VALU-bound) and the CPU oracle timed on a bounded sample.
 
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
 """
@@ -130,9 +135,10 @@ def make_inputs(specs):
     return out
 
 
-def cpu_baseline(inputs, target_s: float):
+def cpu_baseline(inputs, scheds, target_s: float):
     """The oracle as it stands, on a bounded random sample of the workload's
-    instances (spread over its jobs in proportion to their instance counts)."""
+    instances (spread over its jobs in proportion to their instance counts),
+    with the schedules of the reported leg."""
     from oracle import oracle as O
     threads = O.max_threads()
     rng = np.random.default_rng(1)
@@ -142,17 +148,17 @@ def cpu_baseline(inputs, target_s: float):
     def run(frac):
         n_done = 0
         t0 = time.perf_counter()
-        for inp, n_all in zip(inputs, sizes):
+        for inp, sc, n_all in zip(inputs, scheds, sizes):
             j = inp["spec"]
             m = max(1, min(n_all, int(round(frac * n_all))))
             ids = np.sort(rng.choice(n_all, m, replace=False)).astype(np.uint32)
             if j["kind"] == "det":
-                O.detect(inp["H"], inp["y"], inp["noise_var"], j["qam"], j["chains"],
-                         j["sweeps"], inp["beta2"], inp["seed"], inst_ids=ids,
-                         init_mode=j["init"])
+                O.detect(inp["H"], inp["y"], inp["noise_var"], j["qam"], sc["chains"],
+                         sc["sweeps"], sc["beta2"], inp["seed"], inst_ids=ids,
+                         init_mode=sc["init"])
             else:
-                O.vpp_precode(inp["H"], inp["y"], j["qam"], j["chains"], j["sweeps"],
-                              inp["beta2"], inp["seed"], inst_ids=ids)
+                O.vpp_precode(inp["H"], inp["y"], j["qam"], sc["chains"], sc["sweeps"],
+                              sc["beta2"], inp["seed"], inst_ids=ids, init_mode=sc["init"])
             n_done += m
         return n_done, time.perf_counter() - t0
 
@@ -161,7 +167,149 @@ def cpu_baseline(inputs, target_s: float):
     n, dt = run(frac)
     return {"value": n / dt, "unit": "solves/s", "cores": threads, "kind": "oracle",
             "sample": f"{n} of {total} instances of the same slot(s) (random subset), "
-                      f"same chains and sweeps, {dt:.1f} s on {threads} threads"}
+                      f"same schedules as the reported leg, {dt:.1f} s on {threads} threads"}
+
+
+# serving mix: slot jobs, 60% detection / 40% VPP, sizes {8x8, 16x16},
+# modulations {QPSK, 16-QAM, 64-QAM} uniform, SNR uniform 5-30 dB (detection)
+SERVE_RATE = 2000.0          # offered slots per second
+SERVE_DEADLINE_MS = 0.5      # one slot
+
+
+def serve_classes():
+    out = []
+    for kind in ("det", "vpp"):
+        for n in (8, 16):
+            for qam in (4, 16, 64):
+                out.append((kind, n, qam))
+    return out
+
+
+def run_serving(args, M, torch):
+    """Native serving loop on a Poisson stream of slot jobs (see SERVE_*)."""
+    from workload import synth as W
+    rng = np.random.default_rng(5)
+    dev = torch.device("cuda", 0)
+    ctx = M.Context(0)
+    classes = serve_classes()
+    pool = {}
+    for ci, (kind, n, qam) in enumerate(classes):
+        for r in range(2):
+            seed = 6000 + 10 * ci + r
+            if kind == "det":
+                snr = float(rng.uniform(5.0, 30.0))
+                d = W.det_slot(seed, n, n, qam, N_SC, N_SYM, snr)
+                pool[(ci, r)] = dict(H=torch.from_numpy(d.H).to(dev),
+                                     y=torch.from_numpy(d.y).to(dev), nv=d.noise_var,
+                                     sched=M.tuned_schedule(M.KIND_DET, n, n, qam, d.noise_var))
+            else:
+                sl = W.vpp_slot(seed, n, n, qam, N_SC, N_SYM)
+                pool[(ci, r)] = dict(H=torch.from_numpy(sl.H).to(dev),
+                                     y=torch.from_numpy(sl.u).to(dev), nv=0.0,
+                                     sched=M.tuned_schedule(M.KIND_VPP, n, n, qam))
+    torch.cuda.synchronize()
+
+    def draw_job(k):
+        kind = "det" if rng.random() < 0.6 else "vpp"
+        n = int(rng.choice([8, 16]))
+        qam = int(rng.choice([4, 16, 64]))
+        ci = classes.index((kind, n, qam))
+        p = pool[(ci, int(rng.integers(2)))]
+        sc = p["sched"]
+        if kind == "det":
+            j = ctx.det_job(p["H"], p["y"], qam, p["nv"], sc["chains"], sc["sweeps"], sc["beta2"],
+                            W.job_seed(k), init=sc["init"], metric=False)
+        else:
+            j = ctx.vpp_job(p["H"], p["y"], qam, sc["chains"], sc["sweeps"], sc["beta2"],
+                            W.job_seed(k), want_x=False, want_gamma=False, init=sc["init"])
+        return j
+
+    ctx.server_start(max_inflight=3, arena_bytes=2 << 30)
+    try:
+        # warmup
+        ids = [ctx.server_submit(draw_job(k)) for k in range(6)]
+        ctx.server_drain()
+        for i in ids:
+            ctx.server_poll(i)
+        # saturation: everything queued at once -> sustainable slot rate
+        n_sat = max(args.steps, 12)
+        jobs = [draw_job(100 + k) for k in range(n_sat)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ids = [ctx.server_submit(j) for j in jobs]
+        ctx.server_drain()
+        makespan = time.perf_counter() - t0
+        for i in ids:
+            ctx.server_poll(i)
+        sustainable = n_sat / makespan
+        # Poisson arrivals at the offered rate, capped below saturation so that
+        # the queue stays finite
+        rate = min(SERVE_RATE, 0.8 * sustainable)
+        n_arr = max(args.steps * 2, 20)
+        gaps = rng.exponential(1.0 / rate, size=n_arr)
+        jobs = [draw_job(1000 + k) for k in range(n_arr)]
+        torch.cuda.synchronize()
+        ids = []
+        t0 = time.perf_counter()
+        t_next = t0
+        for k in range(n_arr):
+            t_next += gaps[k]
+            while time.perf_counter() < t_next:
+                pass
+            ids.append(ctx.server_submit(jobs[k]))
+        ctx.server_drain()
+        elapsed = time.perf_counter() - t0
+        lat = np.array([ctx.server_poll(i)[1] for i in ids]) / 1e3
+    finally:
+        ctx.server_stop()
+        ctx.close()
+    return {
+        "metric": METRIC,
+        "value": sustainable * N_SC * N_SYM,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": n_sat,
+        "warmup": 6,
+        "ms_per_step": 1e3 / sustainable,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "serving mix: slot jobs of 3276 subcarriers x 12 symbols, 60% uplink "
+                        "detection / 40% VPP, sizes 8x8 and 16x16, QPSK/16-QAM/64-QAM uniform, "
+                        "detection SNR uniform 5-30 dB, i.i.d. Rayleigh; tuned schedules",
+            "name": "serve-mix",
+            "path": "native serving loop: FIFO admission into an HBM arena, batches of the "
+                    "persistent fused kernels on 3 streams",
+        },
+        "sustainable_slots_per_s": sustainable,
+        "offered_slots_per_s": rate,
+        "target_slots_per_s": SERVE_RATE,
+        "arrivals": n_arr,
+        "arrival_window_s": elapsed,
+        "p50_slot_ms": float(np.percentile(lat, 50)),
+        "p99_slot_ms": float(np.percentile(lat, 99)),
+        "deadline_ms": SERVE_DEADLINE_MS,
+        "frac_within_deadline": float(np.mean(lat <= SERVE_DEADLINE_MS)),
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+
+
+def quality(inputs, outs):
+    """Per job: symbol error rate (detection) or mean transmit energy (VPP)."""
+    res = []
+    for inp, o in zip(inputs, outs):
+        j = inp["spec"]
+        n = j["n_sc"] * j["n_sym"]
+        if j["kind"] == "det":
+            truth = inp["raw"].sym.reshape(n, j["cols"])
+            res.append(float(np.mean(o["sym"] != truth)))
+        else:
+            res.append(float(np.mean(o["gamma"].astype(np.float64))))
+    return res
 
 
 def main(argv=None) -> int:  # noqa: C901
@@ -169,9 +317,11 @@ def main(argv=None) -> int:  # noqa: C901
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="det-8x8-16qam", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="det-8x8-16qam",
+                    choices=sorted(WORKLOADS) + ["serve-mix"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain leg")
+    ap.add_argument("--no-tuned", action="store_true", help="skip the tuned leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy three times, so that "
@@ -188,6 +338,10 @@ def main(argv=None) -> int:  # noqa: C901
 
     import paper_2510_01579_amd as M
 
+    if args.workload == "serve-mix":
+        print(json.dumps(run_serving(args, M, torch)), flush=True)
+        return 0
+
     specs = WORKLOADS[args.workload]
     inputs = make_inputs(specs)
     dev = torch.device("cuda", 0)
@@ -195,32 +349,6 @@ def main(argv=None) -> int:  # noqa: C901
         inp["H_d"] = torch.from_numpy(inp["H"]).to(dev)
         inp["y_d"] = torch.from_numpy(inp["y"]).to(dev)
     ctx = M.Context(0)
-
-    def plain_step():
-        outs = []
-        for inp in inputs:
-            j = inp["spec"]
-            if j["kind"] == "det":
-                outs.append(ctx.detect(inp["H_d"], inp["y_d"], j["qam"], inp["noise_var"],
-                                       j["chains"], j["sweeps"], inp["beta2"], inp["seed"],
-                                       init=j["init"]))
-            else:
-                outs.append(ctx.vpp_precode(inp["H_d"], inp["y_d"], j["qam"], j["chains"],
-                                            j["sweeps"], inp["beta2"], inp["seed"]))
-        return outs
-
-    jobs = []
-    for inp in inputs:
-        j = inp["spec"]
-        if j["kind"] == "det":
-            jobs.append(ctx.det_job(inp["H_d"], inp["y_d"], j["qam"], inp["noise_var"],
-                                    j["chains"], j["sweeps"], inp["beta2"], inp["seed"],
-                                    init=j["init"]))
-        else:
-            jobs.append(ctx.vpp_job(inp["H_d"], inp["y_d"], j["qam"], j["chains"], j["sweeps"],
-                                    inp["beta2"], inp["seed"]))
-    plan = ctx.plan_create(jobs, graph=True)
-    n_items, n_blocks = plan.plan_info()
 
     def timed(step, steps):
         start = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
@@ -235,82 +363,128 @@ def main(argv=None) -> int:  # noqa: C901
         elapsed = time.perf_counter() - t0
         return elapsed, np.array([a.elapsed_time(b) for a, b in zip(start, stop)])
 
-    # fused leg (the reported value); the events bracket exactly one plan launch
-    # (counter reset + persistent kernel) on the current stream
-    for _ in range(args.warmup):
-        plan.plan_launch()
-    f_elapsed, f_lat = timed(plan.plan_launch, args.steps)
-    fused_out = [{k: (None if t is None else t.cpu().numpy()) for k, t in jb["outputs"].items()}
-                 for jb in jobs]
+    def fused_leg(scheds):
+        """One plan over every job with the given (chains, sweeps, init, beta2);
+        the events bracket exactly one plan launch (counter reset + persistent
+        kernels) on the current stream."""
+        jobs = []
+        for inp, sc in zip(inputs, scheds):
+            j = inp["spec"]
+            if j["kind"] == "det":
+                jobs.append(ctx.det_job(inp["H_d"], inp["y_d"], j["qam"], inp["noise_var"],
+                                        sc["chains"], sc["sweeps"], sc["beta2"], inp["seed"],
+                                        init=sc["init"]))
+            else:
+                jobs.append(ctx.vpp_job(inp["H_d"], inp["y_d"], j["qam"], sc["chains"],
+                                        sc["sweeps"], sc["beta2"], inp["seed"], init=sc["init"]))
+        plan = ctx.plan_create(jobs, graph=True)
+        info = plan.plan_info()
+        for _ in range(args.warmup):
+            plan.plan_launch()
+        el, lat = timed(plan.plan_launch, args.steps)
+        outs = [{k: (None if t is None else t.cpu().numpy()) for k, t in jb["outputs"].items()}
+                for jb in jobs]
+        plan.plan_destroy()
+        return el, lat, outs, info
 
+    ref_scheds = [dict(chains=i["spec"]["chains"], sweeps=i["spec"]["sweeps"],
+                       init=i["spec"]["init"], beta2=i["beta2"]) for i in inputs]
+    f_el, f_lat, fused_out, (n_items, n_blocks) = fused_leg(ref_scheds)
+
+    total_inst = sum(job_shape(i["spec"])[2] for i in inputs)
     plain = None
     identical = None
+    q_plain = None
     if not args.no_plain:
+        def plain_step():
+            outs = []
+            for inp in inputs:
+                j = inp["spec"]
+                if j["kind"] == "det":
+                    outs.append(ctx.detect(inp["H_d"], inp["y_d"], j["qam"], inp["noise_var"],
+                                           j["chains"], j["sweeps"], inp["beta2"], inp["seed"],
+                                           init=j["init"]))
+                else:
+                    outs.append(ctx.vpp_precode(inp["H_d"], inp["y_d"], j["qam"], j["chains"],
+                                                j["sweeps"], inp["beta2"], inp["seed"]))
+            return outs
+
         for _ in range(args.warmup):
             plain_step()
         ctx.set_profiling(True)
-        p_elapsed, p_lat = timed(plain_step, args.steps)
+        p_el, p_lat = timed(plain_step, args.steps)
         prof = np.array(ctx.profile(args.steps * len(inputs))).reshape(args.steps, len(inputs), 3)
         ctx.set_profiling(False)
         outs = plain_step()
         torch.cuda.synchronize()
         identical = True
+        plain_out = []
         for inp, o, fo in zip(inputs, outs, fused_out):
-            if inp["spec"]["kind"] == "det":
-                pairs = [(o[0], fo["sym"]), (o[1], fo["metric"])]
-            else:
-                pairs = [(o[0], fo["v"]), (o[1], fo["x"]), (o[2], fo["gamma"])]
-            for a, b in pairs:
-                if a.cpu().numpy().tobytes() != b.tobytes():
+            names = ("sym", "metric") if inp["spec"]["kind"] == "det" else ("v", "x", "gamma")
+            po = {k: t.cpu().numpy() for k, t in zip(names, o)}
+            plain_out.append(po)
+            for k in names:
+                if po[k].tobytes() != fo[k].tobytes():
                     identical = False
-        anneal_ms = float(np.mean(prof[:, :, 1].sum(axis=1)))
-        solves = args.steps * sum(job_shape(i["spec"])[2] for i in inputs)
-        plain = {"value": solves / p_elapsed, "unit": "solves/s",
-                 "ms_per_step": p_elapsed / args.steps * 1e3,
+        q_plain = quality(inputs, plain_out)
+        plain = {"value": args.steps * total_inst / p_el, "unit": "solves/s",
+                 "ms_per_step": p_el / args.steps * 1e3,
                  "p50_slot_ms": float(np.percentile(p_lat, 50)),
                  "p99_slot_ms": float(np.percentile(p_lat, 99)),
                  "stage_ms": {"build": float(np.mean(prof[:, :, 0].sum(axis=1))),
-                              "anneal": anneal_ms,
-                              "select": float(np.mean(prof[:, :, 2].sum(axis=1)))}}
+                              "anneal": float(np.mean(prof[:, :, 1].sum(axis=1))),
+                              "select": float(np.mean(prof[:, :, 2].sum(axis=1)))},
+                 "quality": q_plain}
+    q_fused = quality(inputs, fused_out)
 
-    # quality: SER against the transmitted symbols (detection), mean transmit
-    # energy against zero perturbation (VPP)
-    quality = []
-    for inp, fo in zip(inputs, fused_out):
-        j = inp["spec"]
-        n = j["n_sc"] * j["n_sym"]
-        if j["kind"] == "det":
-            fb = ctx.build_ising(M.KIND_DET, inp["H_d"], inp["y_d"], j["qam"],
-                                 noise_var=inp["noise_var"])["x_fb"].cpu().numpy()
-            truth = inp["raw"].sym.reshape(n, j["cols"])
-            quality.append({"job": f"det {j['rows']}x{j['cols']} {j['qam']}-QAM",
-                            "ser": float(np.mean(fo["sym"] != truth)),
-                            "ser_mmse": float(np.mean(levels_to_symbols(fb, j["qam"]) != truth))})
-        else:
-            H = inp["H"].astype(np.complex128)
-            u = inp["y"].astype(np.complex128)
-            W = np.conj(np.swapaxes(H, 1, 2)) @ np.linalg.inv(H @ np.conj(np.swapaxes(H, 1, 2)))
-            x0 = np.einsum("stu,smu->smt", W, u).reshape(n, -1)
-            quality.append({"job": f"vpp {j['rows']}x{j['cols']} {j['qam']}-QAM",
-                            "mean_gamma": float(np.mean(fo["gamma"])),
-                            "mean_gamma_zf": float(np.mean(np.sum(np.abs(x0) ** 2, axis=1)))})
-    plan.plan_destroy()
+    tuned = None
+    if not args.no_tuned:
+        t_scheds = []
+        any_tuned = False
+        for inp in inputs:
+            j = inp["spec"]
+            kind = M.KIND_DET if j["kind"] == "det" else M.KIND_VPP
+            ts = M.tuned_schedule(kind, j["rows"], j["cols"], j["qam"], inp["noise_var"])
+            any_tuned = any_tuned or ts["tuned"]
+            t_scheds.append(ts if ts["tuned"] else ref_scheds[len(t_scheds)])
+        if any_tuned:
+            t_el, t_lat, t_out, _ = fused_leg(t_scheds)
+            q_t = quality(inputs, t_out)
+            base = q_plain if q_plain is not None else q_fused
+            matched = all(qt <= 1.05 * qb + 2e-5 for qt, qb in zip(q_t, base))
+            tuned = {"value": args.steps * total_inst / t_el, "unit": "solves/s",
+                     "ms_per_step": t_el / args.steps * 1e3,
+                     "p50_slot_ms": float(np.percentile(t_lat, 50)),
+                     "p99_slot_ms": float(np.percentile(t_lat, 99)),
+                     "schedules": [f"{s['chains']} chains x {s['sweeps']} sweeps, "
+                                   f"{'fallback' if s['init'] else 'random'} start"
+                                   for s in t_scheds],
+                     "quality": q_t, "quality_matched": matched}
     ctx.close()
 
-    total_inst = sum(job_shape(i["spec"])[2] for i in inputs)
-    attempts = sum(job_shape(i["spec"])[3] for i in inputs)
-    alg_ops = sum(job_shape(i["spec"])[3] * ops_per_attempt(*job_shape(i["spec"])[:2])
-                  for i in inputs)
-    fused_s = float(np.mean(f_lat)) / 1e3
-    achieved = alg_ops / fused_s
-    value = args.steps * total_inst / f_elapsed
+    use_tuned = tuned is not None and tuned["quality_matched"]
+    sel_el = t_el if use_tuned else f_el
+    sel_lat = t_lat if use_tuned else f_lat
+    sel_scheds = t_scheds if use_tuned else ref_scheds
+    value = args.steps * total_inst / sel_el
+
+    # roofline of the dominant kernel on the reported leg: anneal operations of
+    # one launch over its measured duration (HIP events on the launch stream)
+    attempts = 0.0
+    alg_ops = 0.0
+    for inp, sc in zip(inputs, sel_scheds):
+        K, q, n, _ = job_shape(inp["spec"])
+        a = float(n) * sc["chains"] * sc["sweeps"] * K * q
+        attempts += a
+        alg_ops += a * ops_per_attempt(K, q)
+    kern_s = float(np.mean(sel_lat)) / 1e3
+    achieved = alg_ops / kern_s
 
     desc = []
     for j in specs:
         if j["kind"] == "det":
             desc.append(f"uplink ML detection {j['rows']}x{j['cols']} {j['qam']}-QAM, SNR "
-                        f"{j['snr']:g} dB, " + ("random start" if j["init"] == 0 else
-                                                "start from the MMSE fallback"))
+                        f"{j['snr']:g} dB")
         else:
             desc.append(f"downlink VPP {j['rows']}x{j['cols']} {j['qam']}-QAM")
     out = {
@@ -320,7 +494,7 @@ def main(argv=None) -> int:  # noqa: C901
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": f_elapsed / args.steps * 1e3,
+        "ms_per_step": sel_el / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -328,23 +502,28 @@ def main(argv=None) -> int:  # noqa: C901
         "data": "synthetic",
         "config": {
             "workload": "; ".join(desc) + f"; {specs[0]['n_sc']} subcarriers x "
-                        f"{specs[0]['n_sym']} symbols per slot, "
-                        + ", ".join(f"{j['chains']} chains x {j['sweeps']} sweeps" for j in specs)
-                        + ", i.i.d. Rayleigh",
+                        f"{specs[0]['n_sym']} symbols per slot, i.i.d. Rayleigh; reference "
+                        + ", ".join(f"{j['chains']} chains x {j['sweeps']} sweeps" for j in specs),
             "name": args.workload,
             "path": "fused: one persistent build+anneal+select launch per slot, replayed as a "
                     "HIP graph",
+            "schedule": ("tuned: " + "; ".join(tuned["schedules"])) if use_tuned
+                        else "reference",
             "instances_per_step": total_inst,
             "work_items": n_items,
             "workgroups": n_blocks,
         },
-        "p50_slot_ms": float(np.percentile(f_lat, 50)),
-        "p99_slot_ms": float(np.percentile(f_lat, 99)),
-        "flip_attempts_per_s": attempts * args.steps / f_elapsed,
+        "p50_slot_ms": float(np.percentile(sel_lat, 50)),
+        "p99_slot_ms": float(np.percentile(sel_lat, 99)),
+        "flip_attempts_per_s": attempts * args.steps / sel_el,
         "plain": plain,
+        "fused_reference": {"value": args.steps * total_inst / f_el,
+                            "ms_per_step": f_el / args.steps * 1e3,
+                            "p99_slot_ms": float(np.percentile(f_lat, 99)),
+                            "quality": q_fused, "outputs_identical_to_plain": identical},
+        "tuned": tuned,
         "speedup_vs_plain": None if plain is None else value / plain["value"],
-        "outputs_identical_to_plain": identical,
-        "quality": quality,
+        "quality_kind": ["ser" if j["kind"] == "det" else "mean_gamma" for j in specs],
         "roofline": {
             "bound": "alu",
             "kernel": "k_fused",
@@ -353,7 +532,7 @@ def main(argv=None) -> int:  # noqa: C901
             "unit": "T lane-ops/s",
             "frac": achieved / PEAK_ALU_OPS,
             "traffic": stored_traffic(args.workload, "k_fused"),
-            "kernel_ms": fused_s * 1e3,
+            "kernel_ms": kern_s * 1e3,
             "ops_per_launch": alg_ops,
             "attempts_per_launch": attempts,
         },
@@ -367,7 +546,7 @@ def main(argv=None) -> int:  # noqa: C901
         torch.cuda.synchronize()
         del src, dst
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(inputs, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(inputs, sel_scheds, args.cpu_seconds)
     print(json.dumps(out), flush=True)
     return 0
 

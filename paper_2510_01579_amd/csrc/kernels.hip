@@ -42,8 +42,9 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
     for (int r = 0; r < 10; ++r) {
         const uint64_t pa = (uint64_t)0xD2511F53u * c[0];
         const uint64_t pb = (uint64_t)0xCD9E8D57u * c[2];
-        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c[1] ^ k0;
-        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c[3] ^ k1;
+        // three-input XOR in one instruction (truth table 0x96: odd parity)
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(pb >> 32), c[1], k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(pa >> 32), c[3], k1, 0x96);
         c[1] = (uint32_t)pb;
         c[3] = (uint32_t)pa;
         c[0] = n0;
