@@ -172,9 +172,12 @@ _tuned_cache = {}
 def tuned_schedule(kind: int, n_rx: int, n_tx: int, qam: int, noise_var: float = 0.0,
                    table: str = TUNED_TABLE) -> dict:
     """Schedule picked by the offline tuner (``python -m paper_2510_01579_amd.tune``)
-    for a job class: dict(chains, sweeps, init, beta2, tuned).  A class the
-    table does not hold gets the reference schedule of its size (tuned=False).
+    for a job: dict(chains, sweeps, init, beta2, tuned, snr_bucket).
 
+    Detection tables are bucketed by SNR = 10 log10(n_tx / noise_var) (per
+    receive antenna, unit-energy symbols): the job takes the bucket of the
+    smallest tuned SNR >= its own (the last bucket above the grid).  A class the
+    table does not hold gets the reference schedule of its size (tuned=False).
     The temperature shape (r, m) ends the linear-in-beta anneal at m beta1 and
     starts it at r m beta1 (r = 0: at the default beta0)."""
     import json
@@ -185,14 +188,23 @@ def tuned_schedule(kind: int, n_rx: int, n_tx: int, qam: int, noise_var: float =
                 _tuned_cache[table] = json.load(fh).get("classes", {})
     name = f"{'det' if kind == KIND_DET else 'vpp'}-{n_rx}x{n_tx}-{int(qam)}"
     rec = _tuned_cache[table].get(name)
+    bucket = None
     if rec is None:
         big = max(n_rx, n_tx) > 8
-        sched = dict(chains=128 if big and kind == KIND_DET else 64,
-                     sweeps=400 if big and kind == KIND_DET else 200,
+        sched = dict(chains=128 if big else 64, sweeps=400 if big else 200,
                      init=1 if (kind == KIND_DET and qam == 64) else 0, shape=[0.0, 1.0])
         tuned = False
     else:
-        sched = dict(rec["tuned"])
+        buckets = rec["buckets"]
+        pick = buckets[-1]
+        if kind == KIND_DET and buckets[0]["snr_db"] is not None:
+            snr = 10.0 * math.log10(n_tx / max(float(noise_var), 1e-30))
+            for b in buckets:                       # grid ascending
+                if b["snr_db"] >= snr - 1e-3:
+                    pick = b
+                    break
+        sched = dict(pick["tuned"])
+        bucket = pick["snr_db"]
         tuned = True
     b0, b1 = _det_range(qam, n_rx, noise_var) if kind == KIND_DET else _vpp_range(qam)
     r, m = sched.get("shape", [0.0, 1.0])
@@ -201,7 +213,7 @@ def tuned_schedule(kind: int, n_rx: int, n_tx: int, qam: int, noise_var: float =
     return dict(chains=int(sched["chains"]), sweeps=int(sched["sweeps"]),
                 init=int(sched["init"]), beta2=linear_beta2(int(sched["sweeps"]),
                                                             min(start, end), end),
-                tuned=tuned)
+                tuned=tuned, snr_bucket=bucket)
 
 
 class Context:

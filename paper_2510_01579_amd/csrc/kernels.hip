@@ -118,13 +118,16 @@ __device__ __forceinline__ void wave_sync_lds()
 }
 
 // ---------------------------------------------------------------------------
-// Detection build of one subcarrier (all threads of the block):
-//   Cg = H^H H (float64, upper triangle, mirrored)      -> G (real form, x c^2)
-//   F  = H^H y per symbol                               -> f (real form, x c)
+// Detection build of one subcarrier (all threads of the block, a multiple of
+// 64 of them):
+//   Cg = H^H H (float64 matrix cores, upper triangle mirrored) -> G (real form, x c^2)
+//   F  = H^H y per symbol (float64 matrix cores)               -> f (real form, x c)
 //   MMSE (Cg + sigma^2 I)^-1 F by LDL^H, sliced to the nearest PAM level.
 // Writes G (ld x ld, zero padded) to Gout and, for symbols sym0..sym0+ns-1,
 // the field rows to fout, the fallback levels to xout (if non-null) and ||y||^2
 // to ynorm (if non-null).  nt <= NT, nr <= 64, ns <= NS.
+typedef double mfma_v4d __attribute__((ext_vector_type(4)));
+
 template <int NT, int NS>
 struct DetSharedT {
     float2 Hs[64 * NT];
@@ -152,20 +155,68 @@ __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, i
         const int r = e / ld, cc = e % ld;
         if (r >= K || cc >= K) Gout[e] = 0.0f;
     }
+    // Gram X + iY = H^H H and fields F = H^H y on the matrix cores.  With the
+    // stacked real rows A = [Re H; Im H] (2 nr x nt):
+    //   X = A^T A,  Y = A^T [Im H; -Re H],
+    //   Re F = A^T [Re y; Im y],  Im F = A^T [Im y; -Re y],
+    // as 16 x 16 float64 tiles of v_mfma_f64_16x16x4f64 (inner dimension 2 nr in
+    // steps of 4), one tile per wavefront in turn: tile 0 -> X, tile 1 -> Y,
+    // tile 2 + c -> symbols 8c .. 8c+7 (Re F in columns 0..7, Im F in 8..15).
+    // Products of float32 values are exact in float64, so the result differs
+    // from a plain float64 loop only by summation order.
+    // Operand layout of the instruction: lane l supplies A[l % 16][l / 16] and
+    // B[l / 16][l % 16] and receives D[l / 16 + 4 j][l % 16], j = 0..3.
+    {
+        const int wave = tid >> 6, lane = tid & 63, nwave = nthr >> 6;
+        const int lrow = lane & 15, lk = lane >> 4;
+        const int n_inner = 2 * nr, ksteps = (n_inner + 3) / 4;
+        const int ntiles = 2 + (ns + 7) / 8;
+        double *Cgd = reinterpret_cast<double *>(sh.Cg);
+        double *Fsd = reinterpret_cast<double *>(sh.Fs);
+        for (int t = wave; t < ntiles; t += nwave) {
+            mfma_v4d acc = {0.0, 0.0, 0.0, 0.0};
+            const int s_col = (t - 2) * 8 + (lrow & 7);     // symbol of this lane's column
+            for (int ks = 0; ks < ksteps; ++ks) {
+                const int r2 = ks * 4 + lk;
+                const bool top = r2 < nr;
+                const int rr = top ? r2 : r2 - nr;
+                double a = 0.0, b = 0.0;
+                if (r2 < n_inner) {
+                    if (lrow < nt) {
+                        const float2 h = sh.Hs[rr * nt + lrow];
+                        a = top ? (double)h.x : (double)h.y;
+                        if (t == 0) b = a;
+                        else if (t == 1) b = top ? (double)h.y : -(double)h.x;
+                    }
+                    if (t >= 2 && s_col < ns) {
+                        const float2 yv = y[((size_t)sc * nsym + sym0 + s_col) * nr + rr];
+                        if (lrow < 8) b = top ? (double)yv.x : (double)yv.y;
+                        else b = top ? (double)yv.y : -(double)yv.x;
+                    }
+                }
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+            }
+            for (int j = 0; j < 4; ++j) {
+                const int row = lk + 4 * j;
+                if (row >= nt) continue;
+                if (t < 2) {
+                    if (lrow < nt) Cgd[2 * (row * NT + lrow) + t] = acc[j];
+                } else if (s_col < ns) {
+                    Fsd[2 * (s_col * NT + row) + (lrow >= 8 ? 1 : 0)] = acc[j];
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // exactly Hermitian: the upper triangle, mirrored, real diagonal
     const int npair = nt * (nt + 1) / 2;
     for (int p = tid; p < npair; p += nthr) {
         int ia, ib;
         upper_pair(p, nt, ia, ib);
-        double re = 0.0, im = 0.0;
-        for (int r = 0; r < nr; ++r) {
-            const float2 h1 = sh.Hs[r * nt + ia], h2 = sh.Hs[r * nt + ib];
-            const double ar = h1.x, ai = h1.y, br = h2.x, bi = h2.y;
-            const double pre = ar * br + ai * bi;   // conj(h1) h2
-            const double pim = ar * bi - ai * br;
-            re = re + pre;
-            im = im + pim;
-        }
-        if (ia == ib) im = 0.0;
+        const double2 v = sh.Cg[ia * NT + ib];
+        const double re = v.x;
+        const double im = ia == ib ? 0.0 : v.y;
         sh.Cg[ia * NT + ib] = make_double2(re, im);
         sh.Cg[ib * NT + ia] = make_double2(re, 0.0 - im);
         const float gre = (float)(c2 * re);
@@ -181,23 +232,12 @@ __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, i
         Gout[(nt + ia) * ld + ib] = gim;
         Gout[ib * ld + (nt + ia)] = gim;
     }
-
     for (int p = tid; p < ns * nt; p += nthr) {
         const int r0 = p / nt, ia = p % nt;
-        const float2 *ys = y + ((size_t)sc * nsym + sym0 + r0) * nr;
-        double re = 0.0, im = 0.0;
-        for (int r = 0; r < nr; ++r) {
-            const float2 h = sh.Hs[r * nt + ia];
-            const float2 yv = ys[r];
-            const double pre = (double)h.x * (double)yv.x + (double)h.y * (double)yv.y;
-            const double pim = (double)h.x * (double)yv.y - (double)h.y * (double)yv.x;
-            re = re + pre;
-            im = im + pim;
-        }
-        sh.Fs[r0 * NT + ia] = make_double2(re, im);
+        const double2 F = sh.Fs[r0 * NT + ia];
         float *fs = fout + (size_t)r0 * ldf;
-        fs[ia] = (float)(c * re);
-        fs[nt + ia] = (float)(c * im);
+        fs[ia] = (float)(c * F.x);
+        fs[nt + ia] = (float)(c * F.y);
     }
     for (int p = tid; p < ns * (ld - K); p += nthr) {
         const int r0 = p / (ld - K), k = K + p % (ld - K);
@@ -546,7 +586,8 @@ __device__ __forceinline__ float anneal_lane(const float *Gi, const float *fi,
     }
 
     for (int t = 0; t < sweeps; ++t) {
-        const float bd = 128.0f * beta2[t];            // exact: power-of-two scale
+        // the schedule through the scalar cache (wave-uniform)
+        const float bd = 128.0f * opaque(beta2)[t];    // exact: power-of-two scale
         uint32_t r[4] = {0u, 0u, 0u, 0u};
         // rows of G in scalar registers; with KT <= 16 the next row is loaded
         // one dimension ahead, with KT = 32 two rows do not fit the SGPR file

@@ -1,6 +1,6 @@
-"""Offline schedule tuner: per job class, the cheapest anneal schedule (chains,
-sweeps, start state, temperature shape) whose quality stays within a tolerance
-of the class's reference schedule at every SNR of the class's grid.
+"""Offline schedule tuner: per job class and SNR bucket, the cheapest anneal
+schedule (chains, sweeps, start state, temperature shape) whose quality stays
+within a tolerance of the class's reference schedule at that SNR.
 
 A schedule is linear in beta from beta_start to beta_end.  The reference shape
 is the class's default range (beta0, beta1) of ``workload.synth``; a shape
@@ -16,9 +16,17 @@ the anneal: lanes per instance (the chain count, rounded up to a power of two
 when instances share a wavefront, or to whole wavefronts above 32) x sweeps x
 attempts per sweep x operations per attempt.
 
-    python -m paper_2510_01579_amd.tune --out paper_2510_01579_amd/tuned_schedules.json
+A detection job of SNR s uses the bucket of the smallest grid SNR >= s (the
+last one above the grid): longer anneals are needed as the SNR grows, so this
+is the more demanding of the two neighbouring buckets.  VPP quality does not
+depend on an SNR: one bucket.
 
-Needs a GPU.  The table it writes is read by ``tuned_schedule`` in the package.
+    python -m paper_2510_01579_amd.tune --out paper_2510_01579_amd/tuned_schedules.json
+    python -m paper_2510_01579_amd.tune --reselect FILE --out FILE2   # no GPU
+
+Measuring needs a GPU; --reselect recomputes the choice from the quality
+measurements stored in a table.  The table is read by ``tuned_schedule`` in the
+package.
 """
 from __future__ import annotations
 
@@ -47,14 +55,16 @@ CLASSES = {
     "vpp-8x8-4": dict(ref=(64, 200, 0), snr=[None]),
     "vpp-8x8-16": dict(ref=(64, 200, 0), snr=[None]),
     "vpp-8x8-64": dict(ref=(64, 200, 0), snr=[None]),
-    "vpp-16x16-4": dict(ref=(64, 200, 0), snr=[None]),
-    "vpp-16x16-16": dict(ref=(64, 200, 0), snr=[None]),
-    "vpp-16x16-64": dict(ref=(64, 200, 0), snr=[None]),
+    "vpp-16x16-4": dict(ref=(128, 400, 0), snr=[None]),
+    "vpp-16x16-16": dict(ref=(128, 400, 0), snr=[None]),
+    "vpp-16x16-64": dict(ref=(128, 400, 0), snr=[None]),
 }
 CHAINS = (4, 8, 16, 32, 64, 128)
 SWEEPS = (12, 25, 50, 100, 200, 400)
 SHAPES = ((0.0, 1.0), (1.0 / 16, 1.0), (1.0 / 4, 1.0), (1.0 / 16, 4.0))
-TOLERANCE = 0.05
+TOLERANCE = 0.05             # the requirement: quality within 5% of the reference
+SELECT_TOLERANCE = 0.03      # used when choosing, so that other slots (other channel
+                             # and noise draws) keep within TOLERANCE
 
 
 def shaped_range(b0: float, b1: float, shape) -> tuple[float, float]:
@@ -90,6 +100,31 @@ def cost(name, chains, sweeps) -> float:
     q = {4: 1, 16: 2, 64: 3}[qam] if kind == "det" else 2
     KT = 8 if K <= 8 else (16 if K <= 16 else 32)
     return lanes_per_instance(chains) * sweeps * KT * q * (18.5 + KT / q)
+
+
+def parse_key(key):
+    sched, init, shape = key.split("/")
+    C, S = (int(v) for v in sched.split("x"))
+    r, m = (float(v) for v in shape.split(","))
+    return C, S, int(init), (r, m)
+
+
+def select(name, rec):
+    """Per SNR bucket, the cheapest measured schedule within SELECT_TOLERANCE of
+    the reference at that SNR (ties: fewer chains, fewer sweeps)."""
+    ref = rec["reference"]
+    ref_cost = cost(name, ref["chains"], ref["sweeps"])
+    buckets = []
+    for r in rec["per_snr"]:
+        ok = [parse_key(k) for k, v in r["cands"].items()
+              if v <= (1 + SELECT_TOLERANCE) * r["ref"] + 2e-5]
+        best = min(ok, key=lambda c: (cost(name, c[0], c[1]), c[0], c[1], c[2], c[3]))
+        buckets.append({"snr_db": r["snr_db"],
+                        "tuned": {"chains": best[0], "sweeps": best[1], "init": best[2],
+                                  "shape": list(best[3])},
+                        "quality": r["cands"][schedule_key(best)], "ref_quality": r["ref"],
+                        "cost_ratio": ref_cost / cost(name, best[0], best[1])})
+    return buckets
 
 
 def measure(ctx, name, snr, schedules, n_sc, n_sym, seed):
@@ -128,11 +163,30 @@ def main(argv=None) -> int:
     ap.add_argument("--n-sc", type=int, default=3276)
     ap.add_argument("--n-sym", type=int, default=12)
     ap.add_argument("--seed", type=int, default=7000)
+    ap.add_argument("--reselect", default=None,
+                    help="recompute the choice from the measurements in this table (no GPU)")
     args = ap.parse_args(argv)
+
+    if args.reselect:
+        with open(args.reselect) as fh:
+            table = json.load(fh)
+        table["tolerance"] = TOLERANCE
+        table["select_tolerance"] = SELECT_TOLERANCE
+        for name, rec in table["classes"].items():
+            rec["buckets"] = select(name, rec)
+            rec.pop("tuned", None)
+            rec.pop("cost_ratio", None)
+            print(name, [(b["snr_db"], b["tuned"]["chains"], b["tuned"]["sweeps"],
+                          b["tuned"]["init"], b["tuned"]["shape"], round(b["cost_ratio"], 2))
+                         for b in rec["buckets"]])
+        with open(args.out, "w") as fh:
+            json.dump(table, fh, indent=1)
+        return 0
 
     import paper_2510_01579_amd as M
     ctx = M.Context(0)
-    table = {"tolerance": TOLERANCE, "slot": [args.n_sc, args.n_sym], "classes": {}}
+    table = {"tolerance": TOLERANCE, "select_tolerance": SELECT_TOLERANCE,
+             "slot": [args.n_sc, args.n_sym], "classes": {}}
     if os.path.exists(args.out):
         with open(args.out) as fh:
             old = json.load(fh)
@@ -152,24 +206,17 @@ def main(argv=None) -> int:
             per_snr.append({"snr_db": snr, "ref": q[ref],
                             "cands": {schedule_key(c): v for c, v in q.items()}})
             print(f"  {name} snr {snr}: {len(q)} schedules", flush=True)
-        passing = []
-        for c in cands:
-            key = schedule_key(c)
-            ok = all(r["cands"][key] <= (1 + TOLERANCE) * r["ref"] + 2e-5 for r in per_snr)
-            if ok:
-                passing.append(c)
-        best = min(passing, key=lambda s: (cost(name, s[0], s[1]), s[0], s[1], s[3]))
-        table["classes"][name] = {
+        rec = {
             "reference": {"chains": ref[0], "sweeps": ref[1], "init": ref[2],
                           "shape": list(ref[3])},
-            "tuned": {"chains": best[0], "sweeps": best[1], "init": best[2],
-                      "shape": list(best[3])},
-            "cost_ratio": cost(name, ref[0], ref[1]) / cost(name, best[0], best[1]),
             "quality": "ser" if name.startswith("det") else "mean_gamma",
             "per_snr": per_snr,
         }
-        print(f"{name}: ref {ref} -> tuned {best}, cost ratio "
-              f"{table['classes'][name]['cost_ratio']:.2f} ({time.time() - t0:.1f} s)",
+        rec["buckets"] = select(name, rec)
+        table["classes"][name] = rec
+        print(f"{name}: ref {ref} -> " + ", ".join(
+            f"{b['snr_db']} dB {b['tuned']['chains']}x{b['tuned']['sweeps']}/{b['tuned']['init']}"
+            f" (x{b['cost_ratio']:.1f})" for b in rec["buckets"]) + f" ({time.time() - t0:.1f} s)",
               flush=True)
         with open(args.out, "w") as fh:
             json.dump(table, fh, indent=1)
