@@ -1,0 +1,73 @@
+"""The committed tuner table and the runtime bucket choice (no GPU)."""
+import json
+import math
+
+import numpy as np
+import pytest
+
+import paper_2510_01579_amd as M
+from paper_2510_01579_amd import tune as T
+from workload import synth as W
+
+
+@pytest.fixture(scope="module")
+def table():
+    with open(M.TUNED_TABLE) as fh:
+        return json.load(fh)
+
+
+def test_table_covers_every_class_with_sorted_buckets(table):
+    assert set(table["classes"]) == set(T.CLASSES)
+    for name, rec in table["classes"].items():
+        snrs = [b["snr_db"] for b in rec["buckets"]]
+        if name.startswith("vpp"):
+            assert snrs == [None]
+        else:
+            assert snrs == sorted(snrs) == T.CLASSES[name]["snr"]
+
+
+def test_every_choice_meets_the_selection_margin_and_is_not_dearer(table):
+    for name, rec in table["classes"].items():
+        ref = rec["reference"]
+        for b, meas in zip(rec["buckets"], rec["per_snr"]):
+            key = T.schedule_key((b["tuned"]["chains"], b["tuned"]["sweeps"], b["tuned"]["init"],
+                                  tuple(b["tuned"]["shape"])))
+            q = meas["cands"][key]
+            assert q <= (1 + table["select_tolerance"]) * meas["ref"] + 2e-5, (name, b)
+            assert T.cost(name, b["tuned"]["chains"], b["tuned"]["sweeps"]) <= \
+                T.cost(name, ref["chains"], ref["sweeps"])
+
+
+def test_reselect_reproduces_the_table(table, tmp_path):
+    src = tmp_path / "t.json"
+    out = tmp_path / "o.json"
+    src.write_text(json.dumps(table))
+    T.main(["--reselect", str(src), "--out", str(out)])
+    again = json.loads(out.read_text())
+    for name in table["classes"]:
+        assert again["classes"][name]["buckets"] == table["classes"][name]["buckets"]
+
+
+@pytest.mark.parametrize("snr,bucket", [(0.0, 5.0), (5.0, 5.0), (7.5, 10.0), (15.0, 15.0),
+                                        (15.2, 20.0), (25.0, 25.0), (40.0, 25.0)])
+def test_bucket_is_the_smallest_tuned_snr_at_or_above(snr, bucket):
+    t = M.tuned_schedule(M.KIND_DET, 8, 8, 16, W.noise_var(snr, 8))
+    assert t["tuned"] and t["snr_bucket"] == bucket
+
+
+def test_schedule_table_matches_generator_ranges(table):
+    """The beta table of a tuned schedule is the linear schedule between the
+    shaped ends of the default range."""
+    nv = W.noise_var(15.0, 8)
+    t = M.tuned_schedule(M.KIND_DET, 8, 8, 16, nv)
+    rec = [b for b in table["classes"]["det-8x8-16"]["buckets"] if b["snr_db"] == 15.0][0]
+    lo, hi = T.shaped_range(*W.det_beta_range(16, 8, nv), tuple(rec["tuned"]["shape"]))
+    assert np.array_equal(t["beta2"], W.linear_beta2(t["sweeps"], lo, hi))
+    assert t["beta2"].dtype == np.float32 and np.all(np.isfinite(t["beta2"]))
+
+
+def test_unknown_class_gets_the_reference_schedule():
+    t = M.tuned_schedule(M.KIND_DET, 6, 6, 16, 0.1)
+    assert not t["tuned"] and (t["chains"], t["sweeps"]) == (64, 200)
+    t = M.tuned_schedule(M.KIND_DET, 12, 12, 64, 0.1)
+    assert not t["tuned"] and (t["chains"], t["sweeps"], t["init"]) == (128, 400, 1)
