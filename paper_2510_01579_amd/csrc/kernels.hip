@@ -256,6 +256,10 @@ __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, i
     }
     if (!xout) return;   // uniform over the block
     __syncthreads();
+    // The factorisation and the solves are chains of dependent float64 steps
+    // on at most 16 rows: the first wavefront does them alone, synchronising
+    // through LDS at wavefront level instead of across the block.
+    if (tid >= 64) return;
 
     // LDL^H of Cg + sigma^2 I
     for (int j = 0; j < nt; ++j) {
@@ -269,8 +273,8 @@ __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, i
             }
             sh.ds[j] = dj;
         }
-        __syncthreads();
-        for (int i = j + 1 + tid; i < nt; i += nthr) {
+        wave_sync_lds();
+        for (int i = j + 1 + tid; i < nt; i += 64) {
             cd s = ld2(sh.Cg[i * NT + j]);
             for (int k = 0; k < j; ++k) {
                 cd v = cmulc(ld2(sh.Ls[j * NT + k]), ld2(sh.Ls[i * NT + k]));
@@ -281,10 +285,10 @@ __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, i
             }
             sh.Ls[i * NT + j] = make_double2(s.re / sh.ds[j], s.im / sh.ds[j]);
         }
-        __syncthreads();
+        wave_sync_lds();
     }
     // per-symbol solves in place on Fs, then slicing
-    for (int r0 = tid; r0 < ns; r0 += nthr) {
+    for (int r0 = tid; r0 < ns; r0 += 64) {
         double2 *w = sh.Fs + r0 * NT;
         for (int i = 0; i < nt; ++i) {
             cd s = ld2(w[i]);
@@ -371,42 +375,47 @@ __device__ void build_vpp_sc(const float2 *H, const float2 *u, int n, int ntx, i
     }
     __syncthreads();
 
-    for (int j = 0; j < n; ++j) {
-        if (tid == 0) {
-            double dj = sh.As[j * NU + j].x;
-            for (int k = 0; k < j; ++k) {
-                const double2 v = sh.Ls[j * NU + k];
-                double t = v.x * v.x + v.y * v.y;
-                t = t * sh.ds[k];
-                dj = dj - t;
+    // LDL^H and M = L^-1: chains of dependent float64 steps on at most 16
+    // rows, done by the first wavefront alone with wavefront-level
+    // synchronisation through LDS
+    if (tid < 64) {
+        for (int j = 0; j < n; ++j) {
+            if (tid == 0) {
+                double dj = sh.As[j * NU + j].x;
+                for (int k = 0; k < j; ++k) {
+                    const double2 v = sh.Ls[j * NU + k];
+                    double t = v.x * v.x + v.y * v.y;
+                    t = t * sh.ds[k];
+                    dj = dj - t;
+                }
+                sh.ds[j] = dj;
             }
-            sh.ds[j] = dj;
+            wave_sync_lds();
+            for (int i = j + 1 + tid; i < n; i += 64) {
+                cd s = ld2(sh.As[i * NU + j]);
+                for (int k = 0; k < j; ++k) {
+                    cd v = cmulc(ld2(sh.Ls[j * NU + k]), ld2(sh.Ls[i * NU + k]));
+                    v.re = v.re * sh.ds[k];
+                    v.im = v.im * sh.ds[k];
+                    s.re = s.re - v.re;
+                    s.im = s.im - v.im;
+                }
+                sh.Ls[i * NU + j] = make_double2(s.re / sh.ds[j], s.im / sh.ds[j]);
+            }
+            wave_sync_lds();
         }
-        __syncthreads();
-        for (int i = j + 1 + tid; i < n; i += nthr) {
-            cd s = ld2(sh.As[i * NU + j]);
-            for (int k = 0; k < j; ++k) {
-                cd v = cmulc(ld2(sh.Ls[j * NU + k]), ld2(sh.Ls[i * NU + k]));
-                v.re = v.re * sh.ds[k];
-                v.im = v.im * sh.ds[k];
-                s.re = s.re - v.re;
-                s.im = s.im - v.im;
+        // M = L^-1, one column per lane
+        for (int m = tid; m < n; m += 64) {
+            sh.Ms[m * NU + m] = make_double2(1.0, 0.0);
+            for (int i = m + 1; i < n; ++i) {
+                cd s{0.0, 0.0};
+                for (int k = m; k < i; ++k) {
+                    const cd v = cmul(ld2(sh.Ls[i * NU + k]), ld2(sh.Ms[k * NU + m]));
+                    s.re = s.re + v.re;
+                    s.im = s.im + v.im;
+                }
+                sh.Ms[i * NU + m] = make_double2(-s.re, -s.im);
             }
-            sh.Ls[i * NU + j] = make_double2(s.re / sh.ds[j], s.im / sh.ds[j]);
-        }
-        __syncthreads();
-    }
-    // M = L^-1, one column per thread
-    for (int m = tid; m < n; m += nthr) {
-        sh.Ms[m * NU + m] = make_double2(1.0, 0.0);
-        for (int i = m + 1; i < n; ++i) {
-            cd s{0.0, 0.0};
-            for (int k = m; k < i; ++k) {
-                const cd v = cmul(ld2(sh.Ls[i * NU + k]), ld2(sh.Ms[k * NU + m]));
-                s.re = s.re + v.re;
-                s.im = s.im + v.im;
-            }
-            sh.Ms[i * NU + m] = make_double2(-s.re, -s.im);
         }
     }
     __syncthreads();
@@ -1001,7 +1010,7 @@ struct FusedCommon {
     float terms[kWavesPerBlock][32];
     int lvs[kWavesPerBlock][32];
     double2 zsh[kWavesPerBlock][16];
-    int item;
+    int item;               // the current work item, published by thread 0
 };
 __shared__ FusedCommon g_fc;
 
