@@ -141,9 +141,8 @@ template <int NT, int NS>
 __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, int nsym, int sc,
                              int sym0, int ns, int ld, int ldf, int qtop, double c, double c2,
                              double noise_var, float *Gout, float *fout, signed char *xout,
-                             double *ynorm, DetSharedT<NT, NS> &sh)
+                             double *ynorm, DetSharedT<NT, NS> &sh, int tid)
 {
-    const int tid = threadIdx.x;
     const int nthr = blockDim.x;
     const int K = 2 * nt;
 
@@ -343,9 +342,9 @@ struct VppSharedT {
 template <int NU>
 __device__ void build_vpp_sc(const float2 *H, const float2 *u, int n, int ntx, int nsym, int sc,
                              int sym0, int ns, int ld, int ldf, double tau, float *Gout, float *fout,
-                             signed char *xout, double2 *Ainv_out, double *unorm, VppSharedT<NU> &sh)
+                             signed char *xout, double2 *Ainv_out, double *unorm, VppSharedT<NU> &sh,
+                             int tid)
 {
-    const int tid = threadIdx.x;
     const int nthr = blockDim.x;
     const int K = 2 * n;
     const double ht = 0.5 * tau;
@@ -841,7 +840,8 @@ __global__ void __launch_bounds__(kBlock) k_det_build(DetBuildArgs a)
     const size_t o = (size_t)sc * a.n_sym;
     build_det_sc(a.H, a.y, a.n_r, a.n_t, a.n_sym, sc, 0, a.n_sym, a.ld, a.ld, a.qtop, a.c, a.c2,
                  a.noise_var, a.G + (size_t)sc * a.ld * a.ld, a.f + o * a.ld,
-                 a.x_fb ? a.x_fb + o * a.ld : nullptr, a.ynorm ? a.ynorm + o : nullptr, sh);
+                 a.x_fb ? a.x_fb + o * a.ld : nullptr, a.ynorm ? a.ynorm + o : nullptr, sh,
+                 (int)threadIdx.x);
 }
 
 __global__ void __launch_bounds__(kBlock) k_vpp_build(VppBuildArgs a)
@@ -853,7 +853,7 @@ __global__ void __launch_bounds__(kBlock) k_vpp_build(VppBuildArgs a)
                  a.G + (size_t)sc * a.ld * a.ld, a.f + o * a.ld,
                  a.x_fb ? a.x_fb + o * a.ld : nullptr,
                  a.Ainv ? a.Ainv + (size_t)sc * a.n_u * a.n_u : nullptr,
-                 a.unorm ? a.unorm + o : nullptr, sh);
+                 a.unorm ? a.unorm + o : nullptr, sh, (int)threadIdx.x);
 }
 
 // One wavefront = 64 chains of one instance; chains > 64 use several
@@ -1072,7 +1072,7 @@ __device__ __forceinline__ double rfld(double v)
 // after another.
 template <int KT, int Q, bool PACKED>
 __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in, int sc_in,
-                                             int sym0_in, int ns_in)
+                                             int sym0_in, int ns_in, int tid)
 {
     constexpr int NW = (KT * Q + 31) / 32;
     // every descriptor field as a wave-uniform (scalar) value
@@ -1097,8 +1097,8 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
     void *out0 = uniform_ptr(jp->out0), *out1 = uniform_ptr(jp->out1);
     void *out2 = uniform_ptr(jp->out2);
 
-    const int wave = rfl(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
+    const int wave = rfl(tid >> 6);
+    const int lane = tid & 63;
     const float *Gi = Gbase + (size_t)sc * (KT * KT);
     if constexpr (PACKED) {
         const int gl = rfl(jp->glanes);
@@ -1206,12 +1206,12 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
 
 #define MMGAP_FUSED_CALL(kt, qq)                                             \
     do {                                                                     \
-        if (packed) fused_anneal<kt, qq, true>(jobs, it.job, it.sc, it.sym0, it.ns);  \
-        else fused_anneal<kt, qq, false>(jobs, it.job, it.sc, it.sym0, it.ns);        \
+        if (packed) fused_anneal<kt, qq, true>(jobs, it.job, it.sc, it.sym0, it.ns, tid);  \
+        else fused_anneal<kt, qq, false>(jobs, it.job, it.sc, it.sym0, it.ns, tid);        \
     } while (0)
 template <int CLS>
 __device__ __forceinline__ void fused_dispatch(int variant, bool packed, const FusedJob *jobs,
-                                               const FusedItem &it)
+                                               const FusedItem &it, int tid)
 {
     if constexpr (CLS == 0) {
         switch (variant) {
@@ -1252,6 +1252,11 @@ k_fused(const FusedJob *__restrict__ jobs, const FusedItem *__restrict__ items, 
         if (item >= n_items) break;           // every wavefront of the block leaves here
         const FusedItem it = items[item];
         const FusedJob &jb = jobs[it.job];
+        // The thread index, re-derived per item: every lane-dependent offset
+        // of the build, anneal and decode is then recomputed inside the loop
+        // rather than hoisted out of it and spilled to scratch memory.
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
         float *Gs = jb.G + (size_t)it.sc * jb.KT * jb.KT;
         for (int s0 = 0; s0 < it.ns; s0 += kFusedBuildSyms) {
             const int sym = it.sym0 + s0, cnt = min(kFusedBuildSyms, it.ns - s0);
@@ -1261,11 +1266,12 @@ k_fused(const FusedJob *__restrict__ jobs, const FusedItem *__restrict__ items, 
             if (jb.kind == 0) {
                 build_det_sc(jb.H, jb.y, jb.n_rows, jb.n_cols, jb.n_sym, it.sc, sym, cnt, jb.KT,
                              jb.ldf, (1 << jb.Q) - 1, jb.c, jb.c2, jb.noise_var, Gs, fs, xs,
-                             nullptr, bs.det);
+                             nullptr, bs.det, tid);
             } else {
                 build_vpp_sc(jb.H, jb.y, jb.n_rows, jb.n_cols, jb.n_sym, it.sc, sym, cnt, jb.KT,
                              jb.ldf, jb.tau, Gs, fs, xs,
-                             jb.Ainv + (size_t)it.sc * jb.n_rows * jb.n_rows, nullptr, bs.vpp);
+                             jb.Ainv + (size_t)it.sc * jb.n_rows * jb.n_rows, nullptr, bs.vpp,
+                             tid);
             }
         }
         // The couplings and fields were written with vector stores by this
@@ -1283,7 +1289,7 @@ k_fused(const FusedJob *__restrict__ jobs, const FusedItem *__restrict__ items, 
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        fused_dispatch<CLS>(jb.variant, jb.glanes > 0, jobs, it);
+        fused_dispatch<CLS>(jb.variant, jb.glanes > 0, jobs, it, tid);
     }
 }
 
