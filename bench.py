@@ -317,6 +317,19 @@ def run_serving(args, M, torch):
     }
 
 
+def build_bytes(j) -> float:
+    """Algorithmic HBM bytes of the plain build of one job: H and y (or u) in,
+    couplings [n_sc][KT][KT] float32, fields [n][KT] float32 and fallbacks
+    [n][KT] int8 out."""
+    K, q, n, _ = job_shape(j)
+    KT = 8 if K <= 8 else (16 if K <= 16 else 32)
+    n_rx = j["rows"]
+    n_tx = j["cols"]
+    h = j["n_sc"] * n_rx * n_tx * 8
+    y = n * n_rx * 8
+    return float(h + y + j["n_sc"] * KT * KT * 4 + n * KT * 4 + n * KT)
+
+
 def quality(inputs, outs):
     """Per job: symbol error rate (detection) or mean transmit energy (VPP)."""
     res = []
@@ -481,6 +494,14 @@ def main(argv=None) -> int:  # noqa: C901
                      "quality": q_t, "quality_matched": matched}
     ctx.close()
 
+    build_roof = None
+    if plain is not None:
+        b_bytes = sum(build_bytes(i["spec"]) for i in inputs)
+        b_s = plain["stage_ms"]["build"] / 1e3
+        build_roof = {"bound": "hbm", "kernel": "k_det_build / k_vpp_build (plain leg)",
+                      "achieved": b_bytes / b_s / 1e9, "peak": 8000.0, "unit": "GB/s",
+                      "frac": b_bytes / b_s / 8e12, "bytes_per_launch": b_bytes,
+                      "kernel_ms": b_s * 1e3}
     use_tuned = tuned is not None and tuned["quality_matched"]
     sel_el = t_el if use_tuned else f_el
     sel_lat = t_lat if use_tuned else f_lat
@@ -555,6 +576,7 @@ def main(argv=None) -> int:  # noqa: C901
             "ops_per_launch": alg_ops,
             "attempts_per_launch": attempts,
         },
+        "build_roofline": build_roof,
         "cpu_baseline": None,
     }
     if args.copy_calibration:

@@ -128,9 +128,16 @@ __device__ __forceinline__ void wave_sync_lds()
 // to ynorm (if non-null).  nt <= NT, nr <= 64, ns <= NS.
 typedef double mfma_v4d __attribute__((ext_vector_type(4)));
 
+// A complex float32 value in LDS scratch (a plain pair, so that the scratch
+// structs stay trivial types).
+struct cf32 {
+    float x, y;
+};
+__device__ __forceinline__ cf32 to_cf32(float2 v) { return cf32{v.x, v.y}; }
+
 template <int NT, int NS>
 struct DetSharedT {
-    float2 Hs[64 * NT];
+    cf32 Hs[64 * NT];
     double2 Cg[NT * NT];
     double2 Fs[NS * NT];
     double2 Ls[NT * NT];
@@ -147,7 +154,7 @@ __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, i
     const int K = 2 * nt;
 
     const float2 *Hg = H + (size_t)sc * nr * nt;
-    for (int e = tid; e < nr * nt; e += nthr) sh.Hs[e] = Hg[e];
+    for (int e = tid; e < nr * nt; e += nthr) sh.Hs[e] = to_cf32(Hg[e]);
     __syncthreads();
 
     for (int e = tid; e < ld * ld; e += nthr) {
@@ -182,7 +189,7 @@ __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, i
                 double a = 0.0, b = 0.0;
                 if (r2 < n_inner) {
                     if (lrow < nt) {
-                        const float2 h = sh.Hs[rr * nt + lrow];
+                        const cf32 h = sh.Hs[rr * nt + lrow];
                         a = top ? (double)h.x : (double)h.y;
                         if (t == 0) b = a;
                         else if (t == 1) b = top ? (double)h.y : -(double)h.x;
@@ -331,7 +338,7 @@ __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, i
 //   G = (tau/2)^2 Re-form(A^-1),  f = -(tau/2) Re-form(A^-1 u).
 template <int NU>
 struct VppSharedT {
-    float2 Hs[NU * 64];
+    cf32 Hs[NU * 64];
     double2 As[NU * NU];
     double2 Ls[NU * NU];
     double2 Ms[NU * NU];
@@ -352,7 +359,7 @@ __device__ void build_vpp_sc(const float2 *H, const float2 *u, int n, int ntx, i
     const double sf = -ht;
 
     const float2 *Hg = H + (size_t)sc * n * ntx;
-    for (int e = tid; e < n * ntx; e += nthr) sh.Hs[e] = Hg[e];
+    for (int e = tid; e < n * ntx; e += nthr) sh.Hs[e] = to_cf32(Hg[e]);
     __syncthreads();
 
     // A_il = sum_j H_ij conj(H_lj), i >= l
@@ -833,27 +840,44 @@ __device__ void decode_vpp(const int *lv, int n, int sc, int sy, int nsym, int n
 
 // ---------------------------------------------------------------------------
 // Plain path kernels.
-__global__ void __launch_bounds__(kBlock) k_det_build(DetBuildArgs a)
+// One wavefront per subcarrier, scratch sized for the problem (NT, NU = 8 or
+// 16) and symbols taken 16 at a time: the build is a chain of dependent
+// steps, so it pays to have every subcarrier in flight at once rather than
+// more threads on each.
+constexpr int kBuildBlock = 64;
+constexpr int kBuildSyms = 16;
+
+template <int NT>
+__global__ void __launch_bounds__(kBuildBlock) k_det_build(DetBuildArgs a)
 {
-    __shared__ DetSharedT<16, 64> sh;
+    __shared__ DetSharedT<NT, kBuildSyms> sh;
     const int sc = blockIdx.x;
-    const size_t o = (size_t)sc * a.n_sym;
-    build_det_sc(a.H, a.y, a.n_r, a.n_t, a.n_sym, sc, 0, a.n_sym, a.ld, a.ld, a.qtop, a.c, a.c2,
-                 a.noise_var, a.G + (size_t)sc * a.ld * a.ld, a.f + o * a.ld,
-                 a.x_fb ? a.x_fb + o * a.ld : nullptr, a.ynorm ? a.ynorm + o : nullptr, sh,
-                 (int)threadIdx.x);
+    for (int s0 = 0; s0 < a.n_sym; s0 += kBuildSyms) {
+        if (s0 > 0) __syncthreads();
+        const int cnt = min(kBuildSyms, a.n_sym - s0);
+        const size_t o = (size_t)sc * a.n_sym + s0;
+        build_det_sc(a.H, a.y, a.n_r, a.n_t, a.n_sym, sc, s0, cnt, a.ld, a.ld, a.qtop, a.c, a.c2,
+                     a.noise_var, a.G + (size_t)sc * a.ld * a.ld, a.f + o * a.ld,
+                     a.x_fb ? a.x_fb + o * a.ld : nullptr, a.ynorm ? a.ynorm + o : nullptr, sh,
+                     (int)threadIdx.x);
+    }
 }
 
-__global__ void __launch_bounds__(kBlock) k_vpp_build(VppBuildArgs a)
+template <int NU>
+__global__ void __launch_bounds__(kBuildBlock) k_vpp_build(VppBuildArgs a)
 {
-    __shared__ VppSharedT<16> sh;
+    __shared__ VppSharedT<NU> sh;
     const int sc = blockIdx.x;
-    const size_t o = (size_t)sc * a.n_sym;
-    build_vpp_sc(a.H, a.u, a.n_u, a.n_t, a.n_sym, sc, 0, a.n_sym, a.ld, a.ld, a.tau,
-                 a.G + (size_t)sc * a.ld * a.ld, a.f + o * a.ld,
-                 a.x_fb ? a.x_fb + o * a.ld : nullptr,
-                 a.Ainv ? a.Ainv + (size_t)sc * a.n_u * a.n_u : nullptr,
-                 a.unorm ? a.unorm + o : nullptr, sh, (int)threadIdx.x);
+    for (int s0 = 0; s0 < a.n_sym; s0 += kBuildSyms) {
+        if (s0 > 0) __syncthreads();
+        const int cnt = min(kBuildSyms, a.n_sym - s0);
+        const size_t o = (size_t)sc * a.n_sym + s0;
+        build_vpp_sc(a.H, a.u, a.n_u, a.n_t, a.n_sym, sc, s0, cnt, a.ld, a.ld, a.tau,
+                     a.G + (size_t)sc * a.ld * a.ld, a.f + o * a.ld,
+                     a.x_fb ? a.x_fb + o * a.ld : nullptr,
+                     a.Ainv ? a.Ainv + (size_t)sc * a.n_u * a.n_u : nullptr,
+                     a.unorm ? a.unorm + o : nullptr, sh, (int)threadIdx.x);
+    }
 }
 
 // One wavefront = 64 chains of one instance; chains > 64 use several
@@ -1014,11 +1038,16 @@ struct FusedCommon {
 };
 __shared__ FusedCommon g_fc;
 
-// Build scratch per class: detection with n_t <= NTD, VPP with n_u <= NUV.
+// Build scratch per class: detection with n_t <= NTD, VPP with n_u <= NUV,
+// sharing one block of LDS (a job is one or the other).
 template <int NTD, int NUV>
-union FusedBuildShared {
-    DetSharedT<NTD, kFusedBuildSyms> det;
-    VppSharedT<NUV> vpp;
+struct FusedBuildShared {
+    using Det = DetSharedT<NTD, kFusedBuildSyms>;
+    using Vpp = VppSharedT<NUV>;
+    static constexpr size_t kBytes = sizeof(Det) > sizeof(Vpp) ? sizeof(Det) : sizeof(Vpp);
+    alignas(16) unsigned char raw[kBytes];
+    __device__ Det &det() { return *reinterpret_cast<Det *>(raw); }
+    __device__ Vpp &vpp() { return *reinterpret_cast<Vpp *>(raw); }
 };
 template <int CLS> struct FusedClassTraits;
 template <> struct FusedClassTraits<0> {
@@ -1266,11 +1295,11 @@ k_fused(const FusedJob *__restrict__ jobs, const FusedItem *__restrict__ items, 
             if (jb.kind == 0) {
                 build_det_sc(jb.H, jb.y, jb.n_rows, jb.n_cols, jb.n_sym, it.sc, sym, cnt, jb.KT,
                              jb.ldf, (1 << jb.Q) - 1, jb.c, jb.c2, jb.noise_var, Gs, fs, xs,
-                             nullptr, bs.det, tid);
+                             nullptr, bs.det(), tid);
             } else {
                 build_vpp_sc(jb.H, jb.y, jb.n_rows, jb.n_cols, jb.n_sym, it.sc, sym, cnt, jb.KT,
                              jb.ldf, jb.tau, Gs, fs, xs,
-                             jb.Ainv + (size_t)it.sc * jb.n_rows * jb.n_rows, nullptr, bs.vpp,
+                             jb.Ainv + (size_t)it.sc * jb.n_rows * jb.n_rows, nullptr, bs.vpp(),
                              tid);
             }
         }
@@ -1410,14 +1439,16 @@ int fused_kernel_class(int variant)
 hipError_t launch_det_build(const DetBuildArgs &a, hipStream_t s)
 {
     if (a.n_sc <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_det_build, dim3(a.n_sc), dim3(kBlock), 0, s, a);
+    if (a.n_t <= 8) hipLaunchKernelGGL(k_det_build<8>, dim3(a.n_sc), dim3(kBuildBlock), 0, s, a);
+    else hipLaunchKernelGGL(k_det_build<16>, dim3(a.n_sc), dim3(kBuildBlock), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_vpp_build(const VppBuildArgs &a, hipStream_t s)
 {
     if (a.n_sc <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_vpp_build, dim3(a.n_sc), dim3(kBlock), 0, s, a);
+    if (a.n_u <= 8) hipLaunchKernelGGL(k_vpp_build<8>, dim3(a.n_sc), dim3(kBuildBlock), 0, s, a);
+    else hipLaunchKernelGGL(k_vpp_build<16>, dim3(a.n_sc), dim3(kBuildBlock), 0, s, a);
     return hipGetLastError();
 }
 
