@@ -371,7 +371,6 @@ int batch_layout(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, BatchLayout 
     L.o_items = lay.take(sizeof(mmgap::FusedItem) * std::max<size_t>(L.items.size(), 1));
     L.o_counters = lay.take(sizeof(unsigned int) * mmgap::kFusedClasses);
     L.ob.resize(n_jobs);
-    L.oG.resize(n_jobs);
     L.of.resize(n_jobs);
     L.ox.resize(n_jobs);
     L.oA.resize(n_jobs);
@@ -380,7 +379,6 @@ int batch_layout(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, BatchLayout 
     for (int j = 0; j < n_jobs; ++j) {
         const mmgap::FusedJob &f = L.jobs[j];
         const size_t ni = (size_t)f.n_sc * f.n_sym;
-        L.oG[j] = lay.take(sizeof(float) * (size_t)f.n_sc * f.KT * f.KT);
         L.of[j] = lay.take(sizeof(float) * ni * f.ldf);
         L.ox[j] = lay.take(ni * (size_t)f.KT);
         L.oA[j] = f.kind == MMGAP_KIND_VPP
@@ -396,7 +394,6 @@ void batch_bind(BatchLayout &L, char *base, std::vector<unsigned char> &image)
     for (size_t j = 0; j < L.jobs.size(); ++j) {
         mmgap::FusedJob &f = L.jobs[j];
         f.beta2 = reinterpret_cast<const float *>(base + L.ob[j]);
-        f.G = reinterpret_cast<float *>(base + L.oG[j]);
         f.f = reinterpret_cast<float *>(base + L.of[j]);
         f.x_fb = reinterpret_cast<signed char *>(base + L.ox[j]);
         f.Ainv = f.kind == MMGAP_KIND_VPP ? reinterpret_cast<double2 *>(base + L.oA[j]) : nullptr;

@@ -124,7 +124,6 @@ struct FusedJob {
     const float2 *H;
     const float2 *y;        // y (DET) or u (VPP)
     const float *beta2;     // [sweeps] device
-    float *G;               // [n_sc][KT][KT] scratch
     float *f;               // [n_sc*n_sym][ldf] scratch
     signed char *x_fb;      // [n_sc*n_sym][KT] scratch
     double2 *Ainv;          // [n_sc][n_u][n_u] scratch (VPP)

@@ -90,8 +90,8 @@ __device__ __forceinline__ void upper_pair(int p, int n, int &i, int &j)
 }
 
 // Hides a pointer's value from the optimiser so that loads through it are
-// issued where written (here: one dimension ahead) instead of being hoisted
-// out of the sweep loop into registers.  The result lives in the constant
+// issued where written instead of being hoisted out of the sweep loop into
+// registers.  The result lives in the constant
 // address space, so wave-uniform loads through it use the scalar cache.
 typedef const float __attribute__((address_space(4))) cfloat;
 __device__ __forceinline__ cfloat *opaque(const float *p)
@@ -513,8 +513,12 @@ __device__ __forceinline__ float load_field(const float *fi, int k)
 }
 
 // ---------------------------------------------------------------------------
-// The anneal of one lane.  G of the instance is wave-uniform and read through
-// the scalar cache one row ahead of use, as is f unless several instances share
+// The anneal of one lane.  G of the instance is wave-uniform: the caller stages
+// it in LDS (Gl, KT x KT floats, rows 16-byte aligned) and each row is read
+// when the sweep reaches its dimension with 128-bit loads that every lane of
+// the wavefront takes from the same address, so the row lands in vector
+// registers (products with vector operands issue faster than with scalar
+// ones).  f is read through the scalar cache unless several instances share
 // the wavefront (PACKED: f per lane, by vector loads).  Per lane the state is the
 // flip step of every spin, d_i = -2 w_b s_i (+-2w_b as float) -- or one bit per
 // spin (set = spin -1) for large problems, to keep enough wavefronts resident --
@@ -529,7 +533,7 @@ __device__ __forceinline__ float load_field(const float *fi, int k)
 // Returns the final energy sum_k x_k (g_k - f_k); `bits` receives the final
 // spins (bit set = spin -1).
 template <int KT, int Q, bool PACKED = false>
-__device__ __forceinline__ float anneal_lane(const float *Gi, const float *fi,
+__device__ __forceinline__ float anneal_lane(const float *Gl, const float *fi,
                                              const signed char *xfb_i, const float *beta2,
                                              const uint32_t *T, int sweeps, const int (&wts)[4],
                                              uint32_t key0, uint32_t key1, int init_mode,
@@ -604,38 +608,29 @@ __device__ __forceinline__ float anneal_lane(const float *Gi, const float *fi,
         // the schedule through the scalar cache (wave-uniform)
         const float bd = 128.0f * opaque(beta2)[t];    // exact: power-of-two scale
         uint32_t r[4] = {0u, 0u, 0u, 0u};
-        // rows of G in scalar registers; with KT <= 16 the next row is loaded
-        // one dimension ahead, with KT = 32 two rows do not fit the SGPR file
-        // (nor, packed, with KT = 16: the per-lane field loads need the room)
-        constexpr bool kPrefetch = PACKED ? KT <= 8 : KT <= 16;
-        float grow[KT];
-        float fk = 0.0f;
-        if (kPrefetch) {
-            cfloat *base = opaque(Gi);
-#pragma unroll
-            for (int l = 0; l < KT; ++l) grow[l] = base[l];
-            fk = load_field<PACKED>(fi, 0);
-        }
+        // a row offset the optimiser cannot see through, so that the row loads
+        // stay inside the sweep instead of being hoisted into registers
+        int roff = 0;
+        asm volatile("" : "+v"(roff));
+        const float4 *G4 = reinterpret_cast<const float4 *>(Gl) + roff;
 #pragma unroll
         for (int k = 0; k < KT; ++k) {
-            if (!kPrefetch) {
-                cfloat *base = opaque(Gi);
+            float grow[KT];
 #pragma unroll
-                for (int l = 0; l < KT; ++l) grow[l] = base[k * KT + l];
-                fk = load_field<PACKED>(fi, k);
+            for (int l4 = 0; l4 < KT / 4; ++l4) {
+                const float4 v = G4[k * (KT / 4) + l4];
+                grow[4 * l4 + 0] = v.x;
+                grow[4 * l4 + 1] = v.y;
+                grow[4 * l4 + 2] = v.z;
+                grow[4 * l4 + 3] = v.w;
             }
+            const float fk = load_field<PACKED>(fi, k);
             // local field of dimension k from the current levels
             float g = -fk;
 #pragma unroll
             for (int l = 0; l < KT; ++l) g = fmaf(grow[l], x[l], g);
             const float gkk = grow[k];
             const float gkh = 0.5f * gkk;                  // exact
-            if (kPrefetch && k + 1 < KT) {                 // next row, issued early
-                cfloat *base = opaque(Gi);
-#pragma unroll
-                for (int l = 0; l < KT; ++l) grow[l] = base[(k + 1) * KT + l];
-                fk = load_field<PACKED>(fi, k + 1);
-            }
 #pragma unroll
             for (int b = 0; b < Q; ++b) {
                 const int i = k * Q + b;
@@ -672,7 +667,7 @@ __device__ __forceinline__ float anneal_lane(const float *Gi, const float *fi,
     for (int k = 0; k < KT; ++k) {
         float acc = -fi[k];
 #pragma unroll
-        for (int l = 0; l < KT; ++l) acc = fmaf(Gi[k * KT + l], x[l], acc);
+        for (int l = 0; l < KT; ++l) acc = fmaf(Gl[k * KT + l], x[l], acc);
         const float diff = acc - fi[k];
         E = fmaf(x[k], diff, E);
     }
@@ -883,10 +878,16 @@ __global__ void __launch_bounds__(kBuildBlock) k_vpp_build(VppBuildArgs a)
 // One wavefront = 64 chains of one instance; chains > 64 use several
 // wavefronts.  PACKED: one wavefront = 64 / glanes instances of glanes lanes
 // each (glanes a power of two >= chains, <= 32), all sharing one G -- the host
-// guarantees that 64 / glanes divides inst_per_G.  Writes every chain's final
-// energy and spin words.
+// guarantees that 64 / glanes divides inst_per_G.  Each wavefront stages its
+// G in LDS.  Writes every chain's final energy and spin words.
+template <int KT, int Q>
+constexpr int anneal_min_waves()
+{
+    return KT <= 8 ? 8 : KT == 16 ? (Q == 3 ? 4 : 6) : (Q == 1 ? 5 : 4);
+}
 template <int KT, int Q, bool PACKED>
 __global__ void __launch_bounds__(kBlock)
+    __attribute__((amdgpu_waves_per_eu(anneal_min_waves<KT, Q>(), 8)))
 k_anneal(const float *__restrict__ G, int inst_per_G, const float *__restrict__ f,
          const signed char *__restrict__ x_fb, const float *__restrict__ beta2,
          const uint32_t *__restrict__ accept_table, int sweeps, int chains, int n_inst, int w0,
@@ -895,6 +896,7 @@ k_anneal(const float *__restrict__ G, int inst_per_G, const float *__restrict__ 
 {
     constexpr int NW = (KT * Q + 31) / 32;
     __shared__ uint32_t T[kAcceptSteps + 1];
+    __shared__ float4 Gw[kWavesPerBlock][KT * KT / 4];   // each wavefront's copy of its G
     for (int e = threadIdx.x; e <= kAcceptSteps; e += kBlock) T[e] = accept_table[e];
     __syncthreads();
 
@@ -921,11 +923,14 @@ k_anneal(const float *__restrict__ G, int inst_per_G, const float *__restrict__ 
         ch = (gw - inst * wpi) * 64 + lane;
     }
     const float *Gi = G + (size_t)(inst0 / inst_per_G) * (KT * KT);
+    float *Gs = reinterpret_cast<float *>(Gw[wave]);
+    for (int e = lane; e < KT * KT; e += 64) Gs[e] = Gi[e];
+    wave_sync_lds();
     const float *fi = f + (size_t)inst * KT;
     const signed char *xi = x_fb ? x_fb + (size_t)inst * KT : nullptr;
     const int wts[4] = {w0, w1, w2, w3};
     uint32_t bits[NW];
-    const float E = anneal_lane<KT, Q, PACKED>(Gi, fi, xi, beta2, T, sweeps, wts, key0, key1,
+    const float E = anneal_lane<KT, Q, PACKED>(Gs, fi, xi, beta2, T, sweeps, wts, key0, key1,
                                                init_mode, (uint32_t)ch, (uint32_t)inst, bits);
     if (valid && ch < chains) {
         const size_t o = (size_t)inst * chains + ch;
@@ -1039,13 +1044,17 @@ struct FusedCommon {
 __shared__ FusedCommon g_fc;
 
 // Build scratch per class: detection with n_t <= NTD, VPP with n_u <= NUV,
-// sharing one block of LDS (a job is one or the other).
+// sharing one block of LDS (a job is one or the other), and the couplings G of
+// the current item (one subcarrier: KT x KT floats, KT <= 2 max(NTD, NUV)),
+// which the build writes here and the anneal reads.
 template <int NTD, int NUV>
 struct FusedBuildShared {
     using Det = DetSharedT<NTD, kFusedBuildSyms>;
     using Vpp = VppSharedT<NUV>;
     static constexpr size_t kBytes = sizeof(Det) > sizeof(Vpp) ? sizeof(Det) : sizeof(Vpp);
+    static constexpr int kGT = 2 * (NTD > NUV ? NTD : NUV);
     alignas(16) unsigned char raw[kBytes];
+    alignas(16) float G[kGT * kGT];
     __device__ Det &det() { return *reinterpret_cast<Det *>(raw); }
     __device__ Vpp &vpp() { return *reinterpret_cast<Vpp *>(raw); }
 };
@@ -1101,7 +1110,7 @@ __device__ __forceinline__ double rfld(double v)
 // after another.
 template <int KT, int Q, bool PACKED>
 __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in, int sc_in,
-                                             int sym0_in, int ns_in, int tid)
+                                             int sym0_in, int ns_in, const float *Gi, int tid)
 {
     constexpr int NW = (KT * Q + 31) / 32;
     // every descriptor field as a wave-uniform (scalar) value
@@ -1119,7 +1128,6 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
     const float2 *H = uniform_ptr(jp->H);
     const float2 *y = uniform_ptr(jp->y);
     const float *beta2 = uniform_ptr(jp->beta2);
-    const float *Gbase = uniform_ptr(jp->G);
     const float *fbase = uniform_ptr(jp->f);
     const signed char *xbase = uniform_ptr(jp->x_fb);
     const double2 *Abase = uniform_ptr(jp->Ainv);
@@ -1128,7 +1136,6 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
 
     const int wave = rfl(tid >> 6);
     const int lane = tid & 63;
-    const float *Gi = Gbase + (size_t)sc * (KT * KT);
     if constexpr (PACKED) {
         const int gl = rfl(jp->glanes);
         const int lg = __builtin_ctz((unsigned)gl);
@@ -1233,14 +1240,14 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
     }
 }
 
-#define MMGAP_FUSED_CALL(kt, qq)                                             \
-    do {                                                                     \
-        if (packed) fused_anneal<kt, qq, true>(jobs, it.job, it.sc, it.sym0, it.ns, tid);  \
-        else fused_anneal<kt, qq, false>(jobs, it.job, it.sc, it.sym0, it.ns, tid);        \
+#define MMGAP_FUSED_CALL(kt, qq)                                                      \
+    do {                                                                              \
+        if (packed) fused_anneal<kt, qq, true>(jobs, it.job, it.sc, it.sym0, it.ns, G, tid);  \
+        else fused_anneal<kt, qq, false>(jobs, it.job, it.sc, it.sym0, it.ns, G, tid);        \
     } while (0)
 template <int CLS>
 __device__ __forceinline__ void fused_dispatch(int variant, bool packed, const FusedJob *jobs,
-                                               const FusedItem &it, int tid)
+                                               const FusedItem &it, const float *G, int tid)
 {
     if constexpr (CLS == 0) {
         switch (variant) {
@@ -1286,7 +1293,8 @@ k_fused(const FusedJob *__restrict__ jobs, const FusedItem *__restrict__ items, 
         // rather than hoisted out of it and spilled to scratch memory.
         int tid = threadIdx.x;
         asm volatile("" : "+v"(tid));
-        float *Gs = jb.G + (size_t)it.sc * jb.KT * jb.KT;
+        // the couplings of the item's subcarrier go to LDS (rows of KT floats)
+        float *Gs = bs.G;
         for (int s0 = 0; s0 < it.ns; s0 += kFusedBuildSyms) {
             const int sym = it.sym0 + s0, cnt = min(kFusedBuildSyms, it.ns - s0);
             float *fs = jb.f + ((size_t)it.sc * jb.n_sym + sym) * jb.ldf;
@@ -1303,22 +1311,20 @@ k_fused(const FusedJob *__restrict__ jobs, const FusedItem *__restrict__ items, 
                              tid);
             }
         }
-        // The couplings and fields were written with vector stores by this
-        // workgroup and are read back through the scalar cache, which vector
-        // stores do not update.  (1) Every thread waits until its stores are
-        // acknowledged by the L2 of this XCD before the barrier (a
-        // workgroup-scope release alone emits no such wait; an agent-scope one
-        // would also write back and invalidate the L2).  (2) No scalar-cache
-        // line can hold a stale copy: a line is read only after this workgroup
-        // wrote it -- coupling slots (>= 256 B) start on 256-byte boundaries and
-        // field rows are padded to 128 bytes (ldf), so that no line holds data of
-        // two work items; other items of the same subcarrier write identical
-        // couplings.
+        // The fields were written with vector stores by this workgroup and are
+        // read back through the scalar cache, which vector stores do not
+        // update.  (1) Every thread waits until its stores are acknowledged by
+        // the L2 of this XCD before the barrier (a workgroup-scope release
+        // alone emits no such wait; an agent-scope one would also write back
+        // and invalidate the L2).  (2) No scalar-cache line can hold a stale
+        // copy: a line is read only after this workgroup wrote it -- field rows
+        // are padded to 128 bytes (ldf), so that no line holds data of two work
+        // items.  The fallback levels are read with vector loads.
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        fused_dispatch<CLS>(jb.variant, jb.glanes > 0, jobs, it, tid);
+        fused_dispatch<CLS>(jb.variant, jb.glanes > 0, jobs, it, bs.G, tid);
     }
 }
 

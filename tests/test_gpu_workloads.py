@@ -1,0 +1,188 @@
+"""GPU parity at the full workload sizes, in the launch configuration that the
+benchmark times: one graph-captured fused plan per workload, at the reference
+schedule and at the schedule the offline tuner picked.
+
+The oracle recomputes a spread sample of instances one by one (all of them for
+the 4x4 QPSK slot); properties that hold at any size are checked on every
+instance of the slot: the reported metric is the FP64 value of the reported
+answer, and never worse than the fallback's (MMSE for detection, plain ZF for
+VPP), since the fallback takes part in the selection (paper §3.2, §3.3).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O
+from workload import synth as W
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # collected on CPU hosts only with -m gpu
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2510_01579_amd as M
+
+N_SC, N_SYM = 3276, 12
+
+# name -> [(kind, rows, cols, qam, chains, sweeps, snr_db, seed, init, n_sc, n_sym)];
+# the same slots (seeds, SNR, reference schedules) as the benchmark's workloads
+WORKLOADS = {
+    "det-4x4-qpsk": [("det", 4, 4, 4, 32, 100, 10.0, 0, 0, 64, 1)],
+    "det-8x8-16qam": [("det", 8, 8, 16, 64, 200, 15.0, 2001, 0, N_SC, N_SYM)],
+    "det-16x16-64qam": [("det", 16, 16, 64, 128, 400, 25.0, 3001, 1, N_SC, N_SYM)],
+    "vpp-8x8+16x16-16qam": [("vpp", 8, 8, 16, 64, 200, None, 4001, 0, N_SC, N_SYM),
+                            ("vpp", 16, 16, 16, 128, 400, None, 4002, 0, N_SC, N_SYM)],
+}
+SAMPLES = {"det-8x8-16qam": 160, "det-16x16-64qam": 40, "vpp-8x8+16x16-16qam": 48}
+
+
+def note(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def assert_rows_equal(gpu, ora, e_gpu, e_ora, frac=1e-4, tol=1e-5):
+    """Same answers for all but a fraction `frac` of the instances, and those
+    only where the two energies differ by less than `tol`."""
+    gpu = np.asarray(gpu).reshape(len(gpu), -1)
+    ora = np.asarray(ora).reshape(len(ora), -1)
+    bad = np.where(np.any(gpu != ora, axis=1))[0]
+    assert len(bad) <= int(math.floor(frac * len(gpu))), \
+        f"{len(bad)} of {len(gpu)} instances differ: {bad[:10]}"
+    if len(bad):
+        assert np.all(np.abs(np.asarray(e_gpu)[bad] - np.asarray(e_ora)[bad]) < tol)
+
+
+def slot_inputs(spec):
+    kind, a, b, qam, chains, sweeps, snr, seed, init, n_sc, n_sym = spec
+    if kind == "det":
+        d = W.det_slot(seed, a, b, qam, n_sc, n_sym, snr)
+        beta2 = W.linear_beta2(sweeps, *W.det_beta_range(qam, a, d.noise_var))
+        return dict(kind=kind, raw=d, H=d.H, y=d.y, noise_var=d.noise_var, qam=qam,
+                    sched=dict(chains=chains, sweeps=sweeps, init=init, beta2=beta2),
+                    seed=W.job_seed(seed))
+    s = W.vpp_slot(seed, a, b, qam, n_sc, n_sym)
+    beta2 = W.linear_beta2(sweeps, *W.vpp_beta_range(qam, b))
+    return dict(kind=kind, raw=s, H=s.H, y=s.u, noise_var=0.0, qam=qam,
+                sched=dict(chains=chains, sweeps=sweeps, init=init, beta2=beta2),
+                seed=W.job_seed(seed))
+
+
+def tuned(inp, spec):
+    kind = M.KIND_DET if spec[0] == "det" else M.KIND_VPP
+    ts = M.tuned_schedule(kind, spec[1], spec[2], spec[3], inp["noise_var"])
+    return ts if ts["tuned"] else inp["sched"]
+
+
+def same_schedule(a, b):
+    return (a["chains"], a["sweeps"], a["init"]) == (b["chains"], b["sweeps"], b["init"]) and \
+        np.array_equal(np.asarray(a["beta2"]), np.asarray(b["beta2"]))
+
+
+def run_plan(ctx, inputs, scheds):
+    """One graph-captured plan over all jobs, launched twice (the second launch
+    must leave the first's answers unchanged)."""
+    jobs = []
+    for inp, s in zip(inputs, scheds):
+        H, y = dev(inp["H"]), dev(inp["y"])
+        if inp["kind"] == "det":
+            jobs.append(ctx.det_job(H, y, inp["qam"], inp["noise_var"], s["chains"], s["sweeps"],
+                                    s["beta2"], inp["seed"], init=s["init"]))
+        else:
+            jobs.append(ctx.vpp_job(H, y, inp["qam"], s["chains"], s["sweeps"], s["beta2"],
+                                    inp["seed"], init=s["init"]))
+    plan = ctx.plan_create(jobs, graph=True)
+    outs = []
+    for _ in range(2):
+        plan.plan_launch()
+        torch.cuda.synchronize()
+        outs.append([{k: t.cpu().numpy() for k, t in j["outputs"].items() if t is not None}
+                     for j in jobs])
+    plan.plan_destroy()
+    for a, b in zip(*outs):
+        for k in a:
+            assert a[k].tobytes() == b[k].tobytes(), f"relaunch changed {k}"
+    return outs[1]
+
+
+def sample_ids(n, k, seed):
+    if k is None or k >= n:
+        return np.arange(n, dtype=np.uint32)
+    rng = np.random.default_rng(seed)
+    ids = np.concatenate([rng.choice(n, k, replace=False), [0, 1, N_SYM - 1, N_SYM, n - 1]])
+    return np.unique(ids).astype(np.uint32)
+
+
+def check_det(inp, sched, out, n_sample):
+    d, qam = inp["raw"], inp["qam"]
+    n = d.y.shape[0] * d.y.shape[1]
+    sym, met = out["sym"], out["metric"].astype(np.float64)
+    ids = sample_ids(n, n_sample, 7)
+    ref = O.detect(d.H, d.y, d.noise_var, qam, sched["chains"], sched["sweeps"], sched["beta2"],
+                   inp["seed"], inst_ids=ids, init_mode=sched["init"])
+    assert_rows_equal(sym[ids], ref["sym"], met[ids], ref["metric"])
+    assert np.allclose(met[ids], ref["metric"], rtol=1e-4, atol=1e-6)
+    # every instance: metric = FP64 residual of the symbols, <= MMSE's residual
+    li, lq = W.symbol_levels(sym, qam)
+    m64 = O.det_metric(d.H, d.y, np.concatenate([li, lq], axis=1), qam)
+    assert np.allclose(met, m64, rtol=1e-4, atol=1e-6)
+    xfb = O.slice_levels(O.mmse(d.H, d.y, d.noise_var), qam).reshape(n, -1)
+    assert np.all(m64 <= O.det_metric(d.H, d.y, xfb, qam) * (1 + 1e-5) + 1e-6)
+
+
+def check_vpp(inp, sched, out, n_sample):
+    s, qam = inp["raw"], inp["qam"]
+    n_sc, n_sym, n_u = s.u.shape
+    n = n_sc * n_sym
+    v, x, gam = out["v"], out["x"].astype(np.complex128), out["gamma"].astype(np.float64)
+    ids = sample_ids(n, n_sample, 8)
+    ref = O.vpp_precode(s.H, s.u, qam, sched["chains"], sched["sweeps"], sched["beta2"],
+                        inp["seed"], inst_ids=ids, init_mode=sched["init"])
+    assert_rows_equal(v[ids], ref["v"], gam[ids], ref["gamma"])
+    assert np.allclose(gam[ids], ref["gamma"], rtol=1e-4, atol=1e-6)
+    # every instance: x = W (u + tau v) and gamma = ||x||^2 in FP64, <= plain ZF's
+    tau = O.vpp_tau(qam)
+    Wzf = O.zf_precoder(s.H)                                     # [n_sc][n_t][n_u]
+    u = s.u.reshape(n, n_u).astype(np.complex128)
+    pert = u + tau * (v[:, :n_u] + 1j * v[:, n_u:])
+    Wi = np.repeat(Wzf, n_sym, axis=0)
+    x64 = np.einsum("ntu,nu->nt", Wi, pert)
+    g64 = (np.abs(x64) ** 2).sum(-1)
+    assert np.allclose(gam, g64, rtol=1e-4, atol=1e-6)
+    assert np.allclose(x, x64, rtol=1e-4, atol=1e-5 * np.abs(x64).max())
+    g_zf = (np.abs(np.einsum("ntu,nu->nt", Wi, u)) ** 2).sum(-1)
+    assert np.all(g64 <= g_zf * (1 + 1e-5) + 1e-6)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = M.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("schedule", ["reference", "tuned"])
+@pytest.mark.parametrize("name", sorted(WORKLOADS))
+def test_workload_fused_plan_matches_oracle(ctx, name, schedule):
+    specs = WORKLOADS[name]
+    inputs = [slot_inputs(s) for s in specs]
+    scheds = [inp["sched"] if schedule == "reference" else tuned(inp, s)
+              for inp, s in zip(inputs, specs)]
+    if schedule == "tuned" and all(same_schedule(t, inp["sched"]) for t, inp in zip(scheds, inputs)):
+        pytest.skip(f"the tuned schedule of {name} is its reference schedule")
+    note(f"{name} {schedule}: " + ", ".join(f"{s['chains']}x{s['sweeps']} init {s['init']}"
+                                            for s in scheds))
+    outs = run_plan(ctx, inputs, scheds)
+    for inp, s, out in zip(inputs, scheds, outs):
+        if inp["kind"] == "det":
+            check_det(inp, s, out, SAMPLES.get(name))
+        else:
+            check_vpp(inp, s, out, SAMPLES.get(name))
