@@ -373,7 +373,6 @@ int batch_layout(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, BatchLayout 
     L.ob.resize(n_jobs);
     L.of.resize(n_jobs);
     L.ox.resize(n_jobs);
-    L.oA.resize(n_jobs);
     for (int j = 0; j < n_jobs; ++j) L.ob[j] = lay.take(sizeof(float) * L.betas[j].size());
     L.header_bytes = lay.off;
     for (int j = 0; j < n_jobs; ++j) {
@@ -381,9 +380,6 @@ int batch_layout(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, BatchLayout 
         const size_t ni = (size_t)f.n_sc * f.n_sym;
         L.of[j] = lay.take(sizeof(float) * ni * f.ldf);
         L.ox[j] = lay.take(ni * (size_t)f.KT);
-        L.oA[j] = f.kind == MMGAP_KIND_VPP
-                      ? lay.take(sizeof(double2) * (size_t)f.n_sc * f.n_rows * f.n_rows)
-                      : 0;
     }
     L.bytes = lay.off;
     return MMGAP_OK;
@@ -396,7 +392,6 @@ void batch_bind(BatchLayout &L, char *base, std::vector<unsigned char> &image)
         f.beta2 = reinterpret_cast<const float *>(base + L.ob[j]);
         f.f = reinterpret_cast<float *>(base + L.of[j]);
         f.x_fb = reinterpret_cast<signed char *>(base + L.ox[j]);
-        f.Ainv = f.kind == MMGAP_KIND_VPP ? reinterpret_cast<double2 *>(base + L.oA[j]) : nullptr;
     }
     image.assign(L.header_bytes, 0);
     if (!L.jobs.empty())

@@ -126,7 +126,6 @@ struct FusedJob {
     const float *beta2;     // [sweeps] device
     float *f;               // [n_sc*n_sym][ldf] scratch
     signed char *x_fb;      // [n_sc*n_sym][KT] scratch
-    double2 *Ainv;          // [n_sc][n_u][n_u] scratch (VPP)
     void *out0, *out1, *out2;   // DET: sym, metric; VPP: v, x, gamma
 };
 // A work item: symbols sym0..sym0+ns-1 of subcarrier sc of job `job`.

@@ -615,21 +615,32 @@ __device__ __forceinline__ float anneal_lane(const float *Gl, const float *fi,
         const float4 *G4 = reinterpret_cast<const float4 *>(Gl) + roff;
 #pragma unroll
         for (int k = 0; k < KT; ++k) {
-            float grow[KT];
-#pragma unroll
-            for (int l4 = 0; l4 < KT / 4; ++l4) {
-                const float4 v = G4[k * (KT / 4) + l4];
-                grow[4 * l4 + 0] = v.x;
-                grow[4 * l4 + 1] = v.y;
-                grow[4 * l4 + 2] = v.z;
-                grow[4 * l4 + 3] = v.w;
-            }
             const float fk = load_field<PACKED>(fi, k);
-            // local field of dimension k from the current levels
+            // local field of dimension k from the current levels; PACKED reads
+            // the row in chunks of 8 floats, each issued after the previous
+            // chunk's products (the per-lane field loads leave fewer registers)
+            constexpr int kChunk = PACKED ? 8 : KT;
             float g = -fk;
+            float gkk = 0.0f;
 #pragma unroll
-            for (int l = 0; l < KT; ++l) g = fmaf(grow[l], x[l], g);
-            const float gkk = grow[k];
+            for (int c0 = 0; c0 < KT; c0 += kChunk) {
+                int coff = k * (KT / 4) + c0 / 4;
+                if (c0 > 0) asm volatile("" : "+v"(coff) : "v"(g));
+                float grow[kChunk];
+#pragma unroll
+                for (int l4 = 0; l4 < kChunk / 4; ++l4) {
+                    const float4 v = G4[coff + l4];
+                    grow[4 * l4 + 0] = v.x;
+                    grow[4 * l4 + 1] = v.y;
+                    grow[4 * l4 + 2] = v.z;
+                    grow[4 * l4 + 3] = v.w;
+                }
+#pragma unroll
+                for (int l = 0; l < kChunk; ++l) {
+                    g = fmaf(grow[l], x[c0 + l], g);
+                    if (c0 + l == k) gkk = grow[l];
+                }
+            }
             const float gkh = 0.5f * gkk;                  // exact
 #pragma unroll
             for (int b = 0; b < Q; ++b) {
@@ -761,8 +772,9 @@ __device__ void winning_levels(bool use_fb, const signed char *xi, const uint32_
 }
 
 // Decode of the winning levels (lv: this wavefront's LDS copy of K levels).
+// Hsc: H of the instance's subcarrier, [nr][nt] (device memory or an LDS copy).
 __device__ void decode_det(const int *lv, int n, int sc, int sy, int nsym, int nr, int nt, int q,
-                           double c, const float2 *H, const float2 *y, unsigned char *sym_out,
+                           double c, const float2 *Hsc, const float2 *y, unsigned char *sym_out,
                            float *metric_out, int lane)
 {
     const int qtop = (1 << q) - 1;
@@ -775,7 +787,7 @@ __device__ void decode_det(const int *lv, int n, int sc, int sy, int nsym, int n
     if (metric_out) {
         double part = 0.0;
         for (int r = lane; r < nr; r += 64) {
-            const float2 *Hr = H + ((size_t)sc * nr + r) * nt;
+            const float2 *Hr = Hsc + (size_t)r * nt;
             const float2 yv = y[((size_t)sc * nsym + sy) * nr + r];
             double re = yv.x, im = yv.y;
             for (int t = 0; t < nt; ++t) {
@@ -792,10 +804,12 @@ __device__ void decode_det(const int *lv, int n, int sc, int sy, int nsym, int n
     }
 }
 
-// VPP: v = level / 2; x = H^H A^-1 (u + tau v); gamma = ||x||^2.
-// zsh: this wavefront's LDS scratch of 16 double2.
+// VPP: v = level / 2; x = H^H A^-1 (u + tau v); gamma = ||x||^2.  Z: A^-1 of
+// the subcarrier with row stride ldz; Hsc: its H, [nu][ntx] (device memory or
+// LDS copies).  zsh: this wavefront's LDS scratch of 16 double2.
 __device__ void decode_vpp(const int *lv, int n, int sc, int sy, int nsym, int nu, int ntx,
-                           double tau, const double2 *Z, const float2 *H, const float2 *u,
+                           double tau, const double2 *Z, int ldz, const float2 *Hsc,
+                           const float2 *u,
                            signed char *v_out, float2 *x_out, float *gamma_out, double2 *zsh,
                            int lane)
 {
@@ -808,7 +822,7 @@ __device__ void decode_vpp(const int *lv, int n, int sc, int sy, int nsym, int n
         for (int l = 0; l < nu; ++l) {
             const double pr = (double)us[l].x + tau * (double)(lv[l] / 2);
             const double pi = (double)us[l].y + tau * (double)(lv[nu + l] / 2);
-            const double2 zz = Z[lane * nu + l];
+            const double2 zz = Z[lane * ldz + l];
             zr = zr + (zz.x * pr - zz.y * pi);
             zi = zi + (zz.x * pi + zz.y * pr);
         }
@@ -819,7 +833,7 @@ __device__ void decode_vpp(const int *lv, int n, int sc, int sy, int nsym, int n
     for (int j = lane; j < ntx; j += 64) {
         double xr = 0.0, xi = 0.0;
         for (int i = 0; i < nu; ++i) {
-            const float2 h = H[((size_t)sc * nu + i) * ntx + j];
+            const float2 h = Hsc[(size_t)i * ntx + j];
             const double2 z = zsh[i];
             // conj(H_ij) z_i
             xr = xr + ((double)h.x * z.x + (double)h.y * z.y);
@@ -1000,12 +1014,13 @@ __global__ void __launch_bounds__(kBlock) k_select(SelectArgs a)
     }
     const int sc = n / a.n_sym, sy = n % a.n_sym;
     if (a.mode == kSelectDet) {
-        decode_det(lvs[wave], n, sc, sy, a.n_sym, a.n_rows, a.n_cols, q, a.c, a.H, a.y,
-                   a.sym_out, a.metric_out, lane);
+        decode_det(lvs[wave], n, sc, sy, a.n_sym, a.n_rows, a.n_cols, q, a.c,
+                   a.H + (size_t)sc * a.n_rows * a.n_cols, a.y, a.sym_out, a.metric_out, lane);
     } else {
         decode_vpp(lvs[wave], n, sc, sy, a.n_sym, a.n_rows, a.n_cols, a.tau,
-                   a.Ainv + (size_t)sc * a.n_rows * a.n_rows, a.H, a.y, a.v_out, a.x_out,
-                   a.gamma_out, zsh[wave], lane);
+                   a.Ainv + (size_t)sc * a.n_rows * a.n_rows, a.n_rows,
+                   a.H + (size_t)sc * a.n_rows * a.n_cols, a.y, a.v_out, a.x_out, a.gamma_out,
+                   zsh[wave], lane);
     }
 }
 
@@ -1108,10 +1123,22 @@ __device__ __forceinline__ double rfld(double v)
 // anneals instances w P .. w P + P - 1 of the item, glanes = 64 / P lanes each,
 // reduces each group of lanes to its best chain and decodes its instances one
 // after another.
+// LDS copies of the current work item's subcarrier data, left by its build:
+// couplings G (rows of KT floats), H ([n_rows][n_cols]) and, for VPP, A^-1
+// (row stride ldz).
+struct FusedItemLds {
+    const float *G;
+    const float2 *H;
+    const double2 *Z;
+    int ldz;
+};
+
 template <int KT, int Q, bool PACKED>
 __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in, int sc_in,
-                                             int sym0_in, int ns_in, const float *Gi, int tid)
+                                             int sym0_in, int ns_in, const FusedItemLds &lds,
+                                             int tid)
 {
+    const float *Gi = lds.G;
     constexpr int NW = (KT * Q + 31) / 32;
     // every descriptor field as a wave-uniform (scalar) value
     const FusedJob *jp = uniform_ptr(jobs_in) + rfl(job_in);
@@ -1125,12 +1152,10 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
     const int w[4] = {rfl(jp->w[0]), rfl(jp->w[1]), rfl(jp->w[2]), rfl(jp->w[3])};
     const uint32_t key0 = rflu(jp->key0), key1 = rflu(jp->key1);
     const double c = rfld(jp->c), tau = rfld(jp->tau);
-    const float2 *H = uniform_ptr(jp->H);
     const float2 *y = uniform_ptr(jp->y);
     const float *beta2 = uniform_ptr(jp->beta2);
     const float *fbase = uniform_ptr(jp->f);
     const signed char *xbase = uniform_ptr(jp->x_fb);
-    const double2 *Abase = uniform_ptr(jp->Ainv);
     void *out0 = uniform_ptr(jp->out0), *out1 = uniform_ptr(jp->out1);
     void *out2 = uniform_ptr(jp->out2);
 
@@ -1180,11 +1205,11 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
             winning_levels(use_fb, xg, S, K, Q, w, sh.lvs[wave], lane);
             if (kind == 0) {
                 decode_det(sh.lvs[wave], ng, sc, sym0 + first + g, n_sym, n_rows, n_cols, Q, c,
-                           H, y, (unsigned char *)out0, (float *)out1, lane);
+                           lds.H, y, (unsigned char *)out0, (float *)out1, lane);
             } else {
                 decode_vpp(sh.lvs[wave], ng, sc, sym0 + first + g, n_sym, n_rows, n_cols, tau,
-                           Abase + (size_t)sc * n_rows * n_rows, H, y, (signed char *)out0,
-                           (float2 *)out1, (float *)out2, sh.zsh[wave], lane);
+                           lds.Z, lds.ldz, lds.H, y, (signed char *)out0, (float2 *)out1,
+                           (float *)out2, sh.zsh[wave], lane);
             }
             wave_sync_lds();
         }
@@ -1231,23 +1256,23 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
     winning_levels(use_fb, xi, S, K, Q, w, sh.lvs[wave], lane);
     const int sy = sym0 + r0;
     if (kind == 0) {
-        decode_det(sh.lvs[wave], n, sc, sy, n_sym, n_rows, n_cols, Q, c, H, y,
+        decode_det(sh.lvs[wave], n, sc, sy, n_sym, n_rows, n_cols, Q, c, lds.H, y,
                    (unsigned char *)out0, (float *)out1, lane);
     } else {
-        decode_vpp(sh.lvs[wave], n, sc, sy, n_sym, n_rows, n_cols, tau,
-                   Abase + (size_t)sc * n_rows * n_rows, H, y, (signed char *)out0,
-                   (float2 *)out1, (float *)out2, sh.zsh[wave], lane);
+        decode_vpp(sh.lvs[wave], n, sc, sy, n_sym, n_rows, n_cols, tau, lds.Z, lds.ldz, lds.H,
+                   y, (signed char *)out0, (float2 *)out1, (float *)out2, sh.zsh[wave], lane);
     }
 }
 
 #define MMGAP_FUSED_CALL(kt, qq)                                                      \
     do {                                                                              \
-        if (packed) fused_anneal<kt, qq, true>(jobs, it.job, it.sc, it.sym0, it.ns, G, tid);  \
-        else fused_anneal<kt, qq, false>(jobs, it.job, it.sc, it.sym0, it.ns, G, tid);        \
+        if (packed) fused_anneal<kt, qq, true>(jobs, it.job, it.sc, it.sym0, it.ns, lds, tid); \
+        else fused_anneal<kt, qq, false>(jobs, it.job, it.sc, it.sym0, it.ns, lds, tid);       \
     } while (0)
 template <int CLS>
 __device__ __forceinline__ void fused_dispatch(int variant, bool packed, const FusedJob *jobs,
-                                               const FusedItem &it, const float *G, int tid)
+                                               const FusedItem &it, const FusedItemLds &lds,
+                                               int tid)
 {
     if constexpr (CLS == 0) {
         switch (variant) {
@@ -1280,9 +1305,14 @@ k_fused(const FusedJob *__restrict__ jobs, const FusedItem *__restrict__ items, 
     FusedCommon &sh = g_fc;
     auto &bs = fused_build_shared<CLS>();
     for (int e = threadIdx.x; e <= kAcceptSteps; e += kBlock) sh.T[e] = accept_table[e];
+    // the first round of items is taken by block index, the rest through the
+    // work counter (which every launch starts at zero)
+    bool first = true;
     for (;;) {
         __syncthreads();
-        if (threadIdx.x == 0) sh.item = (int)atomicAdd(counter, 1u);
+        if (threadIdx.x == 0)
+            sh.item = first ? (int)blockIdx.x : (int)(atomicAdd(counter, 1u) + gridDim.x);
+        first = false;
         __syncthreads();
         const int item = __builtin_amdgcn_readfirstlane(sh.item);
         if (item >= n_items) break;           // every wavefront of the block leaves here
@@ -1306,9 +1336,7 @@ k_fused(const FusedJob *__restrict__ jobs, const FusedItem *__restrict__ items, 
                              nullptr, bs.det(), tid);
             } else {
                 build_vpp_sc(jb.H, jb.y, jb.n_rows, jb.n_cols, jb.n_sym, it.sc, sym, cnt, jb.KT,
-                             jb.ldf, jb.tau, Gs, fs, xs,
-                             jb.Ainv + (size_t)it.sc * jb.n_rows * jb.n_rows, nullptr, bs.vpp(),
-                             tid);
+                             jb.ldf, jb.tau, Gs, fs, xs, nullptr, nullptr, bs.vpp(), tid);
             }
         }
         // The fields were written with vector stores by this workgroup and are
@@ -1324,7 +1352,19 @@ k_fused(const FusedJob *__restrict__ jobs, const FusedItem *__restrict__ items, 
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        fused_dispatch<CLS>(jb.variant, jb.glanes > 0, jobs, it, bs.G, tid);
+        // the decode reads H (and A^-1) from the build's LDS copies
+        FusedItemLds lds;
+        lds.G = bs.G;
+        if (jb.kind == 0) {
+            lds.H = reinterpret_cast<const float2 *>(bs.det().Hs);
+            lds.Z = nullptr;
+            lds.ldz = 0;
+        } else {
+            lds.H = reinterpret_cast<const float2 *>(bs.vpp().Hs);
+            lds.Z = bs.vpp().Zs;
+            lds.ldz = FusedClassTraits<CLS>::kNUV;
+        }
+        fused_dispatch<CLS>(jb.variant, jb.glanes > 0, jobs, it, lds, tid);
     }
 }
 
