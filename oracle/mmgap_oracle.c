@@ -308,6 +308,226 @@ int oracle_solve(int n, int K, int q, const signed char *w, const float *G, int 
     return bad ? -2 : 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* CIM-CAC anneals (paper §2.3, Eqs. cim1 and cim2; §3.2 "Matrix-Vector
+ * Multiplication Optimization" and Appendix A for the integration).
+ *
+ * Each spin i = k q + b of the structured problem, and one auxiliary spin a
+ * that carries the field, gets a real amplitude x_i and an error variable
+ * e_i > 0.  With the spin couplings J_ij = -2 w_i w_j G_{k(i)k(j)} (i != j) and
+ * fields h_i = 2 w_i f_{k(i)} of the level-domain energy, the model is
+ *   dx_i/dt = (p - 1) x_i - x_i^3 + eps e_i c_i,
+ *   de_i/dt = -zeta (x_i^2 - a) e_i,
+ *   c_i = sum_{j != i} J_ij x_j + h_i x_a,   c_a = sum_i h_i x_i,
+ * integrated by explicit Euler steps of length dt; the coupling terms c are
+ * recomputed every f_mvm steps and held in between.  Through the structure,
+ * the coupling of spin i = (k, b) is
+ *   c_i = (-2 w_b) (g_k - G_kk (w_b x_i)) + (2 w_b f_k) x_a,
+ *   g_k = sum_l G_kl X_l,   X_l = sum_b w_b x_{l,b},
+ *   c_a = sum_k (2 f_k) X_k,
+ * one K x K product instead of an N x N one.  The final spins are
+ * s_i = sign(x_i) sign(x_a) (the auxiliary spin fixes the global sign).
+ *
+ * Arithmetic (float32, RNE, fmaf = one rounding):
+ *   X_l  = fma(w_{q-1}, x_{l,q-1}, ... fma(w_0, x_{l,0}, 0))        b ascending
+ *   g_k  = fma(G_k,K-1, X_K-1, ... fma(G_k0, X_0, 0))                l ascending
+ *   c_i  = ((-2 w_b) * (g_k - G_kk * (w_b * x_i))) + ((2 w_b f_k) * x_a)
+ *   c_a  = fma(2 f_K-1, X_K-1, ... fma(2 f_0, X_0, 0))               k ascending
+ *   step, for every amplitude from the values before the step:
+ *     s2 = x * x;  dx = ((p - 1) * x - s2 * x) + (eps * e) * c;  x' = x + dt * dx
+ *     de = (-zeta) * ((s2 - a) * e);  e' = max(e + dt * de, 2^-20)
+ *   init: e = 1; random start: x_i = amp0 * ((d_i - 32768) / 32768) with d_i
+ *     the 16-bit Philox draw (i, 0xFFFFFFFF, chain, instance) of spin i and
+ *     d_a the draw (0xFFFFFFF8, 0xFFFFFFFF, chain, instance); fallback start:
+ *     x_i = amp0 s_i of the fallback levels' spins, x_a = amp0.
+ * The coupling terms are taken at steps t = 0, f_mvm, 2 f_mvm, ...       */
+typedef struct {
+    float dt;
+    int f_mvm;
+    float p, a, zeta, eps, amp0;
+} cim_params;
+
+static float cim_chain(int K, int q, const signed char *w, const float *G, const float *f,
+                       const signed char *xfb, int steps, const cim_params *P,
+                       const uint32_t key[2], uint32_t inst, uint32_t ch, int init_mode,
+                       signed char *s, float *xl, float *amp, float *err, float *cpl)
+{
+    const int N = K * q;
+    const float inv = 1.0f / 32768.0f;           /* exact */
+    if (init_mode == 1 && xfb != NULL) {
+        for (int k = 0; k < K; ++k) spins_from_level(q, w, (int)xfb[k], s + k * q);
+        for (int i = 0; i < N; ++i) amp[i] = P->amp0 * (float)s[i];
+        amp[N] = P->amp0;
+    } else {
+        for (int i = 0; i < N; ++i) {
+            const uint32_t d = draw16((uint32_t)i, 0xFFFFFFFFu, ch, inst, key);
+            amp[i] = P->amp0 * ((float)((int)d - 32768) * inv);
+        }
+        const uint32_t d = draw16(0xFFFFFFF8u, 0xFFFFFFFFu, ch, inst, key);
+        amp[N] = P->amp0 * ((float)((int)d - 32768) * inv);
+    }
+    for (int i = 0; i <= N; ++i) err[i] = 1.0f;
+    const float pm1 = P->p - 1.0f;
+    const float nzeta = -P->zeta;
+    const float efloor = 1.0f / 1048576.0f;      /* 2^-20 */
+    for (int t = 0; t < steps; ++t) {
+        if (t % P->f_mvm == 0) {
+            for (int l = 0; l < K; ++l) {
+                float X = 0.0f;
+                for (int b = 0; b < q; ++b) X = fmaf((float)w[b], amp[l * q + b], X);
+                xl[l] = X;
+            }
+            const float xa = amp[N];
+            float ca = 0.0f;
+            for (int k = 0; k < K; ++k) {
+                float g = 0.0f;
+                for (int l = 0; l < K; ++l) g = fmaf(G[k * K + l], xl[l], g);
+                const float gkk = G[k * K + k];
+                for (int b = 0; b < q; ++b) {
+                    const int i = k * q + b;
+                    const float wb = (float)w[b];
+                    const float self = gkk * (wb * amp[i]);
+                    const float inner = g - self;
+                    const float t1 = (-2.0f * wb) * inner;
+                    const float t2 = ((2.0f * wb) * f[k]) * xa;
+                    cpl[i] = t1 + t2;
+                }
+                ca = fmaf(2.0f * f[k], xl[k], ca);
+            }
+            cpl[N] = ca;
+        }
+        for (int i = 0; i <= N; ++i) {
+            const float x = amp[i], e = err[i];
+            const float s2 = x * x;
+            const float lin = pm1 * x;
+            const float cub = s2 * x;
+            const float drift = lin - cub;
+            const float gain = P->eps * e;
+            const float push = gain * cpl[i];
+            const float dx = drift + push;
+            const float step = P->dt * dx;
+            const float t1 = s2 - P->a;
+            const float t2 = t1 * e;
+            const float de = nzeta * t2;
+            const float estep = P->dt * de;
+            const float en = e + estep;
+            amp[i] = x + step;
+            err[i] = en > efloor ? en : efloor;
+        }
+    }
+    const int sa_neg = amp[N] < 0.0f;
+    for (int i = 0; i < N; ++i) {
+        const int neg = amp[i] < 0.0f;
+        s[i] = (signed char)((neg != sa_neg) ? -1 : 1);
+    }
+    levels_from_spins(K, q, w, s, xl);
+    return level_energy(K, G, f, xl);
+}
+
+/*
+ * oracle_cim_solve: as oracle_solve, with CIM-CAC anneals of `steps` Euler
+ * steps in place of the Metropolis chains (same selection and fallback).
+ *   params [7] float: dt, f_mvm (integral, >= 1), p, a, zeta, eps, amp0
+ */
+int oracle_cim_solve(int n, int K, int q, const signed char *w, const float *G, int inst_per_G,
+                     long g_base, const float *f, const signed char *x_fb,
+                     const uint32_t *inst_ids, int chains, int steps, const float *params,
+                     uint64_t seed, int init_mode, signed char *spins_out, float *e_out,
+                     int *win_out, float *chain_e_out, int nthreads)
+{
+    if (n < 0 || K <= 0 || q <= 0 || chains <= 0 || steps < 0 || inst_per_G <= 0 || !params)
+        return -1;
+    cim_params P;
+    P.dt = params[0];
+    P.f_mvm = (int)params[1];
+    P.p = params[2];
+    P.a = params[3];
+    P.zeta = params[4];
+    P.eps = params[5];
+    P.amp0 = params[6];
+    if (P.f_mvm < 1) return -1;
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    const int N = K * q;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    int bad = 0;
+#pragma omp parallel
+    {
+        signed char *s = (signed char *)malloc((size_t)N);
+        signed char *sbest = (signed char *)malloc((size_t)N);
+        float *xl = (float *)malloc(sizeof(float) * (size_t)K);
+        float *amp = (float *)malloc(sizeof(float) * (size_t)(N + 1));
+        float *err = (float *)malloc(sizeof(float) * (size_t)(N + 1));
+        float *cpl = (float *)malloc(sizeof(float) * (size_t)(N + 1));
+        if (!s || !sbest || !xl || !amp || !err || !cpl) {
+#pragma omp atomic write
+            bad = 1;
+        } else {
+#pragma omp for schedule(dynamic, 4)
+            for (int idx = 0; idx < n; ++idx) {
+                const uint32_t inst = inst_ids ? inst_ids[idx] : (uint32_t)idx;
+                const long gi = (long)(inst / (uint32_t)inst_per_G) - g_base;
+                const float *Gi = G + (size_t)gi * (size_t)K * (size_t)K;
+                const float *fi = f + (size_t)idx * (size_t)K;
+                const signed char *xi = x_fb ? x_fb + (size_t)idx * (size_t)K : NULL;
+                float ebest = 0.0f;
+                int win = -1;
+                for (int ch = 0; ch < chains; ++ch) {
+                    float e = cim_chain(K, q, w, Gi, fi, xi, steps, &P, key, inst, (uint32_t)ch,
+                                        init_mode, s, xl, amp, err, cpl);
+                    if (chain_e_out) chain_e_out[(size_t)idx * (size_t)chains + (size_t)ch] = e;
+                    if (win < 0 || energy_less(e, ebest)) {
+                        ebest = e;
+                        win = ch;
+                        memcpy(sbest, s, (size_t)N);
+                    }
+                }
+                if (xi) {
+                    for (int k = 0; k < K; ++k) xl[k] = (float)xi[k];
+                    float efb = level_energy(K, Gi, fi, xl);
+                    if (energy_less(efb, ebest)) {
+                        ebest = efb;
+                        win = chains;
+                        for (int k = 0; k < K; ++k) spins_from_level(q, w, (int)xi[k], sbest + k * q);
+                    }
+                }
+                memcpy(spins_out + (size_t)idx * (size_t)N, sbest, (size_t)N);
+                e_out[idx] = ebest;
+                if (win_out) win_out[idx] = win;
+            }
+        }
+        free(s); free(sbest); free(xl); free(amp); free(err); free(cpl);
+    }
+    return bad ? -2 : 0;
+}
+
+/* One CIM-CAC anneal's amplitudes and error variables after `steps` steps
+ * (the N spins, then the auxiliary one), for the invariant tests.          */
+int oracle_cim_trajectory(int K, int q, const signed char *w, const float *G, const float *f,
+                          const signed char *xfb, int steps, const float *params, uint64_t seed,
+                          uint32_t inst, uint32_t ch, int init_mode, float *amp_out, float *err_out,
+                          signed char *spins_out, float *e_out)
+{
+    if (K <= 0 || q <= 0 || steps < 0 || !params || (int)params[1] < 1) return -1;
+    cim_params P = {params[0], (int)params[1], params[2], params[3], params[4], params[5],
+                    params[6]};
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    const int N = K * q;
+    signed char *s = (signed char *)malloc((size_t)N);
+    float *xl = (float *)malloc(sizeof(float) * (size_t)K);
+    float *cpl = (float *)malloc(sizeof(float) * (size_t)(N + 1));
+    if (!s || !xl || !cpl) { free(s); free(xl); free(cpl); return -2; }
+    const float e = cim_chain(K, q, w, G, f, xfb, steps, &P, key, inst, ch, init_mode, s, xl,
+                              amp_out, err_out, cpl);
+    if (spins_out) memcpy(spins_out, s, (size_t)N);
+    if (e_out) *e_out = e;
+    free(s); free(xl); free(cpl);
+    return 0;
+}
+
 /* Energy of given levels with the chains' float32 arithmetic.             */
 float oracle_level_energy(int K, const float *G, const float *f, const signed char *lv)
 {

@@ -22,11 +22,16 @@ Paper passages followed (arXiv 2510.01579):
 Readings (where the paper is silent), all shared with the GPU library's
 contract: binary-weighted spin encoding x_k = sum_b 2^(q-1-b) s_{k,b} of the
 odd PAM levels (VPP: two unit-weight spins per real dimension, levels
-{-2, 0, 2} = 2v); a single-spin-flip Metropolis anneal in place of CIM-CAC,
+{-2, 0, 2} = 2v); a single-spin-flip Metropolis anneal (the default dynamics),
 with the local field of a dimension recomputed from the current levels at each
 visit (one row of the coupling matrix-vector product) and a 16-bit uniform
 compared with a tabulated 2^16 * 2^-z, z quantised to 1/64; couplings and
-fields built in float64 and rounded once to float32.
+fields built in float64 and rounded once to float32.  The paper's own CIM-CAC
+dynamics (§2.3 Eqs. cim1/cim2, integrated as in §3.2 and Appendix A) is the
+second dynamics, ``cim_solve``: Euler steps of the amplitudes and error
+variables, the coupling term through the structured K x K product, refreshed
+every f_mvm steps, spins read as signs; its free parameters a, p, zeta, eps and
+the initial amplitude are readings (``CIM_DEFAULTS``).
 
 Parity pins live in tests/test_oracle_*.py (closed forms, library routines,
 brute force, known-answer vectors, invariants).  The chain dynamics themselves
@@ -75,6 +80,19 @@ def lib():
                                        ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_int]
         L.oracle_vpp_build.restype = ctypes.c_int
+        L.oracle_cim_solve.argtypes = [
+            ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,  # n K q w
+            ctypes.c_void_p, ctypes.c_int, ctypes.c_long,                # G inst_per_G g_base
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,           # f x_fb inst_ids
+            ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+        L.oracle_cim_solve.restype = ctypes.c_int
+        L.oracle_cim_trajectory.argtypes = [
+            ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+            ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
+            ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+            ctypes.c_void_p]
+        L.oracle_cim_trajectory.restype = ctypes.c_int
         L.oracle_max_threads.argtypes = []
         L.oracle_max_threads.restype = ctypes.c_int
         _lib = L
@@ -268,6 +286,77 @@ def solve(G, f, K, q, w, chains, sweeps, beta2, seed, x_fb=None, inst_per_G=1,
     return out
 
 
+# CIM-CAC model parameters (paper §2.3 Eqs. cim1/cim2, Appendix A): the
+# integration step and coupling refresh period are the paper's choice
+# (dt = 0.02, f_mvm = 2, 128 steps = the 2.56 time units of its reference
+# 256 x 0.01); a, p, zeta, eps and the initial amplitude are not given in the
+# paper and are this implementation's reading.
+CIM_DEFAULTS = dict(dt=0.02, f_mvm=2, p=0.9, a=1.0, zeta=1.0, eps=1.0, amp0=0.1)
+CIM_KEYS = ("dt", "f_mvm", "p", "a", "zeta", "eps", "amp0")
+
+
+def cim_param_vector(cim: dict) -> np.ndarray:
+    """The 7 model parameters as the float32 vector the C oracle takes."""
+    P = dict(CIM_DEFAULTS)
+    P.update(cim or {})
+    return np.array([P[k] for k in CIM_KEYS], dtype=np.float32)
+
+
+def cim_solve(G, f, K, q, w, chains, steps, cim, seed, x_fb=None, inst_per_G=1,
+              inst_ids=None, init_mode=0, nthreads=0, want_chain_energies=False):
+    """Best-of-`chains` CIM-CAC anneals of `steps` Euler steps per instance, with
+    optional fallback (same selection as solve()).  cim: model parameters
+    (keys of CIM_DEFAULTS; missing keys take the defaults)."""
+    G = np.ascontiguousarray(G, dtype=np.float32).reshape(-1, K, K)
+    f = np.ascontiguousarray(f, dtype=np.float32).reshape(-1, K)
+    n = f.shape[0]
+    w = np.ascontiguousarray(w, dtype=np.int8)
+    if w.shape != (q,):
+        raise ValueError("w must have q entries")
+    ids = None if inst_ids is None else np.ascontiguousarray(inst_ids, dtype=np.uint32)
+    if ids is not None and ids.shape != (n,):
+        raise ValueError("inst_ids must have one entry per instance")
+    if x_fb is not None:
+        x_fb = np.ascontiguousarray(x_fb, dtype=np.int8).reshape(n, K)
+    params = cim_param_vector(cim)
+    spins = np.zeros((n, K * q), dtype=np.int8)
+    E = np.zeros(n, dtype=np.float32)
+    win = np.zeros(n, dtype=np.int32)
+    chainE = np.zeros((n, chains), dtype=np.float32) if want_chain_energies else None
+    rc = lib().oracle_cim_solve(n, K, q, _ptr(w), _ptr(G), int(inst_per_G), 0, _ptr(f),
+                                _ptr(x_fb), _ptr(ids), int(chains), int(steps), _ptr(params),
+                                int(seed) & 0xFFFFFFFFFFFFFFFF, int(init_mode), _ptr(spins),
+                                _ptr(E), _ptr(win), _ptr(chainE), int(nthreads))
+    if rc != 0:
+        raise RuntimeError(f"oracle_cim_solve failed ({rc})")
+    out = dict(spins=spins, E=E, win=win)
+    if chainE is not None:
+        out["chain_E"] = chainE
+    return out
+
+
+def cim_trajectory(G, f, K, q, w, steps, cim, seed, inst=0, ch=0, x_fb=None, init_mode=0):
+    """Amplitudes [K q + 1] and error variables [K q + 1] of one CIM-CAC anneal
+    after `steps` steps (auxiliary spin last), its final spins and energy."""
+    G = np.ascontiguousarray(G, dtype=np.float32).reshape(K, K)
+    f = np.ascontiguousarray(f, dtype=np.float32).reshape(K)
+    w = np.ascontiguousarray(w, dtype=np.int8)
+    N = K * q
+    amp = np.zeros(N + 1, dtype=np.float32)
+    err = np.zeros(N + 1, dtype=np.float32)
+    spins = np.zeros(N, dtype=np.int8)
+    E = np.zeros(1, dtype=np.float32)
+    if x_fb is not None:
+        x_fb = np.ascontiguousarray(x_fb, dtype=np.int8).reshape(K)
+    rc = lib().oracle_cim_trajectory(K, q, _ptr(w), _ptr(G), _ptr(f), _ptr(x_fb), int(steps),
+                                     _ptr(cim_param_vector(cim)), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                                     int(inst), int(ch), int(init_mode), _ptr(amp), _ptr(err),
+                                     _ptr(spins), _ptr(E))
+    if rc != 0:
+        raise RuntimeError(f"oracle_cim_trajectory failed ({rc})")
+    return dict(amp=amp, err=err, spins=spins, E=float(E[0]))
+
+
 def level_energy32(G: np.ndarray, f: np.ndarray, levels: np.ndarray) -> float:
     """The float32 selection energy of given levels (same arithmetic as the chains)."""
     G = np.ascontiguousarray(G, dtype=np.float32)
@@ -277,7 +366,7 @@ def level_energy32(G: np.ndarray, f: np.ndarray, levels: np.ndarray) -> float:
 
 
 def detect(H, y, noise_var, qam, chains, sweeps, beta2, seed, inst_ids=None,
-           init_mode=0, nthreads=0):
+           init_mode=0, nthreads=0, cim=None):
     """Uplink ML-MIMO detection through the Ising reduction (paper §3.2).
 
     Returns dict(sym uint8 [n][n_t], metric float64 [n], levels int8 [n][K],
@@ -292,9 +381,14 @@ def detect(H, y, noise_var, qam, chains, sweeps, beta2, seed, inst_ids=None,
     x_fb_all = slice_levels(mmse(H, y, noise_var), qam).reshape(-1, K)
     ids = np.arange(n_sc * n_sym, dtype=np.uint32) if inst_ids is None \
         else np.asarray(inst_ids, dtype=np.uint32)
-    res = solve(G, f_all[ids], K, q, w, chains, sweeps, beta2, seed,
-                x_fb=x_fb_all[ids], inst_per_G=n_sym, inst_ids=ids,
-                init_mode=init_mode, nthreads=nthreads)
+    if cim is None:
+        res = solve(G, f_all[ids], K, q, w, chains, sweeps, beta2, seed,
+                    x_fb=x_fb_all[ids], inst_per_G=n_sym, inst_ids=ids,
+                    init_mode=init_mode, nthreads=nthreads)
+    else:   # CIM-CAC anneals of `sweeps` Euler steps (beta2 unused)
+        res = cim_solve(G, f_all[ids], K, q, w, chains, sweeps, cim, seed,
+                        x_fb=x_fb_all[ids], inst_per_G=n_sym, inst_ids=ids,
+                        init_mode=init_mode, nthreads=nthreads)
     lv = levels_from_spins(res["spins"], K, q, w).astype(np.int8)
     sc = ids // n_sym
     sy = ids % n_sym
@@ -336,7 +430,7 @@ def vpp_build(H: np.ndarray, u: np.ndarray, tau: float, nthreads: int = 0):
 
 
 def vpp_precode(H, u, qam, chains, sweeps, beta2, seed, tau=None, inst_ids=None,
-                init_mode=0, nthreads=0):
+                init_mode=0, nthreads=0, cim=None):
     """Vector-perturbation precoding through the Ising reduction (paper §3.3).
 
     Perturbation alphabet {-1, 0, 1} per real dimension, two unit-weight spins
@@ -352,8 +446,12 @@ def vpp_precode(H, u, qam, chains, sweeps, beta2, seed, tau=None, inst_ids=None,
     ids = np.arange(n_sc * n_sym, dtype=np.uint32) if inst_ids is None \
         else np.asarray(inst_ids, dtype=np.uint32)
     x_fb = np.zeros((ids.size, K), dtype=np.int8)
-    res = solve(G, f_all[ids], K, 2, VPP_WEIGHTS, chains, sweeps, beta2, seed, x_fb=x_fb,
-                inst_per_G=n_sym, inst_ids=ids, init_mode=init_mode, nthreads=nthreads)
+    if cim is None:
+        res = solve(G, f_all[ids], K, 2, VPP_WEIGHTS, chains, sweeps, beta2, seed, x_fb=x_fb,
+                    inst_per_G=n_sym, inst_ids=ids, init_mode=init_mode, nthreads=nthreads)
+    else:   # CIM-CAC anneals of `sweeps` Euler steps (beta2 unused)
+        res = cim_solve(G, f_all[ids], K, 2, VPP_WEIGHTS, chains, sweeps, cim, seed, x_fb=x_fb,
+                        inst_per_G=n_sym, inst_ids=ids, init_mode=init_mode, nthreads=nthreads)
     lv = levels_from_spins(res["spins"], K, 2, VPP_WEIGHTS)
     v = (lv // 2).astype(np.int8)
     sc = ids // n_sym
