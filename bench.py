@@ -135,7 +135,7 @@ def make_inputs(specs):
     return out
 
 
-def cpu_baseline(inputs, scheds, target_s: float):
+def cpu_baseline(inputs, scheds, target_s: float, cim=None):
     """The oracle as it stands, on a bounded random sample of the workload's
     instances (spread over its jobs in proportion to their instance counts),
     with the schedules of the reported leg."""
@@ -155,10 +155,11 @@ def cpu_baseline(inputs, scheds, target_s: float):
             if j["kind"] == "det":
                 O.detect(inp["H"], inp["y"], inp["noise_var"], j["qam"], sc["chains"],
                          sc["sweeps"], sc["beta2"], inp["seed"], inst_ids=ids,
-                         init_mode=sc["init"])
+                         init_mode=sc["init"], cim=cim)
             else:
                 O.vpp_precode(inp["H"], inp["y"], j["qam"], sc["chains"], sc["sweeps"],
-                              sc["beta2"], inp["seed"], inst_ids=ids, init_mode=sc["init"])
+                              sc["beta2"], inp["seed"], inst_ids=ids, init_mode=sc["init"],
+                              cim=cim)
             n_done += m
         return n_done, time.perf_counter() - t0
 
@@ -344,6 +345,112 @@ def quality(inputs, outs):
     return res
 
 
+def cim_ops_per_step(K: int, q: int, f_mvm: int) -> float:
+    """Algorithmic 32-bit lane operations of one CIM-CAC Euler step of one
+    anneal with N = K q spins and the auxiliary one: the update of every
+    amplitude and error variable, 15 operations each (square, linear and cubic
+    terms, drift, gain, push, step, amplitude sum; shifted square, product,
+    scaling, step, sum, floor), and, every f_mvm steps, the coupling terms --
+    K q for the levels, K^2 for the K x K product, 7 per spin and K for the
+    auxiliary spin."""
+    N = K * q
+    return 15.0 * (N + 1) + (K * q + K * K + 7.0 * N + K) / f_mvm
+
+
+def run_cim(args, M, torch):
+    """CIM-CAC leg (the paper's own anneal dynamics) on the plain path for a
+    workload whose problems have at most 32 spins: `chains` anneals of
+    M.CIM_STEPS Euler steps with the default constants, the Metropolis plain
+    leg at the reference schedule beside it for quality."""
+    specs = WORKLOADS[args.workload]
+    for j in specs:
+        K, q = job_shape(j)[:2]
+        KT = 8 if K <= 8 else (16 if K <= 16 else 32)
+        if KT * q > 32:
+            raise SystemExit(f"--dynamics cim needs at most 32 spins per problem ({args.workload})")
+    inputs = make_inputs(specs)
+    dev = torch.device("cuda", 0)
+    for inp in inputs:
+        inp["H_d"] = torch.from_numpy(inp["H"]).to(dev)
+        inp["y_d"] = torch.from_numpy(inp["y"]).to(dev)
+    ctx = M.Context(0)
+    chains, steps = args.cim_chains, M.CIM_STEPS
+    cim = dict(M.CIM_DEFAULTS)
+
+    def step(use_cim):
+        outs = []
+        for inp in inputs:
+            j = inp["spec"]
+            ch, sw, b2, kw = (chains, steps, None, dict(cim=cim)) if use_cim else \
+                (j["chains"], j["sweeps"], inp["beta2"], {})
+            if j["kind"] == "det":
+                outs.append(ctx.detect(inp["H_d"], inp["y_d"], j["qam"], inp["noise_var"], ch, sw,
+                                       b2, inp["seed"], init=0, **kw))
+            else:
+                outs.append(ctx.vpp_precode(inp["H_d"], inp["y_d"], j["qam"], ch, sw, b2,
+                                            inp["seed"], **kw))
+        return outs
+
+    def timed(use_cim):
+        for _ in range(args.warmup):
+            step(use_cim)
+        ctx.set_profiling(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(use_cim)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = np.array(ctx.profile(args.steps * len(inputs))).reshape(args.steps, len(inputs), 3)
+        ctx.set_profiling(False)
+        outs = step(use_cim)
+        torch.cuda.synchronize()
+        res = []
+        for inp, o in zip(inputs, outs):
+            names = ("sym", "metric") if inp["spec"]["kind"] == "det" else ("v", "x", "gamma")
+            res.append({k: t.cpu().numpy() for k, t in zip(names, o)})
+        return el, prof, res
+
+    total_inst = sum(job_shape(i["spec"])[2] for i in inputs)
+    c_el, c_prof, c_out = timed(True)
+    m_el, m_prof, m_out = timed(False)
+    anneal_ms = float(np.mean(c_prof[:, :, 1].sum(axis=1)))
+    ops = 0.0
+    for inp in inputs:
+        K, q, n = job_shape(inp["spec"])[:3]
+        ops += n * chains * steps * cim_ops_per_step(K, q, cim["f_mvm"])
+    achieved = ops / (anneal_ms * 1e-3) / 1e12
+    cpu = None
+    if not args.no_cpu_baseline:
+        scheds = [dict(chains=chains, sweeps=steps, beta2=None, init=0) for _ in inputs]
+        cpu = cpu_baseline(inputs, scheds, args.cpu_seconds, cim=cim)
+    ctx.close()
+    return {
+        "metric": METRIC + " (CIM-CAC dynamics)",
+        "value": args.steps * total_inst / c_el, "unit": "solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": c_el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "dynamics": "CIM-CAC",
+                   "path": "plain: build, CIM-CAC anneal and select launches per slot",
+                   "schedule": f"{chains} anneals x {steps} Euler steps",
+                   "constants": cim, "instances_per_step": total_inst},
+        "stage_ms": {"build": float(np.mean(c_prof[:, :, 0].sum(axis=1))),
+                     "anneal": anneal_ms,
+                     "select": float(np.mean(c_prof[:, :, 2].sum(axis=1)))},
+        "quality": quality(inputs, c_out),
+        "metropolis_reference": {"ms_per_step": m_el / args.steps * 1e3,
+                                 "value": args.steps * total_inst / m_el,
+                                 "quality": quality(inputs, m_out)},
+        "roofline": {"bound": "alu", "kernel": "k_cim", "achieved": achieved,
+                     "peak": PEAK_ALU_OPS / 1e12, "unit": "T lane-ops/s",
+                     "frac": achieved * 1e12 / PEAK_ALU_OPS,
+                     "traffic": None, "kernel_ms": anneal_ms,
+                     "ops_per_launch": ops},
+        "cpu_baseline": cpu,
+    }
+
+
 def main(argv=None) -> int:  # noqa: C901
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -352,6 +459,9 @@ def main(argv=None) -> int:  # noqa: C901
     ap.add_argument("--workload", default="det-8x8-16qam",
                     choices=sorted(WORKLOADS) + ["serve-mix"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--dynamics", choices=("metropolis", "cim"), default="metropolis",
+                    help="cim: time the CIM-CAC anneals on the plain path instead")
+    ap.add_argument("--cim-chains", type=int, default=32, help="anneals per instance (cim)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain leg")
     ap.add_argument("--no-tuned", action="store_true", help="skip the tuned leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -369,6 +479,10 @@ def main(argv=None) -> int:  # noqa: C901
     import torch
 
     import paper_2510_01579_amd as M
+
+    if args.dynamics == "cim":
+        print(json.dumps(run_cim(args, M, torch)), flush=True)
+        return 0
 
     if args.workload == "serve-mix":
         print(json.dumps(run_serving(args, M, torch)), flush=True)

@@ -79,12 +79,39 @@ typedef struct {
     float tau;         /* VPP: perturbation spacing; <= 0 selects 2 sqrt(M) c = 2 (c_max + d/2) */
 } mmgap_problem;
 
+/* Anneal dynamics of a schedule. */
+enum { MMGAP_DYN_METROPOLIS = 0, MMGAP_DYN_CIM = 1 };
+
+/*
+ * Constants of the CIM-CAC model (paper §2.3 Eqs. cim1/cim2; §3.2 and Appendix
+ * A for the integration): amplitudes x_i and error variables e_i of every spin
+ * and of one auxiliary spin that carries the field,
+ *   dx_i/dt = (p - 1) x_i - x_i^3 + eps e_i c_i,  de_i/dt = -zeta (x_i^2 - a) e_i,
+ * c_i the coupling term (sum_{j != i} J_ij x_j + h_i x_a, and sum_i h_i x_i for
+ * the auxiliary spin), integrated by explicit Euler steps of length dt with the
+ * coupling term recomputed every f_mvm steps; e_i starts at 1 and is kept
+ * >= 2^-20; initial amplitudes amp0 * u, u uniform in [-1, 1) from Philox
+ * (random start) or amp0 times the fallback's spins (fallback start).  The
+ * final spins are sign(x_i) sign(x_a).
+ */
+typedef struct {
+    float dt;              /* Euler step, finite and > 0 */
+    int f_mvm;             /* steps between recomputations of the coupling term, >= 1 */
+    float p, a, zeta, eps; /* model constants, finite */
+    float amp0;            /* initial amplitude scale, finite */
+} mmgap_cim_params;
+
 typedef struct {
     int chains;            /* independent anneals per instance, 1..1024 */
-    int sweeps;            /* full sweeps over all spins per anneal, 1..8192 */
-    const float *beta2;    /* (host) [sweeps] inverse temperature times log2(e) per sweep, >= 0, finite */
+    int sweeps;            /* Metropolis: full sweeps over all spins per anneal; CIM: Euler
+                              steps per anneal; 1..8192 */
+    const float *beta2;    /* (host) Metropolis: [sweeps] inverse temperature times log2(e)
+                              per sweep, >= 0, finite; CIM: unused (may be NULL) */
     uint64_t seed;         /* Philox4x32-10 key: (seed & 0xffffffff, seed >> 32) */
     int init;              /* 0: random initial spins from Philox; 1: start from the fallback levels */
+    int dynamics;          /* MMGAP_DYN_METROPOLIS (0, also for zero-initialised schedules) or
+                              MMGAP_DYN_CIM (plain entry points only; K q <= 32 spins) */
+    const mmgap_cim_params *cim;  /* (host) constants of MMGAP_DYN_CIM, else unused */
 } mmgap_schedule;
 
 /*
@@ -140,6 +167,23 @@ int mmgap_build_ising(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H,
  * spins: s_i = -1 iff bit 15 of the draw of (i, 0xffffffff, chain, n) is set.
  * Energies E = fma(x_K-1, g_K-1 - f_K-1, ... fma(x_0, g_0 - f_0, 0)) with
  * fresh fields.  Ties in energy keep the lowest chain index.
+ * With sched->dynamics = MMGAP_DYN_CIM each anneal is instead `sweeps` Euler
+ * steps of the CIM-CAC model (mmgap_cim_params), N = K q <= 32, with the
+ * float32 arithmetic (every operation rounded once, fma as above)
+ *   X_l = fma(w_q-1, x_(l,q-1), ... fma(w_0, x_(l,0), 0)),
+ *   g_k = fma(G_k,K-1, X_K-1, ... fma(G_k0, X_0, 0)),
+ *   c_i = ((-2 w_b) (g_k - G_kk (w_b x_i))) + ((2 w_b f_k) x_a)  for i = k q + b,
+ *   c_a = fma(2 f_K-1, X_K-1, ... fma(2 f_0, X_0, 0)),
+ * recomputed at steps t = 0, f_mvm, 2 f_mvm, ..., and per step, for every
+ * amplitude from the values before the step,
+ *   s2 = x x,  dx = ((p - 1) x - s2 x) + (eps e) c,  x' = x + dt dx,
+ *   e' = e + dt ((-zeta) ((s2 - a) e)), replaced by 2^-20 unless greater,
+ * with p - 1 and -zeta rounded once in float32.  Random start: x_i = amp0 (u / 32768)
+ * for the signed 16-bit value u = d - 32768 of the draw d of (i, 0xffffffff,
+ * chain, n), x_a likewise from the draw of (0xfffffff8, 0xffffffff, chain, n);
+ * fallback start: x_i = amp0 s_i of the fallback's spins, x_a = amp0.  Final
+ * spin i is -1 iff (x_i < 0) differs from (x_a < 0); energies and selection as
+ * above.
  */
 int mmgap_solve(mmgap_ctx *ctx, int n_inst, int K, int q, const signed char *w,
                 const float *G, int inst_per_G, const float *f, const signed char *x_fallback,
@@ -209,8 +253,10 @@ enum { MMGAP_PLAN_GRAPH = 1 };   /* record the launch as a HIP graph, replayed b
  * subcarrier and up to 4, 2 or 1 symbols for <= 64, <= 128, <= 256 chains)
  * grouped by register class of the problem size (K <= 8 or K <= 16 with QPSK;
  * K <= 16 with 16-QAM; larger) and ordered by decreasing cost within a class,
- * and allocate the plan's own device scratch (couplings, fields, fallbacks,
- * VPP inverses), counted against the context's HBM budget.  A launch is one
+ * and allocate the plan's own device scratch (fields and fallbacks; the
+ * couplings, H and the VPP inverse of a work item stay in LDS), counted against
+ * the context's HBM budget.  Jobs must use Metropolis dynamics (a CIM schedule
+ * is refused with MMGAP_EUNSUPPORTED).  A launch is one
  * persistent kernel per class present, largest class first.  `blocks` =
  * workgroups of each persistent kernel, 0 = as many as the device holds at
  * once.  flags: MMGAP_PLAN_GRAPH or 0.

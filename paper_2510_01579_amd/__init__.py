@@ -54,10 +54,27 @@ class Problem(ctypes.Structure):
                 ("noise_var", ctypes.c_float), ("tau", ctypes.c_float)]
 
 
+class CimParams(ctypes.Structure):
+    """mmgap_cim_params: constants of the CIM-CAC model."""
+    _fields_ = [("dt", ctypes.c_float), ("f_mvm", ctypes.c_int), ("p", ctypes.c_float),
+                ("a", ctypes.c_float), ("zeta", ctypes.c_float), ("eps", ctypes.c_float),
+                ("amp0", ctypes.c_float)]
+
+
 class Schedule(ctypes.Structure):
     _fields_ = [("chains", ctypes.c_int), ("sweeps", ctypes.c_int),
                 ("beta2", ctypes.POINTER(ctypes.c_float)), ("seed", ctypes.c_uint64),
-                ("init", ctypes.c_int)]
+                ("init", ctypes.c_int), ("dynamics", ctypes.c_int),
+                ("cim", ctypes.POINTER(CimParams))]
+
+
+DYN_METROPOLIS, DYN_CIM = 0, 1
+# CIM-CAC constants used when a caller gives only some of them: the paper's
+# integration step and coupling refresh period (dt = 0.02, f_mvm = 2; 128 steps
+# cover its reference integration length 2.56); a, p, zeta, eps and the initial
+# amplitude scale are this library's choice (the paper leaves them open).
+CIM_DEFAULTS = dict(dt=0.02, f_mvm=2, p=0.9, a=1.0, zeta=1.0, eps=1.0, amp0=0.1)
+CIM_STEPS = 128
 
 
 class Job(ctypes.Structure):
@@ -275,13 +292,28 @@ class Context:
         return t
 
     @staticmethod
-    def _schedule(chains, sweeps, beta2, seed, init):
-        b = np.ascontiguousarray(np.asarray(beta2, dtype=np.float32).reshape(-1))
-        if b.size != sweeps:
-            raise ValueError(f"beta2 must have {sweeps} entries (got {b.size})")
-        s = Schedule(int(chains), int(sweeps), b.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
-                     int(seed) & 0xFFFFFFFFFFFFFFFF, int(init))
-        return s, b
+    def _schedule(chains, sweeps, beta2, seed, init, cim=None):
+        """A Schedule and the host objects it points to (keep them alive).  cim:
+        None for Metropolis anneals, else a dict of CIM-CAC constants (missing
+        keys from CIM_DEFAULTS; `sweeps` is then the number of Euler steps and
+        beta2 may be None)."""
+        if cim is None:
+            b = np.ascontiguousarray(np.asarray(beta2, dtype=np.float32).reshape(-1))
+            if b.size != sweeps:
+                raise ValueError(f"beta2 must have {sweeps} entries (got {b.size})")
+            s = Schedule(int(chains), int(sweeps), b.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                         int(seed) & 0xFFFFFFFFFFFFFFFF, int(init), DYN_METROPOLIS, None)
+            return s, b
+        P = dict(CIM_DEFAULTS)
+        unknown = set(cim) - set(P)
+        if unknown:
+            raise ValueError(f"unknown CIM constants {sorted(unknown)}")
+        P.update(cim)
+        c = CimParams(float(P["dt"]), int(P["f_mvm"]), float(P["p"]), float(P["a"]),
+                      float(P["zeta"]), float(P["eps"]), float(P["amp0"]))
+        s = Schedule(int(chains), int(sweeps), None, int(seed) & 0xFFFFFFFFFFFFFFFF, int(init),
+                     DYN_CIM, ctypes.pointer(c))
+        return s, c
 
     def _problem(self, kind, H, y_or_u, qam, noise_var, tau):
         torch = _torch()
@@ -321,7 +353,7 @@ class Context:
         return out
 
     def solve(self, G, f, K, q, w, chains, sweeps, beta2, seed, x_fallback=None, inst_per_G=1,
-              init=0, stream=None):
+              init=0, stream=None, cim=None):
         """Best of `chains` anneals per instance.  Returns (spins int8 [n][K q],
         energy float32 [n], winning chain int32 [n])."""
         torch = _torch()
@@ -338,7 +370,7 @@ class Context:
         spins = torch.empty((n, K * q), dtype=torch.int8, device=dev)
         E = torch.empty((n,), dtype=torch.float32, device=dev)
         win = torch.empty((n,), dtype=torch.int32, device=dev)
-        s, keep = self._schedule(chains, sweeps, beta2, seed, init)
+        s, keep = self._schedule(chains, sweeps, beta2, seed, init, cim)
         st = stream if stream is not None else _stream(dev)
         self._check(lib().mmgap_solve(self._h, n, K, q, wv, _ptr(G), int(inst_per_G), _ptr(f),
                                       _ptr(x_fallback), ctypes.byref(s), _ptr(spins), _ptr(E),
@@ -347,7 +379,7 @@ class Context:
         return spins, E, win
 
     def detect(self, H, y, qam, noise_var, chains, sweeps, beta2, seed, init=0, metric=True,
-               stream=None):
+               stream=None, cim=None):
         """Uplink detection.  Returns (sym uint8 [n][n_tx], metric float32 [n] or None)."""
         torch = _torch()
         p = self._problem(KIND_DET, H, y, qam, noise_var, 0.0)
@@ -355,7 +387,7 @@ class Context:
         dev = self._dev()
         sym = torch.empty((n, p.n_tx), dtype=torch.uint8, device=dev)
         met = torch.empty((n,), dtype=torch.float32, device=dev) if metric else None
-        s, keep = self._schedule(chains, sweeps, beta2, seed, init)
+        s, keep = self._schedule(chains, sweeps, beta2, seed, init, cim)
         st = stream if stream is not None else _stream(dev)
         self._check(lib().mmgap_detect(self._h, ctypes.byref(p), _ptr(H), _ptr(y),
                                        ctypes.byref(s), _ptr(sym), _ptr(met), st))
@@ -363,7 +395,7 @@ class Context:
         return sym, met
 
     def vpp_precode(self, H, u, qam, chains, sweeps, beta2, seed, tau=0.0, want_x=True,
-                    want_gamma=True, init=0, stream=None):
+                    want_gamma=True, init=0, stream=None, cim=None):
         """Downlink VPP.  Returns (v int8 [n][2 n_rx], x complex64 [n][n_tx] or None,
         gamma float32 [n] or None)."""
         torch = _torch()
@@ -373,7 +405,7 @@ class Context:
         v = torch.empty((n, 2 * p.n_rx), dtype=torch.int8, device=dev)
         x = torch.empty((n, p.n_tx), dtype=torch.complex64, device=dev) if want_x else None
         g = torch.empty((n,), dtype=torch.float32, device=dev) if want_gamma else None
-        s, keep = self._schedule(chains, sweeps, beta2, seed, init)
+        s, keep = self._schedule(chains, sweeps, beta2, seed, init, cim)
         st = stream if stream is not None else _stream(dev)
         self._check(lib().mmgap_vpp_precode(self._h, ctypes.byref(p), _ptr(H), _ptr(u),
                                             ctypes.byref(s), _ptr(v), _ptr(x), _ptr(g), st))

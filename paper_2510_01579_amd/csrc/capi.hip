@@ -118,13 +118,25 @@ int check_schedule(mmgap_ctx *ctx, const mmgap_schedule *s)
         return fail(ctx, MMGAP_EUNSUPPORTED, "chains=%d outside 1..%d", s->chains, mmgap::kMaxChains);
     if (s->sweeps < 1 || s->sweeps > mmgap::kMaxSweeps)
         return fail(ctx, MMGAP_EUNSUPPORTED, "sweeps=%d outside 1..%d", s->sweeps, mmgap::kMaxSweeps);
+    if (s->init != 0 && s->init != 1) return fail(ctx, MMGAP_EINVAL, "schedule.init must be 0 or 1");
+    if (s->dynamics == MMGAP_DYN_CIM) {
+        const mmgap_cim_params *c = s->cim;
+        if (!c) return fail(ctx, MMGAP_EINVAL, "schedule.cim is NULL");
+        const float v[6] = {c->dt, c->p, c->a, c->zeta, c->eps, c->amp0};
+        for (float x : v)
+            if (!std::isfinite(x)) return fail(ctx, MMGAP_EINVAL, "schedule.cim has a non-finite constant");
+        if (!(c->dt > 0.0f)) return fail(ctx, MMGAP_EINVAL, "schedule.cim.dt must be > 0");
+        if (c->f_mvm < 1) return fail(ctx, MMGAP_EINVAL, "schedule.cim.f_mvm must be >= 1");
+        return MMGAP_OK;
+    }
+    if (s->dynamics != MMGAP_DYN_METROPOLIS)
+        return fail(ctx, MMGAP_EINVAL, "schedule.dynamics=%d is not METROPOLIS or CIM", s->dynamics);
     if (!s->beta2) return fail(ctx, MMGAP_EINVAL, "schedule.beta2 is NULL");
     for (int t = 0; t < s->sweeps; ++t) {
         const float b = s->beta2[t];
         if (!(b >= 0.0f) || !std::isfinite(b))
             return fail(ctx, MMGAP_EINVAL, "schedule.beta2[%d]=%g is not finite and >= 0", t, (double)b);
     }
-    if (s->init != 0 && s->init != 1) return fail(ctx, MMGAP_EINVAL, "schedule.init must be 0 or 1");
     return MMGAP_OK;
 }
 
@@ -238,9 +250,15 @@ int run_solver(mmgap_ctx *ctx, hipStream_t st, int n_inst, int K, int q, int KT,
                const mmgap_schedule *sched, float *chainE, uint32_t *chainS,
                mmgap::SelectArgs sel)
 {
+    const bool cim = sched->dynamics == MMGAP_DYN_CIM;
+    if (cim && KT * q > 32)
+        return fail(ctx, MMGAP_EUNSUPPORTED, "CIM dynamics needs K q <= 32 spins (padded %d)",
+                    KT * q);
     const float *beta = nullptr;
-    int rc = upload_beta(ctx, sched, st, &beta);
-    if (rc) return rc;
+    if (!cim) {
+        int rc = upload_beta(ctx, sched, st, &beta);
+        if (rc) return rc;
+    }
     mmgap::AnnealArgs a{};
     a.G = Gp;
     a.inst_per_G = inst_per_G;
@@ -258,9 +276,18 @@ int run_solver(mmgap_ctx *ctx, hipStream_t st, int n_inst, int K, int q, int KT,
     a.glanes = packed_lanes(sched->chains, inst_per_G, 64);
     a.chain_E = chainE;
     a.chain_S = chainS;
+    if (cim) {
+        a.cim.dt = sched->cim->dt;
+        a.cim.pm1 = sched->cim->p - 1.0f;        // rounded once in float32
+        a.cim.a = sched->cim->a;
+        a.cim.nzeta = -sched->cim->zeta;
+        a.cim.eps = sched->cim->eps;
+        a.cim.amp0 = sched->cim->amp0;
+        a.cim.f_mvm = sched->cim->f_mvm;
+    }
     prof_mark(ctx, 1, st);
-    hipError_t e = mmgap::launch_anneal(KT, q, a, st);
-    if (e != hipSuccess) return hip_fail(ctx, e, "anneal launch");
+    hipError_t e = cim ? mmgap::launch_cim(KT, q, a, st) : mmgap::launch_anneal(KT, q, a, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, cim ? "CIM anneal launch" : "anneal launch");
     prof_mark(ctx, 2, st);
     sel.n_inst = n_inst;
     sel.K = K;
@@ -306,6 +333,8 @@ int batch_layout(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, BatchLayout 
         int rc = check_problem(ctx, &jb.prob, -1, &sh);
         if (!rc) rc = check_schedule(ctx, &jb.sched);
         if (rc) return fail(ctx, rc, "job %d: %s", j, ctx->err.c_str());
+        if (jb.sched.dynamics != MMGAP_DYN_METROPOLIS)
+            return fail(ctx, MMGAP_EUNSUPPORTED, "job %d: batches run Metropolis dynamics only", j);
         if (jb.sched.chains > kMaxFusedChains)
             return fail(ctx, MMGAP_EUNSUPPORTED, "job %d: chains=%d > %d in a batch", j,
                         jb.sched.chains, kMaxFusedChains);

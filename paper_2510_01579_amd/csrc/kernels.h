@@ -46,6 +46,13 @@ struct VppBuildArgs {
     double *unorm;          // [n_sc*n_sym] u^H A^-1 u or null
 };
 
+// CIM-CAC model constants as the kernels use them: p - 1 and -zeta rounded
+// once in float32 on the host.
+struct CimParams {
+    float dt, pm1, a, nzeta, eps, amp0;
+    int f_mvm;
+};
+
 struct AnnealArgs {
     const float *G;         // [n_G][KT][KT]
     int inst_per_G;
@@ -63,6 +70,7 @@ struct AnnealArgs {
                             // (64/glanes must divide inst_per_G)
     float *chain_E;         // [n_inst][chains]
     uint32_t *chain_S;      // [n_inst][chains][NW]
+    CimParams cim;          // launch_cim only (sweeps = Euler steps, beta2 unused)
 };
 
 enum SelectMode { kSelectSolve = 0, kSelectDet = 1, kSelectVpp = 2 };
@@ -151,6 +159,8 @@ hipError_t fused_blocks_per_cu(int cls, int *blocks);
 hipError_t launch_det_build(const DetBuildArgs &a, hipStream_t s);
 hipError_t launch_vpp_build(const VppBuildArgs &a, hipStream_t s);
 hipError_t launch_anneal(int KT, int q, const AnnealArgs &a, hipStream_t s);
+// CIM-CAC anneals (same outputs as launch_anneal); KT q <= 32.
+hipError_t launch_cim(int KT, int q, const AnnealArgs &a, hipStream_t s);
 hipError_t launch_select(const SelectArgs &a, hipStream_t s);
 hipError_t launch_expand(const ExpandArgs &a, hipStream_t s);
 // copy [n][K][K] -> [n][KT][KT] (and [m][K] -> [m][KT]) with zero padding

@@ -532,6 +532,24 @@ __device__ __forceinline__ float load_field(const float *fi, int k)
 //   and the flip is accepted iff the 16-bit draw m < T[index] (T in LDS).
 // Returns the final energy sum_k x_k (g_k - f_k); `bits` receives the final
 // spins (bit set = spin -1).
+// Energy sum_k x_k (g_k - f_k) of levels x with fresh fields g = G x - f (G in
+// LDS, rows of KT floats), every field a chain of fused multiply-adds from -f_k.
+template <int KT>
+__device__ __forceinline__ float lane_level_energy(const float *Gl, const float *fi,
+                                                   const float (&x)[KT])
+{
+    float E = 0.0f;
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+        float acc = -fi[k];
+#pragma unroll
+        for (int l = 0; l < KT; ++l) acc = fmaf(Gl[k * KT + l], x[l], acc);
+        const float diff = acc - fi[k];
+        E = fmaf(x[k], diff, E);
+    }
+    return E;
+}
+
 template <int KT, int Q, bool PACKED = false>
 __device__ __forceinline__ float anneal_lane(const float *Gl, const float *fi,
                                              const signed char *xfb_i, const float *beta2,
@@ -672,16 +690,7 @@ __device__ __forceinline__ float anneal_lane(const float *Gl, const float *fi,
         }
     }
 
-    // final state: energy sum_k x_k (g_k - f_k) with fresh fields
-    float E = 0.0f;
-#pragma unroll
-    for (int k = 0; k < KT; ++k) {
-        float acc = -fi[k];
-#pragma unroll
-        for (int l = 0; l < KT; ++l) acc = fmaf(Gl[k * KT + l], x[l], acc);
-        const float diff = acc - fi[k];
-        E = fmaf(x[k], diff, E);
-    }
+    const float E = lane_level_energy<KT>(Gl, fi, x);
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
         uint32_t word = 0u;
@@ -697,6 +706,154 @@ __device__ __forceinline__ float anneal_lane(const float *Gl, const float *fi,
         bits[w] = word;
     }
     return E;
+}
+
+
+// One CIM-CAC anneal per lane (paper §2.3 Eqs. cim1/cim2, Euler steps as in
+// §3.2 and Appendix A).  Per lane: the amplitudes and error variables of the
+// KT Q spins and of one auxiliary spin carrying the field (index KT Q), and the
+// held coupling terms.  The coupling terms go through the structured form --
+// levels X_l = sum_b w_b x_(l,b), one row g_k of G X per dimension (G from LDS
+// as in anneal_lane), then per spin (-2 w_b)(g_k - G_kk w_b x_i) + 2 w_b f_k x_a
+// -- and are recomputed every f_mvm steps.  Padded dimensions have zero
+// couplings and fields, so they never reach a real spin.  Returns the energy of
+// the final spins sign(x_i) sign(x_a); `bits` receives them (bit set = -1).
+template <int KT, int Q, bool PACKED>
+__device__ __forceinline__ float cim_lane(const float *Gl, const float *fi,
+                                          const signed char *xfb_i, const CimParams &P,
+                                          int steps, const int (&wts)[4], uint32_t key0,
+                                          uint32_t key1, int init_mode, uint32_t uch,
+                                          uint32_t uinst, uint32_t (&bits)[(KT * Q + 31) / 32])
+{
+    constexpr int N = KT * Q;
+    constexpr int NW = (N + 31) / 32;
+    constexpr int NG = (N + 7) / 8;
+    float amp[N + 1], err[N + 1], cpl[N + 1];
+    float wf[Q];
+#pragma unroll
+    for (int b = 0; b < Q; ++b) wf[b] = (float)wts[b];
+    // the model constants in vector registers: products with vector operands
+    // issue faster than with scalar ones
+    float dt = P.dt, pm1 = P.pm1, ca0 = P.a, nz = P.nzeta, eps = P.eps;
+    asm volatile("" : "+v"(dt), "+v"(pm1), "+v"(ca0), "+v"(nz), "+v"(eps));
+    const float inv = 1.0f / 32768.0f;                   // exact
+    if (init_mode == 1 && xfb_i != nullptr) {
+#pragma unroll
+        for (int k = 0; k < KT; ++k) {
+            int rem = xfb_i[k];
+#pragma unroll
+            for (int b = 0; b < Q; ++b) {
+                const int sg = rem > 0 ? 1 : -1;
+                rem -= wts[b] * sg;
+                amp[k * Q + b] = P.amp0 * (float)sg;
+            }
+        }
+        amp[N] = P.amp0;
+    } else {
+#pragma unroll
+        for (int j = 0; j < NG; ++j) {
+            uint32_t r[4] = {(uint32_t)j, 0xFFFFFFFFu, uch, uinst};
+            philox4x32_10(r, key0, key1);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int i = 8 * j + e;
+                if (i < N) {
+                    const uint32_t d = (e & 1) ? (r[e >> 1] >> 16) : (r[e >> 1] & 0xFFFFu);
+                    amp[i] = P.amp0 * ((float)((int)d - 32768) * inv);
+                }
+            }
+        }
+        uint32_t r[4] = {0x1FFFFFFFu, 0xFFFFFFFFu, uch, uinst};   // draw 0xfffffff8
+        philox4x32_10(r, key0, key1);
+        amp[N] = P.amp0 * ((float)((int)(r[0] & 0xFFFFu) - 32768) * inv);
+    }
+#pragma unroll
+    for (int i = 0; i <= N; ++i) {
+        err[i] = 1.0f;
+        cpl[i] = 0.0f;
+    }
+    const float efloor = 1.0f / 1048576.0f;             // 2^-20
+    const int fm = P.f_mvm;
+    for (int t = 0; t < steps; ++t) {
+        if (t % fm == 0) {
+            float X[KT];
+#pragma unroll
+            for (int l = 0; l < KT; ++l) {
+                float v = 0.0f;
+#pragma unroll
+                for (int b = 0; b < Q; ++b) v = fmaf(wf[b], amp[l * Q + b], v);
+                X[l] = v;
+            }
+            const float xa = amp[N];
+            float acc_a = 0.0f;
+            int roff = 0;
+            asm volatile("" : "+v"(roff));
+            const float4 *G4 = reinterpret_cast<const float4 *>(Gl) + roff;
+#pragma unroll
+            for (int k = 0; k < KT; ++k) {
+                float g = 0.0f;
+                float gkk = 0.0f;
+#pragma unroll
+                for (int l4 = 0; l4 < KT / 4; ++l4) {
+                    const float4 v = G4[k * (KT / 4) + l4];
+                    const float cv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        g = fmaf(cv[u], X[4 * l4 + u], g);
+                        if (4 * l4 + u == k) gkk = cv[u];
+                    }
+                }
+                const float fk = load_field<PACKED>(fi, k);
+#pragma unroll
+                for (int b = 0; b < Q; ++b) {
+                    const int i = k * Q + b;
+                    const float self = gkk * (wf[b] * amp[i]);
+                    const float inner = g - self;
+                    const float t1 = (-2.0f * wf[b]) * inner;
+                    const float t2 = ((2.0f * wf[b]) * fk) * xa;
+                    cpl[i] = t1 + t2;
+                }
+                acc_a = fmaf(2.0f * fk, X[k], acc_a);
+            }
+            cpl[N] = acc_a;
+        }
+#pragma unroll
+        for (int i = 0; i <= N; ++i) {
+            const float x = amp[i], e = err[i];
+            const float s2 = x * x;
+            const float lin = pm1 * x;
+            const float cub = s2 * x;
+            const float drift = lin - cub;
+            const float gain = eps * e;
+            const float push = gain * cpl[i];
+            const float dx = drift + push;
+            const float stp = dt * dx;
+            const float t1 = s2 - ca0;
+            const float t2 = t1 * e;
+            const float de = nz * t2;
+            const float estp = dt * de;
+            const float en = e + estp;
+            amp[i] = x + stp;
+            err[i] = en > efloor ? en : efloor;
+        }
+    }
+    const bool aneg = amp[N] < 0.0f;
+    float x[KT];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) bits[w] = 0u;
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+        int lv = 0;
+#pragma unroll
+        for (int b = 0; b < Q; ++b) {
+            const int i = k * Q + b;
+            const bool neg = (amp[i] < 0.0f) != aneg;
+            lv += neg ? -wts[b] : wts[b];
+            bits[i >> 5] |= neg ? (1u << (i & 31)) : 0u;
+        }
+        x[k] = (float)lv;
+    }
+    return lane_level_energy<KT>(Gl, fi, x);
 }
 
 // ---------------------------------------------------------------------------
@@ -946,6 +1103,59 @@ k_anneal(const float *__restrict__ G, int inst_per_G, const float *__restrict__ 
     uint32_t bits[NW];
     const float E = anneal_lane<KT, Q, PACKED>(Gs, fi, xi, beta2, T, sweeps, wts, key0, key1,
                                                init_mode, (uint32_t)ch, (uint32_t)inst, bits);
+    if (valid && ch < chains) {
+        const size_t o = (size_t)inst * chains + ch;
+        chain_E[o] = E;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) chain_S[o * NW + w] = bits[w];
+    }
+}
+
+// CIM-CAC anneals with the layout of k_anneal: one wavefront = 64 chains of
+// one instance (several wavefronts for more chains), or PACKED 64 / glanes
+// instances per wavefront sharing one G; each wavefront stages its G in LDS.
+// Writes every chain's final energy and spin words.
+template <int KT, int Q, bool PACKED>
+__global__ void __launch_bounds__(kBlock)
+k_cim(const float *__restrict__ G, int inst_per_G, const float *__restrict__ f,
+      const signed char *__restrict__ x_fb, CimParams prm, int steps, int chains, int n_inst,
+      int w0, int w1, int w2, int w3, uint32_t key0, uint32_t key1, int init_mode, int glanes,
+      float *__restrict__ chain_E, uint32_t *__restrict__ chain_S)
+{
+    constexpr int NW = (KT * Q + 31) / 32;
+    __shared__ float4 Gw[kWavesPerBlock][KT * KT / 4];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int gw = blockIdx.x * kWavesPerBlock + wave;
+    int inst, ch, inst0;
+    bool valid = true;
+    if constexpr (PACKED) {
+        const int per_wave = 64 / glanes;
+        inst0 = gw * per_wave;
+        if (inst0 >= n_inst) return;
+        inst = inst0 + lane / glanes;
+        ch = lane % glanes;
+        if (inst >= n_inst) {               // tail of the last wavefront: any valid data
+            valid = false;
+            inst = inst0;
+        }
+    } else {
+        const int wpi = (chains + 63) >> 6;
+        inst = gw / wpi;
+        if (inst >= n_inst) return;
+        inst0 = inst;
+        ch = (gw - inst * wpi) * 64 + lane;
+    }
+    const float *Gi = G + (size_t)(inst0 / inst_per_G) * (KT * KT);
+    float *Gs = reinterpret_cast<float *>(Gw[wave]);
+    for (int e = lane; e < KT * KT; e += 64) Gs[e] = Gi[e];
+    wave_sync_lds();
+    const float *fi = f + (size_t)inst * KT;
+    const signed char *xi = x_fb ? x_fb + (size_t)inst * KT : nullptr;
+    const int wts[4] = {w0, w1, w2, w3};
+    uint32_t bits[NW];
+    const float E = cim_lane<KT, Q, PACKED>(Gs, fi, xi, prm, steps, wts, key0, key1, init_mode,
+                                            (uint32_t)ch, (uint32_t)inst, bits);
     if (valid && ch < chains) {
         const size_t o = (size_t)inst * chains + ch;
         chain_E[o] = E;
@@ -1467,6 +1677,32 @@ hipError_t launch_anneal_t(const AnnealArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int KT, int Q>
+hipError_t launch_cim_t(const AnnealArgs &a, hipStream_t s)
+{
+    const int per_wave = a.glanes > 0 ? 64 / a.glanes : 1;
+    if (a.glanes > 0 && (a.glanes > 32 || (a.glanes & (a.glanes - 1)) || a.chains > a.glanes ||
+                         a.inst_per_G % per_wave != 0))
+        return hipErrorInvalidValue;
+    if (a.cim.f_mvm < 1) return hipErrorInvalidValue;
+    const size_t waves = a.glanes > 0 ? ((size_t)a.n_inst + per_wave - 1) / per_wave
+                                      : (size_t)a.n_inst * ((a.chains + 63) / 64);
+    const size_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (blocks == 0) return hipSuccess;
+    if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    if (a.glanes > 0)
+        hipLaunchKernelGGL((k_cim<KT, Q, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a.G,
+                           a.inst_per_G, a.f, a.x_fb, a.cim, a.sweeps, a.chains, a.n_inst, a.w[0],
+                           a.w[1], a.w[2], a.w[3], a.key0, a.key1, a.init_mode, a.glanes,
+                           a.chain_E, a.chain_S);
+    else
+        hipLaunchKernelGGL((k_cim<KT, Q, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a.G,
+                           a.inst_per_G, a.f, a.x_fb, a.cim, a.sweeps, a.chains, a.n_inst, a.w[0],
+                           a.w[1], a.w[2], a.w[3], a.key0, a.key1, a.init_mode, 0, a.chain_E,
+                           a.chain_S);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 int fused_variant(int KT, int q)
@@ -1496,6 +1732,21 @@ hipError_t launch_vpp_build(const VppBuildArgs &a, hipStream_t s)
     if (a.n_u <= 8) hipLaunchKernelGGL(k_vpp_build<8>, dim3(a.n_sc), dim3(kBuildBlock), 0, s, a);
     else hipLaunchKernelGGL(k_vpp_build<16>, dim3(a.n_sc), dim3(kBuildBlock), 0, s, a);
     return hipGetLastError();
+}
+
+hipError_t launch_cim(int KT, int q, const AnnealArgs &a, hipStream_t s)
+{
+#define MMGAP_CIM_CASE(kt, qq) \
+    if (KT == kt && q == qq) return launch_cim_t<kt, qq>(a, s);
+    MMGAP_CIM_CASE(8, 1)
+    MMGAP_CIM_CASE(8, 2)
+    MMGAP_CIM_CASE(8, 3)
+    MMGAP_CIM_CASE(8, 4)
+    MMGAP_CIM_CASE(16, 1)
+    MMGAP_CIM_CASE(16, 2)
+    MMGAP_CIM_CASE(32, 1)
+#undef MMGAP_CIM_CASE
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_anneal(int KT, int q, const AnnealArgs &a, hipStream_t s)

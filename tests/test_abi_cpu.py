@@ -34,23 +34,28 @@ def test_every_declared_symbol_is_exported():
     assert set(M.EXPORTS) <= set(declared)
 
 
+def _struct_body(text, name):
+    """Body of `typedef struct { ... } name;` (the struct right before the name)."""
+    head = text[:text.index("} " + name + ";")]
+    return head[head.rindex("typedef struct {") + len("typedef struct {"):]
+
+
+def _field_order(body, names):
+    order = []
+    for f in re.findall(r"\b(" + "|".join(names) + r")\b", body):
+        if f not in order:
+            order.append(f)
+    return order
+
+
 def test_binding_structs_match_header():
-    """Field order of mmgap_problem / mmgap_schedule as declared in the header."""
+    """Field order of mmgap_problem, mmgap_cim_params and mmgap_schedule as
+    declared in the header."""
     text = open(os.path.join(ROOT, "include", "mmgap.h")).read()
-    prob = re.search(r"typedef struct \{(.*?)\} mmgap_problem;", text, re.S).group(1)
-    fields = re.findall(r"\b(kind|n_rx|n_tx|qam|n_sc|n_sym|noise_var|tau)\b", prob)
-    order = []
-    for f in fields:
-        if f not in order:
-            order.append(f)
-    assert order == [f[0] for f in M.Problem._fields_]
-    sched = re.search(r"typedef struct \{(.*?)\} mmgap_schedule;", text, re.S).group(1)
-    fields = re.findall(r"\b(chains|sweeps|beta2|seed|init)\b", sched)
-    order = []
-    for f in fields:
-        if f not in order:
-            order.append(f)
-    assert order == [f[0] for f in M.Schedule._fields_]
+    for name, cls in (("mmgap_problem", M.Problem), ("mmgap_cim_params", M.CimParams),
+                      ("mmgap_schedule", M.Schedule)):
+        names = [f[0] for f in cls._fields_]
+        assert _field_order(_struct_body(text, name), names) == names, name
 
 
 def test_product_does_not_import_the_oracle():
