@@ -504,6 +504,33 @@ int oracle_cim_solve(int n, int K, int q, const signed char *w, const float *G, 
     return bad ? -2 : 0;
 }
 
+/*
+ * oracle_delta_fields: fields of the Ising problem around a guess (paper §2.3,
+ * the Delta-Ising form the paper builds around its MMSE / MMSE-SIC guess; Fig. 5
+ * and §3.2 "MMGaP-E").  With levels x = x_g + z the energy
+ * x^T G x - 2 f^T x equals z^T G z - 2 (f - G x_g)^T z plus a constant, so the
+ * search over the moves z uses the couplings G unchanged and the fields
+ *   f'_k = f_k - fma(G_k,K-1, xg_K-1, ... fma(G_k0, xg_0, 0))        (l ascending).
+ *   G [n_G][K][K]; f, xg, f_out [n][K]; instance idx uses G[inst / inst_per_G - g_base]
+ *   with inst = inst_ids[idx] (or idx).
+ */
+int oracle_delta_fields(int n, int K, const float *G, int inst_per_G, long g_base, const float *f,
+                        const signed char *xg, const uint32_t *inst_ids, float *f_out)
+{
+    if (n < 0 || K <= 0 || inst_per_G <= 0) return -1;
+    for (int idx = 0; idx < n; ++idx) {
+        const uint32_t inst = inst_ids ? inst_ids[idx] : (uint32_t)idx;
+        const long gi = (long)(inst / (uint32_t)inst_per_G) - g_base;
+        const float *Gi = G + (size_t)gi * (size_t)K * (size_t)K;
+        for (int k = 0; k < K; ++k) {
+            float g = 0.0f;
+            for (int l = 0; l < K; ++l) g = fmaf(Gi[k * K + l], (float)xg[(size_t)idx * K + l], g);
+            f_out[(size_t)idx * K + k] = f[(size_t)idx * K + k] - g;
+        }
+    }
+    return 0;
+}
+
 /* One CIM-CAC anneal's amplitudes and error variables after `steps` steps
  * (the N spins, then the auxiliary one), for the invariant tests.          */
 int oracle_cim_trajectory(int K, int q, const signed char *w, const float *G, const float *f,

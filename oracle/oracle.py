@@ -93,6 +93,10 @@ def lib():
             ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
             ctypes.c_void_p]
         L.oracle_cim_trajectory.restype = ctypes.c_int
+        L.oracle_delta_fields.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                          ctypes.c_int, ctypes.c_long, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.oracle_delta_fields.restype = ctypes.c_int
         L.oracle_max_threads.argtypes = []
         L.oracle_max_threads.restype = ctypes.c_int
         _lib = L
@@ -402,6 +406,78 @@ def detect(H, y, noise_var, qam, chains, sweeps, beta2, seed, inst_ids=None,
 
 # --------------------------------------------------------------------------
 # Downlink vector perturbation (paper §2.2, §3.3)
+
+# --------------------------------------------------------------------------
+# Detection around a guess (paper §2.3 Fig. 5 Delta-Ising form; §3.2 MMGaP-E)
+
+DELTA_WEIGHTS = np.array([1, 1], dtype=np.int8)
+
+
+def delta_fields(G, f, xg, inst_per_G=1, inst_ids=None):
+    """f' = f - G x_g (float32, fma chain over l ascending from 0) per instance."""
+    f = np.ascontiguousarray(f, dtype=np.float32)
+    n, K = f.shape
+    G = np.ascontiguousarray(G, dtype=np.float32).reshape(-1, K, K)
+    xg = np.ascontiguousarray(xg, dtype=np.int8).reshape(n, K)
+    ids = None if inst_ids is None else np.ascontiguousarray(inst_ids, dtype=np.uint32)
+    out = np.zeros((n, K), dtype=np.float32)
+    rc = lib().oracle_delta_fields(n, K, _ptr(G), int(inst_per_G), 0, _ptr(f), _ptr(xg),
+                                   _ptr(ids), _ptr(out))
+    if rc != 0:
+        raise RuntimeError(f"oracle_delta_fields failed ({rc})")
+    return out
+
+
+def detect_delta(H, y, noise_var, qam, chains, sweeps, beta2, seed, stages=1, inst_ids=None,
+                 init_mode=0, nthreads=0, cim=None, guess=None):
+    """Detection by moves around a guess (paper §2.3 Delta-Ising form, §3.2
+    MMGaP-E multi-stage).  Each real dimension moves by z in {-2, 0, 2} levels
+    (one neighbouring constellation point either way), encoded by two
+    unit-weight spins; the Ising problem keeps G and takes the fields
+    f' = f - G x_g.  A stage anneals it (Metropolis, or CIM-CAC when `cim` is
+    given) with the zero move as the fallback and the job seed + stage as the
+    Philox key; the winning move is applied and clamped to the constellation,
+    and the result replaces the guess only if its float32 energy is strictly
+    lower.  The guess starts at the sliced MMSE estimate (or `guess`, int8
+    levels [n][K]) and each stage starts from the previous stage's result.
+    Returns dict(sym, metric, levels, stage_levels [stages][n][K])."""
+    n_sc, n_sym, n_r = y.shape
+    n_t = H.shape[-1]
+    K, q = 2 * n_t, qam_bits(qam)
+    top = (1 << q) - 1
+    G, f_all = det_ising(H, y, qam)
+    ids = np.arange(n_sc * n_sym, dtype=np.uint32) if inst_ids is None \
+        else np.asarray(inst_ids, dtype=np.uint32)
+    f = f_all[ids]
+    if guess is None:
+        xg = slice_levels(mmse(H, y, noise_var), qam).reshape(-1, K)[ids].astype(np.int8)
+    else:
+        xg = np.ascontiguousarray(guess, dtype=np.int8).reshape(ids.size, K).copy()
+    zero = np.zeros((ids.size, K), dtype=np.int8)
+    history = []
+    for st in range(stages):
+        fp = delta_fields(G, f, xg, inst_per_G=n_sym, inst_ids=ids)
+        key = (int(seed) + st) & 0xFFFFFFFFFFFFFFFF
+        if cim is None:
+            res = solve(G, fp, K, 2, DELTA_WEIGHTS, chains, sweeps, beta2, key, x_fb=zero,
+                        inst_per_G=n_sym, inst_ids=ids, init_mode=init_mode, nthreads=nthreads)
+        else:
+            res = cim_solve(G, fp, K, 2, DELTA_WEIGHTS, chains, sweeps, cim, key, x_fb=zero,
+                            inst_per_G=n_sym, inst_ids=ids, init_mode=init_mode,
+                            nthreads=nthreads)
+        z = levels_from_spins(res["spins"], K, 2, DELTA_WEIGHTS).astype(np.int64)
+        xc = np.clip(xg.astype(np.int64) + z, -top, top).astype(np.int8)
+        for r in range(ids.size):
+            Gi = G[ids[r] // n_sym]
+            if level_energy32(Gi, f[r], xc[r]) < level_energy32(Gi, f[r], xg[r]):
+                xg[r] = xc[r]
+        history.append(xg.copy())
+    sc = ids // n_sym
+    sy = ids % n_sym
+    metric = det_metric(H[sc], y[sc, sy][:, None, :], xg, qam)
+    return dict(sym=levels_to_symbols(xg, qam), metric=metric, levels=xg, inst_ids=ids,
+                stage_levels=history)
+
 
 def zf_precoder(H: np.ndarray) -> np.ndarray:
     """W = H^H (H H^H)^-1 in float64.  H [.., n_u, n_t] -> W [.., n_t, n_u]."""
