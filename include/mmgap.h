@@ -205,6 +205,28 @@ int mmgap_detect(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, const
                  void *stream);
 
 /*
+ * mmgap_detect_delta -- uplink detection by moves around a guess (paper §2.3,
+ * the Delta-Ising form built around an initial guess, Fig. 5; §3.2 MMGaP-E,
+ * several stages each starting from the previous stage's solution).  Every
+ * real dimension may move by z in {-2, 0, 2} levels (the neighbouring
+ * constellation point either way), two unit-weight spins each; with levels
+ * x = x_g + z the problem keeps the couplings G and takes the fields
+ * f' = f - G x_g, f'_k = f_k - fma(G_k,K-1, xg_K-1, ... fma(G_k0, xg_0, 0)).
+ * Each of `stages` (1..64) stages anneals it with sched (Metropolis or CIM-CAC,
+ * as mmgap_solve with q = 2, w = {1, 1}; Philox key = sched->seed + stage), the
+ * zero move as the fallback; the winning move is applied, clamped to
+ * +-(sqrt(M) - 1), and kept iff the float32 energy x^T G x - 2 f^T x (the
+ * arithmetic of mmgap_solve) is strictly lower than the guess's.  The final
+ * guess is decoded as in mmgap_detect.
+ *   guess   [n_sc*n_sym][2 n_tx] int8 odd levels (nullable: the sliced MMSE
+ *           estimate of mmgap_build_ising)
+ *   sym_out, metric_out   as in mmgap_detect
+ */
+int mmgap_detect_delta(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, const void *y,
+                       const mmgap_schedule *sched, int stages, const signed char *guess,
+                       unsigned char *sym_out, float *metric_out, void *stream);
+
+/*
  * mmgap_vpp_precode -- downlink vector-perturbation precoding (paper §2.2 Eq.
  * VPP, §3.3): the same solver on (H_p = -tau W/2, y~ = W u) with the all-zeros
  * fallback.  H [n_sc][n_rx][n_tx], u [n_sc][n_sym][n_rx] complex64;

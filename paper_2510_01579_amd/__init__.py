@@ -34,7 +34,8 @@ STATUS = {0: "MMGAP_OK", -1: "MMGAP_EINVAL", -2: "MMGAP_ENOMEM", -3: "MMGAP_EDEV
           -4: "MMGAP_EUNSUPPORTED", -5: "MMGAP_EBUSY"}
 
 EXPORTS = ("mmgap_create", "mmgap_destroy", "mmgap_last_error", "mmgap_build_ising",
-           "mmgap_solve", "mmgap_detect", "mmgap_vpp_precode", "mmgap_set_profiling",
+           "mmgap_solve", "mmgap_detect", "mmgap_detect_delta", "mmgap_vpp_precode",
+           "mmgap_set_profiling",
            "mmgap_last_profile", "mmgap_plan_create", "mmgap_plan_launch", "mmgap_plan_info",
            "mmgap_plan_destroy", "mmgap_server_start", "mmgap_server_submit",
            "mmgap_server_poll", "mmgap_server_drain", "mmgap_server_stop")
@@ -106,6 +107,7 @@ def lib() -> ctypes.CDLL:
             L.mmgap_build_ising.argtypes = [vp, P, vp, vp, vp, vp, vp, vp, vp, vp, vp]
             L.mmgap_solve.argtypes = [vp, i, i, i, vp, vp, i, vp, vp, S, vp, vp, vp, vp]
             L.mmgap_detect.argtypes = [vp, P, vp, vp, S, vp, vp, vp]
+            L.mmgap_detect_delta.argtypes = [vp, P, vp, vp, S, i, vp, vp, vp, vp]
             L.mmgap_vpp_precode.argtypes = [vp, P, vp, vp, S, vp, vp, vp, vp]
             L.mmgap_set_profiling.argtypes = [vp, i]
             L.mmgap_last_profile.argtypes = [vp, ctypes.POINTER(f32), i]
@@ -391,6 +393,28 @@ class Context:
         st = stream if stream is not None else _stream(dev)
         self._check(lib().mmgap_detect(self._h, ctypes.byref(p), _ptr(H), _ptr(y),
                                        ctypes.byref(s), _ptr(sym), _ptr(met), st))
+        del keep
+        return sym, met
+
+    def detect_delta(self, H, y, qam, noise_var, chains, sweeps, beta2, seed, stages=1,
+                     guess=None, init=0, metric=True, stream=None, cim=None):
+        """Detection by moves around a guess (mmgap_detect_delta): `stages` anneals
+        of the {-2, 0, 2}-move problem from the sliced MMSE estimate (or `guess`,
+        int8 levels [n][2 n_tx]).  Returns (sym uint8 [n][n_tx], metric float32
+        [n] or None)."""
+        torch = _torch()
+        p = self._problem(KIND_DET, H, y, qam, noise_var, 0.0)
+        n = p.n_sc * p.n_sym
+        if guess is not None:
+            self._check_tensor(guess, "guess", torch.int8, (n, 2 * p.n_tx))
+        dev = self._dev()
+        sym = torch.empty((n, p.n_tx), dtype=torch.uint8, device=dev)
+        met = torch.empty((n,), dtype=torch.float32, device=dev) if metric else None
+        s, keep = self._schedule(chains, sweeps, beta2, seed, init, cim)
+        st = stream if stream is not None else _stream(dev)
+        self._check(lib().mmgap_detect_delta(self._h, ctypes.byref(p), _ptr(H), _ptr(y),
+                                             ctypes.byref(s), int(stages), _ptr(guess),
+                                             _ptr(sym), _ptr(met), st))
         del keep
         return sym, met
 

@@ -765,6 +765,95 @@ int mmgap_detect(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, const
     return end_call(ctx, st);
 }
 
+int mmgap_detect_delta(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, const void *y,
+                       const mmgap_schedule *sched, int stages, const signed char *guess,
+                       unsigned char *sym_out, float *metric_out, void *stream)
+{
+    if (!ctx) return MMGAP_EINVAL;
+    ProblemShape sh;
+    int rc = check_problem(ctx, prob, MMGAP_KIND_DET, &sh);
+    if (rc) return rc;
+    if ((rc = check_schedule(ctx, sched))) return rc;
+    if (stages < 1 || stages > mmgap::kMaxStages)
+        return fail(ctx, MMGAP_EUNSUPPORTED, "stages=%d outside 1..%d", stages, mmgap::kMaxStages);
+    if (sh.n_inst == 0) return MMGAP_OK;
+    if (!H || !y || !sym_out) return fail(ctx, MMGAP_EINVAL, "H, y and sym_out are required");
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    // the move problem: two unit-weight spins per real dimension
+    const int q = 2, KT = sh.KT, NW = mmgap::spin_words(KT, q), ni = sh.n_inst;
+    Bump plan;
+    const size_t oG = plan.take(sizeof(float) * (size_t)prob->n_sc * KT * KT);
+    const size_t of = plan.take(sizeof(float) * (size_t)ni * KT);
+    const size_t ofp = plan.take(sizeof(float) * (size_t)ni * KT);
+    const size_t oxg = plan.take((size_t)ni * KT);
+    const size_t oz = plan.take((size_t)ni * KT);
+    const size_t oE = plan.take(sizeof(float) * (size_t)ni * sched->chains);
+    const size_t oS = plan.take(sizeof(uint32_t) * (size_t)ni * sched->chains * NW);
+    if ((rc = ensure_scratch(ctx, plan.off))) return rc;
+    if ((rc = begin_call(ctx, st))) return rc;
+    prof_mark(ctx, 0, st);
+    mmgap::DetBuildArgs b{};
+    b.H = (const float2 *)H;
+    b.y = (const float2 *)y;
+    b.n_sc = prob->n_sc;
+    b.n_r = prob->n_rx;
+    b.n_t = prob->n_tx;
+    b.n_sym = prob->n_sym;
+    b.ld = KT;
+    b.qtop = (1 << sh.q) - 1;
+    b.c = qam_c(prob->qam);
+    b.c2 = qam_c2(prob->qam);
+    b.noise_var = (double)prob->noise_var;
+    b.G = at<float>(ctx, oG);
+    b.f = at<float>(ctx, of);
+    b.x_fb = at<signed char>(ctx, oxg);     // the sliced MMSE estimate is the first guess
+    b.ynorm = nullptr;
+    hipError_t e = mmgap::launch_det_build(b, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "build launch");
+    if (guess) {
+        e = mmgap::launch_pad_rows_i8(guess, at<signed char>(ctx, oxg), ni, sh.K, KT, st);
+        if (e != hipSuccess) return hip_fail(ctx, e, "guess copy");
+    }
+    e = hipMemsetAsync(at<signed char>(ctx, oz), 0, (size_t)ni * KT, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMemsetAsync(zero moves)");
+    const int w[mmgap::kMaxQ] = {1, 1, 0, 0};
+    for (int s = 0; s < stages; ++s) {
+        mmgap::DeltaPrepArgs d{};
+        d.G = b.G;
+        d.inst_per_G = prob->n_sym;
+        d.f = b.f;
+        d.guess = at<signed char>(ctx, oxg);
+        d.f_out = at<float>(ctx, ofp);
+        d.n_inst = ni;
+        d.KT = KT;
+        e = mmgap::launch_delta_prep(d, st);
+        if (e != hipSuccess) return hip_fail(ctx, e, "move-field launch");
+        mmgap_schedule ss = *sched;
+        ss.seed = sched->seed + (uint64_t)s;      // one Philox key per stage
+        mmgap::SelectArgs sel{};
+        sel.mode = mmgap::kSelectDelta;
+        sel.H = (const float2 *)H;
+        sel.y = (const float2 *)y;
+        sel.n_rows = prob->n_rx;
+        sel.n_cols = prob->n_tx;
+        sel.n_sym = prob->n_sym;
+        sel.c = b.c;
+        sel.sym_out = sym_out;
+        sel.metric_out = metric_out;
+        sel.guess = at<signed char>(ctx, oxg);
+        sel.f_full = b.f;
+        sel.qtop = b.qtop;
+        sel.dq = sh.q;
+        sel.decode = s == stages - 1;
+        rc = run_solver(ctx, st, ni, sh.K, q, KT, w, b.G, prob->n_sym, at<float>(ctx, ofp),
+                        at<signed char>(ctx, oz), &ss, at<float>(ctx, oE), at<uint32_t>(ctx, oS),
+                        sel);
+        if (rc) return rc;
+    }
+    return end_call(ctx, st);
+}
+
 int mmgap_vpp_precode(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, const void *u,
                       const mmgap_schedule *sched, signed char *v_out, void *x_out,
                       float *gamma_out, void *stream)

@@ -13,6 +13,7 @@ constexpr int kMaxK = 32;
 constexpr int kMaxQ = 4;
 constexpr int kMaxChains = 1024;
 constexpr int kMaxSweeps = 8192;
+constexpr int kMaxStages = 64;     // stages of detection around a guess
 // Metropolis threshold table: T[j] = round(2^16 2^(-j/64)), j < 1024; T[1024] = 0
 constexpr int kAcceptTable = 1025;
 
@@ -73,7 +74,7 @@ struct AnnealArgs {
     CimParams cim;          // launch_cim only (sweeps = Euler steps, beta2 unused)
 };
 
-enum SelectMode { kSelectSolve = 0, kSelectDet = 1, kSelectVpp = 2 };
+enum SelectMode { kSelectSolve = 0, kSelectDet = 1, kSelectVpp = 2, kSelectDelta = 3 };
 
 struct SelectArgs {
     int mode;
@@ -102,6 +103,23 @@ struct SelectArgs {
     signed char *v_out;     // [n_inst][2 n_u]
     float2 *x_out;          // [n_inst][n_tx] or null
     float *gamma_out;       // [n_inst] or null
+    // detection around a guess (kSelectDelta): the winning move z (levels in
+    // {-2, 0, 2}) is applied to guess, clamped to +-qtop, and kept when the
+    // float32 energy with the full fields drops; decode != 0 then decodes the
+    // guess as kSelectDet does
+    signed char *guess;     // [n_inst][KT] in/out
+    const float *f_full;    // [n_inst][KT]
+    int qtop, decode, dq;   // dq: bits per real dimension of the constellation (decode)
+};
+
+// Fields of the move problem around a guess: f' = f - G x_g per instance.
+struct DeltaPrepArgs {
+    const float *G;         // [n_G][KT][KT]
+    int inst_per_G;
+    const float *f;         // [n_inst][KT]
+    const signed char *guess;   // [n_inst][KT]
+    float *f_out;           // [n_inst][KT]
+    int n_inst, KT;
 };
 
 struct ExpandArgs {
@@ -162,6 +180,7 @@ hipError_t launch_anneal(int KT, int q, const AnnealArgs &a, hipStream_t s);
 // CIM-CAC anneals (same outputs as launch_anneal); KT q <= 32.
 hipError_t launch_cim(int KT, int q, const AnnealArgs &a, hipStream_t s);
 hipError_t launch_select(const SelectArgs &a, hipStream_t s);
+hipError_t launch_delta_prep(const DeltaPrepArgs &a, hipStream_t s);
 hipError_t launch_expand(const ExpandArgs &a, hipStream_t s);
 // copy [n][K][K] -> [n][KT][KT] (and [m][K] -> [m][KT]) with zero padding
 hipError_t launch_pad_matrix(const float *src, float *dst, int n, int K, int KT, hipStream_t s);

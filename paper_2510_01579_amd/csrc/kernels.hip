@@ -907,6 +907,23 @@ __device__ float fallback_energy(const float *Gi, int KT, int K, const float *fi
     return e;
 }
 
+// Energy of levels lv (this wavefront's LDS copy, K entries) with the chains'
+// arithmetic (one wavefront; `terms` its LDS scratch of 32 floats).
+__device__ float wave_level_energy(const float *Gi, int KT, int K, const float *fi, const int *lv,
+                                   float *terms, int lane)
+{
+    if (lane < K) {
+        float acc = -fi[lane];
+        for (int l = 0; l < K; ++l) acc = fmaf(Gi[lane * KT + l], (float)lv[l], acc);
+        terms[lane] = acc - fi[lane];
+    }
+    wave_sync_lds();
+    float e = 0.0f;
+    for (int k = 0; k < K; ++k) e = fmaf((float)lv[k], terms[k], e);
+    wave_sync_lds();
+    return e;
+}
+
 // Levels of the winning candidate into lv[0..K): the fallback's, or those of
 // the spin words S (bit set = spin -1).
 __device__ void winning_levels(bool use_fb, const signed char *xi, const uint32_t *S, int K, int q,
@@ -1169,6 +1186,7 @@ __global__ void __launch_bounds__(kBlock) k_select(SelectArgs a)
     __shared__ float terms[kWavesPerBlock][32];
     __shared__ int lvs[kWavesPerBlock][32];
     __shared__ double2 zsh[kWavesPerBlock][16];
+    __shared__ int cand[kWavesPerBlock][32];
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -1223,6 +1241,29 @@ __global__ void __launch_bounds__(kBlock) k_select(SelectArgs a)
         return;
     }
     const int sc = n / a.n_sym, sy = n % a.n_sym;
+    if (a.mode == kSelectDelta) {
+        // candidate = guess + move, clamped; kept iff its energy is lower
+        signed char *xg = a.guess + (size_t)n * KT;
+        const float *ff = a.f_full + (size_t)n * KT;
+        if (lane < K) {
+            const int v = (int)xg[lane] + lvs[wave][lane];
+            cand[wave][lane] = v < -a.qtop ? -a.qtop : (v > a.qtop ? a.qtop : v);
+            lvs[wave][lane] = (int)xg[lane];
+        }
+        wave_sync_lds();
+        const float Ec = wave_level_energy(Gi, KT, K, ff, cand[wave], terms[wave], lane);
+        const float Eg = wave_level_energy(Gi, KT, K, ff, lvs[wave], terms[wave], lane);
+        const bool keep = Ec < Eg;
+        if (keep && lane < K) {
+            xg[lane] = (signed char)cand[wave][lane];
+            lvs[wave][lane] = cand[wave][lane];
+        }
+        wave_sync_lds();
+        if (!a.decode) return;
+        decode_det(lvs[wave], n, sc, sy, a.n_sym, a.n_rows, a.n_cols, a.dq, a.c,
+                   a.H + (size_t)sc * a.n_rows * a.n_cols, a.y, a.sym_out, a.metric_out, lane);
+        return;
+    }
     if (a.mode == kSelectDet) {
         decode_det(lvs[wave], n, sc, sy, a.n_sym, a.n_rows, a.n_cols, q, a.c,
                    a.H + (size_t)sc * a.n_rows * a.n_cols, a.y, a.sym_out, a.metric_out, lane);
@@ -1578,6 +1619,20 @@ k_fused(const FusedJob *__restrict__ jobs, const FusedItem *__restrict__ items, 
     }
 }
 
+// f' = f - G x_g, one thread per (instance, dimension); g as a chain of fused
+// multiply-adds over l ascending from 0.
+__global__ void __launch_bounds__(kBlock) k_delta_prep(DeltaPrepArgs a)
+{
+    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (size_t)a.n_inst * a.KT) return;
+    const int n = (int)(t / a.KT), k = (int)(t % a.KT);
+    const float *Gk = a.G + ((size_t)(n / a.inst_per_G) * a.KT + k) * a.KT;
+    const signed char *xg = a.guess + (size_t)n * a.KT;
+    float g = 0.0f;
+    for (int l = 0; l < a.KT; ++l) g = fmaf(Gk[l], (float)xg[l], g);
+    a.f_out[t] = a.f[t] - g;
+}
+
 __global__ void k_reset_counters(unsigned int *counters, int n)
 {
     if (blockIdx.x == 0 && (int)threadIdx.x < n) counters[threadIdx.x] = 0u;
@@ -1774,6 +1829,16 @@ hipError_t launch_select(const SelectArgs &a, hipStream_t s)
     if (a.n_inst <= 0) return hipSuccess;
     const int blocks = (a.n_inst + kWavesPerBlock - 1) / kWavesPerBlock;
     hipLaunchKernelGGL(k_select, dim3(blocks), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_delta_prep(const DeltaPrepArgs &a, hipStream_t s)
+{
+    const size_t total = (size_t)a.n_inst * a.KT;
+    if (total == 0) return hipSuccess;
+    const size_t blocks = (total + kBlock - 1) / kBlock;
+    if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_delta_prep, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
