@@ -252,6 +252,10 @@ int mmgap_vpp_precode(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, 
  *   VPP  y_or_u = u; out0 = v_out [n_sc*n_sym][2 n_rx] int8 (required),
  *        out1 = x_out [n_sc*n_sym][n_tx] complex64 (nullable),
  *        out2 = gamma_out [n_sc*n_sym] float32 (nullable).
+ * stages = 0: the problem as mmgap_detect / mmgap_vpp_precode solve it; DET
+ * with stages >= 1: detection by moves around the sliced MMSE estimate as
+ * mmgap_detect_delta with that many stages (the stages of a work item run
+ * inside the item's workgroup).
  * Every output of a job is bit-identical to that of the single-job entry point
  * on the same arguments, whatever else is in the batch: a chain's random stream
  * depends only on the job's seed and its instance and chain index.
@@ -263,6 +267,7 @@ typedef struct {
     const void *H;            /* device, [n_sc][n_rx][n_tx] complex64 */
     const void *y_or_u;       /* device, [n_sc][n_sym][n_rx] complex64 */
     void *out0, *out1, *out2; /* device, see above */
+    int stages;               /* 0, or DET: stages of moves around the MMSE estimate (1..64) */
 } mmgap_job;
 
 typedef struct mmgap_plan mmgap_plan;

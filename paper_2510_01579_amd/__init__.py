@@ -81,7 +81,7 @@ CIM_STEPS = 128
 class Job(ctypes.Structure):
     _fields_ = [("prob", Problem), ("sched", Schedule), ("H", ctypes.c_void_p),
                 ("y_or_u", ctypes.c_void_p), ("out0", ctypes.c_void_p),
-                ("out1", ctypes.c_void_p), ("out2", ctypes.c_void_p)]
+                ("out1", ctypes.c_void_p), ("out2", ctypes.c_void_p), ("stages", ctypes.c_int)]
 
 
 _lib = None
@@ -437,9 +437,11 @@ class Context:
         return v, x, g
 
     # ------------------------------------------------------------------ batches
-    def det_job(self, H, y, qam, noise_var, chains, sweeps, beta2, seed, init=0, metric=True):
+    def det_job(self, H, y, qam, noise_var, chains, sweeps, beta2, seed, init=0, metric=True,
+                stages=0):
         """A detection job for ``plan_create`` with its output tensors allocated:
-        outputs["sym"] uint8 [n][n_tx], outputs["metric"] float32 [n] or None."""
+        outputs["sym"] uint8 [n][n_tx], outputs["metric"] float32 [n] or None.
+        stages >= 1: detection by moves around the MMSE estimate (detect_delta)."""
         torch = _torch()
         p = self._problem(KIND_DET, H, y, qam, noise_var, 0.0)
         n = p.n_sc * p.n_sym
@@ -448,7 +450,8 @@ class Context:
                    metric=torch.empty((n,), dtype=torch.float32, device=dev) if metric else None)
         s, keep = self._schedule(chains, sweeps, beta2, seed, init)
         job = Job(p, s, _ptr(H).value, _ptr(y).value, _ptr(out["sym"]).value,
-                  None if out["metric"] is None else _ptr(out["metric"]).value, None)
+                  None if out["metric"] is None else _ptr(out["metric"]).value, None,
+                  int(stages))
         return dict(job=job, keep=(H, y, keep), outputs=out)
 
     def vpp_job(self, H, u, qam, chains, sweeps, beta2, seed, tau=0.0, want_x=True,

@@ -310,10 +310,10 @@ int run_solver(mmgap_ctx *ctx, hipStream_t st, int n_inst, int K, int q, int KT,
 
 // Relative cost of one work item: the workgroup is held for `sweeps` sweeps of
 // KT Q flip attempts, each about 20 operations plus the K-term field row shared
-// by the Q attempts of a dimension.
+// by the Q attempts of a dimension, once per stage.
 double item_cost(const mmgap::FusedJob &j)
 {
-    return (double)j.sweeps * j.KT * (20.0 * j.Q + j.KT);
+    return (double)j.sweeps * j.KT * (20.0 * j.Q + j.KT) * (j.stages > 0 ? j.stages : 1);
 }
 
 }  // namespace
@@ -340,7 +340,14 @@ int batch_layout(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, BatchLayout 
                         jb.sched.chains, kMaxFusedChains);
         if (sh.n_inst > 0 && (!jb.H || !jb.y_or_u || !jb.out0))
             return fail(ctx, MMGAP_EINVAL, "job %d: H, y_or_u and out0 are required", j);
-        const int variant = mmgap::fused_variant(sh.KT, sh.q);
+        if (jb.stages < 0 || jb.stages > mmgap::kMaxStages)
+            return fail(ctx, MMGAP_EUNSUPPORTED, "job %d: stages=%d outside 0..%d", j, jb.stages,
+                        mmgap::kMaxStages);
+        if (jb.stages > 0 && jb.prob.kind != MMGAP_KIND_DET)
+            return fail(ctx, MMGAP_EUNSUPPORTED, "job %d: stages apply to detection only", j);
+        // moves around a guess: two unit-weight spins per real dimension
+        const int aq = jb.stages > 0 ? 2 : sh.q;
+        const int variant = mmgap::fused_variant(sh.KT, aq);
         if (variant < 0) return fail(ctx, MMGAP_EUNSUPPORTED, "job %d: no fused variant", j);
         const mmgap_problem &p = jb.prob;
         mmgap::FusedJob &f = L.jobs[j];
@@ -348,7 +355,9 @@ int batch_layout(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, BatchLayout 
         f.kind = p.kind;
         f.variant = variant;
         f.KT = sh.KT;
-        f.Q = sh.q;
+        f.Q = aq;
+        f.dq = sh.q;
+        f.stages = jb.stages;
         f.K = sh.K;
         f.n_rows = p.n_rx;
         f.n_cols = p.n_tx;
@@ -360,7 +369,8 @@ int batch_layout(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, BatchLayout 
         f.wpi = jb.sched.chains <= 64 ? 1 : (jb.sched.chains <= 128 ? 2 : 4);
         f.glanes = packed_lanes(jb.sched.chains, 0, 16);   // an item lies in one subcarrier
         f.ldf = (sh.KT + 31) / 32 * 32;   // 128-byte field rows: no scalar-cache line is shared
-        if (p.kind == MMGAP_KIND_DET) det_weights(sh.q, f.w);
+        if (jb.stages > 0) vpp_weights(f.w);      // {1, 1}: a move of -2, 0 or 2 levels
+        else if (p.kind == MMGAP_KIND_DET) det_weights(sh.q, f.w);
         else vpp_weights(f.w);
         f.key0 = (uint32_t)jb.sched.seed;
         f.key1 = (uint32_t)(jb.sched.seed >> 32);
@@ -401,6 +411,7 @@ int batch_layout(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, BatchLayout 
     L.o_counters = lay.take(sizeof(unsigned int) * mmgap::kFusedClasses);
     L.ob.resize(n_jobs);
     L.of.resize(n_jobs);
+    L.ofp.resize(n_jobs);
     L.ox.resize(n_jobs);
     for (int j = 0; j < n_jobs; ++j) L.ob[j] = lay.take(sizeof(float) * L.betas[j].size());
     L.header_bytes = lay.off;
@@ -408,6 +419,7 @@ int batch_layout(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, BatchLayout 
         const mmgap::FusedJob &f = L.jobs[j];
         const size_t ni = (size_t)f.n_sc * f.n_sym;
         L.of[j] = lay.take(sizeof(float) * ni * f.ldf);
+        L.ofp[j] = f.stages > 0 ? lay.take(sizeof(float) * ni * f.ldf) : 0;
         L.ox[j] = lay.take(ni * (size_t)f.KT);
     }
     L.bytes = lay.off;
@@ -420,6 +432,7 @@ void batch_bind(BatchLayout &L, char *base, std::vector<unsigned char> &image)
         mmgap::FusedJob &f = L.jobs[j];
         f.beta2 = reinterpret_cast<const float *>(base + L.ob[j]);
         f.f = reinterpret_cast<float *>(base + L.of[j]);
+        f.fp = f.stages > 0 ? reinterpret_cast<float *>(base + L.ofp[j]) : nullptr;
         f.x_fb = reinterpret_cast<signed char *>(base + L.ox[j]);
     }
     image.assign(L.header_bytes, 0);

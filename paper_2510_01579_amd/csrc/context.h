@@ -96,13 +96,13 @@ int check_schedule(mmgap_ctx *ctx, const mmgap_schedule *s);
 // descriptors, work items grouped by register class (each group by decreasing
 // cost), and byte offsets of one device block holding
 //   [ descriptors | items | class counters | schedules ]   (the header, uploaded)
-//   [ per job: fields | fallbacks ]   (scratch; the couplings, H and the VPP
-//   inverse of a work item live in LDS only)
+//   [ per job: fields | move fields (detection around a guess) | fallbacks ]
+//   (scratch; the couplings, H and the VPP inverse of a work item live in LDS only)
 struct BatchLayout {
     std::vector<FusedJob> jobs;
     std::vector<FusedItem> items;
     std::vector<std::vector<float>> betas;
-    std::vector<size_t> of, ox, ob;
+    std::vector<size_t> of, ofp, ox, ob;
     size_t o_jobs = 0, o_items = 0, o_counters = 0;
     size_t header_bytes = 0;
     size_t bytes = 0;

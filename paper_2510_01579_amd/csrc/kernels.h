@@ -141,6 +141,8 @@ struct FusedJob {
     int n_rows, n_cols;     // H is n_rows x n_cols (DET: n_r x n_t; VPP: n_u x n_tx)
     int n_sym, n_sc;
     int chains, sweeps, init, wpi;
+    int stages;             // 0, or detection by moves around the MMSE guess: stages
+    int dq;                 // bits per real dimension of the constellation (decode, clamp)
     int glanes;             // 0, or lanes per instance (power of two in [max(chains, 4), 32])
                             // with 64/glanes instances of the item per wavefront
     int ldf;                // row stride of f in floats: a multiple of 32 (128 bytes), >= KT
@@ -151,6 +153,7 @@ struct FusedJob {
     const float2 *y;        // y (DET) or u (VPP)
     const float *beta2;     // [sweeps] device
     float *f;               // [n_sc*n_sym][ldf] scratch
+    float *fp;              // [n_sc*n_sym][ldf] scratch: move fields f - G x_g (stages > 0)
     signed char *x_fb;      // [n_sc*n_sym][KT] scratch
     void *out0, *out1, *out2;   // DET: sym, metric; VPP: v, x, gamma
 };

@@ -92,7 +92,8 @@ __device__ __forceinline__ void upper_pair(int p, int n, int &i, int &j)
 // Hides a pointer's value from the optimiser so that loads through it are
 // issued where written instead of being hoisted out of the sweep loop into
 // registers.  The result lives in the constant
-// address space, so wave-uniform loads through it use the scalar cache.
+// address space, so wave-uniform loads through it use the scalar cache.  The
+// pointer must be wave-uniform and known to the compiler as such.
 typedef const float __attribute__((address_space(4))) cfloat;
 __device__ __forceinline__ cfloat *opaque(const float *p)
 {
@@ -924,6 +925,29 @@ __device__ float wave_level_energy(const float *Gi, int KT, int K, const float *
     return e;
 }
 
+// Applies an instance's winning move (lv: the move levels z in {-2, 0, 2}, this
+// wavefront's LDS copy) to its guess xg (a device row of levels): the candidate
+// clamp(xg + z, -qtop, qtop) replaces the guess iff its energy with the full
+// fields ff is strictly lower.  lv then holds the guess.  cand: LDS scratch of
+// 32 ints.
+__device__ void apply_move(int *lv, signed char *xg, const float *Gi, int KT, int K,
+                           const float *ff, int qtop, int *cand, float *terms, int lane)
+{
+    if (lane < K) {
+        const int v = (int)xg[lane] + lv[lane];
+        cand[lane] = v < -qtop ? -qtop : (v > qtop ? qtop : v);
+        lv[lane] = (int)xg[lane];
+    }
+    wave_sync_lds();
+    const float Ec = wave_level_energy(Gi, KT, K, ff, cand, terms, lane);
+    const float Eg = wave_level_energy(Gi, KT, K, ff, lv, terms, lane);
+    if (Ec < Eg && lane < K) {
+        xg[lane] = (signed char)cand[lane];
+        lv[lane] = cand[lane];
+    }
+    wave_sync_lds();
+}
+
 // Levels of the winning candidate into lv[0..K): the fallback's, or those of
 // the spin words S (bit set = spin -1).
 __device__ void winning_levels(bool use_fb, const signed char *xi, const uint32_t *S, int K, int q,
@@ -1242,23 +1266,8 @@ __global__ void __launch_bounds__(kBlock) k_select(SelectArgs a)
     }
     const int sc = n / a.n_sym, sy = n % a.n_sym;
     if (a.mode == kSelectDelta) {
-        // candidate = guess + move, clamped; kept iff its energy is lower
-        signed char *xg = a.guess + (size_t)n * KT;
-        const float *ff = a.f_full + (size_t)n * KT;
-        if (lane < K) {
-            const int v = (int)xg[lane] + lvs[wave][lane];
-            cand[wave][lane] = v < -a.qtop ? -a.qtop : (v > a.qtop ? a.qtop : v);
-            lvs[wave][lane] = (int)xg[lane];
-        }
-        wave_sync_lds();
-        const float Ec = wave_level_energy(Gi, KT, K, ff, cand[wave], terms[wave], lane);
-        const float Eg = wave_level_energy(Gi, KT, K, ff, lvs[wave], terms[wave], lane);
-        const bool keep = Ec < Eg;
-        if (keep && lane < K) {
-            xg[lane] = (signed char)cand[wave][lane];
-            lvs[wave][lane] = cand[wave][lane];
-        }
-        wave_sync_lds();
+        apply_move(lvs[wave], a.guess + (size_t)n * KT, Gi, KT, K, a.f_full + (size_t)n * KT,
+                   a.qtop, cand[wave], terms[wave], lane);
         if (!a.decode) return;
         decode_det(lvs[wave], n, sc, sy, a.n_sym, a.n_rows, a.n_cols, a.dq, a.c,
                    a.H + (size_t)sc * a.n_rows * a.n_cols, a.y, a.sym_out, a.metric_out, lane);
@@ -1305,6 +1314,8 @@ struct FusedCommon {
     float terms[kWavesPerBlock][32];
     int lvs[kWavesPerBlock][32];
     double2 zsh[kWavesPerBlock][16];
+    int cand[kWavesPerBlock][32];
+    signed char zmove[32];  // the zero move (fallback of detection around a guess)
     int item;               // the current work item, published by thread 0
 };
 __shared__ FusedCommon g_fc;
@@ -1382,6 +1393,7 @@ struct FusedItemLds {
     const float2 *H;
     const double2 *Z;
     int ldz;
+    int stage;              // stage of a job of moves around a guess
 };
 
 template <int KT, int Q, bool PACKED>
@@ -1401,11 +1413,24 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
     const int wpi = rfl(jp->wpi);                       // wavefronts per instance: 1, 2 or 4
     const int ldf = rfl(jp->ldf);
     const int w[4] = {rfl(jp->w[0]), rfl(jp->w[1]), rfl(jp->w[2]), rfl(jp->w[3])};
-    const uint32_t key0 = rflu(jp->key0), key1 = rflu(jp->key1);
+    // moves around a guess (stages > 0): the anneal takes the move fields and
+    // the zero move as its fallback, Philox key seed + stage; the winning move
+    // updates the guess (x_fb) and the last stage decodes the guess
+    const int stages = rfl(jp->stages);
+    const bool delta = stages > 0;
+    const int stage = rfl(lds.stage);
+    uint32_t key0 = rflu(jp->key0), key1 = rflu(jp->key1);
+    if (delta) {
+        const uint64_t kk = (((uint64_t)key1 << 32) | key0) + (uint64_t)stage;
+        key0 = rflu((uint32_t)kk);
+        key1 = rflu((uint32_t)(kk >> 32));
+    }
+    const int dq = rfl(jp->dq);
     const double c = rfld(jp->c), tau = rfld(jp->tau);
     const float2 *y = uniform_ptr(jp->y);
     const float *beta2 = uniform_ptr(jp->beta2);
-    const float *fbase = uniform_ptr(jp->f);
+    const float *ffull = uniform_ptr(jp->f);
+    const float *fbase = delta ? uniform_ptr(jp->fp) : ffull;
     const signed char *xbase = uniform_ptr(jp->x_fb);
     void *out0 = uniform_ptr(jp->out0), *out1 = uniform_ptr(jp->out1);
     void *out2 = uniform_ptr(jp->out2);
@@ -1425,7 +1450,7 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
         const int r = first + (valid ? grp : 0);
         const int n = sc * n_sym + sym0 + r;
         const float *fi = fbase + (size_t)n * ldf;
-        const signed char *xi = xbase + (size_t)n * KT;
+        const signed char *xi = delta ? sh.zmove : xbase + (size_t)n * KT;
         uint32_t bits[NW];
         const float E = anneal_lane<KT, Q, true>(Gi, fi, xi, beta2, sh.T, sweeps, w, key0, key1,
                                                  init, (uint32_t)chn, (uint32_t)n, bits);
@@ -1450,11 +1475,18 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
             const float Ebest = __shfl(E, wl, 64);
             const int ng = sc * n_sym + sym0 + first + g;
             const float *fg = fbase + (size_t)ng * ldf;
-            const signed char *xg = xbase + (size_t)ng * KT;
+            const signed char *xg = delta ? sh.zmove : xbase + (size_t)ng * KT;
             const float Efb = fallback_energy(Gi, KT, K, fg, xg, sh.terms[wave], lane);
             const bool use_fb = energy_less(Efb, Ebest);
             winning_levels(use_fb, xg, S, K, Q, w, sh.lvs[wave], lane);
-            if (kind == 0) {
+            if (delta) {
+                apply_move(sh.lvs[wave], const_cast<signed char *>(xbase) + (size_t)ng * KT, Gi, KT,
+                           K, ffull + (size_t)ng * ldf, (1 << dq) - 1, sh.cand[wave],
+                           sh.terms[wave], lane);
+                if (stage == stages - 1)
+                    decode_det(sh.lvs[wave], ng, sc, sym0 + first + g, n_sym, n_rows, n_cols, dq,
+                               c, lds.H, y, (unsigned char *)out0, (float *)out1, lane);
+            } else if (kind == 0) {
                 decode_det(sh.lvs[wave], ng, sc, sym0 + first + g, n_sym, n_rows, n_cols, Q, c,
                            lds.H, y, (unsigned char *)out0, (float *)out1, lane);
             } else {
@@ -1472,12 +1504,18 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
     const int n = sc * n_sym + sym0 + (active ? r0 : 0);
     const int ch = chunk * 64 + lane;
     const float *fi = fbase + (size_t)n * ldf;
-    const signed char *xi = xbase + (size_t)n * KT;
+    const signed char *xi = delta ? sh.zmove : xbase + (size_t)n * KT;
     uint32_t bits[NW];
     float E = 0.0f;
     if (active) {
-        E = anneal_lane<KT, Q, false>(Gi, fi, xi, beta2, sh.T, sweeps, w, key0, key1, init,
-                                      (uint32_t)ch, (uint32_t)n, bits);
+        // the move fields are rewritten at every stage, so they are read with
+        // vector loads (the scalar cache is not updated by the stores)
+        if (delta)
+            E = anneal_lane<KT, Q, true>(Gi, fi, xi, beta2, sh.T, sweeps, w, key0, key1, init,
+                                         (uint32_t)ch, (uint32_t)n, bits);
+        else    // the row is wave-uniform (re-read from the first lane for the compiler)
+            E = anneal_lane<KT, Q, false>(Gi, uniform_ptr(fi), xi, beta2, sh.T, sweeps, w, key0,
+                                          key1, init, (uint32_t)ch, (uint32_t)n, bits);
         uint64_t key = ~0ull;
         if (ch < chains) key = ((uint64_t)energy_key(E) << 32) | (uint32_t)ch;
         key = wave_min_u64(key);
@@ -1506,7 +1544,13 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
     const bool use_fb = energy_less(Efb, Ebest);
     winning_levels(use_fb, xi, S, K, Q, w, sh.lvs[wave], lane);
     const int sy = sym0 + r0;
-    if (kind == 0) {
+    if (delta) {
+        apply_move(sh.lvs[wave], const_cast<signed char *>(xbase) + (size_t)n * KT, Gi, KT, K,
+                   ffull + (size_t)n * ldf, (1 << dq) - 1, sh.cand[wave], sh.terms[wave], lane);
+        if (stage == stages - 1)
+            decode_det(sh.lvs[wave], n, sc, sy, n_sym, n_rows, n_cols, dq, c, lds.H, y,
+                       (unsigned char *)out0, (float *)out1, lane);
+    } else if (kind == 0) {
         decode_det(sh.lvs[wave], n, sc, sy, n_sym, n_rows, n_cols, Q, c, lds.H, y,
                    (unsigned char *)out0, (float *)out1, lane);
     } else {
@@ -1556,6 +1600,7 @@ k_fused(const FusedJob *__restrict__ jobs, const FusedItem *__restrict__ items, 
     FusedCommon &sh = g_fc;
     auto &bs = fused_build_shared<CLS>();
     for (int e = threadIdx.x; e <= kAcceptSteps; e += kBlock) sh.T[e] = accept_table[e];
+    if (threadIdx.x < 32) sh.zmove[threadIdx.x] = 0;
     // the first round of items is taken by block index, the rest through the
     // work counter (which every launch starts at zero)
     bool first = true;
@@ -1583,7 +1628,7 @@ k_fused(const FusedJob *__restrict__ jobs, const FusedItem *__restrict__ items, 
             if (s0 > 0) __syncthreads();      // the previous pass is done with the scratch
             if (jb.kind == 0) {
                 build_det_sc(jb.H, jb.y, jb.n_rows, jb.n_cols, jb.n_sym, it.sc, sym, cnt, jb.KT,
-                             jb.ldf, (1 << jb.Q) - 1, jb.c, jb.c2, jb.noise_var, Gs, fs, xs,
+                             jb.ldf, (1 << jb.dq) - 1, jb.c, jb.c2, jb.noise_var, Gs, fs, xs,
                              nullptr, bs.det(), tid);
             } else {
                 build_vpp_sc(jb.H, jb.y, jb.n_rows, jb.n_cols, jb.n_sym, it.sc, sym, cnt, jb.KT,
@@ -1615,7 +1660,35 @@ k_fused(const FusedJob *__restrict__ jobs, const FusedItem *__restrict__ items, 
             lds.Z = bs.vpp().Zs;
             lds.ldz = FusedClassTraits<CLS>::kNUV;
         }
-        fused_dispatch<CLS>(jb.variant, jb.glanes > 0, jobs, it, lds, tid);
+        // moves around a guess: per stage the move fields f' = f - G x_g of the
+        // item's instances (the guesses start as the build's sliced MMSE
+        // estimates and are updated by the stage before), then the anneal
+        const int nst = jb.stages > 0 ? jb.stages : 1;
+        for (int st = 0; st < nst; ++st) {
+            if (jb.stages > 0) {
+                if (st > 0) {          // the previous stage's guesses are written
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                    __syncthreads();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                }
+                const int KT = jb.KT, ldf = jb.ldf;
+                for (int e = tid; e < it.ns * KT; e += kBlock) {
+                    const int r = e / KT, k = e % KT;
+                    const size_t n = (size_t)it.sc * jb.n_sym + it.sym0 + r;
+                    const signed char *xg = jb.x_fb + n * KT;
+                    float g = 0.0f;
+                    for (int l = 0; l < KT; ++l) g = fmaf(bs.G[k * KT + l], (float)xg[l], g);
+                    jb.fp[n * ldf + k] = jb.f[n * ldf + k] - g;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                __syncthreads();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            }
+            lds.stage = st;
+            fused_dispatch<CLS>(jb.variant, jb.glanes > 0, jobs, it, lds, tid);
+        }
     }
 }
 
