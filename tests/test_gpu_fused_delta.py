@@ -165,13 +165,14 @@ def test_fused_delta_matches_oracle_directly(ctx, mix):
 
 
 def test_fused_delta_full_slot_16x16_64qam(ctx):
-    """The 16x16 64-QAM slot (3276 x 12, 25 dB), 16 chains x 25 sweeps, one
-    stage around the MMSE guess: the plan equals the multi-launch entry point."""
-    note("fused delta full slot 16x16 64-QAM 3276x12 16x25 1 stage")
+    """The 16x16 64-QAM slot (3276 x 12, 25 dB), 16 chains x 25 sweeps, two
+    stages around the MMSE guess, chains started at the zero move: the plan
+    equals the multi-launch entry point."""
+    note("fused delta full slot 16x16 64-QAM 3276x12 16x25 2 stages init 1")
     d = W.det_slot(3001, 16, 16, 64, 3276, 12, 25.0)
     beta2 = W.linear_beta2(25, *W.det_beta_range(64, 16, d.noise_var))
     inp = dict(H=dev(d.H), y=dev(d.y), qam=64, noise_var=d.noise_var, chains=16, sweeps=25,
-               beta2=beta2, seed=W.job_seed(3001), stages=1, init=1)
+               beta2=beta2, seed=W.job_seed(3001), stages=2, init=1)
     ref = single_call(ctx, inp)
     job = job_of(ctx, inp)
     plan = ctx.plan_create([job])

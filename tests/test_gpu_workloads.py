@@ -186,3 +186,43 @@ def test_workload_fused_plan_matches_oracle(ctx, name, schedule):
             check_det(inp, s, out, SAMPLES.get(name))
         else:
             check_vpp(inp, s, out, SAMPLES.get(name))
+
+
+# detection around the MMSE guess as the benchmark times it: (chains, sweeps, stages)
+DELTA = {"det-16x16-64qam": (16, 12, 1)}
+
+
+@pytest.mark.parametrize("name", sorted(DELTA))
+def test_workload_delta_matches_oracle(ctx, name):
+    """The multi-launch entry point and the fused plan give identical answers
+    on the whole slot; the oracle recomputes a sample; every metric is the
+    FP64 residual of its symbols and never above the MMSE guess's."""
+    chains, sweeps, stages = DELTA[name]
+    inp = slot_inputs(WORKLOADS[name][0])
+    d, qam = inp["raw"], inp["qam"]
+    beta2 = W.linear_beta2(sweeps, *W.det_beta_range(qam, d.H.shape[1], d.noise_var))
+    note(f"{name} delta {chains}x{sweeps} x {stages} stage(s)")
+    H, y = dev(inp["H"]), dev(inp["y"])
+    sym, met = ctx.detect_delta(H, y, qam, d.noise_var, chains, sweeps, beta2, inp["seed"],
+                                stages=stages)
+    torch.cuda.synchronize()
+    plain = dict(sym=sym.cpu().numpy(), metric=met.cpu().numpy())
+    job = ctx.det_job(H, y, qam, d.noise_var, chains, sweeps, beta2, inp["seed"], stages=stages)
+    plan = ctx.plan_create([job], graph=True)
+    plan.plan_launch()
+    torch.cuda.synchronize()
+    fused = {k: t.cpu().numpy() for k, t in job["outputs"].items()}
+    plan.plan_destroy()
+    for k in plain:
+        assert plain[k].tobytes() == fused[k].tobytes(), f"fused plan differs in {k}"
+    n = d.y.shape[0] * d.y.shape[1]
+    ids = sample_ids(n, SAMPLES.get(name), 9)
+    ref = O.detect_delta(d.H, d.y, d.noise_var, qam, chains, sweeps, beta2, inp["seed"],
+                         stages=stages, inst_ids=ids)
+    m = plain["metric"].astype(np.float64)
+    assert_rows_equal(plain["sym"][ids], ref["sym"], m[ids], ref["metric"])
+    li, lq = W.symbol_levels(plain["sym"], qam)
+    m64 = O.det_metric(d.H, d.y, np.concatenate([li, lq], axis=1), qam)
+    assert np.allclose(m, m64, rtol=1e-4, atol=1e-6)
+    xmm = O.slice_levels(O.mmse(d.H, d.y, d.noise_var), qam).reshape(n, -1)
+    assert np.all(m64 <= O.det_metric(d.H, d.y, xmm, qam) * (1 + 1e-5) + 1e-6)
