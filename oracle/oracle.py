@@ -10,6 +10,10 @@ Paper passages followed (arXiv 2510.01579):
 
 * §2.1 Eq. 1 and Eq. ``ml``: y = Hx + noise, x_ML = argmin ||y - Hx||^2.
 * §2.1 MMSE: x_MMSE = (H^H H + rho I)^-1 H^H y, rho = E|noise|^2 / E|x|^2.
+* §1/§4 MMSE-SIC baseline and §3.2 MMGaP-E (two guesses, MMSE and MMSE-SIC,
+  several stages each, best answer overall): ``mmse_sic``, ``detect_e``; the
+  SIC ordering rule is not given in the paper (reading: smallest MMSE error
+  variance first).
 * §2.2 ZF precoder W = H^H (H H^H)^-1 and the VPP problem
   v* = argmin ||W (u + tau v)||; §3.3 rewrites it with y~ = W u and
   H_p = -tau W / 2 as argmin_{v in 2Z} ||y~ - H_p v||, solved like detection
@@ -478,6 +482,97 @@ def detect_delta(H, y, noise_var, qam, chains, sweeps, beta2, seed, stages=1, in
     return dict(sym=levels_to_symbols(xg, qam), metric=metric, levels=xg, inst_ids=ids,
                 stage_levels=history)
 
+
+
+def mmse_sic(H, y, noise_var, qam, inst_ids=None):
+    """MMSE successive interference cancellation (the paper's MMSE-SIC
+    baseline, §1 and §4; MMGaP-E's second guess, §3.2).  The paper does not
+    give the ordering rule; the reading here is the ordered MMSE-SIC: at each
+    step the remaining user with the smallest MMSE error variance (the
+    smallest diagonal entry of (H_R^H H_R + sigma^2 I)^-1, i.e. the largest
+    post-detection SINR; ties to the lower user index) is estimated by its
+    row of (H_R^H H_R + sigma^2 I)^-1 H_R^H applied to the residual, sliced to
+    the nearest constellation point per real dimension, and its contribution
+    h_i s_i is subtracted from the residual.  The ordering depends on H and
+    sigma^2 only.  float64 throughout.
+
+    Returns dict(levels int8 [n][2 n_t] (real-form order), order int
+    [n_sc][n_t] (user detected at each step), sym, metric)."""
+    n_sc, n_sym, n_r = y.shape
+    n_t = H.shape[-1]
+    q = qam_bits(qam)
+    top = (1 << q) - 1
+    c = qam_scale(qam)
+    ids = np.arange(n_sc * n_sym) if inst_ids is None else np.asarray(inst_ids, dtype=np.int64)
+    H = H.astype(np.complex128)
+    y = y.astype(np.complex128)
+    levels = np.zeros((ids.size, 2 * n_t), dtype=np.int8)
+    order = np.zeros((n_sc, n_t), dtype=np.int64)
+    for sc in np.unique(ids // n_sym):
+        rows = np.where(ids // n_sym == sc)[0]
+        Hs = H[sc]
+        r = y[sc, ids[rows] % n_sym].copy()                  # residuals [m][n_r]
+        remaining = list(range(n_t))
+        for step in range(n_t):
+            HR = Hs[:, remaining]
+            P = np.linalg.inv(HR.conj().T @ HR + noise_var * np.eye(len(remaining)))
+            d = np.real(np.diag(P))
+            pos = int(np.argmin(d))                            # first index of the minimum
+            i = remaining[pos]
+            order[sc, step] = i
+            w = P[pos] @ HR.conj().T                           # nulling row [n_r]
+            xh = r @ w                                         # estimates [m]
+            li = np.clip(2.0 * np.floor(xh.real / c / 2.0) + 1.0, -top, top)
+            lq = np.clip(2.0 * np.floor(xh.imag / c / 2.0) + 1.0, -top, top)
+            levels[rows, i] = li.astype(np.int8)
+            levels[rows, n_t + i] = lq.astype(np.int8)
+            r = r - np.outer(c * (li + 1j * lq), Hs[:, i])
+            remaining.pop(pos)
+    sc = ids // n_sym
+    sy = ids % n_sym
+    metric = det_metric(H[sc].astype(np.complex64), y[sc, sy][:, None, :], levels, qam)
+    return dict(levels=levels, order=order, sym=levels_to_symbols(levels, qam), metric=metric)
+
+
+# Philox key offset of the chain of stages that starts from the MMSE-SIC guess
+# (the chain from the MMSE guess takes seed + s): keys never coincide for the
+# at most 64 stages of a chain.
+SIC_KEY_OFFSET = 64
+
+
+def detect_e(H, y, noise_var, qam, chains, sweeps, beta2, seed, stages=1, inst_ids=None,
+             init_mode=0, nthreads=0, cim=None):
+    """MMGaP-E (paper §3.2, Fig. 6): per problem two chains of `stages`
+    stages of moves around a guess, one from the MMSE estimate (Philox keys
+    seed + s) and one from the MMSE-SIC estimate (keys seed + 64 + s); the
+    output is the better of the two final answers by float32 level energy
+    (the MMSE-SIC chain's only if strictly lower).  Returns dict(sym, metric,
+    levels, from_sic bool [n], and the two chains' results a, b)."""
+    n_sc, n_sym, _ = y.shape
+    n_t = H.shape[-1]
+    K = 2 * n_t
+    ids = np.arange(n_sc * n_sym, dtype=np.uint32) if inst_ids is None \
+        else np.asarray(inst_ids, dtype=np.uint32)
+    a = detect_delta(H, y, noise_var, qam, chains, sweeps, beta2, seed, stages=stages,
+                     inst_ids=ids, init_mode=init_mode, nthreads=nthreads, cim=cim)
+    g = mmse_sic(H, y, noise_var, qam, inst_ids=ids)["levels"]
+    b = detect_delta(H, y, noise_var, qam, chains, sweeps, beta2,
+                     (int(seed) + SIC_KEY_OFFSET) & 0xFFFFFFFFFFFFFFFF, stages=stages,
+                     inst_ids=ids, init_mode=init_mode, nthreads=nthreads, cim=cim, guess=g)
+    G, f_all = det_ising(H, y, qam)
+    f = f_all[ids]
+    lv = a["levels"].copy()
+    from_sic = np.zeros(ids.size, dtype=bool)
+    for r in range(ids.size):
+        Gi = G[ids[r] // n_sym]
+        if level_energy32(Gi, f[r], b["levels"][r]) < level_energy32(Gi, f[r], a["levels"][r]):
+            lv[r] = b["levels"][r]
+            from_sic[r] = True
+    sc = ids // n_sym
+    sy = ids % n_sym
+    metric = det_metric(H[sc], y[sc, sy][:, None, :], lv.reshape(-1, K), qam)
+    return dict(sym=levels_to_symbols(lv, qam), metric=metric, levels=lv, from_sic=from_sic,
+                inst_ids=ids, a=a, b=b)
 
 def zf_precoder(H: np.ndarray) -> np.ndarray:
     """W = H^H (H H^H)^-1 in float64.  H [.., n_u, n_t] -> W [.., n_t, n_u]."""
