@@ -227,6 +227,43 @@ int mmgap_detect_delta(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H,
                        unsigned char *sym_out, float *metric_out, void *stream);
 
 /*
+ * mmgap_detect_sic -- ordered MMSE successive interference cancellation, the
+ * MMSE-SIC baseline of the paper's evaluation (§1, §4) and the second initial
+ * guess of MMGaP-E (§3.2).  The paper does not state the ordering rule; here,
+ * with P = (H_R^H H_R + sigma^2 I)^-1 over the users R not yet detected, each
+ * step detects the user i of R with the smallest Re P_ii (the smallest MMSE
+ * error variance; the lowest index among equals), estimates it by the row
+ * P_i,R H_R^H applied to the residual, slices the estimate per real dimension
+ * to the nearest odd PAM level (clamped), and subtracts h_i c (lI + j lQ)
+ * from the residual.  The ordering depends on H and sigma^2 only.  float64
+ * throughout; n_tx <= 16, n_rx <= 64 (else MMGAP_EUNSUPPORTED).
+ * H [n_sc][n_rx][n_tx], y [n_sc][n_sym][n_rx] complex64 (device).
+ *   sym_out     as in mmgap_detect (nullable)
+ *   metric_out  as in mmgap_detect (nullable; needs sym_out)
+ *   levels_out  [n_sc*n_sym][2 n_tx] int8 odd levels, real parts then
+ *               imaginary (out, nullable)
+ *   order_out   [n_sc][n_tx] int32: the user detected at each step (out, nullable)
+ */
+int mmgap_detect_sic(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, const void *y,
+                     unsigned char *sym_out, float *metric_out, signed char *levels_out,
+                     int *order_out, void *stream);
+
+/*
+ * mmgap_detect_e -- MMGaP-E (paper §3.2, Fig. 6): per problem two chains of
+ * `stages` stages of moves around a guess as in mmgap_detect_delta, one from
+ * the sliced MMSE estimate (Philox keys sched->seed + s) and one from the
+ * MMSE-SIC estimate of mmgap_detect_sic (keys sched->seed + 64 + s); the
+ * output is the better final answer by the float32 energy x^T G x - 2 f^T x,
+ * the MMSE-SIC chain's only if strictly lower.  Same limits as both.
+ *   sym_out, metric_out   as in mmgap_detect
+ *   from_sic_out  [n_sc*n_sym] uint8, 1 where the MMSE-SIC chain's answer was
+ *                 taken (out, nullable)
+ */
+int mmgap_detect_e(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, const void *y,
+                   const mmgap_schedule *sched, int stages, unsigned char *sym_out,
+                   float *metric_out, unsigned char *from_sic_out, void *stream);
+
+/*
  * mmgap_vpp_precode -- downlink vector-perturbation precoding (paper §2.2 Eq.
  * VPP, §3.3): the same solver on (H_p = -tau W/2, y~ = W u) with the all-zeros
  * fallback.  H [n_sc][n_rx][n_tx], u [n_sc][n_sym][n_rx] complex64;

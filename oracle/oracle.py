@@ -497,7 +497,10 @@ def mmse_sic(H, y, noise_var, qam, inst_ids=None):
     sigma^2 only.  float64 throughout.
 
     Returns dict(levels int8 [n][2 n_t] (real-form order), order int
-    [n_sc][n_t] (user detected at each step), sym, metric)."""
+    [n_sc][n_t] (user detected at each step), sym, metric, margin [n]: the
+    smallest distance of any scaled estimate x/c to a slicing boundary that
+    changes the level, so that implementations summing in another order can
+    only differ where it is tiny)."""
     n_sc, n_sym, n_r = y.shape
     n_t = H.shape[-1]
     q = qam_bits(qam)
@@ -508,6 +511,11 @@ def mmse_sic(H, y, noise_var, qam, inst_ids=None):
     y = y.astype(np.complex128)
     levels = np.zeros((ids.size, 2 * n_t), dtype=np.int8)
     order = np.zeros((n_sc, n_t), dtype=np.int64)
+    margin = np.full(ids.size, np.inf)
+
+    def boundary_gap(t):
+        b = np.clip(2.0 * np.round(t / 2.0), -(top - 1), top - 1)
+        return np.abs(t - b)
     for sc in np.unique(ids // n_sym):
         rows = np.where(ids // n_sym == sc)[0]
         Hs = H[sc]
@@ -524,6 +532,8 @@ def mmse_sic(H, y, noise_var, qam, inst_ids=None):
             xh = r @ w                                         # estimates [m]
             li = np.clip(2.0 * np.floor(xh.real / c / 2.0) + 1.0, -top, top)
             lq = np.clip(2.0 * np.floor(xh.imag / c / 2.0) + 1.0, -top, top)
+            margin[rows] = np.minimum(margin[rows], np.minimum(boundary_gap(xh.real / c),
+                                                               boundary_gap(xh.imag / c)))
             levels[rows, i] = li.astype(np.int8)
             levels[rows, n_t + i] = lq.astype(np.int8)
             r = r - np.outer(c * (li + 1j * lq), Hs[:, i])
@@ -531,7 +541,8 @@ def mmse_sic(H, y, noise_var, qam, inst_ids=None):
     sc = ids // n_sym
     sy = ids % n_sym
     metric = det_metric(H[sc].astype(np.complex64), y[sc, sy][:, None, :], levels, qam)
-    return dict(levels=levels, order=order, sym=levels_to_symbols(levels, qam), metric=metric)
+    return dict(levels=levels, order=order, sym=levels_to_symbols(levels, qam), metric=metric,
+                margin=margin)
 
 
 # Philox key offset of the chain of stages that starts from the MMSE-SIC guess
@@ -547,7 +558,8 @@ def detect_e(H, y, noise_var, qam, chains, sweeps, beta2, seed, stages=1, inst_i
     seed + s) and one from the MMSE-SIC estimate (keys seed + 64 + s); the
     output is the better of the two final answers by float32 level energy
     (the MMSE-SIC chain's only if strictly lower).  Returns dict(sym, metric,
-    levels, from_sic bool [n], and the two chains' results a, b)."""
+    levels, from_sic bool [n], the two chains' results a, b, and sic_margin,
+    the MMSE-SIC guess's slicing margin per instance)."""
     n_sc, n_sym, _ = y.shape
     n_t = H.shape[-1]
     K = 2 * n_t
@@ -555,7 +567,8 @@ def detect_e(H, y, noise_var, qam, chains, sweeps, beta2, seed, stages=1, inst_i
         else np.asarray(inst_ids, dtype=np.uint32)
     a = detect_delta(H, y, noise_var, qam, chains, sweeps, beta2, seed, stages=stages,
                      inst_ids=ids, init_mode=init_mode, nthreads=nthreads, cim=cim)
-    g = mmse_sic(H, y, noise_var, qam, inst_ids=ids)["levels"]
+    sic = mmse_sic(H, y, noise_var, qam, inst_ids=ids)
+    g = sic["levels"]
     b = detect_delta(H, y, noise_var, qam, chains, sweeps, beta2,
                      (int(seed) + SIC_KEY_OFFSET) & 0xFFFFFFFFFFFFFFFF, stages=stages,
                      inst_ids=ids, init_mode=init_mode, nthreads=nthreads, cim=cim, guess=g)
@@ -572,7 +585,7 @@ def detect_e(H, y, noise_var, qam, chains, sweeps, beta2, seed, stages=1, inst_i
     sy = ids % n_sym
     metric = det_metric(H[sc], y[sc, sy][:, None, :], lv.reshape(-1, K), qam)
     return dict(sym=levels_to_symbols(lv, qam), metric=metric, levels=lv, from_sic=from_sic,
-                inst_ids=ids, a=a, b=b)
+                inst_ids=ids, a=a, b=b, sic_margin=sic["margin"])
 
 def zf_precoder(H: np.ndarray) -> np.ndarray:
     """W = H^H (H H^H)^-1 in float64.  H [.., n_u, n_t] -> W [.., n_t, n_u]."""

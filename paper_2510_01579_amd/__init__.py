@@ -8,7 +8,8 @@ computation runs in the library's HIP kernels.  There is no CPU fallback: if
 the library is missing or no GPU is present the calls raise.
 
 Entry points (same names as the C ABI, without the ``mmgap_`` prefix):
-``build_ising``, ``solve``, ``detect``, ``vpp_precode``; ``Context`` owns a
+``build_ising``, ``solve``, ``detect``, ``detect_delta``, ``detect_sic``,
+``detect_e``, ``vpp_precode``; ``Context`` owns a
 library context (device, scratch, HBM budget); ``Context.plan_create`` returns a
 ``Plan`` (``plan_launch``, ``plan_info``, ``plan_destroy``) that runs a batch of
 mixed jobs in one persistent launch; ``Context.server_start`` runs the native
@@ -34,7 +35,8 @@ STATUS = {0: "MMGAP_OK", -1: "MMGAP_EINVAL", -2: "MMGAP_ENOMEM", -3: "MMGAP_EDEV
           -4: "MMGAP_EUNSUPPORTED", -5: "MMGAP_EBUSY"}
 
 EXPORTS = ("mmgap_create", "mmgap_destroy", "mmgap_last_error", "mmgap_build_ising",
-           "mmgap_solve", "mmgap_detect", "mmgap_detect_delta", "mmgap_vpp_precode",
+           "mmgap_solve", "mmgap_detect", "mmgap_detect_delta", "mmgap_detect_sic",
+           "mmgap_detect_e", "mmgap_vpp_precode",
            "mmgap_set_profiling",
            "mmgap_last_profile", "mmgap_plan_create", "mmgap_plan_launch", "mmgap_plan_info",
            "mmgap_plan_destroy", "mmgap_server_start", "mmgap_server_submit",
@@ -108,6 +110,8 @@ def lib() -> ctypes.CDLL:
             L.mmgap_solve.argtypes = [vp, i, i, i, vp, vp, i, vp, vp, S, vp, vp, vp, vp]
             L.mmgap_detect.argtypes = [vp, P, vp, vp, S, vp, vp, vp]
             L.mmgap_detect_delta.argtypes = [vp, P, vp, vp, S, i, vp, vp, vp, vp]
+            L.mmgap_detect_sic.argtypes = [vp, P, vp, vp, vp, vp, vp, vp, vp]
+            L.mmgap_detect_e.argtypes = [vp, P, vp, vp, S, i, vp, vp, vp, vp]
             L.mmgap_vpp_precode.argtypes = [vp, P, vp, vp, S, vp, vp, vp, vp]
             L.mmgap_set_profiling.argtypes = [vp, i]
             L.mmgap_last_profile.argtypes = [vp, ctypes.POINTER(f32), i]
@@ -417,6 +421,44 @@ class Context:
                                              _ptr(sym), _ptr(met), st))
         del keep
         return sym, met
+
+    def detect_sic(self, H, y, qam, noise_var, metric=True, levels=False, order=False,
+                   stream=None):
+        """Ordered MMSE-SIC (mmgap_detect_sic).  Returns (sym uint8 [n][n_tx],
+        metric float32 [n] or None, levels int8 [n][2 n_tx] or None, order int32
+        [n_sc][n_tx] or None)."""
+        torch = _torch()
+        p = self._problem(KIND_DET, H, y, qam, noise_var, 0.0)
+        n = p.n_sc * p.n_sym
+        dev = self._dev()
+        sym = torch.empty((n, p.n_tx), dtype=torch.uint8, device=dev)
+        met = torch.empty((n,), dtype=torch.float32, device=dev) if metric else None
+        lv = torch.empty((n, 2 * p.n_tx), dtype=torch.int8, device=dev) if levels else None
+        od = torch.empty((p.n_sc, p.n_tx), dtype=torch.int32, device=dev) if order else None
+        st = stream if stream is not None else _stream(dev)
+        self._check(lib().mmgap_detect_sic(self._h, ctypes.byref(p), _ptr(H), _ptr(y), _ptr(sym),
+                                           _ptr(met), _ptr(lv), _ptr(od), st))
+        return sym, met, lv, od
+
+    def detect_e(self, H, y, qam, noise_var, chains, sweeps, beta2, seed, stages=1, init=0,
+                 metric=True, stream=None, cim=None):
+        """MMGaP-E (mmgap_detect_e): stages of moves from the MMSE and from the
+        MMSE-SIC guess, the better answer.  Returns (sym uint8 [n][n_tx], metric
+        float32 [n] or None, from_sic uint8 [n])."""
+        torch = _torch()
+        p = self._problem(KIND_DET, H, y, qam, noise_var, 0.0)
+        n = p.n_sc * p.n_sym
+        dev = self._dev()
+        sym = torch.empty((n, p.n_tx), dtype=torch.uint8, device=dev)
+        met = torch.empty((n,), dtype=torch.float32, device=dev) if metric else None
+        fs = torch.empty((n,), dtype=torch.uint8, device=dev)
+        s, keep = self._schedule(chains, sweeps, beta2, seed, init, cim)
+        st = stream if stream is not None else _stream(dev)
+        self._check(lib().mmgap_detect_e(self._h, ctypes.byref(p), _ptr(H), _ptr(y),
+                                         ctypes.byref(s), int(stages), _ptr(sym), _ptr(met),
+                                         _ptr(fs), st))
+        del keep
+        return sym, met, fs
 
     def vpp_precode(self, H, u, qam, chains, sweeps, beta2, seed, tau=0.0, want_x=True,
                     want_gamma=True, init=0, stream=None, cim=None):

@@ -778,6 +778,99 @@ int mmgap_detect(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, const
     return end_call(ctx, st);
 }
 
+namespace {
+
+// Stages of moves around the guess xg (device, [ni][KT], updated in place):
+// per stage the move fields f - G x_g, an anneal of the {-2, 0, 2}-move
+// problem with the zero move zmov as the fallback and Philox key
+// seed_base + s, and the selection that applies the winning move; the last
+// stage decodes into sym_out / metric_out when `decode`.
+int run_delta_stages(mmgap_ctx *ctx, hipStream_t st, const mmgap_problem *prob,
+                     const ProblemShape &sh, const void *H, const void *y,
+                     const mmgap_schedule *sched, int stages, uint64_t seed_base, float *G,
+                     float *f, float *fp, signed char *xg, signed char *zmov, float *chainE,
+                     uint32_t *chainS, bool decode, unsigned char *sym_out, float *metric_out)
+{
+    const int q = 2, KT = sh.KT, ni = sh.n_inst;
+    const int w[mmgap::kMaxQ] = {1, 1, 0, 0};
+    for (int s = 0; s < stages; ++s) {
+        mmgap::DeltaPrepArgs d{};
+        d.G = G;
+        d.inst_per_G = prob->n_sym;
+        d.f = f;
+        d.guess = xg;
+        d.f_out = fp;
+        d.n_inst = ni;
+        d.KT = KT;
+        hipError_t e = mmgap::launch_delta_prep(d, st);
+        if (e != hipSuccess) return hip_fail(ctx, e, "move-field launch");
+        mmgap_schedule ss = *sched;
+        ss.seed = seed_base + (uint64_t)s;        // one Philox key per stage
+        mmgap::SelectArgs sel{};
+        sel.mode = mmgap::kSelectDelta;
+        sel.H = (const float2 *)H;
+        sel.y = (const float2 *)y;
+        sel.n_rows = prob->n_rx;
+        sel.n_cols = prob->n_tx;
+        sel.n_sym = prob->n_sym;
+        sel.c = qam_c(prob->qam);
+        sel.sym_out = sym_out;
+        sel.metric_out = metric_out;
+        sel.guess = xg;
+        sel.f_full = f;
+        sel.qtop = (1 << sh.q) - 1;
+        sel.dq = sh.q;
+        sel.decode = decode && s == stages - 1;
+        int rc = run_solver(ctx, st, ni, sh.K, q, KT, w, G, prob->n_sym, fp, zmov, &ss, chainE,
+                            chainS, sel);
+        if (rc) return rc;
+    }
+    return MMGAP_OK;
+}
+
+// The detection build into G, f and the sliced MMSE estimate xg.
+int det_build_into(mmgap_ctx *ctx, hipStream_t st, const mmgap_problem *prob,
+                   const ProblemShape &sh, const void *H, const void *y, float *G, float *f,
+                   signed char *xg)
+{
+    mmgap::DetBuildArgs b{};
+    b.H = (const float2 *)H;
+    b.y = (const float2 *)y;
+    b.n_sc = prob->n_sc;
+    b.n_r = prob->n_rx;
+    b.n_t = prob->n_tx;
+    b.n_sym = prob->n_sym;
+    b.ld = sh.KT;
+    b.qtop = (1 << sh.q) - 1;
+    b.c = qam_c(prob->qam);
+    b.c2 = qam_c2(prob->qam);
+    b.noise_var = (double)prob->noise_var;
+    b.G = G;
+    b.f = f;
+    b.x_fb = xg;
+    b.ynorm = nullptr;
+    hipError_t e = mmgap::launch_det_build(b, st);
+    return e == hipSuccess ? MMGAP_OK : hip_fail(ctx, e, "build launch");
+}
+
+mmgap::SicArgs sic_args(const mmgap_problem *prob, const ProblemShape &sh, const void *H,
+                        const void *y)
+{
+    mmgap::SicArgs a{};
+    a.H = (const float2 *)H;
+    a.y = (const float2 *)y;
+    a.n_sc = prob->n_sc;
+    a.n_r = prob->n_rx;
+    a.n_t = prob->n_tx;
+    a.n_sym = prob->n_sym;
+    a.q = sh.q;
+    a.c = qam_c(prob->qam);
+    a.noise_var = (double)prob->noise_var;
+    return a;
+}
+
+}  // namespace
+
 int mmgap_detect_delta(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, const void *y,
                        const mmgap_schedule *sched, int stages, const signed char *guess,
                        unsigned char *sym_out, float *metric_out, void *stream)
@@ -794,7 +887,7 @@ int mmgap_detect_delta(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H,
     DeviceGuard g(ctx->device);
     hipStream_t st = (hipStream_t)stream;
     // the move problem: two unit-weight spins per real dimension
-    const int q = 2, KT = sh.KT, NW = mmgap::spin_words(KT, q), ni = sh.n_inst;
+    const int KT = sh.KT, NW = mmgap::spin_words(KT, 2), ni = sh.n_inst;
     Bump plan;
     const size_t oG = plan.take(sizeof(float) * (size_t)prob->n_sc * KT * KT);
     const size_t of = plan.take(sizeof(float) * (size_t)ni * KT);
@@ -806,64 +899,123 @@ int mmgap_detect_delta(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H,
     if ((rc = ensure_scratch(ctx, plan.off))) return rc;
     if ((rc = begin_call(ctx, st))) return rc;
     prof_mark(ctx, 0, st);
-    mmgap::DetBuildArgs b{};
-    b.H = (const float2 *)H;
-    b.y = (const float2 *)y;
-    b.n_sc = prob->n_sc;
-    b.n_r = prob->n_rx;
-    b.n_t = prob->n_tx;
-    b.n_sym = prob->n_sym;
-    b.ld = KT;
-    b.qtop = (1 << sh.q) - 1;
-    b.c = qam_c(prob->qam);
-    b.c2 = qam_c2(prob->qam);
-    b.noise_var = (double)prob->noise_var;
-    b.G = at<float>(ctx, oG);
-    b.f = at<float>(ctx, of);
-    b.x_fb = at<signed char>(ctx, oxg);     // the sliced MMSE estimate is the first guess
-    b.ynorm = nullptr;
-    hipError_t e = mmgap::launch_det_build(b, st);
-    if (e != hipSuccess) return hip_fail(ctx, e, "build launch");
+    // the sliced MMSE estimate is the first guess
+    rc = det_build_into(ctx, st, prob, sh, H, y, at<float>(ctx, oG), at<float>(ctx, of),
+                        at<signed char>(ctx, oxg));
+    if (rc) return rc;
+    hipError_t e;
     if (guess) {
         e = mmgap::launch_pad_rows_i8(guess, at<signed char>(ctx, oxg), ni, sh.K, KT, st);
         if (e != hipSuccess) return hip_fail(ctx, e, "guess copy");
     }
     e = hipMemsetAsync(at<signed char>(ctx, oz), 0, (size_t)ni * KT, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "hipMemsetAsync(zero moves)");
-    const int w[mmgap::kMaxQ] = {1, 1, 0, 0};
-    for (int s = 0; s < stages; ++s) {
-        mmgap::DeltaPrepArgs d{};
-        d.G = b.G;
-        d.inst_per_G = prob->n_sym;
-        d.f = b.f;
-        d.guess = at<signed char>(ctx, oxg);
-        d.f_out = at<float>(ctx, ofp);
-        d.n_inst = ni;
-        d.KT = KT;
-        e = mmgap::launch_delta_prep(d, st);
-        if (e != hipSuccess) return hip_fail(ctx, e, "move-field launch");
-        mmgap_schedule ss = *sched;
-        ss.seed = sched->seed + (uint64_t)s;      // one Philox key per stage
-        mmgap::SelectArgs sel{};
-        sel.mode = mmgap::kSelectDelta;
-        sel.H = (const float2 *)H;
-        sel.y = (const float2 *)y;
-        sel.n_rows = prob->n_rx;
-        sel.n_cols = prob->n_tx;
-        sel.n_sym = prob->n_sym;
-        sel.c = b.c;
-        sel.sym_out = sym_out;
-        sel.metric_out = metric_out;
-        sel.guess = at<signed char>(ctx, oxg);
-        sel.f_full = b.f;
-        sel.qtop = b.qtop;
-        sel.dq = sh.q;
-        sel.decode = s == stages - 1;
-        rc = run_solver(ctx, st, ni, sh.K, q, KT, w, b.G, prob->n_sym, at<float>(ctx, ofp),
-                        at<signed char>(ctx, oz), &ss, at<float>(ctx, oE), at<uint32_t>(ctx, oS),
-                        sel);
-        if (rc) return rc;
-    }
+    rc = run_delta_stages(ctx, st, prob, sh, H, y, sched, stages, sched->seed, at<float>(ctx, oG),
+                          at<float>(ctx, of), at<float>(ctx, ofp), at<signed char>(ctx, oxg),
+                          at<signed char>(ctx, oz), at<float>(ctx, oE), at<uint32_t>(ctx, oS),
+                          true, sym_out, metric_out);
+    if (rc) return rc;
+    return end_call(ctx, st);
+}
+
+int mmgap_detect_sic(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, const void *y,
+                     unsigned char *sym_out, float *metric_out, signed char *levels_out,
+                     int *order_out, void *stream)
+{
+    if (!ctx) return MMGAP_EINVAL;
+    ProblemShape sh;
+    int rc = check_problem(ctx, prob, MMGAP_KIND_DET, &sh);
+    if (rc) return rc;
+    if (prob->n_tx > 16)
+        return fail(ctx, MMGAP_EUNSUPPORTED, "MMSE-SIC supports n_tx <= 16 (got %d)", prob->n_tx);
+    if (sh.n_inst == 0) return MMGAP_OK;
+    if (!H || !y) return fail(ctx, MMGAP_EINVAL, "H and y are required");
+    if (metric_out && !sym_out) return fail(ctx, MMGAP_EINVAL, "metric_out needs sym_out");
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = begin_call(ctx, st))) return rc;
+    mmgap::SicArgs a = sic_args(prob, sh, H, y);
+    a.levels = levels_out;
+    a.ldl = 2 * prob->n_tx;
+    a.sym_out = sym_out;
+    a.metric_out = metric_out;
+    a.order_out = order_out;
+    hipError_t e = mmgap::launch_sic(a, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "MMSE-SIC launch");
+    return end_call(ctx, st);
+}
+
+int mmgap_detect_e(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, const void *y,
+                   const mmgap_schedule *sched, int stages, unsigned char *sym_out,
+                   float *metric_out, unsigned char *from_sic_out, void *stream)
+{
+    if (!ctx) return MMGAP_EINVAL;
+    ProblemShape sh;
+    int rc = check_problem(ctx, prob, MMGAP_KIND_DET, &sh);
+    if (rc) return rc;
+    if ((rc = check_schedule(ctx, sched))) return rc;
+    if (stages < 1 || stages > mmgap::kMaxStages)
+        return fail(ctx, MMGAP_EUNSUPPORTED, "stages=%d outside 1..%d", stages, mmgap::kMaxStages);
+    if (prob->n_tx > 16)
+        return fail(ctx, MMGAP_EUNSUPPORTED, "MMSE-SIC supports n_tx <= 16 (got %d)", prob->n_tx);
+    if (sh.n_inst == 0) return MMGAP_OK;
+    if (!H || !y || !sym_out) return fail(ctx, MMGAP_EINVAL, "H, y and sym_out are required");
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int KT = sh.KT, NW = mmgap::spin_words(KT, 2), ni = sh.n_inst;
+    Bump plan;
+    const size_t oG = plan.take(sizeof(float) * (size_t)prob->n_sc * KT * KT);
+    const size_t of = plan.take(sizeof(float) * (size_t)ni * KT);
+    const size_t ofp = plan.take(sizeof(float) * (size_t)ni * KT);
+    const size_t oxa = plan.take((size_t)ni * KT);
+    const size_t oxb = plan.take((size_t)ni * KT);
+    const size_t oz = plan.take((size_t)ni * KT);
+    const size_t oE = plan.take(sizeof(float) * (size_t)ni * sched->chains);
+    const size_t oS = plan.take(sizeof(uint32_t) * (size_t)ni * sched->chains * NW);
+    if ((rc = ensure_scratch(ctx, plan.off))) return rc;
+    if ((rc = begin_call(ctx, st))) return rc;
+    prof_mark(ctx, 0, st);
+    float *G = at<float>(ctx, oG), *f = at<float>(ctx, of), *fp = at<float>(ctx, ofp);
+    signed char *xa = at<signed char>(ctx, oxa), *xb = at<signed char>(ctx, oxb);
+    signed char *zm = at<signed char>(ctx, oz);
+    if ((rc = det_build_into(ctx, st, prob, sh, H, y, G, f, xa))) return rc;
+    mmgap::SicArgs sa = sic_args(prob, sh, H, y);
+    sa.levels = xb;
+    sa.ldl = KT;
+    hipError_t e = mmgap::launch_sic(sa, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "MMSE-SIC launch");
+    e = hipMemsetAsync(zm, 0, (size_t)ni * KT, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMemsetAsync(zero moves)");
+    // the chain from the MMSE guess (keys seed + s), then the one from the
+    // MMSE-SIC guess (keys seed + 64 + s)
+    rc = run_delta_stages(ctx, st, prob, sh, H, y, sched, stages, sched->seed, G, f, fp, xa, zm,
+                          at<float>(ctx, oE), at<uint32_t>(ctx, oS), false, nullptr, nullptr);
+    if (rc) return rc;
+    rc = run_delta_stages(ctx, st, prob, sh, H, y, sched, stages,
+                          sched->seed + (uint64_t)mmgap::kMaxStages, G, f, fp, xb, zm,
+                          at<float>(ctx, oE), at<uint32_t>(ctx, oS), false, nullptr, nullptr);
+    if (rc) return rc;
+    mmgap::PickArgs pk{};
+    pk.G = G;
+    pk.inst_per_G = prob->n_sym;
+    pk.f = f;
+    pk.xa = xa;
+    pk.xb = xb;
+    pk.n_inst = ni;
+    pk.K = sh.K;
+    pk.KT = KT;
+    pk.q = sh.q;
+    pk.H = (const float2 *)H;
+    pk.y = (const float2 *)y;
+    pk.n_rows = prob->n_rx;
+    pk.n_cols = prob->n_tx;
+    pk.n_sym = prob->n_sym;
+    pk.c = qam_c(prob->qam);
+    pk.sym_out = sym_out;
+    pk.metric_out = metric_out;
+    pk.from_b = from_sic_out;
+    e = mmgap::launch_pick(pk, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "pick launch");
     return end_call(ctx, st);
 }
 

@@ -122,6 +122,38 @@ struct DeltaPrepArgs {
     int n_inst, KT;
 };
 
+// Ordered MMSE-SIC detection (one wavefront per subcarrier).
+struct SicArgs {
+    const float2 *H;        // [n_sc][n_r][n_t]
+    const float2 *y;        // [n_sc][n_sym][n_r]
+    int n_sc, n_r, n_t, n_sym;
+    int q;                  // bits per real dimension
+    double c;               // constellation scale
+    double noise_var;
+    signed char *levels;    // [n_sc*n_sym][ldl] or null; zero beyond 2 n_t
+    int ldl;
+    unsigned char *sym_out; // [n_sc*n_sym][n_t] or null
+    float *metric_out;      // [n_sc*n_sym] or null (needs sym_out)
+    int *order_out;         // [n_sc][n_t] or null
+};
+
+// The better of two level vectors per instance by float32 energy, then decode.
+struct PickArgs {
+    const float *G;         // [n_G][KT][KT]
+    int inst_per_G;
+    const float *f;         // [n_inst][KT] fields of the detection problem
+    const signed char *xa;  // [n_inst][KT] first candidate
+    const signed char *xb;  // [n_inst][KT] second candidate (wins only if strictly lower)
+    int n_inst, K, KT, q;
+    const float2 *H;
+    const float2 *y;
+    int n_rows, n_cols, n_sym;
+    double c;
+    unsigned char *sym_out; // [n_inst][n_t]
+    float *metric_out;      // [n_inst] or null
+    unsigned char *from_b;  // [n_inst] or null: 1 where the second candidate won
+};
+
 struct ExpandArgs {
     const float *G;         // [n_sc][K][K] (unpadded)
     const float *f;         // [n_inst][K]
@@ -184,6 +216,8 @@ hipError_t launch_anneal(int KT, int q, const AnnealArgs &a, hipStream_t s);
 hipError_t launch_cim(int KT, int q, const AnnealArgs &a, hipStream_t s);
 hipError_t launch_select(const SelectArgs &a, hipStream_t s);
 hipError_t launch_delta_prep(const DeltaPrepArgs &a, hipStream_t s);
+hipError_t launch_sic(const SicArgs &a, hipStream_t s);
+hipError_t launch_pick(const PickArgs &a, hipStream_t s);
 hipError_t launch_expand(const ExpandArgs &a, hipStream_t s);
 // copy [n][K][K] -> [n][KT][KT] (and [m][K] -> [m][KT]) with zero padding
 hipError_t launch_pad_matrix(const float *src, float *dst, int n, int K, int KT, hipStream_t s);

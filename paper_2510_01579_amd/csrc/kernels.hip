@@ -1706,6 +1706,203 @@ __global__ void __launch_bounds__(kBlock) k_delta_prep(DeltaPrepArgs a)
     a.f_out[t] = a.f[t] - g;
 }
 
+// ---------------------------------------------------------------------------
+// Ordered MMSE-SIC of one subcarrier per workgroup of one wavefront.  With
+// P = (H_R^H H_R + sigma^2 I)^-1 over the remaining users R, each step takes
+// the remaining user i with the smallest Re P_ii (the lowest index among
+// equals), its nulling row w = P_i,R H_R^H, and removes i from P by the Schur
+// complement P_jl -= P_ji P_il / P_ii.  The ordering and the nulling rows
+// depend on H only; then every symbol of the subcarrier (one lane each)
+// estimates w . r on its residual r, slices the estimate to the nearest odd
+// PAM level per real dimension and subtracts h_i s_i from r.  float64.
+constexpr int kSicSyms = 16;            // symbols per pass (one lane each)
+
+template <int NT>
+struct SicShared {
+    cf32 Hs[64 * NT];                   // [n_r][n_t]
+    double2 P[NT * NT];
+    double2 W[NT * 64];                 // nulling row of step k at W[k * 64]
+    double2 col[NT], row[NT];
+    double2 res[kSicSyms * 65];         // residuals, rows padded to 65 entries
+    int lv[kSicSyms][2 * NT];
+    int order[NT];
+};
+
+__device__ __forceinline__ int sic_slice(double x, double c, int qtop)
+{
+    // clamped first (no effect on the sliced level) so that the conversion to
+    // int stays in range
+    const double t = fmin(fmax(x / c, -(double)(qtop + 2)), (double)(qtop + 2));
+    int v = 2 * (int)floor(t * 0.5) + 1;
+    return v < -qtop ? -qtop : (v > qtop ? qtop : v);
+}
+
+template <int NT>
+__global__ void __launch_bounds__(64) k_sic(SicArgs a)
+{
+    __shared__ SicShared<NT> sh;
+    const int lane = threadIdx.x;
+    const int sc = blockIdx.x;
+    const int nr = a.n_r, nt = a.n_t, qtop = (1 << a.q) - 1;
+    const float2 *Hg = a.H + (size_t)sc * nr * nt;
+    for (int e = lane; e < nr * nt; e += 64) sh.Hs[e] = to_cf32(Hg[e]);
+    wave_sync_lds();
+    // A = H^H H + sigma^2 I
+    for (int e = lane; e < nt * nt; e += 64) {
+        const int i = e / nt, j = e % nt;
+        cd acc{0.0, 0.0};
+        for (int r = 0; r < nr; ++r) {
+            const cf32 hi = sh.Hs[r * nt + i], hj = sh.Hs[r * nt + j];
+            const cd v = cmulc(cd{hi.x, hi.y}, cd{hj.x, hj.y});   // conj(h_ri) h_rj
+            acc.re = acc.re + v.re;
+            acc.im = acc.im + v.im;
+        }
+        if (i == j) acc.re = acc.re + a.noise_var;
+        sh.P[i * NT + j] = make_double2(acc.re, acc.im);
+    }
+    wave_sync_lds();
+    // in-place Gauss-Jordan inverse (Hermitian positive definite: no pivoting)
+    for (int k = 0; k < nt; ++k) {
+        const cd pk = ld2(sh.P[k * NT + k]);
+        const double den = pk.re * pk.re + pk.im * pk.im;
+        const cd t{pk.re / den, -pk.im / den};
+        if (lane < nt) {
+            const cd v = lane == k ? t : cmul(ld2(sh.P[k * NT + lane]), t);
+            sh.row[lane] = make_double2(v.re, v.im);
+            sh.col[lane] = sh.P[lane * NT + k];
+        }
+        wave_sync_lds();
+        for (int e = lane; e < nt * nt; e += 64) {
+            const int i = e / nt, j = e % nt;
+            if (i == k) {
+                sh.P[i * NT + j] = sh.row[j];
+            } else {
+                const cd old = j == k ? cd{0.0, 0.0} : ld2(sh.P[i * NT + j]);
+                const cd m = cmul(ld2(sh.col[i]), ld2(sh.row[j]));
+                sh.P[i * NT + j] = make_double2(old.re - m.re, old.im - m.im);
+            }
+        }
+        wave_sync_lds();
+    }
+    // ordering, nulling rows and downdates
+    uint32_t rem = nt >= 32 ? 0xFFFFFFFFu : ((1u << nt) - 1u);
+    for (int step = 0; step < nt; ++step) {
+        const bool mine = lane < nt && ((rem >> lane) & 1u);
+        const double d = mine ? sh.P[lane * NT + lane].x : __builtin_inf();
+        double m = d;
+        for (int off = 32; off >= 1; off >>= 1) m = fmin(m, __shfl_xor(m, off, 64));
+        uint64_t ball = __ballot(mine && d == m);
+        if (ball == 0) ball = rem;              // no finite diagonal: the lowest remaining user
+        const int i = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)ball) - 1);
+        if (lane == 0) sh.order[step] = i;
+        for (int r = lane; r < nr; r += 64) {
+            cd acc{0.0, 0.0};
+            for (int j = 0; j < nt; ++j) {
+                if (!((rem >> j) & 1u)) continue;
+                const cf32 h = sh.Hs[r * nt + j];
+                const cd v = cmulc(cd{h.x, h.y}, ld2(sh.P[i * NT + j]));   // P_ij conj(h_rj)
+                acc.re = acc.re + v.re;
+                acc.im = acc.im + v.im;
+            }
+            sh.W[step * 64 + r] = make_double2(acc.re, acc.im);
+        }
+        if (lane < nt) {
+            sh.col[lane] = sh.P[lane * NT + i];
+            sh.row[lane] = sh.P[i * NT + lane];
+        }
+        wave_sync_lds();
+        rem &= ~(1u << i);
+        const cd piv = ld2(sh.col[i]);
+        const double den = piv.re * piv.re + piv.im * piv.im;
+        const cd ip{piv.re / den, -piv.im / den};
+        for (int e = lane; e < nt * nt; e += 64) {
+            const int j = e / nt, l = e % nt;
+            if (!((rem >> j) & 1u) || !((rem >> l) & 1u)) continue;
+            const cd m = cmul(cmul(ld2(sh.col[j]), ld2(sh.row[l])), ip);
+            const cd old = ld2(sh.P[j * NT + l]);
+            sh.P[j * NT + l] = make_double2(old.re - m.re, old.im - m.im);
+        }
+        wave_sync_lds();
+    }
+    if (a.order_out && lane < nt) a.order_out[(size_t)sc * nt + lane] = sh.order[lane];
+    // detection of the symbols, kSicSyms per pass
+    for (int s0 = 0; s0 < a.n_sym; s0 += kSicSyms) {
+        const int cnt = min(kSicSyms, a.n_sym - s0);
+        for (int e = lane; e < cnt * nr; e += 64) {
+            const int s = e / nr, r = e % nr;
+            const float2 v = a.y[((size_t)sc * a.n_sym + s0 + s) * nr + r];
+            sh.res[s * 65 + r] = make_double2((double)v.x, (double)v.y);
+        }
+        wave_sync_lds();
+        if (lane < cnt) {
+            double2 *res = sh.res + lane * 65;
+            for (int k = 0; k < nt; ++k) {
+                const int i = sh.order[k];
+                cd acc{0.0, 0.0};
+                for (int r = 0; r < nr; ++r) {
+                    const cd v = cmul(ld2(sh.W[k * 64 + r]), ld2(res[r]));
+                    acc.re = acc.re + v.re;
+                    acc.im = acc.im + v.im;
+                }
+                const int li = sic_slice(acc.re, a.c, qtop);
+                const int lq = sic_slice(acc.im, a.c, qtop);
+                sh.lv[lane][i] = li;
+                sh.lv[lane][nt + i] = lq;
+                const cd s{a.c * (double)li, a.c * (double)lq};
+                for (int r = 0; r < nr; ++r) {
+                    const cf32 h = sh.Hs[r * nt + i];
+                    const cd m = cmul(cd{h.x, h.y}, s);
+                    const cd o = ld2(res[r]);
+                    res[r] = make_double2(o.re - m.re, o.im - m.im);
+                }
+            }
+        }
+        wave_sync_lds();
+        if (a.levels) {
+            for (int e = lane; e < cnt * a.ldl; e += 64) {
+                const int s = e / a.ldl, k = e % a.ldl;
+                const size_t n = (size_t)sc * a.n_sym + s0 + s;
+                a.levels[n * a.ldl + k] = (signed char)(k < 2 * nt ? sh.lv[s][k] : 0);
+            }
+        }
+        if (a.sym_out) {
+            for (int s = 0; s < cnt; ++s)
+                decode_det(sh.lv[s], (int)((size_t)sc * a.n_sym + s0 + s), sc, s0 + s, a.n_sym, nr,
+                           nt, a.q, a.c, a.H + (size_t)sc * nr * nt, a.y, a.sym_out, a.metric_out,
+                           lane);
+        }
+        wave_sync_lds();
+    }
+}
+
+// The better of two candidates per instance (the second only if its float32
+// level energy is strictly lower), then the decode; one wavefront per instance.
+__global__ void __launch_bounds__(kBlock) k_pick(PickArgs a)
+{
+    __shared__ float terms[kWavesPerBlock][32];
+    __shared__ int la[kWavesPerBlock][32];
+    __shared__ int lb[kWavesPerBlock][32];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int n = blockIdx.x * kWavesPerBlock + wave;
+    if (n >= a.n_inst) return;
+    const int K = a.K, KT = a.KT;
+    const float *Gi = a.G + (size_t)(n / a.inst_per_G) * KT * KT;
+    const float *ff = a.f + (size_t)n * KT;
+    if (lane < K) {
+        la[wave][lane] = a.xa[(size_t)n * KT + lane];
+        lb[wave][lane] = a.xb[(size_t)n * KT + lane];
+    }
+    wave_sync_lds();
+    const float Ea = wave_level_energy(Gi, KT, K, ff, la[wave], terms[wave], lane);
+    const float Eb = wave_level_energy(Gi, KT, K, ff, lb[wave], terms[wave], lane);
+    const bool use_b = Eb < Ea;
+    if (a.from_b && lane == 0) a.from_b[n] = use_b ? 1 : 0;
+    const int sc = n / a.n_sym, sy = n % a.n_sym;
+    decode_det(use_b ? lb[wave] : la[wave], n, sc, sy, a.n_sym, a.n_rows, a.n_cols, a.q, a.c,
+               a.H + (size_t)sc * a.n_rows * a.n_cols, a.y, a.sym_out, a.metric_out, lane);
+}
+
 __global__ void k_reset_counters(unsigned int *counters, int n)
 {
     if (blockIdx.x == 0 && (int)threadIdx.x < n) counters[threadIdx.x] = 0u;
@@ -1912,6 +2109,30 @@ hipError_t launch_delta_prep(const DeltaPrepArgs &a, hipStream_t s)
     const size_t blocks = (total + kBlock - 1) / kBlock;
     if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_delta_prep, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sic(const SicArgs &a, hipStream_t s)
+{
+    if (a.n_sc <= 0) return hipSuccess;
+    if (a.n_r < 1 || a.n_r > 64 || a.n_t < 1 || a.n_t > 16 || a.n_sym < 1 ||
+        (a.levels && a.ldl < 2 * a.n_t) || (a.metric_out && !a.sym_out))
+        return hipErrorInvalidValue;
+    if (a.n_t <= 4)
+        hipLaunchKernelGGL(k_sic<4>, dim3(a.n_sc), dim3(64), 0, s, a);
+    else if (a.n_t <= 8)
+        hipLaunchKernelGGL(k_sic<8>, dim3(a.n_sc), dim3(64), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_sic<16>, dim3(a.n_sc), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_pick(const PickArgs &a, hipStream_t s)
+{
+    if (a.n_inst <= 0) return hipSuccess;
+    if (a.K > 32 || a.KT > 32 || a.K > a.KT) return hipErrorInvalidValue;
+    const int blocks = (a.n_inst + kWavesPerBlock - 1) / kWavesPerBlock;
+    hipLaunchKernelGGL(k_pick, dim3(blocks), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
