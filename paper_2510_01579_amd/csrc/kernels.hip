@@ -893,16 +893,18 @@ __device__ __forceinline__ double wave_sum_f64(double v)
 
 // Energy of the fallback levels with the chains' arithmetic (one wavefront;
 // `terms` is this wavefront's LDS scratch of 32 floats).
-__device__ float fallback_energy(const float *Gi, int KT, int K, const float *fi,
+__device__ float fallback_energy(const float *Gi, int ldg, int K, const float *fi,
                                  const signed char *xi, float *terms, int lane)
 {
     if (lane < K) {
         float acc = -fi[lane];
-        for (int l = 0; l < K; ++l) acc = fmaf(Gi[lane * KT + l], (float)xi[l], acc);
+#pragma unroll 8
+        for (int l = 0; l < K; ++l) acc = fmaf(Gi[lane * ldg + l], (float)xi[l], acc);
         terms[lane] = acc - fi[lane];
     }
     wave_sync_lds();
     float e = 0.0f;
+#pragma unroll 8
     for (int k = 0; k < K; ++k) e = fmaf((float)xi[k], terms[k], e);
     wave_sync_lds();
     return e;
@@ -910,16 +912,18 @@ __device__ float fallback_energy(const float *Gi, int KT, int K, const float *fi
 
 // Energy of levels lv (this wavefront's LDS copy, K entries) with the chains'
 // arithmetic (one wavefront; `terms` its LDS scratch of 32 floats).
-__device__ float wave_level_energy(const float *Gi, int KT, int K, const float *fi, const int *lv,
+__device__ float wave_level_energy(const float *Gi, int ldg, int K, const float *fi, const int *lv,
                                    float *terms, int lane)
 {
     if (lane < K) {
         float acc = -fi[lane];
-        for (int l = 0; l < K; ++l) acc = fmaf(Gi[lane * KT + l], (float)lv[l], acc);
+#pragma unroll 8
+        for (int l = 0; l < K; ++l) acc = fmaf(Gi[lane * ldg + l], (float)lv[l], acc);
         terms[lane] = acc - fi[lane];
     }
     wave_sync_lds();
     float e = 0.0f;
+#pragma unroll 8
     for (int k = 0; k < K; ++k) e = fmaf((float)lv[k], terms[k], e);
     wave_sync_lds();
     return e;
@@ -930,7 +934,7 @@ __device__ float wave_level_energy(const float *Gi, int KT, int K, const float *
 // clamp(xg + z, -qtop, qtop) replaces the guess iff its energy with the full
 // fields ff is strictly lower.  lv then holds the guess.  cand: LDS scratch of
 // 32 ints.
-__device__ void apply_move(int *lv, signed char *xg, const float *Gi, int KT, int K,
+__device__ void apply_move(int *lv, signed char *xg, const float *Gi, int ldg, int K,
                            const float *ff, int qtop, int *cand, float *terms, int lane)
 {
     if (lane < K) {
@@ -939,8 +943,8 @@ __device__ void apply_move(int *lv, signed char *xg, const float *Gi, int KT, in
         lv[lane] = (int)xg[lane];
     }
     wave_sync_lds();
-    const float Ec = wave_level_energy(Gi, KT, K, ff, cand, terms, lane);
-    const float Eg = wave_level_energy(Gi, KT, K, ff, lv, terms, lane);
+    const float Ec = wave_level_energy(Gi, ldg, K, ff, cand, terms, lane);
+    const float Eg = wave_level_energy(Gi, ldg, K, ff, lv, terms, lane);
     if (Ec < Eg && lane < K) {
         xg[lane] = (signed char)cand[lane];
         lv[lane] = cand[lane];
@@ -988,6 +992,7 @@ __device__ void decode_det(const int *lv, int n, int sc, int sy, int nsym, int n
             const float2 *Hr = Hsc + (size_t)r * nt;
             const float2 yv = y[((size_t)sc * nsym + sy) * nr + r];
             double re = yv.x, im = yv.y;
+#pragma unroll 8
             for (int t = 0; t < nt; ++t) {
                 const double xr = c * (double)lv[t];
                 const double xi = c * (double)lv[nt + t];
@@ -1205,12 +1210,33 @@ k_cim(const float *__restrict__ G, int inst_per_G, const float *__restrict__ f,
     }
 }
 
+// Copies an instance's G (KT x KT floats, KT <= 32) into this wavefront's LDS
+// slot with rows of KT + 1 floats, so that lanes reading one row each hit
+// distinct banks; all loads are issued before the stores.
+__device__ __forceinline__ void copy_g_to_lds(float *Gl, const float *Gg, int KT, int lane)
+{
+    const int n = KT * KT;
+    float v[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int e = lane + 64 * j;
+        v[j] = e < n ? Gg[e] : 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int e = lane + 64 * j;
+        if (e < n) Gl[(e / KT) * (KT + 1) + e % KT] = v[j];
+    }
+    wave_sync_lds();
+}
+
 __global__ void __launch_bounds__(kBlock) k_select(SelectArgs a)
 {
     __shared__ float terms[kWavesPerBlock][32];
     __shared__ int lvs[kWavesPerBlock][32];
     __shared__ double2 zsh[kWavesPerBlock][16];
     __shared__ int cand[kWavesPerBlock][32];
+    __shared__ float Gw[kWavesPerBlock][32 * 33];   // each wavefront's copy of its G
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -1229,13 +1255,15 @@ __global__ void __launch_bounds__(kBlock) k_select(SelectArgs a)
     const int bch = (int)(uint32_t)best;
     const float Eb = a.chain_E[(size_t)n * C + bch];
 
-    const float *Gi = a.G + (size_t)(n / a.inst_per_G) * KT * KT;
+    const float *Gg = a.G + (size_t)(n / a.inst_per_G) * KT * KT;
+    float *Gi = Gw[wave];
+    copy_g_to_lds(Gi, Gg, KT, lane);
     const float *fi = a.f + (size_t)n * KT;
     const signed char *xi = a.x_fb ? a.x_fb + (size_t)n * KT : nullptr;
     bool use_fb = false;
     float Efb = 0.0f;
     if (xi) {
-        Efb = fallback_energy(Gi, KT, K, fi, xi, terms[wave], lane);
+        Efb = fallback_energy(Gi, KT + 1, K, fi, xi, terms[wave], lane);
         use_fb = energy_less(Efb, Eb);
     }
     const uint32_t *S = a.chain_S + ((size_t)n * C + bch) * NW;
@@ -1266,7 +1294,7 @@ __global__ void __launch_bounds__(kBlock) k_select(SelectArgs a)
     }
     const int sc = n / a.n_sym, sy = n % a.n_sym;
     if (a.mode == kSelectDelta) {
-        apply_move(lvs[wave], a.guess + (size_t)n * KT, Gi, KT, K, a.f_full + (size_t)n * KT,
+        apply_move(lvs[wave], a.guess + (size_t)n * KT, Gi, KT + 1, K, a.f_full + (size_t)n * KT,
                    a.qtop, cand[wave], terms[wave], lane);
         if (!a.decode) return;
         decode_det(lvs[wave], n, sc, sy, a.n_sym, a.n_rows, a.n_cols, a.dq, a.c,
@@ -1694,15 +1722,17 @@ k_fused(const FusedJob *__restrict__ jobs, const FusedItem *__restrict__ items, 
 
 // f' = f - G x_g, one thread per (instance, dimension); g as a chain of fused
 // multiply-adds over l ascending from 0.
+template <int KT>
 __global__ void __launch_bounds__(kBlock) k_delta_prep(DeltaPrepArgs a)
 {
     const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
-    if (t >= (size_t)a.n_inst * a.KT) return;
-    const int n = (int)(t / a.KT), k = (int)(t % a.KT);
-    const float *Gk = a.G + ((size_t)(n / a.inst_per_G) * a.KT + k) * a.KT;
-    const signed char *xg = a.guess + (size_t)n * a.KT;
+    if (t >= (size_t)a.n_inst * KT) return;
+    const int n = (int)(t / KT), k = (int)(t % KT);
+    const float *Gk = a.G + ((size_t)(n / a.inst_per_G) * KT + k) * KT;
+    const signed char *xg = a.guess + (size_t)n * KT;
     float g = 0.0f;
-    for (int l = 0; l < a.KT; ++l) g = fmaf(Gk[l], (float)xg[l], g);
+#pragma unroll
+    for (int l = 0; l < KT; ++l) g = fmaf(Gk[l], (float)xg[l], g);
     a.f_out[t] = a.f[t] - g;
 }
 
@@ -1882,20 +1912,23 @@ __global__ void __launch_bounds__(kBlock) k_pick(PickArgs a)
     __shared__ float terms[kWavesPerBlock][32];
     __shared__ int la[kWavesPerBlock][32];
     __shared__ int lb[kWavesPerBlock][32];
+    __shared__ float Gw[kWavesPerBlock][32 * 33];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int n = blockIdx.x * kWavesPerBlock + wave;
     if (n >= a.n_inst) return;
     const int K = a.K, KT = a.KT;
-    const float *Gi = a.G + (size_t)(n / a.inst_per_G) * KT * KT;
+    const float *Gg = a.G + (size_t)(n / a.inst_per_G) * KT * KT;
+    float *Gi = Gw[wave];
+    copy_g_to_lds(Gi, Gg, KT, lane);
     const float *ff = a.f + (size_t)n * KT;
     if (lane < K) {
         la[wave][lane] = a.xa[(size_t)n * KT + lane];
         lb[wave][lane] = a.xb[(size_t)n * KT + lane];
     }
     wave_sync_lds();
-    const float Ea = wave_level_energy(Gi, KT, K, ff, la[wave], terms[wave], lane);
-    const float Eb = wave_level_energy(Gi, KT, K, ff, lb[wave], terms[wave], lane);
+    const float Ea = wave_level_energy(Gi, KT + 1, K, ff, la[wave], terms[wave], lane);
+    const float Eb = wave_level_energy(Gi, KT + 1, K, ff, lb[wave], terms[wave], lane);
     const bool use_b = Eb < Ea;
     if (a.from_b && lane == 0) a.from_b[n] = use_b ? 1 : 0;
     const int sc = n / a.n_sym, sy = n % a.n_sym;
@@ -2097,6 +2130,7 @@ hipError_t launch_anneal(int KT, int q, const AnnealArgs &a, hipStream_t s)
 hipError_t launch_select(const SelectArgs &a, hipStream_t s)
 {
     if (a.n_inst <= 0) return hipSuccess;
+    if (a.KT > 32 || a.K > a.KT) return hipErrorInvalidValue;   // G of an instance in LDS
     const int blocks = (a.n_inst + kWavesPerBlock - 1) / kWavesPerBlock;
     hipLaunchKernelGGL(k_select, dim3(blocks), dim3(kBlock), 0, s, a);
     return hipGetLastError();
@@ -2108,7 +2142,14 @@ hipError_t launch_delta_prep(const DeltaPrepArgs &a, hipStream_t s)
     if (total == 0) return hipSuccess;
     const size_t blocks = (total + kBlock - 1) / kBlock;
     if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_delta_prep, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+    if (a.KT == 8)
+        hipLaunchKernelGGL(k_delta_prep<8>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+    else if (a.KT == 16)
+        hipLaunchKernelGGL(k_delta_prep<16>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+    else if (a.KT == 32)
+        hipLaunchKernelGGL(k_delta_prep<32>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
