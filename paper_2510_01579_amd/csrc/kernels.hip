@@ -140,8 +140,8 @@ template <int NT, int NS>
 struct DetSharedT {
     cf32 Hs[64 * NT];
     double2 Cg[NT * NT];
-    double2 Fs[NS * NT];
-    double2 Ls[NT * NT];
+    double2 Fs[NS * (NT + 1)];   // rows padded to NT + 1 (lanes read a row each)
+    double2 Ls[NT * (NT + 1)];
     double ds[NT];
 };
 
@@ -153,6 +153,7 @@ __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, i
 {
     const int nthr = blockDim.x;
     const int K = 2 * nt;
+    constexpr int LD = NT + 1;          // row stride of Fs and Ls
 
     const float2 *Hg = H + (size_t)sc * nr * nt;
     for (int e = tid; e < nr * nt; e += nthr) sh.Hs[e] = to_cf32(Hg[e]);
@@ -183,6 +184,7 @@ __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, i
         for (int t = wave; t < ntiles; t += nwave) {
             mfma_v4d acc = {0.0, 0.0, 0.0, 0.0};
             const int s_col = (t - 2) * 8 + (lrow & 7);     // symbol of this lane's column
+#pragma unroll 4
             for (int ks = 0; ks < ksteps; ++ks) {
                 const int r2 = ks * 4 + lk;
                 const bool top = r2 < nr;
@@ -209,7 +211,7 @@ __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, i
                 if (t < 2) {
                     if (lrow < nt) Cgd[2 * (row * NT + lrow) + t] = acc[j];
                 } else if (s_col < ns) {
-                    Fsd[2 * (s_col * NT + row) + (lrow >= 8 ? 1 : 0)] = acc[j];
+                    Fsd[2 * (s_col * LD + row) + (lrow >= 8 ? 1 : 0)] = acc[j];
                 }
             }
         }
@@ -241,7 +243,7 @@ __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, i
     }
     for (int p = tid; p < ns * nt; p += nthr) {
         const int r0 = p / nt, ia = p % nt;
-        const double2 F = sh.Fs[r0 * NT + ia];
+        const double2 F = sh.Fs[r0 * LD + ia];
         float *fs = fout + (size_t)r0 * ldf;
         fs[ia] = (float)(c * F.x);
         fs[nt + ia] = (float)(c * F.y);
@@ -272,8 +274,9 @@ __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, i
     for (int j = 0; j < nt; ++j) {
         if (tid == 0) {
             double dj = sh.Cg[j * NT + j].x + noise_var;
+#pragma unroll 4
             for (int k = 0; k < j; ++k) {
-                const double2 v = sh.Ls[j * NT + k];
+                const double2 v = sh.Ls[j * LD + k];
                 double t = v.x * v.x + v.y * v.y;
                 t = t * sh.ds[k];
                 dj = dj - t;
@@ -283,24 +286,26 @@ __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, i
         wave_sync_lds();
         for (int i = j + 1 + tid; i < nt; i += 64) {
             cd s = ld2(sh.Cg[i * NT + j]);
+#pragma unroll 4
             for (int k = 0; k < j; ++k) {
-                cd v = cmulc(ld2(sh.Ls[j * NT + k]), ld2(sh.Ls[i * NT + k]));
+                cd v = cmulc(ld2(sh.Ls[j * LD + k]), ld2(sh.Ls[i * LD + k]));
                 v.re = v.re * sh.ds[k];
                 v.im = v.im * sh.ds[k];
                 s.re = s.re - v.re;
                 s.im = s.im - v.im;
             }
-            sh.Ls[i * NT + j] = make_double2(s.re / sh.ds[j], s.im / sh.ds[j]);
+            sh.Ls[i * LD + j] = make_double2(s.re / sh.ds[j], s.im / sh.ds[j]);
         }
         wave_sync_lds();
     }
     // per-symbol solves in place on Fs, then slicing
     for (int r0 = tid; r0 < ns; r0 += 64) {
-        double2 *w = sh.Fs + r0 * NT;
+        double2 *w = sh.Fs + r0 * LD;
         for (int i = 0; i < nt; ++i) {
             cd s = ld2(w[i]);
+#pragma unroll 4
             for (int k = 0; k < i; ++k) {
-                const cd v = cmul(ld2(sh.Ls[i * NT + k]), ld2(w[k]));
+                const cd v = cmul(ld2(sh.Ls[i * LD + k]), ld2(w[k]));
                 s.re = s.re - v.re;
                 s.im = s.im - v.im;
             }
@@ -309,8 +314,9 @@ __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, i
         for (int i = 0; i < nt; ++i) w[i] = make_double2(w[i].x / sh.ds[i], w[i].y / sh.ds[i]);
         for (int i = nt - 1; i >= 0; --i) {
             cd s = ld2(w[i]);
+#pragma unroll 4
             for (int k = i + 1; k < nt; ++k) {
-                const cd v = cmulc(ld2(sh.Ls[k * NT + i]), ld2(w[k]));
+                const cd v = cmulc(ld2(sh.Ls[k * LD + i]), ld2(w[k]));
                 s.re = s.re - v.re;
                 s.im = s.im - v.im;
             }
@@ -1742,21 +1748,24 @@ __global__ void __launch_bounds__(kBlock) k_delta_prep(DeltaPrepArgs a)
 // the remaining user i with the smallest Re P_ii (the lowest index among
 // equals), its nulling row w = P_i,R H_R^H, and removes i from P by the Schur
 // complement P_jl -= P_ji P_il / P_ii.  The ordering and the nulling rows
-// depend on H only; then every symbol of the subcarrier (one lane each)
-// estimates w . r on its residual r, slices the estimate to the nearest odd
-// PAM level per real dimension and subtracts h_i s_i from r.  float64.
-constexpr int kSicSyms = 16;            // symbols per pass (one lane each)
-
-template <int NT>
-struct SicShared {
-    cf32 Hs[64 * NT];                   // [n_r][n_t]
-    double2 P[NT * NT];
-    double2 W[NT * 64];                 // nulling row of step k at W[k * 64]
-    double2 col[NT], row[NT];
-    double2 res[kSicSyms * 65];         // residuals, rows padded to 65 entries
-    int lv[kSicSyms][2 * NT];
-    int order[NT];
-};
+// depend on H only.  Then the symbols of the subcarrier are detected in
+// groups of g = 2^ceil(log2 n_r) lanes, one lane per receive antenna: each
+// lane holds one residual entry r_k in registers, the estimate w . r is a
+// shuffle reduction over the group, every lane slices it to the nearest odd
+// PAM level per real dimension, and subtracts h_ki s_i from its entry.  The
+// residual left after the last user is y - H x, whose squared norm is the
+// reported metric.  float64 throughout.
+//
+// Dynamic LDS: H (n_r x n_t complex float32), P (n_t x n_t complex float64),
+// the nulling rows W (n_t x n_r complex float64), and the levels of the
+// symbols of one pass (64 / g x 2 n_t ints).
+__host__ __device__ inline size_t sic_lds_bytes(int nr, int nt)
+{
+    int g = 1;
+    while (g < nr) g <<= 1;
+    return (size_t)nr * nt * 8 + (size_t)nt * nt * 16 + (size_t)nt * nr * 16 +
+           (size_t)(64 / g) * 2 * nt * 4 + 16 * 4;
+}
 
 __device__ __forceinline__ int sic_slice(double x, double c, int qtop)
 {
@@ -1767,49 +1776,69 @@ __device__ __forceinline__ int sic_slice(double x, double c, int qtop)
     return v < -qtop ? -qtop : (v > qtop ? qtop : v);
 }
 
-template <int NT>
 __global__ void __launch_bounds__(64) k_sic(SicArgs a)
 {
-    __shared__ SicShared<NT> sh;
+    extern __shared__ double2 sic_dyn[];
     const int lane = threadIdx.x;
     const int sc = blockIdx.x;
     const int nr = a.n_r, nt = a.n_t, qtop = (1 << a.q) - 1;
+    double2 *P = sic_dyn;                                   // [nt][nt]
+    double2 *W = P + nt * nt;                               // [nt][nr]
+    cf32 *Hs = reinterpret_cast<cf32 *>(W + nt * nr);       // [nr][nt]
+    int *lv = reinterpret_cast<int *>(Hs + nr * nt);        // [64 / g][2 nt]
+    int g = 1;
+    while (g < nr) g <<= 1;
+    const int spp = 64 / g;                                 // symbols per pass
+    int *order = lv + spp * 2 * nt;                         // [nt]
+
     const float2 *Hg = a.H + (size_t)sc * nr * nt;
-    for (int e = lane; e < nr * nt; e += 64) sh.Hs[e] = to_cf32(Hg[e]);
+    for (int e = lane; e < nr * nt; e += 64) Hs[e] = to_cf32(Hg[e]);
     wave_sync_lds();
     // A = H^H H + sigma^2 I
     for (int e = lane; e < nt * nt; e += 64) {
         const int i = e / nt, j = e % nt;
         cd acc{0.0, 0.0};
+#pragma unroll 4
         for (int r = 0; r < nr; ++r) {
-            const cf32 hi = sh.Hs[r * nt + i], hj = sh.Hs[r * nt + j];
+            const cf32 hi = Hs[r * nt + i], hj = Hs[r * nt + j];
             const cd v = cmulc(cd{hi.x, hi.y}, cd{hj.x, hj.y});   // conj(h_ri) h_rj
             acc.re = acc.re + v.re;
             acc.im = acc.im + v.im;
         }
         if (i == j) acc.re = acc.re + a.noise_var;
-        sh.P[i * NT + j] = make_double2(acc.re, acc.im);
+        P[e] = make_double2(acc.re, acc.im);
     }
     wave_sync_lds();
-    // in-place Gauss-Jordan inverse (Hermitian positive definite: no pivoting)
+    // in-place Gauss-Jordan inverse (Hermitian positive definite: no pivoting);
+    // each lane keeps its elements' row and column factors in registers
     for (int k = 0; k < nt; ++k) {
-        const cd pk = ld2(sh.P[k * NT + k]);
+        const cd pk = ld2(P[k * nt + k]);
         const double den = pk.re * pk.re + pk.im * pk.im;
         const cd t{pk.re / den, -pk.im / den};
-        if (lane < nt) {
-            const cd v = lane == k ? t : cmul(ld2(sh.P[k * NT + lane]), t);
-            sh.row[lane] = make_double2(v.re, v.im);
-            sh.col[lane] = sh.P[lane * NT + k];
+        cd rowv[4], colv[4], old[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = lane + 64 * u;
+            if (e < nt * nt) {
+                const int i = e / nt, j = e % nt;
+                rowv[u] = j == k ? t : cmul(ld2(P[k * nt + j]), t);
+                colv[u] = ld2(P[i * nt + k]);
+                old[u] = ld2(P[e]);
+            }
         }
         wave_sync_lds();
-        for (int e = lane; e < nt * nt; e += 64) {
-            const int i = e / nt, j = e % nt;
-            if (i == k) {
-                sh.P[i * NT + j] = sh.row[j];
-            } else {
-                const cd old = j == k ? cd{0.0, 0.0} : ld2(sh.P[i * NT + j]);
-                const cd m = cmul(ld2(sh.col[i]), ld2(sh.row[j]));
-                sh.P[i * NT + j] = make_double2(old.re - m.re, old.im - m.im);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = lane + 64 * u;
+            if (e < nt * nt) {
+                const int i = e / nt, j = e % nt;
+                if (i == k) {
+                    P[e] = make_double2(rowv[u].re, rowv[u].im);
+                } else {
+                    const cd o = j == k ? cd{0.0, 0.0} : old[u];
+                    const cd m = cmul(colv[u], rowv[u]);
+                    P[e] = make_double2(o.re - m.re, o.im - m.im);
+                }
             }
         }
         wave_sync_lds();
@@ -1818,88 +1847,106 @@ __global__ void __launch_bounds__(64) k_sic(SicArgs a)
     uint32_t rem = nt >= 32 ? 0xFFFFFFFFu : ((1u << nt) - 1u);
     for (int step = 0; step < nt; ++step) {
         const bool mine = lane < nt && ((rem >> lane) & 1u);
-        const double d = mine ? sh.P[lane * NT + lane].x : __builtin_inf();
+        const double d = mine ? P[lane * nt + lane].x : __builtin_inf();
         double m = d;
         for (int off = 32; off >= 1; off >>= 1) m = fmin(m, __shfl_xor(m, off, 64));
         uint64_t ball = __ballot(mine && d == m);
         if (ball == 0) ball = rem;              // no finite diagonal: the lowest remaining user
         const int i = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)ball) - 1);
-        if (lane == 0) sh.order[step] = i;
+        if (lane == 0) order[step] = i;
         for (int r = lane; r < nr; r += 64) {
             cd acc{0.0, 0.0};
+#pragma unroll 4
             for (int j = 0; j < nt; ++j) {
                 if (!((rem >> j) & 1u)) continue;
-                const cf32 h = sh.Hs[r * nt + j];
-                const cd v = cmulc(cd{h.x, h.y}, ld2(sh.P[i * NT + j]));   // P_ij conj(h_rj)
+                const cf32 h = Hs[r * nt + j];
+                const cd v = cmulc(cd{h.x, h.y}, ld2(P[i * nt + j]));   // P_ij conj(h_rj)
                 acc.re = acc.re + v.re;
                 acc.im = acc.im + v.im;
             }
-            sh.W[step * 64 + r] = make_double2(acc.re, acc.im);
+            W[step * nr + r] = make_double2(acc.re, acc.im);
         }
-        if (lane < nt) {
-            sh.col[lane] = sh.P[lane * NT + i];
-            sh.row[lane] = sh.P[i * NT + lane];
-        }
-        wave_sync_lds();
-        rem &= ~(1u << i);
-        const cd piv = ld2(sh.col[i]);
+        // Schur complement of user i
+        const cd piv = ld2(P[i * nt + i]);
         const double den = piv.re * piv.re + piv.im * piv.im;
         const cd ip{piv.re / den, -piv.im / den};
-        for (int e = lane; e < nt * nt; e += 64) {
-            const int j = e / nt, l = e % nt;
-            if (!((rem >> j) & 1u) || !((rem >> l) & 1u)) continue;
-            const cd m = cmul(cmul(ld2(sh.col[j]), ld2(sh.row[l])), ip);
-            const cd old = ld2(sh.P[j * NT + l]);
-            sh.P[j * NT + l] = make_double2(old.re - m.re, old.im - m.im);
-        }
-        wave_sync_lds();
-    }
-    if (a.order_out && lane < nt) a.order_out[(size_t)sc * nt + lane] = sh.order[lane];
-    // detection of the symbols, kSicSyms per pass
-    for (int s0 = 0; s0 < a.n_sym; s0 += kSicSyms) {
-        const int cnt = min(kSicSyms, a.n_sym - s0);
-        for (int e = lane; e < cnt * nr; e += 64) {
-            const int s = e / nr, r = e % nr;
-            const float2 v = a.y[((size_t)sc * a.n_sym + s0 + s) * nr + r];
-            sh.res[s * 65 + r] = make_double2((double)v.x, (double)v.y);
-        }
-        wave_sync_lds();
-        if (lane < cnt) {
-            double2 *res = sh.res + lane * 65;
-            for (int k = 0; k < nt; ++k) {
-                const int i = sh.order[k];
-                cd acc{0.0, 0.0};
-                for (int r = 0; r < nr; ++r) {
-                    const cd v = cmul(ld2(sh.W[k * 64 + r]), ld2(res[r]));
-                    acc.re = acc.re + v.re;
-                    acc.im = acc.im + v.im;
-                }
-                const int li = sic_slice(acc.re, a.c, qtop);
-                const int lq = sic_slice(acc.im, a.c, qtop);
-                sh.lv[lane][i] = li;
-                sh.lv[lane][nt + i] = lq;
-                const cd s{a.c * (double)li, a.c * (double)lq};
-                for (int r = 0; r < nr; ++r) {
-                    const cf32 h = sh.Hs[r * nt + i];
-                    const cd m = cmul(cd{h.x, h.y}, s);
-                    const cd o = ld2(res[r]);
-                    res[r] = make_double2(o.re - m.re, o.im - m.im);
+        const uint32_t keep = rem & ~(1u << i);
+        cd nv[4];
+        bool upd[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = lane + 64 * u;
+            upd[u] = false;
+            if (e < nt * nt) {
+                const int j = e / nt, l = e % nt;
+                if (((keep >> j) & 1u) && ((keep >> l) & 1u)) {
+                    const cd mm = cmul(cmul(ld2(P[j * nt + i]), ld2(P[i * nt + l])), ip);
+                    const cd o = ld2(P[e]);
+                    nv[u] = cd{o.re - mm.re, o.im - mm.im};
+                    upd[u] = true;
                 }
             }
         }
         wave_sync_lds();
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (upd[u]) P[lane + 64 * u] = make_double2(nv[u].re, nv[u].im);
+        rem = keep;
+        wave_sync_lds();
+    }
+    if (a.order_out && lane < nt) a.order_out[(size_t)sc * nt + lane] = order[lane];
+    // detection: symbol sl = lane / g of the pass, receive antenna r = lane % g
+    const int sl = lane / g, r = lane % g;
+    for (int s0 = 0; s0 < a.n_sym; s0 += spp) {
+        const int sy = s0 + sl;
+        const bool act = sl < spp && sy < a.n_sym && r < nr;
+        cd res{0.0, 0.0};
+        if (act) {
+            const float2 v = a.y[((size_t)sc * a.n_sym + sy) * nr + r];
+            res = cd{(double)v.x, (double)v.y};
+        }
+        for (int k = 0; k < nt; ++k) {
+            const int i = order[k];
+            cd prod{0.0, 0.0};
+            if (act) prod = cmul(ld2(W[k * nr + r]), res);
+            for (int off = g >> 1; off >= 1; off >>= 1) {
+                prod.re = prod.re + __shfl_xor(prod.re, off, 64);
+                prod.im = prod.im + __shfl_xor(prod.im, off, 64);
+            }
+            const int li = sic_slice(prod.re, a.c, qtop);
+            const int lq = sic_slice(prod.im, a.c, qtop);
+            if (act && r == 0) {
+                lv[sl * 2 * nt + i] = li;
+                lv[sl * 2 * nt + nt + i] = lq;
+            }
+            if (act) {
+                const cf32 h = Hs[r * nt + i];
+                const cd m = cmul(cd{h.x, h.y}, cd{a.c * (double)li, a.c * (double)lq});
+                res.re = res.re - m.re;
+                res.im = res.im - m.im;
+            }
+        }
+        // metric: the squared norm of the final residual y - H x
+        double e2 = act ? res.re * res.re + res.im * res.im : 0.0;
+        for (int off = g >> 1; off >= 1; off >>= 1) e2 = e2 + __shfl_xor(e2, off, 64);
+        wave_sync_lds();
+        const int cnt = min(spp, a.n_sym - s0);
+        const size_t n0 = (size_t)sc * a.n_sym + s0;
         if (a.levels) {
             for (int e = lane; e < cnt * a.ldl; e += 64) {
                 const int s = e / a.ldl, k = e % a.ldl;
-                const size_t n = (size_t)sc * a.n_sym + s0 + s;
-                a.levels[n * a.ldl + k] = (signed char)(k < 2 * nt ? sh.lv[s][k] : 0);
+                a.levels[(n0 + s) * a.ldl + k] = (signed char)(k < 2 * nt ? lv[s * 2 * nt + k] : 0);
             }
         }
         if (a.sym_out) {
-            for (int s = 0; s < cnt; ++s)
-                decode_det(sh.lv[s], (int)((size_t)sc * a.n_sym + s0 + s), sc, s0 + s, a.n_sym, nr,
-                           nt, a.q, a.c, a.H + (size_t)sc * nr * nt, a.y, a.sym_out, a.metric_out,
-                           lane);
+            for (int e = lane; e < cnt * nt; e += 64) {
+                const int s = e / nt, t = e % nt;
+                const int pI = (lv[s * 2 * nt + t] + qtop) >> 1;
+                const int pQ = (lv[s * 2 * nt + nt + t] + qtop) >> 1;
+                const int gI = pI ^ (pI >> 1), gQ = pQ ^ (pQ >> 1);
+                a.sym_out[(n0 + s) * nt + t] = (unsigned char)((gI << a.q) | gQ);
+            }
+            if (a.metric_out && act && r == 0) a.metric_out[n0 + sl] = (float)e2;
         }
         wave_sync_lds();
     }
@@ -2159,12 +2206,7 @@ hipError_t launch_sic(const SicArgs &a, hipStream_t s)
     if (a.n_r < 1 || a.n_r > 64 || a.n_t < 1 || a.n_t > 16 || a.n_sym < 1 ||
         (a.levels && a.ldl < 2 * a.n_t) || (a.metric_out && !a.sym_out))
         return hipErrorInvalidValue;
-    if (a.n_t <= 4)
-        hipLaunchKernelGGL(k_sic<4>, dim3(a.n_sc), dim3(64), 0, s, a);
-    else if (a.n_t <= 8)
-        hipLaunchKernelGGL(k_sic<8>, dim3(a.n_sc), dim3(64), 0, s, a);
-    else
-        hipLaunchKernelGGL(k_sic<16>, dim3(a.n_sc), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_sic, dim3(a.n_sc), dim3(64), sic_lds_bytes(a.n_r, a.n_t), s, a);
     return hipGetLastError();
 }
 
