@@ -255,12 +255,17 @@ int mmgap_detect_sic(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, c
  * MMSE-SIC estimate of mmgap_detect_sic (keys sched->seed + 64 + s); the
  * output is the better final answer by the float32 energy x^T G x - 2 f^T x,
  * the MMSE-SIC chain's only if strictly lower.  Same limits as both.
+ *   guesses       MMGAP_GUESS_MMSE | MMGAP_GUESS_SIC runs both chains (the
+ *                 paper's MMGaP-E); one of them runs that chain alone, whose
+ *                 answer is then the output (else MMGAP_EINVAL)
  *   sym_out, metric_out   as in mmgap_detect
  *   from_sic_out  [n_sc*n_sym] uint8, 1 where the MMSE-SIC chain's answer was
  *                 taken (out, nullable)
  */
+#define MMGAP_GUESS_MMSE 1
+#define MMGAP_GUESS_SIC 2
 int mmgap_detect_e(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, const void *y,
-                   const mmgap_schedule *sched, int stages, unsigned char *sym_out,
+                   const mmgap_schedule *sched, int stages, int guesses, unsigned char *sym_out,
                    float *metric_out, unsigned char *from_sic_out, void *stream);
 
 /*

@@ -552,26 +552,39 @@ SIC_KEY_OFFSET = 64
 
 
 def detect_e(H, y, noise_var, qam, chains, sweeps, beta2, seed, stages=1, inst_ids=None,
-             init_mode=0, nthreads=0, cim=None):
+             init_mode=0, nthreads=0, cim=None, guesses=3):
     """MMGaP-E (paper §3.2, Fig. 6): per problem two chains of `stages`
     stages of moves around a guess, one from the MMSE estimate (Philox keys
     seed + s) and one from the MMSE-SIC estimate (keys seed + 64 + s); the
     output is the better of the two final answers by float32 level energy
     (the MMSE-SIC chain's only if strictly lower).  Returns dict(sym, metric,
     levels, from_sic bool [n], the two chains' results a, b, and sic_margin,
-    the MMSE-SIC guess's slicing margin per instance)."""
+    the MMSE-SIC guess's slicing margin per instance).  `guesses` (bit 1 the
+    MMSE chain, bit 2 the MMSE-SIC chain) may select one chain alone, whose
+    answer is then the output."""
     n_sc, n_sym, _ = y.shape
     n_t = H.shape[-1]
     K = 2 * n_t
     ids = np.arange(n_sc * n_sym, dtype=np.uint32) if inst_ids is None \
         else np.asarray(inst_ids, dtype=np.uint32)
-    a = detect_delta(H, y, noise_var, qam, chains, sweeps, beta2, seed, stages=stages,
-                     inst_ids=ids, init_mode=init_mode, nthreads=nthreads, cim=cim)
-    sic = mmse_sic(H, y, noise_var, qam, inst_ids=ids)
-    g = sic["levels"]
-    b = detect_delta(H, y, noise_var, qam, chains, sweeps, beta2,
-                     (int(seed) + SIC_KEY_OFFSET) & 0xFFFFFFFFFFFFFFFF, stages=stages,
-                     inst_ids=ids, init_mode=init_mode, nthreads=nthreads, cim=cim, guess=g)
+    if guesses not in (1, 2, 3):
+        raise ValueError("guesses must be 1 (MMSE), 2 (MMSE-SIC) or 3 (both)")
+    a = b = None
+    sic = {"margin": np.full(ids.size, np.inf)}
+    if guesses & 1:
+        a = detect_delta(H, y, noise_var, qam, chains, sweeps, beta2, seed, stages=stages,
+                         inst_ids=ids, init_mode=init_mode, nthreads=nthreads, cim=cim)
+    if guesses & 2:
+        sic = mmse_sic(H, y, noise_var, qam, inst_ids=ids)
+        b = detect_delta(H, y, noise_var, qam, chains, sweeps, beta2,
+                         (int(seed) + SIC_KEY_OFFSET) & 0xFFFFFFFFFFFFFFFF, stages=stages,
+                         inst_ids=ids, init_mode=init_mode, nthreads=nthreads, cim=cim,
+                         guess=sic["levels"])
+    if b is None or a is None:
+        one = a if b is None else b
+        return dict(sym=one["sym"], metric=one["metric"], levels=one["levels"],
+                    from_sic=np.full(ids.size, b is not None), inst_ids=ids, a=a, b=b,
+                    sic_margin=sic["margin"])
     G, f_all = det_ising(H, y, qam)
     f = f_all[ids]
     lv = a["levels"].copy()

@@ -72,6 +72,7 @@ class Schedule(ctypes.Structure):
 
 
 DYN_METROPOLIS, DYN_CIM = 0, 1
+GUESS_MMSE, GUESS_SIC = 1, 2
 # CIM-CAC constants used when a caller gives only some of them: the paper's
 # integration step and coupling refresh period (dt = 0.02, f_mvm = 2; 128 steps
 # cover its reference integration length 2.56); a, p, zeta, eps and the initial
@@ -111,7 +112,7 @@ def lib() -> ctypes.CDLL:
             L.mmgap_detect.argtypes = [vp, P, vp, vp, S, vp, vp, vp]
             L.mmgap_detect_delta.argtypes = [vp, P, vp, vp, S, i, vp, vp, vp, vp]
             L.mmgap_detect_sic.argtypes = [vp, P, vp, vp, vp, vp, vp, vp, vp]
-            L.mmgap_detect_e.argtypes = [vp, P, vp, vp, S, i, vp, vp, vp, vp]
+            L.mmgap_detect_e.argtypes = [vp, P, vp, vp, S, i, i, vp, vp, vp, vp]
             L.mmgap_vpp_precode.argtypes = [vp, P, vp, vp, S, vp, vp, vp, vp]
             L.mmgap_set_profiling.argtypes = [vp, i]
             L.mmgap_last_profile.argtypes = [vp, ctypes.POINTER(f32), i]
@@ -441,10 +442,11 @@ class Context:
         return sym, met, lv, od
 
     def detect_e(self, H, y, qam, noise_var, chains, sweeps, beta2, seed, stages=1, init=0,
-                 metric=True, stream=None, cim=None):
+                 metric=True, stream=None, cim=None, guesses=3):
         """MMGaP-E (mmgap_detect_e): stages of moves from the MMSE and from the
-        MMSE-SIC guess, the better answer.  Returns (sym uint8 [n][n_tx], metric
-        float32 [n] or None, from_sic uint8 [n])."""
+        MMSE-SIC guess, the better answer (`guesses` selects one chain or both).
+        Returns (sym uint8 [n][n_tx], metric float32 [n] or None, from_sic uint8
+        [n])."""
         torch = _torch()
         p = self._problem(KIND_DET, H, y, qam, noise_var, 0.0)
         n = p.n_sc * p.n_sym
@@ -455,8 +457,8 @@ class Context:
         s, keep = self._schedule(chains, sweeps, beta2, seed, init, cim)
         st = stream if stream is not None else _stream(dev)
         self._check(lib().mmgap_detect_e(self._h, ctypes.byref(p), _ptr(H), _ptr(y),
-                                         ctypes.byref(s), int(stages), _ptr(sym), _ptr(met),
-                                         _ptr(fs), st))
+                                         ctypes.byref(s), int(stages), int(guesses), _ptr(sym),
+                                         _ptr(met), _ptr(fs), st))
         del keep
         return sym, met, fs
 

@@ -908,8 +908,8 @@ int mmgap_detect_delta(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H,
         e = mmgap::launch_pad_rows_i8(guess, at<signed char>(ctx, oxg), ni, sh.K, KT, st);
         if (e != hipSuccess) return hip_fail(ctx, e, "guess copy");
     }
-    e = hipMemsetAsync(at<signed char>(ctx, oz), 0, (size_t)ni * KT, st);
-    if (e != hipSuccess) return hip_fail(ctx, e, "hipMemsetAsync(zero moves)");
+    e = mmgap::launch_fill_u8(at<signed char>(ctx, oz), 0, (size_t)ni * KT, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "zero-move fill");
     rc = run_delta_stages(ctx, st, prob, sh, H, y, sched, stages, sched->seed, at<float>(ctx, oG),
                           at<float>(ctx, of), at<float>(ctx, ofp), at<signed char>(ctx, oxg),
                           at<signed char>(ctx, oz), at<float>(ctx, oE), at<uint32_t>(ctx, oS),
@@ -946,7 +946,7 @@ int mmgap_detect_sic(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, c
 }
 
 int mmgap_detect_e(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, const void *y,
-                   const mmgap_schedule *sched, int stages, unsigned char *sym_out,
+                   const mmgap_schedule *sched, int stages, int guesses, unsigned char *sym_out,
                    float *metric_out, unsigned char *from_sic_out, void *stream)
 {
     if (!ctx) return MMGAP_EINVAL;
@@ -956,12 +956,16 @@ int mmgap_detect_e(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, con
     if ((rc = check_schedule(ctx, sched))) return rc;
     if (stages < 1 || stages > mmgap::kMaxStages)
         return fail(ctx, MMGAP_EUNSUPPORTED, "stages=%d outside 1..%d", stages, mmgap::kMaxStages);
+    if (guesses < 1 || guesses > (MMGAP_GUESS_MMSE | MMGAP_GUESS_SIC))
+        return fail(ctx, MMGAP_EINVAL, "guesses=%d is not a non-empty set of MMGAP_GUESS_*",
+                    guesses);
     if (prob->n_tx > 16)
         return fail(ctx, MMGAP_EUNSUPPORTED, "MMSE-SIC supports n_tx <= 16 (got %d)", prob->n_tx);
     if (sh.n_inst == 0) return MMGAP_OK;
     if (!H || !y || !sym_out) return fail(ctx, MMGAP_EINVAL, "H, y and sym_out are required");
     DeviceGuard g(ctx->device);
     hipStream_t st = (hipStream_t)stream;
+    const bool use_a = guesses & MMGAP_GUESS_MMSE, use_b = guesses & MMGAP_GUESS_SIC;
     const int KT = sh.KT, NW = mmgap::spin_words(KT, 2), ni = sh.n_inst;
     Bump plan;
     const size_t oG = plan.take(sizeof(float) * (size_t)prob->n_sc * KT * KT);
@@ -978,23 +982,41 @@ int mmgap_detect_e(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, con
     float *G = at<float>(ctx, oG), *f = at<float>(ctx, of), *fp = at<float>(ctx, ofp);
     signed char *xa = at<signed char>(ctx, oxa), *xb = at<signed char>(ctx, oxb);
     signed char *zm = at<signed char>(ctx, oz);
-    if ((rc = det_build_into(ctx, st, prob, sh, H, y, G, f, xa))) return rc;
-    mmgap::SicArgs sa = sic_args(prob, sh, H, y);
-    sa.levels = xb;
-    sa.ldl = KT;
-    hipError_t e = mmgap::launch_sic(sa, st);
-    if (e != hipSuccess) return hip_fail(ctx, e, "MMSE-SIC launch");
-    e = hipMemsetAsync(zm, 0, (size_t)ni * KT, st);
-    if (e != hipSuccess) return hip_fail(ctx, e, "hipMemsetAsync(zero moves)");
+    // the MMSE estimate (the build's factorisation and solves) only for its chain
+    if ((rc = det_build_into(ctx, st, prob, sh, H, y, G, f, use_a ? xa : nullptr))) return rc;
+    hipError_t e;
+    if (use_b) {
+        mmgap::SicArgs sa = sic_args(prob, sh, H, y);
+        sa.levels = xb;
+        sa.ldl = KT;
+        e = mmgap::launch_sic(sa, st);
+        if (e != hipSuccess) return hip_fail(ctx, e, "MMSE-SIC launch");
+    }
+    e = mmgap::launch_fill_u8(zm, 0, (size_t)ni * KT, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "zero-move fill");
     // the chain from the MMSE guess (keys seed + s), then the one from the
-    // MMSE-SIC guess (keys seed + 64 + s)
-    rc = run_delta_stages(ctx, st, prob, sh, H, y, sched, stages, sched->seed, G, f, fp, xa, zm,
-                          at<float>(ctx, oE), at<uint32_t>(ctx, oS), false, nullptr, nullptr);
-    if (rc) return rc;
-    rc = run_delta_stages(ctx, st, prob, sh, H, y, sched, stages,
-                          sched->seed + (uint64_t)mmgap::kMaxStages, G, f, fp, xb, zm,
-                          at<float>(ctx, oE), at<uint32_t>(ctx, oS), false, nullptr, nullptr);
-    if (rc) return rc;
+    // MMSE-SIC guess (keys seed + 64 + s); a single chain decodes its own answer
+    const bool both = use_a && use_b;
+    if (use_a) {
+        rc = run_delta_stages(ctx, st, prob, sh, H, y, sched, stages, sched->seed, G, f, fp, xa,
+                              zm, at<float>(ctx, oE), at<uint32_t>(ctx, oS), !both, sym_out,
+                              metric_out);
+        if (rc) return rc;
+    }
+    if (use_b) {
+        rc = run_delta_stages(ctx, st, prob, sh, H, y, sched, stages,
+                              sched->seed + (uint64_t)mmgap::kMaxStages, G, f, fp, xb, zm,
+                              at<float>(ctx, oE), at<uint32_t>(ctx, oS), !both, sym_out,
+                              metric_out);
+        if (rc) return rc;
+    }
+    if (!both) {
+        if (from_sic_out) {
+            e = mmgap::launch_fill_u8(from_sic_out, use_b ? 1 : 0, (size_t)ni, st);
+            if (e != hipSuccess) return hip_fail(ctx, e, "from_sic fill");
+        }
+        return end_call(ctx, st);
+    }
     mmgap::PickArgs pk{};
     pk.G = G;
     pk.inst_per_G = prob->n_sym;

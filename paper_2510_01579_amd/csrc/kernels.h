@@ -222,6 +222,7 @@ hipError_t launch_expand(const ExpandArgs &a, hipStream_t s);
 // copy [n][K][K] -> [n][KT][KT] (and [m][K] -> [m][KT]) with zero padding
 hipError_t launch_pad_matrix(const float *src, float *dst, int n, int K, int KT, hipStream_t s);
 hipError_t launch_pad_rows_f32(const float *src, float *dst, int m, int K, int KT, hipStream_t s);
+hipError_t launch_fill_u8(void *dst, unsigned char v, size_t n, hipStream_t s);
 hipError_t launch_pad_rows_i8(const signed char *src, signed char *dst, int m, int K, int KT,
                               hipStream_t s);
 

@@ -2038,6 +2038,14 @@ __global__ void k_pad_matrix(const float *src, float *dst, int n, int K, int KT)
     }
 }
 
+// Byte fill with a kernel (capturable in HIP graphs, unlike a memset node).
+__global__ void k_fill_u8(unsigned char *dst, unsigned char v, size_t n)
+{
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (size_t)gridDim.x * blockDim.x)
+        dst[e] = v;
+}
+
 template <typename T>
 __global__ void k_pad_rows(const T *src, T *dst, int m, int K, int KT)
 {
@@ -2284,6 +2292,14 @@ hipError_t launch_pad_rows_f32(const float *src, float *dst, int m, int K, int K
     if (total == 0) return hipSuccess;
     hipLaunchKernelGGL(k_pad_rows<float>, dim3(grid_for(total)), dim3(kBlock), 0, s, src, dst, m,
                        K, KT);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u8(void *dst, unsigned char v, size_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(n)), dim3(kBlock), 0, s, (unsigned char *)dst, v,
+                       n);
     return hipGetLastError();
 }
 

@@ -123,6 +123,20 @@ def test_mmgap_e_matches_oracle(ctx, n_r, n_t, qam, n_sc, n_sym, snr, chains, sw
     assert np.allclose(host(met).astype(np.float64), ref["metric"], rtol=1e-4, atol=1e-6)
 
 
+@pytest.mark.parametrize("guesses", [1, 2])
+def test_mmgap_e_single_chain_matches_oracle(ctx, guesses):
+    note(f"mmgap-e guesses={guesses} 8x8 64-QAM 9x4 16x20 2 stages")
+    d = W.det_slot(2300 + guesses, 8, 8, 64, 9, 4, 25.0)
+    beta2 = W.linear_beta2(20, *W.det_beta_range(64, 8, d.noise_var))
+    seed = W.job_seed(22)
+    sym, met, fs = ctx.detect_e(dev(d.H), dev(d.y), 64, d.noise_var, 16, 20, beta2, seed,
+                                stages=2, guesses=guesses)
+    ref = O.detect_e(d.H, d.y, d.noise_var, 64, 16, 20, beta2, seed, stages=2, guesses=guesses)
+    assert_rows_equal(host(sym), ref["sym"], ref["sic_margin"])
+    assert np.all(host(fs) == (1 if guesses == 2 else 0))
+    assert np.allclose(host(met).astype(np.float64), ref["metric"], rtol=1e-4, atol=1e-6)
+
+
 def test_mmgap_e_full_slot_16x16_64qam_sampled(ctx):
     note("mmgap-e full slot 16x16 64-QAM 3276x12 16x12 1 stage")
     d = W.det_slot(3001, 16, 16, 64, 3276, 12, 25.0)
@@ -156,3 +170,7 @@ def test_sic_arguments(ctx):
     with pytest.raises(M.MmgapError) as e:
         ctx.detect_e(H, y, 16, d.noise_var, 32, 10, np.ones(10, np.float32), 1, stages=0)
     assert e.value.code == -4
+    for g in (0, 4):
+        with pytest.raises(M.MmgapError) as e:
+            ctx.detect_e(H, y, 16, d.noise_var, 32, 10, np.ones(10, np.float32), 1, guesses=g)
+        assert e.value.code == -1

@@ -123,3 +123,23 @@ def test_mmgap_e_reaches_the_ml_answer_on_tiny_problems():
     m_ml = O.det_metric(d.H, d.y, ml, 16)
     assert np.all(r["metric"] >= m_ml * (1 - 1e-9) - 1e-12)
     assert np.sum(np.isclose(r["metric"], m_ml, rtol=1e-6)) >= 9
+
+
+def test_mmgap_e_single_chains_are_the_plain_searches():
+    """guesses = 1 is the search from the MMSE guess (keys seed + s);
+    guesses = 2 is the search from the MMSE-SIC guess with keys seed + 64 + s."""
+    d = W.det_slot(67, 6, 4, 16, 5, 3, 15.0)
+    b2 = W.linear_beta2(20, *W.det_beta_range(16, 6, d.noise_var))
+    r1 = O.detect_e(d.H, d.y, d.noise_var, 16, 16, 20, b2, 8, stages=2, guesses=1)
+    a = O.detect_delta(d.H, d.y, d.noise_var, 16, 16, 20, b2, 8, stages=2)
+    assert np.array_equal(r1["levels"], a["levels"]) and not r1["from_sic"].any()
+    r2 = O.detect_e(d.H, d.y, d.noise_var, 16, 16, 20, b2, 8, stages=2, guesses=2)
+    g = O.mmse_sic(d.H, d.y, d.noise_var, 16)["levels"]
+    b = O.detect_delta(d.H, d.y, d.noise_var, 16, 16, 20, b2, 8 + 64, stages=2, guess=g)
+    assert np.array_equal(r2["levels"], b["levels"]) and r2["from_sic"].all()
+    r3 = O.detect_e(d.H, d.y, d.noise_var, 16, 16, 20, b2, 8, stages=2)
+    G, f = O.det_ising(d.H, d.y, 16)
+    for n in range(15):
+        e3 = O.level_energy32(G[n // 3], f[n], r3["levels"][n])
+        assert e3 == min(O.level_energy32(G[n // 3], f[n], a["levels"][n]),
+                         O.level_energy32(G[n // 3], f[n], b["levels"][n]))
