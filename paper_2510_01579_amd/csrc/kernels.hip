@@ -697,7 +697,7 @@ __device__ __forceinline__ float anneal_lane(const float *Gl, const float *fi,
         }
     }
 
-    const float E = lane_level_energy<KT>(Gl, fi, x);
+    // the spin words first (the flip steps die here), then the energy
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
         uint32_t word = 0u;
@@ -712,7 +712,7 @@ __device__ __forceinline__ float anneal_lane(const float *Gl, const float *fi,
         }
         bits[w] = word;
     }
-    return E;
+    return lane_level_energy<KT>(Gl, fi, x);
 }
 
 
@@ -1430,6 +1430,47 @@ struct FusedItemLds {
     int stage;              // stage of a job of moves around a guess
 };
 
+// Descriptor fields read after the anneal (through a laundered pointer, so
+// that they are loaded when needed instead of being held, and spilled, across
+// the anneal loop).
+struct FusedPost {
+    int kind, K, n_rows, n_cols, n_sym, chains, wpi, ldf, stages, dq;
+    int w[4];
+    double c, tau;
+    const float2 *y;
+    const float *ffull, *fbase;
+    signed char *xbase;
+    void *out0, *out1, *out2;
+};
+
+__device__ __forceinline__ FusedPost fused_post(const FusedJob *jp_in)
+{
+    const FusedJob *jp = jp_in;
+    asm volatile("" : "+s"(jp));
+    FusedPost p;
+    p.kind = rfl(jp->kind);
+    p.K = rfl(jp->K);
+    p.n_rows = rfl(jp->n_rows);
+    p.n_cols = rfl(jp->n_cols);
+    p.n_sym = rfl(jp->n_sym);
+    p.chains = rfl(jp->chains);
+    p.wpi = rfl(jp->wpi);
+    p.ldf = rfl(jp->ldf);
+    p.stages = rfl(jp->stages);
+    p.dq = rfl(jp->dq);
+    for (int b = 0; b < 4; ++b) p.w[b] = rfl(jp->w[b]);
+    p.c = rfld(jp->c);
+    p.tau = rfld(jp->tau);
+    p.y = uniform_ptr(jp->y);
+    p.ffull = uniform_ptr(jp->f);
+    p.fbase = p.stages > 0 ? uniform_ptr(jp->fp) : p.ffull;
+    p.xbase = uniform_ptr(jp->x_fb);
+    p.out0 = uniform_ptr(jp->out0);
+    p.out1 = uniform_ptr(jp->out1);
+    p.out2 = uniform_ptr(jp->out2);
+    return p;
+}
+
 template <int KT, int Q, bool PACKED>
 __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in, int sc_in,
                                              int sym0_in, int ns_in, const FusedItemLds &lds,
@@ -1437,130 +1478,133 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
 {
     const float *Gi = lds.G;
     constexpr int NW = (KT * Q + 31) / 32;
-    // every descriptor field as a wave-uniform (scalar) value
+    // the descriptor fields the anneal needs, as wave-uniform (scalar) values
     const FusedJob *jp = uniform_ptr(jobs_in) + rfl(job_in);
     const int sc = rfl(sc_in), sym0 = rfl(sym0_in), ns = rfl(ns_in);
     FusedCommon &sh = g_fc;
-    const int kind = rfl(jp->kind), K = rfl(jp->K);
-    const int n_rows = rfl(jp->n_rows), n_cols = rfl(jp->n_cols), n_sym = rfl(jp->n_sym);
-    const int chains = rfl(jp->chains), sweeps = rfl(jp->sweeps), init = rfl(jp->init);
-    const int wpi = rfl(jp->wpi);                       // wavefronts per instance: 1, 2 or 4
-    const int ldf = rfl(jp->ldf);
-    const int w[4] = {rfl(jp->w[0]), rfl(jp->w[1]), rfl(jp->w[2]), rfl(jp->w[3])};
-    // moves around a guess (stages > 0): the anneal takes the move fields and
-    // the zero move as its fallback, Philox key seed + stage; the winning move
-    // updates the guess (x_fb) and the last stage decodes the guess
-    const int stages = rfl(jp->stages);
-    const bool delta = stages > 0;
-    const int stage = rfl(lds.stage);
-    uint32_t key0 = rflu(jp->key0), key1 = rflu(jp->key1);
-    if (delta) {
-        const uint64_t kk = (((uint64_t)key1 << 32) | key0) + (uint64_t)stage;
-        key0 = rflu((uint32_t)kk);
-        key1 = rflu((uint32_t)(kk >> 32));
-    }
-    const int dq = rfl(jp->dq);
-    const double c = rfld(jp->c), tau = rfld(jp->tau);
-    const float2 *y = uniform_ptr(jp->y);
-    const float *beta2 = uniform_ptr(jp->beta2);
-    const float *ffull = uniform_ptr(jp->f);
-    const float *fbase = delta ? uniform_ptr(jp->fp) : ffull;
-    const signed char *xbase = uniform_ptr(jp->x_fb);
-    void *out0 = uniform_ptr(jp->out0), *out1 = uniform_ptr(jp->out1);
-    void *out2 = uniform_ptr(jp->out2);
-
     const int wave = rfl(tid >> 6);
     const int lane = tid & 63;
-    if constexpr (PACKED) {
-        const int gl = rfl(jp->glanes);
-        const int lg = __builtin_ctz((unsigned)gl);
-        const int per_wave = 64 >> lg;
-        const int first = wave * per_wave;    // first instance of this wavefront in the item
-        if (first >= ns) return;              // whole wavefront idle (no barrier follows)
-        const int cnt = min(per_wave, ns - first);
-        const int grp = lane >> lg;
-        const int chn = lane & (gl - 1);
-        const bool valid = grp < cnt;
-        const int r = first + (valid ? grp : 0);
-        const int n = sc * n_sym + sym0 + r;
-        const float *fi = fbase + (size_t)n * ldf;
-        const signed char *xi = delta ? sh.zmove : xbase + (size_t)n * KT;
-        uint32_t bits[NW];
-        const float E = anneal_lane<KT, Q, true>(Gi, fi, xi, beta2, sh.T, sweeps, w, key0, key1,
-                                                 init, (uint32_t)chn, (uint32_t)n, bits);
-        uint64_t key = ~0ull;
-        if (valid && chn < chains) key = ((uint64_t)energy_key(E) << 32) | (uint32_t)chn;
-        for (int off = gl >> 1; off >= 1; off >>= 1) {   // minimum within each group
-            const uint32_t lo = __shfl_xor((uint32_t)key, off, 64);
-            const uint32_t hi = __shfl_xor((uint32_t)(key >> 32), off, 64);
-            const uint64_t o = ((uint64_t)hi << 32) | lo;
-            key = o < key ? o : key;
-        }
-        for (int g = 0; g < cnt; ++g) {
-            const int bch = rfl((int)__shfl((uint32_t)key, g << lg, 64));
-            const int wl = (g << lg) + bch;            // the group's winning lane
-            if (lane == wl) {
-                for (int ww = 0; ww < NW; ++ww) sh.lvs[wave][ww] = (int)bits[ww];
-            }
-            wave_sync_lds();
-            uint32_t S[NW];
-            for (int ww = 0; ww < NW; ++ww) S[ww] = (uint32_t)sh.lvs[wave][ww];
-            wave_sync_lds();
-            const float Ebest = __shfl(E, wl, 64);
-            const int ng = sc * n_sym + sym0 + first + g;
-            const float *fg = fbase + (size_t)ng * ldf;
-            const signed char *xg = delta ? sh.zmove : xbase + (size_t)ng * KT;
-            const float Efb = fallback_energy(Gi, KT, K, fg, xg, sh.terms[wave], lane);
-            const bool use_fb = energy_less(Efb, Ebest);
-            winning_levels(use_fb, xg, S, K, Q, w, sh.lvs[wave], lane);
-            if (delta) {
-                apply_move(sh.lvs[wave], const_cast<signed char *>(xbase) + (size_t)ng * KT, Gi, KT,
-                           K, ffull + (size_t)ng * ldf, (1 << dq) - 1, sh.cand[wave],
-                           sh.terms[wave], lane);
-                if (stage == stages - 1)
-                    decode_det(sh.lvs[wave], ng, sc, sym0 + first + g, n_sym, n_rows, n_cols, dq,
-                               c, lds.H, y, (unsigned char *)out0, (float *)out1, lane);
-            } else if (kind == 0) {
-                decode_det(sh.lvs[wave], ng, sc, sym0 + first + g, n_sym, n_rows, n_cols, Q, c,
-                           lds.H, y, (unsigned char *)out0, (float *)out1, lane);
-            } else {
-                decode_vpp(sh.lvs[wave], ng, sc, sym0 + first + g, n_sym, n_rows, n_cols, tau,
-                           lds.Z, lds.ldz, lds.H, y, (signed char *)out0, (float2 *)out1,
-                           (float *)out2, sh.zsh[wave], lane);
-            }
-            wave_sync_lds();
-        }
-        return;
-    }
-    const int r0 = wave / wpi;                 // instance of this wavefront within the item
-    const int chunk = wave - r0 * wpi;
-    const bool active = r0 < ns;               // uniform over the wavefront
-    const int n = sc * n_sym + sym0 + (active ? r0 : 0);
-    const int ch = chunk * 64 + lane;
-    const float *fi = fbase + (size_t)n * ldf;
-    const signed char *xi = delta ? sh.zmove : xbase + (size_t)n * KT;
     uint32_t bits[NW];
     float E = 0.0f;
-    if (active) {
-        // the move fields are rewritten at every stage, so they are read with
-        // vector loads (the scalar cache is not updated by the stores)
-        if (delta)
+    int w[4];
+    {
+        const int n_sym = rfl(jp->n_sym), ldf = rfl(jp->ldf), wpi = rfl(jp->wpi);
+        const int sweeps = rfl(jp->sweeps), init = rfl(jp->init);
+        for (int b = 0; b < 4; ++b) w[b] = rfl(jp->w[b]);
+        // moves around a guess (stages > 0): the anneal takes the move fields and
+        // the zero move as its fallback, Philox key seed + stage; the winning move
+        // updates the guess (x_fb) and the last stage decodes the guess
+        const bool delta = rfl(jp->stages) > 0;
+        uint32_t key0 = rflu(jp->key0), key1 = rflu(jp->key1);
+        if (delta) {
+            const uint64_t kk = (((uint64_t)key1 << 32) | key0) + (uint64_t)rfl(lds.stage);
+            key0 = rflu((uint32_t)kk);
+            key1 = rflu((uint32_t)(kk >> 32));
+        }
+        const float *beta2 = uniform_ptr(jp->beta2);
+        const float *fbase = delta ? uniform_ptr(jp->fp) : uniform_ptr(jp->f);
+        const signed char *xbase = uniform_ptr(jp->x_fb);
+        if constexpr (PACKED) {
+            const int gl = rfl(jp->glanes);
+            const int lg = __builtin_ctz((unsigned)gl);
+            const int per_wave = 64 >> lg;
+            const int first = wave * per_wave;
+            if (first >= ns) return;              // whole wavefront idle (no barrier follows)
+            const int chains = rfl(jp->chains);
+            const int cnt = min(per_wave, ns - first);
+            const int grp = lane >> lg;
+            const int chn = lane & (gl - 1);
+            const bool valid = grp < cnt;
+            const int r = first + (valid ? grp : 0);
+            const int n = sc * n_sym + sym0 + r;
+            const float *fi = fbase + (size_t)n * ldf;
+            const signed char *xi = delta ? sh.zmove : xbase + (size_t)n * KT;
             E = anneal_lane<KT, Q, true>(Gi, fi, xi, beta2, sh.T, sweeps, w, key0, key1, init,
-                                         (uint32_t)ch, (uint32_t)n, bits);
-        else    // the row is wave-uniform (re-read from the first lane for the compiler)
-            E = anneal_lane<KT, Q, false>(Gi, uniform_ptr(fi), xi, beta2, sh.T, sweeps, w, key0,
-                                          key1, init, (uint32_t)ch, (uint32_t)n, bits);
-        uint64_t key = ~0ull;
-        if (ch < chains) key = ((uint64_t)energy_key(E) << 32) | (uint32_t)ch;
-        key = wave_min_u64(key);
-        if (lane == 0) sh.keys[wave] = key;
+                                         (uint32_t)chn, (uint32_t)n, bits);
+            uint64_t key = ~0ull;
+            if (valid && chn < chains) key = ((uint64_t)energy_key(E) << 32) | (uint32_t)chn;
+            for (int off = gl >> 1; off >= 1; off >>= 1) {   // minimum within each group
+                const uint32_t lo = __shfl_xor((uint32_t)key, off, 64);
+                const uint32_t hi = __shfl_xor((uint32_t)(key >> 32), off, 64);
+                const uint64_t o = ((uint64_t)hi << 32) | lo;
+                key = o < key ? o : key;
+            }
+            const FusedPost p = fused_post(jp);
+            const int stage = rfl(lds.stage);
+            for (int g = 0; g < cnt; ++g) {
+                const int bch = rfl((int)__shfl((uint32_t)key, g << lg, 64));
+                const int wl = (g << lg) + bch;            // the group's winning lane
+                if (lane == wl) {
+                    for (int ww = 0; ww < NW; ++ww) sh.lvs[wave][ww] = (int)bits[ww];
+                }
+                wave_sync_lds();
+                uint32_t S[NW];
+                for (int ww = 0; ww < NW; ++ww) S[ww] = (uint32_t)sh.lvs[wave][ww];
+                wave_sync_lds();
+                const float Ebest = __shfl(E, wl, 64);
+                const int ng = sc * p.n_sym + sym0 + first + g;
+                const float *fg = p.fbase + (size_t)ng * p.ldf;
+                const signed char *xg = p.stages > 0 ? sh.zmove : p.xbase + (size_t)ng * KT;
+                const float Efb = fallback_energy(Gi, KT, p.K, fg, xg, sh.terms[wave], lane);
+                const bool use_fb = energy_less(Efb, Ebest);
+                winning_levels(use_fb, xg, S, p.K, Q, p.w, sh.lvs[wave], lane);
+                if (p.stages > 0) {
+                    apply_move(sh.lvs[wave], p.xbase + (size_t)ng * KT, Gi, KT, p.K,
+                               p.ffull + (size_t)ng * p.ldf, (1 << p.dq) - 1, sh.cand[wave],
+                               sh.terms[wave], lane);
+                    if (stage == p.stages - 1)
+                        decode_det(sh.lvs[wave], ng, sc, sym0 + first + g, p.n_sym, p.n_rows,
+                                   p.n_cols, p.dq, p.c, lds.H, p.y, (unsigned char *)p.out0,
+                                   (float *)p.out1, lane);
+                } else if (p.kind == 0) {
+                    decode_det(sh.lvs[wave], ng, sc, sym0 + first + g, p.n_sym, p.n_rows,
+                               p.n_cols, Q, p.c, lds.H, p.y, (unsigned char *)p.out0,
+                               (float *)p.out1, lane);
+                } else {
+                    decode_vpp(sh.lvs[wave], ng, sc, sym0 + first + g, p.n_sym, p.n_rows,
+                               p.n_cols, p.tau, lds.Z, lds.ldz, lds.H, p.y,
+                               (signed char *)p.out0, (float2 *)p.out1, (float *)p.out2,
+                               sh.zsh[wave], lane);
+                }
+                wave_sync_lds();
+            }
+            return;
+        }
+        const int r0 = wave / wpi;                 // instance of this wavefront within the item
+        const int chunk = wave - r0 * wpi;
+        const bool active = r0 < ns;               // uniform over the wavefront
+        const int n = sc * n_sym + sym0 + (active ? r0 : 0);
+        const int ch = chunk * 64 + lane;
+        const float *fi = fbase + (size_t)n * ldf;
+        const signed char *xi = delta ? sh.zmove : xbase + (size_t)n * KT;
+        if (active) {
+            // the move fields are rewritten at every stage, so they are read with
+            // vector loads (the scalar cache is not updated by the stores)
+            if (delta)
+                E = anneal_lane<KT, Q, true>(Gi, fi, xi, beta2, sh.T, sweeps, w, key0, key1, init,
+                                             (uint32_t)ch, (uint32_t)n, bits);
+            else    // the row is wave-uniform (re-read from the first lane for the compiler)
+                E = anneal_lane<KT, Q, false>(Gi, uniform_ptr(fi), xi, beta2, sh.T, sweeps, w,
+                                              key0, key1, init, (uint32_t)ch, (uint32_t)n, bits);
+            const int chains = rfl(jp->chains);
+            uint64_t key = ~0ull;
+            if (ch < chains) key = ((uint64_t)energy_key(E) << 32) | (uint32_t)ch;
+            key = wave_min_u64(key);
+            if (lane == 0) sh.keys[wave] = key;
+        }
     }
     __syncthreads();
+    // selection and decode: descriptor fields re-read after the anneal
+    const FusedPost p = fused_post(jp);
+    const int r0 = wave / p.wpi;
+    const int chunk = wave - r0 * p.wpi;
+    const bool active = r0 < ns;
+    const int ch = chunk * 64 + lane;
     int bch = 0;
     if (active) {
         uint64_t best = ~0ull;
-        for (int c2 = 0; c2 < wpi; ++c2) {
-            const uint64_t o = sh.keys[r0 * wpi + c2];
+        for (int c2 = 0; c2 < p.wpi; ++c2) {
+            const uint64_t o = sh.keys[r0 * p.wpi + c2];
             best = o < best ? o : best;
         }
         bch = (int)(uint32_t)best;
@@ -1570,26 +1614,31 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
     }
     __syncthreads();
     if (!active || chunk != bch / 64) return;   // the winner's wavefront decodes
+    const int n = sc * p.n_sym + sym0 + r0;
     uint32_t S[NW];
     for (int ww = 0; ww < NW; ++ww) S[ww] = (uint32_t)sh.lvs[wave][ww];
     wave_sync_lds();
     const float Ebest = __shfl(E, bch & 63, 64);
-    const float Efb = fallback_energy(Gi, KT, K, fi, xi, sh.terms[wave], lane);
+    const float *fi = p.fbase + (size_t)n * p.ldf;
+    const signed char *xi = p.stages > 0 ? sh.zmove : p.xbase + (size_t)n * KT;
+    const float Efb = fallback_energy(Gi, KT, p.K, fi, xi, sh.terms[wave], lane);
     const bool use_fb = energy_less(Efb, Ebest);
-    winning_levels(use_fb, xi, S, K, Q, w, sh.lvs[wave], lane);
+    winning_levels(use_fb, xi, S, p.K, Q, p.w, sh.lvs[wave], lane);
     const int sy = sym0 + r0;
-    if (delta) {
-        apply_move(sh.lvs[wave], const_cast<signed char *>(xbase) + (size_t)n * KT, Gi, KT, K,
-                   ffull + (size_t)n * ldf, (1 << dq) - 1, sh.cand[wave], sh.terms[wave], lane);
-        if (stage == stages - 1)
-            decode_det(sh.lvs[wave], n, sc, sy, n_sym, n_rows, n_cols, dq, c, lds.H, y,
-                       (unsigned char *)out0, (float *)out1, lane);
-    } else if (kind == 0) {
-        decode_det(sh.lvs[wave], n, sc, sy, n_sym, n_rows, n_cols, Q, c, lds.H, y,
-                   (unsigned char *)out0, (float *)out1, lane);
+    if (p.stages > 0) {
+        apply_move(sh.lvs[wave], p.xbase + (size_t)n * KT, Gi, KT, p.K,
+                   p.ffull + (size_t)n * p.ldf, (1 << p.dq) - 1, sh.cand[wave], sh.terms[wave],
+                   lane);
+        if (rfl(lds.stage) == p.stages - 1)
+            decode_det(sh.lvs[wave], n, sc, sy, p.n_sym, p.n_rows, p.n_cols, p.dq, p.c, lds.H,
+                       p.y, (unsigned char *)p.out0, (float *)p.out1, lane);
+    } else if (p.kind == 0) {
+        decode_det(sh.lvs[wave], n, sc, sy, p.n_sym, p.n_rows, p.n_cols, Q, p.c, lds.H, p.y,
+                   (unsigned char *)p.out0, (float *)p.out1, lane);
     } else {
-        decode_vpp(sh.lvs[wave], n, sc, sy, n_sym, n_rows, n_cols, tau, lds.Z, lds.ldz, lds.H,
-                   y, (signed char *)out0, (float2 *)out1, (float *)out2, sh.zsh[wave], lane);
+        decode_vpp(sh.lvs[wave], n, sc, sy, p.n_sym, p.n_rows, p.n_cols, p.tau, lds.Z, lds.ldz,
+                   lds.H, p.y, (signed char *)p.out0, (float2 *)p.out1, (float *)p.out2,
+                   sh.zsh[wave], lane);
     }
 }
 
@@ -1682,38 +1731,47 @@ k_fused(const FusedJob *__restrict__ jobs, const FusedItem *__restrict__ items, 
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        // the decode reads H (and A^-1) from the build's LDS copies
-        FusedItemLds lds;
-        lds.G = bs.G;
-        if (jb.kind == 0) {
-            lds.H = reinterpret_cast<const float2 *>(bs.det().Hs);
-            lds.Z = nullptr;
-            lds.ldz = 0;
-        } else {
-            lds.H = reinterpret_cast<const float2 *>(bs.vpp().Hs);
-            lds.Z = bs.vpp().Zs;
-            lds.ldz = FusedClassTraits<CLS>::kNUV;
-        }
-        // moves around a guess: per stage the move fields f' = f - G x_g of the
+        // Moves around a guess: per stage the move fields f' = f - G x_g of the
         // item's instances (the guesses start as the build's sliced MMSE
-        // estimates and are updated by the stage before), then the anneal
+        // estimates and are updated by the stage before), then the anneal.
+        // The item's descriptors are re-read at every stage through a
+        // laundered index, so that only the stage counter and the item index
+        // stay live across the anneal (fewer registers spilled per item).
         const int nst = jb.stages > 0 ? jb.stages : 1;
         for (int st = 0; st < nst; ++st) {
-            if (jb.stages > 0) {
+            int itm = item;
+            asm volatile("" : "+s"(itm));
+            const FusedItem its = items[itm];
+            const FusedJob &js = jobs[its.job];
+            int tds = threadIdx.x;
+            asm volatile("" : "+v"(tds));
+            // the decode reads H (and A^-1) from the build's LDS copies
+            FusedItemLds lds;
+            lds.G = bs.G;
+            if (js.kind == 0) {
+                lds.H = reinterpret_cast<const float2 *>(bs.det().Hs);
+                lds.Z = nullptr;
+                lds.ldz = 0;
+            } else {
+                lds.H = reinterpret_cast<const float2 *>(bs.vpp().Hs);
+                lds.Z = bs.vpp().Zs;
+                lds.ldz = FusedClassTraits<CLS>::kNUV;
+            }
+            if (js.stages > 0) {
                 if (st > 0) {          // the previous stage's guesses are written
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
                     __syncthreads();
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
                 }
-                const int KT = jb.KT, ldf = jb.ldf;
-                for (int e = tid; e < it.ns * KT; e += kBlock) {
+                const int KT = js.KT, ldf = js.ldf;
+                for (int e = tds; e < its.ns * KT; e += kBlock) {
                     const int r = e / KT, k = e % KT;
-                    const size_t n = (size_t)it.sc * jb.n_sym + it.sym0 + r;
-                    const signed char *xg = jb.x_fb + n * KT;
+                    const size_t n = (size_t)its.sc * js.n_sym + its.sym0 + r;
+                    const signed char *xg = js.x_fb + n * KT;
                     float g = 0.0f;
                     for (int l = 0; l < KT; ++l) g = fmaf(bs.G[k * KT + l], (float)xg[l], g);
-                    jb.fp[n * ldf + k] = jb.f[n * ldf + k] - g;
+                    js.fp[n * ldf + k] = js.f[n * ldf + k] - g;
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                 asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -1721,7 +1779,7 @@ k_fused(const FusedJob *__restrict__ jobs, const FusedItem *__restrict__ items, 
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             }
             lds.stage = st;
-            fused_dispatch<CLS>(jb.variant, jb.glanes > 0, jobs, it, lds, tid);
+            fused_dispatch<CLS>(js.variant, js.glanes > 0, jobs, its, lds, tds);
         }
     }
 }
