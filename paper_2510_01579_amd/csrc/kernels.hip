@@ -123,7 +123,7 @@ __device__ __forceinline__ void wave_sync_lds()
 // 64 of them):
 //   Cg = H^H H (float64 matrix cores, upper triangle mirrored) -> G (real form, x c^2)
 //   F  = H^H y per symbol (float64 matrix cores)               -> f (real form, x c)
-//   MMSE (Cg + sigma^2 I)^-1 F by LDL^H, sliced to the nearest PAM level.
+//   MMSE (Cg + sigma^2 I)^-1 F by a Gauss-Jordan inverse, sliced to the nearest PAM level.
 // Writes G (ld x ld, zero padded) to Gout and, for symbols sym0..sym0+ns-1,
 // the field rows to fout, the fallback levels to xout (if non-null) and ||y||^2
 // to ynorm (if non-null).  nt <= NT, nr <= 64, ns <= NS.
@@ -141,8 +141,7 @@ struct DetSharedT {
     cf32 Hs[64 * NT];
     double2 Cg[NT * NT];
     double2 Fs[NS * (NT + 1)];   // rows padded to NT + 1 (lanes read a row each)
-    double2 Ls[NT * (NT + 1)];
-    double ds[NT];
+    double2 Ls[NT * (NT + 1)];  // the inverse of Cg + sigma^2 I
 };
 
 template <int NT, int NS>
@@ -265,76 +264,79 @@ __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, i
     }
     if (!xout) return;   // uniform over the block
     __syncthreads();
-    // The factorisation and the solves are chains of dependent float64 steps
-    // on at most 16 rows: the first wavefront does them alone, synchronising
-    // through LDS at wavefront level instead of across the block.
+    // The inverse is a chain of dependent float64 pivot steps on at most 16
+    // rows: the first wavefront does it alone, synchronising through LDS at
+    // wavefront level instead of across the block.
     if (tid >= 64) return;
 
-    // LDL^H of Cg + sigma^2 I
-    for (int j = 0; j < nt; ++j) {
-        if (tid == 0) {
-            double dj = sh.Cg[j * NT + j].x + noise_var;
-#pragma unroll 4
-            for (int k = 0; k < j; ++k) {
-                const double2 v = sh.Ls[j * LD + k];
-                double t = v.x * v.x + v.y * v.y;
-                t = t * sh.ds[k];
-                dj = dj - t;
+    // (Cg + sigma^2 I)^-1 by in-place Gauss-Jordan (Hermitian positive
+    // definite: no pivoting), each lane holding its elements' pivot-row and
+    // pivot-column factors in registers between the read and write phases
+    double2 *Ai = sh.Ls;                 // rows of LD
+    for (int e = tid; e < nt * nt; e += 64) {
+        const int i = e / nt, j = e % nt;
+        double2 v = sh.Cg[i * NT + j];
+        if (i == j) v.x = v.x + noise_var;
+        Ai[i * LD + j] = v;
+    }
+    wave_sync_lds();
+    for (int k = 0; k < nt; ++k) {
+        const cd pk = ld2(Ai[k * LD + k]);
+        const double den = pk.re * pk.re + pk.im * pk.im;
+        const cd t{pk.re / den, -pk.im / den};
+        cd rowv[4], colv[4], old[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + 64 * u;
+            if (e < nt * nt) {
+                const int i = e / nt, j = e % nt;
+                rowv[u] = j == k ? t : cmul(ld2(Ai[k * LD + j]), t);
+                colv[u] = ld2(Ai[i * LD + k]);
+                old[u] = ld2(Ai[i * LD + j]);
             }
-            sh.ds[j] = dj;
         }
         wave_sync_lds();
-        for (int i = j + 1 + tid; i < nt; i += 64) {
-            cd s = ld2(sh.Cg[i * NT + j]);
-#pragma unroll 4
-            for (int k = 0; k < j; ++k) {
-                cd v = cmulc(ld2(sh.Ls[j * LD + k]), ld2(sh.Ls[i * LD + k]));
-                v.re = v.re * sh.ds[k];
-                v.im = v.im * sh.ds[k];
-                s.re = s.re - v.re;
-                s.im = s.im - v.im;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + 64 * u;
+            if (e < nt * nt) {
+                const int i = e / nt, j = e % nt;
+                if (i == k) {
+                    Ai[i * LD + j] = st2(rowv[u]);
+                } else {
+                    const cd o = j == k ? cd{0.0, 0.0} : old[u];
+                    const cd m = cmul(colv[u], rowv[u]);
+                    Ai[i * LD + j] = make_double2(o.re - m.re, o.im - m.im);
+                }
             }
-            sh.Ls[i * LD + j] = make_double2(s.re / sh.ds[j], s.im / sh.ds[j]);
         }
         wave_sync_lds();
     }
-    // per-symbol solves in place on Fs, then slicing
-    for (int r0 = tid; r0 < ns; r0 += 64) {
-        double2 *w = sh.Fs + r0 * LD;
-        for (int i = 0; i < nt; ++i) {
-            cd s = ld2(w[i]);
+    // x = A^-1 F per symbol, one (symbol, user) pair per lane, then slicing
+    for (int e = tid; e < ns * nt; e += 64) {
+        const int r0 = e / nt, i = e % nt;
+        const double2 *w = sh.Fs + r0 * LD;
+        cd acc{0.0, 0.0};
 #pragma unroll 4
-            for (int k = 0; k < i; ++k) {
-                const cd v = cmul(ld2(sh.Ls[i * LD + k]), ld2(w[k]));
-                s.re = s.re - v.re;
-                s.im = s.im - v.im;
-            }
-            w[i] = st2(s);
+        for (int j = 0; j < nt; ++j) {
+            const cd v = cmul(ld2(Ai[i * LD + j]), ld2(w[j]));
+            acc.re = acc.re + v.re;
+            acc.im = acc.im + v.im;
         }
-        for (int i = 0; i < nt; ++i) w[i] = make_double2(w[i].x / sh.ds[i], w[i].y / sh.ds[i]);
-        for (int i = nt - 1; i >= 0; --i) {
-            cd s = ld2(w[i]);
-#pragma unroll 4
-            for (int k = i + 1; k < nt; ++k) {
-                const cd v = cmulc(ld2(sh.Ls[k * LD + i]), ld2(w[k]));
-                s.re = s.re - v.re;
-                s.im = s.im - v.im;
-            }
-            w[i] = st2(s);
-        }
+        const double tr = acc.re / c, ti = acc.im / c;
+        double lr = 2.0 * floor(tr / 2.0) + 1.0;
+        double li = 2.0 * floor(ti / 2.0) + 1.0;
+        lr = fmin(fmax(lr, (double)-qtop), (double)qtop);
+        li = fmin(fmax(li, (double)-qtop), (double)qtop);
+        if (lr != lr) lr = 1.0;   // NaN input: any valid level
+        if (li != li) li = 1.0;
         signed char *xo = xout + (size_t)r0 * ld;
-        for (int i = 0; i < nt; ++i) {
-            const double tr = w[i].x / c, ti = w[i].y / c;
-            double lr = 2.0 * floor(tr / 2.0) + 1.0;
-            double li = 2.0 * floor(ti / 2.0) + 1.0;
-            lr = fmin(fmax(lr, (double)-qtop), (double)qtop);
-            li = fmin(fmax(li, (double)-qtop), (double)qtop);
-            if (lr != lr) lr = 1.0;   // NaN input: any valid level
-            if (li != li) li = 1.0;
-            xo[i] = (signed char)(int)lr;
-            xo[nt + i] = (signed char)(int)li;
-        }
-        for (int k = K; k < ld; ++k) xo[k] = 0;
+        xo[i] = (signed char)(int)lr;
+        xo[nt + i] = (signed char)(int)li;
+    }
+    for (int e = tid; e < ns * (ld - K); e += 64) {
+        const int r0 = e / (ld - K), k = K + e % (ld - K);
+        xout[(size_t)r0 * ld + k] = 0;
     }
 }
 
