@@ -205,6 +205,24 @@ int mmgap_detect(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, const
                  void *stream);
 
 /*
+ * mmgap_cim_chains -- every CIM-CAC anneal's own final state, for studies of
+ * the integration (paper Appendix A: the sign of the final amplitudes and
+ * whether the integration diverged, against a fine-step reference with the
+ * same initial values).  Arguments as mmgap_solve; sched must select
+ * MMGAP_DYN_CIM (else MMGAP_EINVAL) and K q (padded) <= 32.  No selection.
+ *   spins_out     [n_inst][chains][K q] int8 +-1, sign(x_i) sign(x_a) (out)
+ *   e_out         [n_inst][chains] float32 energies of those spins (out, nullable)
+ *   diverged_out  [n_inst][chains] uint8 (out, nullable): 1 where an amplitude of a
+ *                 real spin or of the auxiliary one ended beyond 1000 in magnitude or
+ *                 not finite, or such an error variable ended not finite
+ */
+int mmgap_cim_chains(mmgap_ctx *ctx, int n_inst, int K, int q, const signed char *w,
+                     const float *G, int inst_per_G, const float *f,
+                     const signed char *x_fallback, const mmgap_schedule *sched,
+                     signed char *spins_out, float *e_out, unsigned char *diverged_out,
+                     void *stream);
+
+/*
  * mmgap_detect_delta -- uplink detection by moves around a guess (paper §2.3,
  * the Delta-Ising form built around an initial guess, Fig. 5; §3.2 MMGaP-E,
  * several stages each starting from the previous stage's solution).  Every

@@ -365,6 +365,62 @@ def cim_trajectory(G, f, K, q, w, steps, cim, seed, inst=0, ch=0, x_fb=None, ini
     return dict(amp=amp, err=err, spins=spins, E=float(E[0]))
 
 
+
+# Largest final amplitude magnitude of a CIM-CAC run not counted as diverged
+# (reading: the paper calls a run diverged when its integration fails to
+# converge, without a threshold; the amplitudes' fixed points are O(1)).
+CIM_DIVERGE_BOUND = 1000.0
+
+
+def cim_diverged(amp, err, n_real):
+    """The divergence rule: an amplitude of one of the first n_real spins or of
+    the auxiliary one (last) beyond the bound or not finite, or such an error
+    variable not finite."""
+    idx = list(range(n_real)) + [len(amp) - 1]
+    a = np.abs(np.asarray(amp, dtype=np.float32)[idx])
+    e = np.abs(np.asarray(err, dtype=np.float32)[idx])
+    return bool(np.any(~(a <= CIM_DIVERGE_BOUND)) or np.any(~np.isfinite(e)))
+
+
+def cim_chains(G, f, K, q, w, chains, steps, cim, seed, x_fb=None, inst_per_G=1, init_mode=0,
+               inst_ids=None):
+    """Every CIM-CAC anneal's final state (paper Appendix A studies): spins
+    [m][chains][K q] (sign(x_i) sign(x_a)), energies [m][chains] and divergence
+    flags [m][chains] for the instances `inst_ids` (default all)."""
+    f = np.ascontiguousarray(f, dtype=np.float32)
+    n = f.shape[0]
+    G = np.ascontiguousarray(G, dtype=np.float32).reshape(-1, K, K)
+    ids = np.arange(n) if inst_ids is None else np.asarray(inst_ids, dtype=np.int64)
+    N = K * q
+    spins = np.zeros((ids.size, chains, N), dtype=np.int8)
+    E = np.zeros((ids.size, chains), dtype=np.float32)
+    div = np.zeros((ids.size, chains), dtype=np.uint8)
+    for r, i in enumerate(ids):
+        xf = None if x_fb is None else np.asarray(x_fb)[i]
+        for c in range(chains):
+            t = cim_trajectory(G[i // inst_per_G], f[i], K, q, w, steps, cim, seed, inst=int(i),
+                               ch=c, x_fb=xf, init_mode=init_mode)
+            spins[r, c] = t["spins"]
+            E[r, c] = t["E"]
+            div[r, c] = cim_diverged(t["amp"], t["err"], N)
+    return dict(spins=spins, E=E, diverged=div)
+
+
+def cim_integration_metrics(ref_spins, ref_div, spins, div):
+    """Appendix A's metrics of a setting against the fine-step reference run
+    from the same initial values: P_diverge = diverged runs / runs; P_error =
+    final spins whose sign differs from the reference's / spins, over the runs
+    that diverged in neither."""
+    ref_div = np.asarray(ref_div).astype(bool).reshape(-1)
+    div = np.asarray(div).astype(bool).reshape(-1)
+    N = np.asarray(spins).shape[-1]
+    ok = ~ref_div & ~div
+    a = np.asarray(ref_spins).reshape(-1, N)[ok]
+    b = np.asarray(spins).reshape(-1, N)[ok]
+    p_err = float(np.mean(a != b)) if a.size else float("nan")
+    return dict(p_diverge=float(np.mean(div)), p_error=p_err, runs=int(div.size),
+                compared=int(ok.sum()))
+
 def level_energy32(G: np.ndarray, f: np.ndarray, levels: np.ndarray) -> float:
     """The float32 selection energy of given levels (same arithmetic as the chains)."""
     G = np.ascontiguousarray(G, dtype=np.float32)

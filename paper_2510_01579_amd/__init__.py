@@ -36,7 +36,7 @@ STATUS = {0: "MMGAP_OK", -1: "MMGAP_EINVAL", -2: "MMGAP_ENOMEM", -3: "MMGAP_EDEV
 
 EXPORTS = ("mmgap_create", "mmgap_destroy", "mmgap_last_error", "mmgap_build_ising",
            "mmgap_solve", "mmgap_detect", "mmgap_detect_delta", "mmgap_detect_sic",
-           "mmgap_detect_e", "mmgap_vpp_precode",
+           "mmgap_detect_e", "mmgap_cim_chains", "mmgap_vpp_precode",
            "mmgap_set_profiling",
            "mmgap_last_profile", "mmgap_plan_create", "mmgap_plan_launch", "mmgap_plan_info",
            "mmgap_plan_destroy", "mmgap_server_start", "mmgap_server_submit",
@@ -113,6 +113,7 @@ def lib() -> ctypes.CDLL:
             L.mmgap_detect_delta.argtypes = [vp, P, vp, vp, S, i, vp, vp, vp, vp]
             L.mmgap_detect_sic.argtypes = [vp, P, vp, vp, vp, vp, vp, vp, vp]
             L.mmgap_detect_e.argtypes = [vp, P, vp, vp, S, i, i, vp, vp, vp, vp]
+            L.mmgap_cim_chains.argtypes = [vp, i, i, i, vp, vp, i, vp, vp, S, vp, vp, vp, vp]
             L.mmgap_vpp_precode.argtypes = [vp, P, vp, vp, S, vp, vp, vp, vp]
             L.mmgap_set_profiling.argtypes = [vp, i]
             L.mmgap_last_profile.argtypes = [vp, ctypes.POINTER(f32), i]
@@ -384,6 +385,33 @@ class Context:
                                       _ptr(win), st))
         del keep
         return spins, E, win
+
+    def cim_chains(self, G, f, K, q, w, chains, steps, seed, cim=None, x_fallback=None,
+                   inst_per_G=1, init=0, stream=None):
+        """Every CIM-CAC anneal's final state (mmgap_cim_chains).  Returns (spins
+        int8 [n][chains][K q], energy float32 [n][chains], diverged uint8
+        [n][chains])."""
+        torch = _torch()
+        n = f.shape[0]
+        n_G = (n + inst_per_G - 1) // inst_per_G if n else 0
+        self._check_tensor(f, "f", torch.float32, (n, K))
+        self._check_tensor(G, "G", torch.float32, (n_G, K, K))
+        if x_fallback is not None:
+            self._check_tensor(x_fallback, "x_fallback", torch.int8, (n, K))
+        if len(w) != q:
+            raise ValueError("w must have q entries")
+        wv = (ctypes.c_byte * len(w))(*[int(v) for v in w])
+        dev = self._dev()
+        spins = torch.empty((n, chains, K * q), dtype=torch.int8, device=dev)
+        E = torch.empty((n, chains), dtype=torch.float32, device=dev)
+        div = torch.empty((n, chains), dtype=torch.uint8, device=dev)
+        s, keep = self._schedule(chains, steps, None, seed, init, {} if cim is None else cim)
+        st = stream if stream is not None else _stream(dev)
+        self._check(lib().mmgap_cim_chains(self._h, n, K, q, wv, _ptr(G), int(inst_per_G), _ptr(f),
+                                           _ptr(x_fallback), ctypes.byref(s), _ptr(spins), _ptr(E),
+                                           _ptr(div), st))
+        del keep
+        return spins, E, div
 
     def detect(self, H, y, qam, noise_var, chains, sweeps, beta2, seed, init=0, metric=True,
                stream=None, cim=None):

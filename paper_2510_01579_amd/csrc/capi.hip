@@ -719,6 +719,95 @@ int mmgap_solve(mmgap_ctx *ctx, int n_inst, int K, int q, const signed char *w,
     return end_call(ctx, st);
 }
 
+int mmgap_cim_chains(mmgap_ctx *ctx, int n_inst, int K, int q, const signed char *w,
+                     const float *G, int inst_per_G, const float *f,
+                     const signed char *x_fallback, const mmgap_schedule *sched,
+                     signed char *spins_out, float *e_out, unsigned char *diverged_out,
+                     void *stream)
+{
+    if (!ctx) return MMGAP_EINVAL;
+    if (n_inst < 0) return fail(ctx, MMGAP_EINVAL, "n_inst=%d < 0", n_inst);
+    if (K < 1 || K > mmgap::kMaxK) return fail(ctx, MMGAP_EUNSUPPORTED, "K=%d outside 1..32", K);
+    if (q < 1 || q > mmgap::kMaxQ) return fail(ctx, MMGAP_EUNSUPPORTED, "q=%d outside 1..4", q);
+    if (!w) return fail(ctx, MMGAP_EINVAL, "w is NULL");
+    int wv[mmgap::kMaxQ] = {1, 1, 1, 1};
+    for (int b = 0; b < q; ++b) {
+        if (!pow2_weight(w[b]))
+            return fail(ctx, MMGAP_EUNSUPPORTED, "w[%d]=%d is not a power of two in 1..64", b, w[b]);
+        wv[b] = w[b];
+    }
+    if (inst_per_G < 1) return fail(ctx, MMGAP_EINVAL, "inst_per_G=%d < 1", inst_per_G);
+    int rc = check_schedule(ctx, sched);
+    if (rc) return rc;
+    if (sched->dynamics != MMGAP_DYN_CIM)
+        return fail(ctx, MMGAP_EINVAL, "mmgap_cim_chains needs a CIM-CAC schedule");
+    const int KT = mmgap::padded_k(K);
+    if (KT * q > 32)
+        return fail(ctx, MMGAP_EUNSUPPORTED, "CIM dynamics needs K q <= 32 spins (padded %d)",
+                    KT * q);
+    if (n_inst == 0) return MMGAP_OK;
+    if (!G || !f || !spins_out)
+        return fail(ctx, MMGAP_EINVAL, "G, f and spins_out are required");
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int NW = mmgap::spin_words(KT, q);
+    const int n_G = (n_inst + inst_per_G - 1) / inst_per_G;
+    const bool pad = KT != K;
+    Bump plan;
+    const size_t oG = pad ? plan.take(sizeof(float) * (size_t)n_G * KT * KT) : 0;
+    const size_t of = pad ? plan.take(sizeof(float) * (size_t)n_inst * KT) : 0;
+    const size_t ox = (pad && x_fallback) ? plan.take((size_t)n_inst * KT) : 0;
+    const size_t oE = plan.take(sizeof(float) * (size_t)n_inst * sched->chains);
+    const size_t oS = plan.take(sizeof(uint32_t) * (size_t)n_inst * sched->chains * NW);
+    if ((rc = ensure_scratch(ctx, plan.off))) return rc;
+    if ((rc = begin_call(ctx, st))) return rc;
+    const float *Gp = G;
+    const float *fp = f;
+    const signed char *xp = x_fallback;
+    hipError_t e = hipSuccess;
+    if (pad) {
+        e = mmgap::launch_pad_matrix(G, at<float>(ctx, oG), n_G, K, KT, st);
+        if (e == hipSuccess) e = mmgap::launch_pad_rows_f32(f, at<float>(ctx, of), n_inst, K, KT, st);
+        if (e == hipSuccess && x_fallback)
+            e = mmgap::launch_pad_rows_i8(x_fallback, at<signed char>(ctx, ox), n_inst, K, KT, st);
+        if (e != hipSuccess) return hip_fail(ctx, e, "pad launch");
+        Gp = at<float>(ctx, oG);
+        fp = at<float>(ctx, of);
+        xp = x_fallback ? at<signed char>(ctx, ox) : nullptr;
+    }
+    mmgap::AnnealArgs a{};
+    a.G = Gp;
+    a.inst_per_G = inst_per_G;
+    a.f = fp;
+    a.x_fb = xp;
+    a.sweeps = sched->sweeps;
+    a.chains = sched->chains;
+    a.n_inst = n_inst;
+    for (int b = 0; b < mmgap::kMaxQ; ++b) a.w[b] = wv[b];
+    a.key0 = (uint32_t)sched->seed;
+    a.key1 = (uint32_t)(sched->seed >> 32);
+    a.init_mode = sched->init;
+    a.glanes = packed_lanes(sched->chains, inst_per_G, 64);
+    a.chain_E = e_out ? e_out : at<float>(ctx, oE);
+    a.chain_S = at<uint32_t>(ctx, oS);
+    a.cim.dt = sched->cim->dt;
+    a.cim.pm1 = sched->cim->p - 1.0f;
+    a.cim.a = sched->cim->a;
+    a.cim.nzeta = -sched->cim->zeta;
+    a.cim.eps = sched->cim->eps;
+    a.cim.amp0 = sched->cim->amp0;
+    a.cim.f_mvm = sched->cim->f_mvm;
+    a.chain_div = diverged_out;
+    a.n_real = K * q;
+    e = mmgap::launch_cim(KT, q, a, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "CIM anneal launch");
+    // spins of every chain, padding dropped (real spins come first in each word row)
+    e = mmgap::launch_chain_spins(a.chain_S, NW, K * q, (size_t)n_inst * sched->chains,
+                                  spins_out, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "spin expansion launch");
+    return end_call(ctx, st);
+}
+
 int mmgap_detect(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, const void *y,
                  const mmgap_schedule *sched, unsigned char *sym_out, float *metric_out,
                  void *stream)

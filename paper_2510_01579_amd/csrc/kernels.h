@@ -72,7 +72,17 @@ struct AnnealArgs {
     float *chain_E;         // [n_inst][chains]
     uint32_t *chain_S;      // [n_inst][chains][NW]
     CimParams cim;          // launch_cim only (sweeps = Euler steps, beta2 unused)
+    unsigned char *chain_div;   // launch_cim: [n_inst][chains] divergence flags, or null
+    int n_real;             // launch_cim: spins K q without the padding (divergence check)
 };
+
+// Largest final amplitude magnitude of a CIM-CAC run that is not counted as
+// diverged (the fixed points of the amplitudes are O(1)).
+constexpr float kCimDivergeBound = 1000.0f;
+
+// Spin words [n][NW] (bit set = -1) -> int8 spins [n][N].
+hipError_t launch_chain_spins(const uint32_t *S, int NW, int N, size_t n, signed char *out,
+                              hipStream_t s);
 
 enum SelectMode { kSelectSolve = 0, kSelectDet = 1, kSelectVpp = 2, kSelectDelta = 3 };
 

@@ -21,6 +21,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cfloat>
+
 #include "kernels.h"
 
 #pragma clang fp contract(off)
@@ -732,7 +734,8 @@ __device__ __forceinline__ float cim_lane(const float *Gl, const float *fi,
                                           const signed char *xfb_i, const CimParams &P,
                                           int steps, const int (&wts)[4], uint32_t key0,
                                           uint32_t key1, int init_mode, uint32_t uch,
-                                          uint32_t uinst, uint32_t (&bits)[(KT * Q + 31) / 32])
+                                          uint32_t uinst, uint32_t (&bits)[(KT * Q + 31) / 32],
+                                          int n_real, bool &diverged)
 {
     constexpr int N = KT * Q;
     constexpr int NW = (N + 31) / 32;
@@ -846,6 +849,15 @@ __device__ __forceinline__ float cim_lane(const float *Gl, const float *fi,
             err[i] = en > efloor ? en : efloor;
         }
     }
+    // diverged: an amplitude of a real spin or of the auxiliary one beyond the
+    // bound or not finite, or such an error variable not finite
+    bool div = false;
+#pragma unroll
+    for (int i = 0; i <= N; ++i) {
+        if (i < n_real || i == N)
+            div = div || !(fabsf(amp[i]) <= kCimDivergeBound) || !(fabsf(err[i]) <= FLT_MAX);
+    }
+    diverged = div;
     const bool aneg = amp[N] < 0.0f;
     float x[KT];
 #pragma unroll
@@ -1174,7 +1186,8 @@ __global__ void __launch_bounds__(kBlock)
 k_cim(const float *__restrict__ G, int inst_per_G, const float *__restrict__ f,
       const signed char *__restrict__ x_fb, CimParams prm, int steps, int chains, int n_inst,
       int w0, int w1, int w2, int w3, uint32_t key0, uint32_t key1, int init_mode, int glanes,
-      float *__restrict__ chain_E, uint32_t *__restrict__ chain_S)
+      float *__restrict__ chain_E, uint32_t *__restrict__ chain_S,
+      unsigned char *__restrict__ chain_div, int n_real)
 {
     constexpr int NW = (KT * Q + 31) / 32;
     __shared__ float4 Gw[kWavesPerBlock][KT * KT / 4];
@@ -1208,13 +1221,15 @@ k_cim(const float *__restrict__ G, int inst_per_G, const float *__restrict__ f,
     const signed char *xi = x_fb ? x_fb + (size_t)inst * KT : nullptr;
     const int wts[4] = {w0, w1, w2, w3};
     uint32_t bits[NW];
+    bool div;
     const float E = cim_lane<KT, Q, PACKED>(Gs, fi, xi, prm, steps, wts, key0, key1, init_mode,
-                                            (uint32_t)ch, (uint32_t)inst, bits);
+                                            (uint32_t)ch, (uint32_t)inst, bits, n_real, div);
     if (valid && ch < chains) {
         const size_t o = (size_t)inst * chains + ch;
         chain_E[o] = E;
 #pragma unroll
         for (int w = 0; w < NW; ++w) chain_S[o * NW + w] = bits[w];
+        if (chain_div) chain_div[o] = div ? 1 : 0;
     }
 }
 
@@ -2098,6 +2113,18 @@ __global__ void k_pad_matrix(const float *src, float *dst, int n, int K, int KT)
     }
 }
 
+// Spin words -> int8 spins: out[r][i] = -1 where bit i of word row r is set.
+__global__ void k_chain_spins(const uint32_t *S, int NW, int N, size_t n, signed char *out)
+{
+    const size_t total = n * (size_t)N;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const size_t r = e / N;
+        const int i = (int)(e % N);
+        out[e] = ((S[r * NW + (i >> 5)] >> (i & 31)) & 1u) ? (signed char)-1 : (signed char)1;
+    }
+}
+
 // Byte fill with a kernel (capturable in HIP graphs, unlike a memset node).
 __global__ void k_fill_u8(unsigned char *dst, unsigned char v, size_t n)
 {
@@ -2167,12 +2194,12 @@ hipError_t launch_cim_t(const AnnealArgs &a, hipStream_t s)
         hipLaunchKernelGGL((k_cim<KT, Q, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a.G,
                            a.inst_per_G, a.f, a.x_fb, a.cim, a.sweeps, a.chains, a.n_inst, a.w[0],
                            a.w[1], a.w[2], a.w[3], a.key0, a.key1, a.init_mode, a.glanes,
-                           a.chain_E, a.chain_S);
+                           a.chain_E, a.chain_S, a.chain_div, a.n_real);
     else
         hipLaunchKernelGGL((k_cim<KT, Q, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a.G,
                            a.inst_per_G, a.f, a.x_fb, a.cim, a.sweeps, a.chains, a.n_inst, a.w[0],
                            a.w[1], a.w[2], a.w[3], a.key0, a.key1, a.init_mode, 0, a.chain_E,
-                           a.chain_S);
+                           a.chain_S, a.chain_div, a.n_real);
     return hipGetLastError();
 }
 
@@ -2352,6 +2379,16 @@ hipError_t launch_pad_rows_f32(const float *src, float *dst, int m, int K, int K
     if (total == 0) return hipSuccess;
     hipLaunchKernelGGL(k_pad_rows<float>, dim3(grid_for(total)), dim3(kBlock), 0, s, src, dst, m,
                        K, KT);
+    return hipGetLastError();
+}
+
+hipError_t launch_chain_spins(const uint32_t *S, int NW, int N, size_t n, signed char *out,
+                              hipStream_t s)
+{
+    if (n == 0 || N == 0) return hipSuccess;
+    if (N > NW * 32) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_chain_spins, dim3(grid_for(n * (size_t)N)), dim3(kBlock), 0, s, S, NW, N,
+                       n, out);
     return hipGetLastError();
 }
 

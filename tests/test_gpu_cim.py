@@ -160,3 +160,51 @@ def test_cim_arguments(ctx):
     with pytest.raises(M.MmgapError) as e:          # batches run Metropolis only
         ctx.plan_create([job])
     assert e.value.code == -4
+
+
+@pytest.mark.parametrize("dt,f_mvm", [(0.01, 1), (0.08, 4), (0.32, 1)])
+def test_cim_chains_match_oracle(ctx, dt, f_mvm):
+    """Every anneal's final spins, energy and divergence flag (the Appendix A
+    study's raw data), including settings that diverge."""
+    note(f"cim chains dt={dt} f_mvm={f_mvm}")
+    from paper_2510_01579_amd import cim_integration as CI
+    K = 16
+    G, f = CI.instances(11, 48, K)
+    steps = int(round(2.56 / dt))
+    s, E, d = ctx.cim_chains(dev(G), dev(f), K, 1, [1], 2, steps, 5, cim=dict(dt=dt, f_mvm=f_mvm))
+    ref = O.cim_chains(G, f, K, 1, np.array([1], np.int8), 2, steps, dict(dt=dt, f_mvm=f_mvm), 5)
+    assert np.array_equal(host(d), ref["diverged"])
+    assert np.array_equal(host(s), ref["spins"])
+    assert np.array_equal(host(E).view(np.uint32), ref["E"].view(np.uint32))
+
+
+def test_cim_integration_study_matches_oracle_metrics(ctx):
+    note("cim integration study, 64 instances, 2 x 2 grid")
+    from paper_2510_01579_amd import cim_integration as CI
+    res = CI.run(ctx, n_inst=64, n_spins=12, seed=4, dts=(0.02, 0.16), fmvms=(1, 4))
+    G, f = CI.instances(4, 64, 12)
+    w = np.array([1], np.int8)
+    ref = O.cim_chains(G, f, 12, 1, w, 1, 256, dict(dt=0.01, f_mvm=1), 5)
+    for row in res["grid"]:
+        r = O.cim_chains(G, f, 12, 1, w, 1, row["steps"], dict(dt=row["dt"], f_mvm=row["f_mvm"]), 5)
+        m = O.cim_integration_metrics(ref["spins"], ref["diverged"], r["spins"], r["diverged"])
+        assert row["p_diverge"] == m["p_diverge"]
+        assert (row["p_error"] is None and m["compared"] == 0) or row["p_error"] == m["p_error"]
+
+
+def test_cim_chains_arguments(ctx):
+    note("cim chains argument errors")
+    G = torch.zeros((2, 8, 8), dtype=torch.float32, device="cuda:0")
+    f = torch.zeros((2, 8), dtype=torch.float32, device="cuda:0")
+    import ctypes
+    s, keep = M.Context._schedule(4, 10, np.ones(10, np.float32), 1, 0, None)   # Metropolis
+    wv = (ctypes.c_byte * 1)(1)
+    out = torch.empty((2, 4, 8), dtype=torch.int8, device="cuda:0")
+    rc = M.lib().mmgap_cim_chains(ctx._h, 2, 8, 1, wv, M._ptr(G), 1, M._ptr(f), None,
+                                  ctypes.byref(s), M._ptr(out), None, None, M._stream(ctx._dev()))
+    assert rc == -1
+    with pytest.raises(M.MmgapError) as e:                  # 64 spins
+        ctx.cim_chains(torch.zeros((1, 32, 32), dtype=torch.float32, device="cuda:0"),
+                       torch.zeros((1, 32), dtype=torch.float32, device="cuda:0"), 32, 2, [2, 1],
+                       1, 10, 1)
+    assert e.value.code == -4

@@ -139,3 +139,57 @@ def test_solve_selects_like_the_metropolis_solver():
     r = O.cim_solve(G[None], f[None], K, q, w, 4, 20, params(), 3, x_fb=gs[None])
     assert r["E"][0] <= min(es) + 1e-6
     assert 0 <= r["win"][0] <= 4
+
+
+def test_divergence_rule_on_hand_built_states():
+    amp = np.array([0.5, -2.0, 0.1, 1.0], np.float32)       # 3 spins + auxiliary
+    err = np.ones(4, np.float32)
+    assert not O.cim_diverged(amp, err, 3)
+    for bad in (np.float32(1e4), np.float32(np.inf), np.float32(np.nan)):
+        a = amp.copy(); a[1] = bad
+        assert O.cim_diverged(a, err, 3)
+        a = amp.copy(); a[3] = bad                           # the auxiliary amplitude
+        assert O.cim_diverged(a, err, 3)
+        a = amp.copy(); a[2] = bad                           # a padded spin is not checked
+        assert not O.cim_diverged(a, err, 2)
+    e = err.copy(); e[0] = np.inf
+    assert O.cim_diverged(amp, e, 3)
+
+
+def random_ising(seed, n, K):
+    from workload import synth as W
+    J, h = W.random_dense_ising(seed, n, K)
+    return (-J / 2).astype(np.float32), (h / 2).astype(np.float32)
+
+
+def test_integration_metrics_follow_the_step_size():
+    """Appendix A: the fine-step reference against itself has no errors; a
+    finer step stays close to it (Euler converges to the ODE solution); the
+    sign errors grow with the step size and with the refresh period."""
+    K, w = 12, np.array([1], np.int8)
+    G, f = random_ising(3, 60, K)
+    ref = O.cim_chains(G, f, K, 1, w, 1, 256, dict(dt=0.01, f_mvm=1), 7)
+    m = O.cim_integration_metrics(ref["spins"], ref["diverged"], ref["spins"], ref["diverged"])
+    assert m["p_error"] == 0.0 and m["p_diverge"] == 0.0
+    fine = O.cim_chains(G, f, K, 1, w, 1, 512, dict(dt=0.005, f_mvm=1), 7)
+    assert O.cim_integration_metrics(ref["spins"], ref["diverged"], fine["spins"],
+                                     fine["diverged"])["p_error"] < 0.05
+    errs = {}
+    for dt, fm in ((0.02, 1), (0.08, 1), (0.08, 4)):
+        r = O.cim_chains(G, f, K, 1, w, 1, int(round(2.56 / dt)), dict(dt=dt, f_mvm=fm), 7)
+        errs[(dt, fm)] = O.cim_integration_metrics(ref["spins"], ref["diverged"], r["spins"],
+                                                   r["diverged"])["p_error"]
+    assert errs[(0.02, 1)] < errs[(0.08, 1)] < errs[(0.08, 4)]
+
+
+def test_uncoupled_signs_survive_any_stable_step():
+    """G = 0, f = 0: each amplitude keeps its sign under every Euler step with
+    dt (1 - p + x^2) < 1, so every setting reproduces the reference spins."""
+    K, w = 8, np.array([1], np.int8)
+    G = np.zeros((20, K, K), np.float32)
+    f = np.zeros((20, K), np.float32)
+    ref = O.cim_chains(G, f, K, 1, w, 1, 256, dict(dt=0.01, f_mvm=1), 3)
+    for dt, fm in ((0.02, 2), (0.08, 8)):
+        r = O.cim_chains(G, f, K, 1, w, 1, int(round(2.56 / dt)), dict(dt=dt, f_mvm=fm), 3)
+        m = O.cim_integration_metrics(ref["spins"], ref["diverged"], r["spins"], r["diverged"])
+        assert m["p_error"] == 0.0 and m["p_diverge"] == 0.0
