@@ -914,12 +914,13 @@ __device__ __forceinline__ double wave_sum_f64(double v)
 // Energy of the fallback levels with the chains' arithmetic (one wavefront;
 // `terms` is this wavefront's LDS scratch of 32 floats).
 __device__ float fallback_energy(const float *Gi, int ldg, int K, const float *fi,
-                                 const signed char *xi, float *terms, int lane)
+                                 const signed char *xi, float *terms, int lane, bool tr = false)
 {
     if (lane < K) {
         float acc = -fi[lane];
 #pragma unroll 8
-        for (int l = 0; l < K; ++l) acc = fmaf(Gi[lane * ldg + l], (float)xi[l], acc);
+        for (int l = 0; l < K; ++l)
+            acc = fmaf(tr ? Gi[l * ldg + lane] : Gi[lane * ldg + l], (float)xi[l], acc);
         terms[lane] = acc - fi[lane];
     }
     wave_sync_lds();
@@ -933,12 +934,13 @@ __device__ float fallback_energy(const float *Gi, int ldg, int K, const float *f
 // Energy of levels lv (this wavefront's LDS copy, K entries) with the chains'
 // arithmetic (one wavefront; `terms` its LDS scratch of 32 floats).
 __device__ float wave_level_energy(const float *Gi, int ldg, int K, const float *fi, const int *lv,
-                                   float *terms, int lane)
+                                   float *terms, int lane, bool tr = false)
 {
     if (lane < K) {
         float acc = -fi[lane];
 #pragma unroll 8
-        for (int l = 0; l < K; ++l) acc = fmaf(Gi[lane * ldg + l], (float)lv[l], acc);
+        for (int l = 0; l < K; ++l)
+            acc = fmaf(tr ? Gi[l * ldg + lane] : Gi[lane * ldg + l], (float)lv[l], acc);
         terms[lane] = acc - fi[lane];
     }
     wave_sync_lds();
@@ -955,7 +957,8 @@ __device__ float wave_level_energy(const float *Gi, int ldg, int K, const float 
 // fields ff is strictly lower.  lv then holds the guess.  cand: LDS scratch of
 // 32 ints.
 __device__ void apply_move(int *lv, signed char *xg, const float *Gi, int ldg, int K,
-                           const float *ff, int qtop, int *cand, float *terms, int lane)
+                           const float *ff, int qtop, int *cand, float *terms, int lane,
+                           bool tr = false)
 {
     if (lane < K) {
         const int v = (int)xg[lane] + lv[lane];
@@ -963,8 +966,8 @@ __device__ void apply_move(int *lv, signed char *xg, const float *Gi, int ldg, i
         lv[lane] = (int)xg[lane];
     }
     wave_sync_lds();
-    const float Ec = wave_level_energy(Gi, ldg, K, ff, cand, terms, lane);
-    const float Eg = wave_level_energy(Gi, ldg, K, ff, lv, terms, lane);
+    const float Ec = wave_level_energy(Gi, ldg, K, ff, cand, terms, lane, tr);
+    const float Eg = wave_level_energy(Gi, ldg, K, ff, lv, terms, lane, tr);
     if (Ec < Eg && lane < K) {
         xg[lane] = (signed char)cand[lane];
         lv[lane] = cand[lane];
@@ -1562,13 +1565,16 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
                 const int ng = sc * p.n_sym + sym0 + first + g;
                 const float *fg = p.fbase + (size_t)ng * p.ldf;
                 const signed char *xg = p.stages > 0 ? sh.zmove : p.xbase + (size_t)ng * KT;
-                const float Efb = fallback_energy(Gi, KT, p.K, fg, xg, sh.terms[wave], lane);
+                // detection couplings are exactly symmetric: column reads (lane-contiguous,
+                // no LDS bank conflicts) give the row's values
+                const bool tr = p.kind == 0;
+                const float Efb = fallback_energy(Gi, KT, p.K, fg, xg, sh.terms[wave], lane, tr);
                 const bool use_fb = energy_less(Efb, Ebest);
                 winning_levels(use_fb, xg, S, p.K, Q, p.w, sh.lvs[wave], lane);
                 if (p.stages > 0) {
                     apply_move(sh.lvs[wave], p.xbase + (size_t)ng * KT, Gi, KT, p.K,
                                p.ffull + (size_t)ng * p.ldf, (1 << p.dq) - 1, sh.cand[wave],
-                               sh.terms[wave], lane);
+                               sh.terms[wave], lane, true);
                     if (stage == p.stages - 1)
                         decode_det(sh.lvs[wave], ng, sc, sym0 + first + g, p.n_sym, p.n_rows,
                                    p.n_cols, p.dq, p.c, lds.H, p.y, (unsigned char *)p.out0,
@@ -1638,14 +1644,16 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
     const float Ebest = __shfl(E, bch & 63, 64);
     const float *fi = p.fbase + (size_t)n * p.ldf;
     const signed char *xi = p.stages > 0 ? sh.zmove : p.xbase + (size_t)n * KT;
-    const float Efb = fallback_energy(Gi, KT, p.K, fi, xi, sh.terms[wave], lane);
+    // detection couplings are exactly symmetric: column reads (lane-contiguous, no
+    // LDS bank conflicts) give the row's values
+    const float Efb = fallback_energy(Gi, KT, p.K, fi, xi, sh.terms[wave], lane, p.kind == 0);
     const bool use_fb = energy_less(Efb, Ebest);
     winning_levels(use_fb, xi, S, p.K, Q, p.w, sh.lvs[wave], lane);
     const int sy = sym0 + r0;
     if (p.stages > 0) {
         apply_move(sh.lvs[wave], p.xbase + (size_t)n * KT, Gi, KT, p.K,
                    p.ffull + (size_t)n * p.ldf, (1 << p.dq) - 1, sh.cand[wave], sh.terms[wave],
-                   lane);
+                   lane, true);
         if (rfl(lds.stage) == p.stages - 1)
             decode_det(sh.lvs[wave], n, sc, sy, p.n_sym, p.n_rows, p.n_cols, p.dq, p.c, lds.H,
                        p.y, (unsigned char *)p.out0, (float *)p.out1, lane);

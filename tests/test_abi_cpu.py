@@ -49,11 +49,11 @@ def _field_order(body, names):
 
 
 def test_binding_structs_match_header():
-    """Field order of mmgap_problem, mmgap_cim_params and mmgap_schedule as
-    declared in the header."""
+    """Field order of mmgap_problem, mmgap_cim_params, mmgap_schedule and
+    mmgap_job as declared in the header."""
     text = open(os.path.join(ROOT, "include", "mmgap.h")).read()
     for name, cls in (("mmgap_problem", M.Problem), ("mmgap_cim_params", M.CimParams),
-                      ("mmgap_schedule", M.Schedule)):
+                      ("mmgap_schedule", M.Schedule), ("mmgap_job", M.Job)):
         names = [f[0] for f in cls._fields_]
         assert _field_order(_struct_body(text, name), names) == names, name
 
