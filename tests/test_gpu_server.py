@@ -189,3 +189,35 @@ def test_server_errors(ctx, mix):
     finally:
         ctx.server_stop()
     ctx.server_stop()                               # stopping twice is harmless
+
+
+def test_server_runs_detection_around_a_guess(ctx, mix):
+    """Jobs with stages >= 1 (moves around the MMSE guess) served beside plain
+    jobs equal mmgap_detect_delta on the same arguments."""
+    inputs, refs = mix
+    note("server: jobs with stages around the MMSE guess in a mix")
+    specs = [(8, 8, 64, 12, 12, 16, 12, 1), (16, 16, 64, 4, 12, 16, 8, 2), (4, 4, 16, 30, 5, 32, 20, 3)]
+    dins, drefs = [], []
+    for i, (a, b, qam, n_sc, n_sym, chains, sweeps, stages) in enumerate(specs):
+        d = W.det_slot(1400 + i, a, b, qam, n_sc, n_sym, 25.0)
+        beta2 = W.linear_beta2(sweeps, *W.det_beta_range(qam, a, d.noise_var))
+        inp = dict(H=dev(d.H), y=dev(d.y), qam=qam, noise_var=d.noise_var, chains=chains,
+                   sweeps=sweeps, beta2=beta2, seed=W.job_seed(90 + i), stages=stages)
+        sym, met = ctx.detect_delta(inp["H"], inp["y"], qam, d.noise_var, chains, sweeps, beta2,
+                                    inp["seed"], stages=stages)
+        torch.cuda.synchronize()
+        dins.append(inp)
+        drefs.append(dict(sym=sym.cpu().numpy(), metric=met.cpu().numpy()))
+    ctx.server_start(max_inflight=2)
+    try:
+        jobs = [ctx.det_job(p["H"], p["y"], p["qam"], p["noise_var"], p["chains"], p["sweeps"],
+                            p["beta2"], p["seed"], stages=p["stages"]) for p in dins]
+        plain = [job_of(ctx, inputs[i]) for i in (0, 1)]
+        ids = [ctx.server_submit(j) for j in jobs[:2] + plain + jobs[2:]]
+        wait_all(ctx, ids)
+        for k, j in enumerate(jobs):
+            assert_same(j, drefs[k], f"delta job {k} {specs[k]}")
+        for k, j in zip((0, 1), plain):
+            assert_same(j, refs[k], f"plain job {k}")
+    finally:
+        ctx.server_stop()
