@@ -143,7 +143,7 @@ struct DetSharedT {
     cf32 Hs[64 * NT];
     double2 Cg[NT * NT];
     double2 Fs[NS * (NT + 1)];   // rows padded to NT + 1 (lanes read a row each)
-    double2 Ls[NT * (NT + 1)];  // the inverse of Cg + sigma^2 I
+    double2 Ls[NT * (NT + 1)];  // the inverse of Cg + sigma^2 I (with Cg as its second buffer)
 };
 
 template <int NT, int NS>
@@ -271,49 +271,39 @@ __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, i
     // wavefront level instead of across the block.
     if (tid >= 64) return;
 
-    // (Cg + sigma^2 I)^-1 by in-place Gauss-Jordan (Hermitian positive
-    // definite: no pivoting), each lane holding its elements' pivot-row and
-    // pivot-column factors in registers between the read and write phases
-    double2 *Ai = sh.Ls;                 // rows of LD
+    // (Cg + sigma^2 I)^-1 by Gauss-Jordan (Hermitian positive definite: no
+    // pivoting), each pivot step reading one LDS buffer and writing the other
+    // (Ls and Cg, rows of NT), so that no element is held in registers across
+    // the step's synchronisation
+    double2 *src = sh.Ls, *dst = sh.Cg;
     for (int e = tid; e < nt * nt; e += 64) {
         const int i = e / nt, j = e % nt;
         double2 v = sh.Cg[i * NT + j];
         if (i == j) v.x = v.x + noise_var;
-        Ai[i * LD + j] = v;
+        src[i * NT + j] = v;
     }
     wave_sync_lds();
     for (int k = 0; k < nt; ++k) {
-        const cd pk = ld2(Ai[k * LD + k]);
+        const cd pk = ld2(src[k * NT + k]);
         const double den = pk.re * pk.re + pk.im * pk.im;
         const cd t{pk.re / den, -pk.im / den};
-        cd rowv[4], colv[4], old[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = tid + 64 * u;
-            if (e < nt * nt) {
-                const int i = e / nt, j = e % nt;
-                rowv[u] = j == k ? t : cmul(ld2(Ai[k * LD + j]), t);
-                colv[u] = ld2(Ai[i * LD + k]);
-                old[u] = ld2(Ai[i * LD + j]);
+        for (int e = tid; e < nt * nt; e += 64) {
+            const int i = e / nt, j = e % nt;
+            const cd rowv = j == k ? t : cmul(ld2(src[k * NT + j]), t);
+            if (i == k) {
+                dst[i * NT + j] = st2(rowv);
+            } else {
+                const cd o = j == k ? cd{0.0, 0.0} : ld2(src[i * NT + j]);
+                const cd m = cmul(ld2(src[i * NT + k]), rowv);
+                dst[i * NT + j] = make_double2(o.re - m.re, o.im - m.im);
             }
         }
         wave_sync_lds();
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = tid + 64 * u;
-            if (e < nt * nt) {
-                const int i = e / nt, j = e % nt;
-                if (i == k) {
-                    Ai[i * LD + j] = st2(rowv[u]);
-                } else {
-                    const cd o = j == k ? cd{0.0, 0.0} : old[u];
-                    const cd m = cmul(colv[u], rowv[u]);
-                    Ai[i * LD + j] = make_double2(o.re - m.re, o.im - m.im);
-                }
-            }
-        }
-        wave_sync_lds();
+        double2 *tmp = src;
+        src = dst;
+        dst = tmp;
     }
+    const double2 *Ai = src;
     // x = A^-1 F per symbol, one (symbol, user) pair per lane, then slicing
     for (int e = tid; e < ns * nt; e += 64) {
         const int r0 = e / nt, i = e % nt;
@@ -321,7 +311,7 @@ __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, i
         cd acc{0.0, 0.0};
 #pragma unroll 4
         for (int j = 0; j < nt; ++j) {
-            const cd v = cmul(ld2(Ai[i * LD + j]), ld2(w[j]));
+            const cd v = cmul(ld2(Ai[i * NT + j]), ld2(w[j]));
             acc.re = acc.re + v.re;
             acc.im = acc.im + v.im;
         }
@@ -913,14 +903,15 @@ __device__ __forceinline__ double wave_sum_f64(double v)
 
 // Energy of the fallback levels with the chains' arithmetic (one wavefront;
 // `terms` is this wavefront's LDS scratch of 32 floats).
+template <bool TR = false>
 __device__ float fallback_energy(const float *Gi, int ldg, int K, const float *fi,
-                                 const signed char *xi, float *terms, int lane, bool tr = false)
+                                 const signed char *xi, float *terms, int lane)
 {
     if (lane < K) {
         float acc = -fi[lane];
 #pragma unroll 8
         for (int l = 0; l < K; ++l)
-            acc = fmaf(tr ? Gi[l * ldg + lane] : Gi[lane * ldg + l], (float)xi[l], acc);
+            acc = fmaf(TR ? Gi[l * ldg + lane] : Gi[lane * ldg + l], (float)xi[l], acc);
         terms[lane] = acc - fi[lane];
     }
     wave_sync_lds();
@@ -933,14 +924,15 @@ __device__ float fallback_energy(const float *Gi, int ldg, int K, const float *f
 
 // Energy of levels lv (this wavefront's LDS copy, K entries) with the chains'
 // arithmetic (one wavefront; `terms` its LDS scratch of 32 floats).
+template <bool TR = false>
 __device__ float wave_level_energy(const float *Gi, int ldg, int K, const float *fi, const int *lv,
-                                   float *terms, int lane, bool tr = false)
+                                   float *terms, int lane)
 {
     if (lane < K) {
         float acc = -fi[lane];
 #pragma unroll 8
         for (int l = 0; l < K; ++l)
-            acc = fmaf(tr ? Gi[l * ldg + lane] : Gi[lane * ldg + l], (float)lv[l], acc);
+            acc = fmaf(TR ? Gi[l * ldg + lane] : Gi[lane * ldg + l], (float)lv[l], acc);
         terms[lane] = acc - fi[lane];
     }
     wave_sync_lds();
@@ -956,9 +948,9 @@ __device__ float wave_level_energy(const float *Gi, int ldg, int K, const float 
 // clamp(xg + z, -qtop, qtop) replaces the guess iff its energy with the full
 // fields ff is strictly lower.  lv then holds the guess.  cand: LDS scratch of
 // 32 ints.
+template <bool TR = false>
 __device__ void apply_move(int *lv, signed char *xg, const float *Gi, int ldg, int K,
-                           const float *ff, int qtop, int *cand, float *terms, int lane,
-                           bool tr = false)
+                           const float *ff, int qtop, int *cand, float *terms, int lane)
 {
     if (lane < K) {
         const int v = (int)xg[lane] + lv[lane];
@@ -966,8 +958,8 @@ __device__ void apply_move(int *lv, signed char *xg, const float *Gi, int ldg, i
         lv[lane] = (int)xg[lane];
     }
     wave_sync_lds();
-    const float Ec = wave_level_energy(Gi, ldg, K, ff, cand, terms, lane, tr);
-    const float Eg = wave_level_energy(Gi, ldg, K, ff, lv, terms, lane, tr);
+    const float Ec = wave_level_energy<TR>(Gi, ldg, K, ff, cand, terms, lane);
+    const float Eg = wave_level_energy<TR>(Gi, ldg, K, ff, lv, terms, lane);
     if (Ec < Eg && lane < K) {
         xg[lane] = (signed char)cand[lane];
         lv[lane] = cand[lane];
@@ -1567,14 +1559,15 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
                 const signed char *xg = p.stages > 0 ? sh.zmove : p.xbase + (size_t)ng * KT;
                 // detection couplings are exactly symmetric: column reads (lane-contiguous,
                 // no LDS bank conflicts) give the row's values
-                const bool tr = p.kind == 0;
-                const float Efb = fallback_energy(Gi, KT, p.K, fg, xg, sh.terms[wave], lane, tr);
+                const float Efb =
+                    p.kind == 0 ? fallback_energy<true>(Gi, KT, p.K, fg, xg, sh.terms[wave], lane)
+                                : fallback_energy<false>(Gi, KT, p.K, fg, xg, sh.terms[wave], lane);
                 const bool use_fb = energy_less(Efb, Ebest);
                 winning_levels(use_fb, xg, S, p.K, Q, p.w, sh.lvs[wave], lane);
                 if (p.stages > 0) {
-                    apply_move(sh.lvs[wave], p.xbase + (size_t)ng * KT, Gi, KT, p.K,
-                               p.ffull + (size_t)ng * p.ldf, (1 << p.dq) - 1, sh.cand[wave],
-                               sh.terms[wave], lane, true);
+                    apply_move<true>(sh.lvs[wave], p.xbase + (size_t)ng * KT, Gi, KT, p.K,
+                                     p.ffull + (size_t)ng * p.ldf, (1 << p.dq) - 1, sh.cand[wave],
+                                     sh.terms[wave], lane);
                     if (stage == p.stages - 1)
                         decode_det(sh.lvs[wave], ng, sc, sym0 + first + g, p.n_sym, p.n_rows,
                                    p.n_cols, p.dq, p.c, lds.H, p.y, (unsigned char *)p.out0,
@@ -1646,14 +1639,16 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
     const signed char *xi = p.stages > 0 ? sh.zmove : p.xbase + (size_t)n * KT;
     // detection couplings are exactly symmetric: column reads (lane-contiguous, no
     // LDS bank conflicts) give the row's values
-    const float Efb = fallback_energy(Gi, KT, p.K, fi, xi, sh.terms[wave], lane, p.kind == 0);
+    const float Efb =
+        p.kind == 0 ? fallback_energy<true>(Gi, KT, p.K, fi, xi, sh.terms[wave], lane)
+                    : fallback_energy<false>(Gi, KT, p.K, fi, xi, sh.terms[wave], lane);
     const bool use_fb = energy_less(Efb, Ebest);
     winning_levels(use_fb, xi, S, p.K, Q, p.w, sh.lvs[wave], lane);
     const int sy = sym0 + r0;
     if (p.stages > 0) {
-        apply_move(sh.lvs[wave], p.xbase + (size_t)n * KT, Gi, KT, p.K,
-                   p.ffull + (size_t)n * p.ldf, (1 << p.dq) - 1, sh.cand[wave], sh.terms[wave],
-                   lane, true);
+        apply_move<true>(sh.lvs[wave], p.xbase + (size_t)n * KT, Gi, KT, p.K,
+                         p.ffull + (size_t)n * p.ldf, (1 << p.dq) - 1, sh.cand[wave],
+                         sh.terms[wave], lane);
         if (rfl(lds.stage) == p.stages - 1)
             decode_det(sh.lvs[wave], n, sc, sy, p.n_sym, p.n_rows, p.n_cols, p.dq, p.c, lds.H,
                        p.y, (unsigned char *)p.out0, (float *)p.out1, lane);
