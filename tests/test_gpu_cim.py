@@ -208,3 +208,19 @@ def test_cim_chains_arguments(ctx):
                        torch.zeros((1, 32), dtype=torch.float32, device="cuda:0"), 32, 2, [2, 1],
                        1, 10, 1)
     assert e.value.code == -4
+
+
+def test_cim_chains_empty_and_padded(ctx):
+    """No instances: nothing to do; K = 5 padded to 8: the padded spins are
+    neither returned nor checked for divergence."""
+    note("cim chains: empty and padded")
+    G = torch.empty((0, 5, 5), dtype=torch.float32, device="cuda:0")
+    f = torch.empty((0, 5), dtype=torch.float32, device="cuda:0")
+    s, E, d = ctx.cim_chains(G, f, 5, 2, [2, 1], 4, 10, 1)
+    assert s.shape == (0, 4, 10)
+    Gn, fn = W.random_structured_ising(77, 9, 1, 5)
+    s, E, d = ctx.cim_chains(dev(Gn), dev(fn), 5, 2, [2, 1], 3, 40, 2, cim=dict(dt=0.16))
+    ref = O.cim_chains(Gn, fn, 5, 2, np.array([2, 1], np.int8), 3, 40, dict(dt=0.16), 2)
+    assert np.array_equal(host(s), ref["spins"])
+    assert np.array_equal(host(d), ref["diverged"])
+    assert np.array_equal(host(E).view(np.uint32), ref["E"].view(np.uint32))

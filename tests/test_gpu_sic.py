@@ -174,3 +174,27 @@ def test_sic_arguments(ctx):
         with pytest.raises(M.MmgapError) as e:
             ctx.detect_e(H, y, 16, d.noise_var, 32, 10, np.ones(10, np.float32), 1, guesses=g)
         assert e.value.code == -1
+
+
+def test_empty_and_largest_inputs(ctx):
+    """Empty slots return without writing; the largest symbol count (64 per
+    subcarrier: four detection passes of 16 lanes at 16 receive antennas) and
+    one symbol per subcarrier match the oracle."""
+    note("sic / mmgap-e / delta: empty and largest inputs")
+    H0 = torch.empty((0, 8, 8), dtype=torch.complex64, device="cuda:0")
+    y0 = torch.empty((0, 3, 8), dtype=torch.complex64, device="cuda:0")
+    sym, met, lv, od = ctx.detect_sic(H0, y0, 16, 0.1, levels=True, order=True)
+    assert sym.shape == (0, 8) and lv.shape == (0, 16)
+    b = np.ones(4, np.float32)
+    sym, met, fs = ctx.detect_e(H0, y0, 16, 0.1, 8, 4, b, 1)
+    assert sym.shape == (0, 8)
+    sym, met = ctx.detect_delta(H0, y0, 16, 0.1, 8, 4, b, 1)
+    assert sym.shape == (0, 8)
+    for n_sym in (64, 1):
+        d = W.det_slot(2400 + n_sym, 16, 12, 16, 3, n_sym, 20.0)
+        sym, met, lv, od = ctx.detect_sic(dev(d.H), dev(d.y), 16, d.noise_var, levels=True,
+                                          order=True)
+        ref = O.mmse_sic(d.H, d.y, d.noise_var, 16)
+        assert np.array_equal(host(od), ref["order"])
+        assert_rows_equal(host(lv), ref["levels"], ref["margin"])
+        assert np.allclose(host(met).astype(np.float64), ref["metric"], rtol=1e-4, atol=1e-6)
