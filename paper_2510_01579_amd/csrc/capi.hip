@@ -154,9 +154,13 @@ int check_problem(mmgap_ctx *ctx, const mmgap_problem *p, int kind, ProblemShape
     const int q = qam_bits(p->qam);
     if (!q) return fail(ctx, MMGAP_EUNSUPPORTED, "qam=%d not in {4,16,64}", p->qam);
     if (p->kind == MMGAP_KIND_DET) {
-        if (p->n_tx > 16 || p->n_rx > 64)
-            return fail(ctx, MMGAP_EUNSUPPORTED, "DET needs n_tx <= 16 and n_rx <= 64 (got %d x %d)",
+        if (p->n_tx > 32 || p->n_rx > 64)
+            return fail(ctx, MMGAP_EUNSUPPORTED, "DET needs n_tx <= 32 and n_rx <= 64 (got %d x %d)",
                         p->n_rx, p->n_tx);
+        if (p->n_tx > 16 && q > 2)
+            return fail(ctx, MMGAP_EUNSUPPORTED,
+                        "DET with more than 16 users supports QPSK and 16-QAM (got %d-QAM)",
+                        p->qam);
         if (!(p->noise_var >= 0.0f) || !std::isfinite(p->noise_var))
             return fail(ctx, MMGAP_EINVAL, "noise_var must be finite and >= 0");
         sh->K = 2 * p->n_tx;
@@ -664,8 +668,10 @@ int mmgap_solve(mmgap_ctx *ctx, int n_inst, int K, int q, const signed char *w,
 {
     if (!ctx) return MMGAP_EINVAL;
     if (n_inst < 0) return fail(ctx, MMGAP_EINVAL, "n_inst=%d < 0", n_inst);
-    if (K < 1 || K > mmgap::kMaxK) return fail(ctx, MMGAP_EUNSUPPORTED, "K=%d outside 1..32", K);
+    if (K < 1 || K > mmgap::kMaxK) return fail(ctx, MMGAP_EUNSUPPORTED, "K=%d outside 1..64", K);
     if (q < 1 || q > mmgap::kMaxQ) return fail(ctx, MMGAP_EUNSUPPORTED, "q=%d outside 1..4", q);
+    if (K > 32 && q > 2)
+        return fail(ctx, MMGAP_EUNSUPPORTED, "K=%d > 32 supports q <= 2 (got %d)", K, q);
     if (!w) return fail(ctx, MMGAP_EINVAL, "w is NULL");
     int wv[mmgap::kMaxQ] = {1, 1, 1, 1};
     for (int b = 0; b < q; ++b) {
@@ -727,8 +733,10 @@ int mmgap_cim_chains(mmgap_ctx *ctx, int n_inst, int K, int q, const signed char
 {
     if (!ctx) return MMGAP_EINVAL;
     if (n_inst < 0) return fail(ctx, MMGAP_EINVAL, "n_inst=%d < 0", n_inst);
-    if (K < 1 || K > mmgap::kMaxK) return fail(ctx, MMGAP_EUNSUPPORTED, "K=%d outside 1..32", K);
+    if (K < 1 || K > mmgap::kMaxK) return fail(ctx, MMGAP_EUNSUPPORTED, "K=%d outside 1..64", K);
     if (q < 1 || q > mmgap::kMaxQ) return fail(ctx, MMGAP_EUNSUPPORTED, "q=%d outside 1..4", q);
+    if (K > 32 && q > 2)
+        return fail(ctx, MMGAP_EUNSUPPORTED, "K=%d > 32 supports q <= 2 (got %d)", K, q);
     if (!w) return fail(ctx, MMGAP_EINVAL, "w is NULL");
     int wv[mmgap::kMaxQ] = {1, 1, 1, 1};
     for (int b = 0; b < q; ++b) {

@@ -9,7 +9,7 @@ namespace mmgap {
 
 // Supported structure of the anneal kernels: K padded up to KT in {8,16,32},
 // q in 1..4 spins per real dimension.
-constexpr int kMaxK = 32;
+constexpr int kMaxK = 64;
 constexpr int kMaxQ = 4;
 constexpr int kMaxChains = 1024;
 constexpr int kMaxSweeps = 8192;
@@ -17,7 +17,7 @@ constexpr int kMaxStages = 64;     // stages of detection around a guess
 // Metropolis threshold table: T[j] = round(2^16 2^(-j/64)), j < 1024; T[1024] = 0
 constexpr int kAcceptTable = 1025;
 
-inline int padded_k(int K) { return K <= 8 ? 8 : (K <= 16 ? 16 : 32); }
+inline int padded_k(int K) { return K <= 8 ? 8 : (K <= 16 ? 16 : (K <= 32 ? 32 : 64)); }
 inline int spin_words(int KT, int q) { return (KT * q + 31) / 32; }
 
 struct DetBuildArgs {

@@ -175,6 +175,36 @@ __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, i
     // from a plain float64 loop only by summation order.
     // Operand layout of the instruction: lane l supplies A[l % 16][l / 16] and
     // B[l / 16][l % 16] and receives D[l / 16 + 4 j][l % 16], j = 0..3.
+    if constexpr (NT > 16) {
+        // more than 16 users: plain float64 sums over the receive antennas
+        // (products of float32 values are exact in float64)
+        double *Cgd = reinterpret_cast<double *>(sh.Cg);
+        double *Fsd = reinterpret_cast<double *>(sh.Fs);
+        for (int e = tid; e < nt * nt; e += nthr) {
+            const int i = e / nt, j = e % nt;
+            double re = 0.0, im = 0.0;
+            for (int r = 0; r < nr; ++r) {
+                const cf32 hi = sh.Hs[r * nt + i], hj = sh.Hs[r * nt + j];
+                re = re + ((double)hi.x * hj.x + (double)hi.y * hj.y);
+                im = im + ((double)hi.x * hj.y - (double)hi.y * hj.x);
+            }
+            Cgd[2 * (i * NT + j)] = re;
+            Cgd[2 * (i * NT + j) + 1] = im;
+        }
+        for (int e = tid; e < ns * nt; e += nthr) {
+            const int s0 = e / nt, i = e % nt;
+            const float2 *ys = y + ((size_t)sc * nsym + sym0 + s0) * nr;
+            double re = 0.0, im = 0.0;
+            for (int r = 0; r < nr; ++r) {
+                const cf32 h = sh.Hs[r * nt + i];
+                const float2 yv = ys[r];
+                re = re + ((double)h.x * yv.x + (double)h.y * yv.y);
+                im = im + ((double)h.x * yv.y - (double)h.y * yv.x);
+            }
+            Fsd[2 * (s0 * LD + i)] = re;
+            Fsd[2 * (s0 * LD + i) + 1] = im;
+        }
+    } else
     {
         const int wave = tid >> 6, lane = tid & 63, nwave = nthr >> 6;
         const int lrow = lane & 15, lk = lane >> 4;
@@ -562,7 +592,7 @@ __device__ __forceinline__ float anneal_lane(const float *Gl, const float *fi,
     constexpr int N = KT * Q;
     constexpr int NW = (N + 31) / 32;
     constexpr int NG = (N + 7) / 8;
-    constexpr bool kBits = N > 48 || KT == 32;
+    constexpr bool kBits = N > 48 || KT >= 32;
     constexpr int ND = kBits ? 1 : N;
     constexpr int NB = kBits ? NW : 1;
 
@@ -638,7 +668,7 @@ __device__ __forceinline__ float anneal_lane(const float *Gl, const float *fi,
             // local field of dimension k from the current levels; PACKED reads
             // the row in chunks of 8 floats, each issued after the previous
             // chunk's products (the per-lane field loads leave fewer registers)
-            constexpr int kChunk = PACKED ? 8 : KT;
+            constexpr int kChunk = PACKED || KT > 32 ? 8 : KT;
             float g = -fk;
             float gkk = 0.0f;
 #pragma unroll
@@ -1115,7 +1145,7 @@ __global__ void __launch_bounds__(kBuildBlock) k_vpp_build(VppBuildArgs a)
 template <int KT, int Q>
 constexpr int anneal_min_waves()
 {
-    return KT <= 8 ? 8 : KT == 16 ? (Q == 3 ? 4 : 6) : (Q == 1 ? 5 : 4);
+    return KT <= 8 ? 8 : KT == 16 ? (Q == 3 ? 4 : 6) : KT == 32 ? (Q == 1 ? 5 : 4) : 2;
 }
 template <int KT, int Q, bool PACKED>
 __global__ void __launch_bounds__(kBlock)
@@ -1228,33 +1258,39 @@ k_cim(const float *__restrict__ G, int inst_per_G, const float *__restrict__ f,
     }
 }
 
-// Copies an instance's G (KT x KT floats, KT <= 32) into this wavefront's LDS
+// Copies an instance's G (KT x KT floats, KT <= GM) into this wavefront's LDS
 // slot with rows of KT + 1 floats, so that lanes reading one row each hit
-// distinct banks; all loads are issued before the stores.
+// distinct banks; the loads of each batch of 16 are issued before its stores.
+template <int GM>
 __device__ __forceinline__ void copy_g_to_lds(float *Gl, const float *Gg, int KT, int lane)
 {
     const int n = KT * KT;
-    float v[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const int e = lane + 64 * j;
-        v[j] = e < n ? Gg[e] : 0.0f;
-    }
+    for (int j0 = 0; j0 < (GM * GM + 63) / 64; j0 += 16) {
+        float v[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const int e = lane + 64 * j;
-        if (e < n) Gl[(e / KT) * (KT + 1) + e % KT] = v[j];
+        for (int j = 0; j < 16; ++j) {
+            const int e = lane + 64 * (j0 + j);
+            v[j] = e < n ? Gg[e] : 0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int e = lane + 64 * (j0 + j);
+            if (e < n) Gl[(e / KT) * (KT + 1) + e % KT] = v[j];
+        }
     }
     wave_sync_lds();
 }
 
+// GM: the largest padded dimension count KT the instantiation serves.
+template <int GM>
 __global__ void __launch_bounds__(kBlock) k_select(SelectArgs a)
 {
-    __shared__ float terms[kWavesPerBlock][32];
-    __shared__ int lvs[kWavesPerBlock][32];
+    __shared__ float terms[kWavesPerBlock][GM];
+    __shared__ int lvs[kWavesPerBlock][GM];
     __shared__ double2 zsh[kWavesPerBlock][16];
-    __shared__ int cand[kWavesPerBlock][32];
-    __shared__ float Gw[kWavesPerBlock][32 * 33];   // each wavefront's copy of its G
+    __shared__ int cand[kWavesPerBlock][GM];
+    __shared__ float Gw[kWavesPerBlock][GM * (GM + 1)];   // each wavefront's copy of its G
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -1275,7 +1311,7 @@ __global__ void __launch_bounds__(kBlock) k_select(SelectArgs a)
 
     const float *Gg = a.G + (size_t)(n / a.inst_per_G) * KT * KT;
     float *Gi = Gw[wave];
-    copy_g_to_lds(Gi, Gg, KT, lane);
+    copy_g_to_lds<GM>(Gi, Gg, KT, lane);
     const float *fi = a.f + (size_t)n * KT;
     const signed char *xi = a.x_fb ? a.x_fb + (size_t)n * KT : nullptr;
     bool use_fb = false;
@@ -2045,7 +2081,7 @@ __global__ void __launch_bounds__(kBlock) k_pick(PickArgs a)
     const int K = a.K, KT = a.KT;
     const float *Gg = a.G + (size_t)(n / a.inst_per_G) * KT * KT;
     float *Gi = Gw[wave];
-    copy_g_to_lds(Gi, Gg, KT, lane);
+    copy_g_to_lds<32>(Gi, Gg, KT, lane);
     const float *ff = a.f + (size_t)n * KT;
     if (lane < K) {
         la[wave][lane] = a.xa[(size_t)n * KT + lane];
@@ -2225,7 +2261,12 @@ hipError_t launch_det_build(const DetBuildArgs &a, hipStream_t s)
 {
     if (a.n_sc <= 0) return hipSuccess;
     if (a.n_t <= 8) hipLaunchKernelGGL(k_det_build<8>, dim3(a.n_sc), dim3(kBuildBlock), 0, s, a);
-    else hipLaunchKernelGGL(k_det_build<16>, dim3(a.n_sc), dim3(kBuildBlock), 0, s, a);
+    else if (a.n_t <= 16)
+        hipLaunchKernelGGL(k_det_build<16>, dim3(a.n_sc), dim3(kBuildBlock), 0, s, a);
+    else if (a.n_t <= 32)
+        hipLaunchKernelGGL(k_det_build<32>, dim3(a.n_sc), dim3(kBuildBlock), 0, s, a);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -2268,6 +2309,8 @@ hipError_t launch_anneal(int KT, int q, const AnnealArgs &a, hipStream_t s)
     MMGAP_ANNEAL_CASE(32, 2)
     MMGAP_ANNEAL_CASE(32, 3)
     MMGAP_ANNEAL_CASE(32, 4)
+    MMGAP_ANNEAL_CASE(64, 1)
+    MMGAP_ANNEAL_CASE(64, 2)
 #undef MMGAP_ANNEAL_CASE
     return hipErrorInvalidValue;
 }
@@ -2275,9 +2318,13 @@ hipError_t launch_anneal(int KT, int q, const AnnealArgs &a, hipStream_t s)
 hipError_t launch_select(const SelectArgs &a, hipStream_t s)
 {
     if (a.n_inst <= 0) return hipSuccess;
-    if (a.KT > 32 || a.K > a.KT) return hipErrorInvalidValue;   // G of an instance in LDS
+    if (a.KT > 64 || a.K > a.KT) return hipErrorInvalidValue;   // G of an instance in LDS
+    if (a.mode == kSelectVpp && a.n_rows > 16) return hipErrorInvalidValue;
     const int blocks = (a.n_inst + kWavesPerBlock - 1) / kWavesPerBlock;
-    hipLaunchKernelGGL(k_select, dim3(blocks), dim3(kBlock), 0, s, a);
+    if (a.KT <= 32)
+        hipLaunchKernelGGL(k_select<32>, dim3(blocks), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_select<64>, dim3(blocks), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
@@ -2293,6 +2340,8 @@ hipError_t launch_delta_prep(const DeltaPrepArgs &a, hipStream_t s)
         hipLaunchKernelGGL(k_delta_prep<16>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
     else if (a.KT == 32)
         hipLaunchKernelGGL(k_delta_prep<32>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+    else if (a.KT == 64)
+        hipLaunchKernelGGL(k_delta_prep<64>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
