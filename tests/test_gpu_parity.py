@@ -260,9 +260,13 @@ def test_invalid_arguments_raise(ctx):
         ctx.solve(dev(np.zeros((1, 4, 4), np.float32)), dev(np.zeros((1, 4), np.float32)), 4, 2,
                   [3, 1], 8, 4, b, 1)
     assert e.value.code == -4
-    big = W.det_slot(602, 4, 17, 4, 1, 1, 10.0)
+    big = W.det_slot(602, 4, 33, 4, 1, 1, 10.0)         # more than 32 users
     with pytest.raises(M.MmgapError) as e:
         ctx.detect(dev(big.H), dev(big.y), 4, 0.1, 8, 4, b, 1)
+    assert e.value.code == -4
+    big = W.det_slot(604, 4, 17, 64, 1, 1, 10.0)        # 17 users at 64-QAM: 204 spins
+    with pytest.raises(M.MmgapError) as e:
+        ctx.detect(dev(big.H), dev(big.y), 64, 0.1, 8, 4, b, 1)
     assert e.value.code == -4
 
 
