@@ -570,13 +570,37 @@ __device__ __forceinline__ float lane_level_energy(const float *Gl, const float 
                                                    const float (&x)[KT])
 {
     float E = 0.0f;
+    if constexpr (KT > 32) {
+        // Rows in chunks of 8 floats. Each chunk's loads wait for the previous
+        // chunk's products (a row's first chunk for the previous row's energy
+        // term) through a zero produced from that value, so that the unrolled
+        // loop keeps one chunk in flight and the kernel stays within 128
+        // registers; the sums are the same chains as below.
 #pragma unroll
-    for (int k = 0; k < KT; ++k) {
-        float acc = -fi[k];
+        for (int k = 0; k < KT; ++k) {
+            float acc = -fi[k];
 #pragma unroll
-        for (int l = 0; l < KT; ++l) acc = fmaf(Gl[k * KT + l], x[l], acc);
-        const float diff = acc - fi[k];
-        E = fmaf(x[k], diff, E);
+            for (int c0 = 0; c0 < KT; c0 += 8) {
+                int cz;
+                asm volatile("v_mov_b32 %0, 0" : "=v"(cz) : "v"(c0 == 0 ? E : acc));
+                const float4 *Gc = reinterpret_cast<const float4 *>(Gl) + cz;
+                const float4 v0 = Gc[(k * KT + c0) / 4], v1 = Gc[(k * KT + c0) / 4 + 1];
+                const float gr[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+                for (int l = 0; l < 8; ++l) acc = fmaf(gr[l], x[c0 + l], acc);
+            }
+            const float diff = acc - fi[k];
+            E = fmaf(x[k], diff, E);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < KT; ++k) {
+            float acc = -fi[k];
+#pragma unroll
+            for (int l = 0; l < KT; ++l) acc = fmaf(Gl[k * KT + l], x[l], acc);
+            const float diff = acc - fi[k];
+            E = fmaf(x[k], diff, E);
+        }
     }
     return E;
 }
@@ -639,7 +663,12 @@ __device__ __forceinline__ float anneal_lane(const float *Gl, const float *fi,
     }
     auto step_of = [&](int i) -> float {
         if constexpr (kBits) {
-            return ((sb[i >> 5] >> (i & 31)) & 1u) ? two_w[i % Q] : -two_w[i % Q];
+            uint32_t wd = sb[i >> 5];
+            // 64 dimensions: the word is read where the spin is tried, so that
+            // the steps of a sweep are not all decoded (into 128 registers) at
+            // its start
+            if constexpr (KT > 32) asm volatile("" : "+v"(wd));
+            return ((wd >> (i & 31)) & 1u) ? two_w[i % Q] : -two_w[i % Q];
         } else {
             return dv[i];
         }
@@ -674,11 +703,22 @@ __device__ __forceinline__ float anneal_lane(const float *Gl, const float *fi,
 #pragma unroll
             for (int c0 = 0; c0 < KT; c0 += kChunk) {
                 int coff = k * (KT / 4) + c0 / 4;
-                if (c0 > 0) asm volatile("" : "+v"(coff) : "v"(g));
+                const float4 *Gc = G4;
+                if constexpr (KT > 32) {
+                    // a zero made from g: the row offset stays a constant the
+                    // loads carry as their immediate (no register per chunk)
+                    if (c0 > 0) {
+                        int cz;
+                        asm volatile("v_mov_b32 %0, 0" : "=v"(cz) : "v"(g));
+                        Gc = G4 + cz;
+                    }
+                } else if (c0 > 0) {
+                    asm volatile("" : "+v"(coff) : "v"(g));
+                }
                 float grow[kChunk];
 #pragma unroll
                 for (int l4 = 0; l4 < kChunk / 4; ++l4) {
-                    const float4 v = G4[coff + l4];
+                    const float4 v = Gc[coff + l4];
                     grow[4 * l4 + 0] = v.x;
                     grow[4 * l4 + 1] = v.y;
                     grow[4 * l4 + 2] = v.z;
@@ -1141,34 +1181,63 @@ __global__ void __launch_bounds__(kBuildBlock) k_vpp_build(VppBuildArgs a)
 // wavefronts.  PACKED: one wavefront = 64 / glanes instances of glanes lanes
 // each (glanes a power of two >= chains, <= 32), all sharing one G -- the host
 // guarantees that 64 / glanes divides inst_per_G.  Each wavefront stages its
-// G in LDS.  Writes every chain's final energy and spin words.
-template <int KT, int Q>
+// G in LDS; with 64 dimensions (16 KB per G) the workgroup instead stages each
+// distinct G of its wavefronts once, in g_slots dynamic LDS slots, so that
+// four wavefronts per SIMD fit.  Writes every chain's final energy and spin
+// words.
+template <int KT, int Q, bool PACKED>
 constexpr int anneal_min_waves()
 {
-    return KT <= 8 ? 8 : KT == 16 ? (Q == 3 ? 4 : 6) : KT == 32 ? (Q == 1 ? 5 : 4) : 2;
+    return KT <= 8 ? 8 : KT == 16 ? (Q == 3 ? 4 : 6) : KT == 32 ? (Q == 1 ? 5 : 4)
+                                                                 : (PACKED ? 2 : 4);
 }
 template <int KT, int Q, bool PACKED>
 __global__ void __launch_bounds__(kBlock)
-    __attribute__((amdgpu_waves_per_eu(anneal_min_waves<KT, Q>(), 8)))
+    __attribute__((amdgpu_waves_per_eu(anneal_min_waves<KT, Q, PACKED>(), 8)))
 k_anneal(const float *__restrict__ G, int inst_per_G, const float *__restrict__ f,
          const signed char *__restrict__ x_fb, const float *__restrict__ beta2,
          const uint32_t *__restrict__ accept_table, int sweeps, int chains, int n_inst, int w0,
          int w1, int w2, int w3, uint32_t key0, uint32_t key1, int init_mode, int glanes,
-         float *__restrict__ chain_E, uint32_t *__restrict__ chain_S)
+         int g_slots, float *__restrict__ chain_E, uint32_t *__restrict__ chain_S)
 {
     constexpr int NW = (KT * Q + 31) / 32;
+    constexpr bool kSharedG = KT > 32;
     __shared__ uint32_t T[kAcceptSteps + 1];
-    __shared__ float4 Gw[kWavesPerBlock][KT * KT / 4];   // each wavefront's copy of its G
+    // each wavefront's copy of its G (fewer than 64 dimensions)
+    __shared__ float4 Gw[kSharedG ? 1 : kWavesPerBlock][kSharedG ? 1 : KT * KT / 4];
+    // 64 dimensions: g_slots copies, 16-byte aligned for the 128-bit row loads
+    extern __shared__ float4 anneal_gdyn4[];
+    float *anneal_gdyn = reinterpret_cast<float *>(anneal_gdyn4);
     for (int e = threadIdx.x; e <= kAcceptSteps; e += kBlock) T[e] = accept_table[e];
-    __syncthreads();
 
+    // the first instance of wavefront w and whether it has work
+    const int per_wave = PACKED ? 64 / glanes : 1;
+    const int wpi = PACKED ? 1 : (chains + 63) >> 6;
+    auto first_inst = [&](int w) { return PACKED ? w * per_wave : w / wpi; };
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int gw = blockIdx.x * kWavesPerBlock + wave;
+    int slot = 0;
+    if constexpr (kSharedG) {
+        // G ids of the block's wavefronts are non-decreasing: stage ids
+        // g0 .. g1 (the last wavefront with work), at most g_slots of them
+        const int gw0 = blockIdx.x * kWavesPerBlock;
+        const int g0 = first_inst(gw0) / inst_per_G;
+        int g1 = g0;
+        for (int w = 1; w < kWavesPerBlock; ++w) {
+            const int i0 = first_inst(gw0 + w);
+            if (i0 < n_inst) g1 = i0 / inst_per_G;
+        }
+        const int ns = min(g1 - g0 + 1, g_slots);
+        const float *Gb = G + (size_t)g0 * (KT * KT);
+        for (int e = threadIdx.x; e < ns * KT * KT; e += kBlock) anneal_gdyn[e] = Gb[e];
+        slot = __builtin_amdgcn_readfirstlane(first_inst(gw) / inst_per_G - g0);
+    }
+    __syncthreads();
+
     int inst, ch, inst0;
     bool valid = true;
     if constexpr (PACKED) {
-        const int per_wave = 64 / glanes;
         inst0 = gw * per_wave;
         if (inst0 >= n_inst) return;
         inst = inst0 + lane / glanes;
@@ -1178,16 +1247,21 @@ k_anneal(const float *__restrict__ G, int inst_per_G, const float *__restrict__ 
             inst = inst0;
         }
     } else {
-        const int wpi = (chains + 63) >> 6;
         inst = gw / wpi;
         if (inst >= n_inst) return;
         inst0 = inst;
         ch = (gw - inst * wpi) * 64 + lane;
     }
-    const float *Gi = G + (size_t)(inst0 / inst_per_G) * (KT * KT);
-    float *Gs = reinterpret_cast<float *>(Gw[wave]);
-    for (int e = lane; e < KT * KT; e += 64) Gs[e] = Gi[e];
-    wave_sync_lds();
+    float *Gs;
+    if constexpr (kSharedG) {
+        if (slot >= g_slots) return;        // the launcher's slot count covers every block
+        Gs = anneal_gdyn + (size_t)slot * (KT * KT);
+    } else {
+        const float *Gi = G + (size_t)(inst0 / inst_per_G) * (KT * KT);
+        Gs = reinterpret_cast<float *>(Gw[wave]);
+        for (int e = lane; e < KT * KT; e += 64) Gs[e] = Gi[e];
+        wave_sync_lds();
+    }
     const float *fi = f + (size_t)inst * KT;
     const signed char *xi = x_fb ? x_fb + (size_t)inst * KT : nullptr;
     const int wts[4] = {w0, w1, w2, w3};
@@ -2203,16 +2277,27 @@ hipError_t launch_anneal_t(const AnnealArgs &a, hipStream_t s)
     const size_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
     if (blocks == 0) return hipSuccess;
     if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    // 64 dimensions: LDS slots for the distinct G of a workgroup's wavefronts.
+    // Wavefront w takes G floor(w / wpg); four consecutive wavefronts span one
+    // G when wpg is a multiple of 4, four when wpg = 1, else at most two.
+    int g_slots = 0;
+    if (KT > 32) {
+        const size_t wpg = a.glanes > 0 ? (size_t)a.inst_per_G / per_wave
+                                        : (size_t)a.inst_per_G * ((a.chains + 63) / 64);
+        if (wpg == 0) return hipErrorInvalidValue;
+        g_slots = wpg % kWavesPerBlock == 0 ? 1 : (wpg == 1 ? kWavesPerBlock : 2);
+    }
+    const size_t lds = (size_t)g_slots * KT * KT * sizeof(float);
     if (a.glanes > 0)
-        hipLaunchKernelGGL((k_anneal<KT, Q, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
+        hipLaunchKernelGGL((k_anneal<KT, Q, true>), dim3((unsigned)blocks), dim3(kBlock), lds, s,
                            a.G, a.inst_per_G, a.f, a.x_fb, a.beta2, a.accept_table, a.sweeps,
                            a.chains, a.n_inst, a.w[0], a.w[1], a.w[2], a.w[3], a.key0, a.key1,
-                           a.init_mode, a.glanes, a.chain_E, a.chain_S);
+                           a.init_mode, a.glanes, g_slots, a.chain_E, a.chain_S);
     else
-        hipLaunchKernelGGL((k_anneal<KT, Q, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                           a.G, a.inst_per_G, a.f, a.x_fb, a.beta2, a.accept_table, a.sweeps,
+        hipLaunchKernelGGL((k_anneal<KT, Q, false>), dim3((unsigned)blocks), dim3(kBlock), lds,
+                           s, a.G, a.inst_per_G, a.f, a.x_fb, a.beta2, a.accept_table, a.sweeps,
                            a.chains, a.n_inst, a.w[0], a.w[1], a.w[2], a.w[3], a.key0, a.key1,
-                           a.init_mode, 0, a.chain_E, a.chain_S);
+                           a.init_mode, 0, g_slots, a.chain_E, a.chain_S);
     return hipGetLastError();
 }
 
