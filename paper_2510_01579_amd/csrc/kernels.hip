@@ -697,7 +697,7 @@ __device__ __forceinline__ float anneal_lane(const float *Gl, const float *fi,
             // local field of dimension k from the current levels; PACKED reads
             // the row in chunks of 8 floats, each issued after the previous
             // chunk's products (the per-lane field loads leave fewer registers)
-            constexpr int kChunk = PACKED || KT > 32 ? 8 : KT;
+            constexpr int kChunk = PACKED ? 8 : KT > 32 ? 16 : KT;
             float g = -fk;
             float gkk = 0.0f;
 #pragma unroll
