@@ -1651,12 +1651,18 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
                 const uint64_t o = ((uint64_t)hi << 32) | lo;
                 key = o < key ? o : key;
             }
+            // the lane re-derived from a fresh thread index: values made from it
+            // before the anneal are not held (spilled) across it
+            // (32 spins and more; smaller problems keep fewer registers this way)
+            int tpost = threadIdx.x;
+            if constexpr (KT * Q >= 32) asm volatile("" : "+v"(tpost) : "v"(E));
+            const int lanep = KT * Q >= 32 ? (tpost & 63) : lane;
             const FusedPost p = fused_post(jp);
             const int stage = rfl(lds.stage);
             for (int g = 0; g < cnt; ++g) {
                 const int bch = rfl((int)__shfl((uint32_t)key, g << lg, 64));
                 const int wl = (g << lg) + bch;            // the group's winning lane
-                if (lane == wl) {
+                if (lanep == wl) {
                     for (int ww = 0; ww < NW; ++ww) sh.lvs[wave][ww] = (int)bits[ww];
                 }
                 wave_sync_lds();
@@ -1670,27 +1676,27 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
                 // detection couplings are exactly symmetric: column reads (lane-contiguous,
                 // no LDS bank conflicts) give the row's values
                 const float Efb =
-                    p.kind == 0 ? fallback_energy<true>(Gi, KT, p.K, fg, xg, sh.terms[wave], lane)
-                                : fallback_energy<false>(Gi, KT, p.K, fg, xg, sh.terms[wave], lane);
+                    p.kind == 0 ? fallback_energy<true>(Gi, KT, p.K, fg, xg, sh.terms[wave], lanep)
+                                : fallback_energy<false>(Gi, KT, p.K, fg, xg, sh.terms[wave], lanep);
                 const bool use_fb = energy_less(Efb, Ebest);
-                winning_levels(use_fb, xg, S, p.K, Q, p.w, sh.lvs[wave], lane);
+                winning_levels(use_fb, xg, S, p.K, Q, p.w, sh.lvs[wave], lanep);
                 if (p.stages > 0) {
                     apply_move<true>(sh.lvs[wave], p.xbase + (size_t)ng * KT, Gi, KT, p.K,
                                      p.ffull + (size_t)ng * p.ldf, (1 << p.dq) - 1, sh.cand[wave],
-                                     sh.terms[wave], lane);
+                                     sh.terms[wave], lanep);
                     if (stage == p.stages - 1)
                         decode_det(sh.lvs[wave], ng, sc, sym0 + first + g, p.n_sym, p.n_rows,
                                    p.n_cols, p.dq, p.c, lds.H, p.y, (unsigned char *)p.out0,
-                                   (float *)p.out1, lane);
+                                   (float *)p.out1, lanep);
                 } else if (p.kind == 0) {
                     decode_det(sh.lvs[wave], ng, sc, sym0 + first + g, p.n_sym, p.n_rows,
                                p.n_cols, Q, p.c, lds.H, p.y, (unsigned char *)p.out0,
-                               (float *)p.out1, lane);
+                               (float *)p.out1, lanep);
                 } else {
                     decode_vpp(sh.lvs[wave], ng, sc, sym0 + first + g, p.n_sym, p.n_rows,
                                p.n_cols, p.tau, lds.Z, lds.ldz, lds.H, p.y,
                                (signed char *)p.out0, (float2 *)p.out1, (float *)p.out2,
-                               sh.zsh[wave], lane);
+                               sh.zsh[wave], lanep);
                 }
                 wave_sync_lds();
             }
@@ -1720,12 +1726,18 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
         }
     }
     __syncthreads();
-    // selection and decode: descriptor fields re-read after the anneal
+    // selection and decode: descriptor fields re-read after the anneal, the lane
+    // from a fresh thread index (values made from it before the anneal are not
+    // held across it; 32 spins and more, smaller problems keep fewer registers
+    // this way)
+    int tpost = threadIdx.x;
+    if constexpr (KT * Q >= 32) asm volatile("" : "+v"(tpost));
+    const int lanep = KT * Q >= 32 ? (tpost & 63) : lane;
     const FusedPost p = fused_post(jp);
     const int r0 = wave / p.wpi;
     const int chunk = wave - r0 * p.wpi;
     const bool active = r0 < ns;
-    const int ch = chunk * 64 + lane;
+    const int ch = chunk * 64 + lanep;
     int bch = 0;
     if (active) {
         uint64_t best = ~0ull;
@@ -1750,25 +1762,25 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
     // detection couplings are exactly symmetric: column reads (lane-contiguous, no
     // LDS bank conflicts) give the row's values
     const float Efb =
-        p.kind == 0 ? fallback_energy<true>(Gi, KT, p.K, fi, xi, sh.terms[wave], lane)
-                    : fallback_energy<false>(Gi, KT, p.K, fi, xi, sh.terms[wave], lane);
+        p.kind == 0 ? fallback_energy<true>(Gi, KT, p.K, fi, xi, sh.terms[wave], lanep)
+                    : fallback_energy<false>(Gi, KT, p.K, fi, xi, sh.terms[wave], lanep);
     const bool use_fb = energy_less(Efb, Ebest);
-    winning_levels(use_fb, xi, S, p.K, Q, p.w, sh.lvs[wave], lane);
+    winning_levels(use_fb, xi, S, p.K, Q, p.w, sh.lvs[wave], lanep);
     const int sy = sym0 + r0;
     if (p.stages > 0) {
         apply_move<true>(sh.lvs[wave], p.xbase + (size_t)n * KT, Gi, KT, p.K,
                          p.ffull + (size_t)n * p.ldf, (1 << p.dq) - 1, sh.cand[wave],
-                         sh.terms[wave], lane);
+                         sh.terms[wave], lanep);
         if (rfl(lds.stage) == p.stages - 1)
             decode_det(sh.lvs[wave], n, sc, sy, p.n_sym, p.n_rows, p.n_cols, p.dq, p.c, lds.H,
-                       p.y, (unsigned char *)p.out0, (float *)p.out1, lane);
+                       p.y, (unsigned char *)p.out0, (float *)p.out1, lanep);
     } else if (p.kind == 0) {
         decode_det(sh.lvs[wave], n, sc, sy, p.n_sym, p.n_rows, p.n_cols, Q, p.c, lds.H, p.y,
-                   (unsigned char *)p.out0, (float *)p.out1, lane);
+                   (unsigned char *)p.out0, (float *)p.out1, lanep);
     } else {
         decode_vpp(sh.lvs[wave], n, sc, sy, p.n_sym, p.n_rows, p.n_cols, p.tau, lds.Z, lds.ldz,
                    lds.H, p.y, (signed char *)p.out0, (float2 *)p.out1, (float *)p.out2,
-                   sh.zsh[wave], lane);
+                   sh.zsh[wave], lanep);
     }
 }
 
