@@ -1188,7 +1188,7 @@ __global__ void __launch_bounds__(kBuildBlock) k_vpp_build(VppBuildArgs a)
 template <int KT, int Q, bool PACKED>
 constexpr int anneal_min_waves()
 {
-    return KT <= 8 ? 8 : KT == 16 ? (Q == 3 ? 4 : 6) : KT == 32 ? (Q == 1 ? 5 : 4)
+    return KT <= 8 ? 8 : KT == 16 ? (Q == 3 ? 4 : 6) : KT == 32 ? (Q == 1 || PACKED ? 5 : 4)
                                                                  : (PACKED ? 2 : 4);
 }
 template <int KT, int Q, bool PACKED>
