@@ -71,6 +71,12 @@ def test_build_32_users(ctx, n_r, n_t, qam, n_sc, n_sym):
     (64, 1, [1], 128, 12, 7, 3, True),
     (40, 2, [2, 1], 64, 10, 5, 1, False),     # K = 40 padded to 64
     (64, 2, [2, 1], 32, 8, 9, 9, True),
+    # the workgroup's LDS copies of G: packed 4 instances per wavefront, two G per
+    # workgroup, ragged last wavefront
+    (64, 2, [2, 1], 16, 8, 37, 8, True),
+    (64, 1, [1], 32, 10, 11, 2, False),       # packed 2 per wavefront, four G per workgroup
+    (64, 2, [2, 1], 64, 8, 10, 4, True),      # one G per workgroup, last G of 2 instances
+    (64, 1, [1], 192, 6, 3, 1, False),        # three wavefronts per G, across workgroups
 ])
 def test_solve_64_dimensions(ctx, K, q, w, chains, sweeps, n, ipg, fb):
     note(f"solve K={K} q={q} chains={chains} sweeps={sweeps} n={n}")
