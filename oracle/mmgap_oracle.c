@@ -309,6 +309,142 @@ int oracle_solve(int n, int K, int q, const signed char *w, const float *G, int 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Plain Metropolis reference (a quality reference, NOT a parity target).
+ *
+ * The same anneal as run_chain -- same sweep order, same initial spins, the
+ * same 16-bit draw m for every attempt -- but taken from the definitions, in
+ * float64, with none of the choices the chain contract above makes for speed:
+ *   g_k  = sum_l G_kl x_l - f_k, summed afresh at every attempt
+ *   dE   = E(x with s_i flipped) - E(x) = d (2 g_k + d G_kk),  d = -2 w_b s_i
+ *   accept iff dE <= 0 or u < 2^(-beta2_t dE) = exp(-beta_t dE),
+ *        u = (m + 1/2) / 2^16 (the draw's uniform, no table, z not quantised)
+ * and the candidates ranked by the float64 energy x^T G x - 2 f^T x (lowest
+ * chain index on ties; the fallback only if strictly lower).  Comparing its
+ * results with oracle_solve's over many instances measures what the tabulated
+ * acceptance (z floored to 1/64, probability up to 1.1% above 2^-z) and the
+ * float32 chain arithmetic change in the solution quality.                  */
+static double field_exact(int K, const float *G, const float *f, const double *x, int k)
+{
+    double acc = 0.0;
+    for (int l = 0; l < K; ++l) acc += (double)G[k * K + l] * x[l];
+    return acc - (double)f[k];
+}
+
+static double energy_exact(int K, const float *G, const float *f, const double *x)
+{
+    double e = 0.0;
+    for (int k = 0; k < K; ++k) {
+        double gx = 0.0;
+        for (int l = 0; l < K; ++l) gx += (double)G[k * K + l] * x[l];
+        e += x[k] * gx - 2.0 * (double)f[k] * x[k];
+    }
+    return e;
+}
+
+static double run_chain_exact(int K, int q, const signed char *w, const float *G, const float *f,
+                              const signed char *xfb, int sweeps, const float *beta2,
+                              const uint32_t key[2], uint32_t inst, uint32_t ch, int init_mode,
+                              signed char *s, double *x)
+{
+    const int N = K * q;
+    if (init_mode == 1 && xfb != NULL) {
+        for (int k = 0; k < K; ++k) spins_from_level(q, w, (int)xfb[k], s + k * q);
+    } else {
+        for (int i = 0; i < N; ++i) {
+            uint32_t d = draw16((uint32_t)i, 0xFFFFFFFFu, ch, inst, key);
+            s[i] = (d & 0x8000u) ? -1 : 1;
+        }
+    }
+    for (int k = 0; k < K; ++k) {
+        int lv = 0;
+        for (int b = 0; b < q; ++b) lv += (int)w[b] * (int)s[k * q + b];
+        x[k] = (double)lv;
+    }
+    for (int t = 0; t < sweeps; ++t) {
+        const double b2 = (double)beta2[t];
+        for (int k = 0; k < K; ++k) {
+            const double gkk = (double)G[k * K + k];
+            for (int b = 0; b < q; ++b) {
+                const int i = k * q + b;
+                const double d = (double)(-2 * (int)w[b] * (int)s[i]);
+                const double g = field_exact(K, G, f, x, k);
+                const double dE = d * (2.0 * g + d * gkk);
+                const uint32_t m = draw16((uint32_t)i, (uint32_t)t, ch, inst, key);
+                const double u = ((double)m + 0.5) / 65536.0;
+                if (dE <= 0.0 || u < exp2(-b2 * dE)) {
+                    s[i] = (signed char)(-s[i]);
+                    x[k] += d;
+                }
+            }
+        }
+    }
+    return energy_exact(K, G, f, x);
+}
+
+/* oracle_solve_exact: as oracle_solve (same arguments and layouts) with the
+ * plain reference chain above; e_out holds float64 energies.               */
+int oracle_solve_exact(int n, int K, int q, const signed char *w, const float *G, int inst_per_G,
+                       long g_base, const float *f, const signed char *x_fb,
+                       const uint32_t *inst_ids, int chains, int sweeps, const float *beta2,
+                       uint64_t seed, int init_mode, signed char *spins_out, double *e_out,
+                       int *win_out, int nthreads)
+{
+    if (n < 0 || K <= 0 || q <= 0 || chains <= 0 || sweeps < 0 || inst_per_G <= 0) return -1;
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    const int N = K * q;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    int bad = 0;
+#pragma omp parallel
+    {
+        signed char *s = (signed char *)malloc((size_t)N);
+        signed char *sbest = (signed char *)malloc((size_t)N);
+        double *x = (double *)malloc(sizeof(double) * (size_t)K);
+        if (!s || !sbest || !x) {
+#pragma omp atomic write
+            bad = 1;
+        } else {
+#pragma omp for schedule(dynamic, 4)
+            for (int idx = 0; idx < n; ++idx) {
+                const uint32_t inst = inst_ids ? inst_ids[idx] : (uint32_t)idx;
+                const long gi = (long)(inst / (uint32_t)inst_per_G) - g_base;
+                const float *Gi = G + (size_t)gi * (size_t)K * (size_t)K;
+                const float *fi = f + (size_t)idx * (size_t)K;
+                const signed char *xi = x_fb ? x_fb + (size_t)idx * (size_t)K : NULL;
+                double ebest = 0.0;
+                int win = -1;
+                for (int ch = 0; ch < chains; ++ch) {
+                    const double e = run_chain_exact(K, q, w, Gi, fi, xi, sweeps, beta2, key,
+                                                     inst, (uint32_t)ch, init_mode, s, x);
+                    if (win < 0 || e < ebest) {
+                        ebest = e;
+                        win = ch;
+                        memcpy(sbest, s, (size_t)N);
+                    }
+                }
+                if (xi) {
+                    for (int k = 0; k < K; ++k) x[k] = (double)xi[k];
+                    const double efb = energy_exact(K, Gi, fi, x);
+                    if (efb < ebest) {
+                        ebest = efb;
+                        win = chains;
+                        for (int k = 0; k < K; ++k) spins_from_level(q, w, (int)xi[k], sbest + k * q);
+                    }
+                }
+                memcpy(spins_out + (size_t)idx * (size_t)N, sbest, (size_t)N);
+                e_out[idx] = ebest;
+                if (win_out) win_out[idx] = win;
+            }
+        }
+        free(s); free(sbest); free(x);
+    }
+    return bad ? -2 : 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* CIM-CAC anneals (paper §2.3, Eqs. cim1 and cim2; §3.2 "Matrix-Vector
  * Multiplication Optimization" and Appendix A for the integration).
  *

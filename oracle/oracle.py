@@ -77,6 +77,13 @@ def lib():
             ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
         L.oracle_solve.restype = ctypes.c_int
+        L.oracle_solve_exact.argtypes = [
+            ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,  # n K q w
+            ctypes.c_void_p, ctypes.c_int, ctypes.c_long,                # G inst_per_G g_base
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,           # f x_fb inst_ids
+            ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+        L.oracle_solve_exact.restype = ctypes.c_int
         L.oracle_level_energy.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.c_void_p]
         L.oracle_level_energy.restype = ctypes.c_float
@@ -294,6 +301,38 @@ def solve(G, f, K, q, w, chains, sweeps, beta2, seed, x_fb=None, inst_per_G=1,
     return out
 
 
+def solve_exact(G, f, K, q, w, chains, sweeps, beta2, seed, x_fb=None, inst_per_G=1,
+                inst_ids=None, init_mode=0, nthreads=0):
+    """Plain Metropolis reference anneals (a quality reference, not a parity
+    target): the anneal of ``solve`` -- same sweep order, initial spins and
+    16-bit draws m -- computed from the definitions in float64, accepting a
+    flip iff dE <= 0 or (m + 1/2)/2^16 < 2^(-beta2_t dE) exactly (no threshold
+    table, z not quantised), candidates ranked by the float64 energy.  Same
+    arguments as ``solve``; returns dict(spins, E float64, win)."""
+    G = np.ascontiguousarray(G, dtype=np.float32).reshape(-1, K, K)
+    f = np.ascontiguousarray(f, dtype=np.float32).reshape(-1, K)
+    n = f.shape[0]
+    w = np.ascontiguousarray(w, dtype=np.int8)
+    beta2 = np.ascontiguousarray(beta2, dtype=np.float32)
+    if w.shape != (q,) or beta2.shape != (sweeps,):
+        raise ValueError("w must have q entries and beta2 `sweeps` entries")
+    ids = None if inst_ids is None else np.ascontiguousarray(inst_ids, dtype=np.uint32)
+    if ids is not None and ids.shape != (n,):
+        raise ValueError("inst_ids must have one entry per instance")
+    if x_fb is not None:
+        x_fb = np.ascontiguousarray(x_fb, dtype=np.int8).reshape(n, K)
+    spins = np.zeros((n, K * q), dtype=np.int8)
+    E = np.zeros(n, dtype=np.float64)
+    win = np.zeros(n, dtype=np.int32)
+    rc = lib().oracle_solve_exact(n, K, q, _ptr(w), _ptr(G), int(inst_per_G), 0, _ptr(f),
+                                  _ptr(x_fb), _ptr(ids), int(chains), int(sweeps), _ptr(beta2),
+                                  int(seed) & 0xFFFFFFFFFFFFFFFF, int(init_mode), _ptr(spins),
+                                  _ptr(E), _ptr(win), int(nthreads))
+    if rc != 0:
+        raise RuntimeError(f"oracle_solve_exact failed ({rc})")
+    return dict(spins=spins, E=E, win=win)
+
+
 # CIM-CAC model parameters (paper §2.3 Eqs. cim1/cim2, Appendix A): the
 # integration step and coupling refresh period are the paper's choice
 # (dt = 0.02, f_mvm = 2, 128 steps = the 2.56 time units of its reference
@@ -461,6 +500,29 @@ def detect(H, y, noise_var, qam, chains, sweeps, beta2, seed, inst_ids=None,
     metric = det_metric(H_sel, y_sel, lv, qam)
     res.update(sym=levels_to_symbols(lv, qam), metric=metric, levels=lv, inst_ids=ids,
                x_fb=x_fb_all[ids])
+    return res
+
+
+def detect_exact(H, y, noise_var, qam, chains, sweeps, beta2, seed, inst_ids=None,
+                 init_mode=0, nthreads=0):
+    """``detect`` with the plain float64 Metropolis reference anneals of
+    ``solve_exact`` in place of the chain contract (same build, fallback,
+    draws and decode).  A quality reference for the tabulated acceptance."""
+    n_sc, n_sym, n_r = y.shape
+    n_t = H.shape[-1]
+    K, q = 2 * n_t, qam_bits(qam)
+    w = det_weights(qam)
+    G, f_all = det_ising(H, y, qam)
+    x_fb_all = slice_levels(mmse(H, y, noise_var), qam).reshape(-1, K)
+    ids = np.arange(n_sc * n_sym, dtype=np.uint32) if inst_ids is None \
+        else np.asarray(inst_ids, dtype=np.uint32)
+    res = solve_exact(G, f_all[ids], K, q, w, chains, sweeps, beta2, seed, x_fb=x_fb_all[ids],
+                      inst_per_G=n_sym, inst_ids=ids, init_mode=init_mode, nthreads=nthreads)
+    lv = levels_from_spins(res["spins"], K, q, w).astype(np.int8)
+    sc = ids // n_sym
+    sy = ids % n_sym
+    metric = det_metric(H[sc], y[sc, sy][:, None, :], lv, qam)
+    res.update(sym=levels_to_symbols(lv, qam), metric=metric, levels=lv, inst_ids=ids)
     return res
 
 
