@@ -17,9 +17,19 @@
  *    throws across this boundary.  Host-side checks (shapes, NULL pointers,
  *    unsupported sizes) fail before anything is enqueued; a device fault or a
  *    failed launch is reported as MMGAP_EDEVICE.
- *  * Instance numbering: problem instance n = sc * n_sym + sym.  The Philox
- *    stream of every chain is keyed by (schedule.seed, n, chain, sweep, spin),
- *    so results do not depend on how instances are grouped into launches.
+ *  * Instance numbering: problem instance n = sc * n_sym + sym of a call.  The
+ *    Philox stream of every chain is keyed by (schedule.seed, schedule.inst_base
+ *    + n, chain, sweep, spin), so results do not depend on how instances are
+ *    grouped into launches, and a call on subcarriers [a, b) of a slot with
+ *    inst_base = a * n_sym draws exactly the random numbers that a call on the
+ *    whole slot draws for them (paper §5.3: the subcarriers of a slot are split
+ *    over GPUs with no exchange between them).
+ *  * Sizes (MMGAP_EUNSUPPORTED outside them): DET n_tx <= 32 users, more than
+ *    16 users only with QPSK or 16-QAM, n_rx <= 64; VPP n_rx <= 16 users,
+ *    n_tx <= 64 antennas; n_sym <= 64; chains 1..1024; sweeps 1..8192.  The
+ *    entry points around MMSE-SIC need n_tx <= 16, CIM-CAC dynamics K q <= 32
+ *    spins (K padded to 8, 16 or 32), batches and the server K <= 32 and
+ *    chains <= 256.
  *  * A context must not be used by two host threads at once.
  *
  * Problem statement (paper §2.1 Eq. 1 and Eq. ml; §2.2; §3.3):
@@ -72,7 +82,8 @@ const char *mmgap_last_error(const mmgap_ctx *ctx);
 
 typedef struct {
     int kind;          /* MMGAP_KIND_DET or MMGAP_KIND_VPP */
-    int n_rx, n_tx;    /* H is n_rx x n_tx; DET: n_tx <= 16, n_rx <= 64; VPP: n_rx <= 16, n_tx <= 64 */
+    int n_rx, n_tx;    /* H is n_rx x n_tx; DET: n_tx <= 32 (more than 16 only with qam 4
+                          or 16), n_rx <= 64; VPP: n_rx <= 16, n_tx <= 64 */
     int qam;           /* 4, 16 or 64 */
     int n_sc, n_sym;   /* H is held per subcarrier for n_sym symbols; n_sym <= 64 */
     float noise_var;   /* DET: sigma^2 per complex receive sample (MMSE regulariser) */
@@ -112,6 +123,8 @@ typedef struct {
     int dynamics;          /* MMGAP_DYN_METROPOLIS (0, also for zero-initialised schedules) or
                               MMGAP_DYN_CIM (plain entry points only; K q <= 32 spins) */
     const mmgap_cim_params *cim;  /* (host) constants of MMGAP_DYN_CIM, else unused */
+    uint32_t inst_base;    /* Philox instance index of the call's instance 0 (0 for a whole
+                              slot; a * n_sym for a call on subcarriers [a, b) of it) */
 } mmgap_schedule;
 
 /*
@@ -144,8 +157,9 @@ int mmgap_build_ising(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H,
  * candidate ranked by its energy, the best candidate kept; a fallback
  * replaces it only when its energy is strictly lower.
  *   n_inst       number of instances (>= 0)
- *   K, q, w      structure: K <= 32 real dimensions, q <= 4 spins each,
- *                w (host) [q] int8 weights, each a power of two in 1..64
+ *   K, q, w      structure: K <= 64 real dimensions with q <= 4 spins each for
+ *                K <= 32 and q <= 2 for K > 32, w (host) [q] int8 weights, each a
+ *                power of two in 1..64
  *   G            [n_inst/inst_per_G rounded up][K][K] float32, symmetric; instance n uses
  *                G[n / inst_per_G]
  *   f            [n_inst][K] float32
@@ -160,11 +174,11 @@ int mmgap_build_ising(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H,
  * a flip of spin i changes x_k by d = -2 w_b s_i with dE = d ((g_k + g_k) + d G_kk),
  * z = beta2_t dE, and is accepted iff m < T[j], where m is the 16-bit Philox
  * draw of (spin i, sweep t, chain, instance n) -- Philox4x32-10 with counter
- * (i/8, t, chain, n) and key (seed_lo, seed_hi), low half of word (i%8)/2 for
+ * (i/8, t, chain, inst_base + n) and key (seed_lo, seed_hi), low half of word (i%8)/2 for
  * even i, high half for odd i --, j = floor(64 z) clamped to
  * [0, 1024] (z <= 0 or NaN gives 0) and T[j] = round(2^16 2^(-j/64)),
  * T[1024] = 0; on acceptance x_k += d and g_k = fma(G_kk, d, g_k).  Initial
- * spins: s_i = -1 iff bit 15 of the draw of (i, 0xffffffff, chain, n) is set.
+ * spins: s_i = -1 iff bit 15 of the draw of (i, 0xffffffff, chain, inst_base + n) is set.
  * Energies E = fma(x_K-1, g_K-1 - f_K-1, ... fma(x_0, g_0 - f_0, 0)) with
  * fresh fields.  Ties in energy keep the lowest chain index.
  * With sched->dynamics = MMGAP_DYN_CIM each anneal is instead `sweeps` Euler
@@ -180,7 +194,8 @@ int mmgap_build_ising(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H,
  *   e' = e + dt ((-zeta) ((s2 - a) e)), replaced by 2^-20 unless greater,
  * with p - 1 and -zeta rounded once in float32.  Random start: x_i = amp0 (u / 32768)
  * for the signed 16-bit value u = d - 32768 of the draw d of (i, 0xffffffff,
- * chain, n), x_a likewise from the draw of (0xfffffff8, 0xffffffff, chain, n);
+ * chain, inst_base + n), x_a likewise from the draw of (0xfffffff8, 0xffffffff,
+ * chain, inst_base + n);
  * fallback start: x_i = amp0 s_i of the fallback's spins, x_a = amp0.  Final
  * spin i is -1 iff (x_i < 0) differs from (x_a < 0); energies and selection as
  * above.
@@ -319,7 +334,8 @@ int mmgap_vpp_precode(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, 
  * Every output of a job is bit-identical to that of the single-job entry point
  * on the same arguments, whatever else is in the batch: a chain's random stream
  * depends only on the job's seed and its instance and chain index.
- * Limits: those of the single-job calls, and chains <= 256.
+ * Limits: those of the single-job calls, K <= 32 real dimensions (DET n_tx <=
+ * 16, VPP n_rx <= 16) and chains <= 256.
  */
 typedef struct {
     mmgap_problem prob;
@@ -368,7 +384,9 @@ int mmgap_plan_destroy(mmgap_plan *plan);
  * order while room in its HBM arena and a free in-flight slot allow, launches
  * each admitted group of jobs as one batch of the persistent fused kernels on
  * its own stream, so that batches overlap on the device, and observes their
- * completion.  Jobs submitted while others run are admitted as soon as slots
+ * completion.  A batch's launches are recorded as a HIP graph and replayed;
+ * each in-flight slot keeps its executable graph and updates it in place while
+ * batches launch the same kernel classes.  Jobs submitted while others run are admitted as soon as slots
  * and memory free up.  Every job's outputs equal those of the single-job entry
  * points (the Philox streams do not depend on batching).  Inputs and outputs
  * stay on the device; the server keeps the job's pointers until the job is

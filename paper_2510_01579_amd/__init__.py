@@ -68,7 +68,7 @@ class Schedule(ctypes.Structure):
     _fields_ = [("chains", ctypes.c_int), ("sweeps", ctypes.c_int),
                 ("beta2", ctypes.POINTER(ctypes.c_float)), ("seed", ctypes.c_uint64),
                 ("init", ctypes.c_int), ("dynamics", ctypes.c_int),
-                ("cim", ctypes.POINTER(CimParams))]
+                ("cim", ctypes.POINTER(CimParams)), ("inst_base", ctypes.c_uint32)]
 
 
 DYN_METROPOLIS, DYN_CIM = 0, 1
@@ -197,7 +197,10 @@ _tuned_cache = {}
 def tuned_schedule(kind: int, n_rx: int, n_tx: int, qam: int, noise_var: float = 0.0,
                    table: str = TUNED_TABLE) -> dict:
     """Schedule picked by the offline tuner (``python -m paper_2510_01579_amd.tune``)
-    for a job: dict(chains, sweeps, init, beta2, tuned, snr_bucket).
+    for a job: dict(chains, sweeps, init, beta2, stages, tuned, snr_bucket);
+    stages >= 1 (detection only) selects moves around the MMSE guess with that
+    many stages (``det_job(..., stages=)``, ``detect_delta``), 0 the binary
+    encoding.
 
     Detection tables are bucketed by SNR = 10 log10(n_tx / noise_var) (per
     receive antenna, unit-energy symbols): the job takes the bucket of the
@@ -238,7 +241,7 @@ def tuned_schedule(kind: int, n_rx: int, n_tx: int, qam: int, noise_var: float =
     return dict(chains=int(sched["chains"]), sweeps=int(sched["sweeps"]),
                 init=int(sched["init"]), beta2=linear_beta2(int(sched["sweeps"]),
                                                             min(start, end), end),
-                tuned=tuned, snr_bucket=bucket)
+                stages=int(sched.get("stages", 0)), tuned=tuned, snr_bucket=bucket)
 
 
 class Context:
@@ -300,17 +303,20 @@ class Context:
         return t
 
     @staticmethod
-    def _schedule(chains, sweeps, beta2, seed, init, cim=None):
+    def _schedule(chains, sweeps, beta2, seed, init, cim=None, inst_base=0):
         """A Schedule and the host objects it points to (keep them alive).  cim:
         None for Metropolis anneals, else a dict of CIM-CAC constants (missing
         keys from CIM_DEFAULTS; `sweeps` is then the number of Euler steps and
-        beta2 may be None)."""
+        beta2 may be None).  inst_base: Philox instance index of instance 0."""
+        ib = int(inst_base)
+        if not 0 <= ib <= 0xFFFFFFFF:
+            raise ValueError("inst_base must fit in 32 bits")
         if cim is None:
             b = np.ascontiguousarray(np.asarray(beta2, dtype=np.float32).reshape(-1))
             if b.size != sweeps:
                 raise ValueError(f"beta2 must have {sweeps} entries (got {b.size})")
             s = Schedule(int(chains), int(sweeps), b.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
-                         int(seed) & 0xFFFFFFFFFFFFFFFF, int(init), DYN_METROPOLIS, None)
+                         int(seed) & 0xFFFFFFFFFFFFFFFF, int(init), DYN_METROPOLIS, None, ib)
             return s, b
         P = dict(CIM_DEFAULTS)
         unknown = set(cim) - set(P)
@@ -320,7 +326,7 @@ class Context:
         c = CimParams(float(P["dt"]), int(P["f_mvm"]), float(P["p"]), float(P["a"]),
                       float(P["zeta"]), float(P["eps"]), float(P["amp0"]))
         s = Schedule(int(chains), int(sweeps), None, int(seed) & 0xFFFFFFFFFFFFFFFF, int(init),
-                     DYN_CIM, ctypes.pointer(c))
+                     DYN_CIM, ctypes.pointer(c), ib)
         return s, c
 
     def _problem(self, kind, H, y_or_u, qam, noise_var, tau):
@@ -361,7 +367,7 @@ class Context:
         return out
 
     def solve(self, G, f, K, q, w, chains, sweeps, beta2, seed, x_fallback=None, inst_per_G=1,
-              init=0, stream=None, cim=None):
+              init=0, stream=None, cim=None, inst_base=0):
         """Best of `chains` anneals per instance.  Returns (spins int8 [n][K q],
         energy float32 [n], winning chain int32 [n])."""
         torch = _torch()
@@ -378,7 +384,7 @@ class Context:
         spins = torch.empty((n, K * q), dtype=torch.int8, device=dev)
         E = torch.empty((n,), dtype=torch.float32, device=dev)
         win = torch.empty((n,), dtype=torch.int32, device=dev)
-        s, keep = self._schedule(chains, sweeps, beta2, seed, init, cim)
+        s, keep = self._schedule(chains, sweeps, beta2, seed, init, cim, inst_base)
         st = stream if stream is not None else _stream(dev)
         self._check(lib().mmgap_solve(self._h, n, K, q, wv, _ptr(G), int(inst_per_G), _ptr(f),
                                       _ptr(x_fallback), ctypes.byref(s), _ptr(spins), _ptr(E),
@@ -387,7 +393,7 @@ class Context:
         return spins, E, win
 
     def cim_chains(self, G, f, K, q, w, chains, steps, seed, cim=None, x_fallback=None,
-                   inst_per_G=1, init=0, stream=None):
+                   inst_per_G=1, init=0, stream=None, inst_base=0):
         """Every CIM-CAC anneal's final state (mmgap_cim_chains).  Returns (spins
         int8 [n][chains][K q], energy float32 [n][chains], diverged uint8
         [n][chains])."""
@@ -405,7 +411,8 @@ class Context:
         spins = torch.empty((n, chains, K * q), dtype=torch.int8, device=dev)
         E = torch.empty((n, chains), dtype=torch.float32, device=dev)
         div = torch.empty((n, chains), dtype=torch.uint8, device=dev)
-        s, keep = self._schedule(chains, steps, None, seed, init, {} if cim is None else cim)
+        s, keep = self._schedule(chains, steps, None, seed, init, {} if cim is None else cim,
+                                 inst_base)
         st = stream if stream is not None else _stream(dev)
         self._check(lib().mmgap_cim_chains(self._h, n, K, q, wv, _ptr(G), int(inst_per_G), _ptr(f),
                                            _ptr(x_fallback), ctypes.byref(s), _ptr(spins), _ptr(E),
@@ -414,7 +421,7 @@ class Context:
         return spins, E, div
 
     def detect(self, H, y, qam, noise_var, chains, sweeps, beta2, seed, init=0, metric=True,
-               stream=None, cim=None):
+               stream=None, cim=None, inst_base=0):
         """Uplink detection.  Returns (sym uint8 [n][n_tx], metric float32 [n] or None)."""
         torch = _torch()
         p = self._problem(KIND_DET, H, y, qam, noise_var, 0.0)
@@ -422,7 +429,7 @@ class Context:
         dev = self._dev()
         sym = torch.empty((n, p.n_tx), dtype=torch.uint8, device=dev)
         met = torch.empty((n,), dtype=torch.float32, device=dev) if metric else None
-        s, keep = self._schedule(chains, sweeps, beta2, seed, init, cim)
+        s, keep = self._schedule(chains, sweeps, beta2, seed, init, cim, inst_base)
         st = stream if stream is not None else _stream(dev)
         self._check(lib().mmgap_detect(self._h, ctypes.byref(p), _ptr(H), _ptr(y),
                                        ctypes.byref(s), _ptr(sym), _ptr(met), st))
@@ -430,7 +437,7 @@ class Context:
         return sym, met
 
     def detect_delta(self, H, y, qam, noise_var, chains, sweeps, beta2, seed, stages=1,
-                     guess=None, init=0, metric=True, stream=None, cim=None):
+                     guess=None, init=0, metric=True, stream=None, cim=None, inst_base=0):
         """Detection by moves around a guess (mmgap_detect_delta): `stages` anneals
         of the {-2, 0, 2}-move problem from the sliced MMSE estimate (or `guess`,
         int8 levels [n][2 n_tx]).  Returns (sym uint8 [n][n_tx], metric float32
@@ -443,7 +450,7 @@ class Context:
         dev = self._dev()
         sym = torch.empty((n, p.n_tx), dtype=torch.uint8, device=dev)
         met = torch.empty((n,), dtype=torch.float32, device=dev) if metric else None
-        s, keep = self._schedule(chains, sweeps, beta2, seed, init, cim)
+        s, keep = self._schedule(chains, sweeps, beta2, seed, init, cim, inst_base)
         st = stream if stream is not None else _stream(dev)
         self._check(lib().mmgap_detect_delta(self._h, ctypes.byref(p), _ptr(H), _ptr(y),
                                              ctypes.byref(s), int(stages), _ptr(guess),
@@ -470,7 +477,7 @@ class Context:
         return sym, met, lv, od
 
     def detect_e(self, H, y, qam, noise_var, chains, sweeps, beta2, seed, stages=1, init=0,
-                 metric=True, stream=None, cim=None, guesses=3):
+                 metric=True, stream=None, cim=None, guesses=3, inst_base=0):
         """MMGaP-E (mmgap_detect_e): stages of moves from the MMSE and from the
         MMSE-SIC guess, the better answer (`guesses` selects one chain or both).
         Returns (sym uint8 [n][n_tx], metric float32 [n] or None, from_sic uint8
@@ -482,7 +489,7 @@ class Context:
         sym = torch.empty((n, p.n_tx), dtype=torch.uint8, device=dev)
         met = torch.empty((n,), dtype=torch.float32, device=dev) if metric else None
         fs = torch.empty((n,), dtype=torch.uint8, device=dev)
-        s, keep = self._schedule(chains, sweeps, beta2, seed, init, cim)
+        s, keep = self._schedule(chains, sweeps, beta2, seed, init, cim, inst_base)
         st = stream if stream is not None else _stream(dev)
         self._check(lib().mmgap_detect_e(self._h, ctypes.byref(p), _ptr(H), _ptr(y),
                                          ctypes.byref(s), int(stages), int(guesses), _ptr(sym),
@@ -491,7 +498,7 @@ class Context:
         return sym, met, fs
 
     def vpp_precode(self, H, u, qam, chains, sweeps, beta2, seed, tau=0.0, want_x=True,
-                    want_gamma=True, init=0, stream=None, cim=None):
+                    want_gamma=True, init=0, stream=None, cim=None, inst_base=0):
         """Downlink VPP.  Returns (v int8 [n][2 n_rx], x complex64 [n][n_tx] or None,
         gamma float32 [n] or None)."""
         torch = _torch()
@@ -501,7 +508,7 @@ class Context:
         v = torch.empty((n, 2 * p.n_rx), dtype=torch.int8, device=dev)
         x = torch.empty((n, p.n_tx), dtype=torch.complex64, device=dev) if want_x else None
         g = torch.empty((n,), dtype=torch.float32, device=dev) if want_gamma else None
-        s, keep = self._schedule(chains, sweeps, beta2, seed, init, cim)
+        s, keep = self._schedule(chains, sweeps, beta2, seed, init, cim, inst_base)
         st = stream if stream is not None else _stream(dev)
         self._check(lib().mmgap_vpp_precode(self._h, ctypes.byref(p), _ptr(H), _ptr(u),
                                             ctypes.byref(s), _ptr(v), _ptr(x), _ptr(g), st))
@@ -510,7 +517,7 @@ class Context:
 
     # ------------------------------------------------------------------ batches
     def det_job(self, H, y, qam, noise_var, chains, sweeps, beta2, seed, init=0, metric=True,
-                stages=0):
+                stages=0, inst_base=0):
         """A detection job for ``plan_create`` with its output tensors allocated:
         outputs["sym"] uint8 [n][n_tx], outputs["metric"] float32 [n] or None.
         stages >= 1: detection by moves around the MMSE estimate (detect_delta)."""
@@ -520,14 +527,14 @@ class Context:
         dev = self._dev()
         out = dict(sym=torch.empty((n, p.n_tx), dtype=torch.uint8, device=dev),
                    metric=torch.empty((n,), dtype=torch.float32, device=dev) if metric else None)
-        s, keep = self._schedule(chains, sweeps, beta2, seed, init)
+        s, keep = self._schedule(chains, sweeps, beta2, seed, init, None, inst_base)
         job = Job(p, s, _ptr(H).value, _ptr(y).value, _ptr(out["sym"]).value,
                   None if out["metric"] is None else _ptr(out["metric"]).value, None,
                   int(stages))
         return dict(job=job, keep=(H, y, keep), outputs=out)
 
     def vpp_job(self, H, u, qam, chains, sweeps, beta2, seed, tau=0.0, want_x=True,
-                want_gamma=True, init=0):
+                want_gamma=True, init=0, inst_base=0):
         """A VPP job for ``plan_create``: outputs["v"] int8 [n][2 n_rx],
         outputs["x"] complex64 [n][n_tx] or None, outputs["gamma"] float32 [n] or None."""
         torch = _torch()
@@ -537,7 +544,7 @@ class Context:
         out = dict(v=torch.empty((n, 2 * p.n_rx), dtype=torch.int8, device=dev),
                    x=torch.empty((n, p.n_tx), dtype=torch.complex64, device=dev) if want_x else None,
                    gamma=torch.empty((n,), dtype=torch.float32, device=dev) if want_gamma else None)
-        s, keep = self._schedule(chains, sweeps, beta2, seed, init)
+        s, keep = self._schedule(chains, sweeps, beta2, seed, init, None, inst_base)
         job = Job(p, s, _ptr(H).value, _ptr(u).value, _ptr(out["v"]).value,
                   None if out["x"] is None else _ptr(out["x"]).value,
                   None if out["gamma"] is None else _ptr(out["gamma"]).value)

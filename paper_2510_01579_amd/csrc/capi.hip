@@ -276,6 +276,7 @@ int run_solver(mmgap_ctx *ctx, hipStream_t st, int n_inst, int K, int q, int KT,
     for (int b = 0; b < mmgap::kMaxQ; ++b) a.w[b] = w[b];
     a.key0 = (uint32_t)sched->seed;
     a.key1 = (uint32_t)(sched->seed >> 32);
+    a.inst_base = sched->inst_base;
     a.init_mode = sched->init;
     a.glanes = packed_lanes(sched->chains, inst_per_G, 64);
     a.chain_E = chainE;
@@ -378,6 +379,7 @@ int batch_layout(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, BatchLayout 
         else vpp_weights(f.w);
         f.key0 = (uint32_t)jb.sched.seed;
         f.key1 = (uint32_t)(jb.sched.seed >> 32);
+        f.inst_base = jb.sched.inst_base;
         f.c = qam_c(p.qam);
         f.c2 = qam_c2(p.qam);
         f.noise_var = (double)p.noise_var;
@@ -794,6 +796,7 @@ int mmgap_cim_chains(mmgap_ctx *ctx, int n_inst, int K, int q, const signed char
     for (int b = 0; b < mmgap::kMaxQ; ++b) a.w[b] = wv[b];
     a.key0 = (uint32_t)sched->seed;
     a.key1 = (uint32_t)(sched->seed >> 32);
+    a.inst_base = sched->inst_base;
     a.init_mode = sched->init;
     a.glanes = packed_lanes(sched->chains, inst_per_G, 64);
     a.chain_E = e_out ? e_out : at<float>(ctx, oE);
@@ -816,28 +819,40 @@ int mmgap_cim_chains(mmgap_ctx *ctx, int n_inst, int K, int q, const signed char
     return end_call(ctx, st);
 }
 
-int mmgap_detect(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, const void *y,
-                 const mmgap_schedule *sched, unsigned char *sym_out, float *metric_out,
-                 void *stream)
+}  // extern "C"
+
+namespace {
+
+// Scratch layout of one detection call (byte offsets from the scratch base).
+struct DetectScratch {
+    size_t oG, of, ox, oE, oS, bytes;
+};
+
+DetectScratch detect_scratch(const mmgap_problem *prob, const ProblemShape &sh,
+                             const mmgap_schedule *sched)
 {
-    if (!ctx) return MMGAP_EINVAL;
-    ProblemShape sh;
-    int rc = check_problem(ctx, prob, MMGAP_KIND_DET, &sh);
-    if (rc) return rc;
-    if ((rc = check_schedule(ctx, sched))) return rc;
-    if (sh.n_inst == 0) return MMGAP_OK;
-    if (!H || !y || !sym_out) return fail(ctx, MMGAP_EINVAL, "H, y and sym_out are required");
-    DeviceGuard g(ctx->device);
-    hipStream_t st = (hipStream_t)stream;
     const int KT = sh.KT, NW = mmgap::spin_words(KT, sh.q), ni = sh.n_inst;
     Bump plan;
-    const size_t oG = plan.take(sizeof(float) * (size_t)prob->n_sc * KT * KT);
-    const size_t of = plan.take(sizeof(float) * (size_t)ni * KT);
-    const size_t ox = plan.take((size_t)ni * KT);
-    const size_t oE = plan.take(sizeof(float) * (size_t)ni * sched->chains);
-    const size_t oS = plan.take(sizeof(uint32_t) * (size_t)ni * sched->chains * NW);
-    if ((rc = ensure_scratch(ctx, plan.off))) return rc;
-    if ((rc = begin_call(ctx, st))) return rc;
+    DetectScratch d;
+    d.oG = plan.take(sizeof(float) * (size_t)prob->n_sc * KT * KT);
+    d.of = plan.take(sizeof(float) * (size_t)ni * KT);
+    d.ox = plan.take((size_t)ni * KT);
+    d.oE = plan.take(sizeof(float) * (size_t)ni * sched->chains);
+    d.oS = plan.take(sizeof(uint32_t) * (size_t)ni * sched->chains * NW);
+    d.bytes = plan.off;
+    return d;
+}
+
+// The detection launches (build, anneal, select/decode) with every scratch
+// buffer at `base` (device memory of at least L.bytes bytes).
+int detect_launches(mmgap_ctx *ctx, hipStream_t st, const mmgap_problem *prob,
+                    const ProblemShape &sh, const DetectScratch &L, char *base, const void *H,
+                    const void *y, const mmgap_schedule *sched, unsigned char *sym_out,
+                    float *metric_out)
+{
+    const int KT = sh.KT, ni = sh.n_inst;
+    int rc = begin_call(ctx, st);
+    if (rc) return rc;
     prof_mark(ctx, 0, st);
     mmgap::DetBuildArgs b{};
     b.H = (const float2 *)H;
@@ -851,9 +866,9 @@ int mmgap_detect(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, const
     b.c = qam_c(prob->qam);
     b.c2 = qam_c2(prob->qam);
     b.noise_var = (double)prob->noise_var;
-    b.G = at<float>(ctx, oG);
-    b.f = at<float>(ctx, of);
-    b.x_fb = at<signed char>(ctx, ox);
+    b.G = reinterpret_cast<float *>(base + L.oG);
+    b.f = reinterpret_cast<float *>(base + L.of);
+    b.x_fb = reinterpret_cast<signed char *>(base + L.ox);
     b.ynorm = nullptr;
     hipError_t e = mmgap::launch_det_build(b, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "build launch");
@@ -870,9 +885,32 @@ int mmgap_detect(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, const
     sel.sym_out = sym_out;
     sel.metric_out = metric_out;
     rc = run_solver(ctx, st, ni, sh.K, sh.q, KT, w, b.G, prob->n_sym, b.f, b.x_fb, sched,
-                    at<float>(ctx, oE), at<uint32_t>(ctx, oS), sel);
+                    reinterpret_cast<float *>(base + L.oE),
+                    reinterpret_cast<uint32_t *>(base + L.oS), sel);
     if (rc) return rc;
     return end_call(ctx, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+int mmgap_detect(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, const void *y,
+                 const mmgap_schedule *sched, unsigned char *sym_out, float *metric_out,
+                 void *stream)
+{
+    if (!ctx) return MMGAP_EINVAL;
+    ProblemShape sh;
+    int rc = check_problem(ctx, prob, MMGAP_KIND_DET, &sh);
+    if (rc) return rc;
+    if ((rc = check_schedule(ctx, sched))) return rc;
+    if (sh.n_inst == 0) return MMGAP_OK;
+    if (!H || !y || !sym_out) return fail(ctx, MMGAP_EINVAL, "H, y and sym_out are required");
+    DeviceGuard g(ctx->device);
+    const DetectScratch L = detect_scratch(prob, sh, sched);
+    if ((rc = ensure_scratch(ctx, L.bytes))) return rc;
+    return detect_launches(ctx, (hipStream_t)stream, prob, sh, L, static_cast<char *>(ctx->scratch),
+                           H, y, sched, sym_out, metric_out);
 }
 
 namespace {

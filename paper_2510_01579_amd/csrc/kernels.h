@@ -64,6 +64,7 @@ struct AnnealArgs {
     int sweeps, chains, n_inst;
     int w[kMaxQ];           // spin weights (powers of two)
     uint32_t key0, key1;
+    uint32_t inst_base;     // Philox instance index of instance 0 of the launch
     int init_mode;
     int glanes;             // 0: one instance per wavefront (or several wavefronts per
                             // instance); else lanes per instance, a power of two in
@@ -190,6 +191,7 @@ struct FusedJob {
     int ldf;                // row stride of f in floats: a multiple of 32 (128 bytes), >= KT
     int w[kMaxQ];
     uint32_t key0, key1;
+    uint32_t inst_base;     // Philox instance index of the job's instance 0
     double c, c2, noise_var, tau;
     const float2 *H;
     const float2 *y;        // y (DET) or u (VPP)

@@ -1197,8 +1197,9 @@ __global__ void __launch_bounds__(kBlock)
 k_anneal(const float *__restrict__ G, int inst_per_G, const float *__restrict__ f,
          const signed char *__restrict__ x_fb, const float *__restrict__ beta2,
          const uint32_t *__restrict__ accept_table, int sweeps, int chains, int n_inst, int w0,
-         int w1, int w2, int w3, uint32_t key0, uint32_t key1, int init_mode, int glanes,
-         int g_slots, float *__restrict__ chain_E, uint32_t *__restrict__ chain_S)
+         int w1, int w2, int w3, uint32_t key0, uint32_t key1, uint32_t inst_base,
+         int init_mode, int glanes, int g_slots, float *__restrict__ chain_E,
+         uint32_t *__restrict__ chain_S)
 {
     constexpr int NW = (KT * Q + 31) / 32;
     constexpr bool kSharedG = KT > 32;
@@ -1266,10 +1267,14 @@ k_anneal(const float *__restrict__ G, int inst_per_G, const float *__restrict__ 
     const signed char *xi = x_fb ? x_fb + (size_t)inst * KT : nullptr;
     const int wts[4] = {w0, w1, w2, w3};
     uint32_t bits[NW];
+    // the Philox instance index is the only instance value kept across the
+    // anneal (hidden from the optimiser); the output row is re-derived from it
+    uint32_t ginst = (uint32_t)inst + inst_base;
+    asm volatile("" : "+v"(ginst));
     const float E = anneal_lane<KT, Q, PACKED>(Gs, fi, xi, beta2, T, sweeps, wts, key0, key1,
-                                               init_mode, (uint32_t)ch, (uint32_t)inst, bits);
+                                               init_mode, (uint32_t)ch, ginst, bits);
     if (valid && ch < chains) {
-        const size_t o = (size_t)inst * chains + ch;
+        const size_t o = (size_t)(ginst - inst_base) * chains + ch;
         chain_E[o] = E;
 #pragma unroll
         for (int w = 0; w < NW; ++w) chain_S[o * NW + w] = bits[w];
@@ -1284,8 +1289,8 @@ template <int KT, int Q, bool PACKED>
 __global__ void __launch_bounds__(kBlock)
 k_cim(const float *__restrict__ G, int inst_per_G, const float *__restrict__ f,
       const signed char *__restrict__ x_fb, CimParams prm, int steps, int chains, int n_inst,
-      int w0, int w1, int w2, int w3, uint32_t key0, uint32_t key1, int init_mode, int glanes,
-      float *__restrict__ chain_E, uint32_t *__restrict__ chain_S,
+      int w0, int w1, int w2, int w3, uint32_t key0, uint32_t key1, uint32_t inst_base,
+      int init_mode, int glanes, float *__restrict__ chain_E, uint32_t *__restrict__ chain_S,
       unsigned char *__restrict__ chain_div, int n_real)
 {
     constexpr int NW = (KT * Q + 31) / 32;
@@ -1321,10 +1326,12 @@ k_cim(const float *__restrict__ G, int inst_per_G, const float *__restrict__ f,
     const int wts[4] = {w0, w1, w2, w3};
     uint32_t bits[NW];
     bool div;
+    uint32_t ginst = (uint32_t)inst + inst_base;
+    asm volatile("" : "+v"(ginst));
     const float E = cim_lane<KT, Q, PACKED>(Gs, fi, xi, prm, steps, wts, key0, key1, init_mode,
-                                            (uint32_t)ch, (uint32_t)inst, bits, n_real, div);
+                                            (uint32_t)ch, ginst, bits, n_real, div);
     if (valid && ch < chains) {
-        const size_t o = (size_t)inst * chains + ch;
+        const size_t o = (size_t)(ginst - inst_base) * chains + ch;
         chain_E[o] = E;
 #pragma unroll
         for (int w = 0; w < NW; ++w) chain_S[o * NW + w] = bits[w];
@@ -1641,8 +1648,10 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
             const int n = sc * n_sym + sym0 + r;
             const float *fi = fbase + (size_t)n * ldf;
             const signed char *xi = delta ? sh.zmove : xbase + (size_t)n * KT;
+            // the Philox instance index of the whole slot
+            const uint32_t un = (uint32_t)n + rflu(jp->inst_base);
             E = anneal_lane<KT, Q, true>(Gi, fi, xi, beta2, sh.T, sweeps, w, key0, key1, init,
-                                         (uint32_t)chn, (uint32_t)n, bits);
+                                         (uint32_t)chn, un, bits);
             uint64_t key = ~0ull;
             if (valid && chn < chains) key = ((uint64_t)energy_key(E) << 32) | (uint32_t)chn;
             for (int off = gl >> 1; off >= 1; off >>= 1) {   // minimum within each group
@@ -1710,14 +1719,16 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
         const float *fi = fbase + (size_t)n * ldf;
         const signed char *xi = delta ? sh.zmove : xbase + (size_t)n * KT;
         if (active) {
+            // the Philox instance index of the whole slot (wave-uniform)
+            const uint32_t un = (uint32_t)n + rflu(jp->inst_base);
             // the move fields are rewritten at every stage, so they are read with
             // vector loads (the scalar cache is not updated by the stores)
             if (delta)
                 E = anneal_lane<KT, Q, true>(Gi, fi, xi, beta2, sh.T, sweeps, w, key0, key1, init,
-                                             (uint32_t)ch, (uint32_t)n, bits);
+                                             (uint32_t)ch, un, bits);
             else    // the row is wave-uniform (re-read from the first lane for the compiler)
                 E = anneal_lane<KT, Q, false>(Gi, uniform_ptr(fi), xi, beta2, sh.T, sweeps, w,
-                                              key0, key1, init, (uint32_t)ch, (uint32_t)n, bits);
+                                              key0, key1, init, (uint32_t)ch, un, bits);
             const int chains = rfl(jp->chains);
             uint64_t key = ~0ull;
             if (ch < chains) key = ((uint64_t)energy_key(E) << 32) | (uint32_t)ch;
@@ -2304,12 +2315,12 @@ hipError_t launch_anneal_t(const AnnealArgs &a, hipStream_t s)
         hipLaunchKernelGGL((k_anneal<KT, Q, true>), dim3((unsigned)blocks), dim3(kBlock), lds, s,
                            a.G, a.inst_per_G, a.f, a.x_fb, a.beta2, a.accept_table, a.sweeps,
                            a.chains, a.n_inst, a.w[0], a.w[1], a.w[2], a.w[3], a.key0, a.key1,
-                           a.init_mode, a.glanes, g_slots, a.chain_E, a.chain_S);
+                           a.inst_base, a.init_mode, a.glanes, g_slots, a.chain_E, a.chain_S);
     else
         hipLaunchKernelGGL((k_anneal<KT, Q, false>), dim3((unsigned)blocks), dim3(kBlock), lds,
                            s, a.G, a.inst_per_G, a.f, a.x_fb, a.beta2, a.accept_table, a.sweeps,
                            a.chains, a.n_inst, a.w[0], a.w[1], a.w[2], a.w[3], a.key0, a.key1,
-                           a.init_mode, 0, g_slots, a.chain_E, a.chain_S);
+                           a.inst_base, a.init_mode, 0, g_slots, a.chain_E, a.chain_S);
     return hipGetLastError();
 }
 
@@ -2329,13 +2340,13 @@ hipError_t launch_cim_t(const AnnealArgs &a, hipStream_t s)
     if (a.glanes > 0)
         hipLaunchKernelGGL((k_cim<KT, Q, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a.G,
                            a.inst_per_G, a.f, a.x_fb, a.cim, a.sweeps, a.chains, a.n_inst, a.w[0],
-                           a.w[1], a.w[2], a.w[3], a.key0, a.key1, a.init_mode, a.glanes,
-                           a.chain_E, a.chain_S, a.chain_div, a.n_real);
+                           a.w[1], a.w[2], a.w[3], a.key0, a.key1, a.inst_base, a.init_mode,
+                           a.glanes, a.chain_E, a.chain_S, a.chain_div, a.n_real);
     else
         hipLaunchKernelGGL((k_cim<KT, Q, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a.G,
                            a.inst_per_G, a.f, a.x_fb, a.cim, a.sweeps, a.chains, a.n_inst, a.w[0],
-                           a.w[1], a.w[2], a.w[3], a.key0, a.key1, a.init_mode, 0, a.chain_E,
-                           a.chain_S, a.chain_div, a.n_real);
+                           a.w[1], a.w[2], a.w[3], a.key0, a.key1, a.inst_base, a.init_mode, 0,
+                           a.chain_E, a.chain_S, a.chain_div, a.n_real);
     return hipGetLastError();
 }
 
