@@ -1,6 +1,12 @@
 """Offline schedule tuner: per job class and SNR bucket, the cheapest anneal
-schedule (chains, sweeps, start state, temperature shape) whose quality stays
-within a tolerance of the class's reference schedule at that SNR.
+schedule whose quality stays within a tolerance of the class's reference
+schedule at that SNR.  Two formulations compete for detection classes:
+
+* the binary encoding (paper §2.3 reduction with log2(M)/2 spins per real
+  dimension): chains, sweeps, start state, temperature shape;
+* moves around the MMSE guess (paper §2.3 Fig. 5, the Delta-Ising form; §3.2
+  stages each starting from the previous stage's answer): chains, sweeps per
+  stage and the number of stages, run as stages of the persistent kernel.
 
 A schedule is linear in beta from beta_start to beta_end.  The reference shape
 is the class's default range (beta0, beta1) of ``workload.synth``; a shape
@@ -61,6 +67,10 @@ CLASSES = {
 }
 CHAINS = (4, 8, 16, 32, 64, 128)
 SWEEPS = (12, 25, 50, 100, 200, 400)
+# moves around the MMSE guess: chains, sweeps per stage, stages
+DELTA_CHAINS = (4, 8, 16, 32)
+DELTA_SWEEPS = (2, 4, 6, 8, 12, 16, 25)
+DELTA_STAGES = (1, 2, 3)
 SHAPES = ((0.0, 1.0), (1.0 / 16, 1.0), (1.0 / 4, 1.0), (1.0 / 16, 4.0))
 TOLERANCE = 0.05             # the requirement: quality within 5% of the reference
 SELECT_TOLERANCE = 0.03      # used when choosing, so that other slots (other channel
@@ -75,7 +85,9 @@ def shaped_range(b0: float, b1: float, shape) -> tuple[float, float]:
 
 
 def schedule_key(c) -> str:
-    C, S, init, shape = c
+    C, S, init, shape = c[:4]
+    if len(c) > 4 and c[4]:
+        return f"{C}x{S}x{c[4]}/delta"
     return f"{C}x{S}/{init}/{shape[0]:g},{shape[1]:g}"
 
 
@@ -94,19 +106,36 @@ def lanes_per_instance(chains: int) -> int:
     return 64 * math.ceil(chains / 64)
 
 
-def cost(name, chains, sweeps) -> float:
+def cost(name, chains, sweeps, stages=0) -> float:
+    """Lane-operations of one instance's anneals.  Moves around a guess anneal
+    two unit-weight spins per real dimension in each stage and add, per stage
+    and instance lane, the move fields and the two energies of the move's
+    acceptance (about 3 KT^2 operations)."""
     kind, rows, cols, qam = parse_class(name)
     K = 2 * (cols if kind == "det" else rows)
     q = {4: 1, 16: 2, 64: 3}[qam] if kind == "det" else 2
     KT = 8 if K <= 8 else (16 if K <= 16 else 32)
+    if stages:
+        per = lanes_per_instance(chains) * sweeps * KT * 2 * (18.5 + KT / 2)
+        return stages * (per + 3.0 * KT * KT * lanes_per_instance(chains))
     return lanes_per_instance(chains) * sweeps * KT * q * (18.5 + KT / q)
 
 
+def parse_key_of(t):
+    """The candidate tuple of a table entry's "tuned" record."""
+    return (t["chains"], t["sweeps"], t["init"], tuple(t["shape"]), t.get("stages", 0))
+
+
 def parse_key(key):
-    sched, init, shape = key.split("/")
+    """(chains, sweeps, init, shape, stages) of a schedule key."""
+    sched, rest = key.split("/", 1)
+    if rest == "delta":
+        C, S, st = (int(v) for v in sched.split("x"))
+        return C, S, 0, (0.0, 1.0), st
+    init, shape = rest.split("/")
     C, S = (int(v) for v in sched.split("x"))
     r, m = (float(v) for v in shape.split(","))
-    return C, S, int(init), (r, m)
+    return C, S, int(init), (r, m), 0
 
 
 def select(name, rec):
@@ -118,17 +147,20 @@ def select(name, rec):
     for r in rec["per_snr"]:
         ok = [parse_key(k) for k, v in r["cands"].items()
               if v <= (1 + SELECT_TOLERANCE) * r["ref"] + 2e-5]
-        best = min(ok, key=lambda c: (cost(name, c[0], c[1]), c[0], c[1], c[2], c[3]))
+        best = min(ok, key=lambda c: (cost(name, c[0], c[1], c[4]), c[4], c[0], c[1], c[2],
+                                      c[3]))
         buckets.append({"snr_db": r["snr_db"],
                         "tuned": {"chains": best[0], "sweeps": best[1], "init": best[2],
-                                  "shape": list(best[3])},
+                                  "shape": list(best[3]), "stages": best[4]},
                         "quality": r["cands"][schedule_key(best)], "ref_quality": r["ref"],
-                        "cost_ratio": ref_cost / cost(name, best[0], best[1])})
+                        "cost_ratio": ref_cost / cost(name, best[0], best[1], best[4])})
     return buckets
 
 
 def measure(ctx, name, snr, schedules, n_sc, n_sym, seed):
-    """Quality of each (chains, sweeps, init) on one synthetic slot."""
+    """Quality of each (chains, sweeps, init, shape, stages) on one synthetic
+    slot; stages > 0: moves around the MMSE guess (mmgap_detect_delta, whose
+    outputs the persistent kernel's stages reproduce bit for bit)."""
     import torch
     from workload import synth as W
     kind, rows, cols, qam = parse_class(name)
@@ -138,20 +170,24 @@ def measure(ctx, name, snr, schedules, n_sc, n_sym, seed):
         d = W.det_slot(seed, rows, cols, qam, n_sc, n_sym, snr)
         H, y = torch.from_numpy(d.H).to(dev), torch.from_numpy(d.y).to(dev)
         truth = torch.from_numpy(d.sym.reshape(n_sc * n_sym, cols)).to(dev)
-        for (C, S, init, shape) in schedules:
+        for (C, S, init, shape, st) in schedules:
             rng = shaped_range(*W.det_beta_range(qam, rows, d.noise_var), shape)
             beta2 = W.linear_beta2(S, *rng)
-            sym, _ = ctx.detect(H, y, qam, d.noise_var, C, S, beta2, W.job_seed(seed),
-                                init=init, metric=False)
-            out[(C, S, init, shape)] = float((sym != truth).float().mean().item())
+            if st:
+                sym, _ = ctx.detect_delta(H, y, qam, d.noise_var, C, S, beta2, W.job_seed(seed),
+                                          stages=st, init=init, metric=False)
+            else:
+                sym, _ = ctx.detect(H, y, qam, d.noise_var, C, S, beta2, W.job_seed(seed),
+                                    init=init, metric=False)
+            out[(C, S, init, shape, st)] = float((sym != truth).float().mean().item())
     else:
         s = W.vpp_slot(seed, rows, cols, qam, n_sc, n_sym)
         H, u = torch.from_numpy(s.H).to(dev), torch.from_numpy(s.u).to(dev)
-        for (C, S, init, shape) in schedules:
+        for (C, S, init, shape, _) in schedules:
             beta2 = W.linear_beta2(S, *shaped_range(*W.vpp_beta_range(qam, cols), shape))
             _, _, g = ctx.vpp_precode(H, u, qam, C, S, beta2, W.job_seed(seed), init=init,
                                       want_x=False)
-            out[(C, S, init, shape)] = float(g.double().mean().item())
+            out[(C, S, init, shape, 0)] = float(g.double().mean().item())
     return out
 
 
@@ -165,6 +201,9 @@ def main(argv=None) -> int:
     ap.add_argument("--seed", type=int, default=7000)
     ap.add_argument("--reselect", default=None,
                     help="recompute the choice from the measurements in this table (no GPU)")
+    ap.add_argument("--add-delta", action="store_true",
+                    help="measure only the moves-around-the-guess candidates of the detection "
+                         "classes and add them to the table in --out (same slots and seeds)")
     args = ap.parse_args(argv)
 
     if args.reselect:
@@ -177,8 +216,8 @@ def main(argv=None) -> int:
             rec.pop("tuned", None)
             rec.pop("cost_ratio", None)
             print(name, [(b["snr_db"], b["tuned"]["chains"], b["tuned"]["sweeps"],
-                          b["tuned"]["init"], b["tuned"]["shape"], round(b["cost_ratio"], 2))
-                         for b in rec["buckets"]])
+                          b["tuned"]["init"], b["tuned"]["shape"], b["tuned"].get("stages", 0),
+                          round(b["cost_ratio"], 2)) for b in rec["buckets"]])
         with open(args.out, "w") as fh:
             json.dump(table, fh, indent=1)
         return 0
@@ -192,13 +231,37 @@ def main(argv=None) -> int:
             old = json.load(fh)
         if old.get("slot") == table["slot"]:
             table["classes"].update(old.get("classes", {}))
+    if args.add_delta:
+        for name in args.classes:
+            if not name.startswith("det") or name not in table["classes"]:
+                continue
+            rec = table["classes"][name]
+            cands = [(C, S, 0, SHAPES[0], st) for C in DELTA_CHAINS for S in DELTA_SWEEPS
+                     for st in DELTA_STAGES]
+            t0 = time.time()
+            for k, r in enumerate(rec["per_snr"]):
+                q = measure(ctx, name, r["snr_db"], cands, args.n_sc, args.n_sym,
+                            args.seed + 17 * k)
+                r["cands"].update({schedule_key(c): v for c, v in q.items()})
+            rec["buckets"] = select(name, rec)
+            print(f"{name}: " + ", ".join(
+                f"{b['snr_db']} dB {schedule_key(parse_key_of(b['tuned']))} "
+                f"(x{b['cost_ratio']:.1f})" for b in rec["buckets"])
+                + f" ({time.time() - t0:.1f} s)", flush=True)
+            with open(args.out, "w") as fh:
+                json.dump(table, fh, indent=1)
+        ctx.close()
+        return 0
     for name in args.classes:
         spec = CLASSES[name]
-        ref = tuple(spec["ref"]) + (SHAPES[0],)
-        cands = sorted({(C, S, i, sh) for C in CHAINS for S in SWEEPS for i in (0, 1)
+        ref = tuple(spec["ref"]) + (SHAPES[0], 0)
+        cands = sorted({(C, S, i, sh, 0) for C in CHAINS for S in SWEEPS for i in (0, 1)
                         for sh in SHAPES
                         if cost(name, C, S) <= cost(name, ref[0], ref[1])} | {ref},
                        key=lambda s: (cost(name, s[0], s[1]), s))
+        if name.startswith("det"):
+            cands += [(C, S, 0, SHAPES[0], st) for C in DELTA_CHAINS for S in DELTA_SWEEPS
+                      for st in DELTA_STAGES]
         t0 = time.time()
         per_snr = []
         for k, snr in enumerate(spec["snr"]):

@@ -30,12 +30,17 @@ def test_every_choice_meets_the_selection_margin_and_is_not_dearer(table):
     for name, rec in table["classes"].items():
         ref = rec["reference"]
         for b, meas in zip(rec["buckets"], rec["per_snr"]):
-            key = T.schedule_key((b["tuned"]["chains"], b["tuned"]["sweeps"], b["tuned"]["init"],
-                                  tuple(b["tuned"]["shape"])))
-            q = meas["cands"][key]
+            cand = T.parse_key_of(b["tuned"])
+            q = meas["cands"][T.schedule_key(cand)]
             assert q <= (1 + table["select_tolerance"]) * meas["ref"] + 2e-5, (name, b)
-            assert T.cost(name, b["tuned"]["chains"], b["tuned"]["sweeps"]) <= \
+            assert T.cost(name, cand[0], cand[1], cand[4]) <= \
                 T.cost(name, ref["chains"], ref["sweeps"])
+            # no measured candidate within the margin is cheaper
+            for key, v in meas["cands"].items():
+                c = T.parse_key(key)
+                if v <= (1 + table["select_tolerance"]) * meas["ref"] + 2e-5:
+                    assert T.cost(name, c[0], c[1], c[4]) >= T.cost(name, cand[0], cand[1],
+                                                                    cand[4]), (name, key)
 
 
 def test_reselect_reproduces_the_table(table, tmp_path):
@@ -71,3 +76,24 @@ def test_unknown_class_gets_the_reference_schedule():
     assert not t["tuned"] and (t["chains"], t["sweeps"]) == (64, 200)
     t = M.tuned_schedule(M.KIND_DET, 12, 12, 64, 0.1)
     assert not t["tuned"] and (t["chains"], t["sweeps"], t["init"]) == (128, 400, 1)
+
+
+def test_schedule_keys_round_trip():
+    for c in [(64, 50, 1, (0.0, 1.0), 0), (16, 12, 0, (0.0, 1.0), 2),
+              (8, 4, 0, (0.0625, 4.0), 0)]:
+        assert T.parse_key(T.schedule_key(c)) == c
+
+
+def test_tuned_schedule_returns_the_stage_count(table):
+    """A bucket that chose moves around the MMSE guess hands its stage count to
+    plans and the server (0 for the binary encoding)."""
+    for name, rec in table["classes"].items():
+        kind, rows, cols, qam = T.parse_class(name)
+        for b in rec["buckets"]:
+            snr = b["snr_db"] if b["snr_db"] is not None else 0.0
+            nv = W.noise_var(snr, cols) if kind == "det" else 0.0
+            t = M.tuned_schedule(M.KIND_DET if kind == "det" else M.KIND_VPP, rows, cols, qam,
+                                 nv)
+            assert t["stages"] == b["tuned"].get("stages", 0), (name, b["snr_db"])
+            if t["stages"]:
+                assert kind == "det"
