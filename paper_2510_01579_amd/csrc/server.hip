@@ -1,7 +1,8 @@
 // Serving loop: a native thread that admits submitted jobs into an HBM arena
 // in arrival order, launches each admitted group as one batch of the
 // persistent fused kernels on one of several streams (batches overlap on the
-// device), and observes their completion.
+// device) -- each batch's launches recorded as a HIP graph and replayed -- and
+// observes their completion.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -41,6 +42,9 @@ struct ServerJob {
 
 struct Slot {
     hipStream_t stream = nullptr;
+    hipStream_t capture = nullptr;  // records the batch's launches (never executes them)
+    hipGraphExec_t exec = nullptr;  // the slot's executable graph, updated per batch
+    int exec_mask = -1;             // kernel classes the executable graph launches
     hipEvent_t done = nullptr;
     bool busy = false;
     size_t off = 0, bytes = 0;      // arena range of the running batch
@@ -93,6 +97,46 @@ void reap(mmgap_server *sv, Slot &sl, hipError_t result, Clock::time_point now)
     sl.busy = false;
 }
 
+// Records a batch's launches (the counter reset, then one persistent kernel
+// per class present) as a HIP graph and replays it on the slot's stream.  The
+// slot keeps its executable graph and updates it in place from the new
+// recording while the batch launches the same kernels (kernel arguments and
+// grid sizes change from batch to batch, the topology does not), so a batch
+// costs one update and one graph launch; otherwise it is instantiated anew.
+hipError_t enqueue_graph(mmgap_server *sv, Slot &sl, const BatchLaunch &bl)
+{
+    int mask = 0;
+    for (int c = 0; c < mmgap::kFusedClasses; ++c)
+        if (bl.count[c] > 0 && bl.blocks[c] > 0) mask |= 1 << c;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(sl.capture, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    const hipError_t el = batch_enqueue(bl, sv->ctx->accept_dev, sl.capture);
+    e = hipStreamEndCapture(sl.capture, &graph);
+    if (e == hipSuccess) e = el;
+    if (e == hipSuccess && sl.exec && sl.exec_mask == mask) {
+        hipGraphNode_t bad = nullptr;
+        hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+        if (hipGraphExecUpdate(sl.exec, graph, &bad, &res) != hipSuccess ||
+            res != hipGraphExecUpdateSuccess) {
+            (void)hipGetLastError();
+            (void)hipGraphExecDestroy(sl.exec);
+            sl.exec = nullptr;
+        }
+    } else if (sl.exec) {
+        (void)hipGraphExecDestroy(sl.exec);
+        sl.exec = nullptr;
+    }
+    if (e == hipSuccess && !sl.exec) {
+        e = hipGraphInstantiate(&sl.exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) sl.exec = nullptr;
+        sl.exec_mask = e == hipSuccess ? mask : -1;
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e == hipSuccess) e = hipGraphLaunch(sl.exec, sl.stream);
+    return e;
+}
+
 // Launches the first k pending jobs as one batch on slot `si`.  Returns false
 // (after completing the jobs with an error) if the batch could not be started.
 bool launch(mmgap_server *sv, int si, int k, size_t bytes, size_t off)
@@ -137,7 +181,7 @@ bool launch(mmgap_server *sv, int si, int k, size_t bytes, size_t off)
         }
         if (e == hipSuccess)
             e = hipMemcpyAsync(base, sl.staging, image.size(), hipMemcpyHostToDevice, sl.stream);
-        if (e == hipSuccess) e = batch_enqueue(bl, sv->ctx->accept_dev, sl.stream);
+        if (e == hipSuccess) e = enqueue_graph(sv, sl, bl);
         if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
     }
     if (rc != MMGAP_OK || e != hipSuccess) {
@@ -202,6 +246,8 @@ void server_free(mmgap_server *sv)
 {
     for (Slot &sl : sv->slots) {
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+        if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
+        if (sl.capture) (void)hipStreamDestroy(sl.capture);
         if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
         if (sl.staging) (void)hipHostFree(sl.staging);
@@ -275,6 +321,7 @@ int mmgap_server_start(mmgap_ctx *ctx, int max_inflight, size_t arena_bytes, int
     sv->slots.resize(max_inflight);
     for (Slot &sl : sv->slots) {
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.capture, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
     }
     if (e != hipSuccess) {
