@@ -1,21 +1,31 @@
 #!/usr/bin/env python3
 """Benchmark of the Ising hot path (ML-MIMO detection / VPP precoding) on one MI355X.
 
-A step is one 5G slot of every job of the workload through the whole path --
-Gram/field build, annealing, selection and decode -- on synthetic i.i.d.
-Rayleigh channels (inputs resident in HBM before the timed region).  Three legs
-run on the same inputs:
-  * plain: the per-size entry points (one build, anneal and select launch each)
-    at the workload's reference schedule -- the baseline;
+A step is one pass of the whole hot path -- Gram/field build, annealing,
+selection and decode -- over every slot of the workload, on synthetic i.i.d.
+Rayleigh channels (inputs resident in HBM before the timed region).  The
+default workload is the uplink 16x16 64-QAM slot (3276 subcarriers x 12
+symbols) at SNR 15, 20, 25 and 30 dB (common random numbers: the four slots
+share channels, symbols and noise draw); each slot is launched and timed on
+its own, so slot latencies are per slot.  Legs on the same inputs:
+  * plain: the per-size entry points (one build, anneal and select launch per
+    slot) at the workload's reference schedule -- the baseline;
   * fused: one persistent launch per slot (a batch plan replayed as a HIP
     graph) at the same schedule -- outputs must be identical to plain;
   * tuned: the fused launch at the schedules the offline tuner picked for each
-    job class (tuned_schedules.json), if it has them.
-The reported value is the tuned leg's throughput when its quality on this
-slot -- symbol error rate (detection) or mean transmit energy (VPP) -- is
-within 5% of the plain leg's, else the fused leg's ("at matched SER").  The
-JSON line also carries slot latency percentiles, the roofline position of the
-dominant kernel (VALU-bound) and the CPU oracle timed on a bounded sample.
+    job's class and SNR bucket -- the binary encoding or moves around the MMSE
+    guess in stages inside the persistent kernel;
+  * delta_separate: the tuned moves-around-the-guess schedules through the
+    multi-launch entry point (move fields, anneal, select per stage) -- must
+    give the tuned leg's bytes;
+  * beside them for detection: MMGaP-E (both guesses), MMSE-SIC alone, the
+    search from the MMSE-SIC guess, the critical path of one subcarrier alone
+    on the GPU, the build over 64 slots, and a bounded serving mix.
+The reported value is the fastest leg whose quality on every slot -- symbol
+error rate (detection) or mean transmit energy (VPP) -- is within 5% of the
+plain leg's ("at matched SER").  The JSON line also carries slot latency
+percentiles, the roofline position of the dominant kernel (VALU-bound) and
+the CPU oracle timed on a bounded sample.
 
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
 """
@@ -38,12 +48,14 @@ METRIC = "Ising solves/sec + p99 slot latency vs plain launch, at matched SER"
 # 32-bit VALU lane-operations per second: 256 CUs x 128 lane-ops per clock x 2.4 GHz,
 # the rate the published FP32 vector peak (157.3 TFLOP/s = 78.6 T FMA/s) implies
 PEAK_ALU_OPS = 256 * 128 * 2.4e9
+PEAK_HBM = 8.0e12
 
 N_SC, N_SYM = 3276, 12
+QUALITY_TOL = 0.05           # matched SER: within 5% of the plain leg's
 
 
-def _det(n_r, n_t, qam, chains, sweeps, snr, seed, init, n_sc=N_SC, n_sym=N_SYM, delta=None,
-         sic_delta=None):
+def _det(n_r, n_t, qam, chains, sweeps, snr, seed, init, n_sc=N_SC, n_sym=N_SYM,
+         delta=(16, 12, 1), sic_delta=(16, 2, 1)):
     return dict(kind="det", rows=n_r, cols=n_t, qam=qam, n_sc=n_sc, n_sym=n_sym, chains=chains,
                 sweeps=sweeps, snr=snr, seed=seed, init=init, delta=delta, sic_delta=sic_delta)
 
@@ -53,22 +65,21 @@ def _vpp(n_u, n_t, qam, chains, sweeps, seed, n_sc=N_SC, n_sym=N_SYM):
                 sweeps=sweeps, snr=None, seed=seed, init=0)
 
 
+# Each workload is a list of groups; a group is one slot launch (its jobs share
+# the launch).  Reference schedules: 4x4 32x100, 8x8 64x200, 16x16 128x400;
+# 64-QAM anneals start from the MMSE fallback (random starts stay trapped with
+# binary weights).
 WORKLOADS = {
-    # the configuration the metric is quoted on: one slot, 8x8 16-QAM
-    "det-8x8-16qam": [_det(8, 8, 16, 64, 200, 15.0, 2001, 0)],
-    # 64-QAM anneals start from the MMSE fallback (random starts stay trapped)
-    # detection around the MMSE guess (paper §2.3 Delta-Ising form): 16 chains x 25
-    # sweeps, one stage -- the cheapest schedule whose SER beat the reference's by
-    # more than 5% on a tuning slot (seed 9101, 1200 instances, CPU oracle)
-    "det-16x16-64qam": [_det(16, 16, 64, 128, 400, 25.0, 3001, 1, delta=(16, 12, 1),
-                             sic_delta=(16, 2, 1))],
+    # the target configuration: 16x16 64-QAM slots over the SNR grid
+    "det-16x16-64qam": [[_det(16, 16, 64, 128, 400, s, 3001, 1)] for s in (15.0, 20.0, 25.0, 30.0)],
+    "det-8x8-16qam": [[_det(8, 8, 16, 64, 200, s, 2001, 0)] for s in (5.0, 10.0, 15.0, 20.0, 25.0)],
     # the paper's high-connectivity case: 32x32, 10 MHz at 30 kHz (24 resource
     # blocks = 288 subcarriers), 16-QAM, 128 anneals; plain path only (the
     # persistent kernel has no 64-dimension variant)
-    "det-32x32-16qam": [_det(32, 32, 16, 128, 100, 15.0, 3501, 0, n_sc=288)],
-    "det-4x4-qpsk": [_det(4, 4, 4, 32, 100, 10.0, 0, 0, n_sc=64, n_sym=1)],
+    "det-32x32-16qam": [[_det(32, 32, 16, 128, 100, 15.0, 3501, 0, n_sc=288)]],
+    "det-4x4-qpsk": [[_det(4, 4, 4, 32, 100, 10.0, 0, 0, n_sc=64, n_sym=1)]],
     # downlink VPP, two sizes batched in one launch
-    "vpp-8x8+16x16-16qam": [_vpp(8, 8, 16, 64, 200, 4001), _vpp(16, 16, 16, 128, 400, 4002)],
+    "vpp-8x8+16x16-16qam": [[_vpp(8, 8, 16, 64, 200, 4001), _vpp(16, 16, 16, 128, 400, 4002)]],
 }
 
 
@@ -77,7 +88,7 @@ def qbits(qam: int) -> int:
 
 
 def job_shape(j):
-    """(K, q, instances, flip attempts per slot) of a job."""
+    """(K, q, instances, flip attempts per slot) of a job at its reference schedule."""
     if j["kind"] == "det":
         K, q = 2 * j["cols"], qbits(j["qam"])
     else:
@@ -93,6 +104,18 @@ def ops_per_attempt(K: int, q: int) -> float:
     state update 4, and the per-visit field row K/q (K fused multiply-adds per
     dimension, shared by its q attempts)."""
     return 18.5 + K / q
+
+
+def sched_work(j, sc):
+    """(flip attempts, algorithmic lane operations) of one job's anneals under
+    schedule sc; moves around a guess anneal two unit-weight spins per real
+    dimension in each stage."""
+    K, q, n, _ = job_shape(j)
+    st = sc.get("stages", 0)
+    if st:
+        q = 2
+    a = float(n) * sc["chains"] * sc["sweeps"] * K * q * max(st, 1)
+    return a, a * ops_per_attempt(K, q)
 
 
 def levels_to_symbols(lv: np.ndarray, qam: int) -> np.ndarray:
@@ -164,7 +187,7 @@ def cpu_baseline(inputs, scheds, target_s: float, cim=None):
             if j["kind"] == "det" and sc.get("stages"):
                 O.detect_delta(inp["H"], inp["y"], inp["noise_var"], j["qam"], sc["chains"],
                                sc["sweeps"], sc["beta2"], inp["seed"], stages=sc["stages"],
-                               inst_ids=ids, cim=cim)
+                               inst_ids=ids, init_mode=sc["init"], cim=cim)
             elif j["kind"] == "det":
                 O.detect(inp["H"], inp["y"], inp["noise_var"], j["qam"], sc["chains"],
                          sc["sweeps"], sc["beta2"], inp["seed"], inst_ids=ids,
@@ -191,16 +214,15 @@ SERVE_DEADLINE_MS = 0.5      # one slot
 
 
 def serve_classes():
-    out = []
-    for kind in ("det", "vpp"):
-        for n in (8, 16):
-            for qam in (4, 16, 64):
-                out.append((kind, n, qam))
-    return out
+    return [(kind, n, qam) for kind in ("det", "vpp") for n in (8, 16) for qam in (4, 16, 64)]
 
 
-def run_serving(args, M, torch):
-    """Native serving loop on a Poisson stream of slot jobs (see SERVE_*)."""
+def serve_mix(M, torch, n_sat: int, n_arr: int, n_full: int):
+    """The native serving loop on a stream of slot jobs drawn from the mix, with
+    the tuner's schedules (moves around the MMSE guess where the tuner chose
+    them).  Three phases: every job queued at once (the sustainable slot rate),
+    Poisson arrivals at min(2000/s, 0.8 x sustainable), and a burst at the full
+    2000/s.  Latency = submission to observed completion."""
     from workload import synth as W
     rng = np.random.default_rng(5)
     dev = torch.device("cuda", 0)
@@ -231,22 +253,34 @@ def run_serving(args, M, torch):
         p = pool[(ci, int(rng.integers(2)))]
         sc = p["sched"]
         if kind == "det":
-            j = ctx.det_job(p["H"], p["y"], qam, p["nv"], sc["chains"], sc["sweeps"], sc["beta2"],
-                            W.job_seed(k), init=sc["init"], metric=False)
-        else:
-            j = ctx.vpp_job(p["H"], p["y"], qam, sc["chains"], sc["sweeps"], sc["beta2"],
-                            W.job_seed(k), want_x=False, want_gamma=False, init=sc["init"])
-        return j
+            return ctx.det_job(p["H"], p["y"], qam, p["nv"], sc["chains"], sc["sweeps"],
+                               sc["beta2"], W.job_seed(k), init=sc["init"], metric=False,
+                               stages=sc["stages"])
+        return ctx.vpp_job(p["H"], p["y"], qam, sc["chains"], sc["sweeps"], sc["beta2"],
+                           W.job_seed(k), want_x=False, want_gamma=False, init=sc["init"])
+
+    def arrivals(rate, n, base):
+        gaps = rng.exponential(1.0 / rate, size=n)
+        jobs = [draw_job(base + k) for k in range(n)]
+        torch.cuda.synchronize()
+        ids = []
+        t0 = time.perf_counter()
+        t_next = t0
+        for k in range(n):
+            t_next += gaps[k]
+            while time.perf_counter() < t_next:
+                pass
+            ids.append(ctx.server_submit(jobs[k]))
+        ctx.server_drain()
+        el = time.perf_counter() - t0
+        return np.array([ctx.server_poll(i)[1] for i in ids]) / 1e3, el
 
     ctx.server_start(max_inflight=3, arena_bytes=2 << 30)
     try:
-        # warmup
-        ids = [ctx.server_submit(draw_job(k)) for k in range(6)]
+        ids = [ctx.server_submit(draw_job(k)) for k in range(6)]       # warmup
         ctx.server_drain()
         for i in ids:
             ctx.server_poll(i)
-        # saturation: everything queued at once -> sustainable slot rate
-        n_sat = max(args.steps, 12)
         jobs = [draw_job(100 + k) for k in range(n_sat)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -256,66 +290,23 @@ def run_serving(args, M, torch):
         for i in ids:
             ctx.server_poll(i)
         sustainable = n_sat / makespan
-        # Poisson arrivals at the offered rate, capped below saturation so that
-        # the queue stays finite
         rate = min(SERVE_RATE, 0.8 * sustainable)
-        n_arr = max(args.steps * 2, 20)
-        gaps = rng.exponential(1.0 / rate, size=n_arr)
-        jobs = [draw_job(1000 + k) for k in range(n_arr)]
-        torch.cuda.synchronize()
-        ids = []
-        t0 = time.perf_counter()
-        t_next = t0
-        for k in range(n_arr):
-            t_next += gaps[k]
-            while time.perf_counter() < t_next:
-                pass
-            ids.append(ctx.server_submit(jobs[k]))
-        ctx.server_drain()
-        elapsed = time.perf_counter() - t0
-        lat = np.array([ctx.server_poll(i)[1] for i in ids]) / 1e3
-        # the full offered rate for a bounded burst (the queue grows when the
-        # rate exceeds the sustainable one; latencies then include the backlog)
-        n_full = max(args.steps, 20)
-        gaps = rng.exponential(1.0 / SERVE_RATE, size=n_full)
-        jobs = [draw_job(5000 + k) for k in range(n_full)]
-        torch.cuda.synchronize()
-        ids = []
-        t_next = time.perf_counter()
-        for k in range(n_full):
-            t_next += gaps[k]
-            while time.perf_counter() < t_next:
-                pass
-            ids.append(ctx.server_submit(jobs[k]))
-        ctx.server_drain()
-        lat_full = np.array([ctx.server_poll(i)[1] for i in ids]) / 1e3
+        lat, elapsed = arrivals(rate, n_arr, 1000)
+        lat_full, _ = arrivals(SERVE_RATE, n_full, 5000)
     finally:
         ctx.server_stop()
         ctx.close()
     return {
-        "metric": METRIC,
-        "value": sustainable * N_SC * N_SYM,
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": n_sat,
-        "warmup": 6,
-        "ms_per_step": 1e3 / sustainable,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {
-            "workload": "serving mix: slot jobs of 3276 subcarriers x 12 symbols, 60% uplink "
-                        "detection / 40% VPP, sizes 8x8 and 16x16, QPSK/16-QAM/64-QAM uniform, "
-                        "detection SNR uniform 5-30 dB, i.i.d. Rayleigh; tuned schedules",
-            "name": "serve-mix",
-            "path": "native serving loop: FIFO admission into an HBM arena, batches of the "
-                    "persistent fused kernels on 3 streams",
-        },
+        "workload": "slot jobs of 3276 subcarriers x 12 symbols, 60% uplink detection / 40% "
+                    "VPP, sizes 8x8 and 16x16, QPSK/16-QAM/64-QAM uniform, detection SNR "
+                    "uniform 5-30 dB, i.i.d. Rayleigh; tuned schedules (moves around the MMSE "
+                    "guess where the tuner chose them)",
+        "path": "native serving loop: FIFO admission into an HBM arena, batches of the "
+                "persistent fused kernels recorded as HIP graphs, on 3 streams",
         "sustainable_slots_per_s": sustainable,
+        "sustainable_solves_per_s": sustainable * N_SC * N_SYM,
+        "saturation_jobs": n_sat,
         "offered_slots_per_s": rate,
-        "target_slots_per_s": SERVE_RATE,
         "arrivals": n_arr,
         "arrival_window_s": elapsed,
         "p50_slot_ms": float(np.percentile(lat, 50)),
@@ -326,22 +317,35 @@ def run_serving(args, M, torch):
                            "p50_slot_ms": float(np.percentile(lat_full, 50)),
                            "p99_slot_ms": float(np.percentile(lat_full, 99)),
                            "frac_within_deadline": float(np.mean(lat_full <= SERVE_DEADLINE_MS))},
-        "roofline": None,
-        "cpu_baseline": None,
     }
 
 
-def build_bytes(j) -> float:
-    """Algorithmic HBM bytes of the plain build of one job: H and y (or u) in,
-    couplings [n_sc][KT][KT] float32, fields [n][KT] float32 and fallbacks
-    [n][KT] int8 out."""
-    K, q, n, _ = job_shape(j)
-    KT = 8 if K <= 8 else (16 if K <= 16 else 32)
-    n_rx = j["rows"]
-    n_tx = j["cols"]
-    h = j["n_sc"] * n_rx * n_tx * 8
-    y = n * n_rx * 8
-    return float(h + y + j["n_sc"] * KT * KT * 4 + n * KT * 4 + n * KT)
+def run_serving(args, M, torch):
+    """The serving mix as its own benchmark line (--workload serve-mix)."""
+    n_sat = max(args.steps, 12)
+    res = serve_mix(M, torch, n_sat, max(args.steps * 2, 20), max(args.steps, 20))
+    return {
+        "metric": METRIC, "value": res["sustainable_solves_per_s"], "unit": "solves/s",
+        "n_gpus": 1, "steps": n_sat, "warmup": 6,
+        "ms_per_step": 1e3 / res["sustainable_slots_per_s"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "serving mix: " + res["workload"], "name": "serve-mix",
+                   "path": res["path"]},
+        "p50_slot_ms": res["p50_slot_ms"], "p99_slot_ms": res["p99_slot_ms"],
+        "serve_mix": res, "roofline": None, "cpu_baseline": None,
+    }
+
+
+def build_bytes(j, n_sc=None) -> float:
+    """Algorithmic HBM bytes of the detection build of one job (unpadded
+    outputs, as mmgap_build_ising writes them): H and y in, couplings
+    [n_sc][K][K] float32, fields [n][K] float32 and fallbacks [n][K] int8 out."""
+    K = 2 * j["cols"]
+    n_sc = j["n_sc"] if n_sc is None else n_sc
+    n = n_sc * j["n_sym"]
+    h = n_sc * j["rows"] * j["cols"] * 8
+    y = n * j["rows"] * 8
+    return float(h + y + n_sc * K * K * 4 + n * K * 4 + n * K)
 
 
 def quality(inputs, outs):
@@ -356,6 +360,10 @@ def quality(inputs, outs):
         else:
             res.append(float(np.mean(o["gamma"].astype(np.float64))))
     return res
+
+
+def matched(q, ref):
+    return all(a <= (1.0 + QUALITY_TOL) * b + 2e-5 for a, b in zip(q, ref))
 
 
 def cim_ops_per_step(K: int, q: int, f_mvm: int) -> float:
@@ -375,7 +383,7 @@ def run_cim(args, M, torch):
     workload whose problems have at most 32 spins: `chains` anneals of
     M.CIM_STEPS Euler steps with the default constants, the Metropolis plain
     leg at the reference schedule beside it for quality."""
-    specs = WORKLOADS[args.workload]
+    specs = [j for g in WORKLOADS[args.workload] for j in g]
     for j in specs:
         K, q = job_shape(j)[:2]
         KT = 8 if K <= 8 else (16 if K <= 16 else 32)
@@ -464,21 +472,27 @@ def run_cim(args, M, torch):
     }
 
 
+def pct(lat):
+    lat = np.asarray(lat, np.float64)
+    return {"p50_slot_ms": float(np.percentile(lat, 50)),
+            "p99_slot_ms": float(np.percentile(lat, 99))}
+
+
 def main(argv=None) -> int:  # noqa: C901
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="det-8x8-16qam",
+    ap.add_argument("--workload", default="det-16x16-64qam",
                     choices=sorted(WORKLOADS) + ["serve-mix"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--dynamics", choices=("metropolis", "cim"), default="metropolis",
                     help="cim: time the CIM-CAC anneals on the plain path instead")
     ap.add_argument("--cim-chains", type=int, default=32, help="anneals per instance (cim)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain leg")
-    ap.add_argument("--no-tuned", action="store_true", help="skip the tuned leg")
-    ap.add_argument("--no-delta", action="store_true",
-                    help="skip the leg of detection around the MMSE guess")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip MMGaP-E, MMSE-SIC, critical path, 64-slot build, serving mix")
+    ap.add_argument("--no-serve", action="store_true", help="skip the bounded serving mix")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy three times, so that "
@@ -494,299 +508,345 @@ def main(argv=None) -> int:  # noqa: C901
     import torch
 
     import paper_2510_01579_amd as M
+    from workload import synth as W
 
     if args.dynamics == "cim":
         print(json.dumps(run_cim(args, M, torch)), flush=True)
         return 0
-
     if args.workload == "serve-mix":
         print(json.dumps(run_serving(args, M, torch)), flush=True)
         return 0
 
-    specs = WORKLOADS[args.workload]
+    groups = WORKLOADS[args.workload]
+    specs = [j for g in groups for j in g]
     inputs = make_inputs(specs)
+    gidx = []                                   # input indices of each group
+    k = 0
+    for g in groups:
+        gidx.append(list(range(k, k + len(g))))
+        k += len(g)
     dev = torch.device("cuda", 0)
     for inp in inputs:
         inp["H_d"] = torch.from_numpy(inp["H"]).to(dev)
         inp["y_d"] = torch.from_numpy(inp["y"]).to(dev)
     ctx = M.Context(0)
+    total_inst = sum(job_shape(i["spec"])[2] for i in inputs)
+    is_det = all(j["kind"] == "det" for j in specs)
+    print(f"[bench] workload {args.workload}: {len(groups)} slot launches per step, "
+          f"{total_inst} instances", file=sys.stderr, flush=True)
 
-    def timed(step, steps):
-        start = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-        stop = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    def timed(launch_group):
+        """W warmup steps, then K timed steps; one HIP event pair around each
+        group's launch on the current stream.  Returns (elapsed s, [K][G] ms)."""
+        for _ in range(args.warmup):
+            for gi in range(len(groups)):
+                launch_group(gi)
+        ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in groups] for _ in range(args.steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for k in range(steps):
-            start[k].record()
-            step()
-            stop[k].record()
+        for st in range(args.steps):
+            for gi in range(len(groups)):
+                ev[st][gi][0].record()
+                launch_group(gi)
+                ev[st][gi][1].record()
         torch.cuda.synchronize()
-        elapsed = time.perf_counter() - t0
-        return elapsed, np.array([a.elapsed_time(b) for a, b in zip(start, stop)])
+        el = time.perf_counter() - t0
+        lat = np.array([[a.elapsed_time(b) for a, b in row] for row in ev])
+        return el, lat
+
+    def leg_record(el, lat, q, extra=None):
+        rec = {"value": args.steps * total_inst / el, "unit": "solves/s",
+               "ms_per_step": el / args.steps * 1e3, **pct(lat.reshape(-1)),
+               "slot_ms_mean": [float(v) for v in lat.mean(axis=0)], "quality": q}
+        rec.update(extra or {})
+        return rec
+
+    def host_outs(outs):
+        return [{k: (None if t is None else t.cpu().numpy()) for k, t in o.items()}
+                for o in outs]
 
     def fused_leg(scheds):
-        """One plan over every job with the given (chains, sweeps, init, beta2
-        and, for detection around the MMSE guess, stages); the events bracket
-        exactly one plan launch (counter reset + persistent kernels) on the
-        current stream."""
-        jobs = []
-        for inp, sc in zip(inputs, scheds):
-            j = inp["spec"]
-            if j["kind"] == "det":
-                jobs.append(ctx.det_job(inp["H_d"], inp["y_d"], j["qam"], inp["noise_var"],
-                                        sc["chains"], sc["sweeps"], sc["beta2"], inp["seed"],
-                                        init=sc["init"], stages=sc.get("stages", 0)))
-            else:
-                jobs.append(ctx.vpp_job(inp["H_d"], inp["y_d"], j["qam"], sc["chains"],
-                                        sc["sweeps"], sc["beta2"], inp["seed"], init=sc["init"]))
-        plan = ctx.plan_create(jobs, graph=True)
-        info = plan.plan_info()
-        for _ in range(args.warmup):
-            plan.plan_launch()
-        el, lat = timed(plan.plan_launch, args.steps)
-        outs = [{k: (None if t is None else t.cpu().numpy()) for k, t in jb["outputs"].items()}
-                for jb in jobs]
-        plan.plan_destroy()
+        """One plan (HIP graph) per group with the given schedules per job."""
+        plans, jobs = [], []
+        for g in gidx:
+            gj = []
+            for i in g:
+                inp, sc, j = inputs[i], scheds[i], inputs[i]["spec"]
+                if j["kind"] == "det":
+                    gj.append(ctx.det_job(inp["H_d"], inp["y_d"], j["qam"], inp["noise_var"],
+                                          sc["chains"], sc["sweeps"], sc["beta2"], inp["seed"],
+                                          init=sc["init"], stages=sc.get("stages", 0)))
+                else:
+                    gj.append(ctx.vpp_job(inp["H_d"], inp["y_d"], j["qam"], sc["chains"],
+                                          sc["sweeps"], sc["beta2"], inp["seed"],
+                                          init=sc["init"]))
+            plans.append(ctx.plan_create(gj, graph=True))
+            jobs.extend(gj)
+        info = [p.plan_info() for p in plans]
+        el, lat = timed(lambda gi: plans[gi].plan_launch())
+        torch.cuda.synchronize()
+        outs = host_outs([jb["outputs"] for jb in jobs])
+        for p in plans:
+            p.plan_destroy()
         return el, lat, outs, info
 
-    ref_scheds = [dict(chains=i["spec"]["chains"], sweeps=i["spec"]["sweeps"],
-                       init=i["spec"]["init"], beta2=i["beta2"]) for i in inputs]
-    # jobs of more than 32 real dimensions run on the plain path only
-    fusable = all(job_shape(i["spec"])[0] <= 32 for i in inputs)
-    if fusable:
-        f_el, f_lat, fused_out, (n_items, n_blocks) = fused_leg(ref_scheds)
-    else:
-        f_el = f_lat = fused_out = None
-        n_items = n_blocks = None
-        if args.no_plain:
-            raise SystemExit("this workload runs on the plain path only; drop --no-plain")
+    def same_bytes(a, b, keys):
+        return all(x[k] is None and y[k] is None or x[k].tobytes() == y[k].tobytes()
+                   for x, y in zip(a, b) for k in keys if k in x and k in y)
 
-    total_inst = sum(job_shape(i["spec"])[2] for i in inputs)
+    ref_scheds = [dict(chains=i["spec"]["chains"], sweeps=i["spec"]["sweeps"],
+                       init=i["spec"]["init"], beta2=i["beta2"], stages=0) for i in inputs]
+    fusable = all(job_shape(j)[0] <= 32 for j in specs)
+    legs = {}
+
+    # ---- plain: per-size build, anneal and select launches, reference schedule
     plain = None
-    identical = None
-    q_plain = None
-    if not args.no_plain:
-        def plain_step():
+    q_ref = None
+    if not args.no_plain or not fusable:
+        def plain_group(gi):
             outs = []
-            for inp in inputs:
-                j = inp["spec"]
+            for i in gidx[gi]:
+                inp, j = inputs[i], inputs[i]["spec"]
                 if j["kind"] == "det":
-                    outs.append(ctx.detect(inp["H_d"], inp["y_d"], j["qam"], inp["noise_var"],
-                                           j["chains"], j["sweeps"], inp["beta2"], inp["seed"],
-                                           init=j["init"]))
+                    o = ctx.detect(inp["H_d"], inp["y_d"], j["qam"], inp["noise_var"],
+                                   j["chains"], j["sweeps"], inp["beta2"], inp["seed"],
+                                   init=j["init"])
+                    outs.append(dict(sym=o[0], metric=o[1]))
                 else:
-                    outs.append(ctx.vpp_precode(inp["H_d"], inp["y_d"], j["qam"], j["chains"],
-                                                j["sweeps"], inp["beta2"], inp["seed"]))
+                    o = ctx.vpp_precode(inp["H_d"], inp["y_d"], j["qam"], j["chains"],
+                                        j["sweeps"], inp["beta2"], inp["seed"])
+                    outs.append(dict(v=o[0], x=o[1], gamma=o[2]))
             return outs
 
-        for _ in range(args.warmup):
-            plain_step()
+        print("[bench] plain leg", file=sys.stderr, flush=True)
         ctx.set_profiling(True)
-        p_el, p_lat = timed(plain_step, args.steps)
-        prof = np.array(ctx.profile(args.steps * len(inputs))).reshape(args.steps, len(inputs), 3)
+        el, lat = timed(plain_group)
+        prof = np.array(ctx.profile(args.steps * len(specs))).reshape(args.steps, len(specs), 3)
         ctx.set_profiling(False)
-        outs = plain_step()
-        torch.cuda.synchronize()
-        identical = True if fusable else None
-        plain_out = []
-        for idx, (inp, o) in enumerate(zip(inputs, outs)):
-            names = ("sym", "metric") if inp["spec"]["kind"] == "det" else ("v", "x", "gamma")
-            po = {k: t.cpu().numpy() for k, t in zip(names, o)}
-            plain_out.append(po)
-            if fusable:
-                for k in names:
-                    if po[k].tobytes() != fused_out[idx][k].tobytes():
-                        identical = False
-        q_plain = quality(inputs, plain_out)
-        plain = {"value": args.steps * total_inst / p_el, "unit": "solves/s",
-                 "ms_per_step": p_el / args.steps * 1e3,
-                 "p50_slot_ms": float(np.percentile(p_lat, 50)),
-                 "p99_slot_ms": float(np.percentile(p_lat, 99)),
-                 "stage_ms": {"build": float(np.mean(prof[:, :, 0].sum(axis=1))),
-                              "anneal": float(np.mean(prof[:, :, 1].sum(axis=1))),
-                              "select": float(np.mean(prof[:, :, 2].sum(axis=1)))},
-                 "quality": q_plain}
-    q_fused = quality(inputs, fused_out) if fusable else None
+        p_out = host_outs([o for gi in range(len(groups)) for o in plain_group(gi)])
+        q_ref = quality(inputs, p_out)
+        plain = leg_record(el, lat, q_ref, {
+            "schedule": "reference",
+            "stage_ms": {"build": float(np.mean(prof[:, :, 0].sum(axis=1))),
+                         "anneal": float(np.mean(prof[:, :, 1].sum(axis=1))),
+                         "select": float(np.mean(prof[:, :, 2].sum(axis=1)))}})
+        legs["plain"] = (el, lat, ref_scheds)
 
+    # ---- fused: the same schedule in one persistent launch per slot
+    fused = None
+    if fusable:
+        print("[bench] fused leg", file=sys.stderr, flush=True)
+        el, lat, f_out, info = fused_leg(ref_scheds)
+        q_f = quality(inputs, f_out)
+        if q_ref is None:
+            q_ref = q_f
+        fused = leg_record(el, lat, q_f, {
+            "work_items": [a for a, _ in info], "workgroups": [b for _, b in info],
+            "outputs_identical_to_plain": None if plain is None else
+            same_bytes(p_out, f_out, ("sym", "metric", "v", "x", "gamma"))})
+        legs["fused"] = (el, lat, ref_scheds)
+
+    # ---- tuned: the tuner's schedule per job (binary encoding or stages)
     tuned = None
-    if not args.no_tuned and fusable:
+    t_scheds = None
+    if fusable:
         t_scheds = []
-        any_tuned = False
         for inp in inputs:
             j = inp["spec"]
             kind = M.KIND_DET if j["kind"] == "det" else M.KIND_VPP
             ts = M.tuned_schedule(kind, j["rows"], j["cols"], j["qam"], inp["noise_var"])
-            any_tuned = any_tuned or ts["tuned"]
             t_scheds.append(ts if ts["tuned"] else ref_scheds[len(t_scheds)])
-        if any_tuned:
-            t_el, t_lat, t_out, _ = fused_leg(t_scheds)
-            q_t = quality(inputs, t_out)
-            base = q_plain if q_plain is not None else q_fused
-            matched = all(qt <= 1.05 * qb + 2e-5 for qt, qb in zip(q_t, base))
-            tuned = {"value": args.steps * total_inst / t_el, "unit": "solves/s",
-                     "ms_per_step": t_el / args.steps * 1e3,
-                     "p50_slot_ms": float(np.percentile(t_lat, 50)),
-                     "p99_slot_ms": float(np.percentile(t_lat, 99)),
-                     "schedules": [f"{s['chains']} chains x {s['sweeps']} sweeps, "
-                                   f"{'fallback' if s['init'] else 'random'} start"
-                                   for s in t_scheds],
-                     "quality": q_t, "quality_matched": matched}
+        print("[bench] tuned leg", file=sys.stderr, flush=True)
+        el, lat, t_out, _ = fused_leg(t_scheds)
+        q_t = quality(inputs, t_out)
+        tuned = leg_record(el, lat, q_t, {
+            "schedules": [f"{s['chains']} chains x {s['sweeps']} sweeps" +
+                          (f" x {s['stages']} stage(s) around the MMSE guess" if s.get("stages")
+                           else f", {'fallback' if s['init'] else 'random'} start")
+                          for s in t_scheds],
+            "quality_matched": matched(q_t, q_ref)})
+        legs["tuned"] = (el, lat, t_scheds)
 
-    delta = None
-    if not args.no_delta and all(i["spec"]["kind"] == "det" and i["spec"].get("delta")
-                                 for i in inputs):
-        d_scheds = []
-        for inp in inputs:
-            j = inp["spec"]
-            ch, sw, st = j["delta"]
-            from workload import synth as W
-            d_scheds.append(dict(chains=ch, sweeps=sw, stages=st, init=0, beta2=W.linear_beta2(
-                sw, *W.det_beta_range(j["qam"], j["rows"], inp["noise_var"]))))
+    # ---- the tuned stages through the multi-launch entry point
+    delta_sep = None
+    if tuned is not None and is_det and all(s.get("stages") for s in t_scheds):
+        def delta_group(gi):
+            outs = []
+            for i in gidx[gi]:
+                inp, sc, j = inputs[i], t_scheds[i], inputs[i]["spec"]
+                o = ctx.detect_delta(inp["H_d"], inp["y_d"], j["qam"], inp["noise_var"],
+                                     sc["chains"], sc["sweeps"], sc["beta2"], inp["seed"],
+                                     stages=sc["stages"], init=sc["init"])
+                outs.append(dict(sym=o[0], metric=o[1]))
+            return outs
 
-        def delta_step():
-            return [ctx.detect_delta(inp["H_d"], inp["y_d"], inp["spec"]["qam"],
-                                     inp["noise_var"], sc["chains"], sc["sweeps"], sc["beta2"],
-                                     inp["seed"], stages=sc["stages"])
-                    for inp, sc in zip(inputs, d_scheds)]
-
-        for _ in range(args.warmup):
-            delta_step()
-        n_stage = sum(sc["stages"] for sc in d_scheds)
+        print("[bench] delta leg (separate launches)", file=sys.stderr, flush=True)
+        n_stage = sum(s["stages"] for s in t_scheds)
         ctx.set_profiling(True)
-        d_el, d_lat = timed(delta_step, args.steps)
+        el, lat = timed(delta_group)
         dprof = np.array(ctx.profile(args.steps * n_stage)).reshape(args.steps, n_stage, 3)
         ctx.set_profiling(False)
-        outs = delta_step()
-        torch.cuda.synchronize()
-        d_out = [{k: t.cpu().numpy() for k, t in zip(("sym", "metric"), o)} for o in outs]
+        d_out = host_outs([o for gi in range(len(groups)) for o in delta_group(gi)])
         q_d = quality(inputs, d_out)
-        base = q_plain if q_plain is not None else q_fused
-        d_matched = all(qd <= 1.05 * qb + 2e-5 for qd, qb in zip(q_d, base))
-        delta = {"value": args.steps * total_inst / d_el, "unit": "solves/s",
-                 "ms_per_step": d_el / args.steps * 1e3,
-                 "p50_slot_ms": float(np.percentile(d_lat, 50)),
-                 "p99_slot_ms": float(np.percentile(d_lat, 99)),
-                 "stage_ms": {"build": float(np.mean(dprof[:, :, 0].sum(axis=1))),
-                              "anneal": float(np.mean(dprof[:, :, 1].sum(axis=1))),
-                              "select": float(np.mean(dprof[:, :, 2].sum(axis=1)))},
-                 "schedules": [f"{sc['chains']} chains x {sc['sweeps']} sweeps x "
-                               f"{sc['stages']} stage(s) around the MMSE guess"
-                               for sc in d_scheds],
-                 "quality": q_d, "quality_matched": d_matched}
-        # the same stages inside the persistent fused kernel (one launch per slot)
-        fd_el, fd_lat, fd_out, _ = fused_leg(d_scheds)
-        fd_same = all(a[k].tobytes() == b[k].tobytes() for a, b in zip(fd_out, d_out)
-                      for k in ("sym", "metric"))
-        delta["fused"] = {"value": args.steps * total_inst / fd_el, "unit": "solves/s",
-                          "ms_per_step": fd_el / args.steps * 1e3,
-                          "p50_slot_ms": float(np.percentile(fd_lat, 50)),
-                          "p99_slot_ms": float(np.percentile(fd_lat, 99)),
-                          "outputs_identical_to_plain_delta": fd_same}
-        # MMGaP-E: the same stages from the MMSE and from the MMSE-SIC guess, and
-        # the MMSE-SIC detector alone (the paper's second baseline)
-        def e_step():
-            return [ctx.detect_e(inp["H_d"], inp["y_d"], inp["spec"]["qam"], inp["noise_var"],
-                                 sc["chains"], sc["sweeps"], sc["beta2"], inp["seed"],
-                                 stages=sc["stages"])
-                    for inp, sc in zip(inputs, d_scheds)]
+        delta_sep = leg_record(el, lat, q_d, {
+            "stage_ms": {"build": float(np.mean(dprof[:, :, 0].sum(axis=1))),
+                         "anneal": float(np.mean(dprof[:, :, 1].sum(axis=1))),
+                         "select": float(np.mean(dprof[:, :, 2].sum(axis=1)))},
+            "outputs_identical_to_tuned": same_bytes(d_out, t_out, ("sym", "metric")),
+            "quality_matched": matched(q_d, q_ref)})
+        legs["delta_separate"] = (el, lat, t_scheds)
 
-        def sic_step():
-            return [ctx.detect_sic(inp["H_d"], inp["y_d"], inp["spec"]["qam"], inp["noise_var"])
-                    for inp in inputs]
+    # ---- detection extras: MMGaP-E, MMSE-SIC, the SIC-guess search
+    extras = {}
+    if is_det and not args.no_extras and all(j["n_sc"] * j["n_sym"] > 0 for j in specs):
+        def delta_sched(inp, which):
+            j = inp["spec"]
+            ch, sw, st = j[which]
+            return dict(chains=ch, sweeps=sw, stages=st, init=0, beta2=W.linear_beta2(
+                sw, *W.det_beta_range(j["qam"], j["rows"], inp["noise_var"])))
 
-        for _ in range(args.warmup):
-            e_step()
-            sic_step()
-        e_el, e_lat = timed(e_step, args.steps)
-        q_e = quality(inputs, [{"sym": o[0].cpu().numpy()} for o in e_step()])
-        s_el, s_lat = timed(sic_step, args.steps)
-        q_s = quality(inputs, [{"sym": o[0].cpu().numpy()} for o in sic_step()])
-        delta["mmgap_e"] = {"value": args.steps * total_inst / e_el, "unit": "solves/s",
-                            "ms_per_step": e_el / args.steps * 1e3,
-                            "p99_slot_ms": float(np.percentile(e_lat, 99)),
-                            "quality": q_e,
-                            "quality_matched": all(qe <= 1.05 * qb + 2e-5
-                                                   for qe, qb in zip(q_e, base))}
-        delta["mmse_sic"] = {"value": args.steps * total_inst / s_el, "unit": "solves/s",
-                             "ms_per_step": s_el / args.steps * 1e3, "quality": q_s}
-        # the search from the MMSE-SIC guess alone (MMGaP-E's second chain), with
-        # its own schedule; reported, not a candidate for the headline value,
-        # since the MMSE-SIC guess alone already meets the quality bar here
-        if all(i["spec"].get("sic_delta") for i in inputs):
-            sd_scheds = []
-            for inp in inputs:
-                j = inp["spec"]
-                ch, sw, st = j["sic_delta"]
-                sd_scheds.append(dict(chains=ch, sweeps=sw, stages=st, beta2=W.linear_beta2(
-                    sw, *W.det_beta_range(j["qam"], j["rows"], inp["noise_var"]))))
+        e_sched = [delta_sched(inp, "delta") for inp in inputs]
+        s_sched = [delta_sched(inp, "sic_delta") for inp in inputs]
 
-            def sd_step():
-                return [ctx.detect_e(inp["H_d"], inp["y_d"], inp["spec"]["qam"],
-                                     inp["noise_var"], sc["chains"], sc["sweeps"], sc["beta2"],
-                                     inp["seed"], stages=sc["stages"], guesses=M.GUESS_SIC)
-                        for inp, sc in zip(inputs, sd_scheds)]
+        def e_group(scheds, guesses):
+            def go(gi):
+                return [ctx.detect_e(inputs[i]["H_d"], inputs[i]["y_d"],
+                                     inputs[i]["spec"]["qam"], inputs[i]["noise_var"],
+                                     scheds[i]["chains"], scheds[i]["sweeps"],
+                                     scheds[i]["beta2"], inputs[i]["seed"],
+                                     stages=scheds[i]["stages"], guesses=guesses)
+                        for i in gidx[gi]]
+            return go
 
-            for _ in range(args.warmup):
-                sd_step()
-            sd_el, sd_lat = timed(sd_step, args.steps)
-            q_sd = quality(inputs, [{"sym": o[0].cpu().numpy()} for o in sd_step()])
-            delta["sic_guess_search"] = {
-                "value": args.steps * total_inst / sd_el, "unit": "solves/s",
-                "ms_per_step": sd_el / args.steps * 1e3,
-                "p50_slot_ms": float(np.percentile(sd_lat, 50)),
-                "p99_slot_ms": float(np.percentile(sd_lat, 99)),
-                "schedules": [f"{sc['chains']} chains x {sc['sweeps']} sweeps x "
-                              f"{sc['stages']} stage(s) around the MMSE-SIC guess"
-                              for sc in sd_scheds],
-                "quality": q_sd}
+        def sic_group(gi):
+            return [ctx.detect_sic(inputs[i]["H_d"], inputs[i]["y_d"], inputs[i]["spec"]["qam"],
+                                   inputs[i]["noise_var"]) for i in gidx[gi]]
+
+        def q_of(go):
+            outs = [o for gi in range(len(groups)) for o in go(gi)]
+            return quality(inputs, [{"sym": o[0].cpu().numpy()} for o in outs])
+
+        print("[bench] MMGaP-E, MMSE-SIC, SIC-guess search", file=sys.stderr, flush=True)
+        sdesc = lambda s, g: f"{s['chains']} chains x {s['sweeps']} sweeps x {s['stages']} " \
+                            f"stage(s) from {g}"
+        el, lat = timed(e_group(e_sched, M.GUESS_MMSE | M.GUESS_SIC))
+        q = q_of(e_group(e_sched, M.GUESS_MMSE | M.GUESS_SIC))
+        extras["mmgap_e"] = leg_record(el, lat, q, {
+            "schedule": sdesc(e_sched[0], "the MMSE and the MMSE-SIC guess, better answer"),
+            "quality_matched": matched(q, q_ref)})
+        el, lat = timed(e_group(s_sched, M.GUESS_SIC))
+        q = q_of(e_group(s_sched, M.GUESS_SIC))
+        extras["sic_guess_search"] = leg_record(el, lat, q, {
+            "schedule": sdesc(s_sched[0], "the MMSE-SIC guess"), "quality_matched": matched(q, q_ref)})
+        el, lat = timed(sic_group)
+        extras["mmse_sic"] = leg_record(el, lat, q_of(sic_group),
+                                        {"schedule": "no anneal: ordered MMSE-SIC alone"})
+
+        # critical path (paper §5.3): one subcarrier's 12 instances alone on the
+        # GPU, for the tuned stages (MMGaP) and for MMGaP-E, from the middle slot
+        mid = inputs[gidx[len(groups) // 2][0]]
+        j = mid["spec"]
+        H1, y1 = mid["H_d"][:1].contiguous(), mid["y_d"][:1].contiguous()
+        ts = t_scheds[gidx[len(groups) // 2][0]] if t_scheds else e_sched[0]
+        st1 = ts.get("stages", 0)
+        reps = 50
+
+        def lat_of(fn):
+            for _ in range(5):
+                fn()
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(reps)]
+            for a, b in ev:
+                a.record()
+                fn()
+                b.record()
+            torch.cuda.synchronize()
+            return pct([a.elapsed_time(b) for a, b in ev])
+
+        job1 = ctx.det_job(H1, y1, j["qam"], mid["noise_var"], ts["chains"], ts["sweeps"],
+                           ts["beta2"], mid["seed"], init=ts["init"], stages=st1)
+        plan1 = ctx.plan_create([job1], graph=True)
+        cp = {"instances": int(j["n_sym"]), "snr_db": j["snr"],
+              "fused_tuned": dict(schedule=tuned["schedules"][0] if tuned else None,
+                                  **lat_of(plan1.plan_launch))}
+        plan1.plan_destroy()
+        if st1:
+            cp["mmgap_separate"] = lat_of(lambda: ctx.detect_delta(
+                H1, y1, j["qam"], mid["noise_var"], ts["chains"], ts["sweeps"], ts["beta2"],
+                mid["seed"], stages=st1))
+        es = e_sched[0]
+        cp["mmgap_e"] = dict(schedule=sdesc(es, "both guesses, one after the other"),
+                             **lat_of(lambda: ctx.detect_e(
+                                 H1, y1, j["qam"], mid["noise_var"], es["chains"], es["sweeps"],
+                                 es["beta2"], mid["seed"], stages=es["stages"])))
+        extras["critical_path"] = cp
+
+        # build over 64 slots (one launch): the HBM-bound contraction at scale
+        jb = specs[0]
+        n64 = 64 * jb["n_sc"]
+        Hb = inputs[0]["H_d"].repeat(64, 1, 1)
+        yb = inputs[0]["y_d"].repeat(64, 1, 1)
+        for _ in range(2):
+            ctx.build_ising(M.KIND_DET, Hb, yb, jb["qam"], inputs[0]["noise_var"])
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(5)]
+        for a, b in ev:
+            a.record()
+            ctx.build_ising(M.KIND_DET, Hb, yb, jb["qam"], inputs[0]["noise_var"])
+            b.record()
+        torch.cuda.synchronize()
+        b_ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+        b_bytes = build_bytes(jb, n64)
+        extras["build_64_slots"] = {
+            "bound": "hbm", "kernel": "k_det_build", "slots": 64, "subcarriers": n64,
+            "achieved": b_bytes / (b_ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+            "frac": b_bytes / (b_ms * 1e-3) / PEAK_HBM, "bytes_per_launch": b_bytes,
+            "kernel_ms": b_ms}
+        del Hb, yb
     ctx.close()
 
-    build_roof = None
-    if plain is not None:
-        b_bytes = sum(build_bytes(i["spec"]) for i in inputs)
-        b_s = plain["stage_ms"]["build"] / 1e3
-        build_roof = {"bound": "hbm", "kernel": "k_det_build / k_vpp_build (plain leg)",
-                      "achieved": b_bytes / b_s / 1e9, "peak": 8000.0, "unit": "GB/s",
-                      "frac": b_bytes / b_s / 8e12, "bytes_per_launch": b_bytes,
-                      "kernel_ms": b_s * 1e3}
-    # the reported leg: the fastest whose quality matches the reference schedule's
-    legs = [("fused", f_el, f_lat, ref_scheds)] if fusable else \
-        [("plain", p_el, p_lat, ref_scheds)]
+    # ---- the reported leg: the fastest whose quality matches the plain leg's
+    cands = [("fused", fused)] if fused is not None else [("plain", plain)]
     if tuned is not None and tuned["quality_matched"]:
-        legs.append(("tuned", t_el, t_lat, t_scheds))
-    if delta is not None and delta["quality_matched"]:
-        legs.append(("delta", d_el, d_lat, d_scheds))
-        if delta["fused"]["outputs_identical_to_plain_delta"]:
-            legs.append(("delta_fused", fd_el, fd_lat, d_scheds))
-    sel_name, sel_el, sel_lat, sel_scheds = min(legs, key=lambda leg: leg[1])
-    use_tuned = sel_name == "tuned"
-    use_delta = sel_name in ("delta", "delta_fused")
+        cands.append(("tuned", tuned))
+    if delta_sep is not None and delta_sep["quality_matched"]:
+        cands.append(("delta_separate", delta_sep))
+    sel_name, sel = min(cands, key=lambda c: c[1]["ms_per_step"])
+    sel_el, sel_lat, sel_scheds = legs[sel_name]
     value = args.steps * total_inst / sel_el
 
-    # roofline of the dominant kernel on the reported leg: anneal operations of
-    # one launch over its measured duration (HIP events on the launch stream;
-    # for the delta leg the library's events around its anneal launches)
-    attempts = 0.0
-    alg_ops = 0.0
+    # roofline of the dominant kernel on the reported leg: the anneals' operations
+    # per slot launch over the launch's measured duration (HIP events on the
+    # launch stream; for separate launches the library's events around its anneal
+    # launches)
+    attempts = ops = 0.0
     for inp, sc in zip(inputs, sel_scheds):
-        K, q, n, _ = job_shape(inp["spec"])
-        if use_delta:
-            q = 2                                   # two unit-weight spins per move
-        a = float(n) * sc["chains"] * sc["sweeps"] * K * q * sc.get("stages", 1)
+        a, o = sched_work(inp["spec"], sc)
         attempts += a
-        alg_ops += a * ops_per_attempt(K, q)
-    kern_s = (delta["stage_ms"]["anneal"] if sel_name == "delta"
-              else plain["stage_ms"]["anneal"] if sel_name == "plain"
-              else float(np.mean(sel_lat))) / 1e3
-    achieved = alg_ops / kern_s
+        ops += o
+    if sel_name == "plain":
+        kern_ms = plain["stage_ms"]["anneal"]
+    elif sel_name == "delta_separate":
+        kern_ms = delta_sep["stage_ms"]["anneal"]
+    else:
+        kern_ms = float(sel_lat.mean(axis=0).sum())
+    achieved = ops / (kern_ms * 1e-3)
+    kname = {"plain": "k_anneal", "delta_separate": "k_anneal (moves around the guess)"}.get(
+        sel_name, "k_fused" + (" (moves around the guess)" if any(s.get("stages")
+                                                                   for s in sel_scheds) else ""))
+    tkey = {"plain": "k_anneal", "delta_separate": "k_anneal_delta"}.get(
+        sel_name, "k_fused_delta" if any(s.get("stages") for s in sel_scheds) else "k_fused")
 
     desc = []
     for j in specs:
         if j["kind"] == "det":
-            desc.append(f"uplink ML detection {j['rows']}x{j['cols']} {j['qam']}-QAM, SNR "
-                        f"{j['snr']:g} dB")
+            desc.append(f"{j['rows']}x{j['cols']} {j['qam']}-QAM at {j['snr']:g} dB")
         else:
-            desc.append(f"downlink VPP {j['rows']}x{j['cols']} {j['qam']}-QAM")
+            desc.append(f"VPP {j['rows']}x{j['cols']} {j['qam']}-QAM")
+    kinds = {j["kind"] for j in specs}
+    head = ("uplink ML detection" if kinds == {"det"} else "downlink VPP" if kinds == {"vpp"}
+            else "detection and VPP")
     out = {
         "metric": METRIC,
         "value": value,
@@ -801,55 +861,51 @@ def main(argv=None) -> int:  # noqa: C901
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "; ".join(desc) + f"; {specs[0]['n_sc']} subcarriers x "
-                        f"{specs[0]['n_sym']} symbols per slot, i.i.d. Rayleigh; reference "
-                        + ", ".join(f"{j['chains']} chains x {j['sweeps']} sweeps" for j in specs),
+            "workload": f"{head}: " + "; ".join(desc) + f"; {specs[0]['n_sc']} subcarriers x "
+                        f"{specs[0]['n_sym']} symbols per slot, i.i.d. Rayleigh, one slot per "
+                        f"launch; reference " + ", ".join(sorted({f"{j['chains']} chains x "
+                                                                 f"{j['sweeps']} sweeps"
+                                                                 for j in specs})),
             "name": args.workload,
-            "path": ("plain: build, then per stage move fields, anneal and select launches "
-                     "(detection around the MMSE guess)") if sel_name == "delta" else
-                    "plain: build, anneal and select launches per slot" if sel_name == "plain" else
-                    ("fused: one persistent build+anneal+select launch per slot, replayed as a "
-                     "HIP graph" + (", every stage of moves around the MMSE guess inside it"
-                                    if sel_name == "delta_fused" else "")),
-            "schedule": ("delta: " + "; ".join(delta["schedules"])) if use_delta else
-                        (("tuned: " + "; ".join(tuned["schedules"])) if use_tuned
-                         else "reference"),
+            "leg": sel_name,
+            "path": {"plain": "plain: build, anneal and select launches per slot",
+                     "fused": "fused: one persistent build+anneal+select launch per slot, "
+                              "replayed as a HIP graph",
+                     "tuned": "fused at the tuned schedules: one persistent launch per slot "
+                              "(HIP graph), stages of moves around the MMSE guess inside it "
+                              "where the tuner chose them",
+                     "delta_separate": "per stage: move fields, anneal and select launches"
+                     }[sel_name],
+            "slots_per_step": len(groups),
             "instances_per_step": total_inst,
-            "work_items": n_items,
-            "workgroups": n_blocks,
         },
         "p50_slot_ms": float(np.percentile(sel_lat, 50)),
         "p99_slot_ms": float(np.percentile(sel_lat, 99)),
+        "deadline_ms": SERVE_DEADLINE_MS,
         "flip_attempts_per_s": attempts * args.steps / sel_el,
-        "plain": plain,
-        "fused_reference": None if not fusable else {
-            "value": args.steps * total_inst / f_el, "ms_per_step": f_el / args.steps * 1e3,
-            "p99_slot_ms": float(np.percentile(f_lat, 99)), "quality": q_fused,
-            "outputs_identical_to_plain": identical},
-        "tuned": tuned,
-        "delta": delta,
-        "speedup_vs_plain": None if plain is None else value / plain["value"],
         "quality_kind": ["ser" if j["kind"] == "det" else "mean_gamma" for j in specs],
+        "quality_per_slot": {"slot": desc, "plain": q_ref,
+                             "reported": (tuned if sel_name == "tuned" else
+                                          delta_sep if sel_name == "delta_separate" else
+                                          fused if sel_name == "fused" else plain)["quality"]},
+        "speedup_vs_plain": None if plain is None else value / plain["value"],
+        "plain": plain,
+        "fused_reference": fused,
+        "tuned": tuned,
+        "delta_separate": delta_sep,
+        **extras,
         "roofline": {
-            "bound": "alu",
-            "kernel": {"delta": "k_anneal (moves around the guess)",
-                       "delta_fused": "k_fused (moves around the guess)",
-                       "plain": "k_anneal"}.get(sel_name, "k_fused"),
-            "achieved": achieved / 1e12,
-            "peak": PEAK_ALU_OPS / 1e12,
-            "unit": "T lane-ops/s",
+            "bound": "alu", "kernel": kname,
+            "achieved": achieved / 1e12, "peak": PEAK_ALU_OPS / 1e12, "unit": "T lane-ops/s",
             "frac": achieved / PEAK_ALU_OPS,
-            "traffic": stored_traffic(args.workload, {"delta": "k_anneal_delta",
-                                                      "delta_fused": "k_fused_delta",
-                                                      "plain": "k_anneal"}
-                                      .get(sel_name, "k_fused")),
-            "kernel_ms": kern_s * 1e3,
-            "ops_per_launch": alg_ops,
-            "attempts_per_launch": attempts,
+            "traffic": stored_traffic(args.workload, tkey),
+            "kernel_ms": kern_ms, "ops_per_step": ops, "attempts_per_step": attempts,
         },
-        "build_roofline": build_roof,
         "cpu_baseline": None,
     }
+    if is_det and not args.no_extras and not args.no_serve:
+        print("[bench] serving mix", file=sys.stderr, flush=True)
+        out["serve_mix"] = serve_mix(M, torch, 12, 20, 20)
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(1)
         dst = torch.empty_like(src)
@@ -858,6 +914,7 @@ def main(argv=None) -> int:  # noqa: C901
         torch.cuda.synchronize()
         del src, dst
     if not args.no_cpu_baseline:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(inputs, sel_scheds, args.cpu_seconds)
     print(json.dumps(out), flush=True)
     return 0
