@@ -1,4 +1,4 @@
-"""GPU parity of the 32x32 high-connectivity shape (paper §5.3: 32 receive
+"""GPU parity of the 32x32 high-connectivity shape (paper §5.2.3: 32 receive
 antennas, 32 users, up to 16-QAM, 128 anneals; K = 64 real dimensions, up to
 128 spins) against the oracle: the build (couplings, fields, sliced MMSE
 guess), the anneals through mmgap_solve, mmgap_detect and mmgap_detect_delta
