@@ -220,6 +220,29 @@ int mmgap_detect(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, const
                  void *stream);
 
 /*
+ * mmgap_detect_noalloc -- mmgap_detect for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same arguments, launches and results, bit for bit,
+ * but its scratch (couplings, fields, fallback levels, every chain's energy
+ * and spins) lives in a fixed array of 128 MiB per device that the library
+ * holds until the process ends; the call allocates nothing, neither device
+ * nor host memory.  The scratch it needs is
+ *   4 n_sc KT^2 + 5 I KT + 4 I C (1 + ceil(KT q / 32)) bytes (each term
+ *   rounded up to 256), I = n_sc n_sym, KT = 2 n_tx rounded up to 8, 16, 32 or 64,
+ * e.g. 27 MB for a 3276 x 12 8x8 16-QAM slot at 64 chains; a call above 128 MiB
+ * returns MMGAP_EUNSUPPORTED with nothing launched (split it by subcarriers,
+ * with schedule.inst_base = first subcarrier x n_sym to keep the random
+ * streams of the whole call).  Every call on one device shares that device's
+ * array: calls on one context are ordered like the context's other calls, but
+ * calls that overlap on one device through different contexts or threads race
+ * and give undefined results.  Nothing in the array needs clearing: each call
+ * writes every value it reads.
+ */
+int mmgap_detect_noalloc(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H,
+                         const void *y, const mmgap_schedule *sched, unsigned char *sym_out,
+                         float *metric_out, void *stream);
+
+/*
  * mmgap_cim_chains -- every CIM-CAC anneal's own final state, for studies of
  * the integration (paper Appendix A: the sign of the final amplitudes and
  * whether the integration diverged, against a fine-step reference with the

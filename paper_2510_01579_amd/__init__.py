@@ -110,6 +110,7 @@ def lib() -> ctypes.CDLL:
             L.mmgap_build_ising.argtypes = [vp, P, vp, vp, vp, vp, vp, vp, vp, vp, vp]
             L.mmgap_solve.argtypes = [vp, i, i, i, vp, vp, i, vp, vp, S, vp, vp, vp, vp]
             L.mmgap_detect.argtypes = [vp, P, vp, vp, S, vp, vp, vp]
+            L.mmgap_detect_noalloc.argtypes = [vp, P, vp, vp, S, vp, vp, vp]
             L.mmgap_detect_delta.argtypes = [vp, P, vp, vp, S, i, vp, vp, vp, vp]
             L.mmgap_detect_sic.argtypes = [vp, P, vp, vp, vp, vp, vp, vp, vp]
             L.mmgap_detect_e.argtypes = [vp, P, vp, vp, S, i, i, vp, vp, vp, vp]
@@ -435,6 +436,30 @@ class Context:
                                        ctypes.byref(s), _ptr(sym), _ptr(met), st))
         del keep
         return sym, met
+
+    def detect_noalloc(self, H, y, qam, noise_var, chains, sweeps, beta2, seed, init=0,
+                       sym=None, metric=None, stream=None, cim=None, inst_base=0):
+        """mmgap_detect_noalloc: detection whose scratch is the library's fixed
+        per-device array (no device allocation inside the call).  `sym` (uint8
+        [n][n_tx]) and `metric` (float32 [n]) may be given as preallocated
+        outputs; otherwise they are allocated here, before the call.  Returns
+        (sym, metric or None)."""
+        torch = _torch()
+        p = self._problem(KIND_DET, H, y, qam, noise_var, 0.0)
+        n = p.n_sc * p.n_sym
+        dev = self._dev()
+        if sym is None:
+            sym = torch.empty((n, p.n_tx), dtype=torch.uint8, device=dev)
+        else:
+            self._check_tensor(sym, "sym", torch.uint8, (n, p.n_tx))
+        if metric is not None:
+            self._check_tensor(metric, "metric", torch.float32, (n,))
+        s, keep = self._schedule(chains, sweeps, beta2, seed, init, cim, inst_base)
+        st = stream if stream is not None else _stream(dev)
+        self._check(lib().mmgap_detect_noalloc(self._h, ctypes.byref(p), _ptr(H), _ptr(y),
+                                               ctypes.byref(s), _ptr(sym), _ptr(metric), st))
+        del keep
+        return sym, metric
 
     def detect_delta(self, H, y, qam, noise_var, chains, sweeps, beta2, seed, stages=1,
                      guess=None, init=0, metric=True, stream=None, cim=None, inst_base=0):

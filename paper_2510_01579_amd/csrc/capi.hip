@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -17,6 +18,33 @@ using namespace mmgap::host;
 
 namespace {
 thread_local std::string g_create_error;
+
+// Scratch of mmgap_detect_noalloc: one fixed array per device, held until the
+// process ends.  In host code the array's name is only a stand-in; the device
+// address of each device's copy comes from hipGetSymbolAddress, taken once per
+// device (with that device current) when a context is created there.
+constexpr size_t kNoAllocScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mutex;
+char *g_noalloc_ptr[kNoAllocDevices] = {};
+
+// The current device's address of `scratch` (the device is `device`).
+hipError_t noalloc_scratch_address(int device, char **out)
+{
+    *out = nullptr;
+    if (device < 0 || device >= kNoAllocDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_noalloc_mutex);
+    if (!g_noalloc_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_noalloc_ptr[device] = static_cast<char *>(p);
+    }
+    *out = g_noalloc_ptr[device];
+    return hipSuccess;
+}
 }  // namespace
 
 namespace mmgap {
@@ -554,6 +582,8 @@ int mmgap_create(mmgap_ctx **out, int device, size_t hbm_budget_bytes)
         table[mmgap::kAcceptTable - 1] = 0u;
         e = hipMemcpy(ctx->accept_dev, table, sizeof table, hipMemcpyHostToDevice);
     }
+    if (e == hipSuccess && device < kNoAllocDevices)
+        e = noalloc_scratch_address(device, &ctx->noalloc_scratch);
     if (e != hipSuccess) {
         mmgap_destroy(ctx);
         return fail(nullptr, MMGAP_EDEVICE, "context setup: %s", hipGetErrorString(e));
@@ -911,6 +941,30 @@ int mmgap_detect(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, const
     if ((rc = ensure_scratch(ctx, L.bytes))) return rc;
     return detect_launches(ctx, (hipStream_t)stream, prob, sh, L, static_cast<char *>(ctx->scratch),
                            H, y, sched, sym_out, metric_out);
+}
+
+int mmgap_detect_noalloc(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H,
+                         const void *y, const mmgap_schedule *sched, unsigned char *sym_out,
+                         float *metric_out, void *stream)
+{
+    if (!ctx) return MMGAP_EINVAL;
+    ProblemShape sh;
+    int rc = check_problem(ctx, prob, MMGAP_KIND_DET, &sh);
+    if (rc) return rc;
+    if ((rc = check_schedule(ctx, sched))) return rc;
+    if (sh.n_inst == 0) return MMGAP_OK;
+    if (!H || !y || !sym_out) return fail(ctx, MMGAP_EINVAL, "H, y and sym_out are required");
+    const DetectScratch L = detect_scratch(prob, sh, sched);
+    if (L.bytes > kNoAllocScratchBytes)
+        return fail(ctx, MMGAP_EUNSUPPORTED,
+                    "the call needs %zu bytes of scratch, above the fixed %zu of "
+                    "mmgap_detect_noalloc (fewer subcarriers or chains per call)",
+                    L.bytes, kNoAllocScratchBytes);
+    if (!ctx->noalloc_scratch)
+        return fail(ctx, MMGAP_EUNSUPPORTED, "no fixed scratch on device %d", ctx->device);
+    DeviceGuard g(ctx->device);
+    return detect_launches(ctx, (hipStream_t)stream, prob, sh, L, ctx->noalloc_scratch, H, y,
+                           sched, sym_out, metric_out);
 }
 
 namespace {

@@ -32,6 +32,7 @@ struct mmgap_ctx {
     std::string err;
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
+    char *noalloc_scratch = nullptr;            // this device's fixed array (capi.hip)
     size_t plan_bytes = 0;                      // device memory held by live plans and the server
     float *beta_dev = nullptr;                  // [kRing][kMaxSweeps]
     float *beta_host = nullptr;                 // pinned, same shape
