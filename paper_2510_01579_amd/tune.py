@@ -67,10 +67,12 @@ CLASSES = {
 }
 CHAINS = (4, 8, 16, 32, 64, 128)
 SWEEPS = (12, 25, 50, 100, 200, 400)
-# moves around the MMSE guess: chains, sweeps per stage, stages
-DELTA_CHAINS = (4, 8, 16, 32)
-DELTA_SWEEPS = (2, 4, 6, 8, 12, 16, 25)
-DELTA_STAGES = (1, 2, 3)
+# moves around the MMSE guess: chains, sweeps per stage, stages, temperature
+# shapes; candidates above DELTA_MAX_WORK chains x sweeps x stages are left out
+DELTA_CHAINS = (4, 8, 16, 32, 64)
+DELTA_SWEEPS = (2, 4, 6, 8, 12, 16, 25, 50)
+DELTA_STAGES = (1, 2, 3, 4)
+DELTA_MAX_WORK = 3200
 SHAPES = ((0.0, 1.0), (1.0 / 16, 1.0), (1.0 / 4, 1.0), (1.0 / 16, 4.0))
 TOLERANCE = 0.05             # the requirement: quality within 5% of the reference
 SELECT_TOLERANCE = 0.03      # used when choosing, so that other slots (other channel
@@ -87,8 +89,16 @@ def shaped_range(b0: float, b1: float, shape) -> tuple[float, float]:
 def schedule_key(c) -> str:
     C, S, init, shape = c[:4]
     if len(c) > 4 and c[4]:
-        return f"{C}x{S}x{c[4]}/delta"
+        if tuple(shape) == SHAPES[0]:
+            return f"{C}x{S}x{c[4]}/delta"
+        return f"{C}x{S}x{c[4]}/delta/{shape[0]:g},{shape[1]:g}"
     return f"{C}x{S}/{init}/{shape[0]:g},{shape[1]:g}"
+
+
+def delta_candidates():
+    """Moves around the MMSE guess: (chains, sweeps, 0, shape, stages)."""
+    return [(C, S, 0, sh, st) for C in DELTA_CHAINS for S in DELTA_SWEEPS for st in DELTA_STAGES
+            for sh in SHAPES if C * S * st <= DELTA_MAX_WORK]
 
 
 def parse_class(name):
@@ -129,9 +139,13 @@ def parse_key_of(t):
 def parse_key(key):
     """(chains, sweeps, init, shape, stages) of a schedule key."""
     sched, rest = key.split("/", 1)
-    if rest == "delta":
+    if rest == "delta" or rest.startswith("delta/"):
         C, S, st = (int(v) for v in sched.split("x"))
-        return C, S, 0, (0.0, 1.0), st
+        shape = SHAPES[0]
+        if rest != "delta":
+            r, m = (float(v) for v in rest.split("/", 1)[1].split(","))
+            shape = (r, m)
+        return C, S, 0, shape, st
     init, shape = rest.split("/")
     C, S = (int(v) for v in sched.split("x"))
     r, m = (float(v) for v in shape.split(","))
@@ -236,8 +250,7 @@ def main(argv=None) -> int:
             if not name.startswith("det") or name not in table["classes"]:
                 continue
             rec = table["classes"][name]
-            cands = [(C, S, 0, SHAPES[0], st) for C in DELTA_CHAINS for S in DELTA_SWEEPS
-                     for st in DELTA_STAGES]
+            cands = delta_candidates()
             t0 = time.time()
             for k, r in enumerate(rec["per_snr"]):
                 q = measure(ctx, name, r["snr_db"], cands, args.n_sc, args.n_sym,
@@ -260,8 +273,7 @@ def main(argv=None) -> int:
                         if cost(name, C, S) <= cost(name, ref[0], ref[1])} | {ref},
                        key=lambda s: (cost(name, s[0], s[1]), s))
         if name.startswith("det"):
-            cands += [(C, S, 0, SHAPES[0], st) for C in DELTA_CHAINS for S in DELTA_SWEEPS
-                      for st in DELTA_STAGES]
+            cands += delta_candidates()
         t0 = time.time()
         per_snr = []
         for k, snr in enumerate(spec["snr"]):
