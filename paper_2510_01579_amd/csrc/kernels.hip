@@ -158,6 +158,15 @@ __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, i
 
     const float2 *Hg = H + (size_t)sc * nr * nt;
     for (int e = tid; e < nr * nt; e += nthr) sh.Hs[e] = to_cf32(Hg[e]);
+    // The symbols' y go to LDS too when they fit in the inverse's buffer (not
+    // used before the factorisation), so that the matrix-core loop below reads
+    // no global memory; else it reads y where it needs it.
+    cf32 *Ys = reinterpret_cast<cf32 *>(sh.Ls);
+    const bool y_lds = NT <= 16 && ns * nr <= (int)(sizeof(sh.Ls) / sizeof(cf32));
+    if (y_lds) {
+        const float2 *yg = y + ((size_t)sc * nsym + sym0) * nr;
+        for (int e = tid; e < ns * nr; e += nthr) Ys[e] = to_cf32(yg[e]);
+    }
     __syncthreads();
 
     for (int e = tid; e < ld * ld; e += nthr) {
@@ -229,7 +238,8 @@ __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, i
                         else if (t == 1) b = top ? (double)h.y : -(double)h.x;
                     }
                     if (t >= 2 && s_col < ns) {
-                        const float2 yv = y[((size_t)sc * nsym + sym0 + s_col) * nr + rr];
+                        const cf32 yv = y_lds ? Ys[s_col * nr + rr]
+                                              : to_cf32(y[((size_t)sc * nsym + sym0 + s_col) * nr + rr]);
                         if (lrow < 8) b = top ? (double)yv.x : (double)yv.y;
                         else b = top ? (double)yv.y : -(double)yv.x;
                     }
@@ -305,27 +315,55 @@ __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, i
     // pivoting), each pivot step reading one LDS buffer and writing the other
     // (Ls and Cg, rows of NT), so that no element is held in registers across
     // the step's synchronisation
+    // (element (i, j) of the NT x NT frame is e = i NT + j, lane e mod 64:
+    // compile-time shifts, no integer division in the pivot loop)
     double2 *src = sh.Ls, *dst = sh.Cg;
-    for (int e = tid; e < nt * nt; e += 64) {
-        const int i = e / nt, j = e % nt;
+    for (int e = tid; e < NT * NT; e += 64) {
+        const int i = e / NT, j = e % NT;
+        if (i >= nt || j >= nt) continue;
         double2 v = sh.Cg[i * NT + j];
         if (i == j) v.x = v.x + noise_var;
         src[i * NT + j] = v;
     }
     wave_sync_lds();
+    // Each pivot step reads every operand of this lane's elements first (one
+    // round of independent LDS loads), then computes and stores; groups of four
+    // elements per lane (all of them for NT <= 16).
+    constexpr int kEpl = (NT * NT + 63) / 64;
+    constexpr int kGrp = kEpl < 4 ? kEpl : 4;
     for (int k = 0; k < nt; ++k) {
         const cd pk = ld2(src[k * NT + k]);
         const double den = pk.re * pk.re + pk.im * pk.im;
         const cd t{pk.re / den, -pk.im / den};
-        for (int e = tid; e < nt * nt; e += 64) {
-            const int i = e / nt, j = e % nt;
-            const cd rowv = j == k ? t : cmul(ld2(src[k * NT + j]), t);
-            if (i == k) {
-                dst[i * NT + j] = st2(rowv);
-            } else {
-                const cd o = j == k ? cd{0.0, 0.0} : ld2(src[i * NT + j]);
-                const cd m = cmul(ld2(src[i * NT + k]), rowv);
-                dst[i * NT + j] = make_double2(o.re - m.re, o.im - m.im);
+#pragma unroll 1
+        for (int m0 = 0; m0 < kEpl; m0 += kGrp) {
+            cd rowk[kGrp], colk[kGrp], old[kGrp];
+#pragma unroll
+            for (int u = 0; u < kGrp; ++u) {
+                const int e = tid + 64 * (m0 + u);
+                const int i = e / NT, j = e % NT;
+                rowk[u] = cd{0.0, 0.0};
+                colk[u] = cd{0.0, 0.0};
+                old[u] = cd{0.0, 0.0};
+                if (e < NT * NT && i < nt && j < nt) {
+                    rowk[u] = ld2(src[k * NT + j]);
+                    colk[u] = ld2(src[i * NT + k]);
+                    old[u] = ld2(src[i * NT + j]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kGrp; ++u) {
+                const int e = tid + 64 * (m0 + u);
+                const int i = e / NT, j = e % NT;
+                if (e >= NT * NT || i >= nt || j >= nt) continue;
+                const cd rowv = j == k ? t : cmul(rowk[u], t);
+                if (i == k) {
+                    dst[i * NT + j] = st2(rowv);
+                } else {
+                    const cd o = j == k ? cd{0.0, 0.0} : old[u];
+                    const cd m = cmul(colk[u], rowv);
+                    dst[i * NT + j] = make_double2(o.re - m.re, o.im - m.im);
+                }
             }
         }
         wave_sync_lds();
@@ -335,12 +373,14 @@ __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, i
     }
     const double2 *Ai = src;
     // x = A^-1 F per symbol, one (symbol, user) pair per lane, then slicing
-    for (int e = tid; e < ns * nt; e += 64) {
-        const int r0 = e / nt, i = e % nt;
+    for (int e = tid; e < ns * NT; e += 64) {
+        const int r0 = e / NT, i = e % NT;
+        if (i >= nt) continue;
         const double2 *w = sh.Fs + r0 * LD;
         cd acc{0.0, 0.0};
-#pragma unroll 4
-        for (int j = 0; j < nt; ++j) {
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            if (j >= nt) break;
             const cd v = cmul(ld2(Ai[i * NT + j]), ld2(w[j]));
             acc.re = acc.re + v.re;
             acc.im = acc.im + v.im;
@@ -1471,6 +1511,8 @@ constexpr int kFusedBuildSyms = 16;   // symbols per build pass (an item may tak
 // State shared by every class: threshold table, per-wavefront selection and
 // decode scratch, the current item.  At namespace scope so that the
 // out-of-line variants address it as LDS.
+// Instances of one packed work item: four wavefronts of at most 16 instances.
+constexpr int kMaxPackedItem = 64;
 struct FusedCommon {
     uint32_t T[kAcceptSteps + 1];
     uint64_t keys[kWavesPerBlock];
@@ -1480,6 +1522,10 @@ struct FusedCommon {
     int cand[kWavesPerBlock][32];
     signed char zmove[32];  // the zero move (fallback of detection around a guess)
     int item;               // the current work item, published by thread 0
+    // winning anneal of each instance of a packed item (spin words, energy),
+    // left by the wavefront that annealed it for the wavefront that decodes it
+    uint32_t wbits[kMaxPackedItem][3];
+    float wE[kMaxPackedItem];
 };
 __shared__ FusedCommon g_fc;
 
@@ -1634,78 +1680,83 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
         const float *fbase = delta ? uniform_ptr(jp->fp) : uniform_ptr(jp->f);
         const signed char *xbase = uniform_ptr(jp->x_fb);
         if constexpr (PACKED) {
+            // Wavefront w anneals instances w P .. w P + P - 1 of the item (P =
+            // 64 / glanes) and leaves each one's winning anneal in LDS; then
+            // the instances' selection tails (fallback, move, decode) are
+            // spread over all four wavefronts, instance r on wavefront r mod 4,
+            // so that no wavefront decodes a whole subcarrier alone.
             const int gl = rfl(jp->glanes);
             const int lg = __builtin_ctz((unsigned)gl);
             const int per_wave = 64 >> lg;
             const int first = wave * per_wave;
-            if (first >= ns) return;              // whole wavefront idle (no barrier follows)
-            const int chains = rfl(jp->chains);
-            const int cnt = min(per_wave, ns - first);
-            const int grp = lane >> lg;
-            const int chn = lane & (gl - 1);
-            const bool valid = grp < cnt;
-            const int r = first + (valid ? grp : 0);
-            const int n = sc * n_sym + sym0 + r;
-            const float *fi = fbase + (size_t)n * ldf;
-            const signed char *xi = delta ? sh.zmove : xbase + (size_t)n * KT;
-            // the Philox instance index of the whole slot
-            const uint32_t un = (uint32_t)n + rflu(jp->inst_base);
-            E = anneal_lane<KT, Q, true>(Gi, fi, xi, beta2, sh.T, sweeps, w, key0, key1, init,
-                                         (uint32_t)chn, un, bits);
-            uint64_t key = ~0ull;
-            if (valid && chn < chains) key = ((uint64_t)energy_key(E) << 32) | (uint32_t)chn;
-            for (int off = gl >> 1; off >= 1; off >>= 1) {   // minimum within each group
-                const uint32_t lo = __shfl_xor((uint32_t)key, off, 64);
-                const uint32_t hi = __shfl_xor((uint32_t)(key >> 32), off, 64);
-                const uint64_t o = ((uint64_t)hi << 32) | lo;
-                key = o < key ? o : key;
+            if (first < ns) {                         // uniform over the wavefront
+                const int chains = rfl(jp->chains);
+                const int cnt = min(per_wave, ns - first);
+                const int grp = lane >> lg;
+                const int chn = lane & (gl - 1);
+                const bool valid = grp < cnt;
+                const int r = first + (valid ? grp : 0);
+                const int n = sc * n_sym + sym0 + r;
+                const float *fi = fbase + (size_t)n * ldf;
+                const signed char *xi = delta ? sh.zmove : xbase + (size_t)n * KT;
+                // the Philox instance index of the whole slot
+                const uint32_t un = (uint32_t)n + rflu(jp->inst_base);
+                E = anneal_lane<KT, Q, true>(Gi, fi, xi, beta2, sh.T, sweeps, w, key0, key1,
+                                             init, (uint32_t)chn, un, bits);
+                uint64_t key = ~0ull;
+                if (valid && chn < chains) key = ((uint64_t)energy_key(E) << 32) | (uint32_t)chn;
+                for (int off = gl >> 1; off >= 1; off >>= 1) {   // minimum within each group
+                    const uint32_t lo = __shfl_xor((uint32_t)key, off, 64);
+                    const uint32_t hi = __shfl_xor((uint32_t)(key >> 32), off, 64);
+                    const uint64_t o = ((uint64_t)hi << 32) | lo;
+                    key = o < key ? o : key;
+                }
+                // each group's winning lane publishes its spins and energy
+                if (valid && (uint32_t)chn == (uint32_t)key) {
+                    for (int ww = 0; ww < NW; ++ww) sh.wbits[r][ww] = bits[ww];
+                    sh.wE[r] = E;
+                }
             }
+        }
+        if constexpr (PACKED) {
+            __syncthreads();
             // the lane re-derived from a fresh thread index: values made from it
             // before the anneal are not held (spilled) across it
-            // (32 spins and more; smaller problems keep fewer registers this way)
             int tpost = threadIdx.x;
-            if constexpr (KT * Q >= 32) asm volatile("" : "+v"(tpost) : "v"(E));
-            const int lanep = KT * Q >= 32 ? (tpost & 63) : lane;
+            asm volatile("" : "+v"(tpost));
+            const int lanep = tpost & 63;
+            const int wavep = rfl(tpost >> 6);
             const FusedPost p = fused_post(jp);
             const int stage = rfl(lds.stage);
-            for (int g = 0; g < cnt; ++g) {
-                const int bch = rfl((int)__shfl((uint32_t)key, g << lg, 64));
-                const int wl = (g << lg) + bch;            // the group's winning lane
-                if (lanep == wl) {
-                    for (int ww = 0; ww < NW; ++ww) sh.lvs[wave][ww] = (int)bits[ww];
-                }
-                wave_sync_lds();
+            for (int r = wavep; r < ns; r += kWavesPerBlock) {
                 uint32_t S[NW];
-                for (int ww = 0; ww < NW; ++ww) S[ww] = (uint32_t)sh.lvs[wave][ww];
-                wave_sync_lds();
-                const float Ebest = __shfl(E, wl, 64);
-                const int ng = sc * p.n_sym + sym0 + first + g;
+                for (int ww = 0; ww < NW; ++ww) S[ww] = sh.wbits[r][ww];
+                const float Ebest = sh.wE[r];
+                const int ng = sc * p.n_sym + sym0 + r;
                 const float *fg = p.fbase + (size_t)ng * p.ldf;
                 const signed char *xg = p.stages > 0 ? sh.zmove : p.xbase + (size_t)ng * KT;
                 // detection couplings are exactly symmetric: column reads (lane-contiguous,
                 // no LDS bank conflicts) give the row's values
                 const float Efb =
-                    p.kind == 0 ? fallback_energy<true>(Gi, KT, p.K, fg, xg, sh.terms[wave], lanep)
-                                : fallback_energy<false>(Gi, KT, p.K, fg, xg, sh.terms[wave], lanep);
+                    p.kind == 0 ? fallback_energy<true>(Gi, KT, p.K, fg, xg, sh.terms[wavep], lanep)
+                                : fallback_energy<false>(Gi, KT, p.K, fg, xg, sh.terms[wavep], lanep);
                 const bool use_fb = energy_less(Efb, Ebest);
-                winning_levels(use_fb, xg, S, p.K, Q, p.w, sh.lvs[wave], lanep);
+                winning_levels(use_fb, xg, S, p.K, Q, p.w, sh.lvs[wavep], lanep);
                 if (p.stages > 0) {
-                    apply_move<true>(sh.lvs[wave], p.xbase + (size_t)ng * KT, Gi, KT, p.K,
-                                     p.ffull + (size_t)ng * p.ldf, (1 << p.dq) - 1, sh.cand[wave],
-                                     sh.terms[wave], lanep);
+                    apply_move<true>(sh.lvs[wavep], p.xbase + (size_t)ng * KT, Gi, KT, p.K,
+                                     p.ffull + (size_t)ng * p.ldf, (1 << p.dq) - 1,
+                                     sh.cand[wavep], sh.terms[wavep], lanep);
                     if (stage == p.stages - 1)
-                        decode_det(sh.lvs[wave], ng, sc, sym0 + first + g, p.n_sym, p.n_rows,
+                        decode_det(sh.lvs[wavep], ng, sc, sym0 + r, p.n_sym, p.n_rows,
                                    p.n_cols, p.dq, p.c, lds.H, p.y, (unsigned char *)p.out0,
                                    (float *)p.out1, lanep);
                 } else if (p.kind == 0) {
-                    decode_det(sh.lvs[wave], ng, sc, sym0 + first + g, p.n_sym, p.n_rows,
-                               p.n_cols, Q, p.c, lds.H, p.y, (unsigned char *)p.out0,
-                               (float *)p.out1, lanep);
+                    decode_det(sh.lvs[wavep], ng, sc, sym0 + r, p.n_sym, p.n_rows, p.n_cols, Q,
+                               p.c, lds.H, p.y, (unsigned char *)p.out0, (float *)p.out1, lanep);
                 } else {
-                    decode_vpp(sh.lvs[wave], ng, sc, sym0 + first + g, p.n_sym, p.n_rows,
-                               p.n_cols, p.tau, lds.Z, lds.ldz, lds.H, p.y,
-                               (signed char *)p.out0, (float2 *)p.out1, (float *)p.out2,
-                               sh.zsh[wave], lanep);
+                    decode_vpp(sh.lvs[wavep], ng, sc, sym0 + r, p.n_sym, p.n_rows, p.n_cols,
+                               p.tau, lds.Z, lds.ldz, lds.H, p.y, (signed char *)p.out0,
+                               (float2 *)p.out1, (float *)p.out2, sh.zsh[wavep], lanep);
                 }
                 wave_sync_lds();
             }
