@@ -115,7 +115,25 @@ def sched_work(j, sc):
     if st:
         q = 2
     a = float(n) * sc["chains"] * sc["sweeps"] * K * q * max(st, 1)
+    if sc.get("guesses", 0) == 3:          # MMGaP-E: a search from each guess
+        a *= 2
     return a, a * ops_per_attempt(K, q)
+
+
+def anneal_calls(sc) -> int:
+    """Anneal launches of one job through the separate-launch entry points."""
+    g = sc.get("guesses", 0)
+    return max(sc.get("stages", 0), 1) * (2 if g == 3 else 1)
+
+
+def sched_desc(s) -> str:
+    g = s.get("guesses", 0)
+    if not g:
+        return f"{s['chains']} chains x {s['sweeps']} sweeps, " \
+               f"{'fallback' if s['init'] else 'random'} start"
+    src = {1: "around the MMSE guess", 2: "around the MMSE-SIC guess",
+           3: "from both guesses, better answer (MMGaP-E)"}[g]
+    return f"{s['chains']} chains x {s['sweeps']} sweeps x {s['stages']} stage(s) {src}"
 
 
 def levels_to_symbols(lv: np.ndarray, qam: int) -> np.ndarray:
@@ -661,10 +679,7 @@ def main(argv=None) -> int:  # noqa: C901
         el, lat, t_out, _ = fused_leg(t_scheds)
         q_t = quality(inputs, t_out)
         tuned = leg_record(el, lat, q_t, {
-            "schedules": [f"{s['chains']} chains x {s['sweeps']} sweeps" +
-                          (f" x {s['stages']} stage(s) around the MMSE guess" if s.get("stages")
-                           else f", {'fallback' if s['init'] else 'random'} start")
-                          for s in t_scheds],
+            "schedules": [sched_desc(s) for s in t_scheds],
             "quality_matched": matched(q_t, q_ref)})
         legs["tuned"] = (el, lat, t_scheds)
 
@@ -696,6 +711,53 @@ def main(argv=None) -> int:  # noqa: C901
             "outputs_identical_to_tuned": same_bytes(d_out, t_out, ("sym", "metric")),
             "quality_matched": matched(q_d, q_ref)})
         legs["delta_separate"] = (el, lat, t_scheds)
+
+    # ---- the tuner's choice among every formulation (MMGaP-E and the MMSE-SIC
+    # guess included) through the separate-launch entry points
+    tuned_sep = None
+    if tuned is not None and is_det:
+        a_scheds = []
+        for inp, ts in zip(inputs, t_scheds):
+            j = inp["spec"]
+            sa = M.tuned_schedule(M.KIND_DET, j["rows"], j["cols"], j["qam"], inp["noise_var"],
+                                  any_formulation=True)
+            a_scheds.append(sa if sa["tuned"] else ts)
+        if any(s.get("guesses", 0) > 1 for s in a_scheds):
+            def sep_group(gi):
+                outs = []
+                for i in gidx[gi]:
+                    inp, sc, j = inputs[i], a_scheds[i], inputs[i]["spec"]
+                    g = sc.get("guesses", 0)
+                    if g > 1:
+                        o = ctx.detect_e(inp["H_d"], inp["y_d"], j["qam"], inp["noise_var"],
+                                         sc["chains"], sc["sweeps"], sc["beta2"], inp["seed"],
+                                         stages=sc["stages"], init=sc["init"], guesses=g)
+                    elif sc.get("stages"):
+                        o = ctx.detect_delta(inp["H_d"], inp["y_d"], j["qam"], inp["noise_var"],
+                                             sc["chains"], sc["sweeps"], sc["beta2"],
+                                             inp["seed"], stages=sc["stages"], init=sc["init"])
+                    else:
+                        o = ctx.detect(inp["H_d"], inp["y_d"], j["qam"], inp["noise_var"],
+                                       sc["chains"], sc["sweeps"], sc["beta2"], inp["seed"],
+                                       init=sc["init"])
+                    outs.append(dict(sym=o[0], metric=o[1]))
+                return outs
+
+            print("[bench] tuned leg, every formulation (separate launches)", file=sys.stderr,
+                  flush=True)
+            n_calls = sum(anneal_calls(s) for s in a_scheds)
+            ctx.set_profiling(True)
+            el, lat = timed(sep_group)
+            m = max(1, min(args.steps, 256 // n_calls))      # the library keeps 256 records
+            sprof = np.array(ctx.profile(m * n_calls)).reshape(m, n_calls, 3)
+            ctx.set_profiling(False)
+            s_out = host_outs([o for gi in range(len(groups)) for o in sep_group(gi)])
+            q_s = quality(inputs, s_out)
+            tuned_sep = leg_record(el, lat, q_s, {
+                "schedules": [sched_desc(s) for s in a_scheds],
+                "stage_ms": {"anneal": float(np.mean(sprof[:, :, 1].sum(axis=1)))},
+                "quality_matched": matched(q_s, q_ref)})
+            legs["tuned_separate"] = (el, lat, a_scheds)
 
     # ---- detection extras: MMGaP-E, MMSE-SIC, the SIC-guess search
     extras = {}
@@ -768,8 +830,7 @@ def main(argv=None) -> int:  # noqa: C901
                            ts["beta2"], mid["seed"], init=ts["init"], stages=st1)
         plan1 = ctx.plan_create([job1], graph=True)
         cp = {"instances": int(j["n_sym"]), "snr_db": j["snr"],
-              "fused_tuned": dict(schedule=tuned["schedules"][0] if tuned else None,
-                                  **lat_of(plan1.plan_launch))}
+              "fused_tuned": dict(schedule=sched_desc(ts), **lat_of(plan1.plan_launch))}
         plan1.plan_destroy()
         if st1:
             cp["mmgap_separate"] = lat_of(lambda: ctx.detect_delta(
@@ -812,6 +873,8 @@ def main(argv=None) -> int:  # noqa: C901
         cands.append(("tuned", tuned))
     if delta_sep is not None and delta_sep["quality_matched"]:
         cands.append(("delta_separate", delta_sep))
+    if tuned_sep is not None and tuned_sep["quality_matched"]:
+        cands.append(("tuned_separate", tuned_sep))
     sel_name, sel = min(cands, key=lambda c: c[1]["ms_per_step"])
     sel_el, sel_lat, sel_scheds = legs[sel_name]
     value = args.steps * total_inst / sel_el
@@ -829,13 +892,17 @@ def main(argv=None) -> int:  # noqa: C901
         kern_ms = plain["stage_ms"]["anneal"]
     elif sel_name == "delta_separate":
         kern_ms = delta_sep["stage_ms"]["anneal"]
+    elif sel_name == "tuned_separate":
+        kern_ms = tuned_sep["stage_ms"]["anneal"]
     else:
         kern_ms = float(sel_lat.mean(axis=0).sum())
     achieved = ops / (kern_ms * 1e-3)
-    kname = {"plain": "k_anneal", "delta_separate": "k_anneal (moves around the guess)"}.get(
+    kname = {"plain": "k_anneal", "delta_separate": "k_anneal (moves around the guess)",
+             "tuned_separate": "k_anneal (tuned formulations, separate launches)"}.get(
         sel_name, "k_fused" + (" (moves around the guess)" if any(s.get("stages")
                                                                    for s in sel_scheds) else ""))
-    tkey = {"plain": "k_anneal", "delta_separate": "k_anneal_delta"}.get(
+    tkey = {"plain": "k_anneal", "delta_separate": "k_anneal_delta",
+            "tuned_separate": "k_anneal_tuned_separate"}.get(
         sel_name, "k_fused_delta" if any(s.get("stages") for s in sel_scheds) else "k_fused")
 
     desc = []
@@ -874,7 +941,10 @@ def main(argv=None) -> int:  # noqa: C901
                      "tuned": "fused at the tuned schedules: one persistent launch per slot "
                               "(HIP graph), stages of moves around the MMSE guess inside it "
                               "where the tuner chose them",
-                     "delta_separate": "per stage: move fields, anneal and select launches"
+                     "delta_separate": "per stage: move fields, anneal and select launches",
+                     "tuned_separate": "the tuned formulation per slot (binary encoding, moves "
+                                       "around the MMSE or MMSE-SIC guess, or MMGaP-E) through "
+                                       "the separate build, anneal and select launches"
                      }[sel_name],
             "slots_per_step": len(groups),
             "instances_per_step": total_inst,
@@ -885,14 +955,15 @@ def main(argv=None) -> int:  # noqa: C901
         "flip_attempts_per_s": attempts * args.steps / sel_el,
         "quality_kind": ["ser" if j["kind"] == "det" else "mean_gamma" for j in specs],
         "quality_per_slot": {"slot": desc, "plain": q_ref,
-                             "reported": (tuned if sel_name == "tuned" else
-                                          delta_sep if sel_name == "delta_separate" else
-                                          fused if sel_name == "fused" else plain)["quality"]},
+                             "reported": {"tuned": tuned, "delta_separate": delta_sep,
+                                          "tuned_separate": tuned_sep, "fused": fused,
+                                          "plain": plain}[sel_name]["quality"]},
         "speedup_vs_plain": None if plain is None else value / plain["value"],
         "plain": plain,
         "fused_reference": fused,
         "tuned": tuned,
         "delta_separate": delta_sep,
+        "tuned_separate": tuned_sep,
         **extras,
         "roofline": {
             "bound": "alu", "kernel": kname,

@@ -196,12 +196,15 @@ _tuned_cache = {}
 
 
 def tuned_schedule(kind: int, n_rx: int, n_tx: int, qam: int, noise_var: float = 0.0,
-                   table: str = TUNED_TABLE) -> dict:
+                   table: str = TUNED_TABLE, any_formulation: bool = False) -> dict:
     """Schedule picked by the offline tuner (``python -m paper_2510_01579_amd.tune``)
-    for a job: dict(chains, sweeps, init, beta2, stages, tuned, snr_bucket);
-    stages >= 1 (detection only) selects moves around the MMSE guess with that
-    many stages (``det_job(..., stages=)``, ``detect_delta``), 0 the binary
-    encoding.
+    for a job: dict(chains, sweeps, init, beta2, stages, guesses, tuned,
+    snr_bucket); stages >= 1 (detection only) selects moves around a guess with
+    that many stages, 0 the binary encoding.  guesses is 0 for the binary
+    encoding, GUESS_MMSE for moves around the MMSE guess (``det_job(...,
+    stages=)``, ``detect_delta``), and -- only with any_formulation, which also
+    admits the formulations that run as separate launches -- GUESS_SIC or
+    GUESS_MMSE | GUESS_SIC (MMGaP-E) for ``detect_e``.
 
     Detection tables are bucketed by SNR = 10 log10(n_tx / noise_var) (per
     receive antenna, unit-energy symbols): the job takes the bucket of the
@@ -232,17 +235,20 @@ def tuned_schedule(kind: int, n_rx: int, n_tx: int, qam: int, noise_var: float =
                 if b["snr_db"] >= snr - 1e-3:
                     pick = b
                     break
-        sched = dict(pick["tuned"])
+        sched = dict(pick["tuned_any"] if any_formulation and "tuned_any" in pick
+                     else pick["tuned"])
         bucket = pick["snr_db"]
         tuned = True
     b0, b1 = _det_range(qam, n_rx, noise_var) if kind == KIND_DET else _vpp_range(qam)
     r, m = sched.get("shape", [0.0, 1.0])
     end = m * b1
     start = b0 if r == 0.0 else max(b0, r * end)
+    stages = int(sched.get("stages", 0))
     return dict(chains=int(sched["chains"]), sweeps=int(sched["sweeps"]),
                 init=int(sched["init"]), beta2=linear_beta2(int(sched["sweeps"]),
                                                             min(start, end), end),
-                stages=int(sched.get("stages", 0)), tuned=tuned, snr_bucket=bucket)
+                stages=stages, guesses=int(sched.get("guesses", GUESS_MMSE if stages else 0)),
+                tuned=tuned, snr_bucket=bucket)
 
 
 class Context:

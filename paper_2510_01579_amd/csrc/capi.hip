@@ -234,7 +234,12 @@ int end_call(mmgap_ctx *ctx, hipStream_t s)
 
 void prof_mark(mmgap_ctx *ctx, int i, hipStream_t s)
 {
-    if (ctx->profiling) (void)hipEventRecord(ctx->prof_ev[ctx->prof_count % kProfRing][i], s);
+    if (!ctx->profiling) return;
+    // a solver launch after the first of one call (stages, two guesses) opens
+    // its own record: its start is its schedule upload
+    if (i == 0) ctx->prof_open = true;
+    else if (i == 1 && !ctx->prof_open) (void)hipEventRecord(ctx->prof_ev[ctx->prof_count % kProfRing][0], s);
+    (void)hipEventRecord(ctx->prof_ev[ctx->prof_count % kProfRing][i], s);
 }
 
 // Copies the host schedule into a device ring slot; returns the device table.
@@ -337,7 +342,10 @@ int run_solver(mmgap_ctx *ctx, hipStream_t st, int n_inst, int K, int q, int KT,
     e = mmgap::launch_select(sel, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "select launch");
     prof_mark(ctx, 3, st);
-    if (ctx->profiling) ++ctx->prof_count;
+    if (ctx->profiling) {
+        ++ctx->prof_count;
+        ctx->prof_open = false;
+    }
     return MMGAP_OK;
 }
 
@@ -1304,6 +1312,7 @@ int mmgap_set_profiling(mmgap_ctx *ctx, int enable)
     }
     ctx->profiling = enable != 0;
     ctx->prof_count = 0;
+    ctx->prof_open = false;
     return MMGAP_OK;
 }
 

@@ -43,6 +43,7 @@ struct mmgap_ctx {
     uint32_t *accept_dev = nullptr;             // Metropolis threshold table
     bool profiling = false;
     long prof_count = 0;                        // profiled calls since enabling
+    bool prof_open = false;                     // the current record has its start event
     hipEvent_t prof_ev[mmgap::host::kProfRing][4] = {};   // start, before/after anneal, end
     int cus = 0;                                // compute units of the device
     int fused_per_cu[mmgap::kFusedClasses] = {};   // resident workgroups per CU, per class

@@ -1,12 +1,15 @@
 """Offline schedule tuner: per job class and SNR bucket, the cheapest anneal
 schedule whose quality stays within a tolerance of the class's reference
-schedule at that SNR.  Two formulations compete for detection classes:
+schedule at that SNR.  These formulations compete for detection classes:
 
 * the binary encoding (paper §2.3 reduction with log2(M)/2 spins per real
   dimension): chains, sweeps, start state, temperature shape;
 * moves around the MMSE guess (paper §2.3 Fig. 5, the Delta-Ising form; §3.2
   stages each starting from the previous stage's answer): chains, sweeps per
-  stage and the number of stages, run as stages of the persistent kernel.
+  stage and the number of stages, run as stages of the persistent kernel;
+* moves around the MMSE-SIC guess, and MMGaP-E (paper §3.2 Fig. 6: the better
+  of the searches from both guesses), through the separate-launch entry point
+  (``tuned_any``; persistent plans take the best of the first two).
 
 A schedule is linear in beta from beta_start to beta_end.  The reference shape
 is the class's default range (beta0, beta1) of ``workload.synth``; a shape
@@ -74,6 +77,8 @@ DELTA_SWEEPS = (2, 4, 6, 8, 12, 16, 25, 50)
 DELTA_STAGES = (1, 2, 3, 4)
 DELTA_MAX_WORK = 3200
 SHAPES = ((0.0, 1.0), (1.0 / 16, 1.0), (1.0 / 4, 1.0), (1.0 / 16, 4.0))
+TIME_SPAN = 64.0             # timed candidates: up to this many times the cheapest's cost
+TIME_MAX = 48                #   and at most this many per SNR bucket
 TOLERANCE = 0.05             # the requirement: quality within 5% of the reference
 SELECT_TOLERANCE = 0.03      # used when choosing, so that other slots (other channel
                              # and noise draws) keep within TOLERANCE
@@ -86,13 +91,43 @@ def shaped_range(b0: float, b1: float, shape) -> tuple[float, float]:
     return min(start, end), end
 
 
+# guess sets of the searches around a guess (the formulation tag of a key)
+GUESS_TAGS = {1: "delta", 2: "sic", 3: "e"}
+TAG_GUESSES = {v: k for k, v in GUESS_TAGS.items()}
+
+
+def guesses_of(c) -> int:
+    """Guess set of a candidate: 0 binary encoding, 1 moves around the MMSE
+    guess, 2 around the MMSE-SIC guess, 3 MMGaP-E (both, the better answer)."""
+    if len(c) > 5:
+        return c[5]
+    return 1 if len(c) > 4 and c[4] else 0
+
+
 def schedule_key(c) -> str:
     C, S, init, shape = c[:4]
-    if len(c) > 4 and c[4]:
+    g = guesses_of(c)
+    if g:
+        tag = GUESS_TAGS[g]
         if tuple(shape) == SHAPES[0]:
-            return f"{C}x{S}x{c[4]}/delta"
-        return f"{C}x{S}x{c[4]}/delta/{shape[0]:g},{shape[1]:g}"
+            return f"{C}x{S}x{c[4]}/{tag}"
+        return f"{C}x{S}x{c[4]}/{tag}/{shape[0]:g},{shape[1]:g}"
     return f"{C}x{S}/{init}/{shape[0]:g},{shape[1]:g}"
+
+
+# MMGaP-E and the MMSE-SIC-guess search (separate launches only: persistent
+# plans run the binary encoding and moves around the MMSE guess)
+E_CHAINS = (4, 8, 16, 32)
+E_SWEEPS = (2, 4, 8, 12, 25)
+E_STAGES = (1, 2, 3)
+E_SHAPES = ((0.0, 1.0), (0.25, 1.0))
+E_MAX_WORK = 1600
+
+
+def e_candidates():
+    """(chains, sweeps, 0, shape, stages, guesses) for guesses 2 (MMSE-SIC) and 3 (both)."""
+    return [(C, S, 0, sh, st, g) for g in (2, 3) for C in E_CHAINS for S in E_SWEEPS
+            for st in E_STAGES for sh in E_SHAPES if C * S * st <= E_MAX_WORK]
 
 
 def delta_candidates():
@@ -116,36 +151,50 @@ def lanes_per_instance(chains: int) -> int:
     return 64 * math.ceil(chains / 64)
 
 
-def cost(name, chains, sweeps, stages=0) -> float:
+def cost(name, chains, sweeps, stages=0, guesses=None) -> float:
     """Lane-operations of one instance's anneals.  Moves around a guess anneal
     two unit-weight spins per real dimension in each stage and add, per stage
     and instance lane, the move fields and the two energies of the move's
-    acceptance (about 3 KT^2 operations)."""
+    acceptance (about 3 KT^2 operations).  A search from the MMSE-SIC guess
+    adds that guess (about 4 KT^3 float64 operations per instance); MMGaP-E
+    runs both searches."""
     kind, rows, cols, qam = parse_class(name)
     K = 2 * (cols if kind == "det" else rows)
     q = {4: 1, 16: 2, 64: 3}[qam] if kind == "det" else 2
     KT = 8 if K <= 8 else (16 if K <= 16 else 32)
+    if guesses is None:
+        guesses = 1 if stages else 0
     if stages:
         per = lanes_per_instance(chains) * sweeps * KT * 2 * (18.5 + KT / 2)
-        return stages * (per + 3.0 * KT * KT * lanes_per_instance(chains))
+        one = stages * (per + 3.0 * KT * KT * lanes_per_instance(chains))
+        sic = 4.0 * KT ** 3
+        return {1: one, 2: one + sic, 3: 2 * one + sic}[guesses]
     return lanes_per_instance(chains) * sweeps * KT * q * (18.5 + KT / q)
 
 
+def cand_cost(name, c) -> float:
+    return cost(name, c[0], c[1], c[4] if len(c) > 4 else 0, guesses_of(c))
+
+
 def parse_key_of(t):
-    """The candidate tuple of a table entry's "tuned" record."""
-    return (t["chains"], t["sweeps"], t["init"], tuple(t["shape"]), t.get("stages", 0))
+    """The candidate tuple of a table entry's "tuned" (or "tuned_any") record."""
+    c = (t["chains"], t["sweeps"], t["init"], tuple(t["shape"]), t.get("stages", 0))
+    g = t.get("guesses", 1 if c[4] else 0)
+    return c + (g,) if g > 1 else c
 
 
 def parse_key(key):
     """(chains, sweeps, init, shape, stages) of a schedule key."""
     sched, rest = key.split("/", 1)
-    if rest == "delta" or rest.startswith("delta/"):
+    tag = rest.split("/", 1)[0]
+    if tag in TAG_GUESSES:
         C, S, st = (int(v) for v in sched.split("x"))
         shape = SHAPES[0]
-        if rest != "delta":
+        if rest != tag:
             r, m = (float(v) for v in rest.split("/", 1)[1].split(","))
             shape = (r, m)
-        return C, S, 0, shape, st
+        g = TAG_GUESSES[tag]
+        return (C, S, 0, shape, st) + ((g,) if g > 1 else ())
     init, shape = rest.split("/")
     C, S = (int(v) for v in sched.split("x"))
     r, m = (float(v) for v in shape.split(","))
@@ -154,20 +203,42 @@ def parse_key(key):
 
 def select(name, rec):
     """Per SNR bucket, the cheapest measured schedule within SELECT_TOLERANCE of
-    the reference at that SNR (ties: fewer chains, fewer sweeps)."""
+    the reference at that SNR (ties: fewer chains, fewer sweeps): "tuned" among
+    the formulations persistent plans run (the binary encoding, moves around
+    the MMSE guess), "tuned_any" among all (adding the MMSE-SIC-guess search and
+    MMGaP-E, which run as separate launches)."""
     ref = rec["reference"]
     ref_cost = cost(name, ref["chains"], ref["sweeps"])
     buckets = []
+
+    def record(best):
+        t = {"chains": best[0], "sweeps": best[1], "init": best[2], "shape": list(best[3]),
+             "stages": best[4]}
+        if guesses_of(best) > 1:
+            t["guesses"] = guesses_of(best)
+        return t
+
     for r in rec["per_snr"]:
         ok = [parse_key(k) for k, v in r["cands"].items()
               if v <= (1 + SELECT_TOLERANCE) * r["ref"] + 2e-5]
-        best = min(ok, key=lambda c: (cost(name, c[0], c[1], c[4]), c[4], c[0], c[1], c[2],
-                                      c[3]))
-        buckets.append({"snr_db": r["snr_db"],
-                        "tuned": {"chains": best[0], "sweeps": best[1], "init": best[2],
-                                  "shape": list(best[3]), "stages": best[4]},
-                        "quality": r["cands"][schedule_key(best)], "ref_quality": r["ref"],
-                        "cost_ratio": ref_cost / cost(name, best[0], best[1], best[4])})
+        order = lambda c: (cand_cost(name, c), c[4], guesses_of(c), c[0], c[1], c[2], c[3])
+        best = min((c for c in ok if guesses_of(c) <= 1), key=order)
+        # through separate launches the fixed costs of the builds, the MMSE-SIC
+        # guess, the selections and every stage's launches weigh in: the
+        # measured time per slot decides among the candidates that were timed
+        timed = r.get("ms", {})
+        okt = [c for c in ok if schedule_key(c) in timed]
+        best_any = min(okt, key=lambda c: (timed[schedule_key(c)],) + order(c)) if okt \
+            else min(ok, key=order)
+        b = {"snr_db": r["snr_db"], "tuned": record(best),
+             "quality": r["cands"][schedule_key(best)], "ref_quality": r["ref"],
+             "cost_ratio": ref_cost / cand_cost(name, best)}
+        if best_any != best:
+            b["tuned_any"] = record(best_any)
+            b["quality_any"] = r["cands"][schedule_key(best_any)]
+            if schedule_key(best_any) in timed:
+                b["ms_any"] = timed[schedule_key(best_any)]
+        buckets.append(b)
     return buckets
 
 
@@ -184,16 +255,21 @@ def measure(ctx, name, snr, schedules, n_sc, n_sym, seed):
         d = W.det_slot(seed, rows, cols, qam, n_sc, n_sym, snr)
         H, y = torch.from_numpy(d.H).to(dev), torch.from_numpy(d.y).to(dev)
         truth = torch.from_numpy(d.sym.reshape(n_sc * n_sym, cols)).to(dev)
-        for (C, S, init, shape, st) in schedules:
+        for c in schedules:
+            C, S, init, shape, st = c[:5]
+            g = guesses_of(c)
             rng = shaped_range(*W.det_beta_range(qam, rows, d.noise_var), shape)
             beta2 = W.linear_beta2(S, *rng)
-            if st:
+            if g > 1:
+                sym, _, _ = ctx.detect_e(H, y, qam, d.noise_var, C, S, beta2, W.job_seed(seed),
+                                         stages=st, init=init, metric=False, guesses=g)
+            elif st:
                 sym, _ = ctx.detect_delta(H, y, qam, d.noise_var, C, S, beta2, W.job_seed(seed),
                                           stages=st, init=init, metric=False)
             else:
                 sym, _ = ctx.detect(H, y, qam, d.noise_var, C, S, beta2, W.job_seed(seed),
                                     init=init, metric=False)
-            out[(C, S, init, shape, st)] = float((sym != truth).float().mean().item())
+            out[c] = float((sym != truth).float().mean().item())
     else:
         s = W.vpp_slot(seed, rows, cols, qam, n_sc, n_sym)
         H, u = torch.from_numpy(s.H).to(dev), torch.from_numpy(s.u).to(dev)
@@ -202,6 +278,42 @@ def measure(ctx, name, snr, schedules, n_sc, n_sym, seed):
             _, _, g = ctx.vpp_precode(H, u, qam, C, S, beta2, W.job_seed(seed), init=init,
                                       want_x=False)
             out[(C, S, init, shape, 0)] = float(g.double().mean().item())
+    return out
+
+
+def time_candidates(ctx, name, snr, cands, n_sc, n_sym, seed, reps=3):
+    """Median milliseconds per slot of each candidate through the separate-launch
+    entry points (mmgap_detect, mmgap_detect_delta, mmgap_detect_e)."""
+    import torch
+    from workload import synth as W
+    kind, rows, cols, qam = parse_class(name)
+    dev = torch.device("cuda", ctx.device)
+    d = W.det_slot(seed, rows, cols, qam, n_sc, n_sym, snr)
+    H, y = torch.from_numpy(d.H).to(dev), torch.from_numpy(d.y).to(dev)
+    out = {}
+    for c in cands:
+        C, S, init, shape, st = c[:5]
+        g = guesses_of(c)
+        beta2 = W.linear_beta2(S, *shaped_range(*W.det_beta_range(qam, rows, d.noise_var),
+                                                shape))
+        if g > 1:
+            fn = lambda: ctx.detect_e(H, y, qam, d.noise_var, C, S, beta2, W.job_seed(seed),
+                                      stages=st, init=init, metric=False, guesses=g)
+        elif st:
+            fn = lambda: ctx.detect_delta(H, y, qam, d.noise_var, C, S, beta2, W.job_seed(seed),
+                                          stages=st, init=init, metric=False)
+        else:
+            fn = lambda: ctx.detect(H, y, qam, d.noise_var, C, S, beta2, W.job_seed(seed),
+                                    init=init, metric=False)
+        fn()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        for a, b in ev:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        out[c] = float(np.median([a.elapsed_time(b) for a, b in ev]))
     return out
 
 
@@ -218,6 +330,13 @@ def main(argv=None) -> int:
     ap.add_argument("--add-delta", action="store_true",
                     help="measure only the moves-around-the-guess candidates of the detection "
                          "classes and add them to the table in --out (same slots and seeds)")
+    ap.add_argument("--add-e", action="store_true",
+                    help="measure only the MMSE-SIC-guess and MMGaP-E candidates of the "
+                         "detection classes and add them to the table in --out")
+    ap.add_argument("--time", action="store_true",
+                    help="time the detection candidates within the selection margin through "
+                         "the separate-launch entry points (cheapest by the cost model first, "
+                         "up to TIME_SPAN times its cost) and add the times to --out")
     args = ap.parse_args(argv)
 
     if args.reselect:
@@ -245,12 +364,38 @@ def main(argv=None) -> int:
             old = json.load(fh)
         if old.get("slot") == table["slot"]:
             table["classes"].update(old.get("classes", {}))
-    if args.add_delta:
+    if args.time:
         for name in args.classes:
             if not name.startswith("det") or name not in table["classes"]:
                 continue
             rec = table["classes"][name]
-            cands = delta_candidates()
+            t0 = time.time()
+            for k, r in enumerate(rec["per_snr"]):
+                ok = sorted((parse_key(key) for key, v in r["cands"].items()
+                             if v <= (1 + SELECT_TOLERANCE) * r["ref"] + 2e-5),
+                            key=lambda c: cand_cost(name, c))
+                lo = cand_cost(name, ok[0])
+                todo = [c for c in ok if cand_cost(name, c) <= TIME_SPAN * lo][:TIME_MAX]
+                ms = time_candidates(ctx, name, r["snr_db"], todo, args.n_sc, args.n_sym,
+                                     args.seed + 17 * k)
+                r["ms"] = {schedule_key(c): v for c, v in ms.items()}
+            rec["buckets"] = select(name, rec)
+            print(f"{name}: " + ", ".join(
+                f"{b['snr_db']} dB any "
+                f"{schedule_key(parse_key_of(b.get('tuned_any', b['tuned'])))} "
+                f"{b.get('ms_any', float('nan')):.3f} ms" for b in rec["buckets"])
+                + f" ({time.time() - t0:.1f} s)", flush=True)
+            with open(args.out, "w") as fh:
+                json.dump(table, fh, indent=1)
+        ctx.close()
+        return 0
+    if args.add_delta or args.add_e:
+        for name in args.classes:
+            if not name.startswith("det") or name not in table["classes"]:
+                continue
+            rec = table["classes"][name]
+            cands = (delta_candidates() if args.add_delta else []) + \
+                (e_candidates() if args.add_e else [])
             t0 = time.time()
             for k, r in enumerate(rec["per_snr"]):
                 q = measure(ctx, name, r["snr_db"], cands, args.n_sc, args.n_sym,
@@ -259,7 +404,9 @@ def main(argv=None) -> int:
             rec["buckets"] = select(name, rec)
             print(f"{name}: " + ", ".join(
                 f"{b['snr_db']} dB {schedule_key(parse_key_of(b['tuned']))} "
-                f"(x{b['cost_ratio']:.1f})" for b in rec["buckets"])
+                f"(x{b['cost_ratio']:.1f})"
+                + (f" / any {schedule_key(parse_key_of(b['tuned_any']))}"
+                   if "tuned_any" in b else "") for b in rec["buckets"])
                 + f" ({time.time() - t0:.1f} s)", flush=True)
             with open(args.out, "w") as fh:
                 json.dump(table, fh, indent=1)
@@ -273,7 +420,7 @@ def main(argv=None) -> int:
                         if cost(name, C, S) <= cost(name, ref[0], ref[1])} | {ref},
                        key=lambda s: (cost(name, s[0], s[1]), s))
         if name.startswith("det"):
-            cands += delta_candidates()
+            cands += delta_candidates() + e_candidates()
         t0 = time.time()
         per_snr = []
         for k, snr in enumerate(spec["snr"]):

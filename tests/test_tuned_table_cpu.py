@@ -31,16 +31,27 @@ def test_every_choice_meets_the_selection_margin_and_is_not_dearer(table):
         ref = rec["reference"]
         for b, meas in zip(rec["buckets"], rec["per_snr"]):
             cand = T.parse_key_of(b["tuned"])
-            q = meas["cands"][T.schedule_key(cand)]
-            assert q <= (1 + table["select_tolerance"]) * meas["ref"] + 2e-5, (name, b)
-            assert T.cost(name, cand[0], cand[1], cand[4]) <= \
-                T.cost(name, ref["chains"], ref["sweeps"])
-            # no measured candidate within the margin is cheaper
+            assert T.guesses_of(cand) <= 1, (name, b)     # plans run these formulations
+            cand_any = T.parse_key_of(b.get("tuned_any", b["tuned"]))
+            for c0 in (cand, cand_any):
+                q = meas["cands"][T.schedule_key(c0)]
+                assert q <= (1 + table["select_tolerance"]) * meas["ref"] + 2e-5, (name, b)
+                assert T.cand_cost(name, c0) <= T.cost(name, ref["chains"], ref["sweeps"])
+            timed = meas.get("ms", {})
+            if T.schedule_key(cand_any) not in timed:
+                assert T.cand_cost(name, cand_any) <= T.cand_cost(name, cand)
+            # no measured candidate within the margin is cheaper (by the cost model
+            # among the plan formulations; by measured time, where timed, among all)
             for key, v in meas["cands"].items():
                 c = T.parse_key(key)
                 if v <= (1 + table["select_tolerance"]) * meas["ref"] + 2e-5:
-                    assert T.cost(name, c[0], c[1], c[4]) >= T.cost(name, cand[0], cand[1],
-                                                                    cand[4]), (name, key)
+                    if T.guesses_of(c) <= 1:
+                        assert T.cand_cost(name, c) >= T.cand_cost(name, cand), (name, key)
+                    if T.schedule_key(cand_any) in timed:
+                        if key in timed:
+                            assert timed[key] >= timed[T.schedule_key(cand_any)], (name, key)
+                    else:
+                        assert T.cand_cost(name, c) >= T.cand_cost(name, cand_any), (name, key)
 
 
 def test_reselect_reproduces_the_table(table, tmp_path):
@@ -80,8 +91,29 @@ def test_unknown_class_gets_the_reference_schedule():
 
 def test_schedule_keys_round_trip():
     for c in [(64, 50, 1, (0.0, 1.0), 0), (16, 12, 0, (0.0, 1.0), 2),
-              (8, 4, 0, (0.0625, 4.0), 0)]:
+              (8, 4, 0, (0.0625, 4.0), 0), (16, 4, 0, (0.25, 1.0), 1, 3),
+              (4, 2, 0, (0.0, 1.0), 2, 2), (16, 8, 0, (0.25, 1.0), 3)]:
         assert T.parse_key(T.schedule_key(c)) == c
+    for c in T.delta_candidates() + T.e_candidates():
+        assert T.parse_key(T.schedule_key(c)) == c
+
+
+def test_any_formulation_returns_the_guess_set(table):
+    """tuned_schedule(any_formulation=True) hands MMGaP-E or the MMSE-SIC-guess
+    search to detect_e where the tuner chose them; plans never see them."""
+    for name, rec in table["classes"].items():
+        kind, rows, cols, qam = T.parse_class(name)
+        if kind != "det":
+            continue
+        for b in rec["buckets"]:
+            nv = W.noise_var(b["snr_db"], cols)
+            t = M.tuned_schedule(M.KIND_DET, rows, cols, qam, nv)
+            ta = M.tuned_schedule(M.KIND_DET, rows, cols, qam, nv, any_formulation=True)
+            assert t["guesses"] == (M.GUESS_MMSE if t["stages"] else 0)
+            want = b.get("tuned_any", b["tuned"])
+            assert ta["guesses"] == want.get("guesses", M.GUESS_MMSE if want["stages"] else 0)
+            assert (ta["chains"], ta["sweeps"], ta["stages"]) == \
+                (want["chains"], want["sweeps"], want["stages"])
 
 
 def test_tuned_schedule_returns_the_stage_count(table):
