@@ -120,6 +120,13 @@ def sched_work(j, sc):
     return a, a * ops_per_attempt(K, q)
 
 
+def guess_arg(sc) -> int:
+    """det_job's guesses for a schedule: 0 unless it searches from the MMSE-SIC
+    guess (alone or in MMGaP-E)."""
+    g = sc.get("guesses", 0)
+    return g if g > 1 else 0
+
+
 def anneal_calls(sc) -> int:
     """Anneal launches of one job through the separate-launch entry points."""
     g = sc.get("guesses", 0)
@@ -202,7 +209,11 @@ def cpu_baseline(inputs, scheds, target_s: float, cim=None):
             j = inp["spec"]
             m = max(1, min(n_all, int(round(frac * n_all))))
             ids = np.sort(rng.choice(n_all, m, replace=False)).astype(np.uint32)
-            if j["kind"] == "det" and sc.get("stages"):
+            if j["kind"] == "det" and sc.get("guesses", 0) > 1:
+                O.detect_e(inp["H"], inp["y"], inp["noise_var"], j["qam"], sc["chains"],
+                           sc["sweeps"], sc["beta2"], inp["seed"], stages=sc["stages"],
+                           inst_ids=ids, init_mode=sc["init"], cim=cim, guesses=sc["guesses"])
+            elif j["kind"] == "det" and sc.get("stages"):
                 O.detect_delta(inp["H"], inp["y"], inp["noise_var"], j["qam"], sc["chains"],
                                sc["sweeps"], sc["beta2"], inp["seed"], stages=sc["stages"],
                                inst_ids=ids, init_mode=sc["init"], cim=cim)
@@ -273,7 +284,7 @@ def serve_mix(M, torch, n_sat: int, n_arr: int, n_full: int):
         if kind == "det":
             return ctx.det_job(p["H"], p["y"], qam, p["nv"], sc["chains"], sc["sweeps"],
                                sc["beta2"], W.job_seed(k), init=sc["init"], metric=False,
-                               stages=sc["stages"])
+                               stages=sc["stages"], guesses=guess_arg(sc))
         return ctx.vpp_job(p["H"], p["y"], qam, sc["chains"], sc["sweeps"], sc["beta2"],
                            W.job_seed(k), want_x=False, want_gamma=False, init=sc["init"])
 
@@ -594,7 +605,8 @@ def main(argv=None) -> int:  # noqa: C901
                 if j["kind"] == "det":
                     gj.append(ctx.det_job(inp["H_d"], inp["y_d"], j["qam"], inp["noise_var"],
                                           sc["chains"], sc["sweeps"], sc["beta2"], inp["seed"],
-                                          init=sc["init"], stages=sc.get("stages", 0)))
+                                          init=sc["init"], stages=sc.get("stages", 0),
+                                          guesses=guess_arg(sc)))
                 else:
                     gj.append(ctx.vpp_job(inp["H_d"], inp["y_d"], j["qam"], sc["chains"],
                                           sc["sweeps"], sc["beta2"], inp["seed"],
@@ -685,7 +697,8 @@ def main(argv=None) -> int:  # noqa: C901
 
     # ---- the tuned stages through the multi-launch entry point
     delta_sep = None
-    if tuned is not None and is_det and all(s.get("stages") for s in t_scheds):
+    if tuned is not None and is_det and all(s.get("stages") and s.get("guesses", 1) <= 1
+                                            for s in t_scheds):
         def delta_group(gi):
             outs = []
             for i in gidx[gi]:
@@ -827,12 +840,17 @@ def main(argv=None) -> int:  # noqa: C901
             return pct([a.elapsed_time(b) for a, b in ev])
 
         job1 = ctx.det_job(H1, y1, j["qam"], mid["noise_var"], ts["chains"], ts["sweeps"],
-                           ts["beta2"], mid["seed"], init=ts["init"], stages=st1)
+                           ts["beta2"], mid["seed"], init=ts["init"], stages=st1,
+                           guesses=guess_arg(ts))
         plan1 = ctx.plan_create([job1], graph=True)
         cp = {"instances": int(j["n_sym"]), "snr_db": j["snr"],
               "fused_tuned": dict(schedule=sched_desc(ts), **lat_of(plan1.plan_launch))}
         plan1.plan_destroy()
-        if st1:
+        if st1 and ts.get("guesses", 0) > 1:
+            cp["mmgap_separate"] = lat_of(lambda: ctx.detect_e(
+                H1, y1, j["qam"], mid["noise_var"], ts["chains"], ts["sweeps"], ts["beta2"],
+                mid["seed"], stages=st1, guesses=ts["guesses"]))
+        elif st1:
             cp["mmgap_separate"] = lat_of(lambda: ctx.detect_delta(
                 H1, y1, j["qam"], mid["noise_var"], ts["chains"], ts["sweeps"], ts["beta2"],
                 mid["seed"], stages=st1))

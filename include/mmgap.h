@@ -353,7 +353,10 @@ int mmgap_vpp_precode(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, 
  * stages = 0: the problem as mmgap_detect / mmgap_vpp_precode solve it; DET
  * with stages >= 1: detection by moves around the sliced MMSE estimate as
  * mmgap_detect_delta with that many stages (the stages of a work item run
- * inside the item's workgroup).
+ * inside the item's workgroup), or, with guesses != 0, as mmgap_detect_e with
+ * those guesses (paper §3.2 Fig. 6, MMGaP-E; the MMSE-SIC guess of a work
+ * item is computed in its workgroup after the build); out2 then takes
+ * from_sic_out [n_sc*n_sym] uint8 (nullable).
  * Every output of a job is bit-identical to that of the single-job entry point
  * on the same arguments, whatever else is in the batch: a chain's random stream
  * depends only on the job's seed and its instance and chain index.
@@ -366,7 +369,11 @@ typedef struct {
     const void *H;            /* device, [n_sc][n_rx][n_tx] complex64 */
     const void *y_or_u;       /* device, [n_sc][n_sym][n_rx] complex64 */
     void *out0, *out1, *out2; /* device, see above */
-    int stages;               /* 0, or DET: stages of moves around the MMSE estimate (1..64) */
+    int stages;               /* 0, or DET: stages of moves around a guess (1..64) */
+    int guesses;              /* DET with stages >= 1: 0 (= MMGAP_GUESS_MMSE) or a set of
+                                 MMGAP_GUESS_* as for mmgap_detect_e; MMGAP_GUESS_SIC needs
+                                 the MMSE-SIC factors to fit a work item's LDS (16 x 16 up to
+                                 34 receive antennas; 8 users up to 27); out2 = from_sic_out */
 } mmgap_job;
 
 typedef struct mmgap_plan mmgap_plan;

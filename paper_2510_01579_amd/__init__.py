@@ -84,7 +84,8 @@ CIM_STEPS = 128
 class Job(ctypes.Structure):
     _fields_ = [("prob", Problem), ("sched", Schedule), ("H", ctypes.c_void_p),
                 ("y_or_u", ctypes.c_void_p), ("out0", ctypes.c_void_p),
-                ("out1", ctypes.c_void_p), ("out2", ctypes.c_void_p), ("stages", ctypes.c_int)]
+                ("out1", ctypes.c_void_p), ("out2", ctypes.c_void_p), ("stages", ctypes.c_int),
+                ("guesses", ctypes.c_int)]
 
 
 _lib = None
@@ -201,10 +202,11 @@ def tuned_schedule(kind: int, n_rx: int, n_tx: int, qam: int, noise_var: float =
     for a job: dict(chains, sweeps, init, beta2, stages, guesses, tuned,
     snr_bucket); stages >= 1 (detection only) selects moves around a guess with
     that many stages, 0 the binary encoding.  guesses is 0 for the binary
-    encoding, GUESS_MMSE for moves around the MMSE guess (``det_job(...,
-    stages=)``, ``detect_delta``), and -- only with any_formulation, which also
-    admits the formulations that run as separate launches -- GUESS_SIC or
-    GUESS_MMSE | GUESS_SIC (MMGaP-E) for ``detect_e``.
+    encoding, GUESS_MMSE for moves around the MMSE guess (``detect_delta``),
+    GUESS_SIC or GUESS_MMSE | GUESS_SIC (MMGaP-E) for ``detect_e``; batch jobs
+    take stages and guesses (``det_job``).  The default is the tuner's choice by
+    its cost model; any_formulation=True takes its choice by measured time per
+    slot through the separate-launch entry points, where it timed candidates.
 
     Detection tables are bucketed by SNR = 10 log10(n_tx / noise_var) (per
     receive antenna, unit-energy symbols): the job takes the bucket of the
@@ -548,20 +550,24 @@ class Context:
 
     # ------------------------------------------------------------------ batches
     def det_job(self, H, y, qam, noise_var, chains, sweeps, beta2, seed, init=0, metric=True,
-                stages=0, inst_base=0):
+                stages=0, inst_base=0, guesses=0):
         """A detection job for ``plan_create`` with its output tensors allocated:
         outputs["sym"] uint8 [n][n_tx], outputs["metric"] float32 [n] or None.
-        stages >= 1: detection by moves around the MMSE estimate (detect_delta)."""
+        stages >= 1: detection by moves around the MMSE estimate (detect_delta),
+        or with guesses (GUESS_MMSE, GUESS_SIC or both) as detect_e, and then
+        outputs["from_sic"] uint8 [n]."""
         torch = _torch()
         p = self._problem(KIND_DET, H, y, qam, noise_var, 0.0)
         n = p.n_sc * p.n_sym
         dev = self._dev()
         out = dict(sym=torch.empty((n, p.n_tx), dtype=torch.uint8, device=dev),
                    metric=torch.empty((n,), dtype=torch.float32, device=dev) if metric else None)
+        if guesses:
+            out["from_sic"] = torch.empty((n,), dtype=torch.uint8, device=dev)
         s, keep = self._schedule(chains, sweeps, beta2, seed, init, None, inst_base)
         job = Job(p, s, _ptr(H).value, _ptr(y).value, _ptr(out["sym"]).value,
-                  None if out["metric"] is None else _ptr(out["metric"]).value, None,
-                  int(stages))
+                  None if out["metric"] is None else _ptr(out["metric"]).value,
+                  _ptr(out["from_sic"]).value if guesses else None, int(stages), int(guesses))
         return dict(job=job, keep=(H, y, keep), outputs=out)
 
     def vpp_job(self, H, u, qam, chains, sweeps, beta2, seed, tau=0.0, want_x=True,

@@ -354,7 +354,8 @@ int run_solver(mmgap_ctx *ctx, hipStream_t st, int n_inst, int K, int q, int KT,
 // by the Q attempts of a dimension, once per stage.
 double item_cost(const mmgap::FusedJob &j)
 {
-    return (double)j.sweeps * j.KT * (20.0 * j.Q + j.KT) * (j.stages > 0 ? j.stages : 1);
+    return (double)j.sweeps * j.KT * (20.0 * j.Q + j.KT) * (j.stages > 0 ? j.stages : 1) *
+           (j.guesses == 3 ? 2 : 1);
 }
 
 }  // namespace
@@ -386,10 +387,18 @@ int batch_layout(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, BatchLayout 
                         mmgap::kMaxStages);
         if (jb.stages > 0 && jb.prob.kind != MMGAP_KIND_DET)
             return fail(ctx, MMGAP_EUNSUPPORTED, "job %d: stages apply to detection only", j);
+        if (jb.guesses < 0 || jb.guesses > (MMGAP_GUESS_MMSE | MMGAP_GUESS_SIC))
+            return fail(ctx, MMGAP_EINVAL, "job %d: guesses=%d is not 0 or a set of MMGAP_GUESS_*",
+                        j, jb.guesses);
+        if (jb.guesses > 0 && jb.stages < 1)
+            return fail(ctx, MMGAP_EINVAL, "job %d: guesses need stages >= 1", j);
         // moves around a guess: two unit-weight spins per real dimension
         const int aq = jb.stages > 0 ? 2 : sh.q;
         const int variant = mmgap::fused_variant(sh.KT, aq);
         if (variant < 0) return fail(ctx, MMGAP_EUNSUPPORTED, "job %d: no fused variant", j);
+        if ((jb.guesses & MMGAP_GUESS_SIC) && jb.prob.n_tx > 16)
+            return fail(ctx, MMGAP_EUNSUPPORTED, "job %d: MMSE-SIC supports n_tx <= 16 (got %d)",
+                        j, jb.prob.n_tx);
         const mmgap_problem &p = jb.prob;
         mmgap::FusedJob &f = L.jobs[j];
         f = mmgap::FusedJob{};
@@ -399,6 +408,7 @@ int batch_layout(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, BatchLayout 
         f.Q = aq;
         f.dq = sh.q;
         f.stages = jb.stages;
+        f.guesses = jb.guesses;
         f.K = sh.K;
         f.n_rows = p.n_rx;
         f.n_cols = p.n_tx;
@@ -455,6 +465,7 @@ int batch_layout(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, BatchLayout 
     L.of.resize(n_jobs);
     L.ofp.resize(n_jobs);
     L.ox.resize(n_jobs);
+    L.oxs.resize(n_jobs);
     for (int j = 0; j < n_jobs; ++j) L.ob[j] = lay.take(sizeof(float) * L.betas[j].size());
     L.header_bytes = lay.off;
     for (int j = 0; j < n_jobs; ++j) {
@@ -463,6 +474,7 @@ int batch_layout(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, BatchLayout 
         L.of[j] = lay.take(sizeof(float) * ni * f.ldf);
         L.ofp[j] = f.stages > 0 ? lay.take(sizeof(float) * ni * f.ldf) : 0;
         L.ox[j] = lay.take(ni * (size_t)f.KT);
+        L.oxs[j] = (f.guesses & MMGAP_GUESS_SIC) ? lay.take(ni * (size_t)f.KT) : 0;
     }
     L.bytes = lay.off;
     return MMGAP_OK;
@@ -476,6 +488,8 @@ void batch_bind(BatchLayout &L, char *base, std::vector<unsigned char> &image)
         f.f = reinterpret_cast<float *>(base + L.of[j]);
         f.fp = f.stages > 0 ? reinterpret_cast<float *>(base + L.ofp[j]) : nullptr;
         f.x_fb = reinterpret_cast<signed char *>(base + L.ox[j]);
+        f.x_sic = (f.guesses & MMGAP_GUESS_SIC) ? reinterpret_cast<signed char *>(base + L.oxs[j])
+                                                : nullptr;
     }
     image.assign(L.header_bytes, 0);
     if (!L.jobs.empty())
@@ -507,12 +521,32 @@ int batch_launch_config(mmgap_ctx *ctx, const BatchLayout &L, char *base, int bl
         b.blocks[c] = std::min(blocks > 0 ? blocks : ctx->fused_per_cu[c] * ctx->cus, b.count[c]);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "occupancy query");
+    for (size_t j = 0; j < L.jobs.size(); ++j) {
+        const mmgap::FusedJob &f = L.jobs[j];
+        if (!(f.guesses & MMGAP_GUESS_SIC) || f.n_sc * f.n_sym == 0) continue;
+        mmgap::SicArgs sa{};
+        sa.H = f.H;
+        sa.y = f.y;
+        sa.n_sc = f.n_sc;
+        sa.n_r = f.n_rows;
+        sa.n_t = f.n_cols;
+        sa.n_sym = f.n_sym;
+        sa.q = f.dq;
+        sa.c = f.c;
+        sa.noise_var = f.noise_var;
+        sa.levels = reinterpret_cast<signed char *>(base + L.oxs[j]);
+        sa.ldl = f.KT;
+        b.sic.push_back(sa);
+    }
     return MMGAP_OK;
 }
 
 hipError_t batch_enqueue(const BatchLaunch &b, const uint32_t *accept_table, hipStream_t st)
 {
     hipError_t e = mmgap::launch_fused_reset(b.counters, st);
+    // the MMSE-SIC guesses of the jobs that search from it, before the
+    // persistent kernels that read them
+    for (size_t k = 0; k < b.sic.size() && e == hipSuccess; ++k) e = mmgap::launch_sic(b.sic[k], st);
     for (int c = mmgap::kFusedClasses - 1; c >= 0 && e == hipSuccess; --c)
         e = mmgap::launch_fused(c, b.jobs, b.items + b.first[c], b.count[c], b.counters + c,
                                 accept_table, b.blocks[c], st);

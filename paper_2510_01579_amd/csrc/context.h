@@ -104,7 +104,7 @@ struct BatchLayout {
     std::vector<FusedJob> jobs;
     std::vector<FusedItem> items;
     std::vector<std::vector<float>> betas;
-    std::vector<size_t> of, ofp, ox, ob;
+    std::vector<size_t> of, ofp, ox, oxs, ob;
     size_t o_jobs = 0, o_items = 0, o_counters = 0;
     size_t header_bytes = 0;
     size_t bytes = 0;
@@ -121,6 +121,7 @@ void batch_bind(BatchLayout &lay, char *dev_base, std::vector<unsigned char> &im
 // One launch of a bound batch: counter reset, then one persistent kernel per
 // class present, largest class first.
 struct BatchLaunch {
+    std::vector<SicArgs> sic;       // MMSE-SIC launches of jobs with that guess
     FusedJob *jobs = nullptr;
     FusedItem *items = nullptr;
     unsigned int *counters = nullptr;

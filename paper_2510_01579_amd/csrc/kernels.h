@@ -199,7 +199,11 @@ struct FusedJob {
     float *f;               // [n_sc*n_sym][ldf] scratch
     float *fp;              // [n_sc*n_sym][ldf] scratch: move fields f - G x_g (stages > 0)
     signed char *x_fb;      // [n_sc*n_sym][KT] scratch
-    void *out0, *out1, *out2;   // DET: sym, metric; VPP: v, x, gamma
+    int guesses;            // stages > 0: chains from 1 the MMSE guess, 2 the MMSE-SIC
+                            // guess, 3 both (MMGaP-E: the better answer)
+    signed char *x_sic;     // [n_sc*n_sym][KT] scratch: the MMSE-SIC chain's guess, written
+                            // by the batch's MMSE-SIC launch before the persistent kernels
+    void *out0, *out1, *out2;   // DET: sym, metric, from-SIC flags; VPP: v, x, gamma
 };
 // A work item: symbols sym0..sym0+ns-1 of subcarrier sc of job `job`.
 struct FusedItem {

@@ -1511,6 +1511,212 @@ constexpr int kFusedBuildSyms = 16;   // symbols per build pass (an item may tak
 // State shared by every class: threshold table, per-wavefront selection and
 // decode scratch, the current item.  At namespace scope so that the
 // out-of-line variants address it as LDS.
+// ---------------------------------------------------------------------------
+// Ordered MMSE-SIC of one subcarrier per workgroup of one wavefront.  With
+// P = (H_R^H H_R + sigma^2 I)^-1 over the remaining users R, each step takes
+// the remaining user i with the smallest Re P_ii (the lowest index among
+// equals), its nulling row w = P_i,R H_R^H, and removes i from P by the Schur
+// complement P_jl -= P_ji P_il / P_ii.  The ordering and the nulling rows
+// depend on H only.  Then the symbols of the subcarrier are detected in
+// groups of g = 2^ceil(log2 n_r) lanes, one lane per receive antenna: each
+// lane holds one residual entry r_k in registers, the estimate w . r is a
+// shuffle reduction over the group, every lane slices it to the nearest odd
+// PAM level per real dimension, and subtracts h_ki s_i from its entry.  The
+// residual left after the last user is y - H x, whose squared norm is the
+// reported metric.  float64 throughout.
+//
+// Dynamic LDS: H (n_r x n_t complex float32), P (n_t x n_t complex float64),
+// the nulling rows W (n_t x n_r complex float64), and the levels of the
+// symbols of one pass (64 / g x 2 n_t ints).
+__host__ __device__ inline size_t sic_lds_bytes(int nr, int nt)
+{
+    int g = 1;
+    while (g < nr) g <<= 1;
+    return (size_t)nr * nt * 8 + (size_t)nt * nt * 16 + (size_t)nt * nr * 16 +
+           (size_t)(64 / g) * 2 * nt * 4 + 16 * 4;
+}
+
+__device__ __forceinline__ int sic_slice(double x, double c, int qtop)
+{
+    // clamped first (no effect on the sliced level) so that the conversion to
+    // int stays in range
+    const double t = fmin(fmax(x / c, -(double)(qtop + 2)), (double)(qtop + 2));
+    int v = 2 * (int)floor(t * 0.5) + 1;
+    return v < -qtop ? -qtop : (v > qtop ? qtop : v);
+}
+
+// Ordered MMSE-SIC of one subcarrier by one wavefront (lane 0..63): symbols
+// sym0 .. sym0 + ns - 1 of subcarrier sc.  Hs: the subcarrier's H in LDS,
+// [nr][nt]; LDS scratch P [nt][nt] and W [nt][nr] (float64 complex), lv
+// [spp][2 nt] and order [nt] (int), spp = min(64 / g, spp_cap) symbols per pass
+// with g = nr rounded up to a power of two.  Writes the levels (a.levels, row
+// stride a.ldl, zero beyond 2 nt), and if asked the symbols, residual metrics
+// and the detection order, all indexed by the slot's instance sc n_sym + sym.
+__device__ void sic_sc(const SicArgs &a, int sc, int sym0, int ns, const cf32 *Hs, double2 *P,
+                       double2 *W, int *lv, int *order, int spp_cap, int lane)
+{
+    const int nr = a.n_r, nt = a.n_t, qtop = (1 << a.q) - 1;
+    int g = 1;
+    while (g < nr) g <<= 1;
+    const int spp = min(64 / g, spp_cap);                   // symbols per pass
+    // A = H^H H + sigma^2 I
+    for (int e = lane; e < nt * nt; e += 64) {
+        const int i = e / nt, j = e % nt;
+        cd acc{0.0, 0.0};
+#pragma unroll 4
+        for (int r = 0; r < nr; ++r) {
+            const cf32 hi = Hs[r * nt + i], hj = Hs[r * nt + j];
+            const cd v = cmulc(cd{hi.x, hi.y}, cd{hj.x, hj.y});   // conj(h_ri) h_rj
+            acc.re = acc.re + v.re;
+            acc.im = acc.im + v.im;
+        }
+        if (i == j) acc.re = acc.re + a.noise_var;
+        P[e] = make_double2(acc.re, acc.im);
+    }
+    wave_sync_lds();
+    // in-place Gauss-Jordan inverse (Hermitian positive definite: no pivoting);
+    // each lane keeps its elements' row and column factors in registers
+    for (int k = 0; k < nt; ++k) {
+        const cd pk = ld2(P[k * nt + k]);
+        const double den = pk.re * pk.re + pk.im * pk.im;
+        const cd t{pk.re / den, -pk.im / den};
+        cd rowv[4], colv[4], old[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = lane + 64 * u;
+            if (e < nt * nt) {
+                const int i = e / nt, j = e % nt;
+                rowv[u] = j == k ? t : cmul(ld2(P[k * nt + j]), t);
+                colv[u] = ld2(P[i * nt + k]);
+                old[u] = ld2(P[e]);
+            }
+        }
+        wave_sync_lds();
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = lane + 64 * u;
+            if (e < nt * nt) {
+                const int i = e / nt, j = e % nt;
+                if (i == k) {
+                    P[e] = make_double2(rowv[u].re, rowv[u].im);
+                } else {
+                    const cd o = j == k ? cd{0.0, 0.0} : old[u];
+                    const cd m = cmul(colv[u], rowv[u]);
+                    P[e] = make_double2(o.re - m.re, o.im - m.im);
+                }
+            }
+        }
+        wave_sync_lds();
+    }
+    // ordering, nulling rows and downdates
+    uint32_t rem = nt >= 32 ? 0xFFFFFFFFu : ((1u << nt) - 1u);
+    for (int step = 0; step < nt; ++step) {
+        const bool mine = lane < nt && ((rem >> lane) & 1u);
+        const double d = mine ? P[lane * nt + lane].x : __builtin_inf();
+        double m = d;
+        for (int off = 32; off >= 1; off >>= 1) m = fmin(m, __shfl_xor(m, off, 64));
+        uint64_t ball = __ballot(mine && d == m);
+        if (ball == 0) ball = rem;              // no finite diagonal: the lowest remaining user
+        const int i = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)ball) - 1);
+        if (lane == 0) order[step] = i;
+        for (int r = lane; r < nr; r += 64) {
+            cd acc{0.0, 0.0};
+#pragma unroll 4
+            for (int j = 0; j < nt; ++j) {
+                if (!((rem >> j) & 1u)) continue;
+                const cf32 h = Hs[r * nt + j];
+                const cd v = cmulc(cd{h.x, h.y}, ld2(P[i * nt + j]));   // P_ij conj(h_rj)
+                acc.re = acc.re + v.re;
+                acc.im = acc.im + v.im;
+            }
+            W[step * nr + r] = make_double2(acc.re, acc.im);
+        }
+        // Schur complement of user i
+        const cd piv = ld2(P[i * nt + i]);
+        const double den = piv.re * piv.re + piv.im * piv.im;
+        const cd ip{piv.re / den, -piv.im / den};
+        const uint32_t keep = rem & ~(1u << i);
+        cd nv[4];
+        bool upd[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = lane + 64 * u;
+            upd[u] = false;
+            if (e < nt * nt) {
+                const int j = e / nt, l = e % nt;
+                if (((keep >> j) & 1u) && ((keep >> l) & 1u)) {
+                    const cd mm = cmul(cmul(ld2(P[j * nt + i]), ld2(P[i * nt + l])), ip);
+                    const cd o = ld2(P[e]);
+                    nv[u] = cd{o.re - mm.re, o.im - mm.im};
+                    upd[u] = true;
+                }
+            }
+        }
+        wave_sync_lds();
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (upd[u]) P[lane + 64 * u] = make_double2(nv[u].re, nv[u].im);
+        rem = keep;
+        wave_sync_lds();
+    }
+    if (a.order_out && lane < nt) a.order_out[(size_t)sc * nt + lane] = order[lane];
+    // detection: symbol sl = lane / g of the pass, receive antenna r = lane % g
+    const int sl = lane / g, r = lane % g;
+    for (int s0 = sym0; s0 < sym0 + ns; s0 += spp) {
+        const int sy = s0 + sl;
+        const bool act = sl < spp && sy < sym0 + ns && r < nr;
+        cd res{0.0, 0.0};
+        if (act) {
+            const float2 v = a.y[((size_t)sc * a.n_sym + sy) * nr + r];
+            res = cd{(double)v.x, (double)v.y};
+        }
+        for (int k = 0; k < nt; ++k) {
+            const int i = order[k];
+            cd prod{0.0, 0.0};
+            if (act) prod = cmul(ld2(W[k * nr + r]), res);
+            for (int off = g >> 1; off >= 1; off >>= 1) {
+                prod.re = prod.re + __shfl_xor(prod.re, off, 64);
+                prod.im = prod.im + __shfl_xor(prod.im, off, 64);
+            }
+            const int li = sic_slice(prod.re, a.c, qtop);
+            const int lq = sic_slice(prod.im, a.c, qtop);
+            if (act && r == 0) {
+                lv[sl * 2 * nt + i] = li;
+                lv[sl * 2 * nt + nt + i] = lq;
+            }
+            if (act) {
+                const cf32 h = Hs[r * nt + i];
+                const cd m = cmul(cd{h.x, h.y}, cd{a.c * (double)li, a.c * (double)lq});
+                res.re = res.re - m.re;
+                res.im = res.im - m.im;
+            }
+        }
+        // metric: the squared norm of the final residual y - H x
+        double e2 = act ? res.re * res.re + res.im * res.im : 0.0;
+        for (int off = g >> 1; off >= 1; off >>= 1) e2 = e2 + __shfl_xor(e2, off, 64);
+        wave_sync_lds();
+        const int cnt = min(spp, sym0 + ns - s0);
+        const size_t n0 = (size_t)sc * a.n_sym + s0;
+        if (a.levels) {
+            for (int e = lane; e < cnt * a.ldl; e += 64) {
+                const int s = e / a.ldl, k = e % a.ldl;
+                a.levels[(n0 + s) * a.ldl + k] = (signed char)(k < 2 * nt ? lv[s * 2 * nt + k] : 0);
+            }
+        }
+        if (a.sym_out) {
+            for (int e = lane; e < cnt * nt; e += 64) {
+                const int s = e / nt, t = e % nt;
+                const int pI = (lv[s * 2 * nt + t] + qtop) >> 1;
+                const int pQ = (lv[s * 2 * nt + nt + t] + qtop) >> 1;
+                const int gI = pI ^ (pI >> 1), gQ = pQ ^ (pQ >> 1);
+                a.sym_out[(n0 + s) * nt + t] = (unsigned char)((gI << a.q) | gQ);
+            }
+            if (a.metric_out && act && r == 0) a.metric_out[n0 + sl] = (float)e2;
+        }
+        wave_sync_lds();
+    }
+}
+
 // Instances of one packed work item: four wavefronts of at most 16 instances.
 constexpr int kMaxPackedItem = 64;
 struct FusedCommon {
@@ -1603,6 +1809,8 @@ struct FusedItemLds {
     const double2 *Z;
     int ldz;
     int stage;              // stage of a job of moves around a guess
+    int chain;              // 0 the chain from the MMSE guess, 1 from the MMSE-SIC guess
+    int last;               // the item's last anneal: decode (MMGaP-E: pick, then decode)
 };
 
 // Descriptor fields read after the anneal (through a laundered pointer, so
@@ -1614,7 +1822,8 @@ struct FusedPost {
     double c, tau;
     const float2 *y;
     const float *ffull, *fbase;
-    signed char *xbase;
+    signed char *xbase, *xsic;
+    int guesses;
     void *out0, *out1, *out2;
 };
 
@@ -1640,10 +1849,42 @@ __device__ __forceinline__ FusedPost fused_post(const FusedJob *jp_in)
     p.ffull = uniform_ptr(jp->f);
     p.fbase = p.stages > 0 ? uniform_ptr(jp->fp) : p.ffull;
     p.xbase = uniform_ptr(jp->x_fb);
+    p.xsic = uniform_ptr(jp->x_sic);
+    p.guesses = rfl(jp->guesses);
     p.out0 = uniform_ptr(jp->out0);
     p.out1 = uniform_ptr(jp->out1);
     p.out2 = uniform_ptr(jp->out2);
     return p;
+}
+
+// The last anneal of an instance of a job of moves around a guess: lv holds
+// this chain's final guess.  MMGaP-E (both chains; this is the MMSE-SIC one):
+// the MMSE chain's final guess is read back, and this chain's answer wins only
+// if its float32 level energy with the full fields is strictly lower; the
+// winner is decoded and the choice written to out2 (if given).  One chain:
+// its answer is decoded (out2: whether it is the MMSE-SIC chain).
+__device__ __noinline__ void fused_final_decode(const FusedPost &p, int n, int sc, int sy, const float *Gi,
+                                   int ldg, const float2 *Hl, int *lv, int *cand, float *terms,
+                                   int lane)
+{
+    bool from_sic = p.guesses == 2;
+    if (p.guesses == 3) {
+        if (lane < p.K) cand[lane] = (int)p.xbase[(size_t)n * ldg + lane];
+        wave_sync_lds();
+        const float *ff = p.ffull + (size_t)n * p.ldf;
+        const float Ea = wave_level_energy<true>(Gi, ldg, p.K, ff, cand, terms, lane);
+        const float Eb = wave_level_energy<true>(Gi, ldg, p.K, ff, lv, terms, lane);
+        // every lane holds the same energies: the choice is wave-uniform
+        from_sic = __builtin_amdgcn_readfirstlane(Eb < Ea ? 1 : 0) != 0;
+        if (!from_sic) {
+            if (lane < p.K) lv[lane] = cand[lane];
+            wave_sync_lds();
+        }
+    }
+    if (p.out2 && lane == 0 && p.guesses > 0)
+        static_cast<unsigned char *>(p.out2)[n] = from_sic ? 1 : 0;
+    decode_det(lv, n, sc, sy, p.n_sym, p.n_rows, p.n_cols, p.dq, p.c, Hl, p.y,
+               (unsigned char *)p.out0, (float *)p.out1, lane);
 }
 
 template <int KT, int Q, bool PACKED>
@@ -1672,7 +1913,10 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
         const bool delta = rfl(jp->stages) > 0;
         uint32_t key0 = rflu(jp->key0), key1 = rflu(jp->key1);
         if (delta) {
-            const uint64_t kk = (((uint64_t)key1 << 32) | key0) + (uint64_t)rfl(lds.stage);
+            // stage s of the chain from the MMSE guess: key seed + s; of the chain
+            // from the MMSE-SIC guess: seed + kMaxStages + s
+            const uint64_t kk = (((uint64_t)key1 << 32) | key0) + (uint64_t)rfl(lds.stage) +
+                                (uint64_t)(rfl(lds.chain) ? kMaxStages : 0);
             key0 = rflu((uint32_t)kk);
             key1 = rflu((uint32_t)(kk >> 32));
         }
@@ -1727,7 +1971,8 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
             const int lanep = tpost & 63;
             const int wavep = rfl(tpost >> 6);
             const FusedPost p = fused_post(jp);
-            const int stage = rfl(lds.stage);
+            const bool last = rfl(lds.last) != 0;
+            signed char *xguess = rfl(lds.chain) ? p.xsic : p.xbase;
             for (int r = wavep; r < ns; r += kWavesPerBlock) {
                 uint32_t S[NW];
                 for (int ww = 0; ww < NW; ++ww) S[ww] = sh.wbits[r][ww];
@@ -1743,13 +1988,12 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
                 const bool use_fb = energy_less(Efb, Ebest);
                 winning_levels(use_fb, xg, S, p.K, Q, p.w, sh.lvs[wavep], lanep);
                 if (p.stages > 0) {
-                    apply_move<true>(sh.lvs[wavep], p.xbase + (size_t)ng * KT, Gi, KT, p.K,
+                    apply_move<true>(sh.lvs[wavep], xguess + (size_t)ng * KT, Gi, KT, p.K,
                                      p.ffull + (size_t)ng * p.ldf, (1 << p.dq) - 1,
                                      sh.cand[wavep], sh.terms[wavep], lanep);
-                    if (stage == p.stages - 1)
-                        decode_det(sh.lvs[wavep], ng, sc, sym0 + r, p.n_sym, p.n_rows,
-                                   p.n_cols, p.dq, p.c, lds.H, p.y, (unsigned char *)p.out0,
-                                   (float *)p.out1, lanep);
+                    if (last)
+                        fused_final_decode(p, ng, sc, sym0 + r, Gi, KT, lds.H, sh.lvs[wavep],
+                                           sh.cand[wavep], sh.terms[wavep], lanep);
                 } else if (p.kind == 0) {
                     decode_det(sh.lvs[wavep], ng, sc, sym0 + r, p.n_sym, p.n_rows, p.n_cols, Q,
                                p.c, lds.H, p.y, (unsigned char *)p.out0, (float *)p.out1, lanep);
@@ -1830,12 +2074,12 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
     winning_levels(use_fb, xi, S, p.K, Q, p.w, sh.lvs[wave], lanep);
     const int sy = sym0 + r0;
     if (p.stages > 0) {
-        apply_move<true>(sh.lvs[wave], p.xbase + (size_t)n * KT, Gi, KT, p.K,
-                         p.ffull + (size_t)n * p.ldf, (1 << p.dq) - 1, sh.cand[wave],
+        apply_move<true>(sh.lvs[wave], (rfl(lds.chain) ? p.xsic : p.xbase) + (size_t)n * KT, Gi,
+                         KT, p.K, p.ffull + (size_t)n * p.ldf, (1 << p.dq) - 1, sh.cand[wave],
                          sh.terms[wave], lanep);
-        if (rfl(lds.stage) == p.stages - 1)
-            decode_det(sh.lvs[wave], n, sc, sy, p.n_sym, p.n_rows, p.n_cols, p.dq, p.c, lds.H,
-                       p.y, (unsigned char *)p.out0, (float *)p.out1, lanep);
+        if (rfl(lds.last))
+            fused_final_decode(p, n, sc, sy, Gi, KT, lds.H, sh.lvs[wave], sh.cand[wave],
+                               sh.terms[wave], lanep);
     } else if (p.kind == 0) {
         decode_det(sh.lvs[wave], n, sc, sy, p.n_sym, p.n_rows, p.n_cols, Q, p.c, lds.H, p.y,
                    (unsigned char *)p.out0, (float *)p.out1, lanep);
@@ -1941,14 +2185,22 @@ k_fused(const FusedJob *__restrict__ jobs, const FusedItem *__restrict__ items, 
         // The item's descriptors are re-read at every stage through a
         // laundered index, so that only the stage counter and the item index
         // stay live across the anneal (fewer registers spilled per item).
-        const int nst = jb.stages > 0 ? jb.stages : 1;
-        for (int st = 0; st < nst; ++st) {
+        // MMGaP-E and the chain from the MMSE-SIC guess: that guess (x_sic) was
+        // written by the batch's MMSE-SIC launch, which precedes this kernel
+        const int guesses = jb.kind == 0 && jb.stages > 0 ? (jb.guesses ? jb.guesses : 1) : 1;
+        // anneal steps: per stage, the chain from the MMSE guess, then the one from
+        // the MMSE-SIC guess (each as its guess set asks)
+        const int nch = guesses == 3 ? 2 : 1;
+        const int nst = (jb.stages > 0 ? jb.stages : 1) * nch;
+        for (int step = 0; step < nst; ++step) {
             int itm = item;
             asm volatile("" : "+s"(itm));
             const FusedItem its = items[itm];
             const FusedJob &js = jobs[its.job];
             int tds = threadIdx.x;
             asm volatile("" : "+v"(tds));
+            const int st = step / nch;
+            const int chain = nch == 2 ? step % 2 : (guesses == 2 ? 1 : 0);
             // the decode reads H (and A^-1) from the build's LDS copies
             FusedItemLds lds;
             lds.G = bs.G;
@@ -1962,7 +2214,7 @@ k_fused(const FusedJob *__restrict__ jobs, const FusedItem *__restrict__ items, 
                 lds.ldz = FusedClassTraits<CLS>::kNUV;
             }
             if (js.stages > 0) {
-                if (st > 0) {          // the previous stage's guesses are written
+                if (step > 0) {        // the previous step's guesses are written
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
                     __syncthreads();
@@ -1972,7 +2224,7 @@ k_fused(const FusedJob *__restrict__ jobs, const FusedItem *__restrict__ items, 
                 for (int e = tds; e < its.ns * KT; e += kBlock) {
                     const int r = e / KT, k = e % KT;
                     const size_t n = (size_t)its.sc * js.n_sym + its.sym0 + r;
-                    const signed char *xg = js.x_fb + n * KT;
+                    const signed char *xg = (chain ? js.x_sic : js.x_fb) + n * KT;
                     float g = 0.0f;
                     for (int l = 0; l < KT; ++l) g = fmaf(bs.G[k * KT + l], (float)xg[l], g);
                     js.fp[n * ldf + k] = js.f[n * ldf + k] - g;
@@ -1983,6 +2235,8 @@ k_fused(const FusedJob *__restrict__ jobs, const FusedItem *__restrict__ items, 
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             }
             lds.stage = st;
+            lds.chain = chain;
+            lds.last = step == nst - 1;
             fused_dispatch<CLS>(js.variant, js.glanes > 0, jobs, its, lds, tds);
         }
     }
@@ -2004,214 +2258,23 @@ __global__ void __launch_bounds__(kBlock) k_delta_prep(DeltaPrepArgs a)
     a.f_out[t] = a.f[t] - g;
 }
 
-// ---------------------------------------------------------------------------
-// Ordered MMSE-SIC of one subcarrier per workgroup of one wavefront.  With
-// P = (H_R^H H_R + sigma^2 I)^-1 over the remaining users R, each step takes
-// the remaining user i with the smallest Re P_ii (the lowest index among
-// equals), its nulling row w = P_i,R H_R^H, and removes i from P by the Schur
-// complement P_jl -= P_ji P_il / P_ii.  The ordering and the nulling rows
-// depend on H only.  Then the symbols of the subcarrier are detected in
-// groups of g = 2^ceil(log2 n_r) lanes, one lane per receive antenna: each
-// lane holds one residual entry r_k in registers, the estimate w . r is a
-// shuffle reduction over the group, every lane slices it to the nearest odd
-// PAM level per real dimension, and subtracts h_ki s_i from its entry.  The
-// residual left after the last user is y - H x, whose squared norm is the
-// reported metric.  float64 throughout.
-//
-// Dynamic LDS: H (n_r x n_t complex float32), P (n_t x n_t complex float64),
-// the nulling rows W (n_t x n_r complex float64), and the levels of the
-// symbols of one pass (64 / g x 2 n_t ints).
-__host__ __device__ inline size_t sic_lds_bytes(int nr, int nt)
-{
-    int g = 1;
-    while (g < nr) g <<= 1;
-    return (size_t)nr * nt * 8 + (size_t)nt * nt * 16 + (size_t)nt * nr * 16 +
-           (size_t)(64 / g) * 2 * nt * 4 + 16 * 4;
-}
-
-__device__ __forceinline__ int sic_slice(double x, double c, int qtop)
-{
-    // clamped first (no effect on the sliced level) so that the conversion to
-    // int stays in range
-    const double t = fmin(fmax(x / c, -(double)(qtop + 2)), (double)(qtop + 2));
-    int v = 2 * (int)floor(t * 0.5) + 1;
-    return v < -qtop ? -qtop : (v > qtop ? qtop : v);
-}
-
 __global__ void __launch_bounds__(64) k_sic(SicArgs a)
 {
     extern __shared__ double2 sic_dyn[];
     const int lane = threadIdx.x;
     const int sc = blockIdx.x;
-    const int nr = a.n_r, nt = a.n_t, qtop = (1 << a.q) - 1;
+    const int nr = a.n_r, nt = a.n_t;
     double2 *P = sic_dyn;                                   // [nt][nt]
     double2 *W = P + nt * nt;                               // [nt][nr]
     cf32 *Hs = reinterpret_cast<cf32 *>(W + nt * nr);       // [nr][nt]
     int *lv = reinterpret_cast<int *>(Hs + nr * nt);        // [64 / g][2 nt]
     int g = 1;
     while (g < nr) g <<= 1;
-    const int spp = 64 / g;                                 // symbols per pass
-    int *order = lv + spp * 2 * nt;                         // [nt]
-
+    int *order = lv + (64 / g) * 2 * nt;                    // [nt]
     const float2 *Hg = a.H + (size_t)sc * nr * nt;
     for (int e = lane; e < nr * nt; e += 64) Hs[e] = to_cf32(Hg[e]);
     wave_sync_lds();
-    // A = H^H H + sigma^2 I
-    for (int e = lane; e < nt * nt; e += 64) {
-        const int i = e / nt, j = e % nt;
-        cd acc{0.0, 0.0};
-#pragma unroll 4
-        for (int r = 0; r < nr; ++r) {
-            const cf32 hi = Hs[r * nt + i], hj = Hs[r * nt + j];
-            const cd v = cmulc(cd{hi.x, hi.y}, cd{hj.x, hj.y});   // conj(h_ri) h_rj
-            acc.re = acc.re + v.re;
-            acc.im = acc.im + v.im;
-        }
-        if (i == j) acc.re = acc.re + a.noise_var;
-        P[e] = make_double2(acc.re, acc.im);
-    }
-    wave_sync_lds();
-    // in-place Gauss-Jordan inverse (Hermitian positive definite: no pivoting);
-    // each lane keeps its elements' row and column factors in registers
-    for (int k = 0; k < nt; ++k) {
-        const cd pk = ld2(P[k * nt + k]);
-        const double den = pk.re * pk.re + pk.im * pk.im;
-        const cd t{pk.re / den, -pk.im / den};
-        cd rowv[4], colv[4], old[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = lane + 64 * u;
-            if (e < nt * nt) {
-                const int i = e / nt, j = e % nt;
-                rowv[u] = j == k ? t : cmul(ld2(P[k * nt + j]), t);
-                colv[u] = ld2(P[i * nt + k]);
-                old[u] = ld2(P[e]);
-            }
-        }
-        wave_sync_lds();
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = lane + 64 * u;
-            if (e < nt * nt) {
-                const int i = e / nt, j = e % nt;
-                if (i == k) {
-                    P[e] = make_double2(rowv[u].re, rowv[u].im);
-                } else {
-                    const cd o = j == k ? cd{0.0, 0.0} : old[u];
-                    const cd m = cmul(colv[u], rowv[u]);
-                    P[e] = make_double2(o.re - m.re, o.im - m.im);
-                }
-            }
-        }
-        wave_sync_lds();
-    }
-    // ordering, nulling rows and downdates
-    uint32_t rem = nt >= 32 ? 0xFFFFFFFFu : ((1u << nt) - 1u);
-    for (int step = 0; step < nt; ++step) {
-        const bool mine = lane < nt && ((rem >> lane) & 1u);
-        const double d = mine ? P[lane * nt + lane].x : __builtin_inf();
-        double m = d;
-        for (int off = 32; off >= 1; off >>= 1) m = fmin(m, __shfl_xor(m, off, 64));
-        uint64_t ball = __ballot(mine && d == m);
-        if (ball == 0) ball = rem;              // no finite diagonal: the lowest remaining user
-        const int i = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)ball) - 1);
-        if (lane == 0) order[step] = i;
-        for (int r = lane; r < nr; r += 64) {
-            cd acc{0.0, 0.0};
-#pragma unroll 4
-            for (int j = 0; j < nt; ++j) {
-                if (!((rem >> j) & 1u)) continue;
-                const cf32 h = Hs[r * nt + j];
-                const cd v = cmulc(cd{h.x, h.y}, ld2(P[i * nt + j]));   // P_ij conj(h_rj)
-                acc.re = acc.re + v.re;
-                acc.im = acc.im + v.im;
-            }
-            W[step * nr + r] = make_double2(acc.re, acc.im);
-        }
-        // Schur complement of user i
-        const cd piv = ld2(P[i * nt + i]);
-        const double den = piv.re * piv.re + piv.im * piv.im;
-        const cd ip{piv.re / den, -piv.im / den};
-        const uint32_t keep = rem & ~(1u << i);
-        cd nv[4];
-        bool upd[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = lane + 64 * u;
-            upd[u] = false;
-            if (e < nt * nt) {
-                const int j = e / nt, l = e % nt;
-                if (((keep >> j) & 1u) && ((keep >> l) & 1u)) {
-                    const cd mm = cmul(cmul(ld2(P[j * nt + i]), ld2(P[i * nt + l])), ip);
-                    const cd o = ld2(P[e]);
-                    nv[u] = cd{o.re - mm.re, o.im - mm.im};
-                    upd[u] = true;
-                }
-            }
-        }
-        wave_sync_lds();
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (upd[u]) P[lane + 64 * u] = make_double2(nv[u].re, nv[u].im);
-        rem = keep;
-        wave_sync_lds();
-    }
-    if (a.order_out && lane < nt) a.order_out[(size_t)sc * nt + lane] = order[lane];
-    // detection: symbol sl = lane / g of the pass, receive antenna r = lane % g
-    const int sl = lane / g, r = lane % g;
-    for (int s0 = 0; s0 < a.n_sym; s0 += spp) {
-        const int sy = s0 + sl;
-        const bool act = sl < spp && sy < a.n_sym && r < nr;
-        cd res{0.0, 0.0};
-        if (act) {
-            const float2 v = a.y[((size_t)sc * a.n_sym + sy) * nr + r];
-            res = cd{(double)v.x, (double)v.y};
-        }
-        for (int k = 0; k < nt; ++k) {
-            const int i = order[k];
-            cd prod{0.0, 0.0};
-            if (act) prod = cmul(ld2(W[k * nr + r]), res);
-            for (int off = g >> 1; off >= 1; off >>= 1) {
-                prod.re = prod.re + __shfl_xor(prod.re, off, 64);
-                prod.im = prod.im + __shfl_xor(prod.im, off, 64);
-            }
-            const int li = sic_slice(prod.re, a.c, qtop);
-            const int lq = sic_slice(prod.im, a.c, qtop);
-            if (act && r == 0) {
-                lv[sl * 2 * nt + i] = li;
-                lv[sl * 2 * nt + nt + i] = lq;
-            }
-            if (act) {
-                const cf32 h = Hs[r * nt + i];
-                const cd m = cmul(cd{h.x, h.y}, cd{a.c * (double)li, a.c * (double)lq});
-                res.re = res.re - m.re;
-                res.im = res.im - m.im;
-            }
-        }
-        // metric: the squared norm of the final residual y - H x
-        double e2 = act ? res.re * res.re + res.im * res.im : 0.0;
-        for (int off = g >> 1; off >= 1; off >>= 1) e2 = e2 + __shfl_xor(e2, off, 64);
-        wave_sync_lds();
-        const int cnt = min(spp, a.n_sym - s0);
-        const size_t n0 = (size_t)sc * a.n_sym + s0;
-        if (a.levels) {
-            for (int e = lane; e < cnt * a.ldl; e += 64) {
-                const int s = e / a.ldl, k = e % a.ldl;
-                a.levels[(n0 + s) * a.ldl + k] = (signed char)(k < 2 * nt ? lv[s * 2 * nt + k] : 0);
-            }
-        }
-        if (a.sym_out) {
-            for (int e = lane; e < cnt * nt; e += 64) {
-                const int s = e / nt, t = e % nt;
-                const int pI = (lv[s * 2 * nt + t] + qtop) >> 1;
-                const int pQ = (lv[s * 2 * nt + nt + t] + qtop) >> 1;
-                const int gI = pI ^ (pI >> 1), gQ = pQ ^ (pQ >> 1);
-                a.sym_out[(n0 + s) * nt + t] = (unsigned char)((gI << a.q) | gQ);
-            }
-            if (a.metric_out && act && r == 0) a.metric_out[n0 + sl] = (float)e2;
-        }
-        wave_sync_lds();
-    }
+    sic_sc(a, sc, 0, a.n_sym, Hs, P, W, lv, order, 64, lane);
 }
 
 // The better of two candidates per instance (the second only if its float32

@@ -8,8 +8,8 @@ schedule at that SNR.  These formulations compete for detection classes:
   stages each starting from the previous stage's answer): chains, sweeps per
   stage and the number of stages, run as stages of the persistent kernel;
 * moves around the MMSE-SIC guess, and MMGaP-E (paper §3.2 Fig. 6: the better
-  of the searches from both guesses), through the separate-launch entry point
-  (``tuned_any``; persistent plans take the best of the first two).
+  of the searches from both guesses), in persistent plans or through
+  mmgap_detect_e (``tuned_any``: ranked by measured time per slot).
 
 A schedule is linear in beta from beta_start to beta_end.  The reference shape
 is the class's default range (beta0, beta1) of ``workload.synth``; a shape
@@ -203,10 +203,10 @@ def parse_key(key):
 
 def select(name, rec):
     """Per SNR bucket, the cheapest measured schedule within SELECT_TOLERANCE of
-    the reference at that SNR (ties: fewer chains, fewer sweeps): "tuned" among
-    the formulations persistent plans run (the binary encoding, moves around
-    the MMSE guess), "tuned_any" among all (adding the MMSE-SIC-guess search and
-    MMGaP-E, which run as separate launches)."""
+    the reference at that SNR (ties: fewer chains, fewer sweeps): "tuned" by
+    the cost model (the choice for persistent plans and the server),
+    "tuned_any" by the measured time per slot through the separate-launch entry
+    points where candidates were timed (--time)."""
     ref = rec["reference"]
     ref_cost = cost(name, ref["chains"], ref["sweeps"])
     buckets = []
@@ -222,7 +222,7 @@ def select(name, rec):
         ok = [parse_key(k) for k, v in r["cands"].items()
               if v <= (1 + SELECT_TOLERANCE) * r["ref"] + 2e-5]
         order = lambda c: (cand_cost(name, c), c[4], guesses_of(c), c[0], c[1], c[2], c[3])
-        best = min((c for c in ok if guesses_of(c) <= 1), key=order)
+        best = min(ok, key=order)
         # through separate launches the fixed costs of the builds, the MMSE-SIC
         # guess, the selections and every stage's launches weigh in: the
         # measured time per slot decides among the candidates that were timed

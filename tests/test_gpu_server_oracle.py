@@ -66,8 +66,10 @@ def make_job(ctx, k, spec):
             sc = dict(chains=ch, sweeps=sw, init=0, stages=st, beta2=W.linear_beta2(
                 sw, *W.det_beta_range(qam, n, d.noise_var)))
         H, y = dev(d.H), dev(d.y)
+        g = sc.get("guesses", 0)
         job = ctx.det_job(H, y, qam, d.noise_var, sc["chains"], sc["sweeps"], sc["beta2"],
-                          W.job_seed(seed), init=sc["init"], stages=sc["stages"])
+                          W.job_seed(seed), init=sc["init"], stages=sc["stages"],
+                          guesses=g if g > 1 else 0)
         return dict(kind=kind, raw=d, H=d.H, y=d.y, nv=d.noise_var, qam=qam, sched=sc,
                     seed=W.job_seed(seed), job=job)
     s = W.vpp_slot(seed, n, n, qam, N_SC, N_SYM)
@@ -80,6 +82,10 @@ def make_job(ctx, k, spec):
 
 def oracle_ref(j, ids):
     sc = j["sched"]
+    if j["kind"] == "det" and sc.get("guesses", 0) > 1:
+        return O.detect_e(j["H"], j["y"], j["nv"], j["qam"], sc["chains"], sc["sweeps"],
+                          sc["beta2"], j["seed"], stages=sc["stages"], inst_ids=ids,
+                          init_mode=sc["init"], guesses=sc["guesses"])
     if j["kind"] == "det" and sc["stages"]:
         return O.detect_delta(j["H"], j["y"], j["nv"], j["qam"], sc["chains"], sc["sweeps"],
                               sc["beta2"], j["seed"], stages=sc["stages"], inst_ids=ids,

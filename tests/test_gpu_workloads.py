@@ -94,8 +94,10 @@ def run_plan(ctx, inputs, scheds):
     for inp, s in zip(inputs, scheds):
         H, y = dev(inp["H"]), dev(inp["y"])
         if inp["kind"] == "det":
+            g = s.get("guesses", 0)
             jobs.append(ctx.det_job(H, y, inp["qam"], inp["noise_var"], s["chains"], s["sweeps"],
-                                    s["beta2"], inp["seed"], init=s["init"]))
+                                    s["beta2"], inp["seed"], init=s["init"],
+                                    stages=s.get("stages", 0), guesses=g if g > 1 else 0))
         else:
             jobs.append(ctx.vpp_job(H, y, inp["qam"], s["chains"], s["sweeps"], s["beta2"],
                                     inp["seed"], init=s["init"]))
@@ -126,10 +128,19 @@ def check_det(inp, sched, out, n_sample):
     n = d.y.shape[0] * d.y.shape[1]
     sym, met = out["sym"], out["metric"].astype(np.float64)
     ids = sample_ids(n, n_sample, 7)
-    ref = O.detect(d.H, d.y, d.noise_var, qam, sched["chains"], sched["sweeps"], sched["beta2"],
-                   inp["seed"], inst_ids=ids, init_mode=sched["init"])
+    args = (d.H, d.y, d.noise_var, qam, sched["chains"], sched["sweeps"], sched["beta2"],
+            inp["seed"])
+    st, g = sched.get("stages", 0), sched.get("guesses", 0)
+    if g > 1:
+        ref = O.detect_e(*args, stages=st, inst_ids=ids, init_mode=sched["init"], guesses=g)
+    elif st:
+        ref = O.detect_delta(*args, stages=st, inst_ids=ids, init_mode=sched["init"])
+    else:
+        ref = O.detect(*args, inst_ids=ids, init_mode=sched["init"])
     assert_rows_equal(sym[ids], ref["sym"], met[ids], ref["metric"])
     assert np.allclose(met[ids], ref["metric"], rtol=1e-4, atol=1e-6)
+    if g == 2:       # the search from the MMSE-SIC guess only: no MMSE bound below
+        return
     # every instance: metric = FP64 residual of the symbols, <= MMSE's residual
     li, lq = W.symbol_levels(sym, qam)
     m64 = O.det_metric(d.H, d.y, np.concatenate([li, lq], axis=1), qam)
