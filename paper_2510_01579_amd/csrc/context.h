@@ -39,6 +39,8 @@ struct mmgap_ctx {
     hipEvent_t ring_ev[mmgap::host::kRing] = {};
     int ring_pos = 0;
     hipEvent_t done = nullptr;                  // end of the last call's work
+    hipStream_t aux = nullptr;                  // second stream (MMGaP-E's MMSE-SIC chain)
+    hipEvent_t aux_ev[3] = {};                  // forks and the join of that stream
     bool done_valid = false;
     uint32_t *accept_dev = nullptr;             // Metropolis threshold table
     bool profiling = false;
