@@ -1810,7 +1810,6 @@ struct FusedItemLds {
     int ldz;
     int stage;              // stage of a job of moves around a guess
     int chain;              // 0 the chain from the MMSE guess, 1 from the MMSE-SIC guess
-    int last;               // the item's last anneal: decode (MMGaP-E: pick, then decode)
 };
 
 // Descriptor fields read after the anneal (through a laundered pointer, so
@@ -1855,36 +1854,6 @@ __device__ __forceinline__ FusedPost fused_post(const FusedJob *jp_in)
     p.out1 = uniform_ptr(jp->out1);
     p.out2 = uniform_ptr(jp->out2);
     return p;
-}
-
-// The last anneal of an instance of a job of moves around a guess: lv holds
-// this chain's final guess.  MMGaP-E (both chains; this is the MMSE-SIC one):
-// the MMSE chain's final guess is read back, and this chain's answer wins only
-// if its float32 level energy with the full fields is strictly lower; the
-// winner is decoded and the choice written to out2 (if given).  One chain:
-// its answer is decoded (out2: whether it is the MMSE-SIC chain).
-__device__ __noinline__ void fused_final_decode(const FusedPost &p, int n, int sc, int sy, const float *Gi,
-                                   int ldg, const float2 *Hl, int *lv, int *cand, float *terms,
-                                   int lane)
-{
-    bool from_sic = p.guesses == 2;
-    if (p.guesses == 3) {
-        if (lane < p.K) cand[lane] = (int)p.xbase[(size_t)n * ldg + lane];
-        wave_sync_lds();
-        const float *ff = p.ffull + (size_t)n * p.ldf;
-        const float Ea = wave_level_energy<true>(Gi, ldg, p.K, ff, cand, terms, lane);
-        const float Eb = wave_level_energy<true>(Gi, ldg, p.K, ff, lv, terms, lane);
-        // every lane holds the same energies: the choice is wave-uniform
-        from_sic = __builtin_amdgcn_readfirstlane(Eb < Ea ? 1 : 0) != 0;
-        if (!from_sic) {
-            if (lane < p.K) lv[lane] = cand[lane];
-            wave_sync_lds();
-        }
-    }
-    if (p.out2 && lane == 0 && p.guesses > 0)
-        static_cast<unsigned char *>(p.out2)[n] = from_sic ? 1 : 0;
-    decode_det(lv, n, sc, sy, p.n_sym, p.n_rows, p.n_cols, p.dq, p.c, Hl, p.y,
-               (unsigned char *)p.out0, (float *)p.out1, lane);
 }
 
 template <int KT, int Q, bool PACKED>
@@ -1971,7 +1940,6 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
             const int lanep = tpost & 63;
             const int wavep = rfl(tpost >> 6);
             const FusedPost p = fused_post(jp);
-            const bool last = rfl(lds.last) != 0;
             signed char *xguess = rfl(lds.chain) ? p.xsic : p.xbase;
             for (int r = wavep; r < ns; r += kWavesPerBlock) {
                 uint32_t S[NW];
@@ -1991,9 +1959,6 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
                     apply_move<true>(sh.lvs[wavep], xguess + (size_t)ng * KT, Gi, KT, p.K,
                                      p.ffull + (size_t)ng * p.ldf, (1 << p.dq) - 1,
                                      sh.cand[wavep], sh.terms[wavep], lanep);
-                    if (last)
-                        fused_final_decode(p, ng, sc, sym0 + r, Gi, KT, lds.H, sh.lvs[wavep],
-                                           sh.cand[wavep], sh.terms[wavep], lanep);
                 } else if (p.kind == 0) {
                     decode_det(sh.lvs[wavep], ng, sc, sym0 + r, p.n_sym, p.n_rows, p.n_cols, Q,
                                p.c, lds.H, p.y, (unsigned char *)p.out0, (float *)p.out1, lanep);
@@ -2077,9 +2042,6 @@ __device__ __forceinline__ void fused_anneal(const FusedJob *jobs_in, int job_in
         apply_move<true>(sh.lvs[wave], (rfl(lds.chain) ? p.xsic : p.xbase) + (size_t)n * KT, Gi,
                          KT, p.K, p.ffull + (size_t)n * p.ldf, (1 << p.dq) - 1, sh.cand[wave],
                          sh.terms[wave], lanep);
-        if (rfl(lds.last))
-            fused_final_decode(p, n, sc, sy, Gi, KT, lds.H, sh.lvs[wave], sh.cand[wave],
-                               sh.terms[wave], lanep);
     } else if (p.kind == 0) {
         decode_det(sh.lvs[wave], n, sc, sy, p.n_sym, p.n_rows, p.n_cols, Q, p.c, lds.H, p.y,
                    (unsigned char *)p.out0, (float *)p.out1, lanep);
@@ -2236,8 +2198,56 @@ k_fused(const FusedJob *__restrict__ jobs, const FusedItem *__restrict__ items, 
             }
             lds.stage = st;
             lds.chain = chain;
-            lds.last = step == nst - 1;
             fused_dispatch<CLS>(js.variant, js.glanes > 0, jobs, its, lds, tds);
+        }
+        // Moves around a guess: the final guesses of the item's instances are
+        // decoded, instance r by wavefront r mod 4.  MMGaP-E takes the answer of
+        // the chain from the MMSE-SIC guess only if its float32 level energy
+        // (full fields) is strictly lower, and writes the choice to out2.
+        if (jb.kind == 0 && jb.stages > 0) {
+            int itm = item;
+            asm volatile("" : "+s"(itm));
+            const FusedItem its = items[itm];
+            const FusedPost p = fused_post(uniform_ptr(jobs) + rfl(its.job));
+            int tds = threadIdx.x;
+            asm volatile("" : "+v"(tds));
+            const int lane = tds & 63, wave = rfl(tds >> 6);
+            const int KT = rfl(jobs[its.job].KT);
+            const int g = p.guesses ? p.guesses : 1;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            const float2 *Hl = reinterpret_cast<const float2 *>(bs.det().Hs);
+            for (int r = wave; r < its.ns; r += kWavesPerBlock) {
+                const int sy = its.sym0 + r;
+                const int n = its.sc * p.n_sym + sy;
+                int *lv = sh.lvs[wave], *cb = sh.cand[wave];
+                if (lane < p.K) {
+                    lv[lane] = (int)(g == 2 ? p.xsic : p.xbase)[(size_t)n * KT + lane];
+                    if (g == 3) cb[lane] = (int)p.xsic[(size_t)n * KT + lane];
+                }
+                wave_sync_lds();
+                bool from_sic = g == 2;
+                if (g == 3) {
+                    const float *ff = p.ffull + (size_t)n * p.ldf;
+                    const float Ea = wave_level_energy<true>(bs.G, KT, p.K, ff, lv, sh.terms[wave],
+                                                             lane);
+                    const float Eb = wave_level_energy<true>(bs.G, KT, p.K, ff, cb, sh.terms[wave],
+                                                             lane);
+                    // every lane holds the same energies: the choice is wave-uniform
+                    from_sic = __builtin_amdgcn_readfirstlane(Eb < Ea ? 1 : 0) != 0;
+                    if (from_sic) {
+                        if (lane < p.K) lv[lane] = cb[lane];
+                        wave_sync_lds();
+                    }
+                }
+                if (p.out2 && lane == 0 && p.guesses > 0)
+                    static_cast<unsigned char *>(p.out2)[n] = from_sic ? 1 : 0;
+                decode_det(lv, n, its.sc, sy, p.n_sym, p.n_rows, p.n_cols, p.dq, p.c, Hl, p.y,
+                           (unsigned char *)p.out0, (float *)p.out1, lane);
+                wave_sync_lds();
+            }
         }
     }
 }
