@@ -127,12 +127,6 @@ def guess_arg(sc) -> int:
     return g if g > 1 else 0
 
 
-def anneal_calls(sc) -> int:
-    """Anneal launches of one job through the separate-launch entry points."""
-    g = sc.get("guesses", 0)
-    return max(sc.get("stages", 0), 1) * (2 if g == 3 else 1)
-
-
 def sched_desc(s) -> str:
     g = s.get("guesses", 0)
     if not g:
@@ -564,6 +558,17 @@ def main(argv=None) -> int:  # noqa: C901
     print(f"[bench] workload {args.workload}: {len(groups)} slot launches per step, "
           f"{total_inst} instances", file=sys.stderr, flush=True)
 
+    def records_per_step(launch_group):
+        """Profiled calls the library records in one pass over every group (one
+        per anneal launch of the stage launches; one per search launch)."""
+        ctx.set_profiling(True)
+        for gi in range(len(groups)):
+            launch_group(gi)
+        torch.cuda.synchronize()
+        n = len(ctx.profile(256))
+        ctx.set_profiling(False)
+        return n
+
     def timed(launch_group):
         """W warmup steps, then K timed steps; one HIP event pair around each
         group's launch on the current stream.  Returns (elapsed s, [K][G] ms)."""
@@ -710,10 +715,11 @@ def main(argv=None) -> int:  # noqa: C901
             return outs
 
         print("[bench] delta leg (separate launches)", file=sys.stderr, flush=True)
-        n_stage = sum(s["stages"] for s in t_scheds)
+        n_stage = records_per_step(delta_group)
         ctx.set_profiling(True)
         el, lat = timed(delta_group)
-        dprof = np.array(ctx.profile(args.steps * n_stage)).reshape(args.steps, n_stage, 3)
+        md = max(1, min(args.steps, 256 // n_stage))      # the library keeps 256 records
+        dprof = np.array(ctx.profile(md * n_stage)).reshape(md, n_stage, 3)
         ctx.set_profiling(False)
         d_out = host_outs([o for gi in range(len(groups)) for o in delta_group(gi)])
         q_d = quality(inputs, d_out)
@@ -758,7 +764,7 @@ def main(argv=None) -> int:  # noqa: C901
 
             print("[bench] tuned leg, every formulation (separate launches)", file=sys.stderr,
                   flush=True)
-            n_calls = sum(anneal_calls(s) for s in a_scheds)
+            n_calls = records_per_step(sep_group)
             ctx.set_profiling(True)
             el, lat = timed(sep_group)
             m = max(1, min(args.steps, 256 // n_calls))      # the library keeps 256 records
@@ -915,12 +921,14 @@ def main(argv=None) -> int:  # noqa: C901
     else:
         kern_ms = float(sel_lat.mean(axis=0).sum())
     achieved = ops / (kern_ms * 1e-3)
-    kname = {"plain": "k_anneal", "delta_separate": "k_anneal (moves around the guess)",
-             "tuned_separate": "k_anneal (tuned formulations, separate launches)"}.get(
+    kname = {"plain": "k_anneal",
+             "delta_separate": "k_search (moves around the guess, one launch per slot)",
+             "tuned_separate": "k_search and k_anneal (tuned formulations: one search "
+                               "launch per slot for moves around a guess and MMGaP-E)"}.get(
         sel_name, "k_fused" + (" (moves around the guess)" if any(s.get("stages")
                                                                    for s in sel_scheds) else ""))
-    tkey = {"plain": "k_anneal", "delta_separate": "k_anneal_delta",
-            "tuned_separate": "k_anneal_tuned_separate"}.get(
+    tkey = {"plain": "k_anneal", "delta_separate": "k_search_delta",
+            "tuned_separate": "k_search_tuned_separate"}.get(
         sel_name, "k_fused_delta" if any(s.get("stages") for s in sel_scheds) else "k_fused")
 
     desc = []
@@ -959,10 +967,14 @@ def main(argv=None) -> int:  # noqa: C901
                      "tuned": "fused at the tuned schedules: one persistent launch per slot "
                               "(HIP graph), stages of moves around the MMSE guess inside it "
                               "where the tuner chose them",
-                     "delta_separate": "per stage: move fields, anneal and select launches",
-                     "tuned_separate": "the tuned formulation per slot (binary encoding, moves "
-                                       "around the MMSE or MMSE-SIC guess, or MMGaP-E) through "
-                                       "the separate build, anneal and select launches"
+                     "delta_separate": "the build, then every stage of the moves around the "
+                                       "MMSE guess, the selections and the decode in one "
+                                       "search launch",
+                     "tuned_separate": "the tuned formulation per slot: the build (and the "
+                                       "MMSE-SIC launch), then one search launch for every "
+                                       "stage, both chains of MMGaP-E, the choice and the "
+                                       "decode (moves around a guess), or anneal and select "
+                                       "launches (binary encoding)"
                      }[sel_name],
             "slots_per_step": len(groups),
             "instances_per_step": total_inst,

@@ -467,6 +467,23 @@ int mmgap_server_stop(mmgap_ctx *ctx);
 int mmgap_set_profiling(mmgap_ctx *ctx, int enable);
 int mmgap_last_profile(mmgap_ctx *ctx, float *ms, int capacity);
 
+/*
+ * Options of a context (results never depend on them).
+ * MMGAP_OPT_STAGE_LAUNCHES -- value 1: mmgap_detect_delta and mmgap_detect_e
+ *   run each stage as separate launches (move fields, anneal, selection) and
+ *   choose between the two guesses in a launch of its own.  Value 0 (the
+ *   default): with Metropolis anneals, KT <= 32, chains <= 64 and n_rx at
+ *   most twice the lanes an instance takes (4 to 64: the power of two at
+ *   least the chain count, and larger when fewer instances than 64 / lanes
+ *   divide n_sym) every stage, both chains, the choice and the decode run in
+ *   one launch after the build (paper §3.2: one pass of the hot path per
+ *   stage, without the round trips through device memory).  The outputs are
+ *   identical; the option is there for measurement and tests.
+ * Returns MMGAP_OK, or MMGAP_EINVAL for an unknown option or value.
+ */
+enum { MMGAP_OPT_STAGE_LAUNCHES = 1 };
+int mmgap_set_option(mmgap_ctx *ctx, int option, int value);
+
 #ifdef __cplusplus
 }
 #endif

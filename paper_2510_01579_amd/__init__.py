@@ -37,12 +37,13 @@ STATUS = {0: "MMGAP_OK", -1: "MMGAP_EINVAL", -2: "MMGAP_ENOMEM", -3: "MMGAP_EDEV
 EXPORTS = ("mmgap_create", "mmgap_destroy", "mmgap_last_error", "mmgap_build_ising",
            "mmgap_solve", "mmgap_detect", "mmgap_detect_delta", "mmgap_detect_sic",
            "mmgap_detect_e", "mmgap_cim_chains", "mmgap_vpp_precode",
-           "mmgap_set_profiling",
+           "mmgap_set_profiling", "mmgap_set_option",
            "mmgap_last_profile", "mmgap_plan_create", "mmgap_plan_launch", "mmgap_plan_info",
            "mmgap_plan_destroy", "mmgap_server_start", "mmgap_server_submit",
            "mmgap_server_poll", "mmgap_server_drain", "mmgap_server_stop")
 
 PLAN_GRAPH = 1
+OPT_STAGE_LAUNCHES = 1
 
 
 class MmgapError(RuntimeError):
@@ -118,6 +119,7 @@ def lib() -> ctypes.CDLL:
             L.mmgap_cim_chains.argtypes = [vp, i, i, i, vp, vp, i, vp, vp, S, vp, vp, vp, vp]
             L.mmgap_vpp_precode.argtypes = [vp, P, vp, vp, S, vp, vp, vp, vp]
             L.mmgap_set_profiling.argtypes = [vp, i]
+            L.mmgap_set_option.argtypes = [vp, i, i]
             L.mmgap_last_profile.argtypes = [vp, ctypes.POINTER(f32), i]
             L.mmgap_plan_create.argtypes = [vp, i, ctypes.POINTER(Job), i, i, ctypes.POINTER(vp)]
             L.mmgap_plan_launch.argtypes = [vp, vp]
@@ -284,6 +286,12 @@ class Context:
 
     def _dev(self):
         return _torch().device("cuda", self.device)
+
+    def set_stage_launches(self, enable: bool = True):
+        """MMGAP_OPT_STAGE_LAUNCHES: run detect_delta / detect_e as separate
+        launches per stage (True) or in one launch where possible (False, the
+        default); the outputs are identical."""
+        self._check(lib().mmgap_set_option(self._h, OPT_STAGE_LAUNCHES, int(bool(enable))))
 
     def set_profiling(self, enable: bool = True):
         """(Re)start recording HIP events around the stages of every later call."""

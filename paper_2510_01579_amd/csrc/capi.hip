@@ -1065,6 +1065,74 @@ int run_delta_stages(mmgap_ctx *ctx, hipStream_t st, const mmgap_problem *prob,
     return MMGAP_OK;
 }
 
+// Lanes per instance of the one-launch search (k_search), or 0 when the stage
+// launches must run it: chains <= 64, 64 / lanes instances of a subcarrier
+// per wavefront (at most 16, so at least 4 lanes), n_rx <= 2 lanes.
+int search_lanes(const mmgap_ctx *ctx, const mmgap_problem *prob, const ProblemShape &sh,
+                 const mmgap_schedule *sched)
+{
+    if (ctx->stage_launches || sched->dynamics == MMGAP_DYN_CIM || sh.KT > 32 ||
+        sched->chains > 64)
+        return 0;
+    int gl = 64;
+    if (sched->chains <= 32) {
+        const int p = packed_lanes(sched->chains, prob->n_sym, 16);
+        if (p) gl = p;
+    }
+    return prob->n_rx <= 2 * gl ? gl : 0;
+}
+
+// Every stage of the chains from guess A and/or guess B (device rows
+// [n][KT], read only), the choice and the decode, in one launch.
+int run_search(mmgap_ctx *ctx, hipStream_t st, const mmgap_problem *prob,
+               const ProblemShape &sh, const void *H, const void *y,
+               const mmgap_schedule *sched, int stages, int lanes, const float *G,
+               const float *f, const signed char *xa, const signed char *xb,
+               unsigned char *sym_out, float *metric_out, unsigned char *from_b)
+{
+    const float *beta = nullptr;
+    int rc = upload_beta(ctx, sched, st, &beta);
+    if (rc) return rc;
+    mmgap::SearchArgs a{};
+    a.G = G;
+    a.inst_per_G = prob->n_sym;
+    a.f = f;
+    a.guess_a = xa;
+    a.guess_b = xb;
+    a.beta2 = beta;
+    a.accept_table = ctx->accept_dev;
+    a.n_inst = sh.n_inst;
+    a.K = sh.K;
+    a.sweeps = sched->sweeps;
+    a.chains = sched->chains;
+    a.stages = stages;
+    a.init_mode = sched->init;
+    a.glanes = lanes;
+    a.key0 = (uint32_t)sched->seed;
+    a.key1 = (uint32_t)(sched->seed >> 32);
+    a.inst_base = sched->inst_base;
+    a.dq = sh.q;
+    a.H = (const float2 *)H;
+    a.y = (const float2 *)y;
+    a.n_rows = prob->n_rx;
+    a.n_cols = prob->n_tx;
+    a.n_sym = prob->n_sym;
+    a.c = qam_c(prob->qam);
+    a.sym_out = sym_out;
+    a.metric_out = metric_out;
+    a.from_b = from_b;
+    prof_mark(ctx, 1, st);
+    hipError_t e = mmgap::launch_search(sh.KT, a, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "search launch");
+    prof_mark(ctx, 2, st);
+    prof_mark(ctx, 3, st);
+    if (ctx->profiling) {
+        ++ctx->prof_count;
+        ctx->prof_open = false;
+    }
+    return MMGAP_OK;
+}
+
 // The detection build into G, f and the sliced MMSE estimate xg.
 int det_build_into(mmgap_ctx *ctx, hipStream_t st, const mmgap_problem *prob,
                    const ProblemShape &sh, const void *H, const void *y, float *G, float *f,
@@ -1130,9 +1198,11 @@ int mmgap_detect_delta(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H,
     const size_t of = plan.take(sizeof(float) * (size_t)ni * KT);
     const size_t ofp = plan.take(sizeof(float) * (size_t)ni * KT);
     const size_t oxg = plan.take((size_t)ni * KT);
-    const size_t oz = plan.take((size_t)ni * KT);
-    const size_t oE = plan.take(sizeof(float) * (size_t)ni * sched->chains);
-    const size_t oS = plan.take(sizeof(uint32_t) * (size_t)ni * sched->chains * NW);
+    const int lanes = search_lanes(ctx, prob, sh, sched);
+    // the stage launches' zero move and chain states (not used by the one-launch search)
+    const size_t oz = lanes ? 0 : plan.take((size_t)ni * KT);
+    const size_t oE = lanes ? 0 : plan.take(sizeof(float) * (size_t)ni * sched->chains);
+    const size_t oS = lanes ? 0 : plan.take(sizeof(uint32_t) * (size_t)ni * sched->chains * NW);
     if ((rc = ensure_scratch(ctx, plan.off))) return rc;
     if ((rc = begin_call(ctx, st))) return rc;
     prof_mark(ctx, 0, st);
@@ -1144,6 +1214,13 @@ int mmgap_detect_delta(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H,
     if (guess) {
         e = mmgap::launch_pad_rows_i8(guess, at<signed char>(ctx, oxg), ni, sh.K, KT, st);
         if (e != hipSuccess) return hip_fail(ctx, e, "guess copy");
+    }
+    if (lanes) {
+        rc = run_search(ctx, st, prob, sh, H, y, sched, stages, lanes, at<float>(ctx, oG),
+                        at<float>(ctx, of), at<signed char>(ctx, oxg), nullptr, sym_out,
+                        metric_out, nullptr);
+        if (rc) return rc;
+        return end_call(ctx, st);
     }
     e = mmgap::launch_fill_u8(at<signed char>(ctx, oz), 0, (size_t)ni * KT, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "zero-move fill");
@@ -1215,8 +1292,11 @@ int mmgap_detect_e(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, con
     const size_t oxa = plan.take((size_t)ni * KT);
     const size_t oxb = plan.take((size_t)ni * KT);
     const size_t oz = plan.take((size_t)ni * KT);
-    size_t ofp[2], oE[2], oS[2];
-    for (int c = 0; c < (both ? 2 : 1); ++c) {
+    // the stage launches' per-chain move fields and chain states (not used by
+    // the one-launch search)
+    const int lanes = search_lanes(ctx, prob, sh, sched);
+    size_t ofp[2] = {}, oE[2] = {}, oS[2] = {};
+    for (int c = 0; c < (lanes ? 0 : both ? 2 : 1); ++c) {
         ofp[c] = plan.take(sizeof(float) * (size_t)ni * KT);
         oE[c] = plan.take(sizeof(float) * (size_t)ni * sched->chains);
         oS[c] = plan.take(sizeof(uint32_t) * (size_t)ni * sched->chains * NW);
@@ -1251,6 +1331,20 @@ int mmgap_detect_e(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, con
     }
     // the MMSE estimate (the build's factorisation and solves) only for its chain
     if ((rc = det_build_into(ctx, st, prob, sh, H, y, G, f, use_a ? xa : nullptr))) return rc;
+    if (lanes) {
+        // both chains, the choice and the decode in one launch after the build
+        // and the MMSE-SIC estimate
+        if (both) {
+            e = hipEventRecord(ctx->aux_ev[2], sb);
+            if (e == hipSuccess) e = hipStreamWaitEvent(st, ctx->aux_ev[2], 0);
+            if (e != hipSuccess) return hip_fail(ctx, e, "second stream");
+        }
+        rc = run_search(ctx, st, prob, sh, H, y, sched, stages, lanes, G, f,
+                        use_a ? xa : nullptr, use_b ? xb : nullptr, sym_out, metric_out,
+                        from_sic_out);
+        if (rc) return rc;
+        return end_call(ctx, st);
+    }
     e = mmgap::launch_fill_u8(zm, 0, (size_t)ni * KT, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "zero-move fill");
     if (both) {                   // the MMSE-SIC chain stays on the second stream
@@ -1366,6 +1460,16 @@ int mmgap_vpp_precode(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, 
                     at<float>(ctx, oE), at<uint32_t>(ctx, oS), sel);
     if (rc) return rc;
     return end_call(ctx, st);
+}
+
+int mmgap_set_option(mmgap_ctx *ctx, int option, int value)
+{
+    if (!ctx) return MMGAP_EINVAL;
+    if (option == MMGAP_OPT_STAGE_LAUNCHES && (value == 0 || value == 1)) {
+        ctx->stage_launches = value != 0;
+        return MMGAP_OK;
+    }
+    return fail(ctx, MMGAP_EINVAL, "unknown option %d or value %d", option, value);
 }
 
 int mmgap_set_profiling(mmgap_ctx *ctx, int enable)

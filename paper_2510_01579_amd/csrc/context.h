@@ -43,6 +43,7 @@ struct mmgap_ctx {
     hipEvent_t aux_ev[3] = {};                  // forks and the join of that stream
     bool done_valid = false;
     uint32_t *accept_dev = nullptr;             // Metropolis threshold table
+    bool stage_launches = false;                // MMGAP_OPT_STAGE_LAUNCHES
     bool profiling = false;
     long prof_count = 0;                        // profiled calls since enabling
     bool prof_open = false;                     // the current record has its start event

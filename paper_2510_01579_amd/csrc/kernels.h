@@ -165,6 +165,33 @@ struct PickArgs {
     unsigned char *from_b;  // [n_inst] or null: 1 where the second candidate won
 };
 
+// Detection by moves around one or two guesses in one launch (the stages,
+// selections, choice and decode of DeltaPrepArgs + AnnealArgs + SelectArgs
+// (kSelectDelta) + PickArgs, with identical results).  Metropolis anneals,
+// two unit-weight spins per real dimension.
+struct SearchArgs {
+    const float *G;         // [n_G][KT][KT] detection couplings (exactly symmetric)
+    int inst_per_G;         // instances per G (n_sym)
+    const float *f;         // [n_inst][KT] fields of the detection problem
+    const signed char *guess_a; // [n_inst][KT] guess of the chain with keys seed + s, or null
+    const signed char *guess_b; // [n_inst][KT] guess of the chain with keys
+                                // seed + kMaxStages + s, or null (B wins only if strictly lower)
+    const float *beta2;     // [sweeps] device
+    const uint32_t *accept_table;
+    int n_inst, K, sweeps, chains, stages, init_mode;
+    int glanes;             // lanes per instance: a power of two in [max(chains, 4), 64];
+                            // 64 / glanes must divide inst_per_G
+    uint32_t key0, key1, inst_base;
+    int dq;                 // bits per real dimension (clamp to +-(2^dq - 1), decode)
+    const float2 *H;        // [n_sc][n_rows][n_cols]
+    const float2 *y;        // [n_sc][n_sym][n_rows]; n_rows <= 2 glanes
+    int n_rows, n_cols, n_sym;
+    double c;
+    unsigned char *sym_out; // [n_inst][n_cols]
+    float *metric_out;      // [n_inst] or null
+    unsigned char *from_b;  // [n_inst] or null: 1 where the answer is chain B's
+};
+
 struct ExpandArgs {
     const float *G;         // [n_sc][K][K] (unpadded)
     const float *f;         // [n_inst][K]
@@ -234,6 +261,8 @@ hipError_t launch_select(const SelectArgs &a, hipStream_t s);
 hipError_t launch_delta_prep(const DeltaPrepArgs &a, hipStream_t s);
 hipError_t launch_sic(const SicArgs &a, hipStream_t s);
 hipError_t launch_pick(const PickArgs &a, hipStream_t s);
+// KT in {8, 16, 32}: the padded dimension count of the detection problem.
+hipError_t launch_search(int KT, const SearchArgs &a, hipStream_t s);
 hipError_t launch_expand(const ExpandArgs &a, hipStream_t s);
 // copy [n][K][K] -> [n][KT][KT] (and [m][K] -> [m][KT]) with zero padding
 hipError_t launch_pad_matrix(const float *src, float *dst, int n, int K, int KT, hipStream_t s);

@@ -570,11 +570,17 @@ __device__ void build_vpp_sc(const float2 *H, const float2 *u, int n, int ntx, i
 
 // Field entry f_k of this lane's instance: through the scalar cache when the
 // instance is wave-uniform, else a vector load whose address is re-derived at
-// each use (so that the compiler keeps no row of f in registers).
-template <bool PACKED>
+// each use (so that the compiler keeps no row of f in registers); FLDS: the
+// row is in LDS (a per-lane LDS address, read with an LDS load).
+template <bool PACKED, bool FLDS = false>
 __device__ __forceinline__ float load_field(const float *fi, int k)
 {
-    if constexpr (PACKED) {
+    if constexpr (FLDS) {
+        typedef __attribute__((address_space(3))) const float lds_float;
+        lds_float *p = (lds_float *)fi;
+        asm volatile("" : "+v"(p));
+        return p[k];
+    } else if constexpr (PACKED) {
         const float *p = fi;
         asm volatile("" : "+v"(p));
         return p[k];
@@ -645,7 +651,7 @@ __device__ __forceinline__ float lane_level_energy(const float *Gl, const float 
     return E;
 }
 
-template <int KT, int Q, bool PACKED = false>
+template <int KT, int Q, bool PACKED = false, bool FLDS = false>
 __device__ __forceinline__ float anneal_lane(const float *Gl, const float *fi,
                                              const signed char *xfb_i, const float *beta2,
                                              const uint32_t *T, int sweeps, const int (&wts)[4],
@@ -733,7 +739,7 @@ __device__ __forceinline__ float anneal_lane(const float *Gl, const float *fi,
         const float4 *G4 = reinterpret_cast<const float4 *>(Gl) + roff;
 #pragma unroll
         for (int k = 0; k < KT; ++k) {
-            const float fk = load_field<PACKED>(fi, k);
+            const float fk = load_field<PACKED, FLDS>(fi, k);
             // local field of dimension k from the current levels; PACKED reads
             // the row in chunks of 8 floats, each issued after the previous
             // chunk's products (the per-lane field loads leave fewer registers)
@@ -2318,6 +2324,240 @@ __global__ void __launch_bounds__(kBlock) k_pick(PickArgs a)
                a.H + (size_t)sc * a.n_rows * a.n_cols, a.y, a.sym_out, a.metric_out, lane);
 }
 
+// ---------------------------------------------------------------------------
+// Detection by moves around a guess (paper §2.3 Fig. 5) and MMGaP-E (§3.2
+// Fig. 6) in one launch: the stages that k_delta_prep, k_anneal, k_select
+// (kSelectDelta) and k_pick run as separate launches, with the same keys,
+// clamp, choices and decode, so the outputs are identical.  A wavefront keeps
+// its P = 64 / glanes instances (one subcarrier: one G, staged in LDS once)
+// from the first stage to the decode; each instance takes glanes lanes (one
+// chain each) and an LDS row for its move fields, guesses and scratch.  The
+// chain from guess A (keys seed + s) runs its stages, then the chain from
+// guess B (keys seed + kMaxStages + s).  Per stage, per instance:
+//   f' = f - G x_g (the move fields),
+//   the anneal of the move problem (levels {-2, 0, 2}) with the zero move as
+//   fallback, the group's best chain (lowest energy, then lowest index), the
+//   zero move instead if its energy is strictly lower,
+//   the move applied and clamped, kept iff the float32 energy with the full
+//   fields drops.
+// Then B's final guess if its energy is strictly lower than A's, and the decode.
+// The group reductions and sums keep the operation order of the
+// one-wavefront-per-instance kernels; the couplings are read by columns
+// (detection couplings are exactly symmetric), which gives the rows' values
+// without LDS bank conflicts.
+
+// LDS row of one instance: move fields, energy terms, guesses A and B, candidate.
+template <int KT>
+constexpr int search_row_bytes()
+{
+    return (11 * KT + 15) / 16 * 16;
+}
+template <int KT>
+struct SearchRow {
+    float *fp, *terms;
+    signed char *xa, *xb, *cand;
+    __device__ SearchRow(unsigned char *rows, int row)
+    {
+        unsigned char *r = rows + (size_t)row * search_row_bytes<KT>();
+        fp = reinterpret_cast<float *>(r);
+        terms = fp + KT;
+        xa = reinterpret_cast<signed char *>(terms + KT);
+        xb = xa + KT;
+        cand = xb + KT;
+    }
+};
+
+// Energy sum_k lv_k (g_k - f_k) with g = G lv - f of each group's instance
+// (the operations and order of wave_level_energy): lane j of a group of GL
+// lanes forms the terms of dimensions j, j + GL, ..., then every lane sums the
+// K terms in order.  Called by the whole wavefront.
+template <int KT>
+__device__ __forceinline__ float group_level_energy(const float *Gl, int K, const float *ff,
+                                                    const signed char *lv, float *terms, int j,
+                                                    int GL)
+{
+    for (int k = j; k < K; k += GL) {
+        float acc = -ff[k];
+        for (int l = 0; l < K; ++l) acc = fmaf(Gl[l * KT + k], (float)lv[l], acc);
+        terms[k] = acc - ff[k];
+    }
+    wave_sync_lds();
+    float e = 0.0f;
+    for (int k = 0; k < K; ++k) e = fmaf((float)lv[k], terms[k], e);
+    wave_sync_lds();
+    return e;
+}
+
+template <int KT>
+constexpr int search_min_waves()
+{
+    return KT <= 8 ? 8 : KT == 16 ? 6 : 5;
+}
+
+template <int KT>
+__global__ void __launch_bounds__(kBlock)
+    __attribute__((amdgpu_waves_per_eu(search_min_waves<KT>(), 8)))
+k_search(SearchArgs a)
+{
+    constexpr int NW = (2 * KT + 31) / 32;
+    __shared__ uint32_t T[kAcceptSteps + 1];
+    __shared__ float4 Gw[kWavesPerBlock][KT * KT / 4];
+    __shared__ signed char zrow[KT];              // the zero move
+    extern __shared__ float4 search_dyn4[];       // the instances' rows
+    unsigned char *rows = reinterpret_cast<unsigned char *>(search_dyn4);
+    for (int e = threadIdx.x; e <= kAcceptSteps; e += kBlock) T[e] = a.accept_table[e];
+    if (threadIdx.x < KT) zrow[threadIdx.x] = 0;
+    __syncthreads();
+
+    const int GL = a.glanes;
+    const int lg = __builtin_ctz((unsigned)GL);
+    const int per_wave = 64 >> lg;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int inst0 = (blockIdx.x * kWavesPerBlock + wave) * per_wave;
+    if (inst0 >= a.n_inst) return;     // whole wavefront; only wave-level exchange below
+    const bool use_a = a.guess_a != nullptr, use_b = a.guess_b != nullptr;
+    float *Gs = reinterpret_cast<float *>(Gw[wave]);
+    {
+        const int lane = threadIdx.x & 63, grp = lane >> lg, j = lane & (GL - 1);
+        const int n = inst0 + grp < a.n_inst ? inst0 + grp : inst0;
+        const float *Gg = a.G + (size_t)(inst0 / a.inst_per_G) * (KT * KT);
+        for (int e = lane; e < KT * KT; e += 64) Gs[e] = Gg[e];
+        const SearchRow<KT> R(rows, wave * per_wave + grp);
+        for (int k = j; k < KT; k += GL) {
+            if (use_a) R.xa[k] = a.guess_a[(size_t)n * KT + k];
+            if (use_b) R.xb[k] = a.guess_b[(size_t)n * KT + k];
+        }
+        wave_sync_lds();
+    }
+    const int qtop = (1 << a.dq) - 1;
+    const int wts[4] = {1, 1, 0, 0};
+    float Efin[2] = {0.0f, 0.0f};
+    for (int chain = 0; chain < 2; ++chain) {
+        if (!(chain ? use_b : use_a)) continue;
+        float Eg = 0.0f;                  // energy of the current guess (full fields)
+        for (int s = 0; s < a.stages; ++s) {
+            uint32_t bits[NW];
+            float E;
+            {
+                // lane coordinates from a fresh thread index at every stage, so
+                // that nothing derived from it is held across the anneal
+                int tid = threadIdx.x;
+                asm volatile("" : "+v"(tid));
+                const int lane = tid & 63, grp = lane >> lg, j = lane & (GL - 1);
+                const int n = inst0 + grp < a.n_inst ? inst0 + grp : inst0;
+                const SearchRow<KT> R(rows, wave * per_wave + grp);
+                const signed char *xg = chain ? R.xb : R.xa;
+                const float *ff = a.f + (size_t)n * KT;
+                if (s == 0) Eg = group_level_energy<KT>(Gs, a.K, ff, xg, R.terms, j, GL);
+                for (int k = j; k < KT; k += GL) {        // the move fields
+                    float g = 0.0f;
+                    for (int l = 0; l < KT; ++l) g = fmaf(Gs[l * KT + k], (float)xg[l], g);
+                    R.fp[k] = ff[k] - g;
+                }
+                wave_sync_lds();
+                const uint64_t kk = (((uint64_t)a.key1 << 32) | a.key0) + (uint64_t)s +
+                                    (uint64_t)(chain ? kMaxStages : 0);
+                uint32_t ginst = (uint32_t)n + a.inst_base;
+                asm volatile("" : "+v"(ginst));
+                E = anneal_lane<KT, 2, true, true>(Gs, R.fp, zrow, a.beta2, T, a.sweeps, wts,
+                                                   (uint32_t)kk, (uint32_t)(kk >> 32),
+                                                   a.init_mode, (uint32_t)j, ginst, bits);
+            }
+            int tid = threadIdx.x;
+            asm volatile("" : "+v"(tid));
+            const int lane = tid & 63, grp = lane >> lg, j = lane & (GL - 1);
+            const bool valid = inst0 + grp < a.n_inst;
+            const int n = valid ? inst0 + grp : inst0;
+            const SearchRow<KT> R(rows, wave * per_wave + grp);
+            signed char *xg = chain ? R.xb : R.xa;
+            const float *ff = a.f + (size_t)n * KT;
+            // the group's best chain: lowest energy, then lowest index
+            uint64_t key = ~0ull;
+            if (valid && j < a.chains) key = ((uint64_t)energy_key(E) << 32) | (uint32_t)j;
+            for (int off = GL >> 1; off >= 1; off >>= 1) {
+                const uint32_t lo = __shfl_xor((uint32_t)key, off, 64);
+                const uint32_t hi = __shfl_xor((uint32_t)(key >> 32), off, 64);
+                const uint64_t o = ((uint64_t)hi << 32) | lo;
+                key = o < key ? o : key;
+            }
+            const int src = (lane & ~(GL - 1)) | (int)((uint32_t)key & (uint32_t)(GL - 1));
+            const float Eb = __shfl(E, src, 64);
+            uint32_t S[NW];
+#pragma unroll
+            for (int w = 0; w < NW; ++w) S[w] = __shfl(bits[w], src, 64);
+            // the zero move (the fallback) with the move fields
+            const float Efb = group_level_energy<KT>(Gs, a.K, R.fp, zrow, R.terms, j, GL);
+            const bool use_fb = energy_less(Efb, Eb);
+            for (int k = j; k < a.K; k += GL) {
+                int z = 0;
+                if (!use_fb) {
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) {
+                        const int i = 2 * k + b;
+                        uint32_t word = S[0];
+#pragma unroll
+                        for (int w = 1; w < NW; ++w)
+                            if ((i >> 5) == w) word = S[w];
+                        z += ((word >> (i & 31)) & 1u) ? -1 : 1;
+                    }
+                }
+                const int v = (int)xg[k] + z;
+                R.cand[k] = (signed char)(v < -qtop ? -qtop : (v > qtop ? qtop : v));
+            }
+            wave_sync_lds();
+            const float Ec = group_level_energy<KT>(Gs, a.K, ff, R.cand, R.terms, j, GL);
+            if (Ec < Eg) {
+                for (int k = j; k < a.K; k += GL) xg[k] = R.cand[k];
+                Eg = Ec;
+            }
+            wave_sync_lds();
+        }
+        Efin[chain] = Eg;
+    }
+    // the answer (B's only if its energy is strictly lower) and its decode, as
+    // decode_det with the group's lanes: lane j takes receive antennas j and
+    // j + GL (n_rows <= 2 GL), and the group's butterfly gives the sum of the
+    // wavefront's
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, grp = lane >> lg, j = lane & (GL - 1);
+    const bool valid = inst0 + grp < a.n_inst;
+    const int n = valid ? inst0 + grp : inst0;
+    const SearchRow<KT> R(rows, wave * per_wave + grp);
+    const bool from_b = use_a && use_b ? Efin[1] < Efin[0] : use_b;
+    const signed char *lv = from_b ? R.xb : R.xa;
+    const int nt = a.n_cols, nr = a.n_rows;
+    const int sc = n / a.n_sym, sy = n - sc * a.n_sym;
+    if (valid) {
+        for (int t = j; t < nt; t += GL) {
+            const int pI = ((int)lv[t] + qtop) >> 1;
+            const int pQ = ((int)lv[nt + t] + qtop) >> 1;
+            const int gI = pI ^ (pI >> 1), gQ = pQ ^ (pQ >> 1);
+            a.sym_out[(size_t)n * nt + t] = (unsigned char)((gI << a.dq) | gQ);
+        }
+        if (a.from_b && j == 0) a.from_b[n] = from_b ? 1 : 0;
+    }
+    if (a.metric_out) {
+        const float2 *Hsc = a.H + (size_t)sc * nr * nt;
+        double part = 0.0;
+        for (int r = j; r < nr; r += GL) {
+            const float2 *Hr = Hsc + (size_t)r * nt;
+            const float2 yv = a.y[((size_t)sc * a.n_sym + sy) * nr + r];
+            double re = yv.x, im = yv.y;
+            for (int t = 0; t < nt; ++t) {
+                const double xr = a.c * (double)lv[t];
+                const double xi = a.c * (double)lv[nt + t];
+                const double hr = Hr[t].x, hi = Hr[t].y;
+                re = re - (hr * xr - hi * xi);
+                im = im - (hr * xi + hi * xr);
+            }
+            part = part + (re * re + im * im);
+        }
+        for (int off = GL >> 1; off >= 1; off >>= 1) part += __shfl_xor(part, off, 64);
+        if (valid && j == 0) a.metric_out[n] = (float)part;
+    }
+}
+
 __global__ void k_reset_counters(unsigned int *counters, int n)
 {
     if (blockIdx.x == 0 && (int)threadIdx.x < n) counters[threadIdx.x] = 0u;
@@ -2587,6 +2827,31 @@ hipError_t launch_sic(const SicArgs &a, hipStream_t s)
         return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_sic, dim3(a.n_sc), dim3(64), sic_lds_bytes(a.n_r, a.n_t), s, a);
     return hipGetLastError();
+}
+
+hipError_t launch_search(int KT, const SearchArgs &a, hipStream_t s)
+{
+    if (a.n_inst <= 0) return hipSuccess;
+    const int gl = a.glanes;
+    if (gl < 4 || gl > 64 || (gl & (gl - 1)) || a.chains < 1 || a.chains > gl ||
+        a.inst_per_G < 1 || a.inst_per_G % (64 / gl) != 0 || a.n_rows > 2 * gl ||
+        a.n_cols < 1 || 2 * a.n_cols != a.K || a.K > KT || a.stages < 1 ||
+        (!a.guess_a && !a.guess_b) || a.dq < 1 || a.dq > 3)
+        return hipErrorInvalidValue;
+    const size_t waves = ((size_t)a.n_inst + 64 / gl - 1) / (64 / gl);
+    const size_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
+#define MMGAP_SEARCH_CASE(kt)                                                               \
+    if (KT == kt) {                                                                        \
+        const size_t lds = (size_t)kWavesPerBlock * (64 / gl) * search_row_bytes<kt>();    \
+        hipLaunchKernelGGL(k_search<kt>, dim3((unsigned)blocks), dim3(kBlock), lds, s, a); \
+        return hipGetLastError();                                                          \
+    }
+    MMGAP_SEARCH_CASE(8)
+    MMGAP_SEARCH_CASE(16)
+    MMGAP_SEARCH_CASE(32)
+#undef MMGAP_SEARCH_CASE
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_pick(const PickArgs &a, hipStream_t s)
