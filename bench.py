@@ -600,10 +600,12 @@ def main(argv=None) -> int:  # noqa: C901
         return [{k: (None if t is None else t.cpu().numpy()) for k, t in o.items()}
                 for o in outs]
 
-    def fused_leg(scheds):
-        """One plan (HIP graph) per group with the given schedules per job."""
+    def fused_leg(scheds, graph=True, one_plan=False, blocks=0):
+        """One plan (a HIP graph unless graph=False) per group with the given
+        schedules per job; one_plan: every group's jobs in one plan, launched
+        once per step; blocks: the plan's grid (0: the library's choice)."""
         plans, jobs = [], []
-        for g in gidx:
+        for g in ([sum(gidx, [])] if one_plan else gidx):
             gj = []
             for i in g:
                 inp, sc, j = inputs[i], scheds[i], inputs[i]["spec"]
@@ -616,10 +618,13 @@ def main(argv=None) -> int:  # noqa: C901
                     gj.append(ctx.vpp_job(inp["H_d"], inp["y_d"], j["qam"], sc["chains"],
                                           sc["sweeps"], sc["beta2"], inp["seed"],
                                           init=sc["init"]))
-            plans.append(ctx.plan_create(gj, graph=True))
+            plans.append(ctx.plan_create(gj, graph=graph, blocks=blocks))
             jobs.extend(gj)
         info = [p.plan_info() for p in plans]
-        el, lat = timed(lambda gi: plans[gi].plan_launch())
+        if one_plan:
+            el, lat = timed(lambda gi: plans[0].plan_launch() if gi == 0 else None)
+        else:
+            el, lat = timed(lambda gi: plans[gi].plan_launch())
         torch.cuda.synchronize()
         outs = host_outs([jb["outputs"] for jb in jobs])
         for p in plans:
@@ -694,6 +699,7 @@ def main(argv=None) -> int:  # noqa: C901
             t_scheds.append(ts if ts["tuned"] else ref_scheds[len(t_scheds)])
         print("[bench] tuned leg", file=sys.stderr, flush=True)
         el, lat, t_out, _ = fused_leg(t_scheds)
+        t_out_ref = t_out
         q_t = quality(inputs, t_out)
         tuned = leg_record(el, lat, q_t, {
             "schedules": [sched_desc(s) for s in t_scheds],
@@ -734,6 +740,7 @@ def main(argv=None) -> int:  # noqa: C901
     # ---- the tuner's choice among every formulation (MMGaP-E and the MMSE-SIC
     # guess included) through the separate-launch entry points
     tuned_sep = None
+    stage_launch_ms = None
     if tuned is not None and is_det:
         a_scheds = []
         for inp, ts in zip(inputs, t_scheds):
@@ -777,6 +784,54 @@ def main(argv=None) -> int:  # noqa: C901
                 "stage_ms": {"anneal": float(np.mean(sprof[:, :, 1].sum(axis=1)))},
                 "quality_matched": matched(q_s, q_ref)})
             legs["tuned_separate"] = (el, lat, a_scheds)
+            if not args.no_extras:
+                # the same jobs with every stage as separate launches
+                ctx.set_stage_launches(True)
+                try:
+                    el_st, _ = timed(sep_group)
+                    st_out = host_outs([o for gi in range(len(groups)) for o in sep_group(gi)])
+                finally:
+                    ctx.set_stage_launches(False)
+                stage_launch_ms = (el_st / args.steps * 1e3,
+                                   same_bytes(st_out, s_out, ("sym", "metric")))
+
+    # ---- ablation: the result-invariant choices, one at a time, at the schedules
+    # above (the survey's split of the speed-up over the plain path)
+    ablation = None
+    if tuned is not None and plain is not None and not args.no_extras:
+        print("[bench] ablation", file=sys.stderr, flush=True)
+
+        def step_ms(el):
+            return el / args.steps * 1e3
+
+        rows = [{"step": "plain: build, anneal, select launches per slot, reference schedule",
+                 "ms_per_step": plain["ms_per_step"]},
+                {"step": "fusion + LDS: one persistent launch per slot (HIP graph), same schedule",
+                 "ms_per_step": fused["ms_per_step"], "identical_outputs": fused[
+                     "outputs_identical_to_plain"]}]
+        el_ng, _, o_ng, _ = fused_leg(t_scheds, graph=False)
+        rows.append({"step": "tuned schedule table (changes SER): one persistent launch per "
+                             "slot, no HIP graph", "ms_per_step": step_ms(el_ng)})
+        rows.append({"step": "+ HIP graph per slot (the tuned leg)",
+                     "ms_per_step": tuned["ms_per_step"],
+                     "identical_outputs": same_bytes(o_ng, t_out_ref, ("sym", "metric"))})
+        if len(groups) > 1:
+            el_one, _, o_one, _ = fused_leg(t_scheds, one_plan=True)
+            rows.append({"step": "mixed-size packing: every slot of the step in one persistent "
+                                 "launch (HIP graph)", "ms_per_step": step_ms(el_one),
+                         "identical_outputs": same_bytes(o_one, t_out_ref, ("sym", "metric"))})
+        el_b, _, o_b, _ = fused_leg(t_scheds, blocks=256)
+        rows.append({"step": "mapping: one workgroup per CU instead of the library's resident "
+                             "count (per slot, HIP graph)", "ms_per_step": step_ms(el_b),
+                     "identical_outputs": same_bytes(o_b, t_out_ref, ("sym", "metric"))})
+        if tuned_sep is not None and stage_launch_ms is not None:
+            rows.append({"step": "separate launches at the fastest tuned formulation, every "
+                                 "stage as its own launches", "ms_per_step": stage_launch_ms[0],
+                         "identical_outputs": stage_launch_ms[1]})
+            rows.append({"step": "+ one search launch per slot for moves around a guess and "
+                                 "MMGaP-E (the tuned_separate leg)",
+                         "ms_per_step": tuned_sep["ms_per_step"]})
+        ablation = {"schedules_fused": [sched_desc(s) for s in t_scheds], "rows": rows}
 
     # ---- detection extras: MMGaP-E, MMSE-SIC, the SIC-guess search
     extras = {}
@@ -995,6 +1050,7 @@ def main(argv=None) -> int:  # noqa: C901
         "delta_separate": delta_sep,
         "tuned_separate": tuned_sep,
         **extras,
+        "ablation": ablation,
         "roofline": {
             "bound": "alu", "kernel": kname,
             "achieved": achieved / 1e12, "peak": PEAK_ALU_OPS / 1e12, "unit": "T lane-ops/s",

@@ -310,10 +310,12 @@ int mmgap_detect_sic(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, c
  * the sliced MMSE estimate (Philox keys sched->seed + s) and one from the
  * MMSE-SIC estimate of mmgap_detect_sic (keys sched->seed + 64 + s); the
  * output is the better final answer by the float32 energy x^T G x - 2 f^T x,
- * the MMSE-SIC chain's only if strictly lower.  Same limits as both.  With
- * both chains the MMSE-SIC estimate and its chain run on a second stream of the
- * context, forked from and joined back into `stream` (the call stays ordered
- * on `stream` like every other call).
+ * the MMSE-SIC chain's only if strictly lower.  Same limits as both.  Where
+ * the one-launch search runs (mmgap_set_option) the MMSE-SIC estimate, the
+ * build and the search follow one another on `stream`; through the stage
+ * launches, with both chains, the MMSE-SIC estimate and its chain run on a
+ * second stream of the context, forked from and joined back into `stream`
+ * (the call stays ordered on `stream` like every other call).
  *   guesses       MMGAP_GUESS_MMSE | MMGAP_GUESS_SIC runs both chains (the
  *                 paper's MMGaP-E); one of them runs that chain alone, whose
  *                 answer is then the output (else MMGAP_EINVAL)

@@ -1281,10 +1281,10 @@ int mmgap_detect_e(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, con
     hipStream_t st = (hipStream_t)stream;
     const bool use_a = guesses & MMGAP_GUESS_MMSE, use_b = guesses & MMGAP_GUESS_SIC;
     const int KT = sh.KT, NW = mmgap::spin_words(KT, 2), ni = sh.n_inst;
-    // Each chain has its own move fields and chain state: with both guesses the
-    // MMSE-SIC guess and its chain run on the context's second stream, beside
-    // the build and the chain from the MMSE guess (paper section 5.3: the two
-    // guesses of MMGaP-E are independent).
+    // Through the stage launches each chain has its own move fields and chain
+    // state, and with both guesses the MMSE-SIC guess and its chain run on the
+    // context's second stream, beside the build and the chain from the MMSE
+    // guess (paper section 5.3: the two guesses of MMGaP-E are independent).
     const bool both = use_a && use_b;
     Bump plan;
     const size_t oG = plan.take(sizeof(float) * (size_t)prob->n_sc * KT * KT);
@@ -1313,11 +1313,13 @@ int mmgap_detect_e(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, con
     signed char *xa = at<signed char>(ctx, oxa), *xb = at<signed char>(ctx, oxb);
     signed char *zm = at<signed char>(ctx, oz);
     hipError_t e = hipSuccess;
-    // with both chains the MMSE-SIC estimate goes to the second stream, beside
-    // the build (alone, the two latency-bound kernels run faster one after the
-    // other on one stream: measured 0.39 against 0.44 ms on a 16x16 slot)
-    hipStream_t sb = both ? ctx->aux : st;
-    if (both) {
+    // with both chains through the stage launches the MMSE-SIC estimate goes to
+    // the second stream, beside the build; otherwise the two latency-bound
+    // kernels run faster one after the other on one stream (measured 0.39
+    // against 0.44 ms for one chain on a 16x16 slot)
+    const bool fork = both && !lanes;
+    hipStream_t sb = fork ? ctx->aux : st;
+    if (fork) {
         e = hipEventRecord(ctx->aux_ev[0], st);
         if (e == hipSuccess) e = hipStreamWaitEvent(sb, ctx->aux_ev[0], 0);
         if (e != hipSuccess) return hip_fail(ctx, e, "second stream");
@@ -1334,11 +1336,6 @@ int mmgap_detect_e(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, con
     if (lanes) {
         // both chains, the choice and the decode in one launch after the build
         // and the MMSE-SIC estimate
-        if (both) {
-            e = hipEventRecord(ctx->aux_ev[2], sb);
-            if (e == hipSuccess) e = hipStreamWaitEvent(st, ctx->aux_ev[2], 0);
-            if (e != hipSuccess) return hip_fail(ctx, e, "second stream");
-        }
         rc = run_search(ctx, st, prob, sh, H, y, sched, stages, lanes, G, f,
                         use_a ? xa : nullptr, use_b ? xb : nullptr, sym_out, metric_out,
                         from_sic_out);
@@ -1347,7 +1344,7 @@ int mmgap_detect_e(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H, con
     }
     e = mmgap::launch_fill_u8(zm, 0, (size_t)ni * KT, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "zero-move fill");
-    if (both) {                   // the MMSE-SIC chain stays on the second stream
+    if (fork) {                   // the MMSE-SIC chain stays on the second stream
         e = hipEventRecord(ctx->aux_ev[1], st);
         if (e == hipSuccess) e = hipStreamWaitEvent(sb, ctx->aux_ev[1], 0);
         if (e != hipSuccess) return hip_fail(ctx, e, "second stream");
