@@ -117,11 +117,11 @@ def schedule_key(c) -> str:
 
 # MMGaP-E and the MMSE-SIC-guess search (separate launches only: persistent
 # plans run the binary encoding and moves around the MMSE guess)
-E_CHAINS = (4, 8, 16, 32)
-E_SWEEPS = (2, 4, 8, 12, 25)
-E_STAGES = (1, 2, 3)
+E_CHAINS = (4, 8, 16, 32, 64)
+E_SWEEPS = (2, 4, 8, 12, 25, 50)
+E_STAGES = (1, 2, 3, 4)
 E_SHAPES = ((0.0, 1.0), (0.25, 1.0))
-E_MAX_WORK = 1600
+E_MAX_WORK = 6400
 
 
 def e_candidates():
@@ -398,7 +398,8 @@ def main(argv=None) -> int:
                 (e_candidates() if args.add_e else [])
             t0 = time.time()
             for k, r in enumerate(rec["per_snr"]):
-                q = measure(ctx, name, r["snr_db"], cands, args.n_sc, args.n_sym,
+                todo = [c for c in cands if schedule_key(c) not in r["cands"]]
+                q = measure(ctx, name, r["snr_db"], todo, args.n_sc, args.n_sym,
                             args.seed + 17 * k)
                 r["cands"].update({schedule_key(c): v for c, v in q.items()})
             rec["buckets"] = select(name, rec)
