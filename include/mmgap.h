@@ -27,8 +27,8 @@
  *  * Sizes (MMGAP_EUNSUPPORTED outside them): DET n_tx <= 32 users, more than
  *    16 users only with QPSK or 16-QAM, n_rx <= 64; VPP n_rx <= 16 users,
  *    n_tx <= 64 antennas; n_sym <= 64; chains 1..1024; sweeps 1..8192.  The
- *    entry points around MMSE-SIC need n_tx <= 16, CIM-CAC dynamics K q <= 32
- *    spins (K padded to 8, 16 or 32), batches and the server K <= 32 and
+ *    entry points around MMSE-SIC need n_tx <= 16, CIM-CAC dynamics K <= 32
+ *    and K q <= 64 spins (K padded to 8, 16 or 32), batches and the server K <= 32 and
  *    chains <= 256.
  *  * A context must not be used by two host threads at once.
  *
@@ -121,7 +121,7 @@ typedef struct {
     uint64_t seed;         /* Philox4x32-10 key: (seed & 0xffffffff, seed >> 32) */
     int init;              /* 0: random initial spins from Philox; 1: start from the fallback levels */
     int dynamics;          /* MMGAP_DYN_METROPOLIS (0, also for zero-initialised schedules) or
-                              MMGAP_DYN_CIM (plain entry points only; K q <= 32 spins) */
+                              MMGAP_DYN_CIM (plain entry points only; K <= 32, K q <= 64) */
     const mmgap_cim_params *cim;  /* (host) constants of MMGAP_DYN_CIM, else unused */
     uint32_t inst_base;    /* Philox instance index of the call's instance 0 (0 for a whole
                               slot; a * n_sym for a call on subcarriers [a, b) of it) */
@@ -182,7 +182,7 @@ int mmgap_build_ising(mmgap_ctx *ctx, const mmgap_problem *prob, const void *H,
  * Energies E = fma(x_K-1, g_K-1 - f_K-1, ... fma(x_0, g_0 - f_0, 0)) with
  * fresh fields.  Ties in energy keep the lowest chain index.
  * With sched->dynamics = MMGAP_DYN_CIM each anneal is instead `sweeps` Euler
- * steps of the CIM-CAC model (mmgap_cim_params), N = K q <= 32, with the
+ * steps of the CIM-CAC model (mmgap_cim_params), N = K q <= 64 (K <= 32), with the
  * float32 arithmetic (every operation rounded once, fma as above)
  *   X_l = fma(w_q-1, x_(l,q-1), ... fma(w_0, x_(l,0), 0)),
  *   g_k = fma(G_k,K-1, X_K-1, ... fma(G_k0, X_0, 0)),
@@ -247,7 +247,8 @@ int mmgap_detect_noalloc(mmgap_ctx *ctx, const mmgap_problem *prob, const void *
  * the integration (paper Appendix A: the sign of the final amplitudes and
  * whether the integration diverged, against a fine-step reference with the
  * same initial values).  Arguments as mmgap_solve; sched must select
- * MMGAP_DYN_CIM (else MMGAP_EINVAL) and K q (padded) <= 32.  No selection.
+ * MMGAP_DYN_CIM (else MMGAP_EINVAL), K (padded) <= 32 and K q (padded) <= 64.
+ * No selection.
  *   spins_out     [n_inst][chains][K q] int8 +-1, sign(x_i) sign(x_a) (out)
  *   e_out         [n_inst][chains] float32 energies of those spins (out, nullable)
  *   diverged_out  [n_inst][chains] uint8 (out, nullable): 1 where an amplitude of a

@@ -288,9 +288,9 @@ int run_solver(mmgap_ctx *ctx, hipStream_t st, int n_inst, int K, int q, int KT,
                mmgap::SelectArgs sel)
 {
     const bool cim = sched->dynamics == MMGAP_DYN_CIM;
-    if (cim && KT * q > 32)
-        return fail(ctx, MMGAP_EUNSUPPORTED, "CIM dynamics needs K q <= 32 spins (padded %d)",
-                    KT * q);
+    if (cim && (KT > 32 || KT * q > 64))
+        return fail(ctx, MMGAP_EUNSUPPORTED,
+                    "CIM dynamics needs K <= 32 and K q <= 64 spins (padded %d x %d)", KT, q);
     const float *beta = nullptr;
     if (!cim) {
         int rc = upload_beta(ctx, sched, st, &beta);
@@ -830,9 +830,9 @@ int mmgap_cim_chains(mmgap_ctx *ctx, int n_inst, int K, int q, const signed char
     if (sched->dynamics != MMGAP_DYN_CIM)
         return fail(ctx, MMGAP_EINVAL, "mmgap_cim_chains needs a CIM-CAC schedule");
     const int KT = mmgap::padded_k(K);
-    if (KT * q > 32)
-        return fail(ctx, MMGAP_EUNSUPPORTED, "CIM dynamics needs K q <= 32 spins (padded %d)",
-                    KT * q);
+    if (KT > 32 || KT * q > 64)
+        return fail(ctx, MMGAP_EUNSUPPORTED,
+                    "CIM dynamics needs K <= 32 and K q <= 64 spins (padded %d x %d)", KT, q);
     if (n_inst == 0) return MMGAP_OK;
     if (!G || !f || !spins_out)
         return fail(ctx, MMGAP_EINVAL, "G, f and spins_out are required");

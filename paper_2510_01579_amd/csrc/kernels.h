@@ -255,7 +255,8 @@ hipError_t fused_blocks_per_cu(int cls, int *blocks);
 hipError_t launch_det_build(const DetBuildArgs &a, hipStream_t s);
 hipError_t launch_vpp_build(const VppBuildArgs &a, hipStream_t s);
 hipError_t launch_anneal(int KT, int q, const AnnealArgs &a, hipStream_t s);
-// CIM-CAC anneals (same outputs as launch_anneal); KT q <= 32.
+// CIM-CAC anneals (same outputs as launch_anneal); KT q <= 32 one lane per
+// anneal, (KT, q) in {(16, 3), (16, 4), (32, 2)} two lanes per anneal.
 hipError_t launch_cim(int KT, int q, const AnnealArgs &a, hipStream_t s);
 hipError_t launch_select(const SelectArgs &a, hipStream_t s);
 hipError_t launch_delta_prep(const DeltaPrepArgs &a, hipStream_t s);

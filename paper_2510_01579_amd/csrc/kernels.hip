@@ -983,6 +983,237 @@ __device__ __forceinline__ float cim_lane(const float *Gl, const float *fi,
     return lane_level_energy<KT>(Gl, fi, x);
 }
 
+// One CIM-CAC anneal per pair of lanes, for 33 to 64 spins (the paper's
+// 16-user move problem has 64 spins and the auxiliary one): lane h of the pair
+// (h = lane & 1) holds the amplitudes, error variables and held coupling terms
+// of dimensions h KT/2 .. (h + 1) KT/2 - 1 (NH = KT Q / 2 spins) and a copy of
+// the auxiliary spin's.  At each coupling refresh the pair swaps its levels
+// (one cross-lane move per level), so that each lane forms the rows g_k of its
+// own dimensions over all KT levels and the auxiliary term over all KT fields,
+// in the order of cim_lane; both lanes then hold the same auxiliary values.
+// Every spin's update is cim_lane's, so the anneal is the same to the bit.
+// Returns the energy of the final spins (both lanes); `bits` receives all
+// spin words (both lanes) and `diverged` the flag over all spins.
+template <int KT, int Q, bool PACKED>
+__device__ __forceinline__ float cim_lane2(const float *Gl, const float *fi,
+                                           const signed char *xfb_i, const CimParams &P,
+                                           int steps, const int (&wts)[4], uint32_t key0,
+                                           uint32_t key1, int init_mode, uint32_t uch,
+                                           uint32_t uinst, uint32_t (&bits)[(KT * Q + 31) / 32],
+                                           int n_real, bool &diverged, int h)
+{
+    constexpr int N = KT * Q;
+    constexpr int NW = (N + 31) / 32;
+    constexpr int KH = KT / 2;                 // dimensions of this lane
+    constexpr int NH = KH * Q;                 // spins of this lane
+    static_assert(NH % 8 == 0, "whole Philox blocks per lane");
+    float amp[NH + 1], err[NH + 1], cpl[NH + 1];
+    float wf[Q];
+#pragma unroll
+    for (int b = 0; b < Q; ++b) wf[b] = (float)wts[b];
+    float dt = P.dt, pm1 = P.pm1, ca0 = P.a, nz = P.nzeta, eps = P.eps;
+    asm volatile("" : "+v"(dt), "+v"(pm1), "+v"(ca0), "+v"(nz), "+v"(eps));
+    const float inv = 1.0f / 32768.0f;                   // exact
+    const int k0 = h * KH;                               // first dimension of this lane
+    if (init_mode == 1 && xfb_i != nullptr) {
+#pragma unroll
+        for (int kl = 0; kl < KH; ++kl) {
+            int rem = xfb_i[k0 + kl];
+#pragma unroll
+            for (int b = 0; b < Q; ++b) {
+                const int sg = rem > 0 ? 1 : -1;
+                rem -= wts[b] * sg;
+                amp[kl * Q + b] = P.amp0 * (float)sg;
+            }
+        }
+        amp[NH] = P.amp0;
+    } else {
+#pragma unroll
+        for (int jj = 0; jj < NH / 8; ++jj) {
+            // spin i = h NH + 8 jj + e takes draw i: block i / 8, half-word i % 8
+            uint32_t r[4] = {(uint32_t)(h * (NH / 8) + jj), 0xFFFFFFFFu, uch, uinst};
+            philox4x32_10(r, key0, key1);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const uint32_t d = (e & 1) ? (r[e >> 1] >> 16) : (r[e >> 1] & 0xFFFFu);
+                amp[8 * jj + e] = P.amp0 * ((float)((int)d - 32768) * inv);
+            }
+        }
+        uint32_t r[4] = {0x1FFFFFFFu, 0xFFFFFFFFu, uch, uinst};   // draw 0xfffffff8
+        philox4x32_10(r, key0, key1);
+        amp[NH] = P.amp0 * ((float)((int)(r[0] & 0xFFFFu) - 32768) * inv);
+    }
+#pragma unroll
+    for (int i = 0; i <= NH; ++i) {
+        err[i] = 1.0f;
+        cpl[i] = 0.0f;
+    }
+    const float efloor = 1.0f / 1048576.0f;             // 2^-20
+    const int fm = P.f_mvm;
+    for (int t = 0; t < steps; ++t) {
+        if (t % fm == 0) {
+            // the levels of all KT dimensions: this lane's and its partner's
+            float X[KT];
+#pragma unroll
+            for (int kl = 0; kl < KH; ++kl) {
+                float v = 0.0f;
+#pragma unroll
+                for (int b = 0; b < Q; ++b) v = fmaf(wf[b], amp[kl * Q + b], v);
+                const float o = __shfl_xor(v, 1, 64);
+                X[kl] = h ? o : v;
+                X[KH + kl] = h ? v : o;
+            }
+            const float xa = amp[NH];
+            float acc_a = 0.0f;
+#pragma unroll
+            for (int k = 0; k < KT; ++k) acc_a = fmaf(2.0f * load_field<PACKED>(fi, k), X[k], acc_a);
+            int roff = k0 * (KT / 4);
+            asm volatile("" : "+v"(roff));
+            const float4 *G4 = reinterpret_cast<const float4 *>(Gl) + roff;
+#pragma unroll
+            for (int kl = 0; kl < KH; ++kl) {
+                float g = 0.0f;
+#pragma unroll
+                for (int l4 = 0; l4 < KT / 4; ++l4) {
+                    const float4 v = G4[kl * (KT / 4) + l4];
+                    g = fmaf(v.x, X[4 * l4 + 0], g);
+                    g = fmaf(v.y, X[4 * l4 + 1], g);
+                    g = fmaf(v.z, X[4 * l4 + 2], g);
+                    g = fmaf(v.w, X[4 * l4 + 3], g);
+                }
+                const int k = k0 + kl;
+                const float gkk = Gl[k * KT + k];
+                const float fk = load_field<PACKED>(fi, k);
+#pragma unroll
+                for (int b = 0; b < Q; ++b) {
+                    const int i = kl * Q + b;
+                    const float self = gkk * (wf[b] * amp[i]);
+                    const float inner = g - self;
+                    const float t1 = (-2.0f * wf[b]) * inner;
+                    const float t2 = ((2.0f * wf[b]) * fk) * xa;
+                    cpl[i] = t1 + t2;
+                }
+            }
+            cpl[NH] = acc_a;
+        }
+#pragma unroll
+        for (int i = 0; i <= NH; ++i) {
+            const float x = amp[i], e = err[i];
+            const float s2 = x * x;
+            const float lin = pm1 * x;
+            const float cub = s2 * x;
+            const float drift = lin - cub;
+            const float gain = eps * e;
+            const float push = gain * cpl[i];
+            const float dx = drift + push;
+            const float stp = dt * dx;
+            const float t1 = s2 - ca0;
+            const float t2 = t1 * e;
+            const float de = nz * t2;
+            const float estp = dt * de;
+            const float en = e + estp;
+            amp[i] = x + stp;
+            err[i] = en > efloor ? en : efloor;
+        }
+    }
+    bool div = !(fabsf(amp[NH]) <= kCimDivergeBound) || !(fabsf(err[NH]) <= FLT_MAX);
+#pragma unroll
+    for (int il = 0; il < NH; ++il) {
+        if (h * NH + il < n_real)
+            div = div || !(fabsf(amp[il]) <= kCimDivergeBound) || !(fabsf(err[il]) <= FLT_MAX);
+    }
+    diverged = div || __shfl_xor(div ? 1 : 0, 1, 64) != 0;
+    const bool aneg = amp[NH] < 0.0f;
+    uint32_t own[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) own[w] = 0u;
+    float x[KT];
+#pragma unroll
+    for (int kl = 0; kl < KH; ++kl) {
+        int lv = 0;
+#pragma unroll
+        for (int b = 0; b < Q; ++b) {
+            const int il = kl * Q + b;
+            const bool neg = (amp[il] < 0.0f) != aneg;
+            lv += neg ? -wts[b] : wts[b];
+            // global spin h NH + il: word and bit for either half
+            const int i0 = il, i1 = NH + il;
+            const uint32_t m = neg ? 1u : 0u;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const uint32_t b0 = (i0 >> 5) == w ? m << (i0 & 31) : 0u;
+                const uint32_t b1 = (i1 >> 5) == w ? m << (i1 & 31) : 0u;
+                own[w] |= h ? b1 : b0;
+            }
+        }
+        const float v = (float)lv;
+        const float o = __shfl_xor(v, 1, 64);
+        x[kl] = h ? o : v;
+        x[KH + kl] = h ? v : o;
+    }
+#pragma unroll
+    for (int w = 0; w < NW; ++w) bits[w] = own[w] | __shfl_xor(own[w], 1, 64);
+    return lane_level_energy<KT>(Gl, fi, x);
+}
+
+// CIM-CAC anneals of 33 to 64 spins, one per pair of lanes (cim_lane2): PACKED
+// 64 / gl2 instances per wavefront with gl2 lanes each (gl2 / 2 anneals), or
+// 32 anneals of one instance per wavefront (several wavefronts for more).
+// Outputs as k_cim.
+template <int KT, int Q, bool PACKED>
+__global__ void __launch_bounds__(kBlock)
+k_cim2(const float *__restrict__ G, int inst_per_G, const float *__restrict__ f,
+       const signed char *__restrict__ x_fb, CimParams prm, int steps, int chains, int n_inst,
+       int w0, int w1, int w2, int w3, uint32_t key0, uint32_t key1, uint32_t inst_base,
+       int init_mode, int gl2, float *__restrict__ chain_E, uint32_t *__restrict__ chain_S,
+       unsigned char *__restrict__ chain_div, int n_real)
+{
+    constexpr int NW = (KT * Q + 31) / 32;
+    __shared__ float4 Gw[kWavesPerBlock][KT * KT / 4];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int gw = blockIdx.x * kWavesPerBlock + wave;
+    int inst, ch, inst0;
+    bool valid = true;
+    if constexpr (PACKED) {
+        const int per_wave = 64 / gl2;
+        inst0 = gw * per_wave;
+        if (inst0 >= n_inst) return;
+        inst = inst0 + lane / gl2;
+        ch = (lane % gl2) >> 1;
+        if (inst >= n_inst) {               // tail of the last wavefront: any valid data
+            valid = false;
+            inst = inst0;
+        }
+    } else {
+        const int wpi = (chains + 31) >> 5;
+        inst = gw / wpi;
+        if (inst >= n_inst) return;
+        inst0 = inst;
+        ch = (gw - inst * wpi) * 32 + (lane >> 1);
+    }
+    const float *Gi = G + (size_t)(inst0 / inst_per_G) * (KT * KT);
+    float *Gs = reinterpret_cast<float *>(Gw[wave]);
+    for (int e = lane; e < KT * KT; e += 64) Gs[e] = Gi[e];
+    wave_sync_lds();
+    const float *fi = f + (size_t)inst * KT;
+    const signed char *xi = x_fb ? x_fb + (size_t)inst * KT : nullptr;
+    const int wts[4] = {w0, w1, w2, w3};
+    uint32_t bits[NW];
+    bool div;
+    uint32_t ginst = (uint32_t)inst + inst_base;
+    asm volatile("" : "+v"(ginst));
+    const float E = cim_lane2<KT, Q, PACKED>(Gs, fi, xi, prm, steps, wts, key0, key1, init_mode,
+                                             (uint32_t)ch, ginst, bits, n_real, div, lane & 1);
+    if (valid && ch < chains && (lane & 1) == 0) {
+        const size_t o = (size_t)(ginst - inst_base) * chains + ch;
+        chain_E[o] = E;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) chain_S[o * NW + w] = bits[w];
+        if (chain_div) chain_div[o] = div ? 1 : 0;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Selection helpers.
 __device__ __forceinline__ uint32_t energy_key(float e)
@@ -2688,6 +2919,34 @@ hipError_t launch_anneal_t(const AnnealArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+// 33 to 64 spins: two lanes per anneal, so an instance takes 2 glanes lanes
+// (32 anneals per wavefront when glanes is 0 or 32).
+template <int KT, int Q>
+hipError_t launch_cim2_t(const AnnealArgs &a, hipStream_t s)
+{
+    if (a.glanes > 0 && (a.glanes > 32 || (a.glanes & (a.glanes - 1)) || a.chains > a.glanes ||
+                         a.inst_per_G % (64 / a.glanes) != 0))
+        return hipErrorInvalidValue;
+    if (a.cim.f_mvm < 1) return hipErrorInvalidValue;
+    const int gl2 = a.glanes > 0 && a.glanes < 32 ? 2 * a.glanes : 0;
+    const size_t waves = gl2 > 0 ? ((size_t)a.n_inst + 64 / gl2 - 1) / (64 / gl2)
+                                 : (size_t)a.n_inst * ((a.chains + 31) / 32);
+    const size_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (blocks == 0) return hipSuccess;
+    if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    if (gl2 > 0)
+        hipLaunchKernelGGL((k_cim2<KT, Q, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a.G,
+                           a.inst_per_G, a.f, a.x_fb, a.cim, a.sweeps, a.chains, a.n_inst, a.w[0],
+                           a.w[1], a.w[2], a.w[3], a.key0, a.key1, a.inst_base, a.init_mode,
+                           gl2, a.chain_E, a.chain_S, a.chain_div, a.n_real);
+    else
+        hipLaunchKernelGGL((k_cim2<KT, Q, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                           a.G, a.inst_per_G, a.f, a.x_fb, a.cim, a.sweeps, a.chains, a.n_inst,
+                           a.w[0], a.w[1], a.w[2], a.w[3], a.key0, a.key1, a.inst_base,
+                           a.init_mode, 0, a.chain_E, a.chain_S, a.chain_div, a.n_real);
+    return hipGetLastError();
+}
+
 template <int KT, int Q>
 hipError_t launch_cim_t(const AnnealArgs &a, hipStream_t s)
 {
@@ -2762,6 +3021,9 @@ hipError_t launch_cim(int KT, int q, const AnnealArgs &a, hipStream_t s)
     MMGAP_CIM_CASE(16, 2)
     MMGAP_CIM_CASE(32, 1)
 #undef MMGAP_CIM_CASE
+    if (KT == 16 && q == 3) return launch_cim2_t<16, 3>(a, s);
+    if (KT == 16 && q == 4) return launch_cim2_t<16, 4>(a, s);
+    if (KT == 32 && q == 2) return launch_cim2_t<32, 2>(a, s);
     return hipErrorInvalidValue;
 }
 

@@ -128,9 +128,9 @@ def test_stages(ctx):
 
 
 def test_cim_spins(ctx):
-    note("CIM-CAC 32 spins (8x8 16-QAM) ok, 48 (8x8 64-QAM) refused")
-    ok_then_refused(lambda: ctx.detect(*det_inputs(8, 8), 16, 1.0, 4, 4, None, 1, cim={}),
-                    lambda: ctx.detect(*det_inputs(8, 8), 64, 1.0, 4, 4, None, 1, cim={}))
+    note("CIM-CAC 64 spins (16x16 16-QAM) ok, 96 (16x16 64-QAM) refused")
+    ok_then_refused(lambda: ctx.detect(*det_inputs(16, 16), 16, 1.0, 4, 4, None, 1, cim={}),
+                    lambda: ctx.detect(*det_inputs(16, 16), 64, 1.0, 4, 4, None, 1, cim={}))
 
 
 def test_batch_limits(ctx):

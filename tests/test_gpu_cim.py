@@ -142,9 +142,9 @@ def test_cim_full_slot_8x8_16qam_sampled(ctx):
 
 def test_cim_arguments(ctx):
     note("cim argument errors")
-    d = W.det_slot(5, 8, 8, 64, 3, 2, 20.0)
+    d = W.det_slot(5, 16, 16, 64, 3, 2, 20.0)
     H, y = dev(d.H), dev(d.y)
-    with pytest.raises(M.MmgapError) as e:          # 8x8 64-QAM: 48 spins
+    with pytest.raises(M.MmgapError) as e:          # 16x16 64-QAM: 96 spins
         ctx.detect(H, y, 64, d.noise_var, 32, 10, None, 1, cim={})
     assert e.value.code == -4
     d = W.det_slot(6, 4, 4, 16, 3, 2, 20.0)
@@ -203,10 +203,10 @@ def test_cim_chains_arguments(ctx):
     rc = M.lib().mmgap_cim_chains(ctx._h, 2, 8, 1, wv, M._ptr(G), 1, M._ptr(f), None,
                                   ctypes.byref(s), M._ptr(out), None, None, M._stream(ctx._dev()))
     assert rc == -1
-    with pytest.raises(M.MmgapError) as e:                  # 64 spins
+    with pytest.raises(M.MmgapError) as e:                  # 96 spins
         ctx.cim_chains(torch.zeros((1, 32, 32), dtype=torch.float32, device="cuda:0"),
-                       torch.zeros((1, 32), dtype=torch.float32, device="cuda:0"), 32, 2, [2, 1],
-                       1, 10, 1)
+                       torch.zeros((1, 32), dtype=torch.float32, device="cuda:0"), 32, 3,
+                       [4, 2, 1], 1, 10, 1)
     assert e.value.code == -4
 
 
