@@ -437,7 +437,7 @@ def run_cim(args, M, torch):
                                              ch, sw, None, inp["seed"], stages=1, **kw))
             elif j["kind"] == "det":
                 outs.append(ctx.detect(inp["H_d"], inp["y_d"], j["qam"], inp["noise_var"], ch, sw,
-                                       b2, inp["seed"], init=0, **kw))
+                                       b2, inp["seed"], init=0 if use_cim else j["init"], **kw))
             else:
                 outs.append(ctx.vpp_precode(inp["H_d"], inp["y_d"], j["qam"], ch, sw, b2,
                                             inp["seed"], **kw))
