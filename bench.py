@@ -874,9 +874,14 @@ def main(argv=None) -> int:  # noqa: C901
             outs = [o for gi in range(len(groups)) for o in go(gi)]
             return quality(inputs, [{"sym": o[0].cpu().numpy()} for o in outs])
 
-        print("[bench] MMGaP-E, MMSE-SIC, SIC-guess search", file=sys.stderr, flush=True)
+        # the legs around MMSE-SIC need at most 16 users, the critical path's
+        # persistent plan at most 32 real dimensions
+        sic_ok = fusable and all(j["cols"] <= 16 for j in specs)
         sdesc = lambda s, g: f"{s['chains']} chains x {s['sweeps']} sweeps x {s['stages']} " \
                             f"stage(s) from {g}"
+    if is_det and not args.no_extras and all(j["n_sc"] * j["n_sym"] > 0 for j in specs) \
+            and sic_ok:
+        print("[bench] MMGaP-E, MMSE-SIC, SIC-guess search", file=sys.stderr, flush=True)
         el, lat = timed(e_group(e_sched, M.GUESS_MMSE | M.GUESS_SIC))
         q = q_of(e_group(e_sched, M.GUESS_MMSE | M.GUESS_SIC))
         extras["mmgap_e"] = leg_record(el, lat, q, {
@@ -933,6 +938,7 @@ def main(argv=None) -> int:  # noqa: C901
                                  es["beta2"], mid["seed"], stages=es["stages"])))
         extras["critical_path"] = cp
 
+    if is_det and not args.no_extras and all(j["n_sc"] * j["n_sym"] > 0 for j in specs):
         # build over 64 slots (one launch): the HBM-bound contraction at scale
         jb = specs[0]
         n64 = 64 * jb["n_sc"]

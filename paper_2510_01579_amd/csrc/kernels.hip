@@ -111,6 +111,19 @@ __device__ __forceinline__ uint32_t opaque_u32(uint32_t v)
     return v;
 }
 
+// The workgroup index in an order where consecutive indices run on one XCD:
+// the dispatcher deals workgroups p = 0, 1, 2, ... to the 8 XCDs in turn (p mod
+// 8), so XCD x receives ceil or floor of n / 8 of them; they take consecutive
+// logical indices, and workgroups that share data (one subcarrier's couplings)
+// meet in one XCD's L2.  A bijection of [0, n).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int p, int n)
+{
+    const int q = n / kXcds, r = n % kXcds;
+    const int x = p % kXcds, i = p / kXcds;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+}
+
 // Orders LDS writes of some lanes before LDS reads of other lanes of the same
 // wavefront.
 __device__ __forceinline__ void wave_sync_lds()
@@ -1494,12 +1507,15 @@ k_anneal(const float *__restrict__ G, int inst_per_G, const float *__restrict__ 
     auto first_inst = [&](int w) { return PACKED ? w * per_wave : w / wpi; };
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int gw = blockIdx.x * kWavesPerBlock + wave;
+    // 64 dimensions: the several workgroups of one subcarrier on one XCD, so
+    // that its couplings come from HBM once
+    const int blk = kSharedG ? xcd_block((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+    const int gw = blk * kWavesPerBlock + wave;
     int slot = 0;
     if constexpr (kSharedG) {
         // G ids of the block's wavefronts are non-decreasing: stage ids
         // g0 .. g1 (the last wavefront with work), at most g_slots of them
-        const int gw0 = blockIdx.x * kWavesPerBlock;
+        const int gw0 = blk * kWavesPerBlock;
         const int g0 = first_inst(gw0) / inst_per_G;
         int g1 = g0;
         for (int w = 1; w < kWavesPerBlock; ++w) {
@@ -1652,7 +1668,10 @@ __global__ void __launch_bounds__(kBlock) k_select(SelectArgs a)
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int n = blockIdx.x * kWavesPerBlock + wave;
+    // 64 dimensions: the workgroups of one subcarrier on one XCD (its couplings
+    // from HBM once)
+    const int blk = GM > 32 ? xcd_block((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+    const int n = blk * kWavesPerBlock + wave;
     if (n >= a.n_inst) return;   // whole wavefront; only wave-level exchange below
     const int C = a.chains, K = a.K, KT = a.KT, q = a.q;
     const int NW = (KT * q + 31) / 32;
