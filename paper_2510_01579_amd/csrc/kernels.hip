@@ -141,7 +141,7 @@ __device__ __forceinline__ void wave_sync_lds()
 //   MMSE (Cg + sigma^2 I)^-1 F by a Gauss-Jordan inverse, sliced to the nearest PAM level.
 // Writes G (ld x ld, zero padded) to Gout and, for symbols sym0..sym0+ns-1,
 // the field rows to fout, the fallback levels to xout (if non-null) and ||y||^2
-// to ynorm (if non-null).  nt <= NT, nr <= 64, ns <= NS.
+// to ynorm (if non-null).  nt <= NT, nr <= NR <= 64, ns <= NS.
 typedef double mfma_v4d __attribute__((ext_vector_type(4)));
 
 // A complex float32 value in LDS scratch (a plain pair, so that the scratch
@@ -151,19 +151,20 @@ struct cf32 {
 };
 __device__ __forceinline__ cf32 to_cf32(float2 v) { return cf32{v.x, v.y}; }
 
-template <int NT, int NS>
+// NR: the most receive antennas the scratch holds (H of the subcarrier).
+template <int NT, int NS, int NR = 64>
 struct DetSharedT {
-    cf32 Hs[64 * NT];
+    cf32 Hs[NR * NT];
     double2 Cg[NT * NT];
     double2 Fs[NS * (NT + 1)];   // rows padded to NT + 1 (lanes read a row each)
     double2 Ls[NT * (NT + 1)];  // the inverse of Cg + sigma^2 I (with Cg as its second buffer)
 };
 
-template <int NT, int NS>
+template <int NT, int NS, int NR>
 __device__ void build_det_sc(const float2 *H, const float2 *y, int nr, int nt, int nsym, int sc,
                              int sym0, int ns, int ld, int ldf, int qtop, double c, double c2,
                              double noise_var, float *Gout, float *fout, signed char *xout,
-                             double *ynorm, DetSharedT<NT, NS> &sh, int tid)
+                             double *ynorm, DetSharedT<NT, NS, NR> &sh, int tid)
 {
     const int nthr = blockDim.x;
     const int K = 2 * nt;
@@ -1434,10 +1435,12 @@ __device__ void decode_vpp(const int *lv, int n, int sc, int sy, int nsym, int n
 constexpr int kBuildBlock = 64;
 constexpr int kBuildSyms = 16;
 
-template <int NT>
+template <int NT, int NR>
 __global__ void __launch_bounds__(kBuildBlock) k_det_build(DetBuildArgs a)
 {
-    __shared__ DetSharedT<NT, kBuildSyms> sh;
+    // H in LDS for at most NR receive antennas: a smaller frame keeps more
+    // subcarriers resident per CU (each is a chain of dependent steps)
+    __shared__ DetSharedT<NT, kBuildSyms, NR> sh;
     const int sc = blockIdx.x;
     for (int s0 = 0; s0 < a.n_sym; s0 += kBuildSyms) {
         if (s0 > 0) __syncthreads();
@@ -3010,13 +3013,22 @@ int fused_kernel_class(int variant)
 hipError_t launch_det_build(const DetBuildArgs &a, hipStream_t s)
 {
     if (a.n_sc <= 0) return hipSuccess;
-    if (a.n_t <= 8) hipLaunchKernelGGL(k_det_build<8>, dim3(a.n_sc), dim3(kBuildBlock), 0, s, a);
-    else if (a.n_t <= 16)
-        hipLaunchKernelGGL(k_det_build<16>, dim3(a.n_sc), dim3(kBuildBlock), 0, s, a);
-    else if (a.n_t <= 32)
-        hipLaunchKernelGGL(k_det_build<32>, dim3(a.n_sc), dim3(kBuildBlock), 0, s, a);
-    else
+    if (a.n_r > 64) return hipErrorInvalidValue;
+    const bool r16 = a.n_r <= 16;
+    if (a.n_t <= 8) {
+        if (r16) hipLaunchKernelGGL((k_det_build<8, 16>), dim3(a.n_sc), dim3(kBuildBlock), 0, s, a);
+        else hipLaunchKernelGGL((k_det_build<8, 64>), dim3(a.n_sc), dim3(kBuildBlock), 0, s, a);
+    } else if (a.n_t <= 16) {
+        if (r16) hipLaunchKernelGGL((k_det_build<16, 16>), dim3(a.n_sc), dim3(kBuildBlock), 0, s, a);
+        else hipLaunchKernelGGL((k_det_build<16, 64>), dim3(a.n_sc), dim3(kBuildBlock), 0, s, a);
+    } else if (a.n_t <= 32) {
+        if (a.n_r <= 32)
+            hipLaunchKernelGGL((k_det_build<32, 32>), dim3(a.n_sc), dim3(kBuildBlock), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_det_build<32, 64>), dim3(a.n_sc), dim3(kBuildBlock), 0, s, a);
+    } else {
         return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
