@@ -37,13 +37,18 @@ def test_every_choice_meets_the_selection_margin_and_is_not_dearer(table):
                 assert q <= (1 + table["select_tolerance"]) * meas["ref"] + 2e-5, (name, b)
                 assert T.cand_cost(name, c0) <= T.cost(name, ref["chains"], ref["sweeps"])
             timed = meas.get("ms", {})
+            val = meas.get("val")
+            if val:     # a validation slot: the choices meet the margin there too
+                assert T.passes_val(meas, cand) and T.passes_val(meas, cand_any), (name, b)
             if T.schedule_key(cand_any) not in timed:
                 assert T.cand_cost(name, cand_any) <= T.cand_cost(name, cand)
-            # no measured candidate within the margin is cheaper (by the cost model
-            # among the plan formulations; by measured time, where timed, among all)
+            # no measured candidate within the margin (and validated, where a
+            # validation slot was measured) is cheaper (by the cost model among
+            # the plan formulations; by measured time, where timed, among all)
             for key, v in meas["cands"].items():
                 c = T.parse_key(key)
-                if v <= (1 + table["select_tolerance"]) * meas["ref"] + 2e-5:
+                if v <= (1 + table["select_tolerance"]) * meas["ref"] + 2e-5 and \
+                        (not val or T.passes_val(meas, c)):
                     assert T.cand_cost(name, c) >= T.cand_cost(name, cand), (name, key)
                     if T.schedule_key(cand_any) in timed:
                         if key in timed:
