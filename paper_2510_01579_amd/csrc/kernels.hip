@@ -2666,7 +2666,10 @@ k_search(SearchArgs a)
     const int lg = __builtin_ctz((unsigned)GL);
     const int per_wave = 64 >> lg;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int inst0 = (blockIdx.x * kWavesPerBlock + wave) * per_wave;
+    // a subcarrier's wavefronts (consecutive) in workgroups on one XCD: its
+    // couplings, H and y come from HBM once
+    const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int inst0 = (blk * kWavesPerBlock + wave) * per_wave;
     if (inst0 >= a.n_inst) return;     // whole wavefront; only wave-level exchange below
     const bool use_a = a.guess_a != nullptr, use_b = a.guess_b != nullptr;
     float *Gs = reinterpret_cast<float *>(Gw[wave]);
