@@ -384,7 +384,10 @@ typedef struct {
 
 typedef struct mmgap_plan mmgap_plan;
 
-enum { MMGAP_PLAN_GRAPH = 1 };   /* record the launch as a HIP graph, replayed by each launch */
+enum {
+    MMGAP_PLAN_GRAPH = 1,        /* record the launch as a HIP graph, replayed by each launch */
+    MMGAP_PLAN_PERSISTENT = 2    /* every Metropolis job through the persistent kernels */
+};
 
 /*
  * mmgap_plan_create -- validate `n_jobs` jobs (host array), copy their
@@ -394,11 +397,17 @@ enum { MMGAP_PLAN_GRAPH = 1 };   /* record the launch as a HIP graph, replayed b
  * K <= 16 with 16-QAM; larger) and ordered by decreasing cost within a class,
  * and allocate the plan's own device scratch (fields and fallbacks; the
  * couplings, H and the VPP inverse of a work item stay in LDS), counted against
- * the context's HBM budget.  Jobs must use Metropolis dynamics (a CIM schedule
- * is refused with MMGAP_EUNSUPPORTED).  A launch is one
+ * the context's HBM budget.  Two kinds of jobs run with launches of their own
+ * inside the batch instead of work items: CIM-CAC jobs (binary encoding,
+ * stages = 0; the build, anneal and selection launches of mmgap_detect /
+ * mmgap_vpp_precode; CIM-CAC with stages is refused with MMGAP_EUNSUPPORTED),
+ * and, unless flags has MMGAP_PLAN_PERSISTENT, jobs with stages that the
+ * one-launch search of mmgap_detect_e can run (the build, the MMSE-SIC guess
+ * where asked, the search).  The outputs are the same either way.  A launch
+ * is: the MMSE-SIC launches, the own-launch jobs in order, then one
  * persistent kernel per class present, largest class first.  `blocks` =
  * workgroups of each persistent kernel, 0 = as many as the device holds at
- * once.  flags: MMGAP_PLAN_GRAPH or 0.
+ * once.  flags: MMGAP_PLAN_GRAPH and/or MMGAP_PLAN_PERSISTENT, or 0.
  * The plan stores the jobs' device pointers, not their contents: inputs may be
  * rewritten between launches; they must stay allocated until the plan is
  * destroyed.  Plans are independent of the context's other calls and must be

@@ -43,6 +43,7 @@ EXPORTS = ("mmgap_create", "mmgap_destroy", "mmgap_last_error", "mmgap_build_isi
            "mmgap_server_poll", "mmgap_server_drain", "mmgap_server_stop")
 
 PLAN_GRAPH = 1
+PLAN_PERSISTENT = 2
 OPT_STAGE_LAUNCHES = 1
 
 
@@ -558,12 +559,13 @@ class Context:
 
     # ------------------------------------------------------------------ batches
     def det_job(self, H, y, qam, noise_var, chains, sweeps, beta2, seed, init=0, metric=True,
-                stages=0, inst_base=0, guesses=0):
+                stages=0, inst_base=0, guesses=0, cim=None):
         """A detection job for ``plan_create`` with its output tensors allocated:
         outputs["sym"] uint8 [n][n_tx], outputs["metric"] float32 [n] or None.
         stages >= 1: detection by moves around the MMSE estimate (detect_delta),
         or with guesses (GUESS_MMSE, GUESS_SIC or both) as detect_e, and then
-        outputs["from_sic"] uint8 [n]."""
+        outputs["from_sic"] uint8 [n].  cim: CIM-CAC constants (as for detect;
+        `sweeps` Euler steps, beta2 None) for a CIM-CAC job."""
         torch = _torch()
         p = self._problem(KIND_DET, H, y, qam, noise_var, 0.0)
         n = p.n_sc * p.n_sym
@@ -572,14 +574,14 @@ class Context:
                    metric=torch.empty((n,), dtype=torch.float32, device=dev) if metric else None)
         if guesses:
             out["from_sic"] = torch.empty((n,), dtype=torch.uint8, device=dev)
-        s, keep = self._schedule(chains, sweeps, beta2, seed, init, None, inst_base)
+        s, keep = self._schedule(chains, sweeps, beta2, seed, init, cim, inst_base)
         job = Job(p, s, _ptr(H).value, _ptr(y).value, _ptr(out["sym"]).value,
                   None if out["metric"] is None else _ptr(out["metric"]).value,
                   _ptr(out["from_sic"]).value if guesses else None, int(stages), int(guesses))
         return dict(job=job, keep=(H, y, keep), outputs=out)
 
     def vpp_job(self, H, u, qam, chains, sweeps, beta2, seed, tau=0.0, want_x=True,
-                want_gamma=True, init=0, inst_base=0):
+                want_gamma=True, init=0, inst_base=0, cim=None):
         """A VPP job for ``plan_create``: outputs["v"] int8 [n][2 n_rx],
         outputs["x"] complex64 [n][n_tx] or None, outputs["gamma"] float32 [n] or None."""
         torch = _torch()
@@ -589,18 +591,19 @@ class Context:
         out = dict(v=torch.empty((n, 2 * p.n_rx), dtype=torch.int8, device=dev),
                    x=torch.empty((n, p.n_tx), dtype=torch.complex64, device=dev) if want_x else None,
                    gamma=torch.empty((n,), dtype=torch.float32, device=dev) if want_gamma else None)
-        s, keep = self._schedule(chains, sweeps, beta2, seed, init, None, inst_base)
+        s, keep = self._schedule(chains, sweeps, beta2, seed, init, cim, inst_base)
         job = Job(p, s, _ptr(H).value, _ptr(u).value, _ptr(out["v"]).value,
                   None if out["x"] is None else _ptr(out["x"]).value,
                   None if out["gamma"] is None else _ptr(out["gamma"]).value)
         return dict(job=job, keep=(H, u, keep), outputs=out)
 
-    def plan_create(self, jobs, graph=True, blocks=0):
-        """A Plan running `jobs` (from det_job / vpp_job) in one persistent launch."""
+    def plan_create(self, jobs, graph=True, blocks=0, persistent=False):
+        """A Plan running `jobs` (from det_job / vpp_job) in one batch launch
+        (persistent: every Metropolis job through the persistent kernels)."""
         arr = (Job * max(len(jobs), 1))(*[j["job"] for j in jobs])
         h = ctypes.c_void_p()
-        self._check(lib().mmgap_plan_create(self._h, len(jobs), arr,
-                                            PLAN_GRAPH if graph else 0, int(blocks),
+        flags = (PLAN_GRAPH if graph else 0) | (PLAN_PERSISTENT if persistent else 0)
+        self._check(lib().mmgap_plan_create(self._h, len(jobs), arr, flags, int(blocks),
                                             ctypes.byref(h)))
         return Plan(self, h, jobs)
 

@@ -123,6 +123,21 @@ int packed_lanes(int chains, int inst_per_G, int max_per_wave)
     return per_wave > 1 ? 64 / per_wave : 0;
 }
 
+// Lanes per instance of the one-launch search (k_search), or 0 when it cannot
+// run the problem: Metropolis anneals, KT <= 32, chains <= 64, 64 / lanes
+// instances of a subcarrier per wavefront (at most 16, so at least 4 lanes),
+// n_rx <= 2 lanes.
+int search_lanes_of(int chains, int n_sym, int n_rx, int KT, bool cim)
+{
+    if (cim || KT > 32 || chains > 64) return 0;
+    int gl = 64;
+    if (chains <= 32) {
+        const int p = packed_lanes(chains, n_sym, 16);
+        if (p) gl = p;
+    }
+    return n_rx <= 2 * gl ? gl : 0;
+}
+
 int qam_bits(int qam)
 {
     switch (qam) {
@@ -363,23 +378,23 @@ double item_cost(const mmgap::FusedJob &j)
 namespace mmgap {
 namespace host {
 
-int batch_layout(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, BatchLayout *out)
+int batch_layout(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, int flags,
+                 BatchLayout *out)
 {
     BatchLayout &L = *out;
     L = BatchLayout();
     L.jobs.resize((size_t)n_jobs);
     L.betas.resize((size_t)n_jobs);
+    L.route.assign((size_t)n_jobs, kRoutePersistent);
+    L.cim.resize((size_t)n_jobs);
+    L.search_lanes.assign((size_t)n_jobs, 0);
     for (int j = 0; j < n_jobs; ++j) {
         const mmgap_job &jb = jobs[j];
         ProblemShape sh;
         int rc = check_problem(ctx, &jb.prob, -1, &sh);
         if (!rc) rc = check_schedule(ctx, &jb.sched);
         if (rc) return fail(ctx, rc, "job %d: %s", j, ctx->err.c_str());
-        if (jb.sched.dynamics != MMGAP_DYN_METROPOLIS)
-            return fail(ctx, MMGAP_EUNSUPPORTED, "job %d: batches run Metropolis dynamics only", j);
-        if (jb.sched.chains > kMaxFusedChains)
-            return fail(ctx, MMGAP_EUNSUPPORTED, "job %d: chains=%d > %d in a batch", j,
-                        jb.sched.chains, kMaxFusedChains);
+        const bool cim = jb.sched.dynamics == MMGAP_DYN_CIM;
         if (sh.n_inst > 0 && (!jb.H || !jb.y_or_u || !jb.out0))
             return fail(ctx, MMGAP_EINVAL, "job %d: H, y_or_u and out0 are required", j);
         if (jb.stages < 0 || jb.stages > mmgap::kMaxStages)
@@ -399,6 +414,31 @@ int batch_layout(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, BatchLayout 
         if ((jb.guesses & MMGAP_GUESS_SIC) && jb.prob.n_tx > 16)
             return fail(ctx, MMGAP_EUNSUPPORTED, "job %d: MMSE-SIC supports n_tx <= 16 (got %d)",
                         j, jb.prob.n_tx);
+        if (cim) {
+            // CIM-CAC anneals: the build, anneal and selection launches of the
+            // plain entry points, inside the batch
+            if (jb.stages > 0)
+                return fail(ctx, MMGAP_EUNSUPPORTED,
+                            "job %d: CIM dynamics in a batch with the binary encoding only "
+                            "(stages = 0)", j);
+            if (sh.KT > 32 || sh.KT * sh.q > 64)
+                return fail(ctx, MMGAP_EUNSUPPORTED,
+                            "job %d: CIM dynamics needs K <= 32 and K q <= 64 spins", j);
+            L.route[j] = kRouteCim;
+            const mmgap_cim_params *c = jb.sched.cim;
+            L.cim[j] = mmgap::CimParams{c->dt, c->p - 1.0f, c->a, -c->zeta, c->eps, c->amp0,
+                                        c->f_mvm};
+        } else if (jb.stages > 0 && !(flags & MMGAP_PLAN_PERSISTENT)) {
+            const int gl = search_lanes_of(jb.sched.chains, jb.prob.n_sym, jb.prob.n_rx, sh.KT,
+                                           false);
+            if (gl) {
+                L.route[j] = kRouteSearch;
+                L.search_lanes[j] = gl;
+            }
+        }
+        if (L.route[j] == kRoutePersistent && jb.sched.chains > kMaxFusedChains)
+            return fail(ctx, MMGAP_EUNSUPPORTED, "job %d: chains=%d > %d in a batch", j,
+                        jb.sched.chains, kMaxFusedChains);
         const mmgap_problem &p = jb.prob;
         mmgap::FusedJob &f = L.jobs[j];
         f = mmgap::FusedJob{};
@@ -435,11 +475,12 @@ int batch_layout(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, BatchLayout 
         f.out0 = jb.out0;
         f.out1 = jb.out1;
         f.out2 = jb.out2;
-        L.betas[j].assign(jb.sched.beta2, jb.sched.beta2 + jb.sched.sweeps);
+        if (!cim) L.betas[j].assign(jb.sched.beta2, jb.sched.beta2 + jb.sched.sweeps);
         const int per = f.glanes ? 4 * (64 / f.glanes) : 4 / f.wpi;
-        for (int sc = 0; sc < p.n_sc; ++sc)
-            for (int s0 = 0; s0 < p.n_sym; s0 += per)
-                L.items.push_back({j, sc, s0, std::min(per, p.n_sym - s0)});
+        if (L.route[j] == kRoutePersistent)
+            for (int sc = 0; sc < p.n_sc; ++sc)
+                for (int s0 = 0; s0 < p.n_sym; s0 += per)
+                    L.items.push_back({j, sc, s0, std::min(per, p.n_sym - s0)});
     }
     if (L.items.size() > 0x7FFFFFFFu) return fail(ctx, MMGAP_EUNSUPPORTED, "too many work items");
     // grouped by register class, each group ordered by decreasing cost
@@ -466,11 +507,31 @@ int batch_layout(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, BatchLayout 
     L.ofp.resize(n_jobs);
     L.ox.resize(n_jobs);
     L.oxs.resize(n_jobs);
+    L.oG.assign(n_jobs, 0);
+    L.oE.assign(n_jobs, 0);
+    L.oS.assign(n_jobs, 0);
+    L.oA.assign(n_jobs, 0);
     for (int j = 0; j < n_jobs; ++j) L.ob[j] = lay.take(sizeof(float) * L.betas[j].size());
     L.header_bytes = lay.off;
     for (int j = 0; j < n_jobs; ++j) {
         const mmgap::FusedJob &f = L.jobs[j];
         const size_t ni = (size_t)f.n_sc * f.n_sym;
+        if (L.route[j] != kRoutePersistent) {
+            // the plain entry points' layout: rows of KT
+            L.oG[j] = lay.take(sizeof(float) * (size_t)f.n_sc * f.KT * f.KT);
+            L.of[j] = lay.take(sizeof(float) * ni * f.KT);
+            L.ofp[j] = 0;
+            L.ox[j] = lay.take(ni * (size_t)f.KT);
+            L.oxs[j] = (f.guesses & MMGAP_GUESS_SIC) ? lay.take(ni * (size_t)f.KT) : 0;
+            if (L.route[j] == kRouteCim) {
+                const size_t nw = (size_t)mmgap::spin_words(f.KT, f.Q);
+                L.oE[j] = lay.take(sizeof(float) * ni * f.chains);
+                L.oS[j] = lay.take(sizeof(uint32_t) * ni * f.chains * nw);
+                if (f.kind == MMGAP_KIND_VPP)
+                    L.oA[j] = lay.take(sizeof(double2) * (size_t)f.n_sc * f.n_rows * f.n_rows);
+            }
+            continue;
+        }
         L.of[j] = lay.take(sizeof(float) * ni * f.ldf);
         L.ofp[j] = f.stages > 0 ? lay.take(sizeof(float) * ni * f.ldf) : 0;
         L.ox[j] = lay.take(ni * (size_t)f.KT);
@@ -523,6 +584,132 @@ int batch_launch_config(mmgap_ctx *ctx, const BatchLayout &L, char *base, int bl
     if (e != hipSuccess) return hip_fail(ctx, e, "occupancy query");
     for (size_t j = 0; j < L.jobs.size(); ++j) {
         const mmgap::FusedJob &f = L.jobs[j];
+        if (L.route[j] == kRoutePersistent || f.n_sc * f.n_sym == 0) continue;
+        SepLaunch sl;
+        sl.route = L.route[j];
+        sl.kind = f.kind;
+        sl.KT = f.KT;
+        sl.q = f.Q;
+        float *G = reinterpret_cast<float *>(base + L.oG[j]);
+        float *fr = reinterpret_cast<float *>(base + L.of[j]);
+        signed char *xr = reinterpret_cast<signed char *>(base + L.ox[j]);
+        const int ni = f.n_sc * f.n_sym;
+        if (f.kind == MMGAP_KIND_DET) {
+            mmgap::DetBuildArgs &d = sl.det;
+            d.H = f.H;
+            d.y = f.y;
+            d.n_sc = f.n_sc;
+            d.n_r = f.n_rows;
+            d.n_t = f.n_cols;
+            d.n_sym = f.n_sym;
+            d.ld = f.KT;
+            d.qtop = (1 << f.dq) - 1;
+            d.c = f.c;
+            d.c2 = f.c2;
+            d.noise_var = f.noise_var;
+            d.G = G;
+            d.f = fr;
+            d.x_fb = xr;
+            d.ynorm = nullptr;
+        } else {
+            mmgap::VppBuildArgs &v = sl.vpp;
+            v.H = f.H;
+            v.u = f.y;
+            v.n_sc = f.n_sc;
+            v.n_u = f.n_rows;
+            v.n_t = f.n_cols;
+            v.n_sym = f.n_sym;
+            v.ld = f.KT;
+            v.tau = f.tau;
+            v.G = G;
+            v.f = fr;
+            v.x_fb = xr;
+            v.Ainv = reinterpret_cast<double2 *>(base + L.oA[j]);
+            v.unorm = nullptr;
+        }
+        if (sl.route == kRouteCim) {
+            mmgap::AnnealArgs &a = sl.ann;
+            a.G = G;
+            a.inst_per_G = f.n_sym;
+            a.f = fr;
+            a.x_fb = xr;
+            a.sweeps = f.sweeps;
+            a.chains = f.chains;
+            a.n_inst = ni;
+            for (int b = 0; b < mmgap::kMaxQ; ++b) a.w[b] = f.w[b];
+            a.key0 = f.key0;
+            a.key1 = f.key1;
+            a.inst_base = f.inst_base;
+            a.init_mode = f.init;
+            a.glanes = packed_lanes(f.chains, f.n_sym, 64);
+            a.chain_E = reinterpret_cast<float *>(base + L.oE[j]);
+            a.chain_S = reinterpret_cast<uint32_t *>(base + L.oS[j]);
+            a.cim = L.cim[j];
+            mmgap::SelectArgs &se = sl.sel;
+            se.mode = f.kind == MMGAP_KIND_DET ? mmgap::kSelectDet : mmgap::kSelectVpp;
+            se.n_inst = ni;
+            se.K = f.K;
+            se.KT = f.KT;
+            se.q = f.Q;
+            se.chains = f.chains;
+            for (int b = 0; b < mmgap::kMaxQ; ++b) se.w[b] = f.w[b];
+            se.G = G;
+            se.inst_per_G = f.n_sym;
+            se.f = fr;
+            se.x_fb = xr;
+            se.chain_E = a.chain_E;
+            se.chain_S = a.chain_S;
+            se.H = f.H;
+            se.y = f.y;
+            se.n_rows = f.n_rows;
+            se.n_cols = f.n_cols;
+            se.n_sym = f.n_sym;
+            se.c = f.c;
+            if (f.kind == MMGAP_KIND_DET) {
+                se.sym_out = static_cast<unsigned char *>(f.out0);
+                se.metric_out = static_cast<float *>(f.out1);
+            } else {
+                se.Ainv = sl.vpp.Ainv;
+                se.tau = f.tau;
+                se.v_out = static_cast<signed char *>(f.out0);
+                se.x_out = static_cast<float2 *>(f.out1);
+                se.gamma_out = static_cast<float *>(f.out2);
+            }
+        } else {
+            mmgap::SearchArgs &r = sl.srch;
+            const int g = f.guesses ? f.guesses : MMGAP_GUESS_MMSE;
+            r.G = G;
+            r.inst_per_G = f.n_sym;
+            r.f = fr;
+            r.guess_a = (g & MMGAP_GUESS_MMSE) ? xr : nullptr;
+            r.guess_b = (g & MMGAP_GUESS_SIC) ? reinterpret_cast<signed char *>(base + L.oxs[j])
+                                              : nullptr;
+            r.beta2 = reinterpret_cast<const float *>(base + L.ob[j]);
+            r.n_inst = ni;
+            r.K = f.K;
+            r.sweeps = f.sweeps;
+            r.chains = f.chains;
+            r.stages = f.stages;
+            r.init_mode = f.init;
+            r.glanes = L.search_lanes[j];
+            r.key0 = f.key0;
+            r.key1 = f.key1;
+            r.inst_base = f.inst_base;
+            r.dq = f.dq;
+            r.H = f.H;
+            r.y = f.y;
+            r.n_rows = f.n_rows;
+            r.n_cols = f.n_cols;
+            r.n_sym = f.n_sym;
+            r.c = f.c;
+            r.sym_out = static_cast<unsigned char *>(f.out0);
+            r.metric_out = static_cast<float *>(f.out1);
+            r.from_b = f.guesses ? static_cast<unsigned char *>(f.out2) : nullptr;
+        }
+        b.sep.push_back(sl);
+    }
+    for (size_t j = 0; j < L.jobs.size(); ++j) {
+        const mmgap::FusedJob &f = L.jobs[j];
         if (!(f.guesses & MMGAP_GUESS_SIC) || f.n_sc * f.n_sym == 0) continue;
         mmgap::SicArgs sa{};
         sa.H = f.H;
@@ -545,8 +732,24 @@ hipError_t batch_enqueue(const BatchLaunch &b, const uint32_t *accept_table, hip
 {
     hipError_t e = mmgap::launch_fused_reset(b.counters, st);
     // the MMSE-SIC guesses of the jobs that search from it, before the
-    // persistent kernels that read them
+    // searches and persistent kernels that read them
     for (size_t k = 0; k < b.sic.size() && e == hipSuccess; ++k) e = mmgap::launch_sic(b.sic[k], st);
+    // jobs with launches of their own: build, then CIM-CAC anneal and
+    // selection, or the search
+    for (size_t k = 0; k < b.sep.size() && e == hipSuccess; ++k) {
+        const SepLaunch &sl = b.sep[k];
+        e = sl.kind == MMGAP_KIND_DET ? mmgap::launch_det_build(sl.det, st)
+                                      : mmgap::launch_vpp_build(sl.vpp, st);
+        if (e != hipSuccess) break;
+        if (sl.route == kRouteCim) {
+            e = mmgap::launch_cim(sl.KT, sl.q, sl.ann, st);
+            if (e == hipSuccess) e = mmgap::launch_select(sl.sel, st);
+        } else {
+            mmgap::SearchArgs r = sl.srch;
+            r.accept_table = accept_table;
+            e = mmgap::launch_search(sl.KT, r, st);
+        }
+    }
     for (int c = mmgap::kFusedClasses - 1; c >= 0 && e == hipSuccess; --c)
         e = mmgap::launch_fused(c, b.jobs, b.items + b.first[c], b.count[c], b.counters + c,
                                 accept_table, b.blocks[c], st);
@@ -1071,15 +1274,9 @@ int run_delta_stages(mmgap_ctx *ctx, hipStream_t st, const mmgap_problem *prob,
 int search_lanes(const mmgap_ctx *ctx, const mmgap_problem *prob, const ProblemShape &sh,
                  const mmgap_schedule *sched)
 {
-    if (ctx->stage_launches || sched->dynamics == MMGAP_DYN_CIM || sh.KT > 32 ||
-        sched->chains > 64)
-        return 0;
-    int gl = 64;
-    if (sched->chains <= 32) {
-        const int p = packed_lanes(sched->chains, prob->n_sym, 16);
-        if (p) gl = p;
-    }
-    return prob->n_rx <= 2 * gl ? gl : 0;
+    if (ctx->stage_launches) return 0;
+    return search_lanes_of(sched->chains, prob->n_sym, prob->n_rx, sh.KT,
+                           sched->dynamics == MMGAP_DYN_CIM);
 }
 
 // Every stage of the chains from guess A and/or guess B (device rows
@@ -1518,11 +1715,12 @@ int mmgap_plan_create(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, int fla
     *out = nullptr;
     if (n_jobs < 0 || (n_jobs > 0 && !jobs))
         return fail(ctx, MMGAP_EINVAL, "n_jobs=%d with jobs=%p", n_jobs, (const void *)jobs);
-    if (flags & ~MMGAP_PLAN_GRAPH) return fail(ctx, MMGAP_EINVAL, "unknown flags 0x%x", flags);
+    if (flags & ~(MMGAP_PLAN_GRAPH | MMGAP_PLAN_PERSISTENT))
+        return fail(ctx, MMGAP_EINVAL, "unknown flags 0x%x", flags);
     if (blocks < 0) return fail(ctx, MMGAP_EINVAL, "blocks=%d < 0", blocks);
 
     BatchLayout lay;
-    int rc = batch_layout(ctx, n_jobs, jobs, &lay);
+    int rc = batch_layout(ctx, n_jobs, jobs, flags, &lay);
     if (rc) return rc;
     if (lay.bytes + ctx->plan_bytes + ctx->scratch_bytes > ctx->budget)
         return fail(ctx, MMGAP_ENOMEM,

@@ -97,6 +97,12 @@ struct ProblemShape {
 int check_problem(mmgap_ctx *ctx, const mmgap_problem *p, int kind, ProblemShape *sh);
 int check_schedule(mmgap_ctx *ctx, const mmgap_schedule *s);
 
+// How a batch job runs: through the persistent kernels' work items; or, with
+// launches of its own inside the batch, by CIM-CAC anneals (build, anneal,
+// selection) or by the one-launch search (build, the MMSE-SIC guess where
+// asked, search).
+enum BatchRoute { kRoutePersistent = 0, kRouteCim = 1, kRouteSearch = 2 };
+
 // A batch of jobs for the persistent fused kernels, laid out on the host:
 // descriptors, work items grouped by register class (each group by decreasing
 // cost), and byte offsets of one device block holding
@@ -108,6 +114,11 @@ struct BatchLayout {
     std::vector<FusedItem> items;
     std::vector<std::vector<float>> betas;
     std::vector<size_t> of, ofp, ox, oxs, ob;
+    std::vector<int> route;             // BatchRoute per job
+    std::vector<CimParams> cim;         // CIM-CAC constants of kRouteCim jobs
+    std::vector<int> search_lanes;      // kRouteSearch: lanes per instance
+    std::vector<size_t> oG, oE, oS, oA; // own-launch routes: couplings [n_sc][KT][KT], chain
+                                        // energies and spin words (CIM), VPP inverse
     size_t o_jobs = 0, o_items = 0, o_counters = 0;
     size_t header_bytes = 0;
     size_t bytes = 0;
@@ -115,16 +126,27 @@ struct BatchLayout {
     int cls_items[kFusedClasses] = {};
 };
 
-// Validates the jobs and lays them out (no device work).
-int batch_layout(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, BatchLayout *out);
+// Validates the jobs and lays them out (no device work).  flags: mmgap_plan
+// flags (MMGAP_PLAN_PERSISTENT keeps Metropolis jobs on the persistent kernels).
+int batch_layout(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, int flags,
+                 BatchLayout *out);
 // Points the descriptors at a device block of out->bytes bytes and writes the
 // header image (header_bytes) that must be copied to its start.
 void batch_bind(BatchLayout &lay, char *dev_base, std::vector<unsigned char> &image);
 
 // One launch of a bound batch: counter reset, then one persistent kernel per
 // class present, largest class first.
+struct SepLaunch {                  // the launches of one own-launch job
+    int route = 0, kind = 0, KT = 0, q = 0;
+    DetBuildArgs det{};
+    VppBuildArgs vpp{};
+    AnnealArgs ann{};
+    SelectArgs sel{};
+    SearchArgs srch{};
+};
 struct BatchLaunch {
     std::vector<SicArgs> sic;       // MMSE-SIC launches of jobs with that guess
+    std::vector<SepLaunch> sep;     // jobs with launches of their own, after the MMSE-SIC ones
     FusedJob *jobs = nullptr;
     FusedItem *items = nullptr;
     unsigned int *counters = nullptr;

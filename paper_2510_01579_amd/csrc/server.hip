@@ -33,6 +33,7 @@ enum JobState { kPending = 0, kRunning = 1, kDone = 2 };
 struct ServerJob {
     mmgap_job job{};
     std::vector<float> beta;        // the job's own copy of its schedule
+    mmgap_cim_params cim{};         // and of its CIM-CAC constants
     size_t footprint = 0;           // device bytes of the job as a batch of its own
     hipEvent_t ready = nullptr;     // caller's stream at submission
     Clock::time_point t_submit, t_done;
@@ -44,7 +45,7 @@ struct Slot {
     hipStream_t stream = nullptr;
     hipStream_t capture = nullptr;  // records the batch's launches (never executes them)
     hipGraphExec_t exec = nullptr;  // the slot's executable graph, updated per batch
-    int exec_mask = -1;             // kernel classes the executable graph launches
+    uint64_t exec_mask = ~0ull;     // the launch sequence the executable graph records
     hipEvent_t done = nullptr;
     bool busy = false;
     size_t off = 0, bytes = 0;      // arena range of the running batch
@@ -97,17 +98,23 @@ void reap(mmgap_server *sv, Slot &sl, hipError_t result, Clock::time_point now)
     sl.busy = false;
 }
 
-// Records a batch's launches (the counter reset, then one persistent kernel
-// per class present) as a HIP graph and replays it on the slot's stream.  The
-// slot keeps its executable graph and updates it in place from the new
-// recording while the batch launches the same kernels (kernel arguments and
-// grid sizes change from batch to batch, the topology does not), so a batch
-// costs one update and one graph launch; otherwise it is instantiated anew.
+// Records a batch's launches (the counter reset, the MMSE-SIC launches, the
+// jobs with launches of their own, then one persistent kernel per class
+// present) as a HIP graph and replays it on the slot's stream.  The slot keeps
+// its executable graph and updates it in place from the new recording while
+// the batch launches the same sequence of kernels (kernel arguments and grid
+// sizes change from batch to batch, the topology does not), so a batch costs
+// one update and one graph launch; otherwise it is instantiated anew.
 hipError_t enqueue_graph(mmgap_server *sv, Slot &sl, const BatchLaunch &bl)
 {
-    int mask = 0;
+    // the launch sequence: classes present, MMSE-SIC launches, and each
+    // own-launch job's kernels (route, kind, KT, q), hashed
+    uint64_t mask = 0;
     for (int c = 0; c < mmgap::kFusedClasses; ++c)
-        if (bl.count[c] > 0 && bl.blocks[c] > 0) mask |= 1 << c;
+        if (bl.count[c] > 0 && bl.blocks[c] > 0) mask |= 1ull << c;
+    mask = mask * 1000003ull + bl.sic.size();
+    for (const SepLaunch &x : bl.sep)
+        mask = mask * 1000003ull + (uint64_t)((x.route * 2 + x.kind) * 256 + x.KT * 8 + x.q);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamBeginCapture(sl.capture, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
@@ -130,7 +137,7 @@ hipError_t enqueue_graph(mmgap_server *sv, Slot &sl, const BatchLaunch &bl)
     if (e == hipSuccess && !sl.exec) {
         e = hipGraphInstantiate(&sl.exec, graph, nullptr, nullptr, 0);
         if (e != hipSuccess) sl.exec = nullptr;
-        sl.exec_mask = e == hipSuccess ? mask : -1;
+        sl.exec_mask = e == hipSuccess ? mask : ~0ull;
     }
     if (graph) (void)hipGraphDestroy(graph);
     if (e == hipSuccess) e = hipGraphLaunch(sl.exec, sl.stream);
@@ -156,7 +163,7 @@ bool launch(mmgap_server *sv, int si, int k, size_t bytes, size_t off)
 
     BatchLayout lay;
     hipError_t e = hipSuccess;
-    int rc = batch_layout(&sv->sink, k, batch.data(), &lay);
+    int rc = batch_layout(&sv->sink, k, batch.data(), 0, &lay);
     if (rc == MMGAP_OK && lay.bytes > bytes) rc = MMGAP_ENOMEM;   // footprints bound it
     char *base = sv->arena + off;
     BatchLaunch bl;
@@ -346,15 +353,18 @@ int mmgap_server_submit(mmgap_ctx *ctx, const mmgap_job *job, void *stream,
     if (!sv) return fail(ctx, MMGAP_EINVAL, "no server is running");
     if (!job || !job_id) return fail(ctx, MMGAP_EINVAL, "job and job_id are required");
     BatchLayout lay;
-    int rc = batch_layout(ctx, 1, job, &lay);
+    int rc = batch_layout(ctx, 1, job, 0, &lay);
     if (rc) return rc;
     if (mmgap::serve::arena_round(lay.bytes) > sv->alloc.capacity())
         return fail(ctx, MMGAP_ENOMEM, "job needs %zu bytes, the server arena holds %zu", lay.bytes,
                     sv->alloc.capacity());
     ServerJob j;
     j.job = *job;
-    j.beta.assign(job->sched.beta2, job->sched.beta2 + job->sched.sweeps);
-    j.job.sched.beta2 = nullptr;            // pointed at the copy once stored
+    const bool cim = job->sched.dynamics == MMGAP_DYN_CIM;
+    if (cim) j.cim = *job->sched.cim;
+    else j.beta.assign(job->sched.beta2, job->sched.beta2 + job->sched.sweeps);
+    j.job.sched.beta2 = nullptr;            // pointed at the copies once stored
+    j.job.sched.cim = nullptr;
     j.footprint = lay.bytes;
     DeviceGuard g(ctx->device);
     hipError_t e = hipEventCreateWithFlags(&j.ready, hipEventDisableTiming);
@@ -374,7 +384,8 @@ int mmgap_server_submit(mmgap_ctx *ctx, const mmgap_job *job, void *stream,
         j.t_submit = Clock::now();
         ServerJob &stored = sv->jobs[id];
         stored = std::move(j);
-        stored.job.sched.beta2 = stored.beta.data();
+        stored.job.sched.beta2 = cim ? nullptr : stored.beta.data();
+        stored.job.sched.cim = cim ? &stored.cim : nullptr;
         sv->pending.push_back(id);
         ++sv->unfinished;
     }

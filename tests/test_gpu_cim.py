@@ -153,11 +153,8 @@ def test_cim_arguments(ctx):
         with pytest.raises(M.MmgapError) as e:
             ctx.detect(H, y, 16, d.noise_var, 32, 10, None, 1, cim=bad)
         assert e.value.code == -1, bad
-    job = ctx.det_job(H, y, 16, d.noise_var, 32, 10, np.ones(10, np.float32), 1)
-    job["job"].sched.dynamics = M.DYN_CIM
-    keep = M.CimParams(0.02, 2, 0.9, 1.0, 1.0, 1.0, 0.1)
-    job["job"].sched.cim = __import__("ctypes").pointer(keep)
-    with pytest.raises(M.MmgapError) as e:          # batches run Metropolis only
+    job = ctx.det_job(H, y, 16, d.noise_var, 32, 10, None, 1, stages=1, cim={})
+    with pytest.raises(M.MmgapError) as e:          # batches: CIM-CAC without stages only
         ctx.plan_create([job])
     assert e.value.code == -4
 

@@ -35,6 +35,13 @@ def ctx():
     c.close()
 
 
+@pytest.fixture(params=[True, False], ids=["persistent", "routed"])
+def persistent(request):
+    """Plans with every job on the persistent kernels, or with the jobs the
+    one-launch search can run routed to it (the default)."""
+    return request.param
+
+
 def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
 
@@ -110,11 +117,11 @@ def mix(ctx):
     return inputs, refs
 
 
-def test_fused_delta_batch_equals_single_calls_on_every_replay(ctx, mix):
+def test_fused_delta_batch_equals_single_calls_on_every_replay(ctx, mix, persistent):
     inputs, refs = mix
     note(f"fused delta batch of {len(inputs)} jobs, graph replays")
     jobs = [job_of(ctx, inp) for inp in inputs]
-    plan = ctx.plan_create(jobs, graph=True)
+    plan = ctx.plan_create(jobs, graph=True, persistent=persistent)
     for rep in range(3):
         clear(jobs)
         a = torch.randn(256, 256, device="cuda:0")
@@ -126,11 +133,11 @@ def test_fused_delta_batch_equals_single_calls_on_every_replay(ctx, mix):
     plan.plan_destroy()
 
 
-def test_fused_delta_direct_launch_few_workgroups(ctx, mix):
+def test_fused_delta_direct_launch_few_workgroups(ctx, mix, persistent):
     inputs, refs = mix
     note("fused delta batch, direct launch, 2 workgroups")
     jobs = [job_of(ctx, inp) for inp in inputs]
-    plan = ctx.plan_create(jobs, graph=False, blocks=2)
+    plan = ctx.plan_create(jobs, graph=False, blocks=2, persistent=persistent)
     plan.plan_launch()
     for i, j in enumerate(jobs):
         assert_same(outputs_of(j), refs[i], f"job {i} {MIX[i]}")
@@ -148,12 +155,12 @@ def test_fused_delta_job_alone(ctx, mix):
         plan.plan_destroy()
 
 
-def test_fused_delta_matches_oracle_directly(ctx, mix):
+def test_fused_delta_matches_oracle_directly(ctx, mix, persistent):
     inputs, _ = mix
     note("fused delta vs oracle, job 1")
     p = inputs[1]
     job = job_of(ctx, p)
-    plan = ctx.plan_create([job])
+    plan = ctx.plan_create([job], persistent=persistent)
     plan.plan_launch()
     got = outputs_of(job)
     plan.plan_destroy()
@@ -164,7 +171,7 @@ def test_fused_delta_matches_oracle_directly(ctx, mix):
     assert np.allclose(got["metric"].astype(np.float64), ref["metric"], rtol=1e-4, atol=1e-6)
 
 
-def test_fused_delta_full_slot_16x16_64qam(ctx):
+def test_fused_delta_full_slot_16x16_64qam(ctx, persistent):
     """The 16x16 64-QAM slot (3276 x 12, 25 dB), 16 chains x 25 sweeps, two
     stages around the MMSE guess, chains started at the zero move: the plan
     equals the multi-launch entry point."""
@@ -175,7 +182,7 @@ def test_fused_delta_full_slot_16x16_64qam(ctx):
                beta2=beta2, seed=W.job_seed(3001), stages=2, init=1)
     ref = single_call(ctx, inp)
     job = job_of(ctx, inp)
-    plan = ctx.plan_create([job])
+    plan = ctx.plan_create([job], persistent=persistent)
     plan.plan_launch()
     assert_same(outputs_of(job), ref, "full slot")
     plan.plan_destroy()

@@ -36,6 +36,13 @@ def ctx():
     c.close()
 
 
+@pytest.fixture(params=[True, False], ids=["persistent", "routed"])
+def persistent(request):
+    """Plans with every job on the persistent kernels, or with the jobs the
+    one-launch search can run routed to it (the default)."""
+    return request.param
+
+
 def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
 
@@ -88,13 +95,13 @@ def assert_same(got, ref, label):
 
 
 @pytest.mark.parametrize("i", range(len(CASES)))
-def test_plan_job_equals_detect_e(ctx, i):
+def test_plan_job_equals_detect_e(ctx, i, persistent):
     spec = CASES[i]
     note(f"fused E job {spec}")
     inp = make(i, spec)
     ref = single(ctx, inp)
     job = job_of(ctx, inp)
-    plan = ctx.plan_create([job], graph=True)
+    plan = ctx.plan_create([job], graph=True, persistent=persistent)
     for rep in range(2):
         for t in job["outputs"].values():
             t.zero_()
@@ -103,7 +110,7 @@ def test_plan_job_equals_detect_e(ctx, i):
     plan.plan_destroy()
 
 
-def test_e_jobs_in_a_mix_on_every_replay(ctx):
+def test_e_jobs_in_a_mix_on_every_replay(ctx, persistent):
     note("fused E jobs beside delta, binary and VPP jobs, graph replays")
     inputs = [make(i, s) for i, s in enumerate(CASES[:4])]
     refs = [single(ctx, inp) for inp in inputs]
@@ -119,7 +126,7 @@ def test_e_jobs_in_a_mix_on_every_replay(ctx):
     d_ref = ctx.detect_delta(H2, y2, 16, d2.noise_var, 32, 20, b2, W.job_seed(2790), stages=2)
     b_ref = ctx.detect(H2, y2, 16, d2.noise_var, 64, 20, b2, W.job_seed(2791))
     torch.cuda.synchronize()
-    plan = ctx.plan_create(jobs, graph=True)
+    plan = ctx.plan_create(jobs, graph=True, persistent=persistent)
     for rep in range(3):
         for j in jobs:
             for t in j["outputs"].values():
@@ -136,12 +143,12 @@ def test_e_jobs_in_a_mix_on_every_replay(ctx):
 
 
 @pytest.mark.parametrize("i", [0, 1, 2])
-def test_plan_job_matches_the_oracle_on_sampled_instances(ctx, i):
+def test_plan_job_matches_the_oracle_on_sampled_instances(ctx, i, persistent):
     spec = CASES[i]
     note(f"fused E job vs oracle {spec}")
     inp = make(i, spec)
     job = job_of(ctx, inp)
-    plan = ctx.plan_create([job], graph=False)
+    plan = ctx.plan_create([job], graph=False, persistent=persistent)
     plan.plan_launch()
     got = outs(job)
     plan.plan_destroy()
