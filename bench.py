@@ -611,10 +611,12 @@ def main(argv=None) -> int:  # noqa: C901
         return [{k: (None if t is None else t.cpu().numpy()) for k, t in o.items()}
                 for o in outs]
 
-    def fused_leg(scheds, graph=True, one_plan=False, blocks=0):
+    def fused_leg(scheds, graph=True, one_plan=False, blocks=0, persistent=True):
         """One plan (a HIP graph unless graph=False) per group with the given
         schedules per job; one_plan: every group's jobs in one plan, launched
-        once per step; blocks: the plan's grid (0: the library's choice)."""
+        once per step; blocks: the plan's grid (0: the library's choice);
+        persistent: every job on the persistent kernels, else jobs with stages
+        take the build and search launches inside the plan."""
         plans, jobs = [], []
         for g in ([sum(gidx, [])] if one_plan else gidx):
             gj = []
@@ -629,7 +631,7 @@ def main(argv=None) -> int:  # noqa: C901
                     gj.append(ctx.vpp_job(inp["H_d"], inp["y_d"], j["qam"], sc["chains"],
                                           sc["sweeps"], sc["beta2"], inp["seed"],
                                           init=sc["init"]))
-            plans.append(ctx.plan_create(gj, graph=graph, blocks=blocks))
+            plans.append(ctx.plan_create(gj, graph=graph, blocks=blocks, persistent=persistent))
             jobs.extend(gj)
         info = [p.plan_info() for p in plans]
         if one_plan:
@@ -751,6 +753,7 @@ def main(argv=None) -> int:  # noqa: C901
     # ---- the tuner's choice among every formulation (MMGaP-E and the MMSE-SIC
     # guess included) through the separate-launch entry points
     tuned_sep = None
+    tuned_plan = None
     stage_launch_ms = None
     if tuned is not None and is_det:
         a_scheds = []
@@ -795,6 +798,19 @@ def main(argv=None) -> int:  # noqa: C901
                 "stage_ms": {"anneal": float(np.mean(sprof[:, :, 1].sum(axis=1)))},
                 "quality_matched": matched(q_s, q_ref)})
             legs["tuned_separate"] = (el, lat, a_scheds)
+            # the same formulations as one HIP graph per slot: the build, the
+            # MMSE-SIC launch and the search (or the persistent kernel for the
+            # binary encoding) replayed
+            print("[bench] tuned leg, every formulation (one graph per slot)", file=sys.stderr,
+                  flush=True)
+            el, lat, tp_out, _ = fused_leg(a_scheds, persistent=False)
+            q_tp = quality(inputs, tp_out)
+            tuned_plan = leg_record(el, lat, q_tp, {
+                "schedules": [sched_desc(s) for s in a_scheds],
+                "outputs_identical_to_tuned_separate": same_bytes(tp_out, s_out,
+                                                                  ("sym", "metric")),
+                "quality_matched": matched(q_tp, q_ref)})
+            legs["tuned_plan"] = (el, lat, a_scheds)
             if not args.no_extras:
                 # the same jobs with every stage as separate launches
                 ctx.set_stage_launches(True)
@@ -842,6 +858,11 @@ def main(argv=None) -> int:  # noqa: C901
             rows.append({"step": "+ one search launch per slot for moves around a guess and "
                                  "MMGaP-E (the tuned_separate leg)",
                          "ms_per_step": tuned_sep["ms_per_step"]})
+            if tuned_plan is not None:
+                rows.append({"step": "+ the slot's launches as one HIP graph (the tuned_plan leg)",
+                             "ms_per_step": tuned_plan["ms_per_step"],
+                             "identical_outputs": tuned_plan[
+                                 "outputs_identical_to_tuned_separate"]})
         ablation = {"schedules_fused": [sched_desc(s) for s in t_scheds], "rows": rows}
 
     # ---- detection extras: MMGaP-E, MMSE-SIC, the SIC-guess search
@@ -971,6 +992,8 @@ def main(argv=None) -> int:  # noqa: C901
         cands.append(("delta_separate", delta_sep))
     if tuned_sep is not None and tuned_sep["quality_matched"]:
         cands.append(("tuned_separate", tuned_sep))
+    if tuned_plan is not None and tuned_plan["quality_matched"]:
+        cands.append(("tuned_plan", tuned_plan))
     sel_name, sel = min(cands, key=lambda c: c[1]["ms_per_step"])
     sel_el, sel_lat, sel_scheds = legs[sel_name]
     value = args.steps * total_inst / sel_el
@@ -988,7 +1011,9 @@ def main(argv=None) -> int:  # noqa: C901
         kern_ms = plain["stage_ms"]["anneal"]
     elif sel_name == "delta_separate":
         kern_ms = delta_sep["stage_ms"]["anneal"]
-    elif sel_name == "tuned_separate":
+    elif sel_name in ("tuned_separate", "tuned_plan"):
+        # the same kernels and schedules: the library's events around the
+        # search and anneal launches of the separate-launch leg
         kern_ms = tuned_sep["stage_ms"]["anneal"]
     else:
         kern_ms = float(sel_lat.mean(axis=0).sum())
@@ -996,11 +1021,15 @@ def main(argv=None) -> int:  # noqa: C901
     kname = {"plain": "k_anneal",
              "delta_separate": "k_search (moves around the guess, one launch per slot)",
              "tuned_separate": "k_search and k_anneal (tuned formulations: one search "
-                               "launch per slot for moves around a guess and MMGaP-E)"}.get(
+                               "launch per slot for moves around a guess and MMGaP-E)",
+             "tuned_plan": "k_search and k_anneal (tuned formulations: one search launch per "
+                           "slot for moves around a guess and MMGaP-E; kernel time from the "
+                           "separate-launch leg's events around the same launches)"}.get(
         sel_name, "k_fused" + (" (moves around the guess)" if any(s.get("stages")
                                                                    for s in sel_scheds) else ""))
     tkey = {"plain": "k_anneal", "delta_separate": "k_search_delta",
-            "tuned_separate": "k_search_tuned_separate"}.get(
+            "tuned_separate": "k_search_tuned_separate",
+            "tuned_plan": "k_search_tuned_separate"}.get(
         sel_name, "k_fused_delta" if any(s.get("stages") for s in sel_scheds) else "k_fused")
 
     desc = []
@@ -1046,7 +1075,12 @@ def main(argv=None) -> int:  # noqa: C901
                                        "MMSE-SIC launch), then one search launch for every "
                                        "stage, both chains of MMGaP-E, the choice and the "
                                        "decode (moves around a guess), or anneal and select "
-                                       "launches (binary encoding)"
+                                       "launches (binary encoding)",
+                     "tuned_plan": "the tuned formulation per slot as one HIP graph: the build "
+                                   "(and the MMSE-SIC launch) and one search launch for every "
+                                   "stage, both chains of MMGaP-E, the choice and the decode "
+                                   "(moves around a guess), or the persistent kernel (binary "
+                                   "encoding)"
                      }[sel_name],
             "slots_per_step": len(groups),
             "instances_per_step": total_inst,
@@ -1058,14 +1092,15 @@ def main(argv=None) -> int:  # noqa: C901
         "quality_kind": ["ser" if j["kind"] == "det" else "mean_gamma" for j in specs],
         "quality_per_slot": {"slot": desc, "plain": q_ref,
                              "reported": {"tuned": tuned, "delta_separate": delta_sep,
-                                          "tuned_separate": tuned_sep, "fused": fused,
-                                          "plain": plain}[sel_name]["quality"]},
+                                          "tuned_separate": tuned_sep, "tuned_plan": tuned_plan,
+                                          "fused": fused, "plain": plain}[sel_name]["quality"]},
         "speedup_vs_plain": None if plain is None else value / plain["value"],
         "plain": plain,
         "fused_reference": fused,
         "tuned": tuned,
         "delta_separate": delta_sep,
         "tuned_separate": tuned_sep,
+        "tuned_plan": tuned_plan,
         **extras,
         "ablation": ablation,
         "roofline": {
