@@ -2599,22 +2599,25 @@ __global__ void __launch_bounds__(kBlock) k_pick(PickArgs a)
 // (detection couplings are exactly symmetric), which gives the rows' values
 // without LDS bank conflicts.
 
-// LDS row of one instance: move fields, energy terms, guesses A and B, candidate.
+// LDS row of one instance: move fields, energy terms, the energies of the
+// current guess and of each chain's final guess (kept here rather than in
+// registers across the anneals), guesses A and B, candidate.
 template <int KT>
 constexpr int search_row_bytes()
 {
-    return (11 * KT + 15) / 16 * 16;
+    return (11 * KT + 16 + 15) / 16 * 16;
 }
 template <int KT>
 struct SearchRow {
-    float *fp, *terms;
+    float *fp, *terms, *E;          // E: [0] current guess, [1] chain A's, [2] chain B's
     signed char *xa, *xb, *cand;
     __device__ SearchRow(unsigned char *rows, int row)
     {
         unsigned char *r = rows + (size_t)row * search_row_bytes<KT>();
         fp = reinterpret_cast<float *>(r);
         terms = fp + KT;
-        xa = reinterpret_cast<signed char *>(terms + KT);
+        E = terms + KT;
+        xa = reinterpret_cast<signed char *>(E + 4);
         xb = xa + KT;
         cand = xb + KT;
     }
@@ -2687,10 +2690,8 @@ k_search(SearchArgs a)
     }
     const int qtop = (1 << a.dq) - 1;
     const int wts[4] = {1, 1, 0, 0};
-    float Efin[2] = {0.0f, 0.0f};
     for (int chain = 0; chain < 2; ++chain) {
         if (!(chain ? use_b : use_a)) continue;
-        float Eg = 0.0f;                  // energy of the current guess (full fields)
         for (int s = 0; s < a.stages; ++s) {
             uint32_t bits[NW];
             float E;
@@ -2704,7 +2705,10 @@ k_search(SearchArgs a)
                 const SearchRow<KT> R(rows, wave * per_wave + grp);
                 const signed char *xg = chain ? R.xb : R.xa;
                 const float *ff = a.f + (size_t)n * KT;
-                if (s == 0) Eg = group_level_energy<KT>(Gs, a.K, ff, xg, R.terms, j, GL);
+                if (s == 0) {       // the energy of the starting guess (full fields)
+                    const float e0 = group_level_energy<KT>(Gs, a.K, ff, xg, R.terms, j, GL);
+                    if (j == 0) R.E[0] = e0;
+                }
                 for (int k = j; k < KT; k += GL) {        // the move fields
                     float g = 0.0f;
                     for (int l = 0; l < KT; ++l) g = fmaf(Gs[l * KT + k], (float)xg[l], g);
@@ -2762,13 +2766,15 @@ k_search(SearchArgs a)
             }
             wave_sync_lds();
             const float Ec = group_level_energy<KT>(Gs, a.K, ff, R.cand, R.terms, j, GL);
+            const float Eg = R.E[0];
             if (Ec < Eg) {
                 for (int k = j; k < a.K; k += GL) xg[k] = R.cand[k];
-                Eg = Ec;
+                if (j == 0) R.E[0] = Ec;
             }
             wave_sync_lds();
+            if (s == a.stages - 1 && j == 0) R.E[1 + chain] = R.E[0];
+            wave_sync_lds();
         }
-        Efin[chain] = Eg;
     }
     // the answer (B's only if its energy is strictly lower) and its decode, as
     // decode_det with the group's lanes: lane j takes receive antennas j and
@@ -2780,7 +2786,7 @@ k_search(SearchArgs a)
     const bool valid = inst0 + grp < a.n_inst;
     const int n = valid ? inst0 + grp : inst0;
     const SearchRow<KT> R(rows, wave * per_wave + grp);
-    const bool from_b = use_a && use_b ? Efin[1] < Efin[0] : use_b;
+    const bool from_b = use_a && use_b ? R.E[2] < R.E[1] : use_b;
     const signed char *lv = from_b ? R.xb : R.xa;
     const int nt = a.n_cols, nr = a.n_rows;
     const int sc = n / a.n_sym, sy = n - sc * a.n_sym;
