@@ -322,10 +322,11 @@ def serve_mix(M, torch, n_sat: int, n_arr: int, n_full: int):
     return {
         "workload": "slot jobs of 3276 subcarriers x 12 symbols, 60% uplink detection / 40% "
                     "VPP, sizes 8x8 and 16x16, QPSK/16-QAM/64-QAM uniform, detection SNR "
-                    "uniform 5-30 dB, i.i.d. Rayleigh; tuned schedules (moves around the MMSE "
-                    "guess where the tuner chose them)",
-        "path": "native serving loop: FIFO admission into an HBM arena, batches of the "
-                "persistent fused kernels recorded as HIP graphs, on 3 streams",
+                    "uniform 5-30 dB, i.i.d. Rayleigh; tuned schedules (searches around a "
+                    "guess and MMGaP-E where the tuner chose them)",
+        "path": "native serving loop: FIFO admission into an HBM arena, batches recorded as "
+                "HIP graphs on 3 streams (search launches for jobs that search around a "
+                "guess, the persistent fused kernels for the rest)",
         "sustainable_slots_per_s": sustainable,
         "sustainable_solves_per_s": sustainable * N_SC * N_SYM,
         "saturation_jobs": n_sat,
