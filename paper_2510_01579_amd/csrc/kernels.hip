@@ -1262,6 +1262,64 @@ __device__ __forceinline__ double wave_sum_f64(double v)
     return v;
 }
 
+// Exchanges inside 16-lane rows by DPP (no LDS round trip): CTRL 0xB1 swaps
+// neighbours (quad_perm 1,0,3,2), 0x4E swaps lane pairs (quad_perm 2,3,0,1),
+// 0x141 mirrors each 8 lanes (lane i <-> 7 - i) and 0x140 each 16 (i <-> 15 - i).
+// Applied in that order, each step pairs a lane with one in the other half of
+// its 2-, 4-, 8- and 16-lane group, so a commutative combine leaves the same
+// value, to the bit, in every lane of the group.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v)
+{
+    return ((uint64_t)dpp_u32<CTRL>((uint32_t)(v >> 32)) << 32) | dpp_u32<CTRL>((uint32_t)v);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    return __longlong_as_double((long long)dpp_u64<CTRL>((uint64_t)__double_as_longlong(v)));
+}
+// Sum over aligned groups of g lanes (g a power of two, 1..64), the same in
+// every lane of a group (the whole wavefront takes part).
+__device__ __forceinline__ double group_sum_f64(double v, int g)
+{
+    if (g >= 2) v = v + dpp_f64<0xB1>(v);
+    if (g >= 4) v = v + dpp_f64<0x4E>(v);
+    if (g >= 8) v = v + dpp_f64<0x141>(v);
+    if (g >= 16) v = v + dpp_f64<0x140>(v);
+    for (int off = 16; off < g; off <<= 1) v = v + __shfl_xor(v, off, 64);
+    return v;
+}
+// Minimum over aligned groups of g lanes (as above).
+__device__ __forceinline__ uint64_t group_min_u64(uint64_t v, int g)
+{
+    uint64_t o;
+    if (g >= 2) { o = dpp_u64<0xB1>(v); v = o < v ? o : v; }
+    if (g >= 4) { o = dpp_u64<0x4E>(v); v = o < v ? o : v; }
+    if (g >= 8) { o = dpp_u64<0x141>(v); v = o < v ? o : v; }
+    if (g >= 16) { o = dpp_u64<0x140>(v); v = o < v ? o : v; }
+    for (int off = 16; off < g; off <<= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)v, off, 64);
+        const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), off, 64);
+        o = ((uint64_t)hi << 32) | lo;
+        v = o < v ? o : v;
+    }
+    return v;
+}
+__device__ __forceinline__ double group_min_f64(double v, int g)
+{
+    if (g >= 2) v = fmin(v, dpp_f64<0xB1>(v));
+    if (g >= 4) v = fmin(v, dpp_f64<0x4E>(v));
+    if (g >= 8) v = fmin(v, dpp_f64<0x141>(v));
+    if (g >= 16) v = fmin(v, dpp_f64<0x140>(v));
+    for (int off = 16; off < g; off <<= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
 // Energy of the fallback levels with the chains' arithmetic (one wavefront;
 // `terms` is this wavefront's LDS scratch of 32 floats).
 template <bool TR = false>
@@ -1795,11 +1853,11 @@ __host__ __device__ inline size_t sic_lds_bytes(int nr, int nt)
            (size_t)(64 / g) * 2 * nt * 4 + 16 * 4;
 }
 
-__device__ __forceinline__ int sic_slice(double x, double c, int qtop)
+__device__ __forceinline__ int sic_slice(double x, double rc, int qtop)
 {
-    // clamped first (no effect on the sliced level) so that the conversion to
-    // int stays in range
-    const double t = fmin(fmax(x / c, -(double)(qtop + 2)), (double)(qtop + 2));
+    // x / c as x times 1 / c (rc); clamped first (no effect on the sliced level)
+    // so that the conversion to int stays in range
+    const double t = fmin(fmax(x * rc, -(double)(qtop + 2)), (double)(qtop + 2));
     int v = 2 * (int)floor(t * 0.5) + 1;
     return v < -qtop ? -qtop : (v > qtop ? qtop : v);
 }
@@ -1815,6 +1873,7 @@ __device__ void sic_sc(const SicArgs &a, int sc, int sym0, int ns, const cf32 *H
                        double2 *W, int *lv, int *order, int spp_cap, int lane)
 {
     const int nr = a.n_r, nt = a.n_t, qtop = (1 << a.q) - 1;
+    const double rc = 1.0 / a.c;
     int g = 1;
     while (g < nr) g <<= 1;
     const int spp = min(64 / g, spp_cap);                   // symbols per pass
@@ -1837,8 +1896,8 @@ __device__ void sic_sc(const SicArgs &a, int sc, int sym0, int ns, const cf32 *H
     // each lane keeps its elements' row and column factors in registers
     for (int k = 0; k < nt; ++k) {
         const cd pk = ld2(P[k * nt + k]);
-        const double den = pk.re * pk.re + pk.im * pk.im;
-        const cd t{pk.re / den, -pk.im / den};
+        const double rden = 1.0 / (pk.re * pk.re + pk.im * pk.im);
+        const cd t{pk.re * rden, -pk.im * rden};
         cd rowv[4], colv[4], old[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -1872,8 +1931,9 @@ __device__ void sic_sc(const SicArgs &a, int sc, int sym0, int ns, const cf32 *H
     for (int step = 0; step < nt; ++step) {
         const bool mine = lane < nt && ((rem >> lane) & 1u);
         const double d = mine ? P[lane * nt + lane].x : __builtin_inf();
-        double m = d;
-        for (int off = 32; off >= 1; off >>= 1) m = fmin(m, __shfl_xor(m, off, 64));
+        // the candidates sit in lanes 0 .. nt - 1 <= 15: the minimum over the
+        // first 16-lane row reaches each of them
+        const double m = group_min_f64(d, 16);
         uint64_t ball = __ballot(mine && d == m);
         if (ball == 0) ball = rem;              // no finite diagonal: the lowest remaining user
         const int i = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)ball) - 1);
@@ -1892,8 +1952,8 @@ __device__ void sic_sc(const SicArgs &a, int sc, int sym0, int ns, const cf32 *H
         }
         // Schur complement of user i
         const cd piv = ld2(P[i * nt + i]);
-        const double den = piv.re * piv.re + piv.im * piv.im;
-        const cd ip{piv.re / den, -piv.im / den};
+        const double rden = 1.0 / (piv.re * piv.re + piv.im * piv.im);
+        const cd ip{piv.re * rden, -piv.im * rden};
         const uint32_t keep = rem & ~(1u << i);
         cd nv[4];
         bool upd[4];
@@ -1933,12 +1993,10 @@ __device__ void sic_sc(const SicArgs &a, int sc, int sym0, int ns, const cf32 *H
             const int i = order[k];
             cd prod{0.0, 0.0};
             if (act) prod = cmul(ld2(W[k * nr + r]), res);
-            for (int off = g >> 1; off >= 1; off >>= 1) {
-                prod.re = prod.re + __shfl_xor(prod.re, off, 64);
-                prod.im = prod.im + __shfl_xor(prod.im, off, 64);
-            }
-            const int li = sic_slice(prod.re, a.c, qtop);
-            const int lq = sic_slice(prod.im, a.c, qtop);
+            prod.re = group_sum_f64(prod.re, g);
+            prod.im = group_sum_f64(prod.im, g);
+            const int li = sic_slice(prod.re, rc, qtop);
+            const int lq = sic_slice(prod.im, rc, qtop);
             if (act && r == 0) {
                 lv[sl * 2 * nt + i] = li;
                 lv[sl * 2 * nt + nt + i] = lq;
@@ -1952,7 +2010,7 @@ __device__ void sic_sc(const SicArgs &a, int sc, int sym0, int ns, const cf32 *H
         }
         // metric: the squared norm of the final residual y - H x
         double e2 = act ? res.re * res.re + res.im * res.im : 0.0;
-        for (int off = g >> 1; off >= 1; off >>= 1) e2 = e2 + __shfl_xor(e2, off, 64);
+        e2 = group_sum_f64(e2, g);
         wave_sync_lds();
         const int cnt = min(spp, sym0 + ns - s0);
         const size_t n0 = (size_t)sc * a.n_sym + s0;
@@ -2623,23 +2681,60 @@ struct SearchRow {
     }
 };
 
+// The levels of one instance, KT signed bytes in LDS (4-byte aligned), as
+// floats (exact small integers), read a word at a time.
+template <int KT>
+__device__ __forceinline__ void lds_levels(const signed char *lv, float (&x)[KT])
+{
+    const uint32_t *w = reinterpret_cast<const uint32_t *>(lv);
+#pragma unroll
+    for (int i = 0; i < KT / 4; ++i) {
+        const uint32_t v = w[i];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) x[4 * i + b] = (float)(int)(int8_t)(v >> (8 * b));
+    }
+}
+
 // Energy sum_k lv_k (g_k - f_k) with g = G lv - f of each group's instance
 // (the operations and order of wave_level_energy): lane j of a group of GL
 // lanes forms the terms of dimensions j, j + GL, ..., then every lane sums the
-// K terms in order.  Called by the whole wavefront.
+// K terms in order.  Called by the whole wavefront.  With K = KT the levels
+// are read once into registers and every loop is unrolled, so the loads of a
+// column issue together.
 template <int KT>
 __device__ __forceinline__ float group_level_energy(const float *Gl, int K, const float *ff,
                                                     const signed char *lv, float *terms, int j,
                                                     int GL)
 {
-    for (int k = j; k < K; k += GL) {
-        float acc = -ff[k];
-        for (int l = 0; l < K; ++l) acc = fmaf(Gl[l * KT + k], (float)lv[l], acc);
-        terms[k] = acc - ff[k];
-    }
-    wave_sync_lds();
     float e = 0.0f;
-    for (int k = 0; k < K; ++k) e = fmaf((float)lv[k], terms[k], e);
+    if (K == KT) {
+        float x[KT];
+        lds_levels<KT>(lv, x);
+        for (int k = j; k < KT; k += GL) {
+            float acc = -ff[k];
+#pragma unroll
+            for (int l = 0; l < KT; ++l) acc = fmaf(Gl[l * KT + k], x[l], acc);
+            terms[k] = acc - ff[k];
+        }
+        wave_sync_lds();
+        const float4 *t4 = reinterpret_cast<const float4 *>(terms);
+#pragma unroll
+        for (int k4 = 0; k4 < KT / 4; ++k4) {
+            const float4 t = t4[k4];
+            e = fmaf(x[4 * k4 + 0], t.x, e);
+            e = fmaf(x[4 * k4 + 1], t.y, e);
+            e = fmaf(x[4 * k4 + 2], t.z, e);
+            e = fmaf(x[4 * k4 + 3], t.w, e);
+        }
+    } else {
+        for (int k = j; k < K; k += GL) {
+            float acc = -ff[k];
+            for (int l = 0; l < K; ++l) acc = fmaf(Gl[l * KT + k], (float)lv[l], acc);
+            terms[k] = acc - ff[k];
+        }
+        wave_sync_lds();
+        for (int k = 0; k < K; ++k) e = fmaf((float)lv[k], terms[k], e);
+    }
     wave_sync_lds();
     return e;
 }
@@ -2658,7 +2753,7 @@ k_search(SearchArgs a)
     constexpr int NW = (2 * KT + 31) / 32;
     __shared__ uint32_t T[kAcceptSteps + 1];
     __shared__ float4 Gw[kWavesPerBlock][KT * KT / 4];
-    __shared__ signed char zrow[KT];              // the zero move
+    __shared__ __align__(16) signed char zrow[KT];   // the zero move
     extern __shared__ float4 search_dyn4[];       // the instances' rows
     unsigned char *rows = reinterpret_cast<unsigned char *>(search_dyn4);
     for (int e = threadIdx.x; e <= kAcceptSteps; e += kBlock) T[e] = a.accept_table[e];
@@ -2676,11 +2771,18 @@ k_search(SearchArgs a)
     if (inst0 >= a.n_inst) return;     // whole wavefront; only wave-level exchange below
     const bool use_a = a.guess_a != nullptr, use_b = a.guess_b != nullptr;
     float *Gs = reinterpret_cast<float *>(Gw[wave]);
+    bool g_bad;                         // a coupling of the wavefront's G is not finite
     {
         const int lane = threadIdx.x & 63, grp = lane >> lg, j = lane & (GL - 1);
         const int n = inst0 + grp < a.n_inst ? inst0 + grp : inst0;
         const float *Gg = a.G + (size_t)(inst0 / a.inst_per_G) * (KT * KT);
-        for (int e = lane; e < KT * KT; e += 64) Gs[e] = Gg[e];
+        bool bad = false;
+        for (int e = lane; e < KT * KT; e += 64) {
+            const float v = Gg[e];
+            bad |= !(fabsf(v) <= FLT_MAX);
+            Gs[e] = v;
+        }
+        g_bad = __ballot(bad) != 0;
         const SearchRow<KT> R(rows, wave * per_wave + grp);
         for (int k = j; k < KT; k += GL) {
             if (use_a) R.xa[k] = a.guess_a[(size_t)n * KT + k];
@@ -2709,10 +2811,15 @@ k_search(SearchArgs a)
                     const float e0 = group_level_energy<KT>(Gs, a.K, ff, xg, R.terms, j, GL);
                     if (j == 0) R.E[0] = e0;
                 }
-                for (int k = j; k < KT; k += GL) {        // the move fields
-                    float g = 0.0f;
-                    for (int l = 0; l < KT; ++l) g = fmaf(Gs[l * KT + k], (float)xg[l], g);
-                    R.fp[k] = ff[k] - g;
+                {                                           // the move fields
+                    float xl[KT];
+                    lds_levels<KT>(xg, xl);
+                    for (int k = j; k < KT; k += GL) {
+                        float g = 0.0f;
+#pragma unroll
+                        for (int l = 0; l < KT; ++l) g = fmaf(Gs[l * KT + k], xl[l], g);
+                        R.fp[k] = ff[k] - g;
+                    }
                 }
                 wave_sync_lds();
                 const uint64_t kk = (((uint64_t)a.key1 << 32) | a.key0) + (uint64_t)s +
@@ -2734,19 +2841,23 @@ k_search(SearchArgs a)
             // the group's best chain: lowest energy, then lowest index
             uint64_t key = ~0ull;
             if (valid && j < a.chains) key = ((uint64_t)energy_key(E) << 32) | (uint32_t)j;
-            for (int off = GL >> 1; off >= 1; off >>= 1) {
-                const uint32_t lo = __shfl_xor((uint32_t)key, off, 64);
-                const uint32_t hi = __shfl_xor((uint32_t)(key >> 32), off, 64);
-                const uint64_t o = ((uint64_t)hi << 32) | lo;
-                key = o < key ? o : key;
-            }
+            key = group_min_u64(key, GL);
             const int src = (lane & ~(GL - 1)) | (int)((uint32_t)key & (uint32_t)(GL - 1));
             const float Eb = __shfl(E, src, 64);
             uint32_t S[NW];
 #pragma unroll
             for (int w = 0; w < NW; ++w) S[w] = __shfl(bits[w], src, 64);
-            // the zero move (the fallback) with the move fields
-            const float Efb = group_level_energy<KT>(Gs, a.K, R.fp, zrow, R.terms, j, GL);
+            // the zero move (the fallback): its energy with the move fields sums
+            // 0 x (-2 f'_k) over k, which is +0 unless a term is not finite (a
+            // coupling or a doubled move field), and then NaN
+            bool fbad = false;
+            for (int k = j; k < a.K; k += GL) {
+                const float fk = R.fp[k];
+                fbad |= !(fabsf(-fk - fk) <= FLT_MAX);
+            }
+            const uint64_t gmask = (GL == 64 ? ~0ull : ((1ull << GL) - 1ull)) << (lane & ~(GL - 1));
+            const bool fb_nan = g_bad || (__ballot(fbad) & gmask) != 0;
+            const float Efb = fb_nan ? __builtin_nanf("") : 0.0f;
             const bool use_fb = energy_less(Efb, Eb);
             for (int k = j; k < a.K; k += GL) {
                 int z = 0;
