@@ -152,3 +152,47 @@ def test_stage_option_arguments(ctx):
     note("set_option argument errors")
     for opt, val in ((M.OPT_STAGE_LAUNCHES, 2), (99, 0)):
         assert M.lib().mmgap_set_option(ctx._h, opt, val) == -1
+
+
+def test_search_non_finite_inputs_equal_stage_launches(ctx):
+    """The search launch takes the zero move's energy as +0 without summing it,
+    and as NaN when a coupling or a doubled move field is not finite; the stage
+    launches sum it.  Subcarrier 1 gets an infinite channel entry (non-finite
+    couplings) and one symbol of subcarrier 2 a received sample of 3e38 (its
+    fields overflow): both paths must still agree everywhere, the finite
+    subcarriers bit for bit and the poisoned ones with NaN where the other has
+    NaN."""
+    note("search 8x8 16-QAM 5x12 with non-finite channel and fields")
+    d = W.det_slot(5301, 8, 8, 16, 5, 12, 15.0)
+    Hn = d.H.copy()
+    yn = d.y.copy()
+    Hn[1, 0, 0] = np.complex64(np.inf)
+    yn[2, 3, :] = np.complex64(3e38)
+    H, y = dev(Hn), dev(yn)
+    beta2 = W.linear_beta2(4, *W.det_beta_range(16, 8, d.noise_var))
+
+    def same_nan(a, b):
+        for x, z in zip(a, b):
+            if x is None:
+                assert z is None
+                continue
+            assert x.dtype == z.dtype and x.shape == z.shape
+            if x.dtype == np.float32:
+                nx, nz = np.isnan(x), np.isnan(z)
+                assert np.array_equal(nx, nz)
+                assert np.array_equal(x[~nx].view(np.uint32), z[~nz].view(np.uint32))
+            else:
+                assert np.array_equal(x, z)
+
+    for guesses in (3, 1):
+        a, b = both_paths(ctx, lambda: ctx.detect_e(H, y, 16, d.noise_var, 16, 4, beta2, 91,
+                                                    stages=2, guesses=guesses))
+        same_nan(a, b)
+    a, b = both_paths(ctx, lambda: ctx.detect_delta(H, y, 16, d.noise_var, 16, 4, beta2, 91,
+                                                    stages=2))
+    same_nan(a, b)
+    # the finite subcarriers are unaffected by the poisoned ones
+    clean = ctx.detect_delta(dev(d.H), dev(d.y), 16, d.noise_var, 16, 4, beta2, 91, stages=2)
+    sym_c, sym_p = host(clean[0]), a[0]
+    rows = np.r_[0:12, 36:60]      # subcarriers 0, 3 and 4
+    assert np.array_equal(sym_c[rows], sym_p[rows])
