@@ -286,6 +286,7 @@ def serve_mix(M, torch, n_sat: int, n_arr: int, n_full: int):
         gaps = rng.exponential(1.0 / rate, size=n)
         jobs = [draw_job(base + k) for k in range(n)]
         torch.cuda.synchronize()
+        ctx.server_stats(SERVE_DEADLINE_MS, reset=True)     # a new accounting period
         ids = []
         t0 = time.perf_counter()
         t_next = t0
@@ -296,7 +297,8 @@ def serve_mix(M, torch, n_sat: int, n_arr: int, n_full: int):
             ids.append(ctx.server_submit(jobs[k]))
         ctx.server_drain()
         el = time.perf_counter() - t0
-        return np.array([ctx.server_poll(i)[1] for i in ids]) / 1e3, el
+        lat = np.array([ctx.server_poll(i)[1] for i in ids]) / 1e3
+        return lat, el, ctx.server_stats(SERVE_DEADLINE_MS)
 
     ctx.server_start(max_inflight=3, arena_bytes=2 << 30)
     try:
@@ -314,8 +316,8 @@ def serve_mix(M, torch, n_sat: int, n_arr: int, n_full: int):
             ctx.server_poll(i)
         sustainable = n_sat / makespan
         rate = min(SERVE_RATE, 0.8 * sustainable)
-        lat, elapsed = arrivals(rate, n_arr, 1000)
-        lat_full, _ = arrivals(SERVE_RATE, n_full, 5000)
+        lat, elapsed, acct = arrivals(rate, n_arr, 1000)
+        lat_full, _, acct_full = arrivals(SERVE_RATE, n_full, 5000)
     finally:
         ctx.server_stop()
         ctx.close()
@@ -337,10 +339,14 @@ def serve_mix(M, torch, n_sat: int, n_arr: int, n_full: int):
         "p99_slot_ms": float(np.percentile(lat, 99)),
         "deadline_ms": SERVE_DEADLINE_MS,
         "frac_within_deadline": float(np.mean(lat <= SERVE_DEADLINE_MS)),
+        "deadline_misses": acct["missed"],
+        "server_accounting": acct,
         "at_target_rate": {"slots_per_s": SERVE_RATE, "arrivals": n_full,
                            "p50_slot_ms": float(np.percentile(lat_full, 50)),
                            "p99_slot_ms": float(np.percentile(lat_full, 99)),
-                           "frac_within_deadline": float(np.mean(lat_full <= SERVE_DEADLINE_MS))},
+                           "frac_within_deadline": float(np.mean(lat_full <= SERVE_DEADLINE_MS)),
+                           "deadline_misses": acct_full["missed"],
+                           "server_accounting": acct_full},
     }
 
 

@@ -452,6 +452,13 @@ int mmgap_plan_destroy(mmgap_plan *plan);
  *   the server saw it complete; a job reported done is forgotten (a later poll
  *   of its id is MMGAP_EINVAL).  Returns the job's status (MMGAP_EDEVICE if its
  *   batch failed).
+ * mmgap_server_stats -- latency accounting of the jobs completed since the
+ *   server started (or since the last call with reset != 0): how many, how
+ *   many took longer than deadline_us (submission to observed completion, as
+ *   mmgap_server_poll reports it), the nearest-rank 50th and 99th percentiles
+ *   and the maximum, in microseconds (all 0 when none completed).  reset != 0
+ *   starts a new accounting period after reading.  MMGAP_EINVAL without a
+ *   server, with out NULL or a negative deadline.
  * mmgap_server_drain -- wait until every submitted job is complete.
  * mmgap_server_stop -- drain, stop the thread, free the arena and streams
  *   (also done by mmgap_destroy).
@@ -463,6 +470,12 @@ int mmgap_server_start(mmgap_ctx *ctx, int max_inflight, size_t arena_bytes, int
 int mmgap_server_submit(mmgap_ctx *ctx, const mmgap_job *job, void *stream,
                         unsigned long long *job_id);
 int mmgap_server_poll(mmgap_ctx *ctx, unsigned long long job_id, int *done, double *latency_us);
+typedef struct {
+    unsigned long long completed;   /* jobs completed in the period */
+    unsigned long long missed;      /* of those, latency > deadline_us */
+    double p50_us, p99_us, max_us;
+} mmgap_server_stats_t;
+int mmgap_server_stats(mmgap_ctx *ctx, double deadline_us, int reset, mmgap_server_stats_t *out);
 int mmgap_server_drain(mmgap_ctx *ctx);
 int mmgap_server_stop(mmgap_ctx *ctx);
 

@@ -40,7 +40,7 @@ EXPORTS = ("mmgap_create", "mmgap_destroy", "mmgap_last_error", "mmgap_build_isi
            "mmgap_set_profiling", "mmgap_set_option",
            "mmgap_last_profile", "mmgap_plan_create", "mmgap_plan_launch", "mmgap_plan_info",
            "mmgap_plan_destroy", "mmgap_server_start", "mmgap_server_submit",
-           "mmgap_server_poll", "mmgap_server_drain", "mmgap_server_stop")
+           "mmgap_server_poll", "mmgap_server_stats", "mmgap_server_drain", "mmgap_server_stop")
 
 PLAN_GRAPH = 1
 PLAN_PERSISTENT = 2
@@ -81,6 +81,13 @@ GUESS_MMSE, GUESS_SIC = 1, 2
 # amplitude scale are this library's choice (the paper leaves them open).
 CIM_DEFAULTS = dict(dt=0.02, f_mvm=2, p=0.9, a=1.0, zeta=1.0, eps=1.0, amp0=0.1)
 CIM_STEPS = 128
+
+
+class ServerStats(ctypes.Structure):
+    """mmgap_server_stats_t."""
+    _fields_ = [("completed", ctypes.c_ulonglong), ("missed", ctypes.c_ulonglong),
+                ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double),
+                ("max_us", ctypes.c_double)]
 
 
 class Job(ctypes.Structure):
@@ -131,6 +138,7 @@ def lib() -> ctypes.CDLL:
                                               ctypes.POINTER(ctypes.c_ulonglong)]
             L.mmgap_server_poll.argtypes = [vp, ctypes.c_ulonglong, ctypes.POINTER(i),
                                             ctypes.POINTER(ctypes.c_double)]
+            L.mmgap_server_stats.argtypes = [vp, ctypes.c_double, i, ctypes.POINTER(ServerStats)]
             L.mmgap_server_drain.argtypes = [vp]
             L.mmgap_server_stop.argtypes = [vp]
             for name in EXPORTS:
@@ -632,6 +640,14 @@ class Context:
             self.__dict__.get("_server_jobs", {}).pop(int(job_id), None)
         self._check(rc)
         return bool(done.value), (lat.value if done.value else None)
+
+    def server_stats(self, deadline_ms: float, reset: bool = False) -> dict:
+        """Latency accounting of the completed jobs (mmgap_server_stats), in ms."""
+        st = ServerStats()
+        self._check(lib().mmgap_server_stats(self._h, float(deadline_ms) * 1e3,
+                                             int(bool(reset)), ctypes.byref(st)))
+        return {"completed": int(st.completed), "missed": int(st.missed),
+                "p50_ms": st.p50_us / 1e3, "p99_ms": st.p99_us / 1e3, "max_ms": st.max_us / 1e3}
 
     def server_drain(self):
         self._check(lib().mmgap_server_drain(self._h))

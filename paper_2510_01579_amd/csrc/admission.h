@@ -1,9 +1,12 @@
 // Admission bookkeeping of the serving loop, free of any device call so that it
-// can be tested on its own: a first-fit allocator of byte ranges in the
-// server's HBM arena, and the FIFO rule that decides how many queued jobs the
-// next launch takes.
+// can be tested on its own (against a simulated device on the host): a
+// first-fit allocator of byte ranges in the server's HBM arena, the FIFO rule
+// that decides how many queued jobs the next launch takes, one admission round
+// over the in-flight slots, and the latency accounting against a deadline.
 #pragma once
 
+#include <algorithm>
+#include <cmath>
 #include <cstddef>
 #include <cstdint>
 #include <iterator>
@@ -106,6 +109,64 @@ inline int admit_prefix(const std::vector<size_t> &footprints, size_t room, int 
         ++k;
     }
     return k;
+}
+
+// One admission round of the serving loop.  busy: the in-flight slots;
+// queue: the footprints of the waiting jobs in arrival order.  Each free slot,
+// in index order, takes the longest prefix of what is still queued (at most
+// max_batch_jobs jobs) that fits the arena's largest free range, as one range
+// taken first-fit; the round ends at the first free slot whose head job does
+// not fit (the head waits for memory, and nothing behind it passes it).
+struct Admitted {
+    int slot;           // in-flight slot that launches the batch
+    int jobs;           // the next `jobs` queued jobs, in order
+    size_t off, bytes;  // the batch's arena range
+};
+inline std::vector<Admitted> admit_round(const std::vector<bool> &busy,
+                                         const std::vector<size_t> &queue, int max_batch_jobs,
+                                         Arena &arena)
+{
+    std::vector<Admitted> out;
+    size_t head = 0;
+    for (int si = 0; si < (int)busy.size() && head < queue.size(); ++si) {
+        if (busy[si]) continue;
+        const int look = (int)std::min<size_t>(queue.size() - head, (size_t)max_batch_jobs);
+        const std::vector<size_t> fp(queue.begin() + head, queue.begin() + head + look);
+        const int k = admit_prefix(fp, arena.largest_free(), look);
+        if (k == 0) break;
+        size_t bytes = 0;
+        for (int i = 0; i < k; ++i) bytes += arena_round(fp[i]);
+        size_t off = 0;
+        if (!arena.alloc(bytes, &off)) break;
+        out.push_back(Admitted{si, k, off, bytes});
+        head += k;
+    }
+    return out;
+}
+
+// Completed jobs' latencies against a deadline: how many, how many strictly
+// above the deadline, and the nearest-rank 50th and 99th percentiles (the
+// smallest latency with at least that share of the jobs at or below it).
+struct LatencyStats {
+    size_t count = 0, missed = 0;
+    double p50 = 0.0, p99 = 0.0, max = 0.0;
+};
+inline LatencyStats latency_stats(std::vector<double> lat, double deadline)
+{
+    LatencyStats s;
+    s.count = lat.size();
+    if (lat.empty()) return s;
+    std::sort(lat.begin(), lat.end());
+    for (double v : lat) s.missed += v > deadline ? 1 : 0;
+    auto rank = [&](double pct) {
+        size_t r = (size_t)std::ceil(pct / 100.0 * (double)lat.size());
+        if (r < 1) r = 1;
+        return lat[r - 1];
+    };
+    s.p50 = rank(50.0);
+    s.p99 = rank(99.0);
+    s.max = lat.back();
+    return s;
 }
 
 }  // namespace serve

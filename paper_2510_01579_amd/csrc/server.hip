@@ -71,6 +71,7 @@ struct mmgap_server {
     std::unordered_map<unsigned long long, ServerJob> jobs;
     unsigned long long next_id = 1;
     size_t unfinished = 0;          // submitted and not yet complete
+    std::vector<double> latencies_us;   // completed jobs since start or the last reset
     bool stopping = false;
     std::thread thread;
 };
@@ -87,6 +88,8 @@ void reap(mmgap_server *sv, Slot &sl, hipError_t result, Clock::time_point now)
         j.state = kDone;
         j.t_done = now;
         j.status = result == hipSuccess ? MMGAP_OK : MMGAP_EDEVICE;
+        sv->latencies_us.push_back(
+            std::chrono::duration<double, std::micro>(j.t_done - j.t_submit).count());
         if (j.ready) {
             (void)hipEventDestroy(j.ready);
             j.ready = nullptr;
@@ -216,22 +219,21 @@ void server_loop(mmgap_server *sv)
             progressed = true;
         }
         if (progressed) sv->idle.notify_all();
-        // admit: the longest FIFO prefix that fits the largest free range,
-        // once per free slot
-        for (int si = 0; si < (int)sv->slots.size() && !sv->pending.empty(); ++si) {
-            if (sv->slots[si].busy) continue;
-            std::vector<size_t> fp;
-            const int look = std::min<int>((int)sv->pending.size(), sv->max_batch_jobs);
-            fp.reserve(look);
-            for (int i = 0; i < look; ++i) fp.push_back(sv->jobs[sv->pending[i]].footprint);
-            const int k = mmgap::serve::admit_prefix(fp, sv->alloc.largest_free(), look);
-            if (k == 0) break;                      // the head waits for memory
-            size_t bytes = 0;
-            for (int i = 0; i < k; ++i) bytes += mmgap::serve::arena_round(fp[i]);
-            size_t off = 0;
-            if (!sv->alloc.alloc(bytes, &off)) break;
-            launch(sv, si, k, bytes, off);
-            progressed = true;
+        // admit: per free slot the longest FIFO prefix that fits the largest
+        // free range (admission.h)
+        if (!sv->pending.empty()) {
+            std::vector<bool> busy;
+            for (const Slot &sl : sv->slots) busy.push_back(sl.busy);
+            const size_t look = std::min(sv->pending.size(),
+                                         (size_t)sv->max_batch_jobs * sv->slots.size());
+            std::vector<size_t> queue;
+            queue.reserve(look);
+            for (size_t i = 0; i < look; ++i) queue.push_back(sv->jobs[sv->pending[i]].footprint);
+            for (const mmgap::serve::Admitted &ad :
+                 mmgap::serve::admit_round(busy, queue, sv->max_batch_jobs, sv->alloc)) {
+                launch(sv, ad.slot, ad.jobs, ad.bytes, ad.off);   // takes the queue's head
+                progressed = true;
+            }
         }
         bool any_busy = false;
         for (const Slot &sl : sv->slots) any_busy = any_busy || sl.busy;
@@ -411,6 +413,24 @@ int mmgap_server_poll(mmgap_ctx *ctx, unsigned long long job_id, int *done, doub
     const int status = j.status;
     sv->jobs.erase(it);
     if (status != MMGAP_OK) return fail(ctx, status, "job %llu: its batch failed on the device", job_id);
+    return MMGAP_OK;
+}
+
+int mmgap_server_stats(mmgap_ctx *ctx, double deadline_us, int reset, mmgap_server_stats_t *out)
+{
+    if (!ctx) return MMGAP_EINVAL;
+    mmgap_server *sv = ctx->server;
+    if (!sv) return fail(ctx, MMGAP_EINVAL, "no server is running");
+    if (!out) return fail(ctx, MMGAP_EINVAL, "out is NULL");
+    if (!(deadline_us >= 0.0)) return fail(ctx, MMGAP_EINVAL, "deadline_us must be >= 0");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    const mmgap::serve::LatencyStats s = mmgap::serve::latency_stats(sv->latencies_us, deadline_us);
+    out->completed = (unsigned long long)s.count;
+    out->missed = (unsigned long long)s.missed;
+    out->p50_us = s.p50;
+    out->p99_us = s.p99;
+    out->max_us = s.max;
+    if (reset) sv->latencies_us.clear();
     return MMGAP_OK;
 }
 

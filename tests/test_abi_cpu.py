@@ -53,7 +53,8 @@ def test_binding_structs_match_header():
     mmgap_job as declared in the header."""
     text = open(os.path.join(ROOT, "include", "mmgap.h")).read()
     for name, cls in (("mmgap_problem", M.Problem), ("mmgap_cim_params", M.CimParams),
-                      ("mmgap_schedule", M.Schedule), ("mmgap_job", M.Job)):
+                      ("mmgap_schedule", M.Schedule), ("mmgap_job", M.Job),
+                      ("mmgap_server_stats_t", M.ServerStats)):
         names = [f[0] for f in cls._fields_]
         assert _field_order(_struct_body(text, name), names) == names, name
 

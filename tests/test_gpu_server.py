@@ -221,3 +221,38 @@ def test_server_runs_detection_around_a_guess(ctx, mix):
             assert_same(j, refs[k], f"plain job {k}")
     finally:
         ctx.server_stop()
+
+
+def test_server_latency_accounting(ctx, mix):
+    """mmgap_server_stats counts every completed job and those above the
+    deadline, with the nearest-rank percentiles of the latencies the polls
+    report (the accounting of admission.h, which tests/test_serve_sim_cpu.py
+    checks on a simulated device)."""
+    import math
+    inputs, _ = mix
+    note("server: latency accounting")
+    ctx.server_start(max_inflight=2)
+    try:
+        s0 = ctx.server_stats(0.5)
+        assert s0["completed"] == 0 and s0["missed"] == 0 and s0["max_ms"] == 0.0
+        jobs = [job_of(ctx, inp) for inp in inputs]
+        ids = [ctx.server_submit(j) for j in jobs]
+        lat = sorted(wait_all(ctx, ids).values())           # microseconds
+        n = len(lat)
+        k = next(i for i in range(n // 2, n) if lat[i - 1] < lat[i])
+        d_us = 0.5 * (lat[k - 1] + lat[k])                  # strictly between two latencies
+        s = ctx.server_stats(d_us / 1e3)
+        assert s["completed"] == n
+        assert s["missed"] == sum(1 for v in lat if v > d_us) == n - k
+        rank = lambda p: lat[max(1, math.ceil(p / 100 * n)) - 1]
+        assert math.isclose(s["p50_ms"] * 1e3, rank(50), rel_tol=1e-12)
+        assert math.isclose(s["p99_ms"] * 1e3, rank(99), rel_tol=1e-12)
+        assert math.isclose(s["max_ms"] * 1e3, lat[-1], rel_tol=1e-12)
+        s = ctx.server_stats(d_us / 1e3, reset=True)        # read, then a new period
+        assert s["completed"] == n
+        assert ctx.server_stats(d_us / 1e3)["completed"] == 0
+        with pytest.raises(M.MmgapError) as e:
+            ctx.server_stats(-1.0)
+        assert e.value.code == -1
+    finally:
+        ctx.server_stop()

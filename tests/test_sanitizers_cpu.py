@@ -74,3 +74,35 @@ def test_admission_under_sanitizers(tmp_path):
         expect.append(str(adm.prefix_model(fps, room, mx)))
     got = _run(exe, "\n".join(ops) + "\n").split("\n")[:len(ops)]
     assert got == expect
+
+
+def test_serve_sim_under_sanitizers(tmp_path):
+    """The scheduler's admission round and latency accounting on a simulated
+    device, built with the sanitizers, on a random mix (checked against the
+    Python model as in tests/test_serve_sim_cpu.py)."""
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    exe = str(tmp_path / "serve_sim_san")
+    subprocess.run([gxx, "-std=c++17", *SAN, "-I", CSRC, "-o", exe,
+                    os.path.join(ROOT, "tests", "serve_sim_harness.cpp")], check=True)
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "sim_model", os.path.join(ROOT, "tests", "test_serve_sim_cpu.py"))
+    sim = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(sim)
+    rng = random.Random(11)
+    t, jobs = 0, []
+    for _ in range(300):
+        t += rng.choice([0, 1, 7, rng.randrange(0, 200)])
+        jobs.append((t, rng.choice([1, 256, 5000, rng.randrange(1, 40000)]), rng.randrange(1, 500)))
+    text = "slots 3 cap 65536 maxjobs 4 deadline 400\n"
+    text += "".join("job %d %d %d\n" % j for j in jobs) + "end\n"
+    r = subprocess.run([exe], input=text, capture_output=True, text=True, env=ENV)
+    assert r.returncode == 0, r.stderr[-3000:]
+    assert "runtime error" not in r.stderr and "Sanitizer" not in r.stderr, r.stderr[-3000:]
+    lines = r.stdout.strip().split("\n")
+    per = [None if l == "refused" else tuple(int(v) for v in l.split()) for l in lines[:-1]]
+    want_per, want_stats = sim.model(3, 65536, 4, 400, jobs)
+    assert per == want_per
+    assert tuple(int(v) for v in lines[-1].split()[1:]) == want_stats
