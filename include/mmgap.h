@@ -28,8 +28,10 @@
  *    16 users only with QPSK or 16-QAM, n_rx <= 64; VPP n_rx <= 16 users,
  *    n_tx <= 64 antennas; n_sym <= 64; chains 1..1024; sweeps 1..8192.  The
  *    entry points around MMSE-SIC need n_tx <= 16, CIM-CAC dynamics K <= 32
- *    and K q <= 64 spins (K padded to 8, 16 or 32), batches and the server K <= 32 and
- *    chains <= 256.
+ *    and K q <= 64 spins (K padded to 8, 16 or 32).  Batches and the server:
+ *    jobs with stages K <= 32; jobs of the persistent kernels chains <= 256;
+ *    detection with more than 16 users (binary encoding) runs the plain
+ *    path's launches inside the batch.
  *  * A context must not be used by two host threads at once.
  *
  * Problem statement (paper §2.1 Eq. 1 and Eq. ml; §2.2; §3.3):
@@ -397,13 +399,17 @@ enum {
  * K <= 16 with 16-QAM; larger) and ordered by decreasing cost within a class,
  * and allocate the plan's own device scratch (fields and fallbacks; the
  * couplings, H and the VPP inverse of a work item stay in LDS), counted against
- * the context's HBM budget.  Two kinds of jobs run with launches of their own
- * inside the batch instead of work items: CIM-CAC jobs (binary encoding,
+ * the context's HBM budget.  Three kinds of jobs run with launches of their
+ * own inside the batch instead of work items: CIM-CAC jobs (binary encoding,
  * stages = 0; the build, anneal and selection launches of mmgap_detect /
- * mmgap_vpp_precode; CIM-CAC with stages is refused with MMGAP_EUNSUPPORTED),
- * and, unless flags has MMGAP_PLAN_PERSISTENT, jobs with stages that the
- * one-launch search of mmgap_detect_e can run (the build, the MMSE-SIC guess
- * where asked, the search).  The outputs are the same either way.  A launch
+ * mmgap_vpp_precode; CIM-CAC with stages is refused with MMGAP_EUNSUPPORTED);
+ * Metropolis jobs wider than the persistent kernels' 32 padded dimensions
+ * (detection with 17 to 32 users, binary encoding: the build, anneal and
+ * selection launches of mmgap_detect; with stages they are refused with
+ * MMGAP_EUNSUPPORTED); and, unless flags has MMGAP_PLAN_PERSISTENT, jobs with
+ * stages that the one-launch search of mmgap_detect_e can run (the build, the
+ * MMSE-SIC guess where asked, the search).  The outputs are the same either
+ * way.  A launch
  * is: the MMSE-SIC launches, the own-launch jobs in order, then one
  * persistent kernel per class present, largest class first.  `blocks` =
  * workgroups of each persistent kernel, 0 = as many as the device holds at

@@ -409,8 +409,13 @@ int batch_layout(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, int flags,
             return fail(ctx, MMGAP_EINVAL, "job %d: guesses need stages >= 1", j);
         // moves around a guess: two unit-weight spins per real dimension
         const int aq = jb.stages > 0 ? 2 : sh.q;
+        // no persistent variant above 32 dimensions: such a job runs the plain
+        // path's launches inside the batch (binary encoding only)
         const int variant = mmgap::fused_variant(sh.KT, aq);
-        if (variant < 0) return fail(ctx, MMGAP_EUNSUPPORTED, "job %d: no fused variant", j);
+        if (variant < 0 && jb.stages > 0)
+            return fail(ctx, MMGAP_EUNSUPPORTED,
+                        "job %d: moves around a guess are batched up to 32 dimensions (K=%d)", j,
+                        sh.K);
         if ((jb.guesses & MMGAP_GUESS_SIC) && jb.prob.n_tx > 16)
             return fail(ctx, MMGAP_EUNSUPPORTED, "job %d: MMSE-SIC supports n_tx <= 16 (got %d)",
                         j, jb.prob.n_tx);
@@ -428,6 +433,8 @@ int batch_layout(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, int flags,
             const mmgap_cim_params *c = jb.sched.cim;
             L.cim[j] = mmgap::CimParams{c->dt, c->p - 1.0f, c->a, -c->zeta, c->eps, c->amp0,
                                         c->f_mvm};
+        } else if (variant < 0) {
+            L.route[j] = kRoutePlain;
         } else if (jb.stages > 0 && !(flags & MMGAP_PLAN_PERSISTENT)) {
             const int gl = search_lanes_of(jb.sched.chains, jb.prob.n_sym, jb.prob.n_rx, sh.KT,
                                            false);
@@ -523,7 +530,7 @@ int batch_layout(mmgap_ctx *ctx, int n_jobs, const mmgap_job *jobs, int flags,
             L.ofp[j] = 0;
             L.ox[j] = lay.take(ni * (size_t)f.KT);
             L.oxs[j] = (f.guesses & MMGAP_GUESS_SIC) ? lay.take(ni * (size_t)f.KT) : 0;
-            if (L.route[j] == kRouteCim) {
+            if (L.route[j] == kRouteCim || L.route[j] == kRoutePlain) {
                 const size_t nw = (size_t)mmgap::spin_words(f.KT, f.Q);
                 L.oE[j] = lay.take(sizeof(float) * ni * f.chains);
                 L.oS[j] = lay.take(sizeof(uint32_t) * ni * f.chains * nw);
@@ -627,7 +634,7 @@ int batch_launch_config(mmgap_ctx *ctx, const BatchLayout &L, char *base, int bl
             v.Ainv = reinterpret_cast<double2 *>(base + L.oA[j]);
             v.unorm = nullptr;
         }
-        if (sl.route == kRouteCim) {
+        if (sl.route == kRouteCim || sl.route == kRoutePlain) {
             mmgap::AnnealArgs &a = sl.ann;
             a.G = G;
             a.inst_per_G = f.n_sym;
@@ -644,7 +651,8 @@ int batch_launch_config(mmgap_ctx *ctx, const BatchLayout &L, char *base, int bl
             a.glanes = packed_lanes(f.chains, f.n_sym, 64);
             a.chain_E = reinterpret_cast<float *>(base + L.oE[j]);
             a.chain_S = reinterpret_cast<uint32_t *>(base + L.oS[j]);
-            a.cim = L.cim[j];
+            if (sl.route == kRouteCim) a.cim = L.cim[j];
+            else a.beta2 = reinterpret_cast<const float *>(base + L.ob[j]);
             mmgap::SelectArgs &se = sl.sel;
             se.mode = f.kind == MMGAP_KIND_DET ? mmgap::kSelectDet : mmgap::kSelectVpp;
             se.n_inst = ni;
@@ -734,8 +742,8 @@ hipError_t batch_enqueue(const BatchLaunch &b, const uint32_t *accept_table, hip
     // the MMSE-SIC guesses of the jobs that search from it, before the
     // searches and persistent kernels that read them
     for (size_t k = 0; k < b.sic.size() && e == hipSuccess; ++k) e = mmgap::launch_sic(b.sic[k], st);
-    // jobs with launches of their own: build, then CIM-CAC anneal and
-    // selection, or the search
+    // jobs with launches of their own: build, then CIM-CAC or Metropolis
+    // anneal and selection, or the search
     for (size_t k = 0; k < b.sep.size() && e == hipSuccess; ++k) {
         const SepLaunch &sl = b.sep[k];
         e = sl.kind == MMGAP_KIND_DET ? mmgap::launch_det_build(sl.det, st)
@@ -743,6 +751,11 @@ hipError_t batch_enqueue(const BatchLaunch &b, const uint32_t *accept_table, hip
         if (e != hipSuccess) break;
         if (sl.route == kRouteCim) {
             e = mmgap::launch_cim(sl.KT, sl.q, sl.ann, st);
+            if (e == hipSuccess) e = mmgap::launch_select(sl.sel, st);
+        } else if (sl.route == kRoutePlain) {
+            mmgap::AnnealArgs a = sl.ann;
+            a.accept_table = accept_table;
+            e = mmgap::launch_anneal(sl.KT, sl.q, a, st);
             if (e == hipSuccess) e = mmgap::launch_select(sl.sel, st);
         } else {
             mmgap::SearchArgs r = sl.srch;

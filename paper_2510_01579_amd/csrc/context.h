@@ -99,9 +99,10 @@ int check_schedule(mmgap_ctx *ctx, const mmgap_schedule *s);
 
 // How a batch job runs: through the persistent kernels' work items; or, with
 // launches of its own inside the batch, by CIM-CAC anneals (build, anneal,
-// selection) or by the one-launch search (build, the MMSE-SIC guess where
-// asked, search).
-enum BatchRoute { kRoutePersistent = 0, kRouteCim = 1, kRouteSearch = 2 };
+// selection), by the one-launch search (build, the MMSE-SIC guess where
+// asked, search), or by the plain path's Metropolis anneals for problems wider
+// than the persistent kernels' 32 dimensions (build, anneal, selection).
+enum BatchRoute { kRoutePersistent = 0, kRouteCim = 1, kRouteSearch = 2, kRoutePlain = 3 };
 
 // A batch of jobs for the persistent fused kernels, laid out on the host:
 // descriptors, work items grouped by register class (each group by decreasing

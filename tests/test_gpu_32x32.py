@@ -157,8 +157,8 @@ def test_32_users_refusals(ctx):
         ctx.detect(dev(d.H), dev(d.y), 64, d.noise_var, 32, 4, b, 1)
     assert e.value.code == -4
     d = W.det_slot(3602, 32, 32, 16, 2, 2, 20.0)
-    job = ctx.det_job(dev(d.H), dev(d.y), 16, d.noise_var, 32, 4, b, 1)
-    with pytest.raises(M.MmgapError) as e:                 # no persistent variant
+    job = ctx.det_job(dev(d.H), dev(d.y), 16, d.noise_var, 32, 4, b, 1, stages=1)
+    with pytest.raises(M.MmgapError) as e:                 # stages in a batch: up to 32 dims
         ctx.plan_create([job])
     assert e.value.code == -4
     with pytest.raises(M.MmgapError) as e:                 # MMSE-SIC up to 16 users

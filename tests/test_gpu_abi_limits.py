@@ -134,15 +134,17 @@ def test_cim_spins(ctx):
 
 
 def test_batch_limits(ctx):
-    note("batches: 16 users ok / 17 refused; 256 chains ok / 257 refused")
+    note("batches: binary 32 users ok / 33 refused; stages 16 users ok / 17 refused; "
+         "256 chains ok / 257 refused")
 
-    def plan(n_t, chains):
+    def plan(n_t, chains, stages=0):
         H, y = det_inputs(n_t, n_t)
-        j = ctx.det_job(H, y, 4, 1.0, chains, 2, b2(2), 1)
+        j = ctx.det_job(H, y, 4, 1.0, chains, 2, b2(2), 1, stages=stages)
         p = ctx.plan_create([j], graph=False)
         p.plan_launch()
         torch.cuda.synchronize()
         p.plan_destroy()
 
-    ok_then_refused(lambda: plan(16, 4), lambda: plan(17, 4))
+    ok_then_refused(lambda: plan(32, 4), lambda: plan(33, 4))          # plain route above 16
+    ok_then_refused(lambda: plan(16, 4, 1), lambda: plan(17, 4, 1))    # moves: 32 dimensions
     ok_then_refused(lambda: plan(8, 256), lambda: plan(8, 257))

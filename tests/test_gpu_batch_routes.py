@@ -1,8 +1,9 @@
 """Jobs that run with launches of their own inside a batch: CIM-CAC jobs (the
 build, anneal and selection launches of the plain entry points; paper §2.3
-Eqs. cim1/cim2) and jobs with stages that the one-launch search runs (moves
-around a guess, MMGaP-E; §2.3 Fig. 5, §3.2 Fig. 6), beside jobs of the
-persistent kernels.  Every job's outputs must equal its single-call entry
+Eqs. cim1/cim2), Metropolis jobs wider than 32 dimensions (the 32x32 shape of
+§5.2.3 and 24 users, by the plain path's launches) and jobs with stages that
+the one-launch search runs (moves around a guess, MMGaP-E; §2.3 Fig. 5, §3.2
+Fig. 6), beside jobs of the persistent kernels.  Every job's outputs must equal its single-call entry
 point's, bit for bit, in plans (on every graph replay) and in the server.
 """
 import sys
@@ -49,6 +50,8 @@ SPECS = [
     ("search MMSE guess 8x8 16-QAM", "det", 8, 8, 16, 17, 12, 16, 6, 2, 0, None),
     ("persistent delta, 128 chains", "det", 8, 8, 16, 5, 4, 128, 4, 1, 0, None),
     ("persistent binary 8x8 16-QAM", "det", 8, 8, 16, 19, 12, 64, 20, 0, 0, None),
+    ("plain 32x32 16-QAM, 64 dimensions", "det", 32, 32, 16, 3, 12, 64, 8, 0, 0, None),
+    ("plain 24 users QPSK, 48 of 64 dimensions", "det", 24, 24, 4, 2, 5, 32, 6, 0, 0, None),
     ("persistent vpp 8x8 16-QAM", "vpp", 8, 8, 16, 9, 6, 32, 20, 0, 0, None),
 ]
 
