@@ -707,16 +707,19 @@ def main(argv=None) -> int:  # noqa: C901
             same_bytes(p_out, f_out, ("sym", "metric", "v", "x", "gamma"))})
         legs["fused"] = (el, lat, ref_scheds)
 
-    # ---- tuned: the tuner's schedule per job (binary encoding or stages)
+    # ---- tuned: the tuner's schedule per job (binary encoding or stages); the
+    # persistent leg where every job fits the persistent kernels
     tuned = None
     t_scheds = None
-    if fusable:
+    t_out = None
+    if fusable or is_det:
         t_scheds = []
         for inp in inputs:
             j = inp["spec"]
             kind = M.KIND_DET if j["kind"] == "det" else M.KIND_VPP
             ts = M.tuned_schedule(kind, j["rows"], j["cols"], j["qam"], inp["noise_var"])
             t_scheds.append(ts if ts["tuned"] else ref_scheds[len(t_scheds)])
+    if fusable:
         print("[bench] tuned leg", file=sys.stderr, flush=True)
         el, lat, t_out, _ = fused_leg(t_scheds)
         t_out_ref = t_out
@@ -728,8 +731,8 @@ def main(argv=None) -> int:  # noqa: C901
 
     # ---- the tuned stages through the multi-launch entry point
     delta_sep = None
-    if tuned is not None and is_det and all(s.get("stages") and s.get("guesses", 1) <= 1
-                                            for s in t_scheds):
+    if t_scheds is not None and is_det and all(s.get("stages") and s.get("guesses", 1) <= 1
+                                               for s in t_scheds):
         def delta_group(gi):
             outs = []
             for i in gidx[gi]:
@@ -753,7 +756,8 @@ def main(argv=None) -> int:  # noqa: C901
             "stage_ms": {"build": float(np.mean(dprof[:, :, 0].sum(axis=1))),
                          "anneal": float(np.mean(dprof[:, :, 1].sum(axis=1))),
                          "select": float(np.mean(dprof[:, :, 2].sum(axis=1)))},
-            "outputs_identical_to_tuned": same_bytes(d_out, t_out, ("sym", "metric")),
+            "outputs_identical_to_tuned": None if t_out is None else
+            same_bytes(d_out, t_out, ("sym", "metric")),
             "quality_matched": matched(q_d, q_ref)})
         legs["delta_separate"] = (el, lat, t_scheds)
 
@@ -762,14 +766,15 @@ def main(argv=None) -> int:  # noqa: C901
     tuned_sep = None
     tuned_plan = None
     stage_launch_ms = None
-    if tuned is not None and is_det:
+    if t_scheds is not None and is_det:
         a_scheds = []
         for inp, ts in zip(inputs, t_scheds):
             j = inp["spec"]
             sa = M.tuned_schedule(M.KIND_DET, j["rows"], j["cols"], j["qam"], inp["noise_var"],
                                   any_formulation=True)
             a_scheds.append(sa if sa["tuned"] else ts)
-        if any(s.get("guesses", 0) > 1 for s in a_scheds):
+        # (also every tuned formulation of jobs the persistent kernels cannot take)
+        if any(s.get("guesses", 0) > 1 for s in a_scheds) or not fusable:
             def sep_group(gi):
                 outs = []
                 for i in gidx[gi]:
@@ -807,17 +812,19 @@ def main(argv=None) -> int:  # noqa: C901
             legs["tuned_separate"] = (el, lat, a_scheds)
             # the same formulations as one HIP graph per slot: the build, the
             # MMSE-SIC launch and the search (or the persistent kernel for the
-            # binary encoding) replayed
-            print("[bench] tuned leg, every formulation (one graph per slot)", file=sys.stderr,
-                  flush=True)
-            el, lat, tp_out, _ = fused_leg(a_scheds, persistent=False)
-            q_tp = quality(inputs, tp_out)
-            tuned_plan = leg_record(el, lat, q_tp, {
-                "schedules": [sched_desc(s) for s in a_scheds],
-                "outputs_identical_to_tuned_separate": same_bytes(tp_out, s_out,
-                                                                  ("sym", "metric")),
-                "quality_matched": matched(q_tp, q_ref)})
-            legs["tuned_plan"] = (el, lat, a_scheds)
+            # binary encoding, or the plain launches above 32 dimensions)
+            # replayed; batches take no stages above 32 dimensions
+            if fusable or all(not s.get("stages") for s in a_scheds):
+                print("[bench] tuned leg, every formulation (one graph per slot)",
+                      file=sys.stderr, flush=True)
+                el, lat, tp_out, _ = fused_leg(a_scheds, persistent=False)
+                q_tp = quality(inputs, tp_out)
+                tuned_plan = leg_record(el, lat, q_tp, {
+                    "schedules": [sched_desc(s) for s in a_scheds],
+                    "outputs_identical_to_tuned_separate": same_bytes(tp_out, s_out,
+                                                                      ("sym", "metric")),
+                    "quality_matched": matched(q_tp, q_ref)})
+                legs["tuned_plan"] = (el, lat, a_scheds)
             if not args.no_extras:
                 # the same jobs with every stage as separate launches
                 ctx.set_stage_launches(True)
@@ -1034,6 +1041,10 @@ def main(argv=None) -> int:  # noqa: C901
                            "separate-launch leg's events around the same launches)"}.get(
         sel_name, "k_fused" + (" (moves around the guess)" if any(s.get("stages")
                                                                    for s in sel_scheds) else ""))
+    if sel_name in ("tuned_separate", "tuned_plan") and not any(s.get("stages")
+                                                                for s in sel_scheds):
+        kname = "k_anneal (tuned schedules of the binary encoding: build, anneal and " \
+                "selection launches per slot)"
     tkey = {"plain": "k_anneal", "delta_separate": "k_search_delta",
             "tuned_separate": "k_search_tuned_separate",
             "tuned_plan": "k_search_tuned_separate"}.get(

@@ -61,6 +61,8 @@ CLASSES = {
     "det-16x16-4": dict(ref=(128, 400, 0), snr=[0.0, 5.0, 10.0, 15.0]),
     "det-16x16-16": dict(ref=(128, 400, 0), snr=[5.0, 10.0, 15.0, 20.0, 25.0]),
     "det-16x16-64": dict(ref=(128, 400, 1), snr=[15.0, 20.0, 25.0, 30.0]),
+    # the 32x32 shape (paper §5.2.3), 16-QAM; no MMSE-SIC guess above 16 users
+    "det-32x32-16": dict(ref=(128, 100, 0), snr=[10.0, 15.0, 20.0]),
     "vpp-8x8-4": dict(ref=(64, 200, 0), snr=[None]),
     "vpp-8x8-16": dict(ref=(64, 200, 0), snr=[None]),
     "vpp-8x8-64": dict(ref=(64, 200, 0), snr=[None]),
@@ -124,8 +126,11 @@ E_SHAPES = ((0.0, 1.0), (0.25, 1.0))
 E_MAX_WORK = 6400
 
 
-def e_candidates():
-    """(chains, sweeps, 0, shape, stages, guesses) for guesses 2 (MMSE-SIC) and 3 (both)."""
+def e_candidates(name=None):
+    """(chains, sweeps, 0, shape, stages, guesses) for guesses 2 (MMSE-SIC) and 3 (both);
+    none for a class above the MMSE-SIC limit of 16 users."""
+    if name is not None and parse_class(name)[2] > 16:
+        return []
     return [(C, S, 0, sh, st, g) for g in (2, 3) for C in E_CHAINS for S in E_SWEEPS
             for st in E_STAGES for sh in E_SHAPES if C * S * st <= E_MAX_WORK]
 
@@ -161,7 +166,7 @@ def cost(name, chains, sweeps, stages=0, guesses=None) -> float:
     kind, rows, cols, qam = parse_class(name)
     K = 2 * (cols if kind == "det" else rows)
     q = {4: 1, 16: 2, 64: 3}[qam] if kind == "det" else 2
-    KT = 8 if K <= 8 else (16 if K <= 16 else 32)
+    KT = 8 if K <= 8 else (16 if K <= 16 else (32 if K <= 32 else 64))
     if guesses is None:
         guesses = 1 if stages else 0
     if stages:
@@ -488,7 +493,7 @@ def main(argv=None) -> int:
                 continue
             rec = table["classes"][name]
             cands = (delta_candidates() if args.add_delta else []) + \
-                (e_candidates() if args.add_e else [])
+                (e_candidates(name) if args.add_e else [])
             t0 = time.time()
             for k, r in enumerate(rec["per_snr"]):
                 todo = [c for c in cands if schedule_key(c) not in r["cands"]]
@@ -514,7 +519,7 @@ def main(argv=None) -> int:
                         if cost(name, C, S) <= cost(name, ref[0], ref[1])} | {ref},
                        key=lambda s: (cost(name, s[0], s[1]), s))
         if name.startswith("det"):
-            cands += delta_candidates() + e_candidates()
+            cands += delta_candidates() + e_candidates(name)
         t0 = time.time()
         per_snr = []
         for k, snr in enumerate(spec["snr"]):
