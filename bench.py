@@ -542,7 +542,7 @@ def main(argv=None) -> int:  # noqa: C901
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the hot path shards by subcarrier with no "
-              "exchange, and multi-GPU runs are not part of this build (use --gpus 1)",
+              "exchange, and it runs one GPU at a time (use --gpus 1)",
               file=sys.stderr)
         return 2
 
