@@ -971,6 +971,19 @@ def main(argv=None) -> int:  # noqa: C901
                              **lat_of(lambda: ctx.detect_e(
                                  H1, y1, j["qam"], mid["noise_var"], es["chains"], es["sweeps"],
                                  es["beta2"], mid["seed"], stages=es["stages"])))
+        # the paper's critical path runs MMGaP-E's two guesses in parallel: the
+        # stage launches put the MMSE-SIC guess and its chain on the context's
+        # second stream, beside the build and the chain from the MMSE guess
+        # (outputs identical to the one-launch search)
+        ctx.set_stage_launches(True)
+        try:
+            cp["mmgap_e_parallel"] = dict(
+                schedule=sdesc(es, "both guesses in parallel on two streams"),
+                **lat_of(lambda: ctx.detect_e(
+                    H1, y1, j["qam"], mid["noise_var"], es["chains"], es["sweeps"],
+                    es["beta2"], mid["seed"], stages=es["stages"])))
+        finally:
+            ctx.set_stage_launches(False)
         extras["critical_path"] = cp
 
     if is_det and not args.no_extras and all(j["n_sc"] * j["n_sym"] > 0 for j in specs):
